@@ -1,0 +1,276 @@
+"""FP64 CPU oracle for the Heun-integrated stochastic LLG spin model.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package; the GPU library
+never loads or calls it.  The arithmetic lives in plain C (``llg.c``,
+``philox.c``), compiled with ``-O2 -ffp-contract=off`` and run on one
+thread.  This module compiles that C, marshals numpy arrays into it, and
+adds the statistics the paper's sweep protocols need (means and blocked
+standard errors), written in numpy.
+
+Paper passages: the section on the classical spin Hamiltonian (energy),
+"Spin Dynamics" and "Langevin Dynamics" (LLG and thermal field), "Time
+Integration of the LLG Equation" (Heun scheme), the temperature-dependent
+magnetisation protocol of the "Curie temperature" test (heating with the
+previous state as the next starting point), and the Stoner-Wohlfarth test
+(relaxation until the torque falls below 1e-6 T).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["philox.c", "llg.c"]
+KB = 1.3807e-23  # J/K, Table 1
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C into ``oracle/liboracle.so`` (gcc, -O2, no FMA contraction)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall", "-Wextra",
+           "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _System(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p),
+        ("col", ctypes.c_void_p),
+        ("ntype", ctypes.c_void_p),
+        ("J", ctypes.c_void_p),
+        ("n_types", ctypes.c_int),
+        ("mu_s", ctypes.c_void_p),
+        ("k_u", ctypes.c_void_p),
+        ("easy_axis", ctypes.c_void_p),
+        ("alpha", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("temperature", ctypes.c_double),
+        ("H", ctypes.c_double * 3),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        L.orc_philox_batch.argtypes = [ctypes.c_int64, P, P, P]
+        L.orc_gaussian3_batch.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, P,
+                                          ctypes.c_uint32, P]
+        L.orc_effective_fields.argtypes = [ctypes.POINTER(_System), P, P]
+        L.orc_energy.argtypes = [ctypes.POINTER(_System), P]
+        L.orc_energy.restype = ctypes.c_double
+        L.orc_magnetisation.argtypes = [ctypes.POINTER(_System), P, P]
+        L.orc_integrate.argtypes = [ctypes.POINTER(_System), P, ctypes.c_uint64, ctypes.c_int64, P, P]
+        L.orc_integrate.restype = ctypes.c_int
+        L.orc_relax.argtypes = [ctypes.POINTER(_System), P, ctypes.c_double, ctypes.c_int64,
+                                ctypes.c_uint64]
+        L.orc_relax.restype = ctypes.c_int64
+        L.orc_max_torque.argtypes = [ctypes.POINTER(_System), P]
+        L.orc_max_torque.restype = ctypes.c_double
+        L.orc_llg_rhs.argtypes = [ctypes.c_double, ctypes.c_double, P, P, P]
+        L.orc_neighbours.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, P, P, P, P, P, ctypes.c_int64]
+        L.orc_neighbours.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 on arrays: ctr uint32 [m, 4], key uint32 [m, 2] -> uint32 [m, 4]."""
+    ctr = np.ascontiguousarray(np.atleast_2d(ctr), dtype=np.uint32)
+    key = np.ascontiguousarray(np.atleast_2d(key), dtype=np.uint32)
+    if key.shape[0] == 1 and ctr.shape[0] > 1:
+        key = np.ascontiguousarray(np.repeat(key, ctr.shape[0], axis=0))
+    out = np.empty_like(ctr)
+    lib().orc_philox_batch(ctr.shape[0], _ptr(ctr), _ptr(key), _ptr(out))
+    return out
+
+
+def gaussians(seed, step, sites, purpose=0):
+    """Thermal normals Gamma (shape [m, 3]) for the given sites at one step."""
+    sites = np.ascontiguousarray(sites, dtype=np.uint64)
+    out = np.empty((sites.size, 3), dtype=np.float64)
+    lib().orc_gaussian3_batch(int(seed), int(step), sites.size, _ptr(sites), int(purpose), _ptr(out))
+    return out
+
+
+def llg_rhs(gamma, alpha, spin, h):
+    spin = np.ascontiguousarray(spin, dtype=np.float64)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    out = np.empty(3)
+    lib().orc_llg_rhs(float(gamma), float(alpha), _ptr(spin), _ptr(h), _ptr(out))
+    return out
+
+
+def neighbours(pos, box, shells):
+    """Brute-force neighbour list.  box: 3 lengths (0 = open axis);
+    shells: list of (r_lo, r_hi), one per interaction type."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    lo = np.ascontiguousarray([s[0] for s in shells], dtype=np.float64)
+    hi = np.ascontiguousarray([s[1] for s in shells], dtype=np.float64)
+    cap = n * 64
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(cap, dtype=np.int32)
+    ntype = np.zeros(cap, dtype=np.uint8)
+    cnt = lib().orc_neighbours(n, _ptr(pos), _ptr(box), len(shells), _ptr(lo), _ptr(hi),
+                               _ptr(row_ptr), _ptr(col), _ptr(ntype), cap)
+    if cnt < 0:
+        raise RuntimeError("neighbour capacity exceeded")
+    return row_ptr, col[:cnt].copy(), ntype[:cnt].copy()
+
+
+class System:
+    """A spin system held in the arrays the C oracle reads.
+
+    Construct from a ``spin_systems.Workload`` (or anything with the same
+    attributes).  Temperature and applied field can be changed between
+    calls, which is how the sweep protocols continue from one point to the
+    next.
+    """
+
+    def __init__(self, w):
+        lat = w.lattice
+        self.n = lat.n
+        self.row_ptr = np.ascontiguousarray(lat.row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(lat.col, dtype=np.int32)
+        self.ntype = np.ascontiguousarray(lat.ntype, dtype=np.uint8)
+        self.J = np.ascontiguousarray(w.J, dtype=np.float64)
+        self.mu_s = np.ascontiguousarray(np.broadcast_to(w.mu_s, (self.n,)), dtype=np.float64)
+        self.k_u = np.ascontiguousarray(np.broadcast_to(w.k_u, (self.n,)), dtype=np.float64)
+        self.easy_axis = np.ascontiguousarray(np.broadcast_to(w.easy_axis, (self.n, 3)),
+                                              dtype=np.float64)
+        self.alpha, self.gamma, self.dt = float(w.alpha), float(w.gamma), float(w.dt)
+        self.temperature = float(w.temperature)
+        self.H = np.array(w.H, dtype=np.float64)
+        self.seed = int(w.seed)
+
+    def _struct(self):
+        s = _System()
+        s.n = self.n
+        s.row_ptr = self.row_ptr.ctypes.data
+        s.col = self.col.ctypes.data if self.col.size else None
+        s.ntype = self.ntype.ctypes.data if self.ntype.size else None
+        s.J = self.J.ctypes.data
+        s.n_types = self.J.size
+        s.mu_s = self.mu_s.ctypes.data
+        s.k_u = self.k_u.ctypes.data
+        s.easy_axis = self.easy_axis.ctypes.data
+        s.alpha, s.gamma, s.dt = self.alpha, self.gamma, self.dt
+        s.temperature = self.temperature
+        s.H = (ctypes.c_double * 3)(*[float(v) for v in self.H])
+        s.seed = self.seed
+        return s
+
+    def integrate(self, S, step0, n_steps, record=True):
+        """Heun steps step0 .. step0+n_steps-1 in place on S ([n, 3] float64).
+        Returns (m [n_steps, 3], E [n_steps]) when record, else (None, None)."""
+        assert S.dtype == np.float64 and S.flags.c_contiguous and S.shape == (self.n, 3)
+        m = np.empty((n_steps, 3)) if record else None
+        E = np.empty(n_steps) if record else None
+        st = self._struct()
+        rc = lib().orc_integrate(ctypes.byref(st), _ptr(S), int(step0), int(n_steps),
+                                 _ptr(m) if record else None, _ptr(E) if record else None)
+        if rc != 0:
+            raise FloatingPointError(f"oracle integrate failed ({rc})")
+        return m, E
+
+    def energy(self, S):
+        st = self._struct()
+        return lib().orc_energy(ctypes.byref(st), _ptr(np.ascontiguousarray(S, dtype=np.float64)))
+
+    def magnetisation(self, S):
+        st = self._struct()
+        out = np.empty(3)
+        lib().orc_magnetisation(ctypes.byref(st), _ptr(np.ascontiguousarray(S, dtype=np.float64)),
+                                _ptr(out))
+        return out
+
+    def fields(self, S):
+        """Deterministic effective field (exchange + anisotropy + applied), [n, 3] tesla."""
+        st = self._struct()
+        out = np.empty((self.n, 3))
+        lib().orc_effective_fields(ctypes.byref(st), _ptr(np.ascontiguousarray(S, dtype=np.float64)),
+                                   _ptr(out))
+        return out
+
+    def max_torque(self, S):
+        st = self._struct()
+        return lib().orc_max_torque(ctypes.byref(st), _ptr(np.ascontiguousarray(S, dtype=np.float64)))
+
+    def relax(self, S, torque_tol=1e-6, max_steps=10_000_000, step0=0):
+        st = self._struct()
+        return int(lib().orc_relax(ctypes.byref(st), _ptr(S), float(torque_tol), int(max_steps),
+                                   int(step0)))
+
+
+def block_stats(x, n_blocks):
+    """Mean of a series and its standard error from n_blocks equal blocks
+    (the series is cut to a multiple of n_blocks)."""
+    x = np.asarray(x, dtype=np.float64)
+    b = x.size // n_blocks
+    if b == 0:
+        return float(x.mean()), float("nan")
+    means = x[: b * n_blocks].reshape(n_blocks, b).mean(axis=1)
+    return float(x.mean()), float(means.std(ddof=1) / np.sqrt(n_blocks))
+
+
+def average(sys: System, S, step0, n_eq, n_avg, n_blocks=10):
+    """Equilibrate n_eq steps, then average over n_avg steps sampled after
+    every step.  Returns (dict, next_step).  The dict holds <|m|> and its
+    blocked standard error, <m> (3), <E> and its standard error."""
+    sys.integrate(S, step0, n_eq, record=False)
+    m, E = sys.integrate(S, step0 + n_eq, n_avg, record=True)
+    mabs = np.sqrt((m * m).sum(axis=1))
+    mean_abs, se_abs = block_stats(mabs, n_blocks)
+    mean_E, se_E = block_stats(E, n_blocks)
+    out = {"m_abs": mean_abs, "m_abs_se": se_abs, "m": m.mean(axis=0), "E": mean_E,
+           "E_se": se_E}
+    return out, step0 + n_eq + n_avg
+
+
+def sweep_temperature(sys: System, S, temperatures, n_eq, n_avg, step0=0, n_blocks=10):
+    """Heating ramp with continuation: the final state at one temperature is
+    the starting state at the next; the step counter keeps running."""
+    rows = []
+    step = step0
+    for T in temperatures:
+        sys.temperature = float(T)
+        r, step = average(sys, S, step, n_eq, n_avg, n_blocks)
+        r["T"] = float(T)
+        rows.append(r)
+    return rows, step
+
+
+def sweep_field(sys: System, S, fields, n_eq, n_avg, step0=0, n_blocks=10):
+    """Field sweep with continuation; each entry of fields is a 3-vector."""
+    rows = []
+    step = step0
+    for H in fields:
+        sys.H = np.asarray(H, dtype=np.float64)
+        r, step = average(sys, S, step, n_eq, n_avg, n_blocks)
+        r["H"] = np.asarray(H, dtype=np.float64)
+        rows.append(r)
+    return rows, step

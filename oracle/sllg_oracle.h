@@ -1,0 +1,106 @@
+/*
+ * sllg_oracle.h -- plain, single-threaded FP64 reference implementation of
+ * the stochastic Landau-Lifshitz-Gilbert (sLLG) spin dynamics integrated
+ * with the Heun predictor-corrector scheme, as described in Evans et al.,
+ * "Atomistic spin model simulations of magnetic nanomaterials"
+ * (J. Phys.: Condens. Matter 26, 103202 (2014); arXiv:1310.6143).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library
+ * against the paper.  It is slow on purpose: one thread, IEEE double,
+ * no FMA contraction, no reordering of the paper's steps.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it; the product path never does.  It shares no code with the GPU library.
+ *
+ * Units are SI as in Table 1 of the paper: moments in J/T, exchange in
+ * joules per link, anisotropy in joules per atom, fields in tesla, time in
+ * seconds, temperature in kelvin.
+ */
+#ifndef SLLG_ORACLE_H
+#define SLLG_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Boltzmann constant, Table 1 of the paper (J/K). */
+#define ORC_KB 1.3807e-23
+
+/* A spin system in the form the Hamiltonian section writes it.
+ * Every per-site array has n entries (easy_axis has 3n).  The neighbour
+ * list is CSR: the entries of row i are row_ptr[i] .. row_ptr[i+1]-1, with
+ * neighbour col[k] coupled by J[ntype[k]] (ntype may be NULL: all type 0). */
+typedef struct {
+    int64_t n;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const uint8_t *ntype;
+    const double *J;
+    int n_types;
+    const double *mu_s;
+    const double *k_u;
+    const double *easy_axis;
+    double alpha;          /* microscopic (Gilbert) damping lambda */
+    double gamma;          /* gyromagnetic ratio, 1/(T s) */
+    double dt;             /* time step, s */
+    double temperature;    /* K */
+    double H[3];           /* applied field, T */
+    uint64_t seed;         /* Philox key */
+} orc_system;
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_philox_batch(int64_t count, const uint32_t *ctr, const uint32_t *key, uint32_t *out);
+
+/* Three standard normals for (site, step): Philox counter
+ * (site, step low word, step high word, purpose), key = seed, then two
+ * Box-Muller pairs of which the fourth normal is dropped. */
+void orc_gaussian3(uint64_t seed, uint64_t step, uint64_t site, uint32_t purpose, double g[3]);
+void orc_gaussian3_batch(uint64_t seed, uint64_t step, int64_t count, const uint64_t *sites,
+                         uint32_t purpose, double *g);
+
+/* Fields (tesla) and the right-hand side of the LLG equation. */
+void orc_exchange_field(const orc_system *s, const double *S, int64_t i, double h[3]);
+void orc_effective_field(const orc_system *s, const double *S, int64_t i, double h[3]);
+void orc_effective_fields(const orc_system *s, const double *S, double *H_out);
+void orc_llg_rhs(double gamma, double alpha, const double spin[3], const double h[3], double ds[3]);
+double orc_thermal_sigma(const orc_system *s, int64_t i);
+
+/* Observables. */
+double orc_energy(const orc_system *s, const double *S);
+void orc_magnetisation(const orc_system *s, const double *S, double m[3]);
+
+/* One Heun step numbered `step` (used as the noise counter).  S (3n) is
+ * updated in place; work must hold 9n doubles.  Returns 0, or -1 if a spin
+ * could not be normalised (zero length or not finite). */
+int orc_heun_step(const orc_system *s, double *S, uint64_t step, double *work);
+
+/* n_steps Heun steps numbered step0, step0+1, ...  After every step the
+ * reduced magnetisation (3 values) and the energy are written to m_out and
+ * E_out when those are not NULL.  Returns 0, -1 on a bad spin, -2 on
+ * allocation failure. */
+int orc_integrate(const orc_system *s, double *S, uint64_t step0, int64_t n_steps,
+                  double *m_out, double *E_out);
+
+/* Zero-temperature relaxation: Heun steps until every spin's torque
+ * |S x H| is at most torque_tol (tesla), or max_steps.  Returns the number
+ * of steps taken, or -1 if max_steps was reached first. */
+int64_t orc_relax(const orc_system *s, double *S, double torque_tol, int64_t max_steps,
+                  uint64_t step0);
+double orc_max_torque(const orc_system *s, const double *S);
+
+/* Brute-force neighbour search over all pairs (minimum image on the axes
+ * with box[a] > 0).  A pair at distance r with shell_lo[t] <= r <= shell_hi[t]
+ * becomes a link of type t.  Rows come out with ascending columns.
+ * Pass row_ptr (n+1) and col/ntype with room for cap entries; returns the
+ * number of entries, or -1 if cap is too small. */
+int64_t orc_neighbours(int64_t n, const double *pos, const double box[3], int n_shells,
+                       const double *shell_lo, const double *shell_hi,
+                       int64_t *row_ptr, int32_t *col, uint8_t *ntype, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
