@@ -1,0 +1,282 @@
+/*
+ * sllg.h -- C ABI of libsllg: stochastic Landau-Lifshitz-Gilbert spin
+ * dynamics of a classical Heisenberg system, integrated with the Heun
+ * predictor-corrector scheme on an AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of Evans et al., "Atomistic spin model simulations
+ * of magnetic nanomaterials" (J. Phys.: Condens. Matter 26, 103202 (2014),
+ * arXiv:1310.6143).  Section names below refer to that paper.
+ *
+ * Conventions for every call
+ *  - Units are SI (Table 1): moments mu_s in J/T, exchange J in joules per
+ *    link, anisotropy k_u in joules per atom, fields in tesla, time in
+ *    seconds, temperature in kelvin, energies in joules.
+ *  - Pointers named *_dev are device (HBM) pointers on the system's GPU; all
+ *    other array pointers are host pointers.
+ *  - Host inputs are copied during the call; the caller keeps ownership and
+ *    may free them on return.  Outputs go to caller-owned buffers.
+ *    Handles belong to the library until the matching destroy call.
+ *  - Every call returns an sllg_status.  On failure the handle is left as it
+ *    was before the call (except where a call says otherwise) and
+ *    sllg_last_error() holds a message.  No C++ exception crosses the ABI.
+ *  - A handle must not be used from two threads at the same time.
+ *  - `stream` is a hipStream_t on the system's device, or NULL for the
+ *    library's own stream.  Calls that take a stream return when the work
+ *    is finished (host outputs are complete).
+ */
+#ifndef SLLG_H
+#define SLLG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SLLG_OK = 0,
+    SLLG_E_ARG = -1,        /* an argument is invalid (range, shape, NaN, ...) */
+    SLLG_E_NOMEM = -2,      /* device or host allocation failed */
+    SLLG_E_DEVICE = -3,     /* a HIP runtime call failed */
+    SLLG_E_STATE = -4,      /* call not valid in the current state (e.g. not set up, not ready) */
+    SLLG_E_BUDGET = -5,     /* request does not fit the server's HBM budget */
+    SLLG_E_NUMERIC = -6,    /* the dynamics produced a non-finite value */
+    SLLG_E_CANCELLED = -7   /* the request was cancelled */
+} sllg_status;
+
+typedef enum { SLLG_FP32 = 0, SLLG_FP64 = 1 } sllg_precision;
+
+typedef struct sllg_system sllg_system;
+
+/* ---------------------------------------------------------------------------
+ * System set-up: the spin Hamiltonian (section "The classical spin
+ * Hamiltonian"), H = -sum_{i!=j} J_ij S_i.S_j - sum_i k_u (S_i.e_i)^2
+ *                    - sum_i mu_s S_i.H_app.
+ * ------------------------------------------------------------------------- */
+
+/* Create an empty system of n_spins spins on HIP device `device`.
+ * precision: SLLG_FP32 stores and integrates spins in single precision (the
+ * magnetisation and energy reductions are always double); SLLG_FP64 does
+ * everything in double.  1 <= n_spins < 2^28.  *out receives the handle.
+ * The device is opened at the first call that needs it (integration,
+ * measurement, reading spins back after integrating); set-up calls only
+ * validate and copy on the host.  Until sllg_set_spins every spin points
+ * along +z; the noise seed and step counter start at 0. */
+sllg_status sllg_create(int device, sllg_precision precision, int64_t n_spins, sllg_system **out);
+
+/* Release a system and all its device memory.  NULL is ignored. */
+void sllg_destroy(sllg_system *sys);
+
+/* Message describing the last failure on this handle ("" if none).  The
+ * string stays valid until the next call on the handle.  NULL -> message of
+ * the last failed sllg_create in this thread. */
+const char *sllg_last_error(const sllg_system *sys);
+
+/* Name of a status code. */
+const char *sllg_status_string(sllg_status status);
+
+/* Interaction list (section "Atomistic system generation": the per-atom
+ * list of exchange partners) in CSR form.  row_ptr[n+1] (row_ptr[0] = 0,
+ * non-decreasing); col[row_ptr[n]] neighbour indices in [0, n), no self
+ * links; ntype[row_ptr[n]] interaction types in [0, n_types), or NULL for
+ * all type 0; J[n_types] exchange constants in joules per link, 1 <= n_types
+ * <= 16.  At most 255 neighbours per site.  Each link must appear in both
+ * rows with the same type (the pair sum runs over i != j with J_ij = J_ji);
+ * this is checked unless the option "check_symmetry" is 0.  The exchange
+ * field on spin i is (1/mu_s,i) sum_k J[ntype[k]] S[col[k]]. */
+sllg_status sllg_set_neighbours(sllg_system *sys, const int64_t *row_ptr, const int32_t *col,
+                                const uint8_t *ntype, const double *J, int n_types);
+
+/* Atomic moments mu_s (J/T, > 0), uniaxial anisotropy constants k_u
+ * (J/atom, any sign) and easy axes e (unit vectors, normalised here).
+ * per_site = 0: one value each (mu_s[1], k_u[1], easy_axis[3]) for every
+ * site; per_site = 1: mu_s[n], k_u[n], easy_axis[3n].  At most 256 distinct
+ * (mu_s, k_u) pairs.  Section "The classical spin Hamiltonian", uniaxial
+ * anisotropy; anisotropy field 2 k_u / mu_s (section "Anisotropy energy"). */
+sllg_status sllg_set_materials(sllg_system *sys, const double *mu_s, const double *k_u,
+                               const double *easy_axis, int per_site);
+
+/* Damping lambda >= 0, gyromagnetic ratio gamma > 0 (1/(T s); Table 1 gives
+ * 1.76e11) and time step dt > 0 (s).  Section "Spin Dynamics" (atomistic LLG
+ * equation) and "Time Integration of the LLG Equation". */
+sllg_status sllg_set_integrator(sllg_system *sys, double alpha, double gamma, double dt);
+
+/* Temperature T >= 0 (K) of the Langevin heat bath (section "Langevin
+ * Dynamics": thermal field of width sqrt(2 lambda kB T / (gamma mu_s dt)))
+ * and applied field H_app[3] (T). */
+sllg_status sllg_set_conditions(sllg_system *sys, double temperature, const double H_app[3]);
+
+/* Noise stream: the thermal field of site i at step n is drawn from
+ * Philox4x32-10 with counter (i, n mod 2^32, n div 2^32, 0) and key
+ * (seed mod 2^32, seed div 2^32), turned into three normals by Box-Muller.
+ * `step` is the number of the next step; every integrated step increments
+ * it, so chunked integration equals one long call. */
+sllg_status sllg_set_rng(sllg_system *sys, uint64_t seed, uint64_t step);
+sllg_status sllg_get_step(const sllg_system *sys, uint64_t *step);
+
+/* Spin directions S[3n] (x, y, z per site).  Each must have finite, non-zero
+ * length; they are normalised here. */
+sllg_status sllg_set_spins(sllg_system *sys, const double *S);
+sllg_status sllg_get_spins(sllg_system *sys, double *S_out);
+
+/* ---------------------------------------------------------------------------
+ * Integration: Heun scheme (section "Time Integration of the LLG Equation").
+ * Each step: predictor S' = S + dS dt on every spin and renormalisation;
+ * effective field re-evaluated at S' with the same thermal field; corrector
+ * S <- S + (dS + dS')/2 dt and renormalisation.
+ * ------------------------------------------------------------------------- */
+
+/* Advance n_steps >= 0 steps.  After every step the reduced magnetisation
+ * m = sum mu_s S / sum mu_s is written to m_out[3*t..3*t+2] and the energy
+ * of the Hamiltonian above (thermal field excluded, each link once) to
+ * E_out[t], if those pointers are not NULL.  Returns SLLG_E_NUMERIC if an
+ * energy came out non-finite (the state is then kept as it is). */
+sllg_status sllg_integrate(sllg_system *sys, int64_t n_steps, double *m_out, double *E_out,
+                           void *stream);
+
+/* Same, with device output arrays m_dev[3*n_steps] and E_dev[n_steps] (either
+ * may be NULL); nothing is copied to the host.  Returns when the work has
+ * been queued on `stream`; the outputs are valid once the stream reaches
+ * that point. */
+sllg_status sllg_integrate_dev(sllg_system *sys, int64_t n_steps, double *m_dev, double *E_dev,
+                               void *stream);
+
+/* Observables of the current state: m[3] and E (either may be NULL). */
+sllg_status sllg_measure(sllg_system *sys, double m[3], double *E, void *stream);
+
+/* Thermal average (the M(T) protocol of the paper: equilibrate, then
+ * average with the magnetisation sampled every step).  Runs n_eq steps, then
+ * n_avg steps, and fills out[8] = { <|m|>, se(<|m|>), <m_x>, <m_y>, <m_z>,
+ * <E>, se(<E>), n_blocks }, where se is the standard error of the mean from
+ * n_blocks (>= 2, <= n_avg) equal consecutive blocks. */
+sllg_status sllg_average(sllg_system *sys, int64_t n_eq, int64_t n_avg, int n_blocks,
+                         double out[8], void *stream);
+
+/* Temperature ramp with continuation (section "Curie temperature": each
+ * point starts from the final state of the previous one): for each of the
+ * n_points temperatures T[k], set T, then sllg_average(n_eq, n_avg).
+ * out[8*k .. 8*k+7] receives the point's averages. */
+sllg_status sllg_sweep_temperature(sllg_system *sys, const double *T, int64_t n_points,
+                                   int64_t n_eq, int64_t n_avg, int n_blocks, double *out,
+                                   void *stream);
+
+/* Field sweep with continuation (hysteresis loop): for each applied field
+ * H[3*k .. 3*k+2], set it and run sllg_average(n_eq, n_avg); out as above. */
+sllg_status sllg_sweep_field(sllg_system *sys, const double *H, int64_t n_points, int64_t n_eq,
+                             int64_t n_avg, int n_blocks, double *out, void *stream);
+
+/* Thermal normals Gamma[3n] of sites 0..n-1 at step `step`, drawn exactly as
+ * the step kernels of the given precision draw them (Philox counter and
+ * Box-Muller as in sllg_set_rng), copied to the host array out.  For
+ * checking the noise stream; 1 <= n < 2^28. */
+sllg_status sllg_thermal_normals(int device, sllg_precision precision, uint64_t seed, uint64_t step,
+                                 int64_t n, double *out);
+
+/* ---------------------------------------------------------------------------
+ * Checkpoint / resume.  The state is the spins, the noise seed and the step
+ * counter; because the noise is counter-based, a restored run continues
+ * exactly as the uninterrupted one would.
+ * ------------------------------------------------------------------------- */
+sllg_status sllg_checkpoint_size(const sllg_system *sys, size_t *bytes);
+sllg_status sllg_checkpoint(sllg_system *sys, void *buf, size_t bytes);
+sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
+
+/* Tuning and behaviour options (integers):
+ *   "check_symmetry"  1 (default) / 0: verify J_ij = J_ji in set_neighbours
+ *   "graph_steps"     steps per captured HIP graph chunk, 0 = no graphs
+ *                     (default: chosen from the system size)
+ *   "block_sites"     sites per workgroup for the step kernels: 256 (default)
+ *   "xcd_remap"       1 (default) / 0: map consecutive site blocks to one XCD
+ */
+sllg_status sllg_set_option(sllg_system *sys, const char *key, int64_t value);
+sllg_status sllg_get_option(const sllg_system *sys, const char *key, int64_t *value);
+
+/* ---------------------------------------------------------------------------
+ * Serving: many independent systems ("statistical parallelism" of the
+ * paper's parallelisation appendix: independent runs for parameter sweeps or
+ * seeds) admitted by HBM budget and advanced together by one batched set of
+ * kernels, in chunks of steps.  Requests that arrive while others run join
+ * at the next chunk boundary (continuous batching).
+ * ------------------------------------------------------------------------- */
+typedef struct sllg_server sllg_server;
+
+typedef struct {
+    size_t hbm_budget;      /* bytes of device memory the server may use for requests */
+    int max_active;         /* most requests on the device at once (<= 4096) */
+    int chunk_steps;        /* steps per batched launch sequence (even, 2..4096) */
+    sllg_precision precision;
+} sllg_server_opts;
+
+typedef struct {
+    int64_t n_spins;
+    const int64_t *row_ptr;   /* CSR as in sllg_set_neighbours */
+    const int32_t *col;
+    const uint8_t *ntype;     /* or NULL */
+    const double *J;
+    int n_types;
+    const double *mu_s;       /* as in sllg_set_materials */
+    const double *k_u;
+    const double *easy_axis;
+    int per_site;
+    const double *S0;         /* initial spins [3n], or NULL for all along +z */
+    double alpha, gamma, dt;
+    double temperature;
+    double H_app[3];
+    uint64_t seed;
+    int64_t n_steps;          /* >= 1 */
+    int64_t n_avg;            /* the last n_avg steps are averaged (0 = none) */
+    int record;               /* 1: keep m and E of every step for sllg_fetch */
+} sllg_request;
+
+typedef enum {
+    SLLG_REQ_QUEUED = 0, SLLG_REQ_RUNNING = 1, SLLG_REQ_DONE = 2,
+    SLLG_REQ_FAILED = 3, SLLG_REQ_CANCELLED = 4
+} sllg_request_state;
+
+typedef struct {
+    int state;                /* sllg_request_state */
+    int status;               /* sllg_status of a failed request */
+    int64_t n_spins, n_steps, steps_done;
+    double m[3], E;           /* final reduced magnetisation and energy */
+    double avg[8];            /* averages over the last n_avg steps, as sllg_average */
+    double t_submit, t_start, t_done;   /* seconds on the server's clock */
+} sllg_result;
+
+typedef struct {
+    int64_t submitted, completed, failed, cancelled, active, queued;
+    size_t hbm_in_use, hbm_budget;
+    double spin_steps;        /* total spin-steps integrated so far */
+    double busy_seconds;      /* time with at least one active request */
+    int64_t chunks;           /* batched chunk launches so far */
+} sllg_server_stats;
+
+/* Start a server on `device`.  The server thread owns its own stream. */
+sllg_status sllg_server_create(int device, const sllg_server_opts *opts, sllg_server **out);
+/* Stop the server thread, cancel outstanding requests, free everything. */
+void sllg_server_destroy(sllg_server *srv);
+const char *sllg_server_last_error(const sllg_server *srv);
+/* Copy a request (inputs are copied) into the queue.  SLLG_E_BUDGET if it
+ * could never fit the budget on its own; SLLG_E_ARG if it is malformed. */
+sllg_status sllg_submit(sllg_server *srv, const sllg_request *req, uint64_t *ticket);
+/* Result so far; SLLG_OK always for a known ticket (check result->state). */
+sllg_status sllg_poll(sllg_server *srv, uint64_t ticket, sllg_result *result);
+/* Block until the request leaves the queue/running states or timeout_s passes
+ * (SLLG_E_STATE on timeout). */
+sllg_status sllg_wait(sllg_server *srv, uint64_t ticket, double timeout_s, sllg_result *result);
+/* Final spins S_out[3n] and, if recorded, m_series[3*n_steps], E_series[n_steps]
+ * of a finished request (any pointer may be NULL).  SLLG_E_STATE if not done. */
+sllg_status sllg_fetch(sllg_server *srv, uint64_t ticket, double *S_out, double *m_series,
+                       double *E_series);
+/* Cancel a queued or running request (it stops at the next chunk boundary). */
+sllg_status sllg_cancel(sllg_server *srv, uint64_t ticket);
+/* Forget a finished request and free its host copies. */
+sllg_status sllg_release(sllg_server *srv, uint64_t ticket);
+sllg_status sllg_server_get_stats(sllg_server *srv, sllg_server_stats *stats);
+/* The server's clock (seconds), the one t_submit/t_start/t_done use. */
+double sllg_server_clock(const sllg_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,442 @@
+"""Python binding of libsllg (stochastic LLG + Heun on MI355X).
+
+Argument marshalling only: every step of the dynamics runs in the HIP
+kernels of ``libsllg.so``; this module converts numpy arrays (and torch
+tensors / streams, when given) into the C ABI declared in
+``include/sllg.h``.  If the library is not built the import of any entry
+point raises at once; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsllg.so")
+
+FP32, FP64 = 0, 1
+STATUS = {0: "SLLG_OK", -1: "SLLG_E_ARG", -2: "SLLG_E_NOMEM", -3: "SLLG_E_DEVICE",
+          -4: "SLLG_E_STATE", -5: "SLLG_E_BUDGET", -6: "SLLG_E_NUMERIC", -7: "SLLG_E_CANCELLED"}
+
+# every symbol include/sllg.h declares
+EXPORTS = [
+    "sllg_create", "sllg_destroy", "sllg_last_error", "sllg_status_string", "sllg_set_neighbours",
+    "sllg_set_materials", "sllg_set_integrator", "sllg_set_conditions", "sllg_set_rng",
+    "sllg_get_step", "sllg_set_spins", "sllg_get_spins", "sllg_integrate", "sllg_integrate_dev",
+    "sllg_measure", "sllg_average", "sllg_sweep_temperature", "sllg_sweep_field",
+    "sllg_thermal_normals", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
+    "sllg_set_option", "sllg_get_option",
+    "sllg_server_create", "sllg_server_destroy", "sllg_server_last_error", "sllg_submit",
+    "sllg_poll", "sllg_wait", "sllg_fetch", "sllg_cancel", "sllg_release", "sllg_server_get_stats",
+    "sllg_server_clock",
+]
+
+
+class SllgError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+_lib = None
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+U64 = ctypes.c_uint64
+D = ctypes.c_double
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int),
+                ("chunk_steps", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n_spins", I64), ("row_ptr", P), ("col", P), ("ntype", P), ("J", P),
+                ("n_types", ctypes.c_int), ("mu_s", P), ("k_u", P), ("easy_axis", P),
+                ("per_site", ctypes.c_int), ("S0", P), ("alpha", D), ("gamma", D), ("dt", D),
+                ("temperature", D), ("H_app", D * 3), ("seed", U64), ("n_steps", I64),
+                ("n_avg", I64), ("record", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("status", ctypes.c_int), ("n_spins", I64), ("n_steps", I64),
+                ("steps_done", I64), ("m", D * 3), ("E", D), ("avg", D * 8), ("t_submit", D),
+                ("t_start", D), ("t_done", D)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", I64), ("completed", I64), ("failed", I64), ("cancelled", I64),
+                ("active", I64), ("queued", I64), ("hbm_in_use", ctypes.c_size_t),
+                ("hbm_budget", ctypes.c_size_t), ("spin_steps", D), ("busy_seconds", D),
+                ("chunks", I64)]
+
+
+def lib():
+    """Load libsllg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc, gfx950); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    c = ctypes.c_int
+    sig = {
+        "sllg_create": (c, [c, c, I64, ctypes.POINTER(P)]),
+        "sllg_destroy": (None, [P]),
+        "sllg_last_error": (ctypes.c_char_p, [P]),
+        "sllg_status_string": (ctypes.c_char_p, [c]),
+        "sllg_set_neighbours": (c, [P, P, P, P, P, c]),
+        "sllg_set_materials": (c, [P, P, P, P, c]),
+        "sllg_set_integrator": (c, [P, D, D, D]),
+        "sllg_set_conditions": (c, [P, D, P]),
+        "sllg_set_rng": (c, [P, U64, U64]),
+        "sllg_get_step": (c, [P, ctypes.POINTER(U64)]),
+        "sllg_set_spins": (c, [P, P]),
+        "sllg_get_spins": (c, [P, P]),
+        "sllg_integrate": (c, [P, I64, P, P, P]),
+        "sllg_integrate_dev": (c, [P, I64, P, P, P]),
+        "sllg_measure": (c, [P, P, P, P]),
+        "sllg_average": (c, [P, I64, I64, c, P, P]),
+        "sllg_sweep_temperature": (c, [P, P, I64, I64, I64, c, P, P]),
+        "sllg_sweep_field": (c, [P, P, I64, I64, I64, c, P, P]),
+        "sllg_thermal_normals": (c, [c, c, U64, U64, I64, P]),
+        "sllg_checkpoint_size": (c, [P, ctypes.POINTER(ctypes.c_size_t)]),
+        "sllg_checkpoint": (c, [P, P, ctypes.c_size_t]),
+        "sllg_restore": (c, [P, P, ctypes.c_size_t]),
+        "sllg_set_option": (c, [P, ctypes.c_char_p, I64]),
+        "sllg_get_option": (c, [P, ctypes.c_char_p, ctypes.POINTER(I64)]),
+        "sllg_server_create": (c, [c, ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]),
+        "sllg_server_destroy": (None, [P]),
+        "sllg_server_last_error": (ctypes.c_char_p, [P]),
+        "sllg_submit": (c, [P, ctypes.POINTER(Request), ctypes.POINTER(U64)]),
+        "sllg_poll": (c, [P, U64, ctypes.POINTER(Result)]),
+        "sllg_wait": (c, [P, U64, D, ctypes.POINTER(Result)]),
+        "sllg_fetch": (c, [P, U64, P, P, P]),
+        "sllg_cancel": (c, [P, U64]),
+        "sllg_release": (c, [P, U64]),
+        "sllg_server_get_stats": (c, [P, ctypes.POINTER(ServerStats)]),
+        "sllg_server_clock": (D, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(P)
+
+
+def _dev_ptr(x):
+    """Device pointer of a torch tensor (or an int address)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return P(x)
+    return P(x.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return P(stream)
+    return P(stream.cuda_stream)
+
+
+def _c64(a, dtype=np.float64, shape=None):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def thermal_normals(seed, step, n, precision=FP64, device=0):
+    """Gamma [n, 3] of sites 0..n-1 at one step, as the kernels draw them."""
+    out = np.empty((n, 3), dtype=np.float64)
+    st = lib().sllg_thermal_normals(device, precision, int(seed), int(step), int(n), _ptr(out))
+    if st != 0:
+        raise SllgError(st, "thermal_normals failed")
+    return out
+
+
+class SpinSystem:
+    """One spin system on the GPU (a handle of the C ABI)."""
+
+    def __init__(self, n, precision=FP32, device=0):
+        self._h = P()
+        L = lib()
+        st = L.sllg_create(int(device), int(precision), int(n), ctypes.byref(self._h))
+        if st != 0:
+            raise SllgError(st, L.sllg_last_error(None).decode())
+        self.n = int(n)
+        self.precision = precision
+
+    def close(self):
+        if self._h:
+            lib().sllg_destroy(self._h)
+            self._h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st):
+        if st != 0:
+            raise SllgError(st, lib().sllg_last_error(self._h).decode())
+
+    # ---- set-up ----------------------------------------------------------
+    def set_neighbours(self, row_ptr, col, ntype, J):
+        row_ptr = _c64(row_ptr, np.int64)
+        col = _c64(col, np.int32)
+        ntype = None if ntype is None else _c64(ntype, np.uint8)
+        J = _c64(np.atleast_1d(J))
+        self._check(lib().sllg_set_neighbours(self._h, _ptr(row_ptr), _ptr(col), _ptr(ntype), _ptr(J),
+                                              int(J.size)))
+
+    def set_materials(self, mu_s, k_u, easy_axis, per_site=None):
+        mu_s = _c64(np.atleast_1d(mu_s))
+        k_u = _c64(np.atleast_1d(k_u))
+        axis = _c64(easy_axis).reshape(-1)
+        if per_site is None:
+            per_site = 1 if mu_s.size > 1 else 0
+        self._check(lib().sllg_set_materials(self._h, _ptr(mu_s), _ptr(k_u), _ptr(axis), int(per_site)))
+
+    def set_integrator(self, alpha, gamma, dt):
+        self._check(lib().sllg_set_integrator(self._h, float(alpha), float(gamma), float(dt)))
+
+    def set_conditions(self, temperature, H=(0.0, 0.0, 0.0)):
+        H = _c64(H)
+        self._check(lib().sllg_set_conditions(self._h, float(temperature), _ptr(H)))
+
+    def set_rng(self, seed, step=0):
+        self._check(lib().sllg_set_rng(self._h, int(seed), int(step)))
+
+    @property
+    def step(self):
+        v = U64()
+        self._check(lib().sllg_get_step(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def set_spins(self, S):
+        S = _c64(S).reshape(-1)
+        self._check(lib().sllg_set_spins(self._h, _ptr(S)))
+
+    def get_spins(self):
+        out = np.empty((self.n, 3))
+        self._check(lib().sllg_get_spins(self._h, _ptr(out)))
+        return out
+
+    def set_option(self, key, value):
+        self._check(lib().sllg_set_option(self._h, key.encode(), int(value)))
+
+    def get_option(self, key):
+        v = I64()
+        self._check(lib().sllg_get_option(self._h, key.encode(), ctypes.byref(v)))
+        return int(v.value)
+
+    # ---- dynamics --------------------------------------------------------
+    def integrate(self, n_steps, record=True, stream=None):
+        """Advance n_steps; returns (m [n,3], E [n]) when record else (None, None)."""
+        m = np.empty((n_steps, 3)) if record else None
+        E = np.empty(n_steps) if record else None
+        self._check(lib().sllg_integrate(self._h, int(n_steps), _ptr(m), _ptr(E), _stream(stream)))
+        return m, E
+
+    def integrate_dev(self, n_steps, m_dev=None, E_dev=None, stream=None):
+        """Advance n_steps with m/E written to device tensors (torch) or raw
+        addresses; asynchronous on `stream` (a torch stream or address)."""
+        self._check(lib().sllg_integrate_dev(self._h, int(n_steps), _dev_ptr(m_dev), _dev_ptr(E_dev),
+                                             _stream(stream)))
+
+    def measure(self):
+        m = np.empty(3)
+        E = np.empty(1)
+        self._check(lib().sllg_measure(self._h, _ptr(m), _ptr(E), None))
+        return m, float(E[0])
+
+    def average(self, n_eq, n_avg, n_blocks=10):
+        out = np.empty(8)
+        self._check(lib().sllg_average(self._h, int(n_eq), int(n_avg), int(n_blocks), _ptr(out), None))
+        return _avg_dict(out)
+
+    def sweep_temperature(self, temperatures, n_eq, n_avg, n_blocks=10):
+        T = _c64(temperatures)
+        out = np.empty((T.size, 8))
+        self._check(lib().sllg_sweep_temperature(self._h, _ptr(T), T.size, int(n_eq), int(n_avg),
+                                                 int(n_blocks), _ptr(out), None))
+        return [_avg_dict(r) | {"T": float(t)} for r, t in zip(out, T)]
+
+    def sweep_field(self, fields, n_eq, n_avg, n_blocks=10):
+        H = _c64(fields).reshape(-1, 3)
+        out = np.empty((H.shape[0], 8))
+        self._check(lib().sllg_sweep_field(self._h, _ptr(np.ascontiguousarray(H)), H.shape[0], int(n_eq),
+                                           int(n_avg), int(n_blocks), _ptr(out), None))
+        return [_avg_dict(r) | {"H": h.copy()} for r, h in zip(out, H)]
+
+    def checkpoint(self):
+        size = ctypes.c_size_t()
+        self._check(lib().sllg_checkpoint_size(self._h, ctypes.byref(size)))
+        buf = np.empty(size.value, dtype=np.uint8)
+        self._check(lib().sllg_checkpoint(self._h, _ptr(buf), size.value))
+        return buf.tobytes()
+
+    def restore(self, blob):
+        buf = np.frombuffer(blob, dtype=np.uint8).copy()
+        self._check(lib().sllg_restore(self._h, _ptr(buf), buf.size))
+
+
+def _avg_dict(o):
+    return {"m_abs": float(o[0]), "m_abs_se": float(o[1]), "m": np.array(o[2:5]), "E": float(o[5]),
+            "E_se": float(o[6]), "n_blocks": int(o[7])}
+
+
+def from_workload(w, precision=FP32, device=0, check_symmetry=True):
+    """Build a SpinSystem from a spin_systems.Workload-like object."""
+    s = SpinSystem(w.lattice.n, precision, device)
+    if not check_symmetry:
+        s.set_option("check_symmetry", 0)
+    lat = w.lattice
+    s.set_neighbours(lat.row_ptr, lat.col, lat.ntype, w.J)
+    mu, ku, ax = np.asarray(w.mu_s), np.asarray(w.k_u), np.asarray(w.easy_axis)
+    uniform = bool(np.all(mu == mu[0]) and np.all(ku == ku[0]) and np.all(ax == ax[0]))
+    if uniform:
+        s.set_materials(mu[:1], ku[:1], ax[:1], per_site=0)
+    else:
+        s.set_materials(mu, ku, ax, per_site=1)
+    s.set_integrator(w.alpha, w.gamma, w.dt)
+    s.set_conditions(w.temperature, w.H)
+    s.set_rng(w.seed, 0)
+    s.set_spins(w.S0)
+    return s
+
+
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
+
+
+def _result_dict(r):
+    return {"state": REQ_STATES.get(r.state, r.state), "status": STATUS.get(r.status, r.status),
+            "n_spins": r.n_spins, "n_steps": r.n_steps, "steps_done": r.steps_done,
+            "m": np.array(r.m[:]), "E": r.E, "avg": _avg_dict(np.array(r.avg[:])),
+            "t_submit": r.t_submit, "t_start": r.t_start, "t_done": r.t_done}
+
+
+class Server:
+    """Continuous-batching request server (sllg_server_* of the C ABI)."""
+
+    def __init__(self, hbm_budget=4 << 30, max_active=256, chunk_steps=64, precision=FP32, device=0):
+        self._h = P()
+        opts = ServerOpts(int(hbm_budget), int(max_active), int(chunk_steps), int(precision))
+        st = lib().sllg_server_create(int(device), ctypes.byref(opts), ctypes.byref(self._h))
+        if st != 0:
+            raise SllgError(st, "server create failed")
+        self.precision = precision
+        self._keep = {}
+
+    def close(self):
+        if self._h:
+            lib().sllg_server_destroy(self._h)
+            self._h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st):
+        if st != 0:
+            raise SllgError(st, lib().sllg_server_last_error(self._h).decode())
+
+    def submit(self, w, n_steps=None, n_avg=0, record=False, S0=None):
+        """Queue one request built from a spin_systems.Workload (initial
+        spins: S0 if given, else the workload's own)."""
+        if S0 is None:
+            S0 = w.S0
+        lat = w.lattice
+        n = lat.n
+        arrays = {
+            "row_ptr": _c64(lat.row_ptr, np.int64), "col": _c64(lat.col, np.int32),
+            "ntype": _c64(lat.ntype, np.uint8), "J": _c64(np.atleast_1d(w.J)),
+        }
+        mu, ku, ax = np.asarray(w.mu_s), np.asarray(w.k_u), np.asarray(w.easy_axis)
+        uniform = bool(np.all(mu == mu[0]) and np.all(ku == ku[0]) and np.all(ax == ax[0]))
+        if uniform:
+            arrays.update(mu_s=_c64(mu[:1]), k_u=_c64(ku[:1]), easy_axis=_c64(ax[:1]).reshape(-1))
+        else:
+            arrays.update(mu_s=_c64(mu), k_u=_c64(ku), easy_axis=_c64(ax).reshape(-1))
+        if S0 is not None:
+            arrays["S0"] = _c64(S0).reshape(-1)
+        req = Request()
+        req.n_spins = n
+        req.row_ptr, req.col, req.ntype, req.J = (arrays[k].ctypes.data for k in ("row_ptr", "col", "ntype", "J"))
+        req.n_types = arrays["J"].size
+        req.mu_s, req.k_u, req.easy_axis = (arrays[k].ctypes.data for k in ("mu_s", "k_u", "easy_axis"))
+        req.per_site = 0 if uniform else 1
+        req.S0 = arrays["S0"].ctypes.data if "S0" in arrays else None
+        req.alpha, req.gamma, req.dt, req.temperature = float(w.alpha), float(w.gamma), float(w.dt), float(w.temperature)
+        req.H_app = (D * 3)(*[float(v) for v in w.H])
+        req.seed = int(w.seed)
+        req.n_steps = int(w.n_steps if n_steps is None else n_steps)
+        req.n_avg = int(n_avg)
+        req.record = 1 if record else 0
+        t = U64()
+        self._check(lib().sllg_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (n, req.n_steps, bool(record))
+        return int(t.value)
+
+    def poll(self, ticket):
+        r = Result()
+        self._check(lib().sllg_poll(self._h, int(ticket), ctypes.byref(r)))
+        return _result_dict(r)
+
+    def wait(self, ticket, timeout=60.0):
+        r = Result()
+        st = lib().sllg_wait(self._h, int(ticket), float(timeout), ctypes.byref(r))
+        if st != 0:
+            raise SllgError(st, f"request {ticket} not finished within {timeout} s")
+        return _result_dict(r)
+
+    def fetch(self, ticket):
+        """(final spins, m series or None, E series or None) of a finished request."""
+        n, n_steps, record = self._keep[ticket]
+        S = np.empty((n, 3))
+        m = np.empty((n_steps, 3)) if record else None
+        E = np.empty(n_steps) if record else None
+        self._check(lib().sllg_fetch(self._h, int(ticket), _ptr(S), _ptr(m), _ptr(E)))
+        return S, m, E
+
+    def cancel(self, ticket):
+        self._check(lib().sllg_cancel(self._h, int(ticket)))
+
+    def release(self, ticket):
+        self._check(lib().sllg_release(self._h, int(ticket)))
+        self._keep.pop(ticket, None)
+
+    def stats(self):
+        s = ServerStats()
+        self._check(lib().sllg_server_get_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in ServerStats._fields_}
+
+    def clock(self):
+        return float(lib().sllg_server_clock(self._h))

@@ -1,0 +1,748 @@
+// C ABI of a single spin system (see include/sllg.h).  A system is a batch
+// of one replica; host-side set-up is kept until the first call that needs
+// the device, then uploaded once.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sllg.h"
+#include "batch.hpp"
+#include "kernels.hpp"
+#include "prepare.hpp"
+
+using namespace sllg;
+
+namespace {
+
+// Fields of the replica record that the host loop edits, independent of the
+// precision.
+struct ReplicaDevBase {
+    double** records;
+    double** acc;
+    int32_t* flags;
+    int32_t* nsteps;
+    int64_t* rec_pos;
+    int64_t* avg_first;
+    int64_t* avg_block_len;
+    int32_t* avg_blocks;
+};
+
+thread_local std::string g_create_error;
+
+constexpr int kAvgCap = 4096;           // most averaging blocks per call
+constexpr int64_t kHostChunk = 1024;    // steps per chunk without graphs
+
+// Precision-independent interface of the one-replica engine.
+struct Engine {
+    virtual ~Engine() = default;
+    virtual void create(const HostStructure& s, const HostMaterials& m, const Dynamics& d,
+                        const std::vector<double>& S, int64_t rec_cap) = 0;
+    virtual void set_spins(const std::vector<double>& S) = 0;
+    virtual void get_spins(double* out, hipStream_t st) = 0;
+    virtual void set_dynamics(const HostStructure& s, const HostMaterials& m, const Dynamics& d) = 0;
+    virtual ReplicaDevBase& rec() = 0;
+    virtual void run_chunk(int K, hipStream_t st, bool graph) = 0;
+    virtual void measure_now(hipStream_t st) = 0;
+    virtual void set_remap(int v) = 0;
+    virtual void mark_dirty() = 0;           // the record mirror changed
+    virtual uint64_t step() = 0;
+    virtual void set_step(uint64_t step) = 0;
+    virtual int64_t rec_cap() = 0;
+};
+
+}  // namespace
+
+namespace {
+
+template <typename R>
+struct EngineT final : Engine {
+    explicit EngineT(int device) : batch(device, &alloc, 1) {}
+    DirectAllocator alloc;
+    Batch<R> batch;
+    int q = -1;
+    int64_t cap = 0;
+    ReplicaDevBase view{};
+
+    void bind()
+    {
+        ReplicaDev<R>& r = batch.mirror(q);
+        view = ReplicaDevBase{&r.records, &r.acc, &r.flags, &r.nsteps, &r.rec_pos,
+                              &r.avg_first, &r.avg_block_len, &r.avg_blocks};
+    }
+    void create(const HostStructure& s, const HostMaterials& m, const Dynamics& d,
+                const std::vector<double>& S, int64_t rec_cap) override
+    {
+        q = batch.add(s, m, d, S, rec_cap, kAvgCap);
+        cap = rec_cap;
+        bind();
+    }
+    void set_spins(const std::vector<double>& S) override { batch.set_spins(q, S); }
+    void get_spins(double* out, hipStream_t st) override { batch.get_spins(q, out, st); }
+    void set_dynamics(const HostStructure& s, const HostMaterials& m, const Dynamics& d) override
+    {
+        ReplicaDev<R>& r = batch.mirror(q);
+        const uint64_t step = r.step;   // the device-side counter is authoritative
+        Dynamics dd = d;
+        dd.step = step;
+        fill_parameters(r, s, m, dd);
+        batch.upload_materials(q, m, dd);
+        batch.mark_dirty();
+    }
+    ReplicaDevBase& rec() override { return view; }
+    void run_chunk(int K, hipStream_t st, bool graph) override { batch.run_chunk(K, st, graph); }
+    void measure_now(hipStream_t st) override { batch.measure_now(st); }
+    void set_remap(int v) override { batch.set_remap(v); }
+    void mark_dirty() override { batch.mark_dirty(); }
+    uint64_t step() override { return batch.mirror(q).step; }
+    void set_step(uint64_t step) override
+    {
+        batch.mirror(q).step = step;
+        batch.mark_dirty();
+    }
+    int64_t rec_cap() override { return cap; }
+};
+
+}  // namespace
+
+struct sllg_system {
+    int device = 0;
+    sllg_precision prec = SLLG_FP32;
+    int64_t n = 0;
+    std::string err;
+    bool has_nb = false, has_mat = false, has_int = false;
+    HostStructure st;
+    HostMaterials mat;
+    Dynamics dyn;
+    std::vector<double> spins;       // host state until the engine exists
+    int64_t opt_check_symmetry = 1;
+    int64_t opt_graph_steps = -1;    // -1 = automatic
+    int64_t opt_block_sites = kBlockSites;
+    int64_t opt_xcd_remap = 1;
+    hipStream_t own = nullptr;
+    std::unique_ptr<Engine> eng;
+    std::vector<double> staging;
+};
+
+namespace {
+
+sllg_status guard(sllg_system* sys, const std::function<void()>& fn);
+
+int64_t graph_steps(const sllg_system* s)
+{
+    if (s->opt_graph_steps >= 0)
+        return s->opt_graph_steps & ~int64_t(1);
+    return s->n < (int64_t(1) << 20) ? 64 : 0;
+}
+
+void ensure_device(sllg_system* s);
+void require_ready(sllg_system* s);
+
+// The caller's stream, or the library's own (opening the device if needed);
+// every caller needs a fully set-up system.
+hipStream_t pick_stream(sllg_system* s, void* stream)
+{
+    require_ready(s);
+    ensure_device(s);
+    return stream ? (hipStream_t)stream : s->own;
+}
+
+void require_ready(sllg_system* s)
+{
+    if (!s->has_nb)
+        fail(SLLG_E_STATE, "neighbour list not set (sllg_set_neighbours)");
+    if (!s->has_mat)
+        fail(SLLG_E_STATE, "materials not set (sllg_set_materials)");
+    if (!s->has_int)
+        fail(SLLG_E_STATE, "integrator not set (sllg_set_integrator)");
+}
+
+// The device is checked and the library stream created at the first call
+// that needs the GPU, so host-side set-up and validation work without one.
+void ensure_device(sllg_system* s)
+{
+    if (s->own)
+        return;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || s->device >= count)
+        fail(SLLG_E_DEVICE, "HIP device " + std::to_string(s->device) + " is not available");
+    hip_check(hipSetDevice(s->device), "hipSetDevice");
+    hip_check(hipStreamCreateWithFlags(&s->own, hipStreamNonBlocking), "hipStreamCreate");
+}
+
+Engine& engine(sllg_system* s)
+{
+    require_ready(s);
+    ensure_device(s);
+    if (!s->eng) {
+        hip_check(hipSetDevice(s->device), "hipSetDevice");
+        if (s->prec == SLLG_FP32)
+            s->eng = std::make_unique<EngineT<float>>(s->device);
+        else
+            s->eng = std::make_unique<EngineT<double>>(s->device);
+        const int64_t G = graph_steps(s);
+        s->eng->create(s->st, s->mat, s->dyn, s->spins, std::max<int64_t>(G, kHostChunk));
+        s->eng->set_remap((int)s->opt_xcd_remap);
+    }
+    hip_check(hipSetDevice(s->device), "hipSetDevice");
+    return *s->eng;
+}
+
+// Tear the engine down after a structural change, keeping the spins and the
+// step counter.
+void drop_engine(sllg_system* s)
+{
+    if (!s->eng)
+        return;
+    s->spins.assign(3 * (size_t)s->n, 0.0);
+    s->eng->get_spins(s->spins.data(), s->own);
+    s->dyn.step = s->eng->step();
+    s->eng.reset();
+}
+
+sllg_status guard(sllg_system* sys, const std::function<void()>& fn)
+{
+    if (!sys)
+        return SLLG_E_ARG;
+    try {
+        fn();
+        sys->err.clear();
+        return SLLG_OK;
+    } catch (const Failure& f) {
+        sys->err = f.msg;
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        sys->err = "host allocation failed";
+        return SLLG_E_NOMEM;
+    } catch (const std::exception& e) {
+        sys->err = e.what();
+        return SLLG_E_DEVICE;
+    } catch (...) {
+        sys->err = "unknown failure";
+        return SLLG_E_DEVICE;
+    }
+}
+
+// Advance n steps in chunks; records (m, E) of each step go to the host
+// arrays and/or the device arrays given.
+void run_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, double* m_dev,
+               double* E_dev, hipStream_t st, int32_t extra_flags)
+{
+    Engine& e = engine(s);
+    ReplicaDevBase& r = e.rec();
+    const bool host_rec = m_out || E_out;
+    const bool dev_rec = m_dev || E_dev;
+    const bool record = host_rec || dev_rec || (extra_flags & kAverage);
+    const int64_t G = graph_steps(s);
+    const int64_t chunk = G > 0 ? G : std::min<int64_t>(kHostChunk, e.rec_cap());
+    const int32_t flags =
+        (*r.flags & ~(kRecord | kRecordSeries | kAverage)) | (record ? kRecord : 0) | extra_flags;
+    if (flags != *r.flags || *r.rec_pos != 0) {
+        *r.flags = flags;
+        *r.rec_pos = 0;
+        e.mark_dirty();
+    }
+    int64_t done = 0;
+    bool bad = false;
+    while (done < n_steps) {
+        const int64_t ns = std::min<int64_t>(chunk, n_steps - done);
+        if (*r.nsteps != (int32_t)ns || *r.flags != flags) {
+            *r.nsteps = (int32_t)ns;
+            *r.flags = flags;
+            e.mark_dirty();
+        }
+        const bool use_graph = G > 0 && ns == G;
+        e.run_chunk((int)(use_graph ? G : ns), st, use_graph);
+        if (dev_rec)
+            hip_check(launch_scatter_records(*r.records, (int)ns, m_dev ? m_dev + 3 * done : nullptr,
+                                             E_dev ? E_dev + done : nullptr, st),
+                      "scatter records");
+        if (host_rec) {
+            s->staging.resize(4 * (size_t)ns);
+            hip_check(hipMemcpyAsync(s->staging.data(), *r.records, 32 * (size_t)ns, hipMemcpyDeviceToHost, st),
+                      "download records");
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            for (int64_t t = 0; t < ns; ++t) {
+                const double* rec = &s->staging[4 * (size_t)t];
+                if (m_out) {
+                    m_out[3 * (done + t)] = rec[0];
+                    m_out[3 * (done + t) + 1] = rec[1];
+                    m_out[3 * (done + t) + 2] = rec[2];
+                }
+                if (E_out)
+                    E_out[done + t] = rec[3];
+                if (!std::isfinite(rec[3]))
+                    bad = true;
+            }
+        }
+        done += ns;
+    }
+    if (bad)
+        fail(SLLG_E_NUMERIC, "the energy became non-finite during integration");
+}
+
+void measure_state(sllg_system* s, double m[3], double* E, hipStream_t st)
+{
+    Engine& e = engine(s);
+    ReplicaDevBase& r = e.rec();
+    const int32_t saved = *r.flags;
+    *r.flags = (saved & ~(kRecordSeries | kAverage)) | kRecord;
+    *r.rec_pos = 0;
+    e.mark_dirty();
+    e.measure_now(st);
+    double rec[4];
+    hip_check(hipMemcpy(rec, *r.records, sizeof(rec), hipMemcpyDeviceToHost), "download record");
+    if (m) {
+        m[0] = rec[0];
+        m[1] = rec[1];
+        m[2] = rec[2];
+    }
+    if (E)
+        *E = rec[3];
+    *r.flags = saved;
+    e.mark_dirty();
+    if (!std::isfinite(rec[3]))
+        fail(SLLG_E_NUMERIC, "the energy of the current state is not finite");
+}
+
+void average(sllg_system* s, int64_t n_eq, int64_t n_avg, int n_blocks, double out[8], hipStream_t st)
+{
+    if (n_eq < 0 || n_avg < 1)
+        fail(SLLG_E_ARG, "need n_eq >= 0 and n_avg >= 1");
+    if (n_blocks < 2 || n_blocks > kAvgCap || n_blocks > n_avg)
+        fail(SLLG_E_ARG, "n_blocks must be in 2..min(n_avg, 4096)");
+    if (!out)
+        fail(SLLG_E_ARG, "out must not be NULL");
+    Engine& e = engine(s);
+    ReplicaDevBase& r = e.rec();
+    const int64_t block_len = n_avg / n_blocks;
+    hip_check(hipMemsetAsync(*r.acc, 0, sizeof(double) * 5 * (size_t)n_blocks, st), "clear sums");
+    run_steps(s, n_eq, nullptr, nullptr, nullptr, nullptr, st, 0);
+    *r.avg_first = (int64_t)e.step();
+    *r.avg_block_len = block_len;
+    *r.avg_blocks = n_blocks;
+    e.mark_dirty();
+    run_steps(s, n_avg, nullptr, nullptr, nullptr, nullptr, st, kAverage);
+    std::vector<double> acc(5 * (size_t)n_blocks);
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    hip_check(hipMemcpy(acc.data(), *r.acc, acc.size() * sizeof(double), hipMemcpyDeviceToHost),
+              "download sums");
+    *r.flags &= ~kAverage;
+    e.mark_dirty();
+    averages_from_block_sums(acc.data(), n_blocks, block_len, out);
+    if (!std::isfinite(out[5]))
+        fail(SLLG_E_NUMERIC, "the energy became non-finite during averaging");
+}
+
+void apply_dynamics(sllg_system* s)
+{
+    if (s->eng)
+        s->eng->set_dynamics(s->st, s->mat, s->dyn);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sllg_status_string(sllg_status status)
+{
+    switch (status) {
+    case SLLG_OK: return "SLLG_OK";
+    case SLLG_E_ARG: return "SLLG_E_ARG";
+    case SLLG_E_NOMEM: return "SLLG_E_NOMEM";
+    case SLLG_E_DEVICE: return "SLLG_E_DEVICE";
+    case SLLG_E_STATE: return "SLLG_E_STATE";
+    case SLLG_E_BUDGET: return "SLLG_E_BUDGET";
+    case SLLG_E_NUMERIC: return "SLLG_E_NUMERIC";
+    case SLLG_E_CANCELLED: return "SLLG_E_CANCELLED";
+    }
+    return "unknown status";
+}
+
+sllg_status sllg_create(int device, sllg_precision precision, int64_t n_spins, sllg_system** out)
+{
+    if (!out) {
+        g_create_error = "out must not be NULL";
+        return SLLG_E_ARG;
+    }
+    *out = nullptr;
+    if (precision != SLLG_FP32 && precision != SLLG_FP64) {
+        g_create_error = "precision must be SLLG_FP32 or SLLG_FP64";
+        return SLLG_E_ARG;
+    }
+    if (n_spins < 1 || n_spins >= (int64_t(1) << kColBits)) {
+        g_create_error = "n_spins must be in 1 .. 2^28-1";
+        return SLLG_E_ARG;
+    }
+    if (device < 0) {
+        g_create_error = "device must be >= 0";
+        return SLLG_E_ARG;
+    }
+    auto* s = new (std::nothrow) sllg_system();
+    if (!s) {
+        g_create_error = "host allocation failed";
+        return SLLG_E_NOMEM;
+    }
+    s->device = device;
+    s->prec = precision;
+    s->n = n_spins;
+    s->spins.assign(3 * (size_t)n_spins, 0.0);
+    for (int64_t i = 0; i < n_spins; ++i)
+        s->spins[3 * i + 2] = 1.0;
+    g_create_error.clear();
+    *out = s;
+    return SLLG_OK;
+}
+
+void sllg_destroy(sllg_system* sys)
+{
+    if (!sys)
+        return;
+    if (sys->own) {
+        (void)hipSetDevice(sys->device);
+        (void)hipStreamSynchronize(sys->own);
+    }
+    sys->eng.reset();
+    if (sys->own)
+        (void)hipStreamDestroy(sys->own);
+    delete sys;
+}
+
+const char* sllg_last_error(const sllg_system* sys)
+{
+    return sys ? sys->err.c_str() : g_create_error.c_str();
+}
+
+sllg_status sllg_set_neighbours(sllg_system* sys, const int64_t* row_ptr, const int32_t* col,
+                                const uint8_t* ntype, const double* J, int n_types)
+{
+    return guard(sys, [&] {
+        HostStructure st = build_structure(sys->n, row_ptr, col, ntype, J, n_types,
+                                           sys->opt_check_symmetry != 0);
+        drop_engine(sys);
+        sys->st = std::move(st);
+        sys->has_nb = true;
+    });
+}
+
+sllg_status sllg_set_materials(sllg_system* sys, const double* mu_s, const double* k_u,
+                               const double* easy_axis, int per_site)
+{
+    return guard(sys, [&] {
+        HostMaterials m = build_materials(sys->n, mu_s, k_u, easy_axis, per_site);
+        if (sys->eng && m.per_site_material == sys->mat.per_site_material &&
+            m.per_site_axis == sys->mat.per_site_axis && !m.per_site_material && !m.per_site_axis &&
+            m.mat_mu.size() == sys->mat.mat_mu.size()) {
+            sys->mat = std::move(m);
+            apply_dynamics(sys);   // uniform materials: a table update suffices
+        } else {
+            drop_engine(sys);
+            sys->mat = std::move(m);
+        }
+        sys->has_mat = true;
+    });
+}
+
+sllg_status sllg_set_integrator(sllg_system* sys, double alpha, double gamma, double dt)
+{
+    return guard(sys, [&] {
+        Dynamics d = sys->dyn;
+        d.alpha = alpha;
+        d.gamma = gamma;
+        d.dt = dt;
+        check_dynamics(d);
+        if (sys->eng)
+            d.step = sys->eng->step();
+        sys->dyn = d;
+        sys->has_int = true;
+        apply_dynamics(sys);
+    });
+}
+
+sllg_status sllg_set_conditions(sllg_system* sys, double temperature, const double H_app[3])
+{
+    return guard(sys, [&] {
+        if (!H_app)
+            fail(SLLG_E_ARG, "H_app must not be NULL");
+        Dynamics d = sys->dyn;
+        d.temperature = temperature;
+        d.H[0] = H_app[0];
+        d.H[1] = H_app[1];
+        d.H[2] = H_app[2];
+        if (!(temperature >= 0.0) || !std::isfinite(temperature))
+            fail(SLLG_E_ARG, "temperature must be finite and >= 0");
+        for (int c = 0; c < 3; ++c)
+            if (!std::isfinite(d.H[c]))
+                fail(SLLG_E_ARG, "applied field must be finite");
+        if (sys->eng)
+            d.step = sys->eng->step();
+        sys->dyn = d;
+        if (sys->has_int)
+            apply_dynamics(sys);
+    });
+}
+
+sllg_status sllg_set_rng(sllg_system* sys, uint64_t seed, uint64_t step)
+{
+    return guard(sys, [&] {
+        sys->dyn.seed = seed;
+        sys->dyn.step = step;
+        if (sys->eng) {
+            // set_dynamics keeps the engine's counter; overwrite it explicitly
+            sys->eng->set_dynamics(sys->st, sys->mat, sys->dyn);
+            sys->eng->set_step(step);
+        }
+    });
+}
+
+sllg_status sllg_get_step(const sllg_system* sys, uint64_t* step)
+{
+    if (!sys || !step)
+        return SLLG_E_ARG;
+    *step = sys->eng ? sys->eng->step() : sys->dyn.step;
+    return SLLG_OK;
+}
+
+sllg_status sllg_set_spins(sllg_system* sys, const double* S)
+{
+    return guard(sys, [&] {
+        std::vector<double> v = normalised_spins(sys->n, S);
+        if (sys->eng) {
+            hip_check(hipSetDevice(sys->device), "hipSetDevice");
+            sys->eng->set_spins(v);
+        } else {
+            sys->spins = std::move(v);
+        }
+    });
+}
+
+sllg_status sllg_get_spins(sllg_system* sys, double* S_out)
+{
+    return guard(sys, [&] {
+        if (!S_out)
+            fail(SLLG_E_ARG, "S_out must not be NULL");
+        if (sys->eng) {
+            hip_check(hipSetDevice(sys->device), "hipSetDevice");
+            sys->eng->get_spins(S_out, sys->own);
+        } else {
+            std::memcpy(S_out, sys->spins.data(), sys->spins.size() * sizeof(double));
+        }
+    });
+}
+
+sllg_status sllg_integrate(sllg_system* sys, int64_t n_steps, double* m_out, double* E_out, void* stream)
+{
+    return guard(sys, [&] {
+        if (n_steps < 0)
+            fail(SLLG_E_ARG, "n_steps must be >= 0");
+        hipStream_t st = pick_stream(sys, stream);
+        run_steps(sys, n_steps, m_out, E_out, nullptr, nullptr, st, 0);
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (!m_out && !E_out && n_steps > 0) {
+            double E;
+            measure_state(sys, nullptr, &E, st);
+        }
+    });
+}
+
+sllg_status sllg_integrate_dev(sllg_system* sys, int64_t n_steps, double* m_dev, double* E_dev, void* stream)
+{
+    return guard(sys, [&] {
+        if (n_steps < 0)
+            fail(SLLG_E_ARG, "n_steps must be >= 0");
+        run_steps(sys, n_steps, nullptr, nullptr, m_dev, E_dev, pick_stream(sys, stream), 0);
+    });
+}
+
+sllg_status sllg_measure(sllg_system* sys, double m[3], double* E, void* stream)
+{
+    return guard(sys, [&] { measure_state(sys, m, E, pick_stream(sys, stream)); });
+}
+
+sllg_status sllg_average(sllg_system* sys, int64_t n_eq, int64_t n_avg, int n_blocks, double out[8],
+                         void* stream)
+{
+    return guard(sys, [&] { average(sys, n_eq, n_avg, n_blocks, out, pick_stream(sys, stream)); });
+}
+
+sllg_status sllg_sweep_temperature(sllg_system* sys, const double* T, int64_t n_points, int64_t n_eq,
+                                   int64_t n_avg, int n_blocks, double* out, void* stream)
+{
+    return guard(sys, [&] {
+        if (!T || !out || n_points < 0)
+            fail(SLLG_E_ARG, "T and out must not be NULL");
+        for (int64_t k = 0; k < n_points; ++k)
+            if (!(T[k] >= 0.0) || !std::isfinite(T[k]))
+                fail(SLLG_E_ARG, "temperatures must be finite and >= 0");
+        hipStream_t st = pick_stream(sys, stream);
+        for (int64_t k = 0; k < n_points; ++k) {
+            Engine& e = engine(sys);
+            sys->dyn.temperature = T[k];
+            sys->dyn.step = e.step();
+            apply_dynamics(sys);
+            average(sys, n_eq, n_avg, n_blocks, out + 8 * k, st);
+        }
+    });
+}
+
+sllg_status sllg_sweep_field(sllg_system* sys, const double* H, int64_t n_points, int64_t n_eq,
+                             int64_t n_avg, int n_blocks, double* out, void* stream)
+{
+    return guard(sys, [&] {
+        if (!H || !out || n_points < 0)
+            fail(SLLG_E_ARG, "H and out must not be NULL");
+        for (int64_t k = 0; k < 3 * n_points; ++k)
+            if (!std::isfinite(H[k]))
+                fail(SLLG_E_ARG, "fields must be finite");
+        hipStream_t st = pick_stream(sys, stream);
+        for (int64_t k = 0; k < n_points; ++k) {
+            Engine& e = engine(sys);
+            sys->dyn.H[0] = H[3 * k];
+            sys->dyn.H[1] = H[3 * k + 1];
+            sys->dyn.H[2] = H[3 * k + 2];
+            sys->dyn.step = e.step();
+            apply_dynamics(sys);
+            average(sys, n_eq, n_avg, n_blocks, out + 8 * k, st);
+        }
+    });
+}
+
+namespace {
+struct CheckpointHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t precision;
+    int64_t n;
+    uint64_t seed;
+    uint64_t step;
+};
+}  // namespace
+
+sllg_status sllg_checkpoint_size(const sllg_system* sys, size_t* bytes)
+{
+    if (!sys || !bytes)
+        return SLLG_E_ARG;
+    *bytes = sizeof(CheckpointHeader) + 3 * (size_t)sys->n * sizeof(double);
+    return SLLG_OK;
+}
+
+sllg_status sllg_checkpoint(sllg_system* sys, void* buf, size_t bytes)
+{
+    return guard(sys, [&] {
+        size_t need = 0;
+        sllg_checkpoint_size(sys, &need);
+        if (!buf || bytes < need)
+            fail(SLLG_E_ARG, "checkpoint buffer too small");
+        CheckpointHeader h{};
+        std::memcpy(h.magic, "SLLGCKP1", 8);
+        h.version = 1;
+        h.precision = (uint32_t)sys->prec;
+        h.n = sys->n;
+        h.seed = sys->dyn.seed;
+        h.step = sys->eng ? sys->eng->step() : sys->dyn.step;
+        std::memcpy(buf, &h, sizeof(h));
+        double* S = reinterpret_cast<double*>(static_cast<char*>(buf) + sizeof(h));
+        if (sys->eng)
+            sys->eng->get_spins(S, sys->own);
+        else
+            std::memcpy(S, sys->spins.data(), sys->spins.size() * sizeof(double));
+    });
+}
+
+sllg_status sllg_restore(sllg_system* sys, const void* buf, size_t bytes)
+{
+    return guard(sys, [&] {
+        CheckpointHeader h{};
+        if (!buf || bytes < sizeof(h))
+            fail(SLLG_E_ARG, "checkpoint buffer too small");
+        std::memcpy(&h, buf, sizeof(h));
+        if (std::memcmp(h.magic, "SLLGCKP1", 8) != 0 || h.version != 1)
+            fail(SLLG_E_ARG, "not a checkpoint of this library");
+        if (h.n != sys->n || h.precision != (uint32_t)sys->prec)
+            fail(SLLG_E_ARG, "checkpoint is of a different system size or precision");
+        if (bytes < sizeof(h) + 3 * (size_t)h.n * sizeof(double))
+            fail(SLLG_E_ARG, "checkpoint truncated");
+        const double* S = reinterpret_cast<const double*>(static_cast<const char*>(buf) + sizeof(h));
+        std::vector<double> v = normalised_spins(sys->n, S, false);
+        if (sys->eng)
+            sys->eng->set_spins(v);
+        else
+            sys->spins = v;
+        if (sllg_set_rng(sys, h.seed, h.step) != SLLG_OK)
+            fail(SLLG_E_DEVICE, sys->err);
+    });
+}
+
+sllg_status sllg_thermal_normals(int device, sllg_precision precision, uint64_t seed, uint64_t step,
+                                 int64_t n, double* out)
+{
+    if (!out || n < 1 || n >= (int64_t(1) << kColBits) ||
+        (precision != SLLG_FP32 && precision != SLLG_FP64))
+        return SLLG_E_ARG;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return SLLG_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess)
+        return SLLG_E_DEVICE;
+    double* d = nullptr;
+    if (hipMalloc(&d, 3 * (size_t)n * sizeof(double)) != hipSuccess)
+        return SLLG_E_NOMEM;
+    hipError_t e = precision == SLLG_FP32 ? launch_noise<float>(seed, step, (int)n, d, nullptr)
+                                          : launch_noise<double>(seed, step, (int)n, d, nullptr);
+    if (e == hipSuccess)
+        e = hipMemcpy(out, d, 3 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    return e == hipSuccess ? SLLG_OK : SLLG_E_DEVICE;
+}
+
+sllg_status sllg_set_option(sllg_system* sys, const char* key, int64_t value)
+{
+    return guard(sys, [&] {
+        if (!key)
+            fail(SLLG_E_ARG, "key must not be NULL");
+        const std::string k(key);
+        if (k == "check_symmetry") {
+            sys->opt_check_symmetry = value ? 1 : 0;
+        } else if (k == "graph_steps") {
+            if (value < -1 || value > 4096 || (value > 0 && (value & 1)))
+                fail(SLLG_E_ARG, "graph_steps must be -1 (auto), 0, or even up to 4096");
+            if (sys->eng && value > sys->eng->rec_cap())
+                fail(SLLG_E_STATE, "graph_steps larger than the record buffer; set it before the first run");
+            sys->opt_graph_steps = value;
+        } else if (k == "block_sites") {
+            if (value != kBlockSites)
+                fail(SLLG_E_ARG, "block_sites: only 256 is built");
+            sys->opt_block_sites = value;
+        } else if (k == "xcd_remap") {
+            sys->opt_xcd_remap = value ? 1 : 0;
+            if (sys->eng)
+                sys->eng->set_remap((int)sys->opt_xcd_remap);
+        } else {
+            fail(SLLG_E_ARG, "unknown option '" + k + "'");
+        }
+    });
+}
+
+sllg_status sllg_get_option(const sllg_system* sys, const char* key, int64_t* value)
+{
+    if (!sys || !key || !value)
+        return SLLG_E_ARG;
+    const std::string k(key);
+    if (k == "check_symmetry")
+        *value = sys->opt_check_symmetry;
+    else if (k == "graph_steps")
+        *value = graph_steps(sys);
+    else if (k == "block_sites")
+        *value = sys->opt_block_sites;
+    else if (k == "xcd_remap")
+        *value = sys->opt_xcd_remap;
+    else
+        return SLLG_E_ARG;
+    return SLLG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,499 @@
+// Batch engine: device buffers of every replica, the replica and work
+// tables the kernels read, and the launch sequence of one chunk of Heun
+// steps (optionally captured once as a HIP graph and replayed).
+//
+// A chunk of K steps is, for k = 0..K-1: predictor(k), corrector(k); then a
+// measuring predictor pass and the record of the last step, the thermal
+// average sums, and the advance of every replica's step counter and
+// ping-pong parity.  Replicas that take fewer than K steps in a chunk exit
+// the later launches at once, so one graph serves a changing batch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "layout.hpp"
+#include "prepare.hpp"
+
+namespace sllg {
+
+inline void hip_check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess)
+        fail(e == hipErrorOutOfMemory ? SLLG_E_NOMEM : SLLG_E_DEVICE,
+             std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device memory source for replica buffers.
+class Allocator {
+public:
+    virtual ~Allocator() = default;
+    virtual void* alloc(size_t bytes) = 0;     // throws Failure on failure
+    virtual void release(void* p) = 0;
+};
+
+class DirectAllocator final : public Allocator {
+public:
+    void* alloc(size_t bytes) override
+    {
+        void* p = nullptr;
+        hip_check(hipMalloc(&p, std::max<size_t>(bytes, 256)), "hipMalloc");
+        return p;
+    }
+    void release(void* p) override
+    {
+        if (p)
+            (void)hipFree(p);
+    }
+};
+
+// First-fit sub-allocator over one device allocation (the server's HBM
+// budget), so admitting and retiring requests never calls hipMalloc/hipFree
+// (hipFree would synchronise the device).
+class PoolAllocator final : public Allocator {
+public:
+    explicit PoolAllocator(size_t bytes) : size_(round(bytes))
+    {
+        hip_check(hipMalloc(&base_, size_), "hipMalloc(pool)");
+        free_[0] = size_;
+    }
+    ~PoolAllocator() override { (void)hipFree(base_); }
+    void* alloc(size_t bytes) override
+    {
+        const size_t need = round(std::max<size_t>(bytes, 1));
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= need) {
+                const size_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > need)
+                    free_[off + need] = len - need;
+                used_[off] = need;
+                in_use_ += need;
+                return static_cast<char*>(base_) + off;
+            }
+        }
+        fail(SLLG_E_BUDGET, "device pool exhausted");
+    }
+    void release(void* p) override
+    {
+        if (!p)
+            return;
+        const size_t off = static_cast<char*>(p) - static_cast<char*>(base_);
+        auto it = used_.find(off);
+        if (it == used_.end())
+            return;
+        size_t len = it->second;
+        used_.erase(it);
+        in_use_ -= len;
+        size_t start = off;
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && nx->first == off + len) {
+            len += nx->second;
+            free_.erase(nx);
+        }
+        auto pv = free_.lower_bound(off);
+        if (pv != free_.begin()) {
+            --pv;
+            if (pv->first + pv->second == off) {
+                start = pv->first;
+                len += pv->second;
+                free_.erase(pv);
+            }
+        }
+        free_[start] = len;
+    }
+    size_t in_use() const { return in_use_; }
+    size_t size() const { return size_; }
+    static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+
+private:
+    void* base_ = nullptr;
+    size_t size_ = 0;
+    size_t in_use_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    std::map<size_t, size_t> used_;
+};
+
+// Bytes of device memory one replica needs (used for admission).
+inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size_t real_bytes,
+                            int64_t rec_cap, int avg_cap)
+{
+    auto r = [](size_t b) { return PoolAllocator::round(b); };
+    const size_t n = (size_t)s.n;
+    const size_t blocks = (n + kBlockSites - 1) / kBlockSites;
+    size_t b = 4 * r(3 * n * real_bytes);                       // S[2], Sp, Bc
+    b += r(s.nb.size() * 4) + r(s.slice_off.size() * 8) + r(n);
+    if (m.per_site_material)
+        b += r(n);
+    if (m.per_site_axis)
+        b += r(3 * n * real_bytes);
+    b += r(m.mat_mu.size() * sizeof(MaterialDev<double>));
+    b += r(blocks * 32) + r((size_t)std::max<int64_t>(rec_cap, 1) * 32) +
+         r((size_t)std::max(avg_cap, 1) * 40);
+    return b;
+}
+
+template <typename R>
+class Batch {
+public:
+    struct Slot {
+        bool used = false;
+        ReplicaDev<R> rec{};
+        std::vector<void*> mem;
+        int64_t rec_cap = 0;
+        int avg_cap = 0;
+        size_t bytes = 0;
+    };
+
+    Batch(int device, Allocator* alloc, int max_replicas)
+        : device_(device), alloc_(alloc), slots_(max_replicas)
+    {
+        hip_check(hipSetDevice(device_), "hipSetDevice");
+        hip_check(hipMalloc(&d_reps_, sizeof(ReplicaDev<R>) * (size_t)max_replicas), "hipMalloc(reps)");
+        hip_check(hipMalloc(&d_nwork_, sizeof(int)), "hipMalloc(nwork)");
+        hip_check(hipMemset(d_nwork_, 0, sizeof(int)), "hipMemset");
+        host_reps_.resize(max_replicas);
+    }
+
+    ~Batch()
+    {
+        (void)hipSetDevice(device_);
+        drop_graph();
+        for (size_t q = 0; q < slots_.size(); ++q)
+            if (slots_[q].used)
+                remove(q);
+        (void)hipFree(d_reps_);
+        (void)hipFree(d_work_);
+        (void)hipFree(d_nwork_);
+    }
+
+    Batch(const Batch&) = delete;
+    Batch& operator=(const Batch&) = delete;
+
+    // Wait for every launch this batch queued.  Host-side changes of the
+    // device tables and buffers go through synchronous copies, which are not
+    // ordered with the (non-blocking) work stream, so they wait first.
+    void quiesce()
+    {
+        if (last_stream_) {
+            hip_check(hipStreamSynchronize(last_stream_), "hipStreamSynchronize");
+            last_stream_ = nullptr;
+        }
+    }
+
+    int capacity() const { return (int)slots_.size(); }
+    Slot& slot(int q) { return slots_[q]; }
+    ReplicaDev<R>& mirror(int q) { return slots_[q].rec; }
+    void mark_dirty() { dirty_ = true; }
+
+    // Allocate and fill the buffers of a new replica; returns its slot.
+    int add(const HostStructure& s, const HostMaterials& m, const Dynamics& d,
+            const std::vector<double>& S0, int64_t rec_cap, int avg_cap)
+    {
+        quiesce();
+        int q = -1;
+        for (size_t i = 0; i < slots_.size(); ++i)
+            if (!slots_[i].used) {
+                q = (int)i;
+                break;
+            }
+        if (q < 0)
+            fail(SLLG_E_BUDGET, "no free replica slot");
+        Slot& sl = slots_[q];
+        sl = Slot{};
+        sl.rec_cap = std::max<int64_t>(rec_cap, 1);
+        sl.avg_cap = std::max(avg_cap, 1);
+        const size_t n = (size_t)s.n;
+        const size_t blocks = (n + kBlockSites - 1) / kBlockSites;
+        try {
+            auto get = [&](size_t bytes) {
+                void* p = alloc_->alloc(bytes);
+                sl.mem.push_back(p);
+                return p;
+            };
+            ReplicaDev<R>& r = sl.rec;
+            r.S[0] = (R*)get(3 * n * sizeof(R));
+            r.S[1] = (R*)get(3 * n * sizeof(R));
+            r.Sp = (R*)get(3 * n * sizeof(R));
+            r.Bc = (R*)get(3 * n * sizeof(R));
+            uint32_t* nb = (uint32_t*)get(std::max<size_t>(s.nb.size(), 1) * 4);
+            int64_t* so = (int64_t*)get(s.slice_off.size() * 8);
+            uint8_t* dg = (uint8_t*)get(n);
+            hip_check(hipMemcpy(nb, s.nb.data(), s.nb.size() * 4, hipMemcpyHostToDevice), "upload nb");
+            hip_check(hipMemcpy(so, s.slice_off.data(), s.slice_off.size() * 8, hipMemcpyHostToDevice),
+                      "upload slices");
+            hip_check(hipMemcpy(dg, s.deg.data(), n, hipMemcpyHostToDevice), "upload deg");
+            r.nb = nb;
+            r.slice_off = so;
+            r.deg = dg;
+            r.matid = nullptr;
+            r.axis = nullptr;
+            if (m.per_site_material) {
+                uint8_t* mi = (uint8_t*)get(n);
+                hip_check(hipMemcpy(mi, m.matid.data(), n, hipMemcpyHostToDevice), "upload matid");
+                r.matid = mi;
+            }
+            if (m.per_site_axis) {
+                std::vector<R> ax(3 * n);
+                for (size_t i = 0; i < 3 * n; ++i)
+                    ax[i] = (R)m.axis_site[i];
+                R* a = (R*)get(3 * n * sizeof(R));
+                hip_check(hipMemcpy(a, ax.data(), 3 * n * sizeof(R), hipMemcpyHostToDevice), "upload axes");
+                r.axis = a;
+            }
+            r.mat = (MaterialDev<R>*)get(m.mat_mu.size() * sizeof(MaterialDev<R>));
+            r.partials = (double*)get(blocks * 4 * sizeof(double));
+            r.records = (double*)get((size_t)sl.rec_cap * 4 * sizeof(double));
+            r.acc = (double*)get((size_t)sl.avg_cap * 5 * sizeof(double));
+            r.flags = 0;
+            fill_parameters(r, s, m, d);
+            upload_materials(q, m, d);
+            r.parity = 0;
+            r.nsteps = 0;
+            r.rec_pos = 0;
+            r.avg_first = 0;
+            r.avg_block_len = 1;
+            r.avg_blocks = 0;
+            set_spins(q, S0);
+            sl.bytes = replica_bytes(s, m, sizeof(R), sl.rec_cap, sl.avg_cap);
+            sl.used = true;
+        } catch (...) {
+            for (void* p : sl.mem)
+                alloc_->release(p);
+            sl = Slot{};
+            throw;
+        }
+        dirty_ = true;
+        return q;
+    }
+
+    void remove(int q)
+    {
+        Slot& sl = slots_[q];
+        if (!sl.used)
+            return;
+        quiesce();
+        for (void* p : sl.mem)
+            alloc_->release(p);
+        sl = Slot{};
+        dirty_ = true;
+    }
+
+    void upload_materials(int q, const HostMaterials& m, const Dynamics& d)
+    {
+        const auto table = material_table<R>(m, d);
+        quiesce();
+        hip_check(hipMemcpy((void*)slots_[q].rec.mat, table.data(), table.size() * sizeof(MaterialDev<R>),
+                            hipMemcpyHostToDevice),
+                  "upload materials");
+    }
+
+    // Write the current state (spins are normalised doubles, 3n).
+    void set_spins(int q, const std::vector<double>& S)
+    {
+        ReplicaDev<R>& r = slots_[q].rec;
+        quiesce();
+        std::vector<R> tmp(S.size());
+        for (size_t i = 0; i < S.size(); ++i)
+            tmp[i] = (R)S[i];
+        hip_check(hipMemcpy(r.S[r.parity], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice),
+                  "upload spins");
+    }
+
+    void get_spins(int q, double* out, hipStream_t st)
+    {
+        ReplicaDev<R>& r = slots_[q].rec;
+        std::vector<R> tmp(3 * (size_t)r.n);
+        quiesce();
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        hip_check(hipMemcpy(tmp.data(), r.S[r.parity], tmp.size() * sizeof(R), hipMemcpyDeviceToHost),
+                  "download spins");
+        for (size_t i = 0; i < tmp.size(); ++i)
+            out[i] = (double)tmp[i];
+    }
+
+    // Upload the replica records and the work list when something changed.
+    void sync_tables()
+    {
+        if (!dirty_)
+            return;
+        quiesce();
+        work_.clear();
+        for (size_t q = 0; q < slots_.size(); ++q) {
+            host_reps_[q] = slots_[q].used ? slots_[q].rec : ReplicaDev<R>{};
+            if (!slots_[q].used)
+                host_reps_[q].nsteps = 0;
+            if (slots_[q].used && slots_[q].rec.nsteps > 0)
+                for (int b = 0; b < slots_[q].rec.blocks; ++b)
+                    work_.push_back(WorkItem{(int32_t)q, b});
+        }
+        const int nwork = (int)work_.size();
+        if (nwork > work_cap_) {
+            drop_graph();
+            (void)hipFree(d_work_);
+            d_work_ = nullptr;
+            work_cap_ = std::max<int64_t>(nwork, 2 * work_cap_);
+            hip_check(hipMalloc(&d_work_, sizeof(WorkItem) * (size_t)work_cap_), "hipMalloc(work)");
+        }
+        // Launch grid: exact for a fixed batch; for a changing batch rounded
+        // up to a power of two so a captured graph survives most changes
+        // (blocks past the device-side work count exit at once).
+        int grid = nwork;
+        if (round_grid_ && grid > 0) {
+            int g = 64;
+            while (g < grid)
+                g *= 2;
+            grid = g;
+        }
+        if (grid != grid_)
+            drop_graph();
+        grid_ = grid;
+        if (!work_.empty())
+            hip_check(hipMemcpy(d_work_, work_.data(), sizeof(WorkItem) * work_.size(), hipMemcpyHostToDevice),
+                      "upload work");
+        hip_check(hipMemcpy(d_nwork_, &nwork, sizeof(int), hipMemcpyHostToDevice), "upload nwork");
+        hip_check(hipMemcpy(d_reps_, host_reps_.data(), sizeof(ReplicaDev<R>) * host_reps_.size(),
+                            hipMemcpyHostToDevice),
+                  "upload replicas");
+        dirty_ = false;
+    }
+
+    // Run one chunk of K launch steps; replica q advances mirror(q).nsteps
+    // (<= K) steps.  With use_graph the launch sequence is captured once per
+    // (K, grid) and replayed.
+    void run_chunk(int K, hipStream_t st, bool use_graph)
+    {
+        sync_tables();
+        last_stream_ = st;
+        if (grid_ > 0) {
+            if (use_graph) {
+                if (!graph_exec_ || graph_K_ != K) {
+                    drop_graph();
+                    hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+                    hipError_t e = enqueue(K, st);
+                    hipGraph_t g = nullptr;
+                    hipError_t e2 = hipStreamEndCapture(st, &g);
+                    hip_check(e, "capture launches");
+                    hip_check(e2, "end capture");
+                    hipError_t e3 = hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    hip_check(e3, "graph instantiate");
+                    graph_K_ = K;
+                }
+                hip_check(hipGraphLaunch(graph_exec_, st), "graph launch");
+            } else {
+                hip_check(enqueue(K, st), "kernel launch");
+            }
+        }
+        // host mirror follows the device-side advance
+        for (auto& sl : slots_) {
+            if (!sl.used || sl.rec.nsteps <= 0)
+                continue;
+            const int ns = sl.rec.nsteps;
+            sl.rec.step += (uint64_t)ns;
+            sl.rec.parity = (sl.rec.parity + ns) & 1;
+            if (sl.rec.flags & kRecordSeries)
+                sl.rec.rec_pos += ns;
+        }
+    }
+
+    // m and E of every recording replica's current state into records[rec_pos].
+    void measure_now(hipStream_t st)
+    {
+        sync_tables();
+        quiesce();
+        // all used replicas, whatever their nsteps, take part
+        std::vector<WorkItem> all;
+        for (size_t q = 0; q < slots_.size(); ++q)
+            if (slots_[q].used && (slots_[q].rec.flags & kRecord))
+                for (int b = 0; b < slots_[q].rec.blocks; ++b)
+                    all.push_back(WorkItem{(int32_t)q, b});
+        if (all.empty())
+            return;
+        WorkItem* d_all = nullptr;
+        int* d_n = nullptr;
+        hip_check(hipMalloc(&d_all, sizeof(WorkItem) * all.size()), "hipMalloc(measure)");
+        hip_check(hipMalloc(&d_n, sizeof(int)), "hipMalloc(measure)");
+        const int n = (int)all.size();
+        hipError_t e = hipMemcpy(d_all, all.data(), sizeof(WorkItem) * all.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(d_n, &n, sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_predict<R>(d_reps_, d_all, d_n, n, 1, 0, true, st);
+        if (e == hipSuccess)
+            e = launch_finalize_tail<R>(d_reps_, (int)slots_.size(), 1, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        (void)hipFree(d_all);
+        (void)hipFree(d_n);
+        hip_check(e, "measure");
+    }
+
+    void set_remap(int v)
+    {
+        if (v != remap_)
+            drop_graph();
+        remap_ = v;
+    }
+    int remap() const { return remap_; }
+    void set_round_grid(bool v) { round_grid_ = v; }
+    int grid() const { return grid_; }
+    int n_replica_slots() const { return (int)slots_.size(); }
+
+private:
+    hipError_t enqueue(int K, hipStream_t st)
+    {
+        const int nrep = (int)slots_.size();
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < K && e == hipSuccess; ++k) {
+            e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, false, st);
+            if (e == hipSuccess)
+                e = launch_correct<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, st);
+        }
+        if (e == hipSuccess)
+            e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 0, remap_, true, st);
+        if (e == hipSuccess)
+            e = launch_finalize_tail<R>(d_reps_, nrep, 0, st);
+        if (e == hipSuccess)
+            e = launch_accumulate<R>(d_reps_, nrep, st);
+        if (e == hipSuccess)
+            e = launch_advance<R>(d_reps_, nrep, st);
+        return e;
+    }
+
+    void drop_graph()
+    {
+        if (graph_exec_) {
+            (void)hipGraphExecDestroy(graph_exec_);
+            graph_exec_ = nullptr;
+        }
+        graph_K_ = -1;
+    }
+
+    int device_;
+    Allocator* alloc_;
+    std::vector<Slot> slots_;
+    std::vector<ReplicaDev<R>> host_reps_;
+    std::vector<WorkItem> work_;
+    ReplicaDev<R>* d_reps_ = nullptr;
+    WorkItem* d_work_ = nullptr;
+    int* d_nwork_ = nullptr;
+    int64_t work_cap_ = 0;
+    int grid_ = 0;
+    int remap_ = 1;
+    bool round_grid_ = false;
+    bool dirty_ = true;
+    hipGraphExec_t graph_exec_ = nullptr;
+    int graph_K_ = -1;
+    hipStream_t last_stream_ = nullptr;
+};
+
+}  // namespace sllg

@@ -1,0 +1,42 @@
+// Host-side launchers of the HIP kernels in kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "layout.hpp"
+
+namespace sllg {
+
+// Predictor of step k of the current chunk over all work items.  With
+// measure it only evaluates m and E: of the state after the chunk (k = 0) or
+// of the current state (k = 1).
+// `grid` workgroups are launched; those whose (remapped) index is at or past
+// *n_work (device memory) exit at once, so a captured graph can serve any
+// batch up to `grid` blocks.
+template <typename R>
+hipError_t launch_predict(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work,
+                          int grid, int k, int remap, bool measure, hipStream_t st);
+// Corrector of step k of the current chunk.
+template <typename R>
+hipError_t launch_correct(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work,
+                          int grid, int k, int remap, hipStream_t st);
+// Thermal-average block sums of every replica with kAverage.
+template <typename R>
+hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t st);
+// Record from the measuring predictor: mode 0 = the chunk's last step
+// (slot nsteps - 1), mode 1 = the current state (slot 0).
+template <typename R>
+hipError_t launch_finalize_tail(const ReplicaDev<R>* reps, int n_rep, int mode, hipStream_t st);
+// Step counter and ping-pong parity update at the end of a chunk.
+template <typename R>
+hipError_t launch_advance(ReplicaDev<R>* reps, int n_rep, hipStream_t st);
+// Thermal normals of sites 0..n-1 at one step, as the step kernels draw them.
+template <typename R>
+hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStream_t st);
+
+hipError_t launch_scatter_records(const double* rec, int count, double* m_dev, double* E_dev,
+                                  hipStream_t st);
+
+}  // namespace sllg

@@ -1,0 +1,82 @@
+// Device-side data layout of libsllg, shared by the kernels and the host
+// runtime.  Holds plain structs only.
+//
+// One "replica" is one independent spin system.  A single system created
+// through sllg_create is a batch of one replica; the server batches many.
+// Every replica owns its device buffers; the kernels find them through a
+// table of ReplicaDev records, and a table of work items maps each
+// workgroup to (replica, block of kBlockSites consecutive sites).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sllg {
+
+constexpr int kBlockSites = 256;      // sites per workgroup (one site per lane)
+constexpr int kSlice = 64;            // rows per SELL slice = one wavefront
+constexpr int kMaxTypes = 16;         // interaction types per replica
+constexpr uint32_t kColBits = 28;     // packed neighbour: type << 28 | column
+constexpr uint32_t kColMask = (1u << kColBits) - 1u;
+constexpr int kMaxDegree = 255;
+
+// Per-material constants, pre-scaled to field units (tesla).
+template <typename R>
+struct MaterialDev {
+    R mu_rel;       // mu_ref / mu_s: exchange field = mu_rel * sum_k jt[type] S_j
+    R ani;          // 2 k_u / mu_s  (anisotropy field factor)
+    R ku_mu;        // k_u / mu_s    (anisotropy energy per unit moment)
+    R sigma;        // thermal-field width sqrt(2 lambda kB T / (gamma mu_s dt))
+    R axis[3];      // easy axis when it is uniform over the material
+    double mu_s;    // J/T, for the energy and magnetisation sums
+};
+
+enum ReplicaFlags : int32_t {
+    kPerSiteMaterial = 1,   // matid[] selects the material of each site
+    kPerSiteAxis = 2,       // axis[] holds one easy axis per site
+    kRecord = 4,            // compute m and E after every step
+    kRecordSeries = 8,      // records[] holds the whole run: rec_pos advances per chunk
+    kAverage = 16,          // add the records to the thermal-average block sums acc[]
+};
+
+template <typename R>
+struct ReplicaDev {
+    R* S[2];                        // ping-pong spin buffers [3n]
+    R* Sp;                          // predicted spins S' [3n]
+    R* Bc;                          // corrector base S + dS dt / 2 [3n]
+    const uint32_t* nb;             // SELL-64 neighbour entries
+    const int64_t* slice_off;       // [n_slices + 1] first entry of each slice
+    const uint8_t* deg;             // [n] neighbours per site
+    const uint8_t* matid;           // [n] or null
+    const R* axis;                  // [3n] or null
+    const MaterialDev<R>* mat;      // materials
+    double* partials;               // [blocks][4]: sum mu S (3), energy
+    double* records;                // [cap][4] per-step m (3) and E
+    double* acc;                    // [avg_blocks][5] sums of |m|, m (3), E per averaging block
+    R jt[kMaxTypes];                // J / mu_ref per type (tesla)
+    R gdt;                          // gamma / (1 + lambda^2) * dt
+    R alpha;                        // lambda
+    R H[3];                         // applied field (T)
+    double inv_mu_total;            // 1 / sum_i mu_s,i
+    uint64_t seed;                  // Philox key
+    uint64_t step;                  // number of the next step (advanced on the device)
+    int64_t rec_pos;                // record slot of the chunk's first step
+    int64_t avg_first;              // first averaged step number (its post-step state)
+    int64_t avg_block_len;          // samples per averaging block
+    int32_t avg_blocks;             // number of averaging blocks
+    int32_t pad0;
+    int32_t n;                      // sites
+    int32_t blocks;                 // ceil(n / kBlockSites)
+    int32_t parity;                 // S[parity] holds the current state (advanced on the device)
+    int32_t nsteps;                 // steps this replica takes in the current chunk
+    int32_t flags;                  // ReplicaFlags
+    int32_t pad;
+};
+
+struct WorkItem {
+    int32_t replica;
+    int32_t block;
+};
+
+}  // namespace sllg

@@ -1,0 +1,275 @@
+// Host-side validation and layout conversion (see prepare.hpp).
+#include "prepare.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <utility>
+
+namespace sllg {
+
+void fail(sllg_status code, const std::string& msg) { throw Failure{code, msg}; }
+
+HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                              const uint8_t* ntype, const double* J, int n_types,
+                              bool check_symmetry)
+{
+    if (n <= 0)
+        fail(SLLG_E_ARG, "system has no spins");
+    if (!row_ptr || !J)
+        fail(SLLG_E_ARG, "row_ptr and J must not be NULL");
+    if (n_types < 1 || n_types > kMaxTypes)
+        fail(SLLG_E_ARG, "n_types must be in 1..16");
+    for (int t = 0; t < n_types; ++t)
+        if (!std::isfinite(J[t]))
+            fail(SLLG_E_ARG, "J table holds a non-finite value");
+    if (row_ptr[0] != 0)
+        fail(SLLG_E_ARG, "row_ptr[0] must be 0");
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t d = row_ptr[i + 1] - row_ptr[i];
+        if (d < 0)
+            fail(SLLG_E_ARG, "row_ptr is decreasing at row " + std::to_string(i));
+        if (d > kMaxDegree)
+            fail(SLLG_E_ARG, "row " + std::to_string(i) + " has more than 255 neighbours");
+    }
+    const int64_t nnz = row_ptr[n];
+    if (nnz > 0 && !col)
+        fail(SLLG_E_ARG, "col must not be NULL");
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const int64_t j = col[k];
+            if (j < 0 || j >= n)
+                fail(SLLG_E_ARG, "column out of range in row " + std::to_string(i));
+            if (j == i)
+                fail(SLLG_E_ARG, "self link in row " + std::to_string(i));
+            if (ntype && ntype[k] >= n_types)
+                fail(SLLG_E_ARG, "interaction type out of range in row " + std::to_string(i));
+        }
+    }
+    if (check_symmetry) {
+        for (int64_t i = 0; i < n; ++i) {
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+                const int64_t j = col[k];
+                const int t = ntype ? ntype[k] : 0;
+                bool found = false;
+                for (int64_t q = row_ptr[j]; q < row_ptr[j + 1] && !found; ++q)
+                    found = (col[q] == i) && ((ntype ? ntype[q] : 0) == t);
+                if (!found)
+                    fail(SLLG_E_ARG, "link " + std::to_string(i) + "->" + std::to_string(j) +
+                                         " has no reverse link of the same type");
+            }
+        }
+    }
+
+    HostStructure s;
+    s.n = n;
+    s.nnz = nnz;
+    s.n_types = n_types;
+    s.J.assign(J, J + n_types);
+    const int64_t n_slices = (n + kSlice - 1) / kSlice;
+    s.slice_off.assign(n_slices + 1, 0);
+    s.deg.resize(n);
+    for (int64_t i = 0; i < n; ++i)
+        s.deg[i] = (uint8_t)(row_ptr[i + 1] - row_ptr[i]);
+    for (int64_t sl = 0; sl < n_slices; ++sl) {
+        int width = 0;
+        for (int64_t i = sl * kSlice; i < std::min<int64_t>(n, (sl + 1) * kSlice); ++i)
+            width = std::max<int>(width, s.deg[i]);
+        s.slice_off[sl + 1] = s.slice_off[sl] + (int64_t)kSlice * width;
+    }
+    s.nb.assign((size_t)s.slice_off[n_slices], 0u);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t base = s.slice_off[i / kSlice] + (i % kSlice);
+        int k = 0;
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q, ++k) {
+            const uint32_t t = ntype ? ntype[q] : 0u;
+            s.nb[(size_t)(base + (int64_t)k * kSlice)] = (t << kColBits) | (uint32_t)col[q];
+        }
+    }
+    return s;
+}
+
+HostMaterials build_materials(int64_t n, const double* mu_s, const double* k_u,
+                              const double* easy_axis, int per_site)
+{
+    if (!mu_s || !k_u || !easy_axis)
+        fail(SLLG_E_ARG, "mu_s, k_u and easy_axis must not be NULL");
+    if (per_site != 0 && per_site != 1)
+        fail(SLLG_E_ARG, "per_site must be 0 or 1");
+    const int64_t m = per_site ? n : 1;
+    for (int64_t i = 0; i < m; ++i) {
+        if (!(mu_s[i] > 0.0) || !std::isfinite(mu_s[i]))
+            fail(SLLG_E_ARG, "mu_s must be positive and finite");
+        if (!std::isfinite(k_u[i]))
+            fail(SLLG_E_ARG, "k_u must be finite");
+        const double* e = easy_axis + 3 * i;
+        const double len = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        if (!(len > 0.0) || !std::isfinite(len))
+            fail(SLLG_E_ARG, "easy axis of zero or non-finite length");
+    }
+    HostMaterials h;
+    h.n = n;
+    std::map<std::pair<double, double>, int> ids;
+    std::vector<uint8_t> matid(per_site ? n : 0);
+    for (int64_t i = 0; i < m; ++i) {
+        auto key = std::make_pair(mu_s[i], k_u[i]);
+        auto it = ids.find(key);
+        int id;
+        if (it == ids.end()) {
+            id = (int)ids.size();
+            if (id >= 256)
+                fail(SLLG_E_ARG, "more than 256 distinct (mu_s, k_u) materials");
+            ids.emplace(key, id);
+            h.mat_mu.push_back(mu_s[i]);
+            h.mat_ku.push_back(k_u[i]);
+        } else {
+            id = it->second;
+        }
+        if (per_site)
+            matid[i] = (uint8_t)id;
+    }
+    h.per_site_material = h.mat_mu.size() > 1;
+    if (h.per_site_material)
+        h.matid = std::move(matid);
+    // easy axes
+    auto unit = [&](int64_t i, double out[3]) {
+        const double* e = easy_axis + 3 * i;
+        const double len = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        out[0] = e[0] / len;
+        out[1] = e[1] / len;
+        out[2] = e[2] / len;
+    };
+    unit(0, h.axis);
+    if (per_site) {
+        for (int64_t i = 1; i < n && !h.per_site_axis; ++i) {
+            const double* e = easy_axis + 3 * i;
+            h.per_site_axis = e[0] != easy_axis[0] || e[1] != easy_axis[1] || e[2] != easy_axis[2];
+        }
+        if (h.per_site_axis) {
+            h.axis_site.resize(3 * (size_t)n);
+            for (int64_t i = 0; i < n; ++i)
+                unit(i, &h.axis_site[3 * (size_t)i]);
+        }
+    }
+    h.mu_ref = h.mat_mu[0];
+    double tot = 0.0;
+    if (per_site) {
+        for (int64_t i = 0; i < n; ++i)
+            tot += mu_s[i];
+    } else {
+        tot = mu_s[0] * (double)n;
+    }
+    h.mu_total = tot;
+    return h;
+}
+
+std::vector<double> normalised_spins(int64_t n, const double* S, bool normalise)
+{
+    if (!S)
+        fail(SLLG_E_ARG, "spin array must not be NULL");
+    std::vector<double> out(3 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        const double* s = S + 3 * i;
+        const double len = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        if (!(len > 0.0) || !std::isfinite(len))
+            fail(SLLG_E_ARG, "spin " + std::to_string(i) + " has zero or non-finite length");
+        out[3 * i] = normalise ? s[0] / len : s[0];
+        out[3 * i + 1] = normalise ? s[1] / len : s[1];
+        out[3 * i + 2] = normalise ? s[2] / len : s[2];
+    }
+    return out;
+}
+
+void check_dynamics(const Dynamics& d)
+{
+    if (!(d.alpha >= 0.0) || !std::isfinite(d.alpha))
+        fail(SLLG_E_ARG, "damping must be finite and >= 0");
+    if (!(d.gamma > 0.0) || !std::isfinite(d.gamma))
+        fail(SLLG_E_ARG, "gamma must be finite and > 0");
+    if (!(d.dt > 0.0) || !std::isfinite(d.dt))
+        fail(SLLG_E_ARG, "dt must be finite and > 0");
+    if (!(d.temperature >= 0.0) || !std::isfinite(d.temperature))
+        fail(SLLG_E_ARG, "temperature must be finite and >= 0");
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(d.H[c]))
+            fail(SLLG_E_ARG, "applied field must be finite");
+}
+
+template <typename R>
+std::vector<MaterialDev<R>> material_table(const HostMaterials& m, const Dynamics& d)
+{
+    std::vector<MaterialDev<R>> t(m.mat_mu.size());
+    for (size_t q = 0; q < t.size(); ++q) {
+        const double mu = m.mat_mu[q], ku = m.mat_ku[q];
+        t[q].mu_rel = (R)(m.mu_ref / mu);
+        t[q].ani = (R)(2.0 * ku / mu);
+        t[q].ku_mu = (R)(ku / mu);
+        t[q].sigma = (R)std::sqrt(2.0 * d.alpha * kBoltzmann * d.temperature / (d.gamma * mu * d.dt));
+        t[q].axis[0] = (R)m.axis[0];
+        t[q].axis[1] = (R)m.axis[1];
+        t[q].axis[2] = (R)m.axis[2];
+        t[q].mu_s = mu;
+    }
+    return t;
+}
+
+template <typename R>
+void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMaterials& m,
+                     const Dynamics& d)
+{
+    for (int t = 0; t < kMaxTypes; ++t)
+        rec.jt[t] = t < s.n_types ? (R)(s.J[t] / m.mu_ref) : (R)0;
+    rec.gdt = (R)(d.gamma / (1.0 + d.alpha * d.alpha) * d.dt);
+    rec.alpha = (R)d.alpha;
+    rec.H[0] = (R)d.H[0];
+    rec.H[1] = (R)d.H[1];
+    rec.H[2] = (R)d.H[2];
+    rec.inv_mu_total = 1.0 / m.mu_total;
+    rec.seed = d.seed;
+    rec.step = d.step;
+    rec.n = (int32_t)s.n;
+    rec.blocks = (int32_t)((s.n + kBlockSites - 1) / kBlockSites);
+    int32_t flags = rec.flags & (kRecord | kRecordSeries);
+    if (m.per_site_material)
+        flags |= kPerSiteMaterial;
+    if (m.per_site_axis)
+        flags |= kPerSiteAxis;
+    rec.flags = flags;
+}
+
+void averages_from_block_sums(const double* acc, int n_blocks, int64_t block_len, double out[8])
+{
+    double tot[5] = {0, 0, 0, 0, 0};
+    for (int b = 0; b < n_blocks; ++b)
+        for (int c = 0; c < 5; ++c)
+            tot[c] += acc[5 * b + c];
+    const double ns = (double)block_len * n_blocks;
+    auto se = [&](int c) {
+        if (n_blocks < 2)
+            return std::nan("");
+        const double mean = tot[c] / ns;
+        double v = 0.0;
+        for (int b = 0; b < n_blocks; ++b) {
+            const double d = acc[5 * b + c] / (double)block_len - mean;
+            v += d * d;
+        }
+        return std::sqrt(v / (n_blocks - 1) / n_blocks);
+    };
+    out[0] = tot[0] / ns;
+    out[1] = se(0);
+    out[2] = tot[1] / ns;
+    out[3] = tot[2] / ns;
+    out[4] = tot[3] / ns;
+    out[5] = tot[4] / ns;
+    out[6] = se(4);
+    out[7] = (double)n_blocks;
+}
+
+template std::vector<MaterialDev<float>> material_table<float>(const HostMaterials&, const Dynamics&);
+template std::vector<MaterialDev<double>> material_table<double>(const HostMaterials&, const Dynamics&);
+template void fill_parameters<float>(ReplicaDev<float>&, const HostStructure&, const HostMaterials&,
+                                     const Dynamics&);
+template void fill_parameters<double>(ReplicaDev<double>&, const HostStructure&, const HostMaterials&,
+                                      const Dynamics&);
+
+}  // namespace sllg

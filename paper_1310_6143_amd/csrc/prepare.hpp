@@ -1,0 +1,91 @@
+// Host-side preparation of a spin system for the device: validation of the
+// caller's CSR neighbour list and material arrays, conversion of the CSR to
+// the SELL-64 layout the step kernels read, and the material table.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sllg.h"
+#include "layout.hpp"
+
+namespace sllg {
+
+// Internal failure carrying an ABI status; caught at the C boundary.
+struct Failure {
+    sllg_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(sllg_status code, const std::string& msg);
+
+// Boltzmann constant (J/K), Table 1 of the paper.
+constexpr double kBoltzmann = 1.3807e-23;
+
+// Neighbour structure in SELL-64 form.
+struct HostStructure {
+    int64_t n = 0;
+    int64_t nnz = 0;
+    int n_types = 0;
+    std::vector<double> J;             // joules per link, per type
+    std::vector<uint32_t> nb;          // packed entries, 64 rows per slice, column-major
+    std::vector<int64_t> slice_off;    // [n_slices + 1]
+    std::vector<uint8_t> deg;          // [n]
+};
+
+// Validates and converts.  Throws Failure(SLLG_E_ARG) on malformed input.
+HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                              const uint8_t* ntype, const double* J, int n_types,
+                              bool check_symmetry);
+
+// Materials: distinct (mu_s, k_u) pairs, per-site ids when there is more
+// than one, per-site easy axes when they differ.
+struct HostMaterials {
+    int64_t n = 0;
+    std::vector<double> mat_mu;        // J/T per material
+    std::vector<double> mat_ku;        // J per material
+    double axis[3] = {0, 0, 1};        // uniform easy axis (when !per_site_axis)
+    std::vector<uint8_t> matid;        // [n] when per_site_material
+    std::vector<double> axis_site;     // [3n] when per_site_axis
+    bool per_site_material = false;
+    bool per_site_axis = false;
+    double mu_ref = 0.0;               // reference moment for the field units
+    double mu_total = 0.0;             // sum over sites of mu_s
+};
+
+HostMaterials build_materials(int64_t n, const double* mu_s, const double* k_u,
+                              const double* easy_axis, int per_site);
+
+// Validate spins (3n doubles; throws on zero or non-finite length) and
+// normalise them, or with normalise = false copy them unchanged (a restored
+// checkpoint continues bit for bit).
+std::vector<double> normalised_spins(int64_t n, const double* S, bool normalise = true);
+
+// Integration parameters of one replica.
+struct Dynamics {
+    double alpha = -1.0, gamma = -1.0, dt = -1.0;
+    double temperature = 0.0;
+    double H[3] = {0.0, 0.0, 0.0};
+    uint64_t seed = 0;
+    uint64_t step = 0;
+};
+
+void check_dynamics(const Dynamics& d);
+
+// Device material table for the current dynamics (thermal width depends on
+// lambda, T, gamma and dt).
+template <typename R>
+std::vector<MaterialDev<R>> material_table(const HostMaterials& m, const Dynamics& d);
+
+// Fill the parameter part of a replica record (J table, gamma dt, field, ...).
+template <typename R>
+void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMaterials& m,
+                     const Dynamics& d);
+
+// Thermal averages from per-block sums acc[b][5] = sums of (|m|, m_x, m_y,
+// m_z, E) over block_len samples each: out = { <|m|>, se, <m_x>, <m_y>,
+// <m_z>, <E>, se(E), n_blocks }, se = std of the block means / sqrt(n_blocks).
+void averages_from_block_sums(const double* acc, int n_blocks, int64_t block_len, double out[8]);
+
+}  // namespace sllg

@@ -1,0 +1,20 @@
+"""Helpers shared by the GPU tests (no arithmetic of the method here)."""
+import numpy as np
+
+
+def max_angle(a, b):
+    """Largest angle (rad) between corresponding unit vectors of a and b,
+    atan2(|a x b|, a.b)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    cr = np.linalg.norm(np.cross(a, b), axis=1)
+    dt = (a * b).sum(axis=1)
+    return float(np.arctan2(cr, dt).max())
+
+
+def mean_angle(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    cr = np.linalg.norm(np.cross(a, b), axis=1)
+    dt = (a * b).sum(axis=1)
+    return float(np.arctan2(cr, dt).mean())

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs and the same Philox noise stream.
+
+Tolerances (the per-spin angle is atan2(|a x b|, a.b)):
+- FP64 GPU vs oracle: max angle <= 1e-5 rad after 1000 steps (the bar for
+  the 4096-spin simple-cubic system); observed differences come only from
+  FMA contraction and libm-vs-device transcendentals (~1 ulp).
+- FP32 GPU vs oracle: max angle after 1000 steps <= 2e-3 rad and mean
+  angle <= 2e-4 rad (FP32 rounding of |S| ~ 6e-8 per step, amplified by the
+  chaotic thermal dynamics over 1000 steps); |dm| <= 1e-4, |dE/E| <= 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1310_6143_amd as sl
+from spin_systems import bcc_block, fcc_nanoparticle, sc_reference, bcc_film
+from tests.gpu_util import max_angle, mean_angle
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_run(w, n_steps, step0=0):
+    ref = oracle.System(w)
+    S = np.ascontiguousarray(w.S0.copy())
+    m, E = ref.integrate(S, step0, n_steps)
+    return S, m, E
+
+
+def _gpu_run(w, n_steps, precision, **opts):
+    with sl.from_workload(w, precision=precision) as g:
+        for k, v in opts.items():
+            g.set_option(k, v)
+        m, E = g.integrate(n_steps)
+        return g.get_spins(), m, E
+
+
+@pytest.mark.parametrize("step", [0, 7, (1 << 32) + 5])
+def test_noise_stream_matches_oracle(step):
+    n = 100_000
+    ref = oracle.gaussians(42, step, np.arange(n))
+    g64 = sl.thermal_normals(42, step, n, sl.FP64)
+    assert np.abs(g64 - ref).max() < 1e-12
+    g32 = sl.thermal_normals(42, step, n, sl.FP32)
+    err = np.abs(g32 - ref)
+    # hardware log2 / sin / cos in FP32: absolute error grows with |g|
+    assert np.all(err <= 2e-5 * (1.0 + np.abs(ref))), err.max()
+
+
+@pytest.mark.parametrize("T", [300.0, 0.0])
+def test_sc4096_fp64_matches_oracle(T):
+    w = sc_reference(L=16, temperature=T, n_steps=1000, seed=42)
+    S_ref, m_ref, E_ref = _oracle_run(w, 1000)
+    S, m, E = _gpu_run(w, 1000, sl.FP64)
+    ang = max_angle(S, S_ref)
+    print(f"FP64 T={T}: max angle {ang:.3e} rad")
+    assert ang <= 1e-5
+    assert np.abs(m - m_ref).max() <= 1e-9
+    assert np.abs(E - E_ref).max() <= 1e-9 * np.abs(E_ref).max()
+    assert np.abs(np.linalg.norm(S, axis=1) - 1).max() <= 1e-15
+
+
+def test_sc4096_fp32_within_stated_bound():
+    w = sc_reference(L=16, temperature=300.0, n_steps=1000, seed=42)
+    S_ref, m_ref, E_ref = _oracle_run(w, 1000)
+    S, m, E = _gpu_run(w, 1000, sl.FP32)
+    amax, amean = max_angle(S, S_ref), mean_angle(S, S_ref)
+    dm = np.abs(m - m_ref).max()
+    dE = (np.abs(E - E_ref) / np.abs(E_ref)).max()
+    print(f"FP32: max angle {amax:.3e}, mean angle {amean:.3e}, |dm| {dm:.3e}, |dE/E| {dE:.3e}")
+    assert amax <= 2e-3 and amean <= 2e-4
+    assert dm <= 1e-4 and dE <= 1e-4
+    assert np.abs(np.linalg.norm(S, axis=1) - 1).max() <= 1e-6
+
+
+def test_ragged_sphere_per_site_axes_fp64():
+    # a small fcc particle: ragged rows (3..12 neighbours), per-site materials
+    # and random easy axes, spans several 256-site blocks and a partial one
+    w = fcc_nanoparticle(radius_nm=1.6, temperature=300.0)
+    w.H = np.array([0.2, -0.1, 0.5])
+    assert w.n % 256 != 0 and w.n > 3 * 256
+    S_ref, m_ref, E_ref = _oracle_run(w, 300)
+    S, m, E = _gpu_run(w, 300, sl.FP64)
+    ang = max_angle(S, S_ref)
+    print(f"sphere n={w.n}: max angle {ang:.3e}")
+    assert ang <= 1e-5
+    assert np.abs(E - E_ref).max() <= 1e-9 * np.abs(E_ref).max()
+
+
+def test_film_open_surfaces_fp64():
+    w = bcc_film(nx=12, ny=10, nz=5)
+    w.temperature = 500.0
+    S_ref, m_ref, E_ref = _oracle_run(w, 300)
+    S, m, E = _gpu_run(w, 300, sl.FP64)
+    assert max_angle(S, S_ref) <= 1e-5
+    assert np.abs(m - m_ref).max() <= 1e-9
+
+
+def test_bcc_j1j2_32cubed_fp64():
+    """The 32^3-cell periodic bcc J1+J2 system (65,536 spins) with the large
+    block's parameters, 1000 steps against the oracle."""
+    w = bcc_block(cells=32, n_steps=1000)
+    S_ref, m_ref, E_ref = _oracle_run(w, 1000)
+    S, m, E = _gpu_run(w, 1000, sl.FP64)
+    ang = max_angle(S, S_ref)
+    print(f"bcc 32^3 J1+J2 FP64: max angle {ang:.3e}")
+    assert ang <= 1e-5
+    assert np.abs(E - E_ref).max() <= 1e-9 * np.abs(E_ref).max()
+
+
+def test_chunked_equals_single_call_bitwise():
+    w = sc_reference(L=12, temperature=300.0, seed=9)
+    for prec in (sl.FP32, sl.FP64):
+        with sl.from_workload(w, precision=prec) as a, sl.from_workload(w, precision=prec) as b:
+            m1, E1 = a.integrate(1000)
+            m2a, E2a = b.integrate(500)
+            m2b, E2b = b.integrate(500)
+            assert np.array_equal(a.get_spins(), b.get_spins())
+            assert np.array_equal(m1, np.concatenate([m2a, m2b]))
+            assert np.array_equal(E1, np.concatenate([E2a, E2b]))
+            assert a.step == b.step == 1000
+
+
+def test_graph_and_direct_launches_agree_bitwise():
+    w = sc_reference(L=10, temperature=300.0, seed=3)
+    out = []
+    for gs in (0, 64, 16):
+        with sl.from_workload(w, precision=sl.FP32) as g:
+            g.set_option("graph_steps", gs)
+            m, E = g.integrate(333)
+            out.append((g.get_spins(), m, E))
+    for S, m, E in out[1:]:
+        assert np.array_equal(S, out[0][0])
+        assert np.array_equal(m, out[0][1])
+        assert np.array_equal(E, out[0][2])
+
+
+def test_xcd_remap_does_not_change_results():
+    w = sc_reference(L=20, temperature=300.0, seed=5)
+    res = []
+    for remap in (0, 1):
+        with sl.from_workload(w, precision=sl.FP32) as g:
+            g.set_option("xcd_remap", remap)
+            m, E = g.integrate(100)
+            res.append((g.get_spins(), m, E))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][2], res[1][2])
+
+
+def test_run_to_run_determinism():
+    w = sc_reference(L=16, temperature=300.0, seed=42)
+    a = _gpu_run(w, 200, sl.FP32)
+    b = _gpu_run(w, 200, sl.FP32)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_checkpoint_resume_is_exact():
+    w = sc_reference(L=8, temperature=300.0, seed=11)
+    with sl.from_workload(w, precision=sl.FP64) as a:
+        a.integrate(500, record=False)
+        blob = a.checkpoint()
+        m_cont, E_cont = a.integrate(500)
+        S_cont = a.get_spins()
+    with sl.from_workload(w, precision=sl.FP64) as b:
+        b.restore(blob)
+        assert b.step == 500
+        m_res, E_res = b.integrate(500)
+        assert np.array_equal(b.get_spins(), S_cont)
+        assert np.array_equal(m_res, m_cont) and np.array_equal(E_res, E_cont)
+
+
+def test_measure_initial_state_closed_form():
+    w = sc_reference(L=8)
+    w.H = np.array([0.0, 0.0, 0.3])
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        m, E = g.measure()
+    links = w.lattice.nnz // 2
+    expect = -links * 6e-21 - w.n * 1e-23 - w.n * w.mu_s[0] * 0.3
+    assert np.allclose(m, [0, 0, 1], atol=1e-15)
+    assert np.isclose(E, expect, rtol=1e-13)
+
+
+def test_average_matches_oracle():
+    w = sc_reference(L=8, temperature=400.0, seed=21)
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        r = g.average(300, 1000, 10)
+    ref = oracle.System(w)
+    S = w.S0.copy()
+    o, _ = oracle.average(ref, S, 0, 300, 1000, 10)
+    assert abs(r["m_abs"] - o["m_abs"]) < 1e-8
+    assert abs(r["m_abs_se"] - o["m_abs_se"]) < 1e-8
+    assert np.allclose(r["m"], o["m"], atol=1e-8)
+    assert abs(r["E"] - o["E"]) < 1e-8 * abs(o["E"])
+
+
+def test_temperature_sweep_continuation_matches_oracle():
+    w = sc_reference(L=6, seed=8)
+    temps = [0.0, 200.0, 600.0]
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        rows = g.sweep_temperature(temps, 100, 200, 4)
+        step = g.step
+    ref = oracle.System(w)
+    S = w.S0.copy()
+    orows, ostep = oracle.sweep_temperature(ref, S, temps, 100, 200, 0, 4)
+    assert step == ostep
+    for a, b in zip(rows, orows):
+        assert abs(a["m_abs"] - b["m_abs"]) < 1e-8
+        assert abs(a["E"] - b["E"]) < 1e-8 * abs(b["E"])
+
+
+def test_field_sweep_matches_oracle():
+    w = sc_reference(L=6, seed=8, temperature=50.0)
+    fields = [[0, 0, -2.0], [0, 0, 0.0], [0, 0, 2.0]]
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        rows = g.sweep_field(fields, 100, 200, 4)
+    ref = oracle.System(w)
+    S = w.S0.copy()
+    orows, _ = oracle.sweep_field(ref, S, fields, 100, 200, 0, 4)
+    for a, b in zip(rows, orows):
+        assert np.allclose(a["m"], b["m"], atol=1e-8)
