@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Throughput of the Heun-integrated stochastic LLG step on one MI355X.
+
+Workload: periodic bcc block of 160^3 cells (8,192,000 spins) with first
+(J1 = 7.05e-21 J, 8 per site) and second (J2 = 3.0e-21 J, 6 per site)
+neighbours, mu_s = 2.22 muB, k_u = 5.65e-25 J along z, T = 300 K,
+lambda = 0.05, dt = 1e-16 s, spins starting along +z, noise seed 4.  A step
+is one full Heun step over the whole system: thermal noise, exchange
+gather, anisotropy, Zeeman, predictor, corrector, renormalisation, and the
+FP64 reductions of m and E.  Inputs are resident in HBM before timing.
+
+Prints one JSON line: FP32 spin-steps/s as `value`, with the FP64 run, the
+FP32-vs-FP64 difference, the roofline of the step kernels, the serving
+workload's p50/p99 latency and the single-threaded CPU oracle beside it.
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-steps/s (Heun sLLG) FP32 vs FP64 at 1 GPU; p50/p99 latency of batched sweeps"
+HBM_PEAK_GBS = 8000.0
+COUNTER_FILE = os.path.join(ROOT, "profiles", "bcc160_step_hbm_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1310_6143_amd", "csrc", "kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_spin_step(w_bytes, mean_degree):
+    """Bytes the method itself must move per spin and step: read S once,
+    write S once (6w), read the neighbour structure once (4 B row offset plus
+    4 B per neighbour entry); the thermal noise is generated, not read."""
+    return 6 * w_bytes + 4 + 4 * mean_degree
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(precision):
+    """HBM bytes per step from the committed rocprofv3 counter summary, or
+    None when it is missing or the kernels changed since it was taken."""
+    if not os.path.exists(COUNTER_FILE):
+        return None
+    text = open(COUNTER_FILE).read()
+    h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    v = re.search(rf"{precision}_hbm_bytes_per_step:\s*([0-9.eE+]+)", text)
+    if not h or not v or h.group(1) != kernel_hash():
+        return None
+    return float(v.group(1))
+
+
+def run_gpu(w, precision, steps, warmup, torch):
+    import paper_1310_6143_amd as sl
+
+    t0 = time.time()
+    sysm = sl.from_workload(w, precision=precision, check_symmetry=False)
+    log(f"precision {'fp32' if precision == sl.FP32 else 'fp64'}: set-up {time.time() - t0:.1f} s")
+    st = torch.cuda.Stream()
+    m_w = torch.empty((max(warmup, 1), 3), dtype=torch.float64, device="cuda")
+    E_w = torch.empty(max(warmup, 1), dtype=torch.float64, device="cuda")
+    m_dev = torch.empty((steps, 3), dtype=torch.float64, device="cuda")
+    E_dev = torch.empty(steps, dtype=torch.float64, device="cuda")
+    if warmup:
+        sysm.integrate_dev(warmup, m_w, E_w, stream=st)
+    st.synchronize()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record(st)
+    sysm.integrate_dev(steps, m_dev, E_dev, stream=st)
+    ev1.record(st)
+    st.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = ev0.elapsed_time(ev1)
+    m = m_dev.cpu().numpy()
+    E = E_dev.cpu().numpy()
+    if not np.all(np.isfinite(E)):
+        raise SystemExit("non-finite energy in the timed run")
+    sysm.close()
+    log(f"  {steps} steps in {ms:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
+    return {"ms": ms, "wall_s": wall, "m": m, "E": E}
+
+
+def run_serving(args):
+    """The serving workload: Poisson arrivals of independent simple-cubic
+    requests admitted by HBM budget into the continuous-batching server."""
+    import paper_1310_6143_amd as sl
+    from spin_systems import serving_requests, sc_request_system
+
+    reqs = serving_requests(n_requests=args.serving_requests)
+    t0 = time.time()
+    systems = [sc_request_system(r["L"], r["temperature"], r["H"], r["n_steps"], r["seed"]) for r in reqs]
+    log(f"serving: {len(reqs)} requests prepared in {time.time() - t0:.1f} s")
+    total = float(sum(w.n * w.n_steps for w in systems))
+    with sl.Server(hbm_budget=args.serving_budget << 20, max_active=512, chunk_steps=args.serving_chunk,
+                   precision=sl.FP32) as srv:
+        # warm the server (graph capture, allocator) with one small request
+        srv.wait(srv.submit(sc_request_system(8, 300.0, [0, 0, 0], 64, 1)), 60)
+        tickets = []
+        start = srv.clock()
+        for r, w in zip(reqs, systems):
+            delay = start + r["arrival_s"] - srv.clock()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(w, n_avg=w.n_steps // 2))
+        res = [srv.wait(t, 600) for t in tickets]
+        stats = srv.stats()
+    bad = [r for r in res if r["state"] != "done"]
+    if bad:
+        raise SystemExit(f"{len(bad)} serving requests did not complete")
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    return {
+        "workload": "512 requests, Poisson arrivals at 200/s, periodic sc L^3 with L~U{8..48}, "
+                    "T~U[0,1200] K, |H|~U[0,2] T, 2000..20000 steps, FP32",
+        "requests": len(res),
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_latency_s": float(lat.mean()),
+        "spin_steps_per_s": total / span,
+        "busy_spin_steps_per_s": stats["spin_steps"] / max(stats["busy_seconds"], 1e-9),
+        "total_spin_steps": total,
+        "makespan_s": span,
+        "chunks": int(stats["chunks"]),
+    }
+
+
+def cpu_baseline(w, n_steps):
+    import oracle
+
+    sysm = oracle.System(w)
+    S = np.ascontiguousarray(w.S0.copy())
+    t0 = time.perf_counter()
+    sysm.integrate(S, 0, n_steps, record=True)
+    dt = time.perf_counter() - t0
+    return {
+        "value": w.n * n_steps / dt,
+        "unit": "spin-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{n_steps} Heun steps (with per-step m and E) of the full {w.n}-spin block, "
+                  f"FP64 oracle on one thread of {platform.processor() or platform.machine()} "
+                  f"({os.cpu_count()} host threads)",
+        "seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cells", type=int, default=160)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--serving-budget", type=int, default=16384, help="MiB")
+    ap.add_argument("--serving-chunk", type=int, default=64)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (for counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the multi-GPU path of this library is a design "
+              "only (independent requests shard by rank; one large system needs a halo exchange "
+              "that is not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 18          # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}))
+        return
+
+    from spin_systems import bcc_block
+
+    t0 = time.time()
+    w = bcc_block(cells=args.cells)
+    deg = w.lattice.nnz / w.n
+    log(f"workload: {w.n} spins, {w.lattice.nnz} neighbour entries, built in {time.time() - t0:.1f} s")
+
+    import paper_1310_6143_amd as sl
+
+    r32 = run_gpu(w, sl.FP32, args.steps, args.warmup, torch)
+    r64 = None if args.no_fp64 else run_gpu(w, sl.FP64, args.steps, args.warmup, torch)
+
+    n = w.n
+    ms_step = r32["ms"] / args.steps
+    value = n * args.steps / (r32["ms"] / 1e3)
+    b_alg = algorithmic_bytes_per_spin_step(4, deg)
+    achieved = b_alg * n / (ms_step / 1e3) / 1e9
+    traffic = measured_traffic("fp32")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "spin-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"periodic bcc {args.cells}^3 cells, J1+J2 14-entry CSR, {n} spins, T=300 K, "
+                        "alpha=0.05, dt=1e-16 s, seed 4; FP32 spins, FP64 m/E reductions every step",
+            "n_spins": n,
+            "neighbour_entries": int(w.lattice.nnz),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None if traffic is None else traffic * n,
+            "kernel": "Heun step (predictor + corrector launches)",
+            "algorithmic_bytes_per_spin_step": b_alg,
+        },
+    }
+    if r64 is not None:
+        ms64 = r64["ms"] / args.steps
+        b64 = algorithmic_bytes_per_spin_step(8, deg)
+        out["fp64"] = {
+            "value": n * args.steps / (r64["ms"] / 1e3),
+            "ms_per_step": ms64,
+            "roofline_achieved_GBs": b64 * n / (ms64 / 1e3) / 1e9,
+            "algorithmic_bytes_per_spin_step": b64,
+        }
+        dm = np.abs(r32["m"] - r64["m"]).max()
+        dE = (np.abs(r32["E"] - r64["E"]) / np.abs(r64["E"])).max()
+        out["fp32_vs_fp64"] = {"max_abs_dm": float(dm), "max_rel_dE": float(dE),
+                               "steps_compared": args.steps}
+    if not args.no_serving:
+        out["serving"] = run_serving(args)
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: {args.cpu_steps} oracle steps on {n} spins")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
