@@ -188,6 +188,11 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     (default: chosen from the system size)
  *   "block_sites"     sites per workgroup for the step kernels: 256 (default)
  *   "xcd_remap"       1 (default) / 0: map consecutive site blocks to one XCD
+ *   "stencil"         1 (default) / 0: let the next sllg_set_neighbours store
+ *                     the list as per-site stencil patterns when at most 256
+ *                     distinct (column - row, type) rows occur (<= 2048
+ *                     entries in all); 0 keeps the general SELL-64 form
+ * sllg_get_option also reads "neighbour_format": 1 stencil, 0 SELL, -1 unset.
  */
 sllg_status sllg_set_option(sllg_system *sys, const char *key, int64_t value);
 sllg_status sllg_get_option(const sllg_system *sys, const char *key, int64_t *value);
@@ -241,6 +246,7 @@ typedef struct {
     double m[3], E;           /* final reduced magnetisation and energy */
     double avg[8];            /* averages over the last n_avg steps, as sllg_average */
     double t_submit, t_start, t_done;   /* seconds on the server's clock */
+    size_t hbm_bytes;         /* device memory the request holds while it runs */
 } sllg_result;
 
 typedef struct {

@@ -64,7 +64,7 @@ class Request(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int), ("status", ctypes.c_int), ("n_spins", I64), ("n_steps", I64),
                 ("steps_done", I64), ("m", D * 3), ("E", D), ("avg", D * 8), ("t_submit", D),
-                ("t_start", D), ("t_done", D)]
+                ("t_start", D), ("t_done", D), ("hbm_bytes", ctypes.c_size_t)]
 
 
 class ServerStats(ctypes.Structure):
@@ -305,11 +305,14 @@ def _avg_dict(o):
             "E_se": float(o[6]), "n_blocks": int(o[7])}
 
 
-def from_workload(w, precision=FP32, device=0, check_symmetry=True):
-    """Build a SpinSystem from a spin_systems.Workload-like object."""
+def from_workload(w, precision=FP32, device=0, check_symmetry=True, stencil=1):
+    """Build a SpinSystem from a spin_systems.Workload-like object.
+    stencil=0 keeps the general SELL-64 neighbour layout."""
     s = SpinSystem(w.lattice.n, precision, device)
     if not check_symmetry:
         s.set_option("check_symmetry", 0)
+    if not stencil:
+        s.set_option("stencil", 0)
     lat = w.lattice
     s.set_neighbours(lat.row_ptr, lat.col, lat.ntype, w.J)
     mu, ku, ax = np.asarray(w.mu_s), np.asarray(w.k_u), np.asarray(w.easy_axis)
@@ -332,7 +335,8 @@ def _result_dict(r):
     return {"state": REQ_STATES.get(r.state, r.state), "status": STATUS.get(r.status, r.status),
             "n_spins": r.n_spins, "n_steps": r.n_steps, "steps_done": r.steps_done,
             "m": np.array(r.m[:]), "E": r.E, "avg": _avg_dict(np.array(r.avg[:])),
-            "t_submit": r.t_submit, "t_start": r.t_start, "t_done": r.t_done}
+            "t_submit": r.t_submit, "t_start": r.t_start, "t_done": r.t_done,
+            "hbm_bytes": int(r.hbm_bytes)}
 
 
 class Server:

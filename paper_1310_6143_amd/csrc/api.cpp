@@ -123,6 +123,7 @@ struct sllg_system {
     int64_t opt_graph_steps = -1;    // -1 = automatic
     int64_t opt_block_sites = kBlockSites;
     int64_t opt_xcd_remap = 1;
+    int64_t opt_stencil = 1;
     hipStream_t own = nullptr;
     std::unique_ptr<Engine> eng;
     std::vector<double> staging;
@@ -422,7 +423,7 @@ sllg_status sllg_set_neighbours(sllg_system* sys, const int64_t* row_ptr, const 
 {
     return guard(sys, [&] {
         HostStructure st = build_structure(sys->n, row_ptr, col, ntype, J, n_types,
-                                           sys->opt_check_symmetry != 0);
+                                           sys->opt_check_symmetry != 0, sys->opt_stencil != 0);
         drop_engine(sys);
         sys->st = std::move(st);
         sys->has_nb = true;
@@ -717,6 +718,8 @@ sllg_status sllg_set_option(sllg_system* sys, const char* key, int64_t value)
             if (value != kBlockSites)
                 fail(SLLG_E_ARG, "block_sites: only 256 is built");
             sys->opt_block_sites = value;
+        } else if (k == "stencil") {
+            sys->opt_stencil = value ? 1 : 0;   // applies to the next sllg_set_neighbours
         } else if (k == "xcd_remap") {
             sys->opt_xcd_remap = value ? 1 : 0;
             if (sys->eng)
@@ -740,6 +743,10 @@ sllg_status sllg_get_option(const sllg_system* sys, const char* key, int64_t* va
         *value = sys->opt_block_sites;
     else if (k == "xcd_remap")
         *value = sys->opt_xcd_remap;
+    else if (k == "stencil")
+        *value = sys->opt_stencil;
+    else if (k == "neighbour_format")
+        *value = sys->has_nb ? (sys->st.stencil ? 1 : 0) : -1;
     else
         return SLLG_E_ARG;
     return SLLG_OK;

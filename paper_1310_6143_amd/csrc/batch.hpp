@@ -130,12 +130,17 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
     const size_t n = (size_t)s.n;
     const size_t blocks = (n + kBlockSites - 1) / kBlockSites;
     size_t b = 4 * r(3 * n * real_bytes);                       // S[2], Sp, Bc
-    b += r(s.nb.size() * 4) + r(s.slice_off.size() * 8) + r(n);
+    if (s.stencil)
+        b += r(n) + r(s.pat_tab.size() * 4) + r(s.pat_start.size() * 2);
+    else
+        b += r(s.nb.size() * 4) + r(s.slice_off.size() * 8) + r(n);
     if (m.per_site_material)
         b += r(n);
     if (m.per_site_axis)
         b += r(3 * n * real_bytes);
     b += r(m.mat_mu.size() * sizeof(MaterialDev<double>));
+    const size_t groups = (blocks + kGroupTiles - 1) / kGroupTiles;
+    b += r(groups * 32);
     b += r(blocks * 32) + r((size_t)std::max<int64_t>(rec_cap, 1) * 32) +
          r((size_t)std::max(avg_cap, 1) * 40);
     return b;
@@ -161,6 +166,10 @@ public:
         hip_check(hipMalloc(&d_nwork_, sizeof(int)), "hipMalloc(nwork)");
         hip_check(hipMemset(d_nwork_, 0, sizeof(int)), "hipMemset");
         host_reps_.resize(max_replicas);
+        resident_ = resident_blocks<R>(device_);
+        if (resident_ < 8)
+            resident_ = 8 * 256;
+        resident_ &= ~7;
     }
 
     ~Batch()
@@ -224,16 +233,36 @@ public:
             r.S[1] = (R*)get(3 * n * sizeof(R));
             r.Sp = (R*)get(3 * n * sizeof(R));
             r.Bc = (R*)get(3 * n * sizeof(R));
-            uint32_t* nb = (uint32_t*)get(std::max<size_t>(s.nb.size(), 1) * 4);
-            int64_t* so = (int64_t*)get(s.slice_off.size() * 8);
-            uint8_t* dg = (uint8_t*)get(n);
-            hip_check(hipMemcpy(nb, s.nb.data(), s.nb.size() * 4, hipMemcpyHostToDevice), "upload nb");
-            hip_check(hipMemcpy(so, s.slice_off.data(), s.slice_off.size() * 8, hipMemcpyHostToDevice),
-                      "upload slices");
-            hip_check(hipMemcpy(dg, s.deg.data(), n, hipMemcpyHostToDevice), "upload deg");
-            r.nb = nb;
-            r.slice_off = so;
-            r.deg = dg;
+            r.nb = nullptr;
+            r.slice_off = nullptr;
+            r.deg = nullptr;
+            r.pat_id = nullptr;
+            r.pat_tab = nullptr;
+            r.pat_start = nullptr;
+            if (s.stencil) {
+                uint8_t* pid = (uint8_t*)get(n);
+                int32_t* tab = (int32_t*)get(std::max<size_t>(s.pat_tab.size(), 1) * 4);
+                uint16_t* ps = (uint16_t*)get(s.pat_start.size() * 2);
+                hip_check(hipMemcpy(pid, s.pat_id.data(), n, hipMemcpyHostToDevice), "upload pattern ids");
+                hip_check(hipMemcpy(tab, s.pat_tab.data(), s.pat_tab.size() * 4, hipMemcpyHostToDevice),
+                          "upload patterns");
+                hip_check(hipMemcpy(ps, s.pat_start.data(), s.pat_start.size() * 2, hipMemcpyHostToDevice),
+                          "upload pattern starts");
+                r.pat_id = pid;
+                r.pat_tab = tab;
+                r.pat_start = ps;
+            } else {
+                uint32_t* nb = (uint32_t*)get(std::max<size_t>(s.nb.size(), 1) * 4);
+                int64_t* so = (int64_t*)get(s.slice_off.size() * 8);
+                uint8_t* dg = (uint8_t*)get(n);
+                hip_check(hipMemcpy(nb, s.nb.data(), s.nb.size() * 4, hipMemcpyHostToDevice), "upload nb");
+                hip_check(hipMemcpy(so, s.slice_off.data(), s.slice_off.size() * 8, hipMemcpyHostToDevice),
+                          "upload slices");
+                hip_check(hipMemcpy(dg, s.deg.data(), n, hipMemcpyHostToDevice), "upload deg");
+                r.nb = nb;
+                r.slice_off = so;
+                r.deg = dg;
+            }
             r.matid = nullptr;
             r.axis = nullptr;
             if (m.per_site_material) {
@@ -251,6 +280,8 @@ public:
             }
             r.mat = (MaterialDev<R>*)get(m.mat_mu.size() * sizeof(MaterialDev<R>));
             r.partials = (double*)get(blocks * 4 * sizeof(double));
+            const size_t groups = (blocks + kGroupTiles - 1) / kGroupTiles;
+            r.group_partials = (double*)get(groups * 4 * sizeof(double));
             r.records = (double*)get((size_t)sl.rec_cap * 4 * sizeof(double));
             r.acc = (double*)get((size_t)sl.avg_cap * 5 * sizeof(double));
             r.flags = 0;
@@ -326,6 +357,19 @@ public:
         if (!dirty_)
             return;
         quiesce();
+        // A replica's flags must match the buffers it owns: the kernels pick
+        // the neighbour layout, material and axis lookups from the flags.
+        for (const auto& sl : slots_) {
+            if (!sl.used)
+                continue;
+            const ReplicaDev<R>& r = sl.rec;
+            const bool stencil = (r.flags & kStencil) != 0;
+            if ((stencil && (!r.pat_id || !r.pat_tab || !r.pat_start)) ||
+                (!stencil && (!r.nb || !r.slice_off || !r.deg)) ||
+                ((r.flags & kPerSiteMaterial) && !r.matid) || ((r.flags & kPerSiteAxis) && !r.axis) ||
+                ((r.flags & kAverage) && (!(r.flags & kRecord) || !r.acc)))
+                fail(SLLG_E_STATE, "replica flags do not match its buffers");
+        }
         work_.clear();
         for (size_t q = 0; q < slots_.size(); ++q) {
             host_reps_[q] = slots_[q].used ? slots_[q].rec : ReplicaDev<R>{};
@@ -343,16 +387,15 @@ public:
             work_cap_ = std::max<int64_t>(nwork, 2 * work_cap_);
             hip_check(hipMalloc(&d_work_, sizeof(WorkItem) * (size_t)work_cap_), "hipMalloc(work)");
         }
-        // Launch grid: exact for a fixed batch; for a changing batch rounded
-        // up to a power of two so a captured graph survives most changes
-        // (blocks past the device-side work count exit at once).
-        int grid = nwork;
-        if (round_grid_ && grid > 0) {
-            int g = 64;
-            while (g < grid)
-                g *= 2;
-            grid = g;
-        }
+        // Launch grid: the tiles are swept by at most as many workgroups as
+        // fit on the device at once (a multiple of 8 for the XCD mapping).
+        // A changing batch always launches the full resident grid so that
+        // one captured graph serves every batch.
+        int grid = (int)std::min<int64_t>(((int64_t)nwork + 7) & ~int64_t(7), resident_);
+        if (round_grid_)
+            grid = resident_;
+        if (nwork == 0)
+            grid = 0;
         if (grid != grid_)
             drop_graph();
         grid_ = grid;
@@ -429,7 +472,7 @@ public:
         if (e == hipSuccess)
             e = launch_predict<R>(d_reps_, d_all, d_n, n, 1, 0, true, st);
         if (e == hipSuccess)
-            e = launch_finalize_tail<R>(d_reps_, (int)slots_.size(), 1, st);
+            e = launch_finish<R>(d_reps_, (int)slots_.size(), 1, st);
         if (e == hipSuccess)
             e = hipStreamSynchronize(st);
         (void)hipFree(d_all);
@@ -461,7 +504,7 @@ private:
         if (e == hipSuccess)
             e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 0, remap_, true, st);
         if (e == hipSuccess)
-            e = launch_finalize_tail<R>(d_reps_, nrep, 0, st);
+            e = launch_finish<R>(d_reps_, nrep, 0, st);
         if (e == hipSuccess)
             e = launch_accumulate<R>(d_reps_, nrep, st);
         if (e == hipSuccess)
@@ -488,6 +531,7 @@ private:
     int* d_nwork_ = nullptr;
     int64_t work_cap_ = 0;
     int grid_ = 0;
+    int resident_ = 0;
     int remap_ = 1;
     bool round_grid_ = false;
     bool dirty_ = true;

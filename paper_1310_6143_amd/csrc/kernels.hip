@@ -100,18 +100,31 @@ struct V3 {
     R x, y, z;
 };
 
+// Every buffer the kernels touch lives in global memory; saying so lets the
+// compiler emit global_load/global_store instead of generic flat accesses
+// for pointers it reads out of the replica table.
+#define SLLG_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ T gload(const T* p, int64_t i)
+{
+    return ((const SLLG_GLOBAL T*)p)[i];
+}
+
 template <typename R>
 __device__ __forceinline__ V3<R> load3(const R* __restrict__ p, int64_t i)
 {
-    return V3<R>{p[3 * i], p[3 * i + 1], p[3 * i + 2]};
+    const SLLG_GLOBAL R* g = (const SLLG_GLOBAL R*)p + 3 * i;
+    return V3<R>{g[0], g[1], g[2]};
 }
 
 template <typename R>
 __device__ __forceinline__ void store3(R* __restrict__ p, int64_t i, V3<R> v)
 {
-    p[3 * i] = v.x;
-    p[3 * i + 1] = v.y;
-    p[3 * i + 2] = v.z;
+    SLLG_GLOBAL R* g = (SLLG_GLOBAL R*)p + 3 * i;
+    g[0] = v.x;
+    g[1] = v.y;
+    g[2] = v.z;
 }
 
 template <typename R>
@@ -136,19 +149,106 @@ __device__ __forceinline__ V3<R> normalised(V3<R> v)
     return V3<R>{v.x * inv, v.y * inv, v.z * inv};
 }
 
-// sum_k jt[type_k] S[col_k] over the SELL row of site i.
+// Spins are read through buffer descriptors: a 32-bit byte offset per
+// lane instead of a 64-bit address, and hardware bounds (an offset past the
+// buffer reads 0).  The offsets of a stencil pattern are byte offsets.
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v3i __attribute__((ext_vector_type(3)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t spin_rsrc(const void* base, int n)
+{
+    // 0x00020000: dword 3 of a raw (untyped) buffer descriptor on gfx9
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, n, 0x00020000);
+}
+
+__device__ __forceinline__ V3<float> bload3(__amdgpu_buffer_rsrc_t rs, int off, float)
+{
+    const v3i v = __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0);
+    return V3<float>{__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z)};
+}
+
+__device__ __forceinline__ V3<double> bload3(__amdgpu_buffer_rsrc_t rs, int off, double)
+{
+    const v4i a = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    const v2i b = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 16, 0, 0);
+    auto d = [](int lo, int hi) {
+        return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+    };
+    return V3<double>{d(a.x, a.y), d(a.z, a.w), d(b.x, b.y)};
+}
+
+// Neighbour tables a workgroup stages in LDS: the J table and, for the
+// stencil layout, every pattern entry as (byte offset of the neighbour's spin
+// from the site's own, J of the link).
+template <typename R>
+struct PatEntry;
+template <>
+struct PatEntry<float> {
+    int32_t off;
+    float J;
+};
+template <>
+struct PatEntry<double> {
+    int32_t off;
+    int32_t pad;
+    double J;
+};
+
+template <typename R>
+struct Shared {
+    R jt[kMaxTypes];
+    uint16_t pat_start[kMaxPatterns + 1];
+    PatEntry<R> pat[kMaxPatternEntries];
+};
+
+template <typename R>
+__device__ __forceinline__ void stage_tables(const ReplicaDev<R>& r, Shared<R>& sh)
+{
+    if (threadIdx.x < kMaxTypes)
+        sh.jt[threadIdx.x] = r.jt[threadIdx.x];
+    if (r.flags & kStencil) {
+        const int np = r.n_patterns;
+        for (int q = threadIdx.x; q <= np; q += kBlockSites)
+            sh.pat_start[q] = gload(r.pat_start, q);
+        const int ne = gload(r.pat_start, np);
+        for (int q = threadIdx.x; q < ne; q += kBlockSites) {
+            const int32_t raw = gload(r.pat_tab, q);
+            sh.pat[q].off = (raw >> 4) * (int)(3 * sizeof(R));
+            sh.pat[q].J = r.jt[raw & 15];
+        }
+    }
+    __syncthreads();
+}
+
+// sum_k J_k S[j_k] over the neighbours of site i: from the site's stencil
+// pattern (LDS) or from its SELL row.
 template <typename R>
 __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* __restrict__ S,
-                                              const R* jt, int i)
+                                              const Shared<R>& sh, int i)
 {
-    const int64_t base = r.slice_off[i >> 6] + (i & 63);
-    const int d = r.deg[i];
-    const uint32_t* __restrict__ p = r.nb + base;
     V3<R> h{0, 0, 0};
+    if (r.flags & kStencil) {
+        const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, r.n * (int)(3 * sizeof(R)));
+        const int ib = i * (int)(3 * sizeof(R));
+        const int p = gload(r.pat_id, i);
+        const int b = sh.pat_start[p], e = sh.pat_start[p + 1];
+#pragma unroll 8
+        for (int k = b; k < e; ++k) {
+            const PatEntry<R> pe = sh.pat[k];
+            const V3<R> sj = bload3(rs, ib + pe.off, R(0));
+            h.x += pe.J * sj.x;
+            h.y += pe.J * sj.y;
+            h.z += pe.J * sj.z;
+        }
+        return h;
+    }
+    const int64_t base = gload(r.slice_off, i >> 6) + (i & 63);
+    const int d = gload(r.deg, i);
 #pragma unroll 2
     for (int k = 0; k < d; ++k) {
-        const uint32_t e = p[(int64_t)k * kSlice];
-        const R J = jt[e >> kColBits];
+        const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
+        const R J = sh.jt[e >> kColBits];
         const V3<R> sj = load3(S, (int64_t)(e & kColMask));
         h.x += J * sj.x;
         h.y += J * sj.y;
@@ -157,73 +257,179 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
     return h;
 }
 
-__device__ __forceinline__ int logical_block(int b, int n, int remap)
+// Work distribution.  A launch has a fixed number of workgroups (about the
+// number that fit on the chip at once), each sweeping many 256-site tiles.
+// Workgroups are handed to the 8 XCDs round-robin, so with `remap` the
+// workgroups of XCD x share one contiguous range of tiles and neighbouring
+// sites meet in that XCD's L2.
+struct TileIter {
+    int64_t t, end, stride;
+    __device__ TileIter(int W, int remap)
+    {
+        const int G = (int)gridDim.x, b = (int)blockIdx.x;
+        if (remap && (G & 7) == 0) {
+            const int x = b & 7;
+            const int64_t lo = (int64_t)W * x / 8, hi = (int64_t)W * (x + 1) / 8;
+            t = lo + (b >> 3);
+            end = hi;
+            stride = G >> 3;
+        } else {
+            t = b;
+            end = W;
+            stride = G;
+        }
+    }
+    __device__ bool more() const { return t < end; }
+    __device__ void next() { t += stride; }
+};
+
+// ---------------------------------------------------------------------------
+// Reductions of m and E.  Every sum has a fixed order: sites of a tile (256,
+// by lane, row of 16 lanes, wavefront), tiles of a group (kGroupTiles, by
+// tile), groups (by group).  Which workgroup computes a sum never changes
+// its order, so a step's record is the same bit for bit whatever the launch
+// shape, the chunking or the rest of the batch.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
 {
-    if (!remap)
-        return b;
-    // Workgroups are handed to the 8 XCDs round-robin; give XCD x one
-    // contiguous range of blocks so neighbouring sites share its L2.
-    const int q = n >> 3, rem = n & 7;
-    const int x = b & 7, idx = b >> 3;
-    return x * q + (x < rem ? x : rem) + idx;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        v += __shfl_xor(v, off, 64);
+    const uint64_t u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Sum within each row of 16 lanes (quad swaps, then rotations by 4 and 8).
+template <typename T>
+__device__ __forceinline__ T row_sum(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        v += dpp_f<0xB1>(v);    // quad_perm [1,0,3,2]
+        v += dpp_f<0x4E>(v);    // quad_perm [2,3,0,1]
+        v += dpp_f<0x124>(v);   // row_ror:4
+        v += dpp_f<0x128>(v);   // row_ror:8
+    } else {
+        v += dpp_d<0xB1>(v);
+        v += dpp_d<0x4E>(v);
+        v += dpp_d<0x124>(v);
+        v += dpp_d<0x128>(v);
+    }
     return v;
 }
 
-// Block-wide sum of four doubles in a fixed order; result valid in thread 0.
-__device__ __forceinline__ void block_sum4(double acc[4], double (*red)[kBlockSites / 64])
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t l = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)h << 32) | l));
+}
+
+__device__ __forceinline__ double lane_value(float v, int lane)
+{
+    return (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Wavefront total in double: rows summed in the value's own precision
+// (FP32 rows hold 16 single-precision site terms), rows added in FP64.
+template <typename T>
+__device__ __forceinline__ double wave_sum(T v)
+{
+    v = row_sum(v);
+    return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+}
+
+constexpr int kWaves = kBlockSites / 64;
+
+// Block-wide sum of four values in a fixed order; result valid in thread 0.
+// Ends with a barrier so `red` can be reused at once.
+template <typename T>
+__device__ __forceinline__ void block_sum4(const T v[4], double out[4], double (*red)[kWaves])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const double v = wave_sum(acc[c]);
+        const double w = wave_sum(v[c]);
         if (lane == 0)
-            red[c][wave] = v;
+            red[c][wave] = w;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             double s = 0.0;
-            for (int w = 0; w < kBlockSites / 64; ++w)
+            for (int w = 0; w < kWaves; ++w)
                 s += red[c][w];
-            acc[c] = s;
+            out[c] = s;
         }
+    }
+    __syncthreads();
+}
+
+// Group g of a replica's tile partials -> group partial g.
+template <typename R>
+__device__ void group_reduce(const ReplicaDev<R>& r, int g, double (*red)[kWaves])
+{
+    const int lo = g * kGroupTiles;
+    const int cnt = min(kGroupTiles, r.blocks - lo);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if ((int)threadIdx.x < cnt) {
+        const double* p = r.partials + 4 * (int64_t)(lo + (int)threadIdx.x);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            v[c] = p[c];
+    }
+    double out[4];
+    block_sum4(v, out, red);
+    if (threadIdx.x == 0) {
+        double* q = r.group_partials + 4 * (int64_t)g;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            q[c] = out[c];
     }
 }
 
-// Sum the per-block partials of one replica (fixed order, independent of the
-// launch) into record `slot`: m = sum mu S / sum mu, and E.
+// All group partials -> record `slot` (m = sum mu S / sum mu, E).
 template <typename R>
-__device__ void finalize_record(const ReplicaDev<R>& r, int slot, double (*red)[kBlockSites / 64])
+__device__ void final_reduce(const ReplicaDev<R>& r, int slot, double (*red)[kWaves])
 {
-    __syncthreads();
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < r.blocks; b += kBlockSites) {
+    const int n_groups = (r.blocks + kGroupTiles - 1) / kGroupTiles;
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < n_groups; q0 += kBlockSites) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        const int q = q0 + (int)threadIdx.x;
+        if (q < n_groups) {
+            const double* p = r.group_partials + 4 * (int64_t)q;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            acc[c] += r.partials[4 * (int64_t)b + c];
+            for (int c = 0; c < 4; ++c)
+                v[c] = p[c];
+        }
+        double out[4];
+        block_sum4(v, out, red);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 4; ++c)
+                tot[c] += out[c];
     }
-    block_sum4(acc, red);
     if (threadIdx.x == 0) {
         double* out = r.records + 4 * (r.rec_pos + slot);
-        out[0] = acc[0] * r.inv_mu_total;
-        out[1] = acc[1] * r.inv_mu_total;
-        out[2] = acc[2] * r.inv_mu_total;
-        out[3] = acc[3];
+        const double f = r.mu_ref * r.inv_mu_total;
+        out[0] = tot[0] * f;
+        out[1] = tot[1] * f;
+        out[2] = tot[2] * f;
+        out[3] = -r.mu_ref * tot[3];
     }
 }
 
 template <typename R>
 __device__ __forceinline__ const MaterialDev<R>& site_material(const ReplicaDev<R>& r, int i)
 {
-    return (r.flags & kPerSiteMaterial) ? r.mat[r.matid[i]] : r.mat[0];
+    return (r.flags & kPerSiteMaterial) ? r.mat[gload(r.matid, i)] : r.mat[0];
 }
 
 template <typename R>
@@ -234,13 +440,31 @@ __device__ __forceinline__ V3<R> site_axis(const ReplicaDev<R>& r, const Materia
     return V3<R>{m.axis[0], m.axis[1], m.axis[2]};
 }
 
+template <typename R>
+__device__ __forceinline__ void thermal_field(const ReplicaDev<R>& r, const MaterialDev<R>& m, int k, int i,
+                                              V3<R>& h)
+{
+    if (m.sigma != (R)0) {
+        R g[3];
+        thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
+        h.x += m.sigma * g[0];
+        h.y += m.sigma * g[1];
+        h.z += m.sigma * g[2];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Predictor.  For step k of the chunk: reads S (current state), writes the
 // predicted spin S' = |S + dS dt| and the corrector base S + dS dt / 2.
-// With MEASURE it only evaluates m and E of the state after the chunk.
-// When recording, the energy and magnetisation of the current state (the
-// state after the previous step) go to the replica's block partials: the
-// exchange field needed for the energy is the one the predictor computes.
+// With MEASURE it only evaluates m and E: of the state after the chunk's
+// steps (k == 0) or of the current state (k == 1).
+//
+// Records: the state the predictor reads at step k >= 1 is the state after
+// step k - 1, and its exchange field is at hand, so the predictor leaves
+// per-tile partials of m and E for record k - 1; the corrector of the same
+// step sums them by groups, and the tile-0 workgroup of the next predictor
+// (or of the measuring pass at the end of the chunk) adds the groups into
+// the record.  The chunk's last record is completed by k_finish.
 // ---------------------------------------------------------------------------
 template <typename R, bool MEASURE>
 __global__ __launch_bounds__(kBlockSites) void k_predict(const ReplicaDev<R>* __restrict__ reps,
@@ -248,67 +472,69 @@ __global__ __launch_bounds__(kBlockSites) void k_predict(const ReplicaDev<R>* __
                                                          const int* __restrict__ n_work, int k,
                                                          int remap)
 {
-    __shared__ R jt_s[kMaxTypes];
-    __shared__ double red[4][kBlockSites / 64];
-    const int lb = logical_block((int)blockIdx.x, (int)gridDim.x, remap);
-    if (lb >= *n_work)
-        return;
-    const WorkItem w = work[lb];
-    const ReplicaDev<R>& r = reps[w.replica];
-    // MEASURE with k == 0: the state after this chunk's steps; k == 1: the
-    // current state (no steps taken).
-    const int nsteps = r.nsteps;
-    if (MEASURE ? (!(r.flags & kRecord) || (k == 0 && nsteps <= 0)) : (k >= nsteps))
-        return;   // uniform over the block
-    const bool record = MEASURE || (r.flags & kRecord);
-    if (threadIdx.x < kMaxTypes)
-        jt_s[threadIdx.x] = r.jt[threadIdx.x];
-    __syncthreads();
-
-    const int i = w.block * kBlockSites + (int)threadIdx.x;
-    const int par = (r.parity + (MEASURE ? (k == 0 ? nsteps : 0) : k)) & 1;
-    const R* __restrict__ S = r.S[par];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < r.n) {
-        const MaterialDev<R>& m = site_material(r, i);
-        const V3<R> s = load3(S, i);
-        const V3<R> sum = exchange_sum(r, S, jt_s, i);
-        const V3<R> hex{m.mu_rel * sum.x, m.mu_rel * sum.y, m.mu_rel * sum.z};
-        const V3<R> e = site_axis(r, m, i);
-        const R se = dot(s, e);
-        const V3<R> Happ{r.H[0], r.H[1], r.H[2]};
-        if (record) {
-            const double mu = m.mu_s;
-            acc[0] = mu * (double)s.x;
-            acc[1] = mu * (double)s.y;
-            acc[2] = mu * (double)s.z;
-            const R eu = (R)0.5 * dot(s, hex) + m.ku_mu * se * se + dot(s, Happ);
-            acc[3] = -mu * (double)eu;
+    __shared__ Shared<R> sh;
+    __shared__ double red[4][kWaves];
+    const int W = *n_work;
+    int staged = -1;
+    for (TileIter it(W, remap); it.more(); it.next()) {
+        const WorkItem w = work[it.t];
+        const ReplicaDev<R>& r = reps[w.replica];
+        const int nsteps = r.nsteps;
+        if (MEASURE ? (!(r.flags & kRecord) || (k == 0 && nsteps <= 0)) : (k >= nsteps))
+            continue;   // uniform over the block
+        if (w.replica != staged) {
+            __syncthreads();
+            stage_tables(r, sh);
+            staged = w.replica;
         }
-        if (!MEASURE) {
-            V3<R> h{hex.x + m.ani * se * e.x + Happ.x, hex.y + m.ani * se * e.y + Happ.y,
-                    hex.z + m.ani * se * e.z + Happ.z};
-            if (m.sigma != (R)0) {
-                R g[3];
-                thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
-                h.x += m.sigma * g[0];
-                h.y += m.sigma * g[1];
-                h.z += m.sigma * g[2];
+        const bool recording = (r.flags & kRecord) != 0;
+        const bool partials = recording && (MEASURE || k >= 1);
+        const int i = w.block * kBlockSites + (int)threadIdx.x;
+        const int par = (r.parity + (MEASURE ? (k == 0 ? nsteps : 0) : k)) & 1;
+        const R* __restrict__ S = r.S[par];
+        R v[4] = {0, 0, 0, 0};
+        if (i < r.n) {
+            const MaterialDev<R>& m = site_material(r, i);
+            const V3<R> s = load3(S, i);
+            const V3<R> sum = exchange_sum(r, S, sh, i);
+            const V3<R> hex{m.mu_rel * sum.x, m.mu_rel * sum.y, m.mu_rel * sum.z};
+            const V3<R> e = site_axis(r, m, i);
+            const R se = dot(s, e);
+            const V3<R> Happ{r.H[0], r.H[1], r.H[2]};
+            if (partials) {
+                // in units of mu_ref: mu_s/mu_ref S and mu_s/mu_ref (-E_i/mu_s)
+                v[0] = m.mu_frac * s.x;
+                v[1] = m.mu_frac * s.y;
+                v[2] = m.mu_frac * s.z;
+                v[3] = m.mu_frac * ((R)0.5 * dot(s, hex) + m.ku_mu * se * se + dot(s, Happ));
             }
-            const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
-            const V3<R> sp = normalised(V3<R>{s.x + ds.x, s.y + ds.y, s.z + ds.z});
-            store3(r.Sp, i, sp);
-            store3(r.Bc, i, V3<R>{s.x + (R)0.5 * ds.x, s.y + (R)0.5 * ds.y, s.z + (R)0.5 * ds.z});
+            if (!MEASURE) {
+                V3<R> h{hex.x + m.ani * se * e.x + Happ.x, hex.y + m.ani * se * e.y + Happ.y,
+                        hex.z + m.ani * se * e.z + Happ.z};
+                thermal_field(r, m, k, i, h);
+                const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
+                const V3<R> sp = normalised(V3<R>{s.x + ds.x, s.y + ds.y, s.z + ds.z});
+                store3(r.Sp, i, sp);
+                store3(r.Bc, i, V3<R>{s.x + (R)0.5 * ds.x, s.y + (R)0.5 * ds.y, s.z + (R)0.5 * ds.z});
+            }
         }
-    }
-    if (record) {
-        block_sum4(acc, red);
-        if (threadIdx.x == 0) {
-            double* p = r.partials + 4 * (int64_t)w.block;
-            p[0] = acc[0];
-            p[1] = acc[1];
-            p[2] = acc[2];
-            p[3] = acc[3];
+        if (partials) {
+            double out[4];
+            block_sum4(v, out, red);
+            if (threadIdx.x == 0) {
+                double* p = r.partials + 4 * (int64_t)w.block;
+                p[0] = out[0];
+                p[1] = out[1];
+                p[2] = out[2];
+                p[3] = out[3];
+            }
+        }
+        // group partials left by the previous corrector -> their record
+        if (recording && w.block == 0) {
+            if (!MEASURE && k >= 2)
+                final_reduce(r, k - 2, red);
+            else if (MEASURE && k == 0 && nsteps >= 2)
+                final_reduce(r, nsteps - 2, red);
         }
     }
 }
@@ -316,8 +542,8 @@ __global__ __launch_bounds__(kBlockSites) void k_predict(const ReplicaDev<R>* __
 // ---------------------------------------------------------------------------
 // Corrector.  Field at S' with the same thermal numbers (same counter),
 // slope dS', and S_new = |S + (dS + dS') dt / 2| written to the other
-// ping-pong buffer.  Block 0 of each recording replica also reduces the
-// partials the predictor of this step left (the state after step k - 1).
+// ping-pong buffer.  Workgroups whose tile opens a group of kGroupTiles also
+// sum that group of the predictor's partials.
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(kBlockSites) void k_correct(const ReplicaDev<R>* __restrict__ reps,
@@ -325,56 +551,57 @@ __global__ __launch_bounds__(kBlockSites) void k_correct(const ReplicaDev<R>* __
                                                          const int* __restrict__ n_work, int k,
                                                          int remap)
 {
-    __shared__ R jt_s[kMaxTypes];
-    __shared__ double red[4][kBlockSites / 64];
-    const int lb = logical_block((int)blockIdx.x, (int)gridDim.x, remap);
-    if (lb >= *n_work)
-        return;
-    const WorkItem w = work[lb];
-    const ReplicaDev<R>& r = reps[w.replica];
-    if (k >= r.nsteps)
-        return;
-    if (threadIdx.x < kMaxTypes)
-        jt_s[threadIdx.x] = r.jt[threadIdx.x];
-    __syncthreads();
-
-    const int i = w.block * kBlockSites + (int)threadIdx.x;
-    if (i < r.n) {
-        const MaterialDev<R>& m = site_material(r, i);
-        const V3<R> sp = load3((const R*)r.Sp, i);
-        const V3<R> sum = exchange_sum(r, (const R*)r.Sp, jt_s, i);
-        const V3<R> e = site_axis(r, m, i);
-        const R se = dot(sp, e);
-        V3<R> h{m.mu_rel * sum.x + m.ani * se * e.x + r.H[0],
-                m.mu_rel * sum.y + m.ani * se * e.y + r.H[1],
-                m.mu_rel * sum.z + m.ani * se * e.z + r.H[2]};
-        if (m.sigma != (R)0) {
-            R g[3];
-            thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
-            h.x += m.sigma * g[0];
-            h.y += m.sigma * g[1];
-            h.z += m.sigma * g[2];
+    __shared__ Shared<R> sh;
+    __shared__ double red[4][kWaves];
+    const int W = *n_work;
+    int staged = -1;
+    for (TileIter it(W, remap); it.more(); it.next()) {
+        const WorkItem w = work[it.t];
+        const ReplicaDev<R>& r = reps[w.replica];
+        if (k >= r.nsteps)
+            continue;
+        if (w.replica != staged) {
+            __syncthreads();
+            stage_tables(r, sh);
+            staged = w.replica;
         }
-        const V3<R> ds = llg_step(sp, h, r.gdt, r.alpha);
-        const V3<R> b = load3((const R*)r.Bc, i);
-        const V3<R> sn = normalised(V3<R>{b.x + (R)0.5 * ds.x, b.y + (R)0.5 * ds.y, b.z + (R)0.5 * ds.z});
-        store3(r.S[(r.parity + k + 1) & 1], i, sn);
+        const int i = w.block * kBlockSites + (int)threadIdx.x;
+        if (i < r.n) {
+            const MaterialDev<R>& m = site_material(r, i);
+            const V3<R> sp = load3((const R*)r.Sp, i);
+            const V3<R> b = load3((const R*)r.Bc, i);
+            const V3<R> sum = exchange_sum(r, (const R*)r.Sp, sh, i);
+            const V3<R> e = site_axis(r, m, i);
+            const R se = dot(sp, e);
+            V3<R> h{m.mu_rel * sum.x + m.ani * se * e.x + r.H[0],
+                    m.mu_rel * sum.y + m.ani * se * e.y + r.H[1],
+                    m.mu_rel * sum.z + m.ani * se * e.z + r.H[2]};
+            thermal_field(r, m, k, i, h);
+            const V3<R> ds = llg_step(sp, h, r.gdt, r.alpha);
+            const V3<R> sn = normalised(V3<R>{b.x + (R)0.5 * ds.x, b.y + (R)0.5 * ds.y, b.z + (R)0.5 * ds.z});
+            store3(r.S[(r.parity + k + 1) & 1], i, sn);
+        }
+        if ((r.flags & kRecord) && k >= 1 && (w.block % kGroupTiles) == 0)
+            group_reduce(r, w.block / kGroupTiles, red);
     }
-    if ((r.flags & kRecord) && w.block == 0 && k > 0)
-        finalize_record(r, k - 1, red);
 }
 
-// Record from the MEASURE predictor's partials: mode 0 = last step of the
-// chunk (slot nsteps - 1), mode 1 = current state (slot 0).
+// The last record of a chunk (mode 0) or the current state's (mode 1): all
+// groups, then the total, by one workgroup per replica, in the same order
+// as the per-step path.
 template <typename R>
-__global__ __launch_bounds__(kBlockSites) void k_finalize_tail(const ReplicaDev<R>* __restrict__ reps,
-                                                               int mode)
+__global__ __launch_bounds__(kBlockSites) void k_finish(const ReplicaDev<R>* __restrict__ reps, int mode)
 {
-    __shared__ double red[4][kBlockSites / 64];
+    __shared__ double red[4][kWaves];
     const ReplicaDev<R>& r = reps[blockIdx.x];
     if (!(r.flags & kRecord) || (mode == 0 && r.nsteps <= 0))
         return;
-    finalize_record(r, mode == 0 ? r.nsteps - 1 : 0, red);
+    const int n_groups = (r.blocks + kGroupTiles - 1) / kGroupTiles;
+    for (int g = 0; g < n_groups; ++g)
+        group_reduce(r, g, red);
+    __threadfence_block();
+    __syncthreads();
+    final_reduce(r, mode == 0 ? r.nsteps - 1 : 0, red);
 }
 
 // End of a chunk: advance the step counter and the ping-pong parity.
@@ -486,11 +713,11 @@ hipError_t launch_correct(const ReplicaDev<R>* reps, const WorkItem* work, const
 }
 
 template <typename R>
-hipError_t launch_finalize_tail(const ReplicaDev<R>* reps, int n_rep, int mode, hipStream_t st)
+hipError_t launch_finish(const ReplicaDev<R>* reps, int n_rep, int mode, hipStream_t st)
 {
     if (n_rep <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((k_finalize_tail<R>), dim3(n_rep), dim3(kBlockSites), 0, st, reps, mode);
+    hipLaunchKernelGGL((k_finish<R>), dim3(n_rep), dim3(kBlockSites), 0, st, reps, mode);
     return hipGetLastError();
 }
 
@@ -510,6 +737,20 @@ hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStr
         return hipSuccess;
     hipLaunchKernelGGL((k_noise<R>), dim3((n + 255) / 256), dim3(256), 0, st, seed, step, n, out);
     return hipGetLastError();
+}
+
+template <typename R>
+int resident_blocks(int device)
+{
+    int cus = 0, a = 0, b = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)k_predict<R, false>, kBlockSites, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)k_correct<R>, kBlockSites, 0) != hipSuccess)
+        return 0;
+    const int per_cu = a < b ? a : b;
+    return cus * (per_cu > 0 ? per_cu : 1);
 }
 
 hipError_t launch_scatter_records(const double* rec, int count, double* m_dev, double* E_dev,
@@ -537,9 +778,10 @@ hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t s
     template hipError_t launch_correct<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, \
                                           int, hipStream_t);                                         \
     template hipError_t launch_accumulate<R>(const ReplicaDev<R>*, int, hipStream_t);                \
-    template hipError_t launch_finalize_tail<R>(const ReplicaDev<R>*, int, int, hipStream_t);             \
+    template hipError_t launch_finish<R>(const ReplicaDev<R>*, int, int, hipStream_t);              \
     template hipError_t launch_advance<R>(ReplicaDev<R>*, int, hipStream_t);                         \
-    template hipError_t launch_noise<R>(uint64_t, uint64_t, int, double*, hipStream_t);
+    template hipError_t launch_noise<R>(uint64_t, uint64_t, int, double*, hipStream_t);             \
+    template int resident_blocks<R>(int);
 
 SLLG_INSTANTIATE(float)
 SLLG_INSTANTIATE(double)

@@ -25,16 +25,22 @@ hipError_t launch_correct(const ReplicaDev<R>* reps, const WorkItem* work, const
 // Thermal-average block sums of every replica with kAverage.
 template <typename R>
 hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t st);
-// Record from the measuring predictor: mode 0 = the chunk's last step
-// (slot nsteps - 1), mode 1 = the current state (slot 0).
+// Completes the record of the measuring predictor's state for every
+// recording replica: mode 0 = the chunk's last step (slot nsteps - 1),
+// mode 1 = the current state (slot 0).
 template <typename R>
-hipError_t launch_finalize_tail(const ReplicaDev<R>* reps, int n_rep, int mode, hipStream_t st);
+hipError_t launch_finish(const ReplicaDev<R>* reps, int n_rep, int mode, hipStream_t st);
 // Step counter and ping-pong parity update at the end of a chunk.
 template <typename R>
 hipError_t launch_advance(ReplicaDev<R>* reps, int n_rep, hipStream_t st);
 // Thermal normals of sites 0..n-1 at one step, as the step kernels draw them.
 template <typename R>
 hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStream_t st);
+
+// Workgroups of the step kernels that fit on the device at once
+// (compute units x resident blocks per unit); 0 if it cannot be queried.
+template <typename R>
+int resident_blocks(int device);
 
 hipError_t launch_scatter_records(const double* rec, int count, double* m_dev, double* E_dev,
                                   hipStream_t st);

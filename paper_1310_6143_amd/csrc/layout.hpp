@@ -15,16 +15,23 @@
 namespace sllg {
 
 constexpr int kBlockSites = 256;      // sites per workgroup (one site per lane)
+constexpr int kGroupTiles = 256;      // tile partials summed together at the second level
 constexpr int kSlice = 64;            // rows per SELL slice = one wavefront
 constexpr int kMaxTypes = 16;         // interaction types per replica
 constexpr uint32_t kColBits = 28;     // packed neighbour: type << 28 | column
 constexpr uint32_t kColMask = (1u << kColBits) - 1u;
 constexpr int kMaxDegree = 255;
+// Stencil format: rows whose (column - row, type) lists coincide share one
+// pattern; a site stores only its pattern id (uint8).  Pattern entries pack
+// (column - row) << 4 | type in an int32 (offsets within +-2^27).
+constexpr int kMaxPatterns = 256;
+constexpr int kMaxPatternEntries = 1024;   // all patterns' entries, staged in LDS
 
 // Per-material constants, pre-scaled to field units (tesla).
 template <typename R>
 struct MaterialDev {
     R mu_rel;       // mu_ref / mu_s: exchange field = mu_rel * sum_k jt[type] S_j
+    R mu_frac;      // mu_s / mu_ref: weight of the site in m and E
     R ani;          // 2 k_u / mu_s  (anisotropy field factor)
     R ku_mu;        // k_u / mu_s    (anisotropy energy per unit moment)
     R sigma;        // thermal-field width sqrt(2 lambda kB T / (gamma mu_s dt))
@@ -38,6 +45,7 @@ enum ReplicaFlags : int32_t {
     kRecord = 4,            // compute m and E after every step
     kRecordSeries = 8,      // records[] holds the whole run: rec_pos advances per chunk
     kAverage = 16,          // add the records to the thermal-average block sums acc[]
+    kStencil = 32,          // neighbours in stencil form (pat_id / pat_tab) instead of SELL
 };
 
 template <typename R>
@@ -48,10 +56,14 @@ struct ReplicaDev {
     const uint32_t* nb;             // SELL-64 neighbour entries
     const int64_t* slice_off;       // [n_slices + 1] first entry of each slice
     const uint8_t* deg;             // [n] neighbours per site
+    const uint8_t* pat_id;          // [n] stencil pattern of each site (kStencil)
+    const int32_t* pat_tab;         // [pat_entries] packed offset << 4 | type
+    const uint16_t* pat_start;      // [n_patterns + 1] first entry of each pattern
     const uint8_t* matid;           // [n] or null
     const R* axis;                  // [3n] or null
     const MaterialDev<R>* mat;      // materials
-    double* partials;               // [blocks][4]: sum mu S (3), energy
+    double* partials;               // [blocks][4]: sum mu S (3), energy of each tile
+    double* group_partials;         // [groups][4]: sums over kGroupTiles consecutive tiles
     double* records;                // [cap][4] per-step m (3) and E
     double* acc;                    // [avg_blocks][5] sums of |m|, m (3), E per averaging block
     R jt[kMaxTypes];                // J / mu_ref per type (tesla)
@@ -59,6 +71,7 @@ struct ReplicaDev {
     R alpha;                        // lambda
     R H[3];                         // applied field (T)
     double inv_mu_total;            // 1 / sum_i mu_s,i
+    double mu_ref;                  // unit of the per-site m and E terms (J/T)
     uint64_t seed;                  // Philox key
     uint64_t step;                  // number of the next step (advanced on the device)
     int64_t rec_pos;                // record slot of the chunk's first step
@@ -71,7 +84,7 @@ struct ReplicaDev {
     int32_t parity;                 // S[parity] holds the current state (advanced on the device)
     int32_t nsteps;                 // steps this replica takes in the current chunk
     int32_t flags;                  // ReplicaFlags
-    int32_t pad;
+    int32_t n_patterns;             // stencil patterns (kStencil)
 };
 
 struct WorkItem {

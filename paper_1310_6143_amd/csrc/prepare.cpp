@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <unordered_map>
 #include <utility>
 
 namespace sllg {
@@ -12,7 +13,7 @@ void fail(sllg_status code, const std::string& msg) { throw Failure{code, msg}; 
 
 HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* col,
                               const uint8_t* ntype, const double* J, int n_types,
-                              bool check_symmetry)
+                              bool check_symmetry, bool allow_stencil)
 {
     if (n <= 0)
         fail(SLLG_E_ARG, "system has no spins");
@@ -76,6 +77,57 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
         for (int64_t i = sl * kSlice; i < std::min<int64_t>(n, (sl + 1) * kSlice); ++i)
             width = std::max<int>(width, s.deg[i]);
         s.slice_off[sl + 1] = s.slice_off[sl] + (int64_t)kSlice * width;
+    }
+    // Stencil form: the interaction list of a row, written relative to the
+    // row, repeats across a crystal (the paper builds it from the unit
+    // cell's neighbour template), so few patterns cover every row.
+    {
+        std::unordered_map<std::string, int> ids;
+        std::vector<uint8_t> pid((size_t)n);
+        std::vector<int32_t> tab;
+        std::vector<uint16_t> start{0};
+        std::string key;
+        bool ok = allow_stencil;
+        for (int64_t i = 0; i < n && ok; ++i) {
+            key.clear();
+            for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+                const int64_t off = (int64_t)col[q] - i;
+                const int32_t t = ntype ? ntype[q] : 0;
+                if (off < -(int64_t(1) << 27) || off >= (int64_t(1) << 27) || n * 24 >= (int64_t(1) << 31)) {
+                    ok = false;
+                    break;
+                }
+                const int32_t e = (int32_t)((uint32_t)off << 4) | t;
+                key.append(reinterpret_cast<const char*>(&e), sizeof(e));
+            }
+            if (!ok)
+                break;
+            auto it = ids.find(key);
+            if (it == ids.end()) {
+                const int id = (int)ids.size();
+                const size_t entries = tab.size() + key.size() / sizeof(int32_t);
+                if (id >= kMaxPatterns || entries > (size_t)kMaxPatternEntries) {
+                    ok = false;
+                    break;
+                }
+                it = ids.emplace(key, id).first;
+                const int32_t* e = reinterpret_cast<const int32_t*>(key.data());
+                tab.insert(tab.end(), e, e + key.size() / sizeof(int32_t));
+                start.push_back((uint16_t)tab.size());
+            }
+            pid[(size_t)i] = (uint8_t)it->second;
+        }
+        if (ok) {
+            s.stencil = true;
+            s.pat_id = std::move(pid);
+            s.pat_tab = std::move(tab);
+            s.pat_start = std::move(start);
+        }
+    }
+    if (s.stencil) {
+        std::vector<int64_t>().swap(s.slice_off);
+        std::vector<uint8_t>().swap(s.deg);
+        return s;
     }
     s.nb.assign((size_t)s.slice_off[n_slices], 0u);
     for (int64_t i = 0; i < n; ++i) {
@@ -202,6 +254,7 @@ std::vector<MaterialDev<R>> material_table(const HostMaterials& m, const Dynamic
     for (size_t q = 0; q < t.size(); ++q) {
         const double mu = m.mat_mu[q], ku = m.mat_ku[q];
         t[q].mu_rel = (R)(m.mu_ref / mu);
+        t[q].mu_frac = (R)(mu / m.mu_ref);
         t[q].ani = (R)(2.0 * ku / mu);
         t[q].ku_mu = (R)(ku / mu);
         t[q].sigma = (R)std::sqrt(2.0 * d.alpha * kBoltzmann * d.temperature / (d.gamma * mu * d.dt));
@@ -225,6 +278,7 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
     rec.H[1] = (R)d.H[1];
     rec.H[2] = (R)d.H[2];
     rec.inv_mu_total = 1.0 / m.mu_total;
+    rec.mu_ref = m.mu_ref;
     rec.seed = d.seed;
     rec.step = d.step;
     rec.n = (int32_t)s.n;
@@ -234,7 +288,10 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
         flags |= kPerSiteMaterial;
     if (m.per_site_axis)
         flags |= kPerSiteAxis;
+    if (s.stencil)
+        flags |= kStencil;
     rec.flags = flags;
+    rec.n_patterns = s.stencil ? (int32_t)s.pat_start.size() - 1 : 0;
 }
 
 void averages_from_block_sums(const double* acc, int n_blocks, int64_t block_len, double out[8])

@@ -32,12 +32,18 @@ struct HostStructure {
     std::vector<uint32_t> nb;          // packed entries, 64 rows per slice, column-major
     std::vector<int64_t> slice_off;    // [n_slices + 1]
     std::vector<uint8_t> deg;          // [n]
+    // stencil form, filled when every row matches one of few patterns
+    bool stencil = false;
+    std::vector<uint8_t> pat_id;       // [n]
+    std::vector<int32_t> pat_tab;      // packed (col - row) << 4 | type
+    std::vector<uint16_t> pat_start;   // [n_patterns + 1]
 };
 
 // Validates and converts.  Throws Failure(SLLG_E_ARG) on malformed input.
+// allow_stencil = false keeps the SELL form even when patterns would fit.
 HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* col,
                               const uint8_t* ntype, const double* J, int n_types,
-                              bool check_symmetry);
+                              bool check_symmetry, bool allow_stencil = true);
 
 // Materials: distinct (mu_s, k_u) pairs, per-site ids when there is more
 // than one, per-site easy axes when they differ.

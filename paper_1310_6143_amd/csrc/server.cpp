@@ -83,7 +83,9 @@ struct ServerT final : ServerBase {
         ReplicaDev<R>& r = batch.mirror(j.slot);
         const int64_t left = j.n_steps - j.steps_done;
         const int32_t ns = (int32_t)std::min<int64_t>(K, left);
-        int32_t flags = (r.flags & (kPerSiteMaterial | kPerSiteAxis)) | kRecord;
+        // keep the structural bits (materials, axes, neighbour layout); set
+        // only the per-run ones
+        int32_t flags = (r.flags & ~(kRecord | kRecordSeries | kAverage)) | kRecord;
         if (j.record)
             flags |= kRecordSeries;
         if (j.n_avg > 0)
@@ -457,6 +459,7 @@ void fill_result(const Job& j, sllg_result* r)
     r->t_submit = j.t_submit;
     r->t_start = j.t_start;
     r->t_done = j.t_done;
+    r->hbm_bytes = j.bytes;
 }
 bool settled(int state) { return state >= SLLG_REQ_DONE; }
 }  // namespace

@@ -27,8 +27,8 @@ def _oracle_run(w, n_steps, step0=0):
     return S, m, E
 
 
-def _gpu_run(w, n_steps, precision, **opts):
-    with sl.from_workload(w, precision=precision) as g:
+def _gpu_run(w, n_steps, precision, stencil=1, **opts):
+    with sl.from_workload(w, precision=precision, stencil=stencil) as g:
         for k, v in opts.items():
             g.set_option(k, v)
         m, E = g.integrate(n_steps)
@@ -47,13 +47,13 @@ def test_noise_stream_matches_oracle(step):
     assert np.all(err <= 2e-5 * (1.0 + np.abs(ref))), err.max()
 
 
-@pytest.mark.parametrize("T", [300.0, 0.0])
-def test_sc4096_fp64_matches_oracle(T):
+@pytest.mark.parametrize("T,stencil", [(300.0, 1), (0.0, 1), (300.0, 0)])
+def test_sc4096_fp64_matches_oracle(T, stencil):
     w = sc_reference(L=16, temperature=T, n_steps=1000, seed=42)
     S_ref, m_ref, E_ref = _oracle_run(w, 1000)
-    S, m, E = _gpu_run(w, 1000, sl.FP64)
+    S, m, E = _gpu_run(w, 1000, sl.FP64, stencil=stencil)
     ang = max_angle(S, S_ref)
-    print(f"FP64 T={T}: max angle {ang:.3e} rad")
+    print(f"FP64 T={T} stencil={stencil}: max angle {ang:.3e} rad")
     assert ang <= 1e-5
     assert np.abs(m - m_ref).max() <= 1e-9
     assert np.abs(E - E_ref).max() <= 1e-9 * np.abs(E_ref).max()
@@ -106,6 +106,25 @@ def test_bcc_j1j2_32cubed_fp64():
     print(f"bcc 32^3 J1+J2 FP64: max angle {ang:.3e}")
     assert ang <= 1e-5
     assert np.abs(E - E_ref).max() <= 1e-9 * np.abs(E_ref).max()
+
+
+@pytest.mark.parametrize("make", [lambda: sc_reference(L=12, temperature=300.0, seed=2),
+                                  lambda: bcc_film(nx=8, ny=6, nz=4, seed=3),
+                                  lambda: bcc_block(cells=10, n_steps=100)])
+def test_stencil_and_sell_layouts_agree_bitwise(make):
+    """Both neighbour layouts keep the CSR order of each row, so the exchange
+    sums, and hence whole trajectories, are identical bit for bit."""
+    w = make()
+    w.temperature = 300.0
+    for prec in (sl.FP32, sl.FP64):
+        with sl.from_workload(w, precision=prec, stencil=1) as a, \
+                sl.from_workload(w, precision=prec, stencil=0) as b:
+            assert a.get_option("neighbour_format") == 1
+            assert b.get_option("neighbour_format") == 0
+            ma, Ea = a.integrate(150)
+            mb, Eb = b.integrate(150)
+            assert np.array_equal(a.get_spins(), b.get_spins())
+            assert np.array_equal(ma, mb) and np.array_equal(Ea, Eb)
 
 
 def test_chunked_equals_single_call_bitwise():

@@ -119,10 +119,13 @@ def test_cancel_and_budget():
 
 
 def test_queue_drains_when_budget_admits_one_at_a_time():
-    # each L = 40 FP32 request needs about 4.7 MB of device memory; with an
-    # 8 MB budget they must run one after another, in arrival order
+    # with a budget of 1.5 requests the requests must run one after another,
+    # in arrival order
     reqs = [sc_request_system(40, 200.0, [0, 0, 0], 150, 40 + k) for k in range(4)]
-    with sl.Server(hbm_budget=8 << 20, chunk_steps=32) as srv:
+    with sl.Server(hbm_budget=1 << 30, chunk_steps=32) as probe:
+        size = probe.wait(probe.submit(reqs[0]), 60)["hbm_bytes"]
+    assert size > 1 << 20
+    with sl.Server(hbm_budget=int(1.5 * size), chunk_steps=32) as srv:
         tickets = [srv.submit(w) for w in reqs]
         res = [srv.wait(t, 120) for t in tickets]
         assert all(r["state"] == "done" for r in res)
