@@ -189,10 +189,17 @@ def main():
         n = args.calibrate_copy << 18          # float32 elements
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
         for _ in range(5):
             dst.copy_(src)
+        ev1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}))
+        ms = ev0.elapsed_time(ev1) / 5
+        print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 6, "ms_per_copy": ms,
+                          "read_plus_write_GBs": 2 * n * 4 / (ms / 1e3) / 1e9}))
         return
 
     from spin_systems import bcc_block

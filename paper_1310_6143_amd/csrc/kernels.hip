@@ -25,6 +25,23 @@
 #include "kernels.hpp"
 #include "layout.hpp"
 
+// Build-time tuning of the step kernels: gather-loop unroll depth (4 was
+// fastest on MI355X among 2, 4, 8 and 16) and an optional waves-per-SIMD
+// target (none: forcing 8 waves was slower).
+#ifndef SLLG_GATHER_UNROLL
+#define SLLG_GATHER_UNROLL 4
+#endif
+#ifndef SLLG_WAVES_PER_EU
+#define SLLG_WAVES_PER_EU 0
+#endif
+#if SLLG_WAVES_PER_EU > 0
+#define SLLG_STEP_ATTRS __launch_bounds__(kBlockSites) __attribute__((amdgpu_waves_per_eu(SLLG_WAVES_PER_EU)))
+#else
+#define SLLG_STEP_ATTRS __launch_bounds__(kBlockSites)
+#endif
+#define SLLG_PRAGMA(x) _Pragma(#x)
+#define SLLG_UNROLL(n) SLLG_PRAGMA(unroll n)
+
 namespace sllg {
 namespace {
 
@@ -233,7 +250,7 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
         const int ib = i * (int)(3 * sizeof(R));
         const int p = gload(r.pat_id, i);
         const int b = sh.pat_start[p], e = sh.pat_start[p + 1];
-#pragma unroll 8
+        SLLG_UNROLL(SLLG_GATHER_UNROLL)
         for (int k = b; k < e; ++k) {
             const PatEntry<R> pe = sh.pat[k];
             const V3<R> sj = bload3(rs, ib + pe.off, R(0));
@@ -467,7 +484,7 @@ __device__ __forceinline__ void thermal_field(const ReplicaDev<R>& r, const Mate
 // the record.  The chunk's last record is completed by k_finish.
 // ---------------------------------------------------------------------------
 template <typename R, bool MEASURE>
-__global__ __launch_bounds__(kBlockSites) void k_predict(const ReplicaDev<R>* __restrict__ reps,
+__global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps,
                                                          const WorkItem* __restrict__ work,
                                                          const int* __restrict__ n_work, int k,
                                                          int remap)
@@ -546,7 +563,7 @@ __global__ __launch_bounds__(kBlockSites) void k_predict(const ReplicaDev<R>* __
 // sum that group of the predictor's partials.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(kBlockSites) void k_correct(const ReplicaDev<R>* __restrict__ reps,
+__global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps,
                                                          const WorkItem* __restrict__ work,
                                                          const int* __restrict__ n_work, int k,
                                                          int remap)
