@@ -62,13 +62,20 @@ def measured_traffic(precision):
     return float(v.group(1))
 
 
-def run_gpu(w, precision, steps, warmup, torch):
+def run_gpu(w, precision, steps, warmup, torch, launch=None):
     import paper_1310_6143_amd as sl
 
     t0 = time.time()
     sysm = sl.from_workload(w, precision=precision, check_symmetry=False)
     log(f"precision {'fp32' if precision == sl.FP32 else 'fp64'}: set-up {time.time() - t0:.1f} s")
     st = torch.cuda.Stream()
+    if launch:
+        sysm.set_option("xcd_remap", launch[0])
+        sysm.set_option("grid_scale_pct", launch[1])
+        choice = {"xcd_remap": launch[0], "grid_scale_pct": launch[1], "graph_steps": sysm.get_option("graph_steps")}
+    else:
+        tuned_us, choice = sysm.autotune(10, stream=st)
+        log(f"  autotune: {tuned_us:.1f} us/step with {choice}")
     m_w = torch.empty((max(warmup, 1), 3), dtype=torch.float64, device="cuda")
     E_w = torch.empty(max(warmup, 1), dtype=torch.float64, device="cuda")
     m_dev = torch.empty((steps, 3), dtype=torch.float64, device="cuda")
@@ -93,7 +100,7 @@ def run_gpu(w, precision, steps, warmup, torch):
         raise SystemExit("non-finite energy in the timed run")
     sysm.close()
     log(f"  {steps} steps in {ms:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
-    return {"ms": ms, "wall_s": wall, "m": m, "E": E}
+    return {"ms": ms, "wall_s": wall, "m": m, "E": E, "launch": choice}
 
 
 def run_serving(args):
@@ -140,6 +147,67 @@ def run_serving(args):
     }
 
 
+def run_sweep(kind, precision, args):
+    """Full sweep workloads.  film: M(T) heating ramp 0..1500 K in 50 K steps
+    with 5000 + 5000 steps per point and continuation (bcc 64x64x16 film).
+    sphere: hysteresis H_z = -5..5 T in 0.1 T steps, 2000 steps per point
+    (1000 + 1000 averaged), fcc particle of radius 8 nm at 10 K."""
+    import paper_1310_6143_amd as sl
+    from spin_systems import bcc_film, fcc_nanoparticle
+
+    if kind == "film":
+        w = bcc_film()
+        pts = w.extra["temperatures"]
+        n_eq, n_avg = w.extra["n_eq"], w.extra["n_avg"]
+    else:
+        w = fcc_nanoparticle()
+        pts = np.stack([np.zeros_like(w.extra["fields_z"]), np.zeros_like(w.extra["fields_z"]),
+                        w.extra["fields_z"]], axis=1)
+        n_eq, n_avg = 1000, 1000
+    if args.sweep_points:
+        pts = pts[: args.sweep_points]
+    sysm = sl.from_workload(w, precision=precision)
+    sysm.integrate(10, record=False)              # first use: upload, graph capture
+    t0 = time.perf_counter()
+    if kind == "film":
+        rows = sysm.sweep_temperature(pts, n_eq, n_avg, 10)
+    else:
+        rows = sysm.sweep_field(pts, n_eq, n_avg, 10)
+    dt = time.perf_counter() - t0
+    sysm.close()
+    steps = len(pts) * (n_eq + n_avg)
+    return {"spin_steps_per_s": w.n * steps / dt, "seconds": dt, "n_spins": w.n, "steps": steps,
+            "points": [{"x": (float(r["T"]) if kind == "film" else float(r["H"][2])),
+                        "m_abs": r["m_abs"], "m_abs_se": r["m_abs_se"], "m_z": float(r["m"][2]),
+                        "E": r["E"], "E_se": r["E_se"]} for r in rows]}
+
+
+def sweep_main(args):
+    import paper_1310_6143_amd as sl
+
+    kind = args.workload
+    r32 = run_sweep(kind, sl.FP32, args)
+    out = {
+        "metric": METRIC, "value": r32["spin_steps_per_s"], "unit": "spin-steps/s", "n_gpus": 1,
+        "steps": r32["steps"], "warmup": 10, "ms_per_step": r32["seconds"] * 1e3 / r32["steps"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": ("M(T) ramp, bcc 64x64x16 film (131,072 spins), 0..1500 K in 50 K steps, "
+                                "5000 + 5000 steps per point, lambda = 1" if kind == "film" else
+                                "hysteresis sweep, fcc sphere R = 8 nm (196,053 spins), H_z = -5..5 T in "
+                                "0.1 T steps, 2000 steps per point, T = 10 K")},
+        "fp32": r32,
+    }
+    if not args.no_fp64:
+        r64 = run_sweep(kind, sl.FP64, args)
+        out["fp64"] = r64
+        dm = [abs(a["m_abs"] - b["m_abs"]) for a, b in zip(r32["points"], r64["points"])]
+        se = [np.hypot(a["m_abs_se"], b["m_abs_se"]) for a, b in zip(r32["points"], r64["points"])]
+        out["fp32_vs_fp64"] = {"max_abs_dM_over_Ms": float(max(dm)),
+                               "max_dM_in_combined_se": float(max(d / s if s > 0 else 0.0 for d, s in zip(dm, se)))}
+    print(json.dumps(out))
+
+
 def cpu_baseline(w, n_steps):
     import oracle
 
@@ -167,12 +235,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cells", type=int, default=160)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--only-fp64", action="store_true", help="time only the FP64 run (profiling)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-budget", type=int, default=16384, help="MiB")
     ap.add_argument("--serving-chunk", type=int, default=64)
+    ap.add_argument("--workload", default="block", choices=["block", "film", "sphere"],
+                    help="block: 8.19M-spin bcc step throughput (default); film: full M(T) ramp; "
+                         "sphere: full hysteresis sweep")
+    ap.add_argument("--sweep-points", type=int, default=0, help="limit the sweep to its first points")
+    ap.add_argument("--launch", default="", help="fixed launch shape 'tile_order,grid_scale_pct' "
+                    "instead of autotuning (for profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy of this many MiB (for counter calibration)")
     args = ap.parse_args()
@@ -202,6 +277,10 @@ def main():
                           "read_plus_write_GBs": 2 * n * 4 / (ms / 1e3) / 1e9}))
         return
 
+    if args.workload != "block":
+        sweep_main(args)
+        return
+
     from spin_systems import bcc_block
 
     t0 = time.time()
@@ -211,8 +290,13 @@ def main():
 
     import paper_1310_6143_amd as sl
 
-    r32 = run_gpu(w, sl.FP32, args.steps, args.warmup, torch)
-    r64 = None if args.no_fp64 else run_gpu(w, sl.FP64, args.steps, args.warmup, torch)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    if args.only_fp64:
+        r64 = run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch)
+        print(json.dumps({"fp64_ms_per_step": r64["ms"] / args.steps}))
+        return
+    r32 = run_gpu(w, sl.FP32, args.steps, args.warmup, torch, launch)
+    r64 = None if args.no_fp64 else run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch)
 
     n = w.n
     ms_step = r32["ms"] / args.steps
@@ -238,6 +322,7 @@ def main():
                         "alpha=0.05, dt=1e-16 s, seed 4; FP32 spins, FP64 m/E reductions every step",
             "n_spins": n,
             "neighbour_entries": int(w.lattice.nnz),
+            "launch_shape": r32["launch"],
         },
         "roofline": {
             "bound": "hbm",

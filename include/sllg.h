@@ -166,6 +166,17 @@ sllg_status sllg_sweep_temperature(sllg_system *sys, const double *T, int64_t n_
 sllg_status sllg_sweep_field(sllg_system *sys, const double *H, int64_t n_points, int64_t n_eq,
                              int64_t n_avg, int n_blocks, double *out, void *stream);
 
+/* Launch-shape autotuner: times every candidate launch configuration of the
+ * step kernels (tile orders 0, 1, 2 of "xcd_remap"; 1/2, 1 or 2 resident
+ * grids of workgroups per launch; for systems under 2^20 spins, 16, 64 or
+ * 256 steps per captured HIP graph) over trial_steps (2..100000) steps of
+ * this system, keeps the fastest and writes its time per step (us) to
+ * *us_per_step (may be NULL).  The spins, the step counter and every
+ * result stay exactly as they were: launch shapes do not change the
+ * arithmetic.  The choice can be read back with sllg_get_option
+ * ("xcd_remap", "grid_scale_pct", "graph_steps", "tuned_ns_per_step"). */
+sllg_status sllg_autotune(sllg_system *sys, int trial_steps, double *us_per_step, void *stream);
+
 /* Thermal normals Gamma[3n] of sites 0..n-1 at step `step`, drawn exactly as
  * the step kernels of the given precision draw them (Philox counter and
  * Box-Muller as in sllg_set_rng), copied to the host array out.  For
@@ -187,7 +198,13 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *   "graph_steps"     steps per captured HIP graph chunk, 0 = no graphs
  *                     (default: chosen from the system size)
  *   "block_sites"     sites per workgroup for the step kernels: 256 (default)
- *   "xcd_remap"       1 (default) / 0: map consecutive site blocks to one XCD
+ *   "xcd_remap"       tile order of the step launches: 1 (default) each XCD
+ *                     sweeps one contiguous range of 256-site tiles,
+ *                     interleaved over its workgroups; 2 the same ranges cut
+ *                     into one contiguous run per workgroup; 0 plain
+ *                     grid-stride order
+ *   "grid_scale_pct"  workgroups per step launch, in % of the resident grid
+ *                     (10..800, default 100)
  *   "stencil"         1 (default) / 0: let the next sllg_set_neighbours store
  *                     the list as per-site stencil patterns when at most 256
  *                     distinct (column - row, type) rows occur (<= 2048

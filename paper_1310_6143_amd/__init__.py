@@ -26,7 +26,7 @@ EXPORTS = [
     "sllg_set_materials", "sllg_set_integrator", "sllg_set_conditions", "sllg_set_rng",
     "sllg_get_step", "sllg_set_spins", "sllg_get_spins", "sllg_integrate", "sllg_integrate_dev",
     "sllg_measure", "sllg_average", "sllg_sweep_temperature", "sllg_sweep_field",
-    "sllg_thermal_normals", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
+    "sllg_thermal_normals", "sllg_autotune", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
     "sllg_set_option", "sllg_get_option",
     "sllg_server_create", "sllg_server_destroy", "sllg_server_last_error", "sllg_submit",
     "sllg_poll", "sllg_wait", "sllg_fetch", "sllg_cancel", "sllg_release", "sllg_server_get_stats",
@@ -104,6 +104,7 @@ def lib():
         "sllg_sweep_temperature": (c, [P, P, I64, I64, I64, c, P, P]),
         "sllg_sweep_field": (c, [P, P, I64, I64, I64, c, P, P]),
         "sllg_thermal_normals": (c, [c, c, U64, U64, I64, P]),
+        "sllg_autotune": (c, [P, c, ctypes.POINTER(D), P]),
         "sllg_checkpoint_size": (c, [P, ctypes.POINTER(ctypes.c_size_t)]),
         "sllg_checkpoint": (c, [P, P, ctypes.c_size_t]),
         "sllg_restore": (c, [P, P, ctypes.c_size_t]),
@@ -262,6 +263,13 @@ class SpinSystem:
         addresses; asynchronous on `stream` (a torch stream or address)."""
         self._check(lib().sllg_integrate_dev(self._h, int(n_steps), _dev_ptr(m_dev), _dev_ptr(E_dev),
                                              _stream(stream)))
+
+    def autotune(self, trial_steps=20, stream=None):
+        """Pick the fastest launch shape for this system (state unchanged);
+        returns (us per step, chosen options)."""
+        us = D()
+        self._check(lib().sllg_autotune(self._h, int(trial_steps), ctypes.byref(us), _stream(stream)))
+        return us.value, {k: self.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps")}
 
     def measure(self):
         m = np.empty(3)

@@ -49,6 +49,12 @@ struct Engine {
     virtual void run_chunk(int K, hipStream_t st, bool graph) = 0;
     virtual void measure_now(hipStream_t st) = 0;
     virtual void set_remap(int v) = 0;
+    virtual void set_grid_scale(double f) = 0;
+    virtual size_t spin_bytes() = 0;
+    virtual void save_spins(void* dst, hipStream_t st) = 0;
+    virtual void load_spins(const void* src, hipStream_t st) = 0;
+    virtual int parity() = 0;
+    virtual void set_parity(int p) = 0;
     virtual void mark_dirty() = 0;           // the record mirror changed
     virtual uint64_t step() = 0;
     virtual void set_step(uint64_t step) = 0;
@@ -97,6 +103,16 @@ struct EngineT final : Engine {
     void run_chunk(int K, hipStream_t st, bool graph) override { batch.run_chunk(K, st, graph); }
     void measure_now(hipStream_t st) override { batch.measure_now(st); }
     void set_remap(int v) override { batch.set_remap(v); }
+    void set_grid_scale(double f) override { batch.set_grid_scale(f); }
+    size_t spin_bytes() override { return 3 * (size_t)batch.mirror(q).n * sizeof(R); }
+    void save_spins(void* dst, hipStream_t st) override { batch.save_spins(q, dst, st); }
+    void load_spins(const void* src, hipStream_t st) override { batch.load_spins(q, src, st); }
+    int parity() override { return batch.mirror(q).parity; }
+    void set_parity(int p) override
+    {
+        batch.mirror(q).parity = p;
+        batch.mark_dirty();
+    }
     void mark_dirty() override { batch.mark_dirty(); }
     uint64_t step() override { return batch.mirror(q).step; }
     void set_step(uint64_t step) override
@@ -123,6 +139,9 @@ struct sllg_system {
     int64_t opt_graph_steps = -1;    // -1 = automatic
     int64_t opt_block_sites = kBlockSites;
     int64_t opt_xcd_remap = 1;
+    int64_t opt_grid_scale_pct = 100;   // workgroups per launch, % of the resident grid
+    bool tuned = false;
+    double tuned_us = 0.0;
     int64_t opt_stencil = 1;
     hipStream_t own = nullptr;
     std::unique_ptr<Engine> eng;
@@ -188,6 +207,7 @@ Engine& engine(sllg_system* s)
         const int64_t G = graph_steps(s);
         s->eng->create(s->st, s->mat, s->dyn, s->spins, std::max<int64_t>(G, kHostChunk));
         s->eng->set_remap((int)s->opt_xcd_remap);
+        s->eng->set_grid_scale(s->opt_grid_scale_pct / 100.0);
     }
     hip_check(hipSetDevice(s->device), "hipSetDevice");
     return *s->eng;
@@ -337,6 +357,90 @@ void average(sllg_system* s, int64_t n_eq, int64_t n_avg, int n_blocks, double o
     averages_from_block_sums(acc.data(), n_blocks, block_len, out);
     if (!std::isfinite(out[5]))
         fail(SLLG_E_NUMERIC, "the energy became non-finite during averaging");
+}
+
+// Launch-shape autotuner: time each candidate (XCD-contiguous tile ranges or
+// not; workgroups per launch as 1/2, 1 or 2 resident grids; for small
+// systems the steps per captured graph) over a few steps of the real system
+// and keep the fastest.  Results do not depend on these choices, and the
+// spins, step counter and buffer parity are restored afterwards, so tuning
+// leaves the trajectory untouched.
+double autotune(sllg_system* s, int trial_steps, hipStream_t st)
+{
+    Engine& e = engine(s);
+    ReplicaDevBase& r = e.rec();
+    const uint64_t step0 = e.step();
+    const int par0 = e.parity();
+    void* saved = nullptr;
+    hip_check(hipMalloc(&saved, e.spin_bytes()), "hipMalloc(autotune)");
+    struct Cand {
+        int remap;
+        int64_t scale_pct;
+        int64_t graph;
+    };
+    std::vector<Cand> cands;
+    const bool small = s->n < (int64_t(1) << 20);
+    for (int remap : {1, 2, 0})
+        for (int64_t scale : {100, 50, 200})
+            for (int64_t g : small ? std::vector<int64_t>{64, 16, 256} : std::vector<int64_t>{0})
+                cands.push_back({remap, scale, g});
+    hipEvent_t a = nullptr, b = nullptr;
+    double best = 1e30;
+    Cand best_c = {(int)s->opt_xcd_remap, s->opt_grid_scale_pct, graph_steps(s)};
+    const int32_t flags0 = *r.flags;
+    try {
+        hip_check(hipEventCreate(&a), "hipEventCreate");
+        hip_check(hipEventCreate(&b), "hipEventCreate");
+        e.save_spins(saved, st);
+        for (const Cand& c : cands) {
+            if (c.graph > e.rec_cap())
+                continue;
+            s->opt_xcd_remap = c.remap;
+            s->opt_grid_scale_pct = c.scale_pct;
+            s->opt_graph_steps = c.graph;
+            e.set_remap(c.remap);
+            e.set_grid_scale(c.scale_pct / 100.0);
+            const int steps = c.graph > 0 ? (int)std::max<int64_t>(c.graph, trial_steps) : trial_steps;
+            run_steps(s, std::max<int64_t>(c.graph, 2), nullptr, nullptr, nullptr, nullptr, st, 0);  // warm
+            hip_check(hipEventRecord(a, st), "hipEventRecord");
+            run_steps(s, steps, nullptr, nullptr, nullptr, nullptr, st, 0);
+            hip_check(hipEventRecord(b, st), "hipEventRecord");
+            hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+            const double us = 1e3 * ms / steps;
+            if (us < best) {
+                best = us;
+                best_c = c;
+            }
+        }
+    } catch (...) {
+        (void)hipFree(saved);
+        if (a)
+            (void)hipEventDestroy(a);
+        if (b)
+            (void)hipEventDestroy(b);
+        throw;
+    }
+    // restore the state and apply the winner
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    e.set_parity(par0);
+    e.load_spins(saved, st);
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    e.set_step(step0);
+    *r.flags = flags0;
+    e.mark_dirty();
+    (void)hipFree(saved);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    s->opt_xcd_remap = best_c.remap;
+    s->opt_grid_scale_pct = best_c.scale_pct;
+    s->opt_graph_steps = best_c.graph;
+    e.set_remap(best_c.remap);
+    e.set_grid_scale(best_c.scale_pct / 100.0);
+    s->tuned = true;
+    s->tuned_us = best;
+    return best;
 }
 
 void apply_dynamics(sllg_system* s)
@@ -678,6 +782,17 @@ sllg_status sllg_restore(sllg_system* sys, const void* buf, size_t bytes)
     });
 }
 
+sllg_status sllg_autotune(sllg_system* sys, int trial_steps, double* us_per_step, void* stream)
+{
+    return guard(sys, [&] {
+        if (trial_steps < 2 || trial_steps > 100000)
+            fail(SLLG_E_ARG, "trial_steps must be in 2..100000");
+        const double us = autotune(sys, trial_steps, pick_stream(sys, stream));
+        if (us_per_step)
+            *us_per_step = us;
+    });
+}
+
 sllg_status sllg_thermal_normals(int device, sllg_precision precision, uint64_t seed, uint64_t step,
                                  int64_t n, double* out)
 {
@@ -718,10 +833,18 @@ sllg_status sllg_set_option(sllg_system* sys, const char* key, int64_t value)
             if (value != kBlockSites)
                 fail(SLLG_E_ARG, "block_sites: only 256 is built");
             sys->opt_block_sites = value;
+        } else if (k == "grid_scale_pct") {
+            if (value < 10 || value > 800)
+                fail(SLLG_E_ARG, "grid_scale_pct must be in 10..800");
+            sys->opt_grid_scale_pct = value;
+            if (sys->eng)
+                sys->eng->set_grid_scale(value / 100.0);
         } else if (k == "stencil") {
             sys->opt_stencil = value ? 1 : 0;   // applies to the next sllg_set_neighbours
         } else if (k == "xcd_remap") {
-            sys->opt_xcd_remap = value ? 1 : 0;
+            if (value < 0 || value > 2)
+                fail(SLLG_E_ARG, "xcd_remap must be 0, 1 or 2");
+            sys->opt_xcd_remap = value;
             if (sys->eng)
                 sys->eng->set_remap((int)sys->opt_xcd_remap);
         } else {
@@ -745,6 +868,10 @@ sllg_status sllg_get_option(const sllg_system* sys, const char* key, int64_t* va
         *value = sys->opt_xcd_remap;
     else if (k == "stencil")
         *value = sys->opt_stencil;
+    else if (k == "grid_scale_pct")
+        *value = sys->opt_grid_scale_pct;
+    else if (k == "tuned_ns_per_step")
+        *value = sys->tuned ? (int64_t)(sys->tuned_us * 1e3) : -1;
     else if (k == "neighbour_format")
         *value = sys->has_nb ? (sys->st.stencil ? 1 : 0) : -1;
     else

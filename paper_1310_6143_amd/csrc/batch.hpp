@@ -391,7 +391,8 @@ public:
         // fit on the device at once (a multiple of 8 for the XCD mapping).
         // A changing batch always launches the full resident grid so that
         // one captured graph serves every batch.
-        int grid = (int)std::min<int64_t>(((int64_t)nwork + 7) & ~int64_t(7), resident_);
+        const int64_t cap = std::max<int64_t>(8, ((int64_t)(resident_ * grid_scale_) + 7) & ~int64_t(7));
+        int grid = (int)std::min<int64_t>(((int64_t)nwork + 7) & ~int64_t(7), cap);
         if (round_grid_)
             grid = resident_;
         if (nwork == 0)
@@ -488,6 +489,30 @@ public:
     }
     int remap() const { return remap_; }
     void set_round_grid(bool v) { round_grid_ = v; }
+    // Workgroups per launch as a multiple of the resident grid (the tiles are
+    // swept by that many workgroups; more than resident lets the hardware
+    // schedule them, fewer keeps each on its XCD range longer).
+    void set_grid_scale(double f)
+    {
+        if (f != grid_scale_) {
+            grid_scale_ = f;
+            dirty_ = true;
+        }
+    }
+    double grid_scale() const { return grid_scale_; }
+    // Copy the current spins of replica q to / from a device scratch buffer.
+    void save_spins(int q, void* dst, hipStream_t st)
+    {
+        const ReplicaDev<R>& r = slots_[q].rec;
+        hip_check(hipMemcpyAsync(dst, r.S[r.parity], 3 * (size_t)r.n * sizeof(R), hipMemcpyDeviceToDevice, st),
+                  "save spins");
+    }
+    void load_spins(int q, const void* src, hipStream_t st)
+    {
+        const ReplicaDev<R>& r = slots_[q].rec;
+        hip_check(hipMemcpyAsync(r.S[r.parity], src, 3 * (size_t)r.n * sizeof(R), hipMemcpyDeviceToDevice, st),
+                  "restore spins");
+    }
     int grid() const { return grid_; }
     int n_replica_slots() const { return (int)slots_.size(); }
 
@@ -532,6 +557,7 @@ private:
     int64_t work_cap_ = 0;
     int grid_ = 0;
     int resident_ = 0;
+    double grid_scale_ = 1.0;
     int remap_ = 1;
     bool round_grid_ = false;
     bool dirty_ = true;

@@ -276,20 +276,30 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
 
 // Work distribution.  A launch has a fixed number of workgroups (about the
 // number that fit on the chip at once), each sweeping many 256-site tiles.
-// Workgroups are handed to the 8 XCDs round-robin, so with `remap` the
-// workgroups of XCD x share one contiguous range of tiles and neighbouring
-// sites meet in that XCD's L2.
+// Workgroups are handed to the 8 XCDs round-robin.  Mode 0: plain
+// grid-stride.  Mode 1: the workgroups of XCD x share one contiguous range
+// of tiles (neighbouring sites meet in that XCD's L2), interleaved tile by
+// tile.  Mode 2: the same XCD ranges, each split into one contiguous run of
+// tiles per workgroup (the previous tiles of a run are still in the
+// workgroup's L1 when the next one needs them).
 struct TileIter {
     int64_t t, end, stride;
-    __device__ TileIter(int W, int remap)
+    __device__ TileIter(int W, int mode)
     {
         const int G = (int)gridDim.x, b = (int)blockIdx.x;
-        if (remap && (G & 7) == 0) {
-            const int x = b & 7;
+        if (mode != 0 && (G & 7) == 0) {
+            const int x = b & 7, u = b >> 3, Gx = G >> 3;
             const int64_t lo = (int64_t)W * x / 8, hi = (int64_t)W * (x + 1) / 8;
-            t = lo + (b >> 3);
-            end = hi;
-            stride = G >> 3;
+            if (mode == 2) {
+                const int64_t run = (hi - lo + Gx - 1) / Gx;
+                t = lo + (int64_t)u * run;
+                end = t + run < hi ? t + run : hi;
+                stride = 1;
+            } else {
+                t = lo + u;
+                end = hi;
+                stride = Gx;
+            }
         } else {
             t = b;
             end = W;

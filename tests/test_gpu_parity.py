@@ -157,14 +157,30 @@ def test_graph_and_direct_launches_agree_bitwise():
 def test_xcd_remap_does_not_change_results():
     w = sc_reference(L=20, temperature=300.0, seed=5)
     res = []
-    for remap in (0, 1):
+    for remap in (0, 1, 2):
         with sl.from_workload(w, precision=sl.FP32) as g:
             g.set_option("xcd_remap", remap)
             m, E = g.integrate(100)
             res.append((g.get_spins(), m, E))
-    assert np.array_equal(res[0][0], res[1][0])
-    assert np.array_equal(res[0][1], res[1][1])
-    assert np.array_equal(res[0][2], res[1][2])
+    for other in res[1:]:
+        assert np.array_equal(res[0][0], other[0])
+        assert np.array_equal(res[0][1], other[1])
+        assert np.array_equal(res[0][2], other[2])
+
+
+@pytest.mark.parametrize("L", [12, 64])
+def test_autotune_leaves_trajectory_unchanged(L):
+    w = sc_reference(L=L, temperature=300.0, seed=13)
+    with sl.from_workload(w, precision=sl.FP32) as a, sl.from_workload(w, precision=sl.FP32) as b:
+        a.integrate(7, record=False)
+        b.integrate(7, record=False)
+        us, choice = a.autotune(8)
+        assert us > 0 and choice["grid_scale_pct"] in (50, 100, 200)
+        assert a.step == b.step == 7
+        ma, Ea = a.integrate(100)
+        mb, Eb = b.integrate(100)
+        assert np.array_equal(a.get_spins(), b.get_spins())
+        assert np.array_equal(ma, mb) and np.array_equal(Ea, Eb)
 
 
 def test_run_to_run_determinism():
