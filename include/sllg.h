@@ -197,9 +197,8 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *   "check_symmetry"  1 (default) / 0: verify J_ij = J_ji in set_neighbours
  *   "graph_steps"     steps per captured HIP graph chunk, 0 = no graphs
  *                     (default: chosen from the system size)
- *   "block_sites"     sites per workgroup for the step kernels: 256 (default)
  *   "xcd_remap"       tile order of the step launches: 1 (default) each XCD
- *                     sweeps one contiguous range of 256-site tiles,
+ *                     sweeps one contiguous range of tiles,
  *                     interleaved over its workgroups; 2 the same ranges cut
  *                     into one contiguous run per workgroup; 0 plain
  *                     grid-stride order
@@ -207,9 +206,12 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     (10..800, default 100)
  *   "stencil"         1 (default) / 0: let the next sllg_set_neighbours store
  *                     the list as per-site stencil patterns when at most 256
- *                     distinct (column - row, type) rows occur (<= 2048
+ *                     distinct (column - row, type) rows occur (<= 1024
  *                     entries in all); 0 keeps the general SELL-64 form
- * sllg_get_option also reads "neighbour_format": 1 stencil, 0 SELL, -1 unset.
+ * sllg_get_option also reads "neighbour_format": 1 stencil, 0 SELL, -1 unset;
+ * "tile_sites": consecutive sites one workgroup integrates together (1024 in
+ * FP32, 512 in FP64); "halo": neighbours with |column - row| up to this many
+ * sites are read from the tile's window in LDS, the rest from HBM (-1 unset).
  */
 sllg_status sllg_set_option(sllg_system *sys, const char *key, int64_t value);
 sllg_status sllg_get_option(const sllg_system *sys, const char *key, int64_t *value);

@@ -137,7 +137,6 @@ struct sllg_system {
     std::vector<double> spins;       // host state until the engine exists
     int64_t opt_check_symmetry = 1;
     int64_t opt_graph_steps = -1;    // -1 = automatic
-    int64_t opt_block_sites = kBlockSites;
     int64_t opt_xcd_remap = 1;
     int64_t opt_grid_scale_pct = 100;   // workgroups per launch, % of the resident grid
     bool tuned = false;
@@ -527,7 +526,7 @@ sllg_status sllg_set_neighbours(sllg_system* sys, const int64_t* row_ptr, const 
 {
     return guard(sys, [&] {
         HostStructure st = build_structure(sys->n, row_ptr, col, ntype, J, n_types,
-                                           sys->opt_check_symmetry != 0, sys->opt_stencil != 0);
+                                           sys->opt_check_symmetry != 0, kHaloCap, sys->opt_stencil != 0);
         drop_engine(sys);
         sys->st = std::move(st);
         sys->has_nb = true;
@@ -829,10 +828,6 @@ sllg_status sllg_set_option(sllg_system* sys, const char* key, int64_t value)
             if (sys->eng && value > sys->eng->rec_cap())
                 fail(SLLG_E_STATE, "graph_steps larger than the record buffer; set it before the first run");
             sys->opt_graph_steps = value;
-        } else if (k == "block_sites") {
-            if (value != kBlockSites)
-                fail(SLLG_E_ARG, "block_sites: only 256 is built");
-            sys->opt_block_sites = value;
         } else if (k == "grid_scale_pct") {
             if (value < 10 || value > 800)
                 fail(SLLG_E_ARG, "grid_scale_pct must be in 10..800");
@@ -862,8 +857,10 @@ sllg_status sllg_get_option(const sllg_system* sys, const char* key, int64_t* va
         *value = sys->opt_check_symmetry;
     else if (k == "graph_steps")
         *value = graph_steps(sys);
-    else if (k == "block_sites")
-        *value = sys->opt_block_sites;
+    else if (k == "tile_sites")
+        *value = sys->prec == SLLG_FP64 ? tile_sites<double>() : tile_sites<float>();
+    else if (k == "halo")
+        *value = sys->has_nb ? sys->st.halo : -1;
     else if (k == "xcd_remap")
         *value = sys->opt_xcd_remap;
     else if (k == "stencil")

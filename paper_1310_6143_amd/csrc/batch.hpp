@@ -122,18 +122,21 @@ private:
     std::map<size_t, size_t> used_;
 };
 
+inline size_t pad16(size_t b) { return (b + 15) & ~size_t(15); }
+
 // Bytes of device memory one replica needs (used for admission).
 inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size_t real_bytes,
                             int64_t rec_cap, int avg_cap)
 {
     auto r = [](size_t b) { return PoolAllocator::round(b); };
     const size_t n = (size_t)s.n;
-    const size_t blocks = (n + kBlockSites - 1) / kBlockSites;
-    size_t b = 4 * r(3 * n * real_bytes);                       // S[2], Sp, Bc
+    const size_t tile = real_bytes == 4 ? tile_sites<float>() : tile_sites<double>();
+    const size_t blocks = (n + tile - 1) / tile;
+    size_t b = 4 * r(spin_buffer_bytes(s.n, real_bytes));       // S[2], Sp, Bc
     if (s.stencil)
-        b += r(n) + r(s.pat_tab.size() * 4) + r(s.pat_start.size() * 2);
+        b += r(pad16(n)) + r(s.pat_tab.size() * 4) + r(s.pat_start.size() * 2) + r(s.pat_far.size() * 2);
     else
-        b += r(s.nb.size() * 4) + r(s.slice_off.size() * 8) + r(n);
+        b += r(s.nb.size() * 4) + r(s.slice_off.size() * 8) + r(2 * n);
     if (m.per_site_material)
         b += r(n);
     if (m.per_site_axis)
@@ -221,7 +224,7 @@ public:
         sl.rec_cap = std::max<int64_t>(rec_cap, 1);
         sl.avg_cap = std::max(avg_cap, 1);
         const size_t n = (size_t)s.n;
-        const size_t blocks = (n + kBlockSites - 1) / kBlockSites;
+        const size_t blocks = (n + tile_sites<R>() - 1) / tile_sites<R>();
         try {
             auto get = [&](size_t bytes) {
                 void* p = alloc_->alloc(bytes);
@@ -229,21 +232,30 @@ public:
                 return p;
             };
             ReplicaDev<R>& r = sl.rec;
-            r.S[0] = (R*)get(3 * n * sizeof(R));
-            r.S[1] = (R*)get(3 * n * sizeof(R));
-            r.Sp = (R*)get(3 * n * sizeof(R));
-            r.Bc = (R*)get(3 * n * sizeof(R));
+            const size_t sb = spin_buffer_bytes(s.n, sizeof(R));
+            r.S[0] = (R*)get(sb);
+            r.S[1] = (R*)get(sb);
+            r.Sp = (R*)get(sb);
+            r.Bc = (R*)get(sb);
+            // the padding is staged with the last tile's window: keep it finite
+            for (void* p : {(void*)r.S[0], (void*)r.S[1], (void*)r.Sp, (void*)r.Bc})
+                hip_check(hipMemset(p, 0, sb), "clear spins");
             r.nb = nullptr;
             r.slice_off = nullptr;
             r.deg = nullptr;
             r.pat_id = nullptr;
             r.pat_tab = nullptr;
             r.pat_start = nullptr;
+            r.pat_far = nullptr;
             if (s.stencil) {
-                uint8_t* pid = (uint8_t*)get(n);
+                uint8_t* pid = (uint8_t*)get(pad16(n));
                 int32_t* tab = (int32_t*)get(std::max<size_t>(s.pat_tab.size(), 1) * 4);
                 uint16_t* ps = (uint16_t*)get(s.pat_start.size() * 2);
+                uint16_t* pf = (uint16_t*)get(std::max<size_t>(s.pat_far.size(), 1) * 2);
+                hip_check(hipMemset(pid, 0, pad16(n)), "clear pattern ids");
                 hip_check(hipMemcpy(pid, s.pat_id.data(), n, hipMemcpyHostToDevice), "upload pattern ids");
+                hip_check(hipMemcpy(pf, s.pat_far.data(), s.pat_far.size() * 2, hipMemcpyHostToDevice),
+                          "upload pattern splits");
                 hip_check(hipMemcpy(tab, s.pat_tab.data(), s.pat_tab.size() * 4, hipMemcpyHostToDevice),
                           "upload patterns");
                 hip_check(hipMemcpy(ps, s.pat_start.data(), s.pat_start.size() * 2, hipMemcpyHostToDevice),
@@ -251,14 +263,15 @@ public:
                 r.pat_id = pid;
                 r.pat_tab = tab;
                 r.pat_start = ps;
+                r.pat_far = pf;
             } else {
                 uint32_t* nb = (uint32_t*)get(std::max<size_t>(s.nb.size(), 1) * 4);
                 int64_t* so = (int64_t*)get(s.slice_off.size() * 8);
-                uint8_t* dg = (uint8_t*)get(n);
+                uint16_t* dg = (uint16_t*)get(2 * n);
                 hip_check(hipMemcpy(nb, s.nb.data(), s.nb.size() * 4, hipMemcpyHostToDevice), "upload nb");
                 hip_check(hipMemcpy(so, s.slice_off.data(), s.slice_off.size() * 8, hipMemcpyHostToDevice),
                           "upload slices");
-                hip_check(hipMemcpy(dg, s.deg.data(), n, hipMemcpyHostToDevice), "upload deg");
+                hip_check(hipMemcpy(dg, s.deg.data(), 2 * n, hipMemcpyHostToDevice), "upload deg");
                 r.nb = nb;
                 r.slice_off = so;
                 r.deg = dg;
@@ -364,7 +377,7 @@ public:
                 continue;
             const ReplicaDev<R>& r = sl.rec;
             const bool stencil = (r.flags & kStencil) != 0;
-            if ((stencil && (!r.pat_id || !r.pat_tab || !r.pat_start)) ||
+            if ((stencil && (!r.pat_id || !r.pat_tab || !r.pat_start || !r.pat_far)) ||
                 (!stencil && (!r.nb || !r.slice_off || !r.deg)) ||
                 ((r.flags & kPerSiteMaterial) && !r.matid) || ((r.flags & kPerSiteAxis) && !r.axis) ||
                 ((r.flags & kAverage) && (!(r.flags & kRecord) || !r.acc)))

@@ -14,10 +14,14 @@
 //    global "all predictors before any corrector" barrier.
 //
 // Data layout (see layout.hpp): spins are xyz-interleaved (3 reals per
-// site); neighbours are SELL-64 (a slice of 64 consecutive rows is stored
-// column-major, so lane l of a wavefront reads entry k of its row at
-// nb[slice_off + 64 k + l]: every load instruction of the gather is one
-// contiguous 256-byte run); each entry packs type << 28 | column.
+// site).  Neighbours are stencil patterns (a uint8 pattern id per site, the
+// patterns' (offset, J) lists in LDS) or SELL-64 (a slice of 64 consecutive
+// rows is stored column-major, so lane l of a wavefront reads entry k of its
+// row at nb[slice_off + 64 k + l]; each entry packs type << 28 | column).
+// A workgroup integrates a tile of consecutive sites; it first copies the
+// tile's spins and a halo on either side into LDS with 16-byte loads, reads
+// the near links of every row (listed first) from there and only the far
+// ones from global memory.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -34,10 +38,21 @@
 #ifndef SLLG_WAVES_PER_EU
 #define SLLG_WAVES_PER_EU 0
 #endif
+// Near (LDS) gathers per unrolled step, and far gathers held in registers
+// while the near part is summed.
+#ifndef SLLG_NEAR_UNROLL
+#define SLLG_NEAR_UNROLL 4
+#endif
+#ifndef SLLG_FAR_REGS_F32
+#define SLLG_FAR_REGS_F32 6
+#endif
+#ifndef SLLG_FAR_REGS_F64
+#define SLLG_FAR_REGS_F64 6
+#endif
 #if SLLG_WAVES_PER_EU > 0
-#define SLLG_STEP_ATTRS __launch_bounds__(kBlockSites) __attribute__((amdgpu_waves_per_eu(SLLG_WAVES_PER_EU)))
+#define SLLG_STEP_ATTRS __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(SLLG_WAVES_PER_EU)))
 #else
-#define SLLG_STEP_ATTRS __launch_bounds__(kBlockSites)
+#define SLLG_STEP_ATTRS __launch_bounds__(kBlockThreads)
 #endif
 #define SLLG_PRAGMA(x) _Pragma(#x)
 #define SLLG_UNROLL(n) SLLG_PRAGMA(unroll n)
@@ -216,9 +231,20 @@ template <typename R>
 struct Shared {
     R jt[kMaxTypes];
     uint16_t pat_start[kMaxPatterns + 1];
+    uint16_t pat_far[kMaxPatterns];
     PatEntry<R> pat[kMaxPatternEntries];
 };
 
+// The tile being integrated: spins of sites [i0 - halo, i0 + tile + halo)
+// and the tile's pattern ids.
+template <typename R>
+struct TileLds {
+    static constexpr int kWindow = tile_sites<R>() + 2 * kHaloCap;
+    alignas(16) R win[3 * kWindow];
+    alignas(16) uint8_t pid[tile_sites<R>()];
+};
+
+// Caller synchronises before (tables may still be read) and after.
 template <typename R>
 __device__ __forceinline__ void stage_tables(const ReplicaDev<R>& r, Shared<R>& sh)
 {
@@ -226,56 +252,149 @@ __device__ __forceinline__ void stage_tables(const ReplicaDev<R>& r, Shared<R>& 
         sh.jt[threadIdx.x] = r.jt[threadIdx.x];
     if (r.flags & kStencil) {
         const int np = r.n_patterns;
-        for (int q = threadIdx.x; q <= np; q += kBlockSites)
+        for (int q = threadIdx.x; q <= np; q += kBlockThreads)
             sh.pat_start[q] = gload(r.pat_start, q);
+        for (int q = threadIdx.x; q < np; q += kBlockThreads)
+            sh.pat_far[q] = gload(r.pat_far, q);
         const int ne = gload(r.pat_start, np);
-        for (int q = threadIdx.x; q < ne; q += kBlockSites) {
+        for (int q = threadIdx.x; q < ne; q += kBlockThreads) {
             const int32_t raw = gload(r.pat_tab, q);
             sh.pat[q].off = (raw >> 4) * (int)(3 * sizeof(R));
             sh.pat[q].J = r.jt[raw & 15];
         }
     }
-    __syncthreads();
 }
 
-// sum_k J_k S[j_k] over the neighbours of site i: from the site's stencil
-// pattern (LDS) or from its SELL row.
+// 16-byte chunks [skip, skip + lim) of dst come from memory at base, the
+// others are zero.
+__device__ __forceinline__ void stage_chunks(const void* base, int skip, int lim, int nc, v4i* dst)
+{
+    const __amdgpu_buffer_rsrc_t rs = spin_rsrc(base, lim * 16);
+    for (int q = threadIdx.x; q < nc; q += kBlockThreads) {
+        const int c = q - skip;
+        v4i v = {0, 0, 0, 0};
+        if (c >= 0 && c < lim)
+            v = __builtin_amdgcn_raw_buffer_load_b128(rs, c * 16, 0, 0);
+        dst[q] = v;
+    }
+}
+
+// Spins of window sites [wb, wb + wn) (wb and wn multiples of 4, so every
+// chunk boundary is a site-group boundary); sites outside the replica read
+// as zero and are never used.
+template <typename R>
+__device__ __forceinline__ void stage_window(const R* __restrict__ S, int n, int wb, int wn, R* win)
+{
+    constexpr int kSiteBytes = 3 * (int)sizeof(R);
+    const int first = wb < 0 ? 0 : wb;
+    const int skip = (first - wb) * kSiteBytes / 16;
+    const int nc = wn * kSiteBytes / 16;
+    const int64_t avail = (int64_t)spin_buffer_bytes(n, sizeof(R)) - (int64_t)first * kSiteBytes;
+    const int lim = (int)min<int64_t>(avail > 0 ? avail / 16 : 0, (int64_t)(nc - skip));
+    stage_chunks(S + 3 * (int64_t)first, skip, lim, nc, (v4i*)win);
+}
+
+template <typename R>
+__device__ __forceinline__ void stage_ids(const uint8_t* __restrict__ pid, int n, int i0, uint8_t* dst)
+{
+    constexpr int nc = tile_sites<R>() / 16;
+    const int64_t avail = (((int64_t)n + 15) & ~int64_t(15)) - i0;
+    const int lim = (int)min<int64_t>(avail / 16, (int64_t)nc);
+    stage_chunks(pid + i0, 0, lim, nc, (v4i*)dst);
+}
+
+template <typename R>
+__device__ __forceinline__ V3<R> wload3(const R* win, int byte_off)
+{
+    const R* p = (const R*)((const char*)win + byte_off);
+    return V3<R>{p[0], p[1], p[2]};
+}
+
+// sum_k J_k S[j_k] over the neighbours of site i (tile position l, window
+// base site wb): the near part from the window, the far part from global
+// memory, each in the row's order, then near + far.
+template <typename R>
+constexpr int kFarRegs = sizeof(R) == 4 ? SLLG_FAR_REGS_F32 : SLLG_FAR_REGS_F64;
+
 template <typename R>
 __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* __restrict__ S,
-                                              const Shared<R>& sh, int i)
+                                              const Shared<R>& sh, const TileLds<R>& tl, int i, int l,
+                                              int wb)
 {
-    V3<R> h{0, 0, 0};
+    constexpr int kSiteBytes = 3 * (int)sizeof(R);
+    V3<R> hn{0, 0, 0}, hf{0, 0, 0};
     if (r.flags & kStencil) {
-        const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, r.n * (int)(3 * sizeof(R)));
-        const int ib = i * (int)(3 * sizeof(R));
-        const int p = gload(r.pat_id, i);
-        const int b = sh.pat_start[p], e = sh.pat_start[p + 1];
+        const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, r.n * kSiteBytes);
+        const int ib = i * kSiteBytes;
+        const int wbyte = (i - wb) * kSiteBytes;
+        const int p = tl.pid[l];
+        const int b = sh.pat_start[p], f = sh.pat_far[p], e = sh.pat_start[p + 1];
+        // The first kFarRegs<R> far gathers are issued before the near part is
+        // summed from LDS, so their latency overlaps it.
+        int fo[kFarRegs<R>];
+        V3<R> fr[kFarRegs<R>];
+#pragma unroll
+        for (int q = 0; q < kFarRegs<R>; ++q)
+            fo[q] = sh.pat[min(f + q, kMaxPatternEntries - 1)].off;
+#pragma unroll
+        for (int q = 0; q < kFarRegs<R>; ++q) {
+            fr[q] = V3<R>{0, 0, 0};
+            if (f + q < e)
+                fr[q] = bload3(rs, ib + fo[q], R(0));
+        }
+        SLLG_UNROLL(SLLG_NEAR_UNROLL)
+        for (int k = b; k < f; ++k) {
+            const PatEntry<R> pe = sh.pat[k];
+            const V3<R> sj = wload3(tl.win, wbyte + pe.off);
+            hn.x += pe.J * sj.x;
+            hn.y += pe.J * sj.y;
+            hn.z += pe.J * sj.z;
+        }
+#pragma unroll
+        for (int q = 0; q < kFarRegs<R>; ++q) {
+            if (f + q < e) {
+                const R J = sh.pat[f + q].J;
+                hf.x += J * fr[q].x;
+                hf.y += J * fr[q].y;
+                hf.z += J * fr[q].z;
+            }
+        }
         SLLG_UNROLL(SLLG_GATHER_UNROLL)
-        for (int k = b; k < e; ++k) {
+        for (int k = f + kFarRegs<R>; k < e; ++k) {
             const PatEntry<R> pe = sh.pat[k];
             const V3<R> sj = bload3(rs, ib + pe.off, R(0));
-            h.x += pe.J * sj.x;
-            h.y += pe.J * sj.y;
-            h.z += pe.J * sj.z;
+            hf.x += pe.J * sj.x;
+            hf.y += pe.J * sj.y;
+            hf.z += pe.J * sj.z;
         }
-        return h;
-    }
-    const int64_t base = gload(r.slice_off, i >> 6) + (i & 63);
-    const int d = gload(r.deg, i);
+    } else {
+        const int64_t base = gload(r.slice_off, i >> 6) + (i & 63);
+        const int dw = gload(r.deg, i);
+        const int d = dw & 255, nn = dw >> 8;
 #pragma unroll 2
-    for (int k = 0; k < d; ++k) {
-        const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
-        const R J = sh.jt[e >> kColBits];
-        const V3<R> sj = load3(S, (int64_t)(e & kColMask));
-        h.x += J * sj.x;
-        h.y += J * sj.y;
-        h.z += J * sj.z;
+        for (int k = nn; k < d; ++k) {
+            const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
+            const R J = sh.jt[e >> kColBits];
+            const V3<R> sj = load3(S, (int64_t)(e & kColMask));
+            hf.x += J * sj.x;
+            hf.y += J * sj.y;
+            hf.z += J * sj.z;
+        }
+        SLLG_UNROLL(SLLG_NEAR_UNROLL)
+        for (int k = 0; k < nn; ++k) {
+            const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
+            const R J = sh.jt[e >> kColBits];
+            const V3<R> sj = wload3(tl.win, ((int)(e & kColMask) - wb) * kSiteBytes);
+            hn.x += J * sj.x;
+            hn.y += J * sj.y;
+            hn.z += J * sj.z;
+        }
     }
-    return h;
+    return V3<R>{hn.x + hf.x, hn.y + hf.y, hn.z + hf.z};
 }
 
 // Work distribution.  A launch has a fixed number of workgroups (about the
-// number that fit on the chip at once), each sweeping many 256-site tiles.
+// number that fit on the chip at once), each sweeping many tiles.
 // Workgroups are handed to the 8 XCDs round-robin.  Mode 0: plain
 // grid-stride.  Mode 1: the workgroups of XCD x share one contiguous range
 // of tiles (neighbouring sites meet in that XCD's L2), interleaved tile by
@@ -311,9 +430,9 @@ struct TileIter {
 };
 
 // ---------------------------------------------------------------------------
-// Reductions of m and E.  Every sum has a fixed order: sites of a tile (256,
-// by lane, row of 16 lanes, wavefront), tiles of a group (kGroupTiles, by
-// tile), groups (by group).  Which workgroup computes a sum never changes
+// Reductions of m and E, in FP64.  Every sum has a fixed order: sites of a
+// tile (the sites of each lane in turn, then by row of 16 lanes, wavefront),
+// tiles of a group (kGroupTiles, by tile), groups (by group).  Which workgroup computes a sum never changes
 // its order, so a step's record is the same bit for bit whatever the launch
 // shape, the chunking or the rest of the batch.
 // ---------------------------------------------------------------------------
@@ -363,21 +482,18 @@ __device__ __forceinline__ double lane_value(float v, int lane)
     return (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Wavefront total in double: rows summed in the value's own precision
-// (FP32 rows hold 16 single-precision site terms), rows added in FP64.
-template <typename T>
-__device__ __forceinline__ double wave_sum(T v)
+// Wavefront total: rows of 16 lanes, then the four rows.
+__device__ __forceinline__ double wave_sum(double v)
 {
     v = row_sum(v);
     return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
 }
 
-constexpr int kWaves = kBlockSites / 64;
+constexpr int kWaves = kBlockThreads / 64;
 
 // Block-wide sum of four values in a fixed order; result valid in thread 0.
 // Ends with a barrier so `red` can be reused at once.
-template <typename T>
-__device__ __forceinline__ void block_sum4(const T v[4], double out[4], double (*red)[kWaves])
+__device__ __forceinline__ void block_sum4(const double v[4], double out[4], double (*red)[kWaves])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -428,7 +544,7 @@ __device__ void final_reduce(const ReplicaDev<R>& r, int slot, double (*red)[kWa
 {
     const int n_groups = (r.blocks + kGroupTiles - 1) / kGroupTiles;
     double tot[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int q0 = 0; q0 < n_groups; q0 += kBlockSites) {
+    for (int q0 = 0; q0 < n_groups; q0 += kBlockThreads) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         const int q = q0 + (int)threadIdx.x;
         if (q < n_groups) {
@@ -495,11 +611,12 @@ __device__ __forceinline__ void thermal_field(const ReplicaDev<R>& r, const Mate
 // ---------------------------------------------------------------------------
 template <typename R, bool MEASURE>
 __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps,
-                                                         const WorkItem* __restrict__ work,
-                                                         const int* __restrict__ n_work, int k,
-                                                         int remap)
+                                          const WorkItem* __restrict__ work,
+                                          const int* __restrict__ n_work, int k, int remap)
 {
+    constexpr int T = tile_sites<R>();
     __shared__ Shared<R> sh;
+    __shared__ TileLds<R> tl;
     __shared__ double red[4][kWaves];
     const int W = *n_work;
     int staged = -1;
@@ -509,31 +626,38 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
         const int nsteps = r.nsteps;
         if (MEASURE ? (!(r.flags & kRecord) || (k == 0 && nsteps <= 0)) : (k >= nsteps))
             continue;   // uniform over the block
+        const bool recording = (r.flags & kRecord) != 0;
+        const bool partials = recording && (MEASURE || k >= 1);
+        const int par = (r.parity + (MEASURE ? (k == 0 ? nsteps : 0) : k)) & 1;
+        const R* __restrict__ S = r.S[par];
+        const int i0 = w.block * T, wb = i0 - r.halo;
+        __syncthreads();   // every lane is done with the previous tile's LDS
         if (w.replica != staged) {
-            __syncthreads();
             stage_tables(r, sh);
             staged = w.replica;
         }
-        const bool recording = (r.flags & kRecord) != 0;
-        const bool partials = recording && (MEASURE || k >= 1);
-        const int i = w.block * kBlockSites + (int)threadIdx.x;
-        const int par = (r.parity + (MEASURE ? (k == 0 ? nsteps : 0) : k)) & 1;
-        const R* __restrict__ S = r.S[par];
-        R v[4] = {0, 0, 0, 0};
-        if (i < r.n) {
+        stage_window(S, r.n, wb, T + 2 * r.halo, tl.win);
+        if (r.flags & kStencil)
+            stage_ids<R>(r.pat_id, r.n, i0, tl.pid);
+        __syncthreads();
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
+            const int i = i0 + l;
+            if (i >= r.n)
+                break;
             const MaterialDev<R>& m = site_material(r, i);
-            const V3<R> s = load3(S, i);
-            const V3<R> sum = exchange_sum(r, S, sh, i);
+            const V3<R> s = wload3(tl.win, (i - wb) * 3 * (int)sizeof(R));
+            const V3<R> sum = exchange_sum(r, S, sh, tl, i, l, wb);
             const V3<R> hex{m.mu_rel * sum.x, m.mu_rel * sum.y, m.mu_rel * sum.z};
             const V3<R> e = site_axis(r, m, i);
             const R se = dot(s, e);
             const V3<R> Happ{r.H[0], r.H[1], r.H[2]};
             if (partials) {
                 // in units of mu_ref: mu_s/mu_ref S and mu_s/mu_ref (-E_i/mu_s)
-                v[0] = m.mu_frac * s.x;
-                v[1] = m.mu_frac * s.y;
-                v[2] = m.mu_frac * s.z;
-                v[3] = m.mu_frac * ((R)0.5 * dot(s, hex) + m.ku_mu * se * se + dot(s, Happ));
+                v[0] += (double)(m.mu_frac * s.x);
+                v[1] += (double)(m.mu_frac * s.y);
+                v[2] += (double)(m.mu_frac * s.z);
+                v[3] += (double)(m.mu_frac * ((R)0.5 * dot(s, hex) + m.ku_mu * se * se + dot(s, Happ)));
             }
             if (!MEASURE) {
                 V3<R> h{hex.x + m.ani * se * e.x + Happ.x, hex.y + m.ani * se * e.y + Happ.y,
@@ -574,11 +698,12 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps,
-                                                         const WorkItem* __restrict__ work,
-                                                         const int* __restrict__ n_work, int k,
-                                                         int remap)
+                                          const WorkItem* __restrict__ work,
+                                          const int* __restrict__ n_work, int k, int remap)
 {
+    constexpr int T = tile_sites<R>();
     __shared__ Shared<R> sh;
+    __shared__ TileLds<R> tl;
     __shared__ double red[4][kWaves];
     const int W = *n_work;
     int staged = -1;
@@ -587,17 +712,26 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
         const ReplicaDev<R>& r = reps[w.replica];
         if (k >= r.nsteps)
             continue;
+        const R* __restrict__ Sp = r.Sp;
+        const int i0 = w.block * T, wb = i0 - r.halo;
+        __syncthreads();   // every lane is done with the previous tile's LDS
         if (w.replica != staged) {
-            __syncthreads();
             stage_tables(r, sh);
             staged = w.replica;
         }
-        const int i = w.block * kBlockSites + (int)threadIdx.x;
-        if (i < r.n) {
+        stage_window(Sp, r.n, wb, T + 2 * r.halo, tl.win);
+        if (r.flags & kStencil)
+            stage_ids<R>(r.pat_id, r.n, i0, tl.pid);
+        __syncthreads();
+        R* __restrict__ Sn = r.S[(r.parity + k + 1) & 1];
+        for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
+            const int i = i0 + l;
+            if (i >= r.n)
+                break;
             const MaterialDev<R>& m = site_material(r, i);
-            const V3<R> sp = load3((const R*)r.Sp, i);
+            const V3<R> sp = wload3(tl.win, (i - wb) * 3 * (int)sizeof(R));
             const V3<R> b = load3((const R*)r.Bc, i);
-            const V3<R> sum = exchange_sum(r, (const R*)r.Sp, sh, i);
+            const V3<R> sum = exchange_sum(r, Sp, sh, tl, i, l, wb);
             const V3<R> e = site_axis(r, m, i);
             const R se = dot(sp, e);
             V3<R> h{m.mu_rel * sum.x + m.ani * se * e.x + r.H[0],
@@ -606,7 +740,7 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
             thermal_field(r, m, k, i, h);
             const V3<R> ds = llg_step(sp, h, r.gdt, r.alpha);
             const V3<R> sn = normalised(V3<R>{b.x + (R)0.5 * ds.x, b.y + (R)0.5 * ds.y, b.z + (R)0.5 * ds.z});
-            store3(r.S[(r.parity + k + 1) & 1], i, sn);
+            store3(Sn, i, sn);
         }
         if ((r.flags & kRecord) && k >= 1 && (w.block % kGroupTiles) == 0)
             group_reduce(r, w.block / kGroupTiles, red);
@@ -617,7 +751,7 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
 // groups, then the total, by one workgroup per replica, in the same order
 // as the per-step path.
 template <typename R>
-__global__ __launch_bounds__(kBlockSites) void k_finish(const ReplicaDev<R>* __restrict__ reps, int mode)
+__global__ __launch_bounds__(kBlockThreads) void k_finish(const ReplicaDev<R>* __restrict__ reps, int mode)
 {
     __shared__ double red[4][kWaves];
     const ReplicaDev<R>& r = reps[blockIdx.x];
@@ -720,10 +854,10 @@ hipError_t launch_predict(const ReplicaDev<R>* reps, const WorkItem* work, const
     if (grid <= 0)
         return hipSuccess;
     if (measure)
-        hipLaunchKernelGGL((k_predict<R, true>), dim3(grid), dim3(kBlockSites), 0, st, reps, work,
+        hipLaunchKernelGGL((k_predict<R, true>), dim3(grid), dim3(kBlockThreads), 0, st, reps, work,
                            n_work, k, remap);
     else
-        hipLaunchKernelGGL((k_predict<R, false>), dim3(grid), dim3(kBlockSites), 0, st, reps, work,
+        hipLaunchKernelGGL((k_predict<R, false>), dim3(grid), dim3(kBlockThreads), 0, st, reps, work,
                            n_work, k, remap);
     return hipGetLastError();
 }
@@ -734,7 +868,7 @@ hipError_t launch_correct(const ReplicaDev<R>* reps, const WorkItem* work, const
 {
     if (grid <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(kBlockSites), 0, st, reps, work, n_work, k,
+    hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(kBlockThreads), 0, st, reps, work, n_work, k,
                        remap);
     return hipGetLastError();
 }
@@ -744,7 +878,7 @@ hipError_t launch_finish(const ReplicaDev<R>* reps, int n_rep, int mode, hipStre
 {
     if (n_rep <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((k_finish<R>), dim3(n_rep), dim3(kBlockSites), 0, st, reps, mode);
+    hipLaunchKernelGGL((k_finish<R>), dim3(n_rep), dim3(kBlockThreads), 0, st, reps, mode);
     return hipGetLastError();
 }
 
@@ -772,9 +906,9 @@ int resident_blocks(int device)
     int cus = 0, a = 0, b = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)k_predict<R, false>, kBlockSites, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)k_predict<R, false>, kBlockThreads, 0) !=
             hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)k_correct<R>, kBlockSites, 0) != hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)k_correct<R>, kBlockThreads, 0) != hipSuccess)
         return 0;
     const int per_cu = a < b ? a : b;
     return cus * (per_cu > 0 ? per_cu : 1);

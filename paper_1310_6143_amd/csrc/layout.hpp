@@ -4,8 +4,9 @@
 // One "replica" is one independent spin system.  A single system created
 // through sllg_create is a batch of one replica; the server batches many.
 // Every replica owns its device buffers; the kernels find them through a
-// table of ReplicaDev records, and a table of work items maps each
-// workgroup to (replica, block of kBlockSites consecutive sites).
+// table of ReplicaDev records, and a table of work items maps each tile of
+// tile_sites<R>() consecutive sites of a replica to the workgroup that
+// sweeps it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,7 +15,36 @@
 
 namespace sllg {
 
-constexpr int kBlockSites = 256;      // sites per workgroup (one site per lane)
+// Step kernels: workgroups of kBlockThreads lanes sweep tiles of
+// tile_sites<R>() consecutive sites (tile_sites / kBlockThreads per lane).
+// A workgroup stages its tile's spins plus a halo of up to kHaloCap sites
+// on either side in LDS; neighbours within the halo are read from there,
+// the rest from global memory.
+#ifndef SLLG_TILE_SITES_F32
+#define SLLG_TILE_SITES_F32 1024
+#endif
+#ifndef SLLG_TILE_SITES_F64
+#define SLLG_TILE_SITES_F64 512
+#endif
+#ifndef SLLG_HALO_CAP
+#define SLLG_HALO_CAP 384
+#endif
+constexpr int kBlockThreads = 256;
+template <typename R>
+constexpr int tile_sites()
+{
+    return sizeof(R) == 4 ? SLLG_TILE_SITES_F32 : SLLG_TILE_SITES_F64;
+}
+constexpr int kHaloCap = SLLG_HALO_CAP;
+static_assert(SLLG_TILE_SITES_F32 % kBlockThreads == 0 && SLLG_TILE_SITES_F64 % kBlockThreads == 0,
+              "a tile is a whole number of sites per lane");
+static_assert(SLLG_HALO_CAP % 4 == 0, "the halo keeps 16-byte alignment of the staged window");
+// Spin buffers are padded to a multiple of 16 bytes so that a tile's
+// window is staged with whole 16-byte loads.
+__host__ __device__ inline size_t spin_buffer_bytes(int64_t n, size_t real_bytes)
+{
+    return (3 * (size_t)n * real_bytes + 15) & ~size_t(15);
+}
 constexpr int kGroupTiles = 256;      // tile partials summed together at the second level
 constexpr int kSlice = 64;            // rows per SELL slice = one wavefront
 constexpr int kMaxTypes = 16;         // interaction types per replica
@@ -55,10 +85,11 @@ struct ReplicaDev {
     R* Bc;                          // corrector base S + dS dt / 2 [3n]
     const uint32_t* nb;             // SELL-64 neighbour entries
     const int64_t* slice_off;       // [n_slices + 1] first entry of each slice
-    const uint8_t* deg;             // [n] neighbours per site
-    const uint8_t* pat_id;          // [n] stencil pattern of each site (kStencil)
+    const uint16_t* deg;            // [n] near << 8 | neighbours, per site (SELL)
+    const uint8_t* pat_id;          // [n padded to 16] stencil pattern of each site (kStencil)
     const int32_t* pat_tab;         // [pat_entries] packed offset << 4 | type
     const uint16_t* pat_start;      // [n_patterns + 1] first entry of each pattern
+    const uint16_t* pat_far;        // [n_patterns] first entry beyond the halo, per pattern
     const uint8_t* matid;           // [n] or null
     const R* axis;                  // [3n] or null
     const MaterialDev<R>* mat;      // materials
@@ -78,9 +109,9 @@ struct ReplicaDev {
     int64_t avg_first;              // first averaged step number (its post-step state)
     int64_t avg_block_len;          // samples per averaging block
     int32_t avg_blocks;             // number of averaging blocks
-    int32_t pad0;
+    int32_t halo;                   // window halo in sites (multiple of 4, <= kHaloCap)
     int32_t n;                      // sites
-    int32_t blocks;                 // ceil(n / kBlockSites)
+    int32_t blocks;                 // tiles: ceil(n / tile_sites)
     int32_t parity;                 // S[parity] holds the current state (advanced on the device)
     int32_t nsteps;                 // steps this replica takes in the current chunk
     int32_t flags;                  // ReplicaFlags
@@ -89,7 +120,7 @@ struct ReplicaDev {
 
 struct WorkItem {
     int32_t replica;
-    int32_t block;
+    int32_t block;                  // tile index within the replica
 };
 
 }  // namespace sllg

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <unordered_map>
 #include <utility>
@@ -13,7 +15,7 @@ void fail(sllg_status code, const std::string& msg) { throw Failure{code, msg}; 
 
 HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* col,
                               const uint8_t* ntype, const double* J, int n_types,
-                              bool check_symmetry, bool allow_stencil)
+                              bool check_symmetry, int halo_cap, bool allow_stencil)
 {
     if (n <= 0)
         fail(SLLG_E_ARG, "system has no spins");
@@ -67,17 +69,31 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
     s.nnz = nnz;
     s.n_types = n_types;
     s.J.assign(J, J + n_types);
-    const int64_t n_slices = (n + kSlice - 1) / kSlice;
-    s.slice_off.assign(n_slices + 1, 0);
-    s.deg.resize(n);
-    for (int64_t i = 0; i < n; ++i)
-        s.deg[i] = (uint8_t)(row_ptr[i + 1] - row_ptr[i]);
-    for (int64_t sl = 0; sl < n_slices; ++sl) {
-        int width = 0;
-        for (int64_t i = sl * kSlice; i < std::min<int64_t>(n, (sl + 1) * kSlice); ++i)
-            width = std::max<int>(width, s.deg[i]);
-        s.slice_off[sl + 1] = s.slice_off[sl] + (int64_t)kSlice * width;
+    if (halo_cap < 0 || halo_cap % 4 != 0)
+        fail(SLLG_E_ARG, "halo cap must be a non-negative multiple of 4");
+
+    // Row order of the device forms: near links first, then far ones.
+    auto near = [&](int64_t i, int64_t q) {
+        const int64_t off = (int64_t)col[q] - i;
+        return off >= -halo_cap && off <= halo_cap;
+    };
+    std::vector<int64_t> order((size_t)nnz);   // CSR positions, rows reordered
+    std::vector<uint8_t> n_near((size_t)n);
+    int64_t max_near = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t w = row_ptr[i];
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q)
+            if (near(i, q)) {
+                order[(size_t)w++] = q;
+                max_near = std::max<int64_t>(max_near, std::llabs((int64_t)col[q] - i));
+            }
+        n_near[(size_t)i] = (uint8_t)(w - row_ptr[i]);
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q)
+            if (!near(i, q))
+                order[(size_t)w++] = q;
     }
+    s.halo = (int)((max_near + 3) & ~int64_t(3));
+
     // Stencil form: the interaction list of a row, written relative to the
     // row, repeats across a crystal (the paper builds it from the unit
     // cell's neighbour template), so few patterns cover every row.
@@ -85,12 +101,14 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
         std::unordered_map<std::string, int> ids;
         std::vector<uint8_t> pid((size_t)n);
         std::vector<int32_t> tab;
-        std::vector<uint16_t> start{0};
+        std::vector<uint16_t> start{0}, far;
         std::string key;
         bool ok = allow_stencil;
         for (int64_t i = 0; i < n && ok; ++i) {
             key.clear();
-            for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+            key.push_back((char)n_near[(size_t)i]);
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                const int64_t q = order[(size_t)p];
                 const int64_t off = (int64_t)col[q] - i;
                 const int32_t t = ntype ? ntype[q] : 0;
                 if (off < -(int64_t(1) << 27) || off >= (int64_t(1) << 27) || n * 24 >= (int64_t(1) << 31)) {
@@ -105,14 +123,18 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
             auto it = ids.find(key);
             if (it == ids.end()) {
                 const int id = (int)ids.size();
-                const size_t entries = tab.size() + key.size() / sizeof(int32_t);
-                if (id >= kMaxPatterns || entries > (size_t)kMaxPatternEntries) {
+                const size_t cnt = (key.size() - 1) / sizeof(int32_t);
+                if (id >= kMaxPatterns || tab.size() + cnt > (size_t)kMaxPatternEntries) {
                     ok = false;
                     break;
                 }
                 it = ids.emplace(key, id).first;
-                const int32_t* e = reinterpret_cast<const int32_t*>(key.data());
-                tab.insert(tab.end(), e, e + key.size() / sizeof(int32_t));
+                far.push_back((uint16_t)(tab.size() + (uint8_t)key[0]));
+                for (size_t c = 0; c < cnt; ++c) {
+                    int32_t e;
+                    std::memcpy(&e, key.data() + 1 + c * sizeof(int32_t), sizeof(e));
+                    tab.push_back(e);
+                }
                 start.push_back((uint16_t)tab.size());
             }
             pid[(size_t)i] = (uint8_t)it->second;
@@ -122,18 +144,28 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
             s.pat_id = std::move(pid);
             s.pat_tab = std::move(tab);
             s.pat_start = std::move(start);
+            s.pat_far = std::move(far);
+            return s;
         }
     }
-    if (s.stencil) {
-        std::vector<int64_t>().swap(s.slice_off);
-        std::vector<uint8_t>().swap(s.deg);
-        return s;
+
+    const int64_t n_slices = (n + kSlice - 1) / kSlice;
+    s.slice_off.assign(n_slices + 1, 0);
+    s.deg.resize(n);
+    for (int64_t i = 0; i < n; ++i)
+        s.deg[i] = (uint16_t)(((uint32_t)n_near[(size_t)i] << 8) | (uint32_t)(row_ptr[i + 1] - row_ptr[i]));
+    for (int64_t sl = 0; sl < n_slices; ++sl) {
+        int width = 0;
+        for (int64_t i = sl * kSlice; i < std::min<int64_t>(n, (sl + 1) * kSlice); ++i)
+            width = std::max<int>(width, s.deg[i] & 255);
+        s.slice_off[sl + 1] = s.slice_off[sl] + (int64_t)kSlice * width;
     }
     s.nb.assign((size_t)s.slice_off[n_slices], 0u);
     for (int64_t i = 0; i < n; ++i) {
         const int64_t base = s.slice_off[i / kSlice] + (i % kSlice);
         int k = 0;
-        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q, ++k) {
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p, ++k) {
+            const int64_t q = order[(size_t)p];
             const uint32_t t = ntype ? ntype[q] : 0u;
             s.nb[(size_t)(base + (int64_t)k * kSlice)] = (t << kColBits) | (uint32_t)col[q];
         }
@@ -282,7 +314,8 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
     rec.seed = d.seed;
     rec.step = d.step;
     rec.n = (int32_t)s.n;
-    rec.blocks = (int32_t)((s.n + kBlockSites - 1) / kBlockSites);
+    rec.blocks = (int32_t)((s.n + tile_sites<R>() - 1) / tile_sites<R>());
+    rec.halo = s.halo;
     int32_t flags = rec.flags & (kRecord | kRecordSeries);
     if (m.per_site_material)
         flags |= kPerSiteMaterial;

@@ -23,27 +23,34 @@ struct Failure {
 // Boltzmann constant (J/K), Table 1 of the paper.
 constexpr double kBoltzmann = 1.3807e-23;
 
-// Neighbour structure in SELL-64 form.
+// Neighbour structure in stencil or SELL-64 form.  Every row lists its
+// near links (|col - row| <= halo_cap) first and the far ones after, each
+// part in the caller's order; the step kernels sum the two parts separately
+// (near ones from the LDS window), so both forms add the same terms in the
+// same order.
 struct HostStructure {
     int64_t n = 0;
     int64_t nnz = 0;
     int n_types = 0;
+    int halo = 0;                      // window halo: max near |col - row|, rounded up to 4
     std::vector<double> J;             // joules per link, per type
     std::vector<uint32_t> nb;          // packed entries, 64 rows per slice, column-major
     std::vector<int64_t> slice_off;    // [n_slices + 1]
-    std::vector<uint8_t> deg;          // [n]
+    std::vector<uint16_t> deg;         // [n] near << 8 | degree
     // stencil form, filled when every row matches one of few patterns
     bool stencil = false;
     std::vector<uint8_t> pat_id;       // [n]
     std::vector<int32_t> pat_tab;      // packed (col - row) << 4 | type
     std::vector<uint16_t> pat_start;   // [n_patterns + 1]
+    std::vector<uint16_t> pat_far;     // [n_patterns] first far entry of each pattern
 };
 
 // Validates and converts.  Throws Failure(SLLG_E_ARG) on malformed input.
 // allow_stencil = false keeps the SELL form even when patterns would fit.
+// halo_cap (a multiple of 4) bounds the offsets read from the LDS window.
 HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* col,
                               const uint8_t* ntype, const double* J, int n_types,
-                              bool check_symmetry, bool allow_stencil = true);
+                              bool check_symmetry, int halo_cap, bool allow_stencil = true);
 
 // Materials: distinct (mu_s, k_u) pairs, per-site ids when there is more
 // than one, per-site easy axes when they differ.

@@ -395,7 +395,8 @@ sllg_status sllg_submit(sllg_server* srv, const sllg_request* req, uint64_t* tic
         if (req->n_avg < 0 || req->n_avg > req->n_steps)
             fail(SLLG_E_ARG, "n_avg must be in 0 .. n_steps");
         j->n = req->n_spins;
-        j->st = build_structure(req->n_spins, req->row_ptr, req->col, req->ntype, req->J, req->n_types, true);
+        j->st = build_structure(req->n_spins, req->row_ptr, req->col, req->ntype, req->J, req->n_types, true,
+                                kHaloCap);
         j->mat = build_materials(req->n_spins, req->mu_s, req->k_u, req->easy_axis, req->per_site);
         j->dyn.alpha = req->alpha;
         j->dyn.gamma = req->gamma;
