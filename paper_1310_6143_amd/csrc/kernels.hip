@@ -29,14 +29,9 @@
 #include "kernels.hpp"
 #include "layout.hpp"
 
-// Build-time tuning of the step kernels: gather-loop unroll depth (4 was
-// fastest on MI355X among 2, 4, 8 and 16) and an optional waves-per-SIMD
-// target (none: forcing 8 waves was slower).
+// Build-time tuning of the step kernels: gather-loop unroll depth.
 #ifndef SLLG_GATHER_UNROLL
 #define SLLG_GATHER_UNROLL 4
-#endif
-#ifndef SLLG_WAVES_PER_EU
-#define SLLG_WAVES_PER_EU 0
 #endif
 // Near (LDS) gathers per unrolled step, and far gathers held in registers
 // while the near part is summed.
@@ -49,11 +44,16 @@
 #ifndef SLLG_FAR_REGS_F64
 #define SLLG_FAR_REGS_F64 6
 #endif
-#if SLLG_WAVES_PER_EU > 0
-#define SLLG_STEP_ATTRS __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(SLLG_WAVES_PER_EU)))
-#else
-#define SLLG_STEP_ATTRS __launch_bounds__(kBlockThreads)
+#ifndef SLLG_WAVES_F32
+#define SLLG_WAVES_F32 5
 #endif
+#ifndef SLLG_WAVES_F64
+#define SLLG_WAVES_F64 3
+#endif
+// Waves per SIMD the step kernels are compiled for: as many as their LDS
+// allows (register use is capped to match).
+#define SLLG_STEP_ATTRS \
+    __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? SLLG_WAVES_F32 : SLLG_WAVES_F64)))
 #define SLLG_PRAGMA(x) _Pragma(#x)
 #define SLLG_UNROLL(n) SLLG_PRAGMA(unroll n)
 
@@ -310,38 +310,48 @@ __device__ __forceinline__ V3<R> wload3(const R* win, int byte_off)
     return V3<R>{p[0], p[1], p[2]};
 }
 
-// sum_k J_k S[j_k] over the neighbours of site i (tile position l, window
-// base site wb): the near part from the window, the far part from global
-// memory, each in the row's order, then near + far.
 template <typename R>
 constexpr int kFarRegs = sizeof(R) == 4 ? SLLG_FAR_REGS_F32 : SLLG_FAR_REGS_F64;
+// A buffer offset at or past the end of any spin buffer the stencil form
+// allows (3 n sizeof(R) < 2^31).
+constexpr int kPastEnd = 0x7FFFFFF0;
 
+// x * 3 * sizeof(R) with shifts (a 32-bit integer multiply is quarter rate).
 template <typename R>
+__device__ __forceinline__ int site_bytes(int x)
+{
+    return sizeof(R) == 4 ? (x << 3) + (x << 2) : (x << 4) + (x << 3);
+}
+
+// sum_k J_k S[j_k] over the neighbours of site i (tile position l, window
+// base site wb): the near part from the window, the far part from global
+// memory, each in the row's order, then near + far.  `overlap` runs while
+// the far gathers are in flight.
+template <typename R, typename F>
 __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* __restrict__ S,
                                               const Shared<R>& sh, const TileLds<R>& tl, int i, int l,
-                                              int wb)
+                                              int wb, F&& overlap)
 {
-    constexpr int kSiteBytes = 3 * (int)sizeof(R);
     V3<R> hn{0, 0, 0}, hf{0, 0, 0};
     if (r.flags & kStencil) {
-        const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, r.n * kSiteBytes);
-        const int ib = i * kSiteBytes;
-        const int wbyte = (i - wb) * kSiteBytes;
+        const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, site_bytes<R>(r.n));
+        const int ib = site_bytes<R>(i);
+        const int wbyte = site_bytes<R>(i - wb);
         const int p = tl.pid[l];
         const int b = sh.pat_start[p], f = sh.pat_far[p], e = sh.pat_start[p + 1];
-        // The first kFarRegs<R> far gathers are issued before the near part is
-        // summed from LDS, so their latency overlaps it.
+        // The first kFarRegs far gathers are issued before anything else,
+        // unconditionally (a lane without that entry reads past the end of
+        // the buffer, which returns zero without a memory access), so the
+        // loads issued earlier can be waited for one by one.
         int fo[kFarRegs<R>];
         V3<R> fr[kFarRegs<R>];
 #pragma unroll
         for (int q = 0; q < kFarRegs<R>; ++q)
             fo[q] = sh.pat[min(f + q, kMaxPatternEntries - 1)].off;
 #pragma unroll
-        for (int q = 0; q < kFarRegs<R>; ++q) {
-            fr[q] = V3<R>{0, 0, 0};
-            if (f + q < e)
-                fr[q] = bload3(rs, ib + fo[q], R(0));
-        }
+        for (int q = 0; q < kFarRegs<R>; ++q)
+            fr[q] = bload3(rs, f + q < e ? ib + fo[q] : kPastEnd, R(0));
+        overlap();
         SLLG_UNROLL(SLLG_NEAR_UNROLL)
         for (int k = b; k < f; ++k) {
             const PatEntry<R> pe = sh.pat[k];
@@ -368,6 +378,7 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
             hf.z += pe.J * sj.z;
         }
     } else {
+        overlap();
         const int64_t base = gload(r.slice_off, i >> 6) + (i & 63);
         const int dw = gload(r.deg, i);
         const int d = dw & 255, nn = dw >> 8;
@@ -384,7 +395,7 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
         for (int k = 0; k < nn; ++k) {
             const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
             const R J = sh.jt[e >> kColBits];
-            const V3<R> sj = wload3(tl.win, ((int)(e & kColMask) - wb) * kSiteBytes);
+            const V3<R> sj = wload3(tl.win, site_bytes<R>((int)(e & kColMask) - wb));
             hn.x += J * sj.x;
             hn.y += J * sj.y;
             hn.z += J * sj.z;
@@ -583,13 +594,11 @@ __device__ __forceinline__ V3<R> site_axis(const ReplicaDev<R>& r, const Materia
     return V3<R>{m.axis[0], m.axis[1], m.axis[2]};
 }
 
+// Adds the thermal field sigma * g (normals g drawn for this site and step).
 template <typename R>
-__device__ __forceinline__ void thermal_field(const ReplicaDev<R>& r, const MaterialDev<R>& m, int k, int i,
-                                              V3<R>& h)
+__device__ __forceinline__ void add_thermal(const MaterialDev<R>& m, const R g[3], V3<R>& h)
 {
     if (m.sigma != (R)0) {
-        R g[3];
-        thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
         h.x += m.sigma * g[0];
         h.y += m.sigma * g[1];
         h.z += m.sigma * g[2];
@@ -645,9 +654,13 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
             const int i = i0 + l;
             if (i >= r.n)
                 break;
-            const MaterialDev<R>& m = site_material(r, i);
-            const V3<R> s = wload3(tl.win, (i - wb) * 3 * (int)sizeof(R));
-            const V3<R> sum = exchange_sum(r, S, sh, tl, i, l, wb);
+            const MaterialDev<R> m = site_material(r, i);   // loaded before the gathers are issued
+            const V3<R> s = wload3(tl.win, site_bytes<R>(i - wb));
+            R g[3] = {0, 0, 0};
+            const V3<R> sum = exchange_sum(r, S, sh, tl, i, l, wb, [&] {
+                if (!MEASURE && m.sigma != (R)0)
+                    thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
+            });
             const V3<R> hex{m.mu_rel * sum.x, m.mu_rel * sum.y, m.mu_rel * sum.z};
             const V3<R> e = site_axis(r, m, i);
             const R se = dot(s, e);
@@ -662,7 +675,7 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
             if (!MEASURE) {
                 V3<R> h{hex.x + m.ani * se * e.x + Happ.x, hex.y + m.ani * se * e.y + Happ.y,
                         hex.z + m.ani * se * e.z + Happ.z};
-                thermal_field(r, m, k, i, h);
+                add_thermal(m, g, h);
                 const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
                 const V3<R> sp = normalised(V3<R>{s.x + ds.x, s.y + ds.y, s.z + ds.z});
                 store3(r.Sp, i, sp);
@@ -728,16 +741,20 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
             const int i = i0 + l;
             if (i >= r.n)
                 break;
-            const MaterialDev<R>& m = site_material(r, i);
-            const V3<R> sp = wload3(tl.win, (i - wb) * 3 * (int)sizeof(R));
+            const MaterialDev<R> m = site_material(r, i);   // loaded before the gathers are issued
+            const V3<R> sp = wload3(tl.win, site_bytes<R>(i - wb));
             const V3<R> b = load3((const R*)r.Bc, i);
-            const V3<R> sum = exchange_sum(r, Sp, sh, tl, i, l, wb);
+            R g[3] = {0, 0, 0};
+            const V3<R> sum = exchange_sum(r, Sp, sh, tl, i, l, wb, [&] {
+                if (m.sigma != (R)0)
+                    thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
+            });
             const V3<R> e = site_axis(r, m, i);
             const R se = dot(sp, e);
             V3<R> h{m.mu_rel * sum.x + m.ani * se * e.x + r.H[0],
                     m.mu_rel * sum.y + m.ani * se * e.y + r.H[1],
                     m.mu_rel * sum.z + m.ani * se * e.z + r.H[2]};
-            thermal_field(r, m, k, i, h);
+            add_thermal(m, g, h);
             const V3<R> ds = llg_step(sp, h, r.gdt, r.alpha);
             const V3<R> sn = normalised(V3<R>{b.x + (R)0.5 * ds.x, b.y + (R)0.5 * ds.y, b.z + (R)0.5 * ds.z});
             store3(Sn, i, sn);
