@@ -72,9 +72,11 @@ def run_gpu(w, precision, steps, warmup, torch, launch=None):
     if launch:
         sysm.set_option("xcd_remap", launch[0])
         sysm.set_option("grid_scale_pct", launch[1])
-        choice = {"xcd_remap": launch[0], "grid_scale_pct": launch[1], "graph_steps": sysm.get_option("graph_steps")}
+        if len(launch) > 2:
+            sysm.set_option("tile_order", launch[2])
+        choice = {k: sysm.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps", "tile_order")}
     else:
-        tuned_us, choice = sysm.autotune(10, stream=st)
+        tuned_us, choice = sysm.autotune(25, stream=st)
         log(f"  autotune: {tuned_us:.1f} us/step with {choice}")
     m_w = torch.empty((max(warmup, 1), 3), dtype=torch.float64, device="cuda")
     E_w = torch.empty(max(warmup, 1), dtype=torch.float64, device="cuda")
@@ -246,7 +248,7 @@ def main():
                     help="block: 8.19M-spin bcc step throughput (default); film: full M(T) ramp; "
                          "sphere: full hysteresis sweep")
     ap.add_argument("--sweep-points", type=int, default=0, help="limit the sweep to its first points")
-    ap.add_argument("--launch", default="", help="fixed launch shape 'tile_order,grid_scale_pct' "
+    ap.add_argument("--launch", default="", help="fixed launch shape 'xcd_remap,grid_scale_pct[,tile_order]' "
                     "instead of autotuning (for profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy of this many MiB (for counter calibration)")

@@ -204,6 +204,13 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     grid-stride order
  *   "grid_scale_pct"  workgroups per step launch, in % of the resident grid
  *                     (10..800, default 100)
+ *   "tile_order"      1 (default): when the stencil's far links point about
+ *                     one lattice plane away, list the tiles as groups of
+ *                     "tile_group" adjacent columns swept plane by plane (a
+ *                     tile's far neighbours were read a few tiles earlier
+ *                     and are still cached); 0 site order
+ *   "tile_group"      tile columns per group for tile_order 1 (1..4096;
+ *                     0, the default, sizes the groups from the L2 capacity)
  *   "stencil"         1 (default) / 0: let the next sllg_set_neighbours store
  *                     the list as per-site stencil patterns when at most 256
  *                     distinct (column - row, type) rows occur (<= 1024

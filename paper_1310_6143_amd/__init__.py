@@ -269,7 +269,8 @@ class SpinSystem:
         returns (us per step, chosen options)."""
         us = D()
         self._check(lib().sllg_autotune(self._h, int(trial_steps), ctypes.byref(us), _stream(stream)))
-        return us.value, {k: self.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps")}
+        return us.value, {k: self.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps",
+                                                          "tile_order")}
 
     def measure(self):
         m = np.empty(3)

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -149,6 +150,61 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
     return b;
 }
 
+// Plane stride of a stencil lattice in tiles: the median over sites of
+// |column - row| of the far links (those beyond the LDS halo), divided by
+// the tile size; 0 when there are none or they are within two tiles.
+inline int plane_tiles(const HostStructure& s, int tile)
+{
+    if (!s.stencil)
+        return 0;
+    const int np = (int)s.pat_start.size() - 1;
+    std::vector<int64_t> uses(np, 0);
+    for (uint8_t p : s.pat_id)
+        ++uses[p];
+    std::vector<std::pair<int64_t, int64_t>> far;   // (|offset|, sites)
+    int64_t total = 0;
+    for (int p = 0; p < np; ++p)
+        for (int k = s.pat_far[p]; k < s.pat_start[p + 1]; ++k) {
+            far.emplace_back(std::llabs((int64_t)(s.pat_tab[k] >> 4)), uses[p]);
+            total += uses[p];
+        }
+    if (total == 0)
+        return 0;
+    std::sort(far.begin(), far.end());
+    int64_t acc = 0, median = 0;
+    for (const auto& f : far)
+        if ((acc += f.second) * 2 >= total) {
+            median = f.first;
+            break;
+        }
+    const int64_t pt = (median + tile / 2) / tile;
+    return pt >= 2 && pt < (int64_t(1) << 30) ? (int)pt : 0;
+}
+
+// Order in which a replica's tiles are listed for the step launches.  With
+// a plane stride of pt tiles, groups of `group` adjacent tile columns are
+// swept plane after plane, so a tile's far neighbours (one plane away) were
+// read a few tiles earlier and are still in the L2.
+inline std::vector<int32_t> tile_order(int blocks, int pt, int group)
+{
+    std::vector<int32_t> o;
+    o.reserve((size_t)blocks);
+    if (pt < 2 || group <= 0 || pt >= blocks) {
+        for (int b = 0; b < blocks; ++b)
+            o.push_back(b);
+        return o;
+    }
+    const int64_t nz = ((int64_t)blocks + pt - 1) / pt;
+    for (int c0 = 0; c0 < pt; c0 += group)
+        for (int64_t z = 0; z < nz; ++z)
+            for (int c = c0; c < std::min(c0 + group, pt); ++c) {
+                const int64_t t = z * pt + c;
+                if (t < blocks)
+                    o.push_back((int32_t)t);
+            }
+    return o;
+}
+
 template <typename R>
 class Batch {
 public:
@@ -159,6 +215,7 @@ public:
         int64_t rec_cap = 0;
         int avg_cap = 0;
         size_t bytes = 0;
+        int plane_tiles = 0;     // see plane_tiles()
     };
 
     Batch(int device, Allocator* alloc, int max_replicas)
@@ -170,6 +227,14 @@ public:
         hip_check(hipMemset(d_nwork_, 0, sizeof(int)), "hipMemset");
         host_reps_.resize(max_replicas);
         resident_ = resident_blocks<R>(device_);
+        // A group's tiles stream about 9 sizeof(R) bytes per site through the
+        // L2 per launch (S read, S' and Bc written, then read back); the
+        // plane-to-plane reuse spans two planes of a group, kept within a
+        // quarter of one L2 (the L2 of one XCD on MI355X).
+        int l2 = 0;
+        if (hipDeviceGetAttribute(&l2, hipDeviceAttributeL2CacheSize, device_) != hipSuccess || l2 <= 0)
+            l2 = 4 << 20;
+        auto_group_ = std::max(1, (int)((int64_t)l2 / (4 * 9 * (int64_t)sizeof(R) * tile_sites<R>())));
         if (resident_ < 8)
             resident_ = 8 * 256;
         resident_ &= ~7;
@@ -308,6 +373,7 @@ public:
             r.avg_blocks = 0;
             set_spins(q, S0);
             sl.bytes = replica_bytes(s, m, sizeof(R), sl.rec_cap, sl.avg_cap);
+            sl.plane_tiles = plane_tiles(s, tile_sites<R>());
             sl.used = true;
         } catch (...) {
             for (void* p : sl.mem)
@@ -389,7 +455,8 @@ public:
             if (!slots_[q].used)
                 host_reps_[q].nsteps = 0;
             if (slots_[q].used && slots_[q].rec.nsteps > 0)
-                for (int b = 0; b < slots_[q].rec.blocks; ++b)
+                for (int32_t b : tile_order(slots_[q].rec.blocks, order_ ? slots_[q].plane_tiles : 0,
+                                            group_ > 0 ? group_ : balanced_group(slots_[q].plane_tiles)))
                     work_.push_back(WorkItem{(int32_t)q, b});
         }
         const int nwork = (int)work_.size();
@@ -501,6 +568,17 @@ public:
         remap_ = v;
     }
     int remap() const { return remap_; }
+    // Tile listing: 0 in site order, 1 plane-swept column groups of
+    // `group` tiles (lattices with a detected plane stride); group 0 sizes
+    // the groups from the L2 capacity.
+    void set_tile_order(int order, int group)
+    {
+        if (order != order_ || group != group_) {
+            order_ = order;
+            group_ = group;
+            dirty_ = true;
+        }
+    }
     void set_round_grid(bool v) { round_grid_ = v; }
     // Workgroups per launch as a multiple of the resident grid (the tiles are
     // swept by that many workgroups; more than resident lets the hardware
@@ -572,6 +650,18 @@ private:
     int resident_ = 0;
     double grid_scale_ = 1.0;
     int remap_ = 1;
+    // At most auto_group_ columns per group, the plane's columns split evenly.
+    int balanced_group(int pt) const
+    {
+        if (pt <= auto_group_)
+            return std::max(pt, 1);
+        const int groups = (pt + auto_group_ - 1) / auto_group_;
+        return (pt + groups - 1) / groups;
+    }
+
+    int order_ = 1;
+    int group_ = 0;
+    int auto_group_ = 8;
     bool round_grid_ = false;
     bool dirty_ = true;
     hipGraphExec_t graph_exec_ = nullptr;

@@ -55,7 +55,10 @@ constexpr int kMaxDegree = 255;
 // pattern; a site stores only its pattern id (uint8).  Pattern entries pack
 // (column - row) << 4 | type in an int32 (offsets within +-2^27).
 constexpr int kMaxPatterns = 256;
-constexpr int kMaxPatternEntries = 1024;   // all patterns' entries, staged in LDS
+#ifndef SLLG_MAX_PATTERN_ENTRIES
+#define SLLG_MAX_PATTERN_ENTRIES 1024
+#endif
+constexpr int kMaxPatternEntries = SLLG_MAX_PATTERN_ENTRIES;   // all patterns' entries, staged in LDS
 
 // Per-material constants, pre-scaled to field units (tesla).
 template <typename R>

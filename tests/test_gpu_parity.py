@@ -112,8 +112,9 @@ def test_bcc_j1j2_32cubed_fp64():
                                   lambda: bcc_film(nx=8, ny=6, nz=4, seed=3),
                                   lambda: bcc_block(cells=10, n_steps=100)])
 def test_stencil_and_sell_layouts_agree_bitwise(make):
-    """Both neighbour layouts keep the CSR order of each row, so the exchange
-    sums, and hence whole trajectories, are identical bit for bit."""
+    """Both neighbour layouts list a row's near links (read from the LDS
+    window) before its far ones, each part in CSR order, and add the two
+    partial sums the same way, so trajectories are identical bit for bit."""
     w = make()
     w.temperature = 300.0
     for prec in (sl.FP32, sl.FP64):
@@ -166,6 +167,24 @@ def test_xcd_remap_does_not_change_results():
         assert np.array_equal(res[0][0], other[0])
         assert np.array_equal(res[0][1], other[1])
         assert np.array_equal(res[0][2], other[2])
+
+
+def test_tile_order_does_not_change_results():
+    """Plane-swept tile lists (any group width) only reorder the work: every
+    tile's sums and the reduction tree are fixed by the tile index."""
+    w = bcc_block(cells=32, n_steps=100)
+    for prec in (sl.FP32, sl.FP64):
+        res = []
+        for order, group in ((0, 0), (1, 0), (1, 1), (1, 3)):
+            with sl.from_workload(w, precision=prec, check_symmetry=False) as g:
+                g.set_option("tile_order", order)
+                g.set_option("tile_group", group)
+                m, E = g.integrate(60)
+                res.append((g.get_spins(), m, E))
+        for other in res[1:]:
+            assert np.array_equal(res[0][0], other[0])
+            assert np.array_equal(res[0][1], other[1])
+            assert np.array_equal(res[0][2], other[2])
 
 
 @pytest.mark.parametrize("L", [12, 64])
