@@ -394,6 +394,8 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
     double best = 1e30;
     Cand best_c = {(int)s->opt_xcd_remap, s->opt_grid_scale_pct, graph_steps(s), s->opt_tile_order};
     const int32_t flags0 = *r.flags;
+    const char* log_env = std::getenv("SLLG_AUTOTUNE_LOG");   // print every candidate's time
+    const bool log = log_env && *log_env && *log_env != '0';
     try {
         hip_check(hipEventCreate(&a), "hipEventCreate");
         hip_check(hipEventCreate(&b), "hipEventCreate");
@@ -421,6 +423,9 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
                 hip_check(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
                 us = std::min(us, 1e3 * ms / steps);
             }
+            if (log)
+                std::fprintf(stderr, "[sllg autotune] xcd_remap %d grid %lld%% graph %lld tile_order %lld: %.1f us/step\n",
+                             c.remap, (long long)c.scale_pct, (long long)c.graph, (long long)c.order, us);
             if (us < best) {
                 best = us;
                 best_c = c;

@@ -258,11 +258,19 @@ struct PatEntry<double> {
 };
 
 template <typename R>
+constexpr int kFarRegs = sizeof(R) == 4 ? SLLG_FAR_REGS_F32 : SLLG_FAR_REGS_F64;
+// A buffer offset at or past the end of any spin buffer the stencil form
+// allows (3 n sizeof(R) <= 0x7FFFF000, checked on the host).
+constexpr int kPastEnd = 0x7FFFFF00;
+
+// The entry table carries kFarRegs zero entries past its end, so the
+// register-held far gathers of the last pattern read inside the table.
+template <typename R>
 struct Shared {
     R jt[kMaxTypes];
     uint16_t pat_start[kMaxPatterns + 1];
     uint16_t pat_far[kMaxPatterns];
-    PatEntry<R> pat[kMaxPatternEntries];
+    PatEntry<R> pat[kMaxPatternEntries + kFarRegs<R>];
 };
 
 // The tile being integrated: spins of sites [i0 - halo, i0 + tile + halo)
@@ -287,10 +295,10 @@ __device__ __forceinline__ void stage_tables(const ReplicaDev<R>& r, Shared<R>& 
         for (int q = threadIdx.x; q < np; q += kBlockThreads)
             sh.pat_far[q] = gload(r.pat_far, q);
         const int ne = gload(r.pat_start, np);
-        for (int q = threadIdx.x; q < ne; q += kBlockThreads) {
-            const int32_t raw = gload(r.pat_tab, q);
+        for (int q = threadIdx.x; q < ne + kFarRegs<R>; q += kBlockThreads) {
+            const int32_t raw = q < ne ? gload(r.pat_tab, q) : 0;
             sh.pat[q].off = (raw >> 4) * (int)(3 * sizeof(R));
-            sh.pat[q].J = r.jt[raw & 15];
+            sh.pat[q].J = q < ne ? r.jt[raw & 15] : (R)0;
         }
     }
 }
@@ -340,17 +348,13 @@ __device__ __forceinline__ V3<R> wload3(const R* win, int byte_off)
     return V3<R>{p[0], p[1], p[2]};
 }
 
-template <typename R>
-constexpr int kFarRegs = sizeof(R) == 4 ? SLLG_FAR_REGS_F32 : SLLG_FAR_REGS_F64;
-// A buffer offset at or past the end of any spin buffer the stencil form
-// allows (3 n sizeof(R) < 2^31).
-constexpr int kPastEnd = 0x7FFFFFF0;
 
-// x * 3 * sizeof(R) with shifts (a 32-bit integer multiply is quarter rate).
+// x * 3 * sizeof(R) for 0 <= x < 2^24 (a 24-bit multiply is full rate, a
+// 32-bit one quarter rate).
 template <typename R>
 __device__ __forceinline__ int site_bytes(int x)
 {
-    return sizeof(R) == 4 ? (x << 3) + (x << 2) : (x << 4) + (x << 3);
+    return (int)__umul24((unsigned)x, 3u * (unsigned)sizeof(R));
 }
 
 // sum_k J_k S[j_k] over the neighbours of site i (tile position l, window
@@ -360,27 +364,27 @@ __device__ __forceinline__ int site_bytes(int x)
 template <typename R, typename F>
 __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* __restrict__ S,
                                               const Shared<R>& sh, const TileLds<R>& tl, int i, int l,
-                                              int wb, F&& overlap)
+                                              int wb, int wbyte, F&& overlap)
 {
     V3<R> hn{0, 0, 0}, hf{0, 0, 0};
     if (r.flags & kStencil) {
-        const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, site_bytes<R>(r.n));
-        const int ib = site_bytes<R>(i);
-        const int wbyte = site_bytes<R>(i - wb);
+        // byte offsets fit in 31 bits in the stencil form
+        const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, r.n * (int)(3 * sizeof(R)));
+        const int ib = (i - l) * (int)(3 * sizeof(R)) + site_bytes<R>(l);
         const int p = tl.pid[l];
         const int b = sh.pat_start[p], f = sh.pat_far[p], e = sh.pat_start[p + 1];
         // The first kFarRegs far gathers are issued before anything else,
         // unconditionally (a lane without that entry reads past the end of
         // the buffer, which returns zero without a memory access), so the
         // loads issued earlier can be waited for one by one.
-        int fo[kFarRegs<R>];
+        const int nf = e - f;
+        const PatEntry<R>* fp = sh.pat + f;
         V3<R> fr[kFarRegs<R>];
 #pragma unroll
-        for (int q = 0; q < kFarRegs<R>; ++q)
-            fo[q] = sh.pat[min(f + q, kMaxPatternEntries - 1)].off;
-#pragma unroll
-        for (int q = 0; q < kFarRegs<R>; ++q)
-            fr[q] = bload3(rs, f + q < e ? ib + fo[q] : kPastEnd, R(0));
+        for (int q = 0; q < kFarRegs<R>; ++q) {
+            const int keep = -(int)(q < nf);   // all ones when the entry exists
+            fr[q] = bload3(rs, ((ib + fp[q].off) & keep) | (kPastEnd & ~keep), R(0));
+        }
         overlap();
         SLLG_UNROLL(SLLG_NEAR_UNROLL)
         for (int k = b; k < f; ++k) {
@@ -390,14 +394,14 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
             hn.y += pe.J * sj.y;
             hn.z += pe.J * sj.z;
         }
+        // An absent entry contributes J * 0 = 0 (J is finite): the sum keeps
+        // its value.
 #pragma unroll
         for (int q = 0; q < kFarRegs<R>; ++q) {
-            if (f + q < e) {
-                const R J = sh.pat[f + q].J;
-                hf.x += J * fr[q].x;
-                hf.y += J * fr[q].y;
-                hf.z += J * fr[q].z;
-            }
+            const R J = fp[q].J;
+            hf.x += J * fr[q].x;
+            hf.y += J * fr[q].y;
+            hf.z += J * fr[q].z;
         }
         SLLG_UNROLL(SLLG_GATHER_UNROLL)
         for (int k = f + kFarRegs<R>; k < e; ++k) {
@@ -611,9 +615,21 @@ __device__ void final_reduce(const ReplicaDev<R>& r, int slot, double (*red)[kWa
 }
 
 template <typename R>
-__device__ __forceinline__ const MaterialDev<R>& site_material(const ReplicaDev<R>& r, int i)
+__device__ __forceinline__ MaterialDev<R> site_material(const ReplicaDev<R>& r, int i)
 {
-    return (r.flags & kPerSiteMaterial) ? r.mat[gload(r.matid, i)] : r.mat[0];
+    const int q = (r.flags & kPerSiteMaterial) ? gload(r.matid, i) : 0;
+    const SLLG_GLOBAL MaterialDev<R>& g = ((const SLLG_GLOBAL MaterialDev<R>*)r.mat)[q];
+    MaterialDev<R> m;
+    m.mu_rel = g.mu_rel;
+    m.mu_frac = g.mu_frac;
+    m.ani = g.ani;
+    m.ku_mu = g.ku_mu;
+    m.sigma = g.sigma;
+    m.axis[0] = g.axis[0];
+    m.axis[1] = g.axis[1];
+    m.axis[2] = g.axis[2];
+    m.mu_s = g.mu_s;
+    return m;
 }
 
 template <typename R>
@@ -685,9 +701,10 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
             if (i >= r.n)
                 break;
             const MaterialDev<R> m = site_material(r, i);   // loaded before the gathers are issued
-            const V3<R> s = wload3(tl.win, site_bytes<R>(i - wb));
+            const int wbyte = site_bytes<R>(l + r.halo);
+            const V3<R> s = wload3(tl.win, wbyte);
             R g[3] = {0, 0, 0};
-            const V3<R> sum = exchange_sum(r, S, sh, tl, i, l, wb, [&] {
+            const V3<R> sum = exchange_sum(r, S, sh, tl, i, l, wb, wbyte, [&] {
                 if (!MEASURE && m.sigma != (R)0)
                     thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
             });
@@ -772,10 +789,11 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
             if (i >= r.n)
                 break;
             const MaterialDev<R> m = site_material(r, i);   // loaded before the gathers are issued
-            const V3<R> sp = wload3(tl.win, site_bytes<R>(i - wb));
+            const int wbyte = site_bytes<R>(l + r.halo);
+            const V3<R> sp = wload3(tl.win, wbyte);
             const V3<R> b = load3_once((const R*)r.Bc, i);
             R g[3] = {0, 0, 0};
-            const V3<R> sum = exchange_sum(r, Sp, sh, tl, i, l, wb, [&] {
+            const V3<R> sum = exchange_sum(r, Sp, sh, tl, i, l, wb, wbyte, [&] {
                 if (m.sigma != (R)0)
                     thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
             });

@@ -111,7 +111,7 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
                 const int64_t q = order[(size_t)p];
                 const int64_t off = (int64_t)col[q] - i;
                 const int32_t t = ntype ? ntype[q] : 0;
-                if (off < -(int64_t(1) << 27) || off >= (int64_t(1) << 27) || n * 24 >= (int64_t(1) << 31)) {
+                if (off < -(int64_t(1) << 27) || off >= (int64_t(1) << 27) || n * 24 > 0x7FFFF000) {
                     ok = false;
                     break;
                 }
