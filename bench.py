@@ -62,7 +62,7 @@ def measured_traffic(precision):
     return float(v.group(1))
 
 
-def run_gpu(w, precision, steps, warmup, torch, launch=None):
+def run_gpu(w, precision, steps, warmup, torch, launch=None, autotune=False):
     import paper_1310_6143_amd as sl
 
     t0 = time.time()
@@ -75,9 +75,11 @@ def run_gpu(w, precision, steps, warmup, torch, launch=None):
         if len(launch) > 2:
             sysm.set_option("tile_order", launch[2])
         choice = {k: sysm.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps", "tile_order")}
-    else:
+    elif autotune:
         tuned_us, choice = sysm.autotune(25, stream=st)
         log(f"  autotune: {tuned_us:.1f} us/step with {choice}")
+    else:   # the library's default launch shape (the one the counter summary was taken at)
+        choice = {k: sysm.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps", "tile_order")}
     m_w = torch.empty((max(warmup, 1), 3), dtype=torch.float64, device="cuda")
     E_w = torch.empty(max(warmup, 1), dtype=torch.float64, device="cuda")
     m_dev = torch.empty((steps, 3), dtype=torch.float64, device="cuda")
@@ -249,7 +251,9 @@ def main():
                          "sphere: full hysteresis sweep")
     ap.add_argument("--sweep-points", type=int, default=0, help="limit the sweep to its first points")
     ap.add_argument("--launch", default="", help="fixed launch shape 'xcd_remap,grid_scale_pct[,tile_order]' "
-                    "instead of autotuning (for profiling runs)")
+                    "instead of the library default")
+    ap.add_argument("--autotune", action="store_true", help="time the candidate launch shapes first "
+                    "and run the fastest (sllg_autotune)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy of this many MiB (for counter calibration)")
     args = ap.parse_args()
@@ -294,11 +298,11 @@ def main():
 
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     if args.only_fp64:
-        r64 = run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch)
+        r64 = run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch, args.autotune)
         print(json.dumps({"fp64_ms_per_step": r64["ms"] / args.steps}))
         return
-    r32 = run_gpu(w, sl.FP32, args.steps, args.warmup, torch, launch)
-    r64 = None if args.no_fp64 else run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch)
+    r32 = run_gpu(w, sl.FP32, args.steps, args.warmup, torch, launch, args.autotune)
+    r64 = None if args.no_fp64 else run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch, args.autotune)
 
     n = w.n
     ms_step = r32["ms"] / args.steps

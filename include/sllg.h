@@ -216,8 +216,8 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     distinct (column - row, type) rows occur (<= 1024
  *                     entries in all); 0 keeps the general SELL-64 form
  * sllg_get_option also reads "neighbour_format": 1 stencil, 0 SELL, -1 unset;
- * "tile_sites": consecutive sites one workgroup integrates together (1024 in
- * FP32, 512 in FP64); "halo": neighbours with |column - row| up to this many
+ * "tile_sites": consecutive sites one workgroup integrates together (2048 in
+ * FP32, 1024 in FP64); "halo": neighbours with |column - row| up to this many
  * sites are read from the tile's window in LDS, the rest from HBM (-1 unset).
  */
 sllg_status sllg_set_option(sllg_system *sys, const char *key, int64_t value);

@@ -226,7 +226,14 @@ public:
         hip_check(hipMalloc(&d_nwork_, sizeof(int)), "hipMalloc(nwork)");
         hip_check(hipMemset(d_nwork_, 0, sizeof(int)), "hipMemset");
         host_reps_.resize(max_replicas);
-        resident_ = resident_blocks<R>(device_);
+        for (int ps = 0; ps < 2; ++ps) {
+            int& res = resident_pair_[ps];
+            res = resident_blocks<R>(device_, ps != 0);
+            if (res < 8)
+                res = 8 * 256;
+            res &= ~7;
+        }
+        resident_ = resident_pair_[0];
         // A group's tiles stream about 9 sizeof(R) bytes per site through the
         // L2 per launch (S read, S' and Bc written, then read back); the
         // plane-to-plane reuse spans two planes of a group, kept within a
@@ -235,9 +242,6 @@ public:
         if (hipDeviceGetAttribute(&l2, hipDeviceAttributeL2CacheSize, device_) != hipSuccess || l2 <= 0)
             l2 = 4 << 20;
         auto_group_ = std::max(1, (int)((int64_t)l2 / (4 * 9 * (int64_t)sizeof(R) * tile_sites<R>())));
-        if (resident_ < 8)
-            resident_ = 8 * 256;
-        resident_ &= ~7;
     }
 
     ~Batch()
@@ -449,6 +453,14 @@ public:
                 ((r.flags & kAverage) && (!(r.flags & kRecord) || !r.acc)))
                 fail(SLLG_E_STATE, "replica flags do not match its buffers");
         }
+        // the per-site kernel variant is needed when any replica has per-site data
+        bool per_site = false;
+        for (const auto& sl : slots_)
+            per_site = per_site || (sl.used && (sl.rec.flags & (kPerSiteMaterial | kPerSiteAxis)));
+        if (per_site != per_site_)
+            drop_graph();
+        per_site_ = per_site;
+        resident_ = resident_pair_[per_site_ ? 1 : 0];
         work_.clear();
         for (size_t q = 0; q < slots_.size(); ++q) {
             host_reps_[q] = slots_[q].used ? slots_[q].rec : ReplicaDev<R>{};
@@ -551,7 +563,7 @@ public:
         if (e == hipSuccess)
             e = hipMemcpy(d_n, &n, sizeof(int), hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = launch_predict<R>(d_reps_, d_all, d_n, n, 1, 0, true, st);
+            e = launch_predict<R>(d_reps_, d_all, d_n, n, 1, 0, true, per_site_, st);
         if (e == hipSuccess)
             e = launch_finish<R>(d_reps_, (int)slots_.size(), 1, st);
         if (e == hipSuccess)
@@ -613,12 +625,12 @@ private:
         const int nrep = (int)slots_.size();
         hipError_t e = hipSuccess;
         for (int k = 0; k < K && e == hipSuccess; ++k) {
-            e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, false, st);
+            e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, false, per_site_, st);
             if (e == hipSuccess)
-                e = launch_correct<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, st);
+                e = launch_correct<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, per_site_, st);
         }
         if (e == hipSuccess)
-            e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 0, remap_, true, st);
+            e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 0, remap_, true, per_site_, st);
         if (e == hipSuccess)
             e = launch_finish<R>(d_reps_, nrep, 0, st);
         if (e == hipSuccess)
@@ -648,6 +660,8 @@ private:
     int64_t work_cap_ = 0;
     int grid_ = 0;
     int resident_ = 0;
+    int resident_pair_[2] = {0, 0};   // resident workgroups: uniform / per-site kernel variant
+    bool per_site_ = false;
     double grid_scale_ = 1.0;
     int remap_ = 1;
     // At most auto_group_ columns per group, the plane's columns split evenly.

@@ -56,15 +56,23 @@
 #define SLLG_FAR_REGS_F64 6
 #endif
 #ifndef SLLG_WAVES_F32
-#define SLLG_WAVES_F32 5
+#define SLLG_WAVES_F32 6
 #endif
 #ifndef SLLG_WAVES_F64
-#define SLLG_WAVES_F64 3
+#define SLLG_WAVES_F64 4
+#endif
+#ifndef SLLG_WAVES_F32_PS
+#define SLLG_WAVES_F32_PS 5
+#endif
+#ifndef SLLG_WAVES_F64_PS
+#define SLLG_WAVES_F64_PS 3
 #endif
 // Waves per SIMD the step kernels are compiled for: as many as their LDS
-// allows (register use is capped to match).
-#define SLLG_STEP_ATTRS \
-    __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? SLLG_WAVES_F32 : SLLG_WAVES_F64)))
+// allows (register use is capped to match).  PS: the variant that reads
+// per-site materials and easy axes.
+#define SLLG_STEP_ATTRS                                                                        \
+    __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(                       \
+        sizeof(R) == 4 ? (PS ? SLLG_WAVES_F32_PS : SLLG_WAVES_F32) : (PS ? SLLG_WAVES_F64_PS : SLLG_WAVES_F64))))
 #define SLLG_PRAGMA(x) _Pragma(#x)
 #define SLLG_UNROLL(n) SLLG_PRAGMA(unroll n)
 
@@ -632,6 +640,37 @@ __device__ __forceinline__ MaterialDev<R> site_material(const ReplicaDev<R>& r, 
     return m;
 }
 
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// The replica's only material (no per-site materials), in scalar registers.
+template <typename R>
+__device__ __forceinline__ MaterialDev<R> uniform_material(const ReplicaDev<R>& r)
+{
+    const SLLG_GLOBAL MaterialDev<R>& g = *(const SLLG_GLOBAL MaterialDev<R>*)r.mat;
+    MaterialDev<R> m;
+    m.mu_rel = wave_uniform(g.mu_rel);
+    m.mu_frac = wave_uniform(g.mu_frac);
+    m.ani = wave_uniform(g.ani);
+    m.ku_mu = wave_uniform(g.ku_mu);
+    m.sigma = wave_uniform(g.sigma);
+    m.axis[0] = wave_uniform(g.axis[0]);
+    m.axis[1] = wave_uniform(g.axis[1]);
+    m.axis[2] = wave_uniform(g.axis[2]);
+    m.mu_s = wave_uniform(g.mu_s);
+    return m;
+}
+
 template <typename R>
 __device__ __forceinline__ V3<R> site_axis(const ReplicaDev<R>& r, const MaterialDev<R>& m, int i)
 {
@@ -664,7 +703,51 @@ __device__ __forceinline__ void add_thermal(const MaterialDev<R>& m, const R g[3
 // (or of the measuring pass at the end of the chunk) adds the groups into
 // the record.  The chunk's last record is completed by k_finish.
 // ---------------------------------------------------------------------------
-template <typename R, bool MEASURE>
+// The sites of one tile (PS: per-site materials or axes; otherwise the
+// material is read once into scalar registers).
+template <typename R, bool MEASURE, bool PS>
+__device__ __forceinline__ void predict_sites(const ReplicaDev<R>& r, const R* __restrict__ S,
+                                              const Shared<R>& sh, const TileLds<R>& tl, int i0, int wb,
+                                              int k, bool partials, double v[4])
+{
+    constexpr int T = tile_sites<R>();
+    const MaterialDev<R> m0 = PS ? MaterialDev<R>{} : uniform_material(r);
+    for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
+        const int i = i0 + l;
+        if (i >= r.n)
+            break;
+        const MaterialDev<R> m = PS ? site_material(r, i) : m0;   // loaded before the gathers are issued
+        const int wbyte = site_bytes<R>(l + r.halo);
+        const V3<R> s = wload3(tl.win, wbyte);
+        R g[3] = {0, 0, 0};
+        const V3<R> sum = exchange_sum(r, S, sh, tl, i, l, wb, wbyte, [&] {
+            if (!MEASURE && m.sigma != (R)0)
+                thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
+        });
+        const V3<R> hex{m.mu_rel * sum.x, m.mu_rel * sum.y, m.mu_rel * sum.z};
+        const V3<R> e = PS ? site_axis(r, m, i) : V3<R>{m.axis[0], m.axis[1], m.axis[2]};
+        const R se = dot(s, e);
+        const V3<R> Happ{r.H[0], r.H[1], r.H[2]};
+        if (partials) {
+            // in units of mu_ref: mu_s/mu_ref S and mu_s/mu_ref (-E_i/mu_s)
+            v[0] += (double)(m.mu_frac * s.x);
+            v[1] += (double)(m.mu_frac * s.y);
+            v[2] += (double)(m.mu_frac * s.z);
+            v[3] += (double)(m.mu_frac * ((R)0.5 * dot(s, hex) + m.ku_mu * se * se + dot(s, Happ)));
+        }
+        if (!MEASURE) {
+            V3<R> h{hex.x + m.ani * se * e.x + Happ.x, hex.y + m.ani * se * e.y + Happ.y,
+                    hex.z + m.ani * se * e.z + Happ.z};
+            add_thermal(m, g, h);
+            const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
+            const V3<R> sp = normalised(V3<R>{s.x + ds.x, s.y + ds.y, s.z + ds.z});
+            store3(r.Sp, i, sp);
+            store3(r.Bc, i, V3<R>{s.x + (R)0.5 * ds.x, s.y + (R)0.5 * ds.y, s.z + (R)0.5 * ds.z});
+        }
+    }
+}
+
+template <typename R, bool MEASURE, bool PS>
 __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps,
                                           const WorkItem* __restrict__ work,
                                           const int* __restrict__ n_work, int k, int remap)
@@ -696,39 +779,10 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
             stage_ids<R>(r.pat_id, r.n, i0, tl.pid);
         __syncthreads();
         double v[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
-            const int i = i0 + l;
-            if (i >= r.n)
-                break;
-            const MaterialDev<R> m = site_material(r, i);   // loaded before the gathers are issued
-            const int wbyte = site_bytes<R>(l + r.halo);
-            const V3<R> s = wload3(tl.win, wbyte);
-            R g[3] = {0, 0, 0};
-            const V3<R> sum = exchange_sum(r, S, sh, tl, i, l, wb, wbyte, [&] {
-                if (!MEASURE && m.sigma != (R)0)
-                    thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
-            });
-            const V3<R> hex{m.mu_rel * sum.x, m.mu_rel * sum.y, m.mu_rel * sum.z};
-            const V3<R> e = site_axis(r, m, i);
-            const R se = dot(s, e);
-            const V3<R> Happ{r.H[0], r.H[1], r.H[2]};
-            if (partials) {
-                // in units of mu_ref: mu_s/mu_ref S and mu_s/mu_ref (-E_i/mu_s)
-                v[0] += (double)(m.mu_frac * s.x);
-                v[1] += (double)(m.mu_frac * s.y);
-                v[2] += (double)(m.mu_frac * s.z);
-                v[3] += (double)(m.mu_frac * ((R)0.5 * dot(s, hex) + m.ku_mu * se * se + dot(s, Happ)));
-            }
-            if (!MEASURE) {
-                V3<R> h{hex.x + m.ani * se * e.x + Happ.x, hex.y + m.ani * se * e.y + Happ.y,
-                        hex.z + m.ani * se * e.z + Happ.z};
-                add_thermal(m, g, h);
-                const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
-                const V3<R> sp = normalised(V3<R>{s.x + ds.x, s.y + ds.y, s.z + ds.z});
-                store3(r.Sp, i, sp);
-                store3(r.Bc, i, V3<R>{s.x + (R)0.5 * ds.x, s.y + (R)0.5 * ds.y, s.z + (R)0.5 * ds.z});
-            }
-        }
+        if (PS && (r.flags & (kPerSiteMaterial | kPerSiteAxis)))
+            predict_sites<R, MEASURE, true>(r, S, sh, tl, i0, wb, k, partials, v);
+        else
+            predict_sites<R, MEASURE, false>(r, S, sh, tl, i0, wb, k, partials, v);
         if (partials) {
             double out[4];
             block_sum4(v, out, red);
@@ -756,7 +810,39 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
 // ping-pong buffer.  Workgroups whose tile opens a group of kGroupTiles also
 // sum that group of the predictor's partials.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, bool PS>
+__device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* __restrict__ Sp,
+                                              R* __restrict__ Sn, const Shared<R>& sh,
+                                              const TileLds<R>& tl, int i0, int wb, int k)
+{
+    constexpr int T = tile_sites<R>();
+    const MaterialDev<R> m0 = PS ? MaterialDev<R>{} : uniform_material(r);
+    for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
+        const int i = i0 + l;
+        if (i >= r.n)
+            break;
+        const MaterialDev<R> m = PS ? site_material(r, i) : m0;   // loaded before the gathers are issued
+        const int wbyte = site_bytes<R>(l + r.halo);
+        const V3<R> sp = wload3(tl.win, wbyte);
+        const V3<R> b = load3_once((const R*)r.Bc, i);
+        R g[3] = {0, 0, 0};
+        const V3<R> sum = exchange_sum(r, Sp, sh, tl, i, l, wb, wbyte, [&] {
+            if (m.sigma != (R)0)
+                thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
+        });
+        const V3<R> e = PS ? site_axis(r, m, i) : V3<R>{m.axis[0], m.axis[1], m.axis[2]};
+        const R se = dot(sp, e);
+        V3<R> h{m.mu_rel * sum.x + m.ani * se * e.x + r.H[0],
+                m.mu_rel * sum.y + m.ani * se * e.y + r.H[1],
+                m.mu_rel * sum.z + m.ani * se * e.z + r.H[2]};
+        add_thermal(m, g, h);
+        const V3<R> ds = llg_step(sp, h, r.gdt, r.alpha);
+        const V3<R> sn = normalised(V3<R>{b.x + (R)0.5 * ds.x, b.y + (R)0.5 * ds.y, b.z + (R)0.5 * ds.z});
+        store3(Sn, i, sn);
+    }
+}
+
+template <typename R, bool PS>
 __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps,
                                           const WorkItem* __restrict__ work,
                                           const int* __restrict__ n_work, int k, int remap)
@@ -784,29 +870,10 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
             stage_ids<R>(r.pat_id, r.n, i0, tl.pid);
         __syncthreads();
         R* __restrict__ Sn = r.S[(r.parity + k + 1) & 1];
-        for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
-            const int i = i0 + l;
-            if (i >= r.n)
-                break;
-            const MaterialDev<R> m = site_material(r, i);   // loaded before the gathers are issued
-            const int wbyte = site_bytes<R>(l + r.halo);
-            const V3<R> sp = wload3(tl.win, wbyte);
-            const V3<R> b = load3_once((const R*)r.Bc, i);
-            R g[3] = {0, 0, 0};
-            const V3<R> sum = exchange_sum(r, Sp, sh, tl, i, l, wb, wbyte, [&] {
-                if (m.sigma != (R)0)
-                    thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
-            });
-            const V3<R> e = site_axis(r, m, i);
-            const R se = dot(sp, e);
-            V3<R> h{m.mu_rel * sum.x + m.ani * se * e.x + r.H[0],
-                    m.mu_rel * sum.y + m.ani * se * e.y + r.H[1],
-                    m.mu_rel * sum.z + m.ani * se * e.z + r.H[2]};
-            add_thermal(m, g, h);
-            const V3<R> ds = llg_step(sp, h, r.gdt, r.alpha);
-            const V3<R> sn = normalised(V3<R>{b.x + (R)0.5 * ds.x, b.y + (R)0.5 * ds.y, b.z + (R)0.5 * ds.z});
-            store3(Sn, i, sn);
-        }
+        if (PS && (r.flags & (kPerSiteMaterial | kPerSiteAxis)))
+            correct_sites<R, true>(r, Sp, Sn, sh, tl, i0, wb, k);
+        else
+            correct_sites<R, false>(r, Sp, Sn, sh, tl, i0, wb, k);
         if ((r.flags & kRecord) && k >= 1 && (w.block % kGroupTiles) == 0)
             group_reduce(r, w.block / kGroupTiles, red);
     }
@@ -914,27 +981,33 @@ __global__ void k_accumulate(const ReplicaDev<R>* __restrict__ reps, int n_rep)
 // ---------------------------------------------------------------------------
 template <typename R>
 hipError_t launch_predict(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work,
-                          int grid, int k, int remap, bool measure, hipStream_t st)
+                          int grid, int k, int remap, bool measure, bool per_site, hipStream_t st)
 {
     if (grid <= 0)
         return hipSuccess;
-    if (measure)
-        hipLaunchKernelGGL((k_predict<R, true>), dim3(grid), dim3(kBlockThreads), 0, st, reps, work,
-                           n_work, k, remap);
+    const dim3 g(grid), b(kBlockThreads);
+    if (measure && per_site)
+        hipLaunchKernelGGL((k_predict<R, true, true>), g, b, 0, st, reps, work, n_work, k, remap);
+    else if (measure)
+        hipLaunchKernelGGL((k_predict<R, true, false>), g, b, 0, st, reps, work, n_work, k, remap);
+    else if (per_site)
+        hipLaunchKernelGGL((k_predict<R, false, true>), g, b, 0, st, reps, work, n_work, k, remap);
     else
-        hipLaunchKernelGGL((k_predict<R, false>), dim3(grid), dim3(kBlockThreads), 0, st, reps, work,
-                           n_work, k, remap);
+        hipLaunchKernelGGL((k_predict<R, false, false>), g, b, 0, st, reps, work, n_work, k, remap);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_correct(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work,
-                          int grid, int k, int remap, hipStream_t st)
+                          int grid, int k, int remap, bool per_site, hipStream_t st)
 {
     if (grid <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((k_correct<R>), dim3(grid), dim3(kBlockThreads), 0, st, reps, work, n_work, k,
-                       remap);
+    const dim3 g(grid), b(kBlockThreads);
+    if (per_site)
+        hipLaunchKernelGGL((k_correct<R, true>), g, b, 0, st, reps, work, n_work, k, remap);
+    else
+        hipLaunchKernelGGL((k_correct<R, false>), g, b, 0, st, reps, work, n_work, k, remap);
     return hipGetLastError();
 }
 
@@ -966,14 +1039,15 @@ hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStr
 }
 
 template <typename R>
-int resident_blocks(int device)
+int resident_blocks(int device, bool per_site)
 {
     int cus = 0, a = 0, b = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)k_predict<R, false>, kBlockThreads, 0) !=
-            hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)k_correct<R>, kBlockThreads, 0) != hipSuccess)
+    const void* kp = per_site ? (const void*)k_predict<R, false, true> : (const void*)k_predict<R, false, false>;
+    const void* kc = per_site ? (const void*)k_correct<R, true> : (const void*)k_correct<R, false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kp, kBlockThreads, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kc, kBlockThreads, 0) != hipSuccess)
         return 0;
     const int per_cu = a < b ? a : b;
     return cus * (per_cu > 0 ? per_cu : 1);
@@ -1000,14 +1074,14 @@ hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t s
 
 #define SLLG_INSTANTIATE(R)                                                                          \
     template hipError_t launch_predict<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, \
-                                          int, bool, hipStream_t);                                   \
+                                          int, bool, bool, hipStream_t);                             \
     template hipError_t launch_correct<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, \
-                                          int, hipStream_t);                                         \
+                                          int, bool, hipStream_t);                                   \
     template hipError_t launch_accumulate<R>(const ReplicaDev<R>*, int, hipStream_t);                \
     template hipError_t launch_finish<R>(const ReplicaDev<R>*, int, int, hipStream_t);              \
     template hipError_t launch_advance<R>(ReplicaDev<R>*, int, hipStream_t);                         \
     template hipError_t launch_noise<R>(uint64_t, uint64_t, int, double*, hipStream_t);             \
-    template int resident_blocks<R>(int);
+    template int resident_blocks<R>(int, bool);
 
 SLLG_INSTANTIATE(float)
 SLLG_INSTANTIATE(double)

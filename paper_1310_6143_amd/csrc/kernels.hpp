@@ -15,13 +15,15 @@ namespace sllg {
 // `grid` workgroups are launched; those whose (remapped) index is at or past
 // *n_work (device memory) exit at once, so a captured graph can serve any
 // batch up to `grid` blocks.
+// per_site selects the kernels that can read per-site materials and easy
+// axes (needed when any replica of the batch has them).
 template <typename R>
 hipError_t launch_predict(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work,
-                          int grid, int k, int remap, bool measure, hipStream_t st);
+                          int grid, int k, int remap, bool measure, bool per_site, hipStream_t st);
 // Corrector of step k of the current chunk.
 template <typename R>
 hipError_t launch_correct(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work,
-                          int grid, int k, int remap, hipStream_t st);
+                          int grid, int k, int remap, bool per_site, hipStream_t st);
 // Thermal-average block sums of every replica with kAverage.
 template <typename R>
 hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t st);
@@ -40,7 +42,7 @@ hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStr
 // Workgroups of the step kernels that fit on the device at once
 // (compute units x resident blocks per unit); 0 if it cannot be queried.
 template <typename R>
-int resident_blocks(int device);
+int resident_blocks(int device, bool per_site);
 
 hipError_t launch_scatter_records(const double* rec, int count, double* m_dev, double* E_dev,
                                   hipStream_t st);

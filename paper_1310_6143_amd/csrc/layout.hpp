@@ -21,15 +21,18 @@ namespace sllg {
 // on either side in LDS; neighbours within the halo are read from there,
 // the rest from global memory.
 #ifndef SLLG_TILE_SITES_F32
-#define SLLG_TILE_SITES_F32 1024
+#define SLLG_TILE_SITES_F32 2048
 #endif
 #ifndef SLLG_TILE_SITES_F64
-#define SLLG_TILE_SITES_F64 512
+#define SLLG_TILE_SITES_F64 1024
 #endif
 #ifndef SLLG_HALO_CAP
 #define SLLG_HALO_CAP 384
 #endif
-constexpr int kBlockThreads = 256;
+#ifndef SLLG_BLOCK_THREADS
+#define SLLG_BLOCK_THREADS 512
+#endif
+constexpr int kBlockThreads = SLLG_BLOCK_THREADS;
 template <typename R>
 constexpr int tile_sites()
 {
@@ -39,6 +42,7 @@ constexpr int kHaloCap = SLLG_HALO_CAP;
 static_assert(SLLG_TILE_SITES_F32 % kBlockThreads == 0 && SLLG_TILE_SITES_F64 % kBlockThreads == 0,
               "a tile is a whole number of sites per lane");
 static_assert(SLLG_HALO_CAP % 4 == 0, "the halo keeps 16-byte alignment of the staged window");
+static_assert(SLLG_BLOCK_THREADS % 64 == 0 && SLLG_BLOCK_THREADS >= 256, "whole wavefronts; a group sum takes one lane per tile");
 // Spin buffers are padded to a multiple of 16 bytes so that a tile's
 // window is staged with whole 16-byte loads.
 __host__ __device__ inline size_t spin_buffer_bytes(int64_t n, size_t real_bytes)
