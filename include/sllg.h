@@ -211,13 +211,20 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     and are still cached); 0 site order
  *   "tile_group"      tile columns per group for tile_order 1 (1..4096;
  *                     0, the default, sizes the groups from the L2 capacity)
+ *   "tile_sites"      consecutive sites one workgroup integrates together:
+ *                     0 (default) = from the system size (the largest tile,
+ *                     2048 in FP32 / 1024 in FP64, halved down to 512 until
+ *                     the system has at least 2048 tiles), or a power of two
+ *                     in that range.  Trajectories do not depend on it; the
+ *                     m and E records do at the level of FP64 rounding (the
+ *                     tile is the first level of their summation tree).  The
+ *                     server always uses the largest tile.
  *   "stencil"         1 (default) / 0: let the next sllg_set_neighbours store
  *                     the list as per-site stencil patterns when at most 256
  *                     distinct (column - row, type) rows occur (<= 1024
  *                     entries in all); 0 keeps the general SELL-64 form
  * sllg_get_option also reads "neighbour_format": 1 stencil, 0 SELL, -1 unset;
- * "tile_sites": consecutive sites one workgroup integrates together (2048 in
- * FP32, 1024 in FP64); "halo": neighbours with |column - row| up to this many
+ * "halo": neighbours with |column - row| up to this many
  * sites are read from the tile's window in LDS, the rest from HBM (-1 unset).
  */
 sllg_status sllg_set_option(sllg_system *sys, const char *key, int64_t value);

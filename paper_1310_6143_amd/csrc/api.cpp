@@ -143,6 +143,7 @@ struct sllg_system {
     int64_t opt_grid_scale_pct = 100;   // workgroups per launch, % of the resident grid
     int64_t opt_tile_order = 1;         // plane-swept column groups when a plane stride is found
     int64_t opt_tile_group = 0;         // tile columns per group, 0 = from the L2 size
+    int64_t opt_tile_sites = 0;         // sites per tile, 0 = from the system size
     bool tuned = false;
     double tuned_us = 0.0;
     int64_t opt_stencil = 1;
@@ -547,6 +548,7 @@ sllg_status sllg_set_neighbours(sllg_system* sys, const int64_t* row_ptr, const 
     return guard(sys, [&] {
         HostStructure st = build_structure(sys->n, row_ptr, col, ntype, J, n_types,
                                            sys->opt_check_symmetry != 0, kHaloCap, sys->opt_stencil != 0);
+        st.tile_request = (int)sys->opt_tile_sites;
         drop_engine(sys);
         sys->st = std::move(st);
         sys->has_nb = true;
@@ -856,6 +858,19 @@ sllg_status sllg_set_option(sllg_system* sys, const char* key, int64_t value)
                 sys->eng->set_grid_scale(value / 100.0);
         } else if (k == "stencil") {
             sys->opt_stencil = value ? 1 : 0;   // applies to the next sllg_set_neighbours
+        } else if (k == "tile_sites") {
+            const int64_t largest = sys->prec == SLLG_FP64 ? tile_sites<double>() : tile_sites<float>();
+            bool ok = value == 0;
+            for (int64_t t = kBlockThreads; t <= largest && !ok; t *= 2)
+                ok = value == t;
+            if (!ok)
+                fail(SLLG_E_ARG, "tile_sites must be 0 (automatic) or a power of two from " +
+                                     std::to_string(kBlockThreads) + " to " + std::to_string(largest));
+            if (value != sys->opt_tile_sites) {
+                drop_engine(sys);   // rebuilt at the next run with the new tiling, state kept
+                sys->opt_tile_sites = value;
+                sys->st.tile_request = (int)value;
+            }
         } else if (k == "tile_order") {
             if (value < 0 || value > 1)
                 fail(SLLG_E_ARG, "tile_order must be 0 or 1");
@@ -889,8 +904,12 @@ sllg_status sllg_get_option(const sllg_system* sys, const char* key, int64_t* va
         *value = sys->opt_check_symmetry;
     else if (k == "graph_steps")
         *value = graph_steps(sys);
-    else if (k == "tile_sites")
-        *value = sys->prec == SLLG_FP64 ? tile_sites<double>() : tile_sites<float>();
+    else if (k == "tile_sites") {
+        HostStructure probe;
+        probe.n = sys->n;
+        probe.tile_request = (int)sys->opt_tile_sites;
+        *value = tile_of(probe, sys->prec == SLLG_FP64 ? 8 : 4);
+    }
     else if (k == "halo")
         *value = sys->has_nb ? sys->st.halo : -1;
     else if (k == "xcd_remap")

@@ -24,6 +24,10 @@
 #include "layout.hpp"
 #include "prepare.hpp"
 
+#ifndef SLLG_DEFAULT_REMAP
+#define SLLG_DEFAULT_REMAP 1
+#endif
+
 namespace sllg {
 
 inline void hip_check(hipError_t e, const char* what)
@@ -131,7 +135,7 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
 {
     auto r = [](size_t b) { return PoolAllocator::round(b); };
     const size_t n = (size_t)s.n;
-    const size_t tile = real_bytes == 4 ? tile_sites<float>() : tile_sites<double>();
+    const size_t tile = (size_t)tile_of(s, real_bytes);
     const size_t blocks = (n + tile - 1) / tile;
     size_t b = 4 * r(spin_buffer_bytes(s.n, real_bytes));       // S[2], Sp, Bc
     if (s.stencil)
@@ -237,11 +241,12 @@ public:
         // A group's tiles stream about 9 sizeof(R) bytes per site through the
         // L2 per launch (S read, S' and Bc written, then read back); the
         // plane-to-plane reuse spans two planes of a group, kept within a
-        // quarter of one L2 (the L2 of one XCD on MI355X).
+        // quarter of one L2 (the L2 of one XCD on MI355X): group_sites_ is
+        // that budget in sites.
         int l2 = 0;
         if (hipDeviceGetAttribute(&l2, hipDeviceAttributeL2CacheSize, device_) != hipSuccess || l2 <= 0)
             l2 = 4 << 20;
-        auto_group_ = std::max(1, (int)((int64_t)l2 / (4 * 9 * (int64_t)sizeof(R) * tile_sites<R>())));
+        group_sites_ = (int64_t)l2 / (4 * 9 * (int64_t)sizeof(R));
     }
 
     ~Batch()
@@ -293,7 +298,8 @@ public:
         sl.rec_cap = std::max<int64_t>(rec_cap, 1);
         sl.avg_cap = std::max(avg_cap, 1);
         const size_t n = (size_t)s.n;
-        const size_t blocks = (n + tile_sites<R>() - 1) / tile_sites<R>();
+        const size_t tile = (size_t)tile_of(s, sizeof(R));
+        const size_t blocks = (n + tile - 1) / tile;
         try {
             auto get = [&](size_t bytes) {
                 void* p = alloc_->alloc(bytes);
@@ -377,7 +383,7 @@ public:
             r.avg_blocks = 0;
             set_spins(q, S0);
             sl.bytes = replica_bytes(s, m, sizeof(R), sl.rec_cap, sl.avg_cap);
-            sl.plane_tiles = plane_tiles(s, tile_sites<R>());
+            sl.plane_tiles = plane_tiles(s, (int)tile);
             sl.used = true;
         } catch (...) {
             for (void* p : sl.mem)
@@ -468,7 +474,8 @@ public:
                 host_reps_[q].nsteps = 0;
             if (slots_[q].used && slots_[q].rec.nsteps > 0)
                 for (int32_t b : tile_order(slots_[q].rec.blocks, order_ ? slots_[q].plane_tiles : 0,
-                                            group_ > 0 ? group_ : balanced_group(slots_[q].plane_tiles)))
+                                            group_ > 0 ? group_
+                                                       : balanced_group(slots_[q].plane_tiles, slots_[q].rec.tile)))
                     work_.push_back(WorkItem{(int32_t)q, b});
         }
         const int nwork = (int)work_.size();
@@ -663,19 +670,21 @@ private:
     int resident_pair_[2] = {0, 0};   // resident workgroups: uniform / per-site kernel variant
     bool per_site_ = false;
     double grid_scale_ = 1.0;
-    int remap_ = 1;
-    // At most auto_group_ columns per group, the plane's columns split evenly.
-    int balanced_group(int pt) const
+    int remap_ = SLLG_DEFAULT_REMAP;
+    // Columns per group sized from the L2 (group_sites_ sites), the plane's
+    // columns split evenly.
+    int balanced_group(int pt, int tile) const
     {
-        if (pt <= auto_group_)
+        const int cap = (int)std::max<int64_t>(1, group_sites_ / std::max(tile, 1));
+        if (pt <= cap)
             return std::max(pt, 1);
-        const int groups = (pt + auto_group_ - 1) / auto_group_;
+        const int groups = (pt + cap - 1) / cap;
         return (pt + groups - 1) / groups;
     }
 
     int order_ = 1;
     int group_ = 0;
-    int auto_group_ = 8;
+    int64_t group_sites_ = 1 << 14;
     bool round_grid_ = false;
     bool dirty_ = true;
     hipGraphExec_t graph_exec_ = nullptr;

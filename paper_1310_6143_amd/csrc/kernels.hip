@@ -340,10 +340,9 @@ __device__ __forceinline__ void stage_window(const R* __restrict__ S, int n, int
     stage_chunks(S + 3 * (int64_t)first, skip, lim, nc, (v4i*)win);
 }
 
-template <typename R>
-__device__ __forceinline__ void stage_ids(const uint8_t* __restrict__ pid, int n, int i0, uint8_t* dst)
+__device__ __forceinline__ void stage_ids(const uint8_t* __restrict__ pid, int n, int i0, int T, uint8_t* dst)
 {
-    constexpr int nc = tile_sites<R>() / 16;
+    const int nc = T / 16;
     const int64_t avail = (((int64_t)n + 15) & ~int64_t(15)) - i0;
     const int lim = (int)min<int64_t>(avail / 16, (int64_t)nc);
     stage_chunks(pid + i0, 0, lim, nc, (v4i*)dst);
@@ -710,7 +709,7 @@ __device__ __forceinline__ void predict_sites(const ReplicaDev<R>& r, const R* _
                                               const Shared<R>& sh, const TileLds<R>& tl, int i0, int wb,
                                               int k, bool partials, double v[4])
 {
-    constexpr int T = tile_sites<R>();
+    const int T = r.tile;
     const MaterialDev<R> m0 = PS ? MaterialDev<R>{} : uniform_material(r);
     for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
         const int i = i0 + l;
@@ -752,7 +751,6 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
                                           const WorkItem* __restrict__ work,
                                           const int* __restrict__ n_work, int k, int remap)
 {
-    constexpr int T = tile_sites<R>();
     __shared__ Shared<R> sh;
     __shared__ TileLds<R> tl;
     __shared__ double red[4][kWaves];
@@ -768,6 +766,7 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
         const bool partials = recording && (MEASURE || k >= 1);
         const int par = (r.parity + (MEASURE ? (k == 0 ? nsteps : 0) : k)) & 1;
         const R* __restrict__ S = r.S[par];
+        const int T = r.tile;
         const int i0 = w.block * T, wb = i0 - r.halo;
         __syncthreads();   // every lane is done with the previous tile's LDS
         if (w.replica != staged) {
@@ -776,7 +775,7 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
         }
         stage_window(S, r.n, wb, T + 2 * r.halo, tl.win);
         if (r.flags & kStencil)
-            stage_ids<R>(r.pat_id, r.n, i0, tl.pid);
+            stage_ids(r.pat_id, r.n, i0, T, tl.pid);
         __syncthreads();
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         if (PS && (r.flags & (kPerSiteMaterial | kPerSiteAxis)))
@@ -815,7 +814,7 @@ __device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* _
                                               R* __restrict__ Sn, const Shared<R>& sh,
                                               const TileLds<R>& tl, int i0, int wb, int k)
 {
-    constexpr int T = tile_sites<R>();
+    const int T = r.tile;
     const MaterialDev<R> m0 = PS ? MaterialDev<R>{} : uniform_material(r);
     for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
         const int i = i0 + l;
@@ -847,7 +846,6 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
                                           const WorkItem* __restrict__ work,
                                           const int* __restrict__ n_work, int k, int remap)
 {
-    constexpr int T = tile_sites<R>();
     __shared__ Shared<R> sh;
     __shared__ TileLds<R> tl;
     __shared__ double red[4][kWaves];
@@ -859,6 +857,7 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
         if (k >= r.nsteps)
             continue;
         const R* __restrict__ Sp = r.Sp;
+        const int T = r.tile;
         const int i0 = w.block * T, wb = i0 - r.halo;
         __syncthreads();   // every lane is done with the previous tile's LDS
         if (w.replica != staged) {
@@ -867,7 +866,7 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
         }
         stage_window(Sp, r.n, wb, T + 2 * r.halo, tl.win);
         if (r.flags & kStencil)
-            stage_ids<R>(r.pat_id, r.n, i0, tl.pid);
+            stage_ids(r.pat_id, r.n, i0, T, tl.pid);
         __syncthreads();
         R* __restrict__ Sn = r.S[(r.parity + k + 1) & 1];
         if (PS && (r.flags & (kPerSiteMaterial | kPerSiteAxis)))

@@ -5,8 +5,7 @@
 // through sllg_create is a batch of one replica; the server batches many.
 // Every replica owns its device buffers; the kernels find them through a
 // table of ReplicaDev records, and a table of work items maps each tile of
-// tile_sites<R>() consecutive sites of a replica to the workgroup that
-// sweeps it.
+// consecutive sites of a replica to the workgroup that sweeps it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,7 +15,7 @@
 namespace sllg {
 
 // Step kernels: workgroups of kBlockThreads lanes sweep tiles of
-// tile_sites<R>() consecutive sites (tile_sites / kBlockThreads per lane).
+// consecutive sites (tile_for(): a few sites per lane).
 // A workgroup stages its tile's spins plus a halo of up to kHaloCap sites
 // on either side in LDS; neighbours within the halo are read from there,
 // the rest from global memory.
@@ -33,13 +32,30 @@ namespace sllg {
 #define SLLG_BLOCK_THREADS 512
 #endif
 constexpr int kBlockThreads = SLLG_BLOCK_THREADS;
+// Largest tile (the LDS arrays are sized for it).
 template <typename R>
 constexpr int tile_sites()
 {
     return sizeof(R) == 4 ? SLLG_TILE_SITES_F32 : SLLG_TILE_SITES_F64;
 }
+// Tiles a replica should have at least, so that small systems still spread
+// over the whole chip.
+constexpr int64_t kMinTiles = 2048;
+// Tile size of an n-site replica: the largest power-of-two fraction of the
+// largest tile (down to one site per lane) that still gives kMinTiles
+// tiles.  A function of n and the precision only, so a replica is tiled the
+// same way alone and in any batch.
+__host__ __device__ inline int tile_for(int64_t n, size_t real_bytes)
+{
+    int t = real_bytes == 4 ? SLLG_TILE_SITES_F32 : SLLG_TILE_SITES_F64;
+    while (t > kBlockThreads && (n + t - 1) / t < kMinTiles)
+        t /= 2;
+    return t;
+}
 constexpr int kHaloCap = SLLG_HALO_CAP;
-static_assert(SLLG_TILE_SITES_F32 % kBlockThreads == 0 && SLLG_TILE_SITES_F64 % kBlockThreads == 0,
+static_assert(SLLG_TILE_SITES_F32 % kBlockThreads == 0 && SLLG_TILE_SITES_F64 % kBlockThreads == 0 &&
+                  (SLLG_TILE_SITES_F32 / kBlockThreads & (SLLG_TILE_SITES_F32 / kBlockThreads - 1)) == 0 &&
+                  (SLLG_TILE_SITES_F64 / kBlockThreads & (SLLG_TILE_SITES_F64 / kBlockThreads - 1)) == 0,
               "a tile is a whole number of sites per lane");
 static_assert(SLLG_HALO_CAP % 4 == 0, "the halo keeps 16-byte alignment of the staged window");
 static_assert(SLLG_BLOCK_THREADS % 64 == 0 && SLLG_BLOCK_THREADS >= 256, "whole wavefronts; a group sum takes one lane per tile");
@@ -118,11 +134,13 @@ struct ReplicaDev {
     int32_t avg_blocks;             // number of averaging blocks
     int32_t halo;                   // window halo in sites (multiple of 4, <= kHaloCap)
     int32_t n;                      // sites
-    int32_t blocks;                 // tiles: ceil(n / tile_sites)
+    int32_t blocks;                 // tiles: ceil(n / tile)
     int32_t parity;                 // S[parity] holds the current state (advanced on the device)
     int32_t nsteps;                 // steps this replica takes in the current chunk
     int32_t flags;                  // ReplicaFlags
     int32_t n_patterns;             // stencil patterns (kStencil)
+    int32_t tile;                   // sites per tile: tile_for(n, sizeof(R))
+    int32_t pad1;
 };
 
 struct WorkItem {

@@ -13,6 +13,16 @@ namespace sllg {
 
 void fail(sllg_status code, const std::string& msg) { throw Failure{code, msg}; }
 
+int tile_of(const HostStructure& s, size_t real_bytes)
+{
+    const int largest = real_bytes == 4 ? tile_sites<float>() : tile_sites<double>();
+    if (s.tile_request < 0)
+        return largest;
+    if (s.tile_request == 0)
+        return tile_for(s.n, real_bytes);
+    return std::min(s.tile_request, largest);
+}
+
 HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* col,
                               const uint8_t* ntype, const double* J, int n_types,
                               bool check_symmetry, int halo_cap, bool allow_stencil)
@@ -314,7 +324,8 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
     rec.seed = d.seed;
     rec.step = d.step;
     rec.n = (int32_t)s.n;
-    rec.blocks = (int32_t)((s.n + tile_sites<R>() - 1) / tile_sites<R>());
+    rec.tile = tile_of(s, sizeof(R));
+    rec.blocks = (int32_t)((s.n + rec.tile - 1) / rec.tile);
     rec.halo = s.halo;
     int32_t flags = rec.flags & (kRecord | kRecordSeries);
     if (m.per_site_material)

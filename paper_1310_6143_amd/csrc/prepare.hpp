@@ -33,6 +33,7 @@ struct HostStructure {
     int64_t nnz = 0;
     int n_types = 0;
     int halo = 0;                      // window halo: max near |col - row|, rounded up to 4
+    int tile_request = 0;              // sites per tile: 0 from n (tile_for), -1 the largest, else this
     std::vector<double> J;             // joules per link, per type
     std::vector<uint32_t> nb;          // packed entries, 64 rows per slice, column-major
     std::vector<int64_t> slice_off;    // [n_slices + 1]
@@ -44,6 +45,9 @@ struct HostStructure {
     std::vector<uint16_t> pat_start;   // [n_patterns + 1]
     std::vector<uint16_t> pat_far;     // [n_patterns] first far entry of each pattern
 };
+
+// Sites per tile of this structure at a precision (see tile_request).
+int tile_of(const HostStructure& s, size_t real_bytes);
 
 // Validates and converts.  Throws Failure(SLLG_E_ARG) on malformed input.
 // allow_stencil = false keeps the SELL form even when patterns would fit.

@@ -397,6 +397,9 @@ sllg_status sllg_submit(sllg_server* srv, const sllg_request* req, uint64_t* tic
         j->n = req->n_spins;
         j->st = build_structure(req->n_spins, req->row_ptr, req->col, req->ntype, req->J, req->n_types, true,
                                 kHaloCap);
+        // a batch has parallelism across requests: the largest tiles keep
+        // the per-tile overheads lowest
+        j->st.tile_request = -1;
         j->mat = build_materials(req->n_spins, req->mu_s, req->k_u, req->easy_axis, req->per_site);
         j->dyn.alpha = req->alpha;
         j->dyn.gamma = req->gamma;

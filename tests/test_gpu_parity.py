@@ -187,6 +187,24 @@ def test_tile_order_does_not_change_results():
             assert np.array_equal(res[0][2], other[2])
 
 
+def test_tile_size_changes_only_record_rounding():
+    """Spin updates never depend on the tiling; the m/E records differ only
+    by the FP64 summation order of their first reduction level."""
+    w = bcc_block(cells=24, n_steps=100)
+    for prec, largest in ((sl.FP32, 2048), (sl.FP64, 1024)):
+        res = []
+        for tile in (0, 512, largest):
+            with sl.from_workload(w, precision=prec, check_symmetry=False) as g:
+                g.set_option("tile_sites", tile)
+                assert g.get_option("tile_sites") == (tile or 512)
+                m, E = g.integrate(80)
+                res.append((g.get_spins(), m, E))
+        for S, m, E in res[1:]:
+            assert np.array_equal(S, res[0][0])
+            assert np.allclose(m, res[0][1], rtol=0, atol=1e-13)
+            assert np.allclose(E, res[0][2], rtol=1e-13, atol=0)
+
+
 @pytest.mark.parametrize("L", [12, 64])
 def test_autotune_leaves_trajectory_unchanged(L):
     w = sc_reference(L=L, temperature=300.0, seed=13)
