@@ -44,16 +44,9 @@
 #ifndef SLLG_NT_LOADS
 #define SLLG_NT_LOADS 1
 #endif
-// Near (LDS) gathers per unrolled step, and far gathers held in registers
-// while the near part is summed.
+// Near (LDS) gathers per unrolled step.
 #ifndef SLLG_NEAR_UNROLL
 #define SLLG_NEAR_UNROLL 4
-#endif
-#ifndef SLLG_FAR_REGS_F32
-#define SLLG_FAR_REGS_F32 6
-#endif
-#ifndef SLLG_FAR_REGS_F64
-#define SLLG_FAR_REGS_F64 6
 #endif
 #ifndef SLLG_WAVES_F32
 #define SLLG_WAVES_F32 6
@@ -266,19 +259,11 @@ struct PatEntry<double> {
 };
 
 template <typename R>
-constexpr int kFarRegs = sizeof(R) == 4 ? SLLG_FAR_REGS_F32 : SLLG_FAR_REGS_F64;
-// A buffer offset at or past the end of any spin buffer the stencil form
-// allows (3 n sizeof(R) <= 0x7FFFF000, checked on the host).
-constexpr int kPastEnd = 0x7FFFFF00;
-
-// The entry table carries kFarRegs zero entries past its end, so the
-// register-held far gathers of the last pattern read inside the table.
-template <typename R>
 struct Shared {
     R jt[kMaxTypes];
     uint16_t pat_start[kMaxPatterns + 1];
     uint16_t pat_far[kMaxPatterns];
-    PatEntry<R> pat[kMaxPatternEntries + kFarRegs<R>];
+    PatEntry<R> pat[kMaxPatternEntries];
 };
 
 // The tile being integrated: spins of sites [i0 - halo, i0 + tile + halo)
@@ -303,10 +288,10 @@ __device__ __forceinline__ void stage_tables(const ReplicaDev<R>& r, Shared<R>& 
         for (int q = threadIdx.x; q < np; q += kBlockThreads)
             sh.pat_far[q] = gload(r.pat_far, q);
         const int ne = gload(r.pat_start, np);
-        for (int q = threadIdx.x; q < ne + kFarRegs<R>; q += kBlockThreads) {
-            const int32_t raw = q < ne ? gload(r.pat_tab, q) : 0;
+        for (int q = threadIdx.x; q < ne; q += kBlockThreads) {
+            const int32_t raw = gload(r.pat_tab, q);
             sh.pat[q].off = (raw >> 4) * (int)(3 * sizeof(R));
-            sh.pat[q].J = q < ne ? r.jt[raw & 15] : (R)0;
+            sh.pat[q].J = (raw >> 4) != 0 ? r.jt[raw & 15] : (R)0;   // offset 0: padding
         }
     }
 }
@@ -381,16 +366,16 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
         const int p = tl.pid[l];
         const int b = sh.pat_start[p], f = sh.pat_far[p], e = sh.pat_start[p + 1];
         // The first kFarRegs far gathers are issued before anything else,
-        // unconditionally (a lane without that entry reads past the end of
-        // the buffer, which returns zero without a memory access), so the
-        // loads issued earlier can be waited for one by one.
-        const int nf = e - f;
+        // so their latency overlaps the rest.  Every pattern has at least
+        // kFarRegs far entries (padding: offset 0, J = 0, which adds J * S_i
+        // = 0 and keeps the sum's value) unless none has any.
+        const bool far = !(r.flags & kNoFar);
         const PatEntry<R>* fp = sh.pat + f;
-        V3<R> fr[kFarRegs<R>];
+        V3<R> fr[kFarRegs];
+        if (far) {
 #pragma unroll
-        for (int q = 0; q < kFarRegs<R>; ++q) {
-            const int keep = -(int)(q < nf);   // all ones when the entry exists
-            fr[q] = bload3(rs, ((ib + fp[q].off) & keep) | (kPastEnd & ~keep), R(0));
+            for (int q = 0; q < kFarRegs; ++q)
+                fr[q] = bload3(rs, ib + fp[q].off, R(0));
         }
         overlap();
         SLLG_UNROLL(SLLG_NEAR_UNROLL)
@@ -401,17 +386,17 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
             hn.y += pe.J * sj.y;
             hn.z += pe.J * sj.z;
         }
-        // An absent entry contributes J * 0 = 0 (J is finite): the sum keeps
-        // its value.
+        if (far) {
 #pragma unroll
-        for (int q = 0; q < kFarRegs<R>; ++q) {
-            const R J = fp[q].J;
-            hf.x += J * fr[q].x;
-            hf.y += J * fr[q].y;
-            hf.z += J * fr[q].z;
+            for (int q = 0; q < kFarRegs; ++q) {
+                const R J = fp[q].J;
+                hf.x += J * fr[q].x;
+                hf.y += J * fr[q].y;
+                hf.z += J * fr[q].z;
+            }
         }
         SLLG_UNROLL(SLLG_GATHER_UNROLL)
-        for (int k = f + kFarRegs<R>; k < e; ++k) {
+        for (int k = f + kFarRegs; k < e; ++k) {
             const PatEntry<R> pe = sh.pat[k];
             const V3<R> sj = bload3(rs, ib + pe.off, R(0));
             hf.x += pe.J * sj.x;

@@ -75,6 +75,10 @@ constexpr int kMaxDegree = 255;
 // pattern; a site stores only its pattern id (uint8).  Pattern entries pack
 // (column - row) << 4 | type in an int32 (offsets within +-2^27).
 constexpr int kMaxPatterns = 256;
+// Far links of a stencil row the step kernels keep in flight in registers;
+// the host pads every pattern's far part to at least this many entries
+// (offset 0, J = 0) unless no pattern has any far link.
+constexpr int kFarRegs = 6;
 #ifndef SLLG_MAX_PATTERN_ENTRIES
 #define SLLG_MAX_PATTERN_ENTRIES 1024
 #endif
@@ -99,6 +103,7 @@ enum ReplicaFlags : int32_t {
     kRecordSeries = 8,      // records[] holds the whole run: rec_pos advances per chunk
     kAverage = 16,          // add the records to the thermal-average block sums acc[]
     kStencil = 32,          // neighbours in stencil form (pat_id / pat_tab) instead of SELL
+    kNoFar = 64,            // stencil form without far links (every neighbour in the LDS window)
 };
 
 template <typename R>

@@ -114,6 +114,12 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
         std::vector<uint16_t> start{0}, far;
         std::string key;
         bool ok = allow_stencil;
+        // Far parts are padded to kFarRegs entries (offset 0: never a real
+        // link, self links are rejected above) unless no row has far links.
+        bool any_far = false;
+        for (int64_t i = 0; i < n && !any_far; ++i)
+            any_far = n_near[(size_t)i] < row_ptr[i + 1] - row_ptr[i];
+        const size_t far_min = any_far ? (size_t)kFarRegs : 0;
         for (int64_t i = 0; i < n && ok; ++i) {
             key.clear();
             key.push_back((char)n_near[(size_t)i]);
@@ -134,7 +140,9 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
             if (it == ids.end()) {
                 const int id = (int)ids.size();
                 const size_t cnt = (key.size() - 1) / sizeof(int32_t);
-                if (id >= kMaxPatterns || tab.size() + cnt > (size_t)kMaxPatternEntries) {
+                const size_t n_far = cnt - (uint8_t)key[0];
+                const size_t pad = n_far < far_min ? far_min - n_far : 0;
+                if (id >= kMaxPatterns || tab.size() + cnt + pad > (size_t)kMaxPatternEntries) {
                     ok = false;
                     break;
                 }
@@ -145,6 +153,7 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
                     std::memcpy(&e, key.data() + 1 + c * sizeof(int32_t), sizeof(e));
                     tab.push_back(e);
                 }
+                tab.insert(tab.end(), pad, 0);
                 start.push_back((uint16_t)tab.size());
             }
             pid[(size_t)i] = (uint8_t)it->second;
@@ -155,6 +164,7 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
             s.pat_tab = std::move(tab);
             s.pat_start = std::move(start);
             s.pat_far = std::move(far);
+            s.no_far = !any_far;
             return s;
         }
     }
@@ -334,6 +344,8 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
         flags |= kPerSiteAxis;
     if (s.stencil)
         flags |= kStencil;
+    if (s.stencil && s.no_far)
+        flags |= kNoFar;
     rec.flags = flags;
     rec.n_patterns = s.stencil ? (int32_t)s.pat_start.size() - 1 : 0;
 }

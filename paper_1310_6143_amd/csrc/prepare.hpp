@@ -44,6 +44,7 @@ struct HostStructure {
     std::vector<int32_t> pat_tab;      // packed (col - row) << 4 | type
     std::vector<uint16_t> pat_start;   // [n_patterns + 1]
     std::vector<uint16_t> pat_far;     // [n_patterns] first far entry of each pattern
+    bool no_far = false;               // no pattern has a far link (no padding then)
 };
 
 // Sites per tile of this structure at a precision (see tile_request).
