@@ -1,0 +1,95 @@
+"""GPU parity at the edges: degenerate systems (one spin, two spins),
+ragged sizes that end mid-wavefront and mid-tile, and the full 8,192,000-spin
+bcc block in the launch configuration bench.py times.  Everything is checked
+against the FP64 oracle on the same inputs and noise stream.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1310_6143_amd as sl
+from spin_systems import bcc_block, single_spin
+from spin_systems.lattice import Lattice
+from spin_systems.workloads import GAMMA, MU_B, Workload
+from tests.gpu_util import max_angle
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(w, n_steps):
+    S = np.ascontiguousarray(w.S0.copy())
+    m, E = oracle.System(w).integrate(S, 0, n_steps)
+    return S, m, E
+
+
+def _gpu(w, n_steps, precision, **opts):
+    with sl.from_workload(w, precision=precision) as g:
+        for k, v in opts.items():
+            g.set_option(k, v)
+        m, E = g.integrate(n_steps)
+        return g.get_spins(), m, E
+
+
+def _ring(n, temperature=300.0, seed=5, J=6.0e-21):
+    """A periodic chain of n spins (two neighbours each), tilted start."""
+    i = np.arange(n)
+    col = np.stack([(i - 1) % n, (i + 1) % n], axis=1).astype(np.int32).ravel()
+    row_ptr = np.arange(0, 2 * n + 1, 2, dtype=np.int64)
+    lat = Lattice(f"ring {n}", np.stack([i, 0 * i, 0 * i], axis=1).astype(float), row_ptr, col,
+                  np.zeros(2 * n, dtype=np.uint8))
+    rng = np.random.default_rng(n)
+    S0 = np.tile([0.0, 0.0, 1.0], (n, 1)) + 0.3 * rng.standard_normal((n, 3))
+    S0 /= np.linalg.norm(S0, axis=1, keepdims=True)
+    return Workload(name=f"ring {n}", lattice=lat, J=np.array([J]), mu_s=np.full(n, 1.5 * MU_B),
+                    k_u=np.full(n, 1e-23), easy_axis=np.tile([0.0, 0.0, 1.0], (n, 1)), alpha=0.1,
+                    gamma=GAMMA, dt=1e-16, temperature=temperature, H=np.array([0.0, 0.2, -0.5]),
+                    seed=seed, n_steps=200, S0=S0)
+
+
+@pytest.mark.parametrize("temperature", [0.0, 300.0])
+def test_single_spin(temperature):
+    """One spin, no neighbours: anisotropy, field and noise only."""
+    w = single_spin(k_u=1e-23, H=(0.5, 0.0, 2.0), temperature=temperature, S0=(1.0, 0.2, 0.1),
+                    seed=9, dt=1e-16, n_steps=2000)
+    S_ref, m_ref, E_ref = _oracle(w, 2000)
+    S, m, E = _gpu(w, 2000, sl.FP64)
+    assert max_angle(S, S_ref) <= 1e-10
+    assert np.abs(m - m_ref).max() <= 1e-10
+    S32, m32, _ = _gpu(w, 2000, sl.FP32)
+    assert max_angle(S32, S_ref) <= 1e-3
+    assert np.abs(m32 - m_ref).max() <= 1e-3
+
+
+@pytest.mark.parametrize("n", [3, 63, 65, 511, 513, 2047, 2049, 4097])
+def test_ragged_ring_sizes(n):
+    """Systems ending mid-wavefront and mid-tile (tiles of 512 sites here)."""
+    w = _ring(n)
+    S_ref, m_ref, E_ref = _oracle(w, 200)
+    S, m, E = _gpu(w, 200, sl.FP64)
+    assert max_angle(S, S_ref) <= 1e-9
+    assert np.abs(m - m_ref).max() <= 1e-10
+    assert np.abs(E - E_ref).max() <= 1e-9 * np.abs(E_ref).max()
+    S32, _, _ = _gpu(w, 200, sl.FP32)
+    assert max_angle(S32, S_ref) <= 1e-3
+
+
+def test_full_size_block_matches_oracle():
+    """The 8,192,000-spin bcc J1+J2 block at its real size and in the default
+    launch configuration: 3 steps against the oracle (every site)."""
+    w = bcc_block(cells=160, n_steps=3)
+    rng = np.random.default_rng(11)
+    S0 = np.tile([0.0, 0.0, 1.0], (w.n, 1)) + 0.1 * rng.standard_normal((w.n, 3))
+    w.S0 = S0 / np.linalg.norm(S0, axis=1, keepdims=True)
+    S_ref, m_ref, E_ref = _oracle(w, 3)
+    # m and E are sums over 8.2M sites: the oracle adds them one by one, the
+    # GPU as a tree, so FP64 records agree to about N * eps = 1e-9
+    for prec, ang_tol, rec_tol in ((sl.FP64, 1e-10, 1e-9), (sl.FP32, 1e-5, 1e-6)):
+        with sl.from_workload(w, precision=prec, check_symmetry=False) as g:
+            assert g.get_option("tile_sites") == (2048 if prec == sl.FP32 else 1024)
+            m, E = g.integrate(3)
+            S = g.get_spins()
+        ang = max_angle(S, S_ref)
+        print(f"full block {'FP32' if prec == sl.FP32 else 'FP64'}: max angle {ang:.2e}")
+        assert ang <= ang_tol
+        assert np.abs(m - m_ref).max() <= rec_tol
+        assert np.abs(E - E_ref).max() <= rec_tol * np.abs(E_ref).max()
