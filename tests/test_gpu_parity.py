@@ -75,10 +75,10 @@ def test_sc4096_fp32_within_stated_bound():
 
 def test_ragged_sphere_per_site_axes_fp64():
     # a small fcc particle: ragged rows (3..12 neighbours), per-site materials
-    # and random easy axes, spans several 256-site blocks and a partial one
+    # and random easy axes, spans several 512-site tiles and a partial one
     w = fcc_nanoparticle(radius_nm=1.6, temperature=300.0)
     w.H = np.array([0.2, -0.1, 0.5])
-    assert w.n % 256 != 0 and w.n > 3 * 256
+    assert w.n % 512 != 0 and w.n > 3 * 512
     S_ref, m_ref, E_ref = _oracle_run(w, 300)
     S, m, E = _gpu_run(w, 300, sl.FP64)
     ang = max_angle(S, S_ref)
