@@ -167,14 +167,15 @@ sllg_status sllg_sweep_field(sllg_system *sys, const double *H, int64_t n_points
                              int64_t n_avg, int n_blocks, double *out, void *stream);
 
 /* Launch-shape autotuner: times every candidate launch configuration of the
- * step kernels ("tile_order" 1 or 0; XCD mappings 0, 1, 2 of "xcd_remap";
+ * step kernels ("lds_window" 1 or 0; "tile_order" 1 or 0; XCD mappings 0,
+ * 1, 2 of "xcd_remap";
  * 1/2, 1 or 2 resident grids of workgroups per launch; for systems under
  * 2^20 spins, 16, 64 or 256 steps per captured HIP graph), the best of two
  * runs of trial_steps (2..100000) steps of this system each, keeps the
  * fastest and writes its time per step (us) to *us_per_step (may be NULL).
  * The spins, the step counter and every result stay exactly as they were:
  * launch shapes do not change the arithmetic.  The choice can be read back
- * with sllg_get_option ("tile_order", "xcd_remap", "grid_scale_pct",
+ * with sllg_get_option ("lds_window", "tile_order", "xcd_remap", "grid_scale_pct",
  * "graph_steps", "tuned_ns_per_step").  Setting SLLG_AUTOTUNE_LOG=1 in the
  * environment prints every candidate's time to stderr. */
 sllg_status sllg_autotune(sllg_system *sys, int trial_steps, double *us_per_step, void *stream);
@@ -213,6 +214,11 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     and are still cached); 0 site order
  *   "tile_group"      tile columns per group for tile_order 1 (1..4096;
  *                     0, the default, sizes the groups from the L2 capacity)
+ *   "lds_window"      1 (default): a workgroup copies its tile's spins and a
+ *                     halo into LDS and reads near neighbours from there; 0:
+ *                     every neighbour and the site's own spin are read from
+ *                     global memory (can be faster for small, cache-resident
+ *                     systems).  Results are the same bit for bit.
  *   "tile_sites"      consecutive sites one workgroup integrates together:
  *                     0 (default) = from the system size (the largest tile,
  *                     2048 in FP32 / 1024 in FP64, halved down to 512 until

@@ -270,7 +270,7 @@ class SpinSystem:
         us = D()
         self._check(lib().sllg_autotune(self._h, int(trial_steps), ctypes.byref(us), _stream(stream)))
         return us.value, {k: self.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps",
-                                                          "tile_order")}
+                                                          "tile_order", "lds_window")}
 
     def measure(self):
         m = np.empty(3)

@@ -51,6 +51,7 @@ struct Engine {
     virtual void set_remap(int v) = 0;
     virtual void set_grid_scale(double f) = 0;
     virtual void set_tile_order(int order, int group) = 0;
+    virtual void set_window(bool on) = 0;
     virtual size_t spin_bytes() = 0;
     virtual void save_spins(void* dst, hipStream_t st) = 0;
     virtual void load_spins(const void* src, hipStream_t st) = 0;
@@ -106,6 +107,7 @@ struct EngineT final : Engine {
     void set_remap(int v) override { batch.set_remap(v); }
     void set_grid_scale(double f) override { batch.set_grid_scale(f); }
     void set_tile_order(int order, int group) override { batch.set_tile_order(order, group); }
+    void set_window(bool on) override { batch.set_window(on); }
     size_t spin_bytes() override { return 3 * (size_t)batch.mirror(q).n * sizeof(R); }
     void save_spins(void* dst, hipStream_t st) override { batch.save_spins(q, dst, st); }
     void load_spins(const void* src, hipStream_t st) override { batch.load_spins(q, src, st); }
@@ -144,6 +146,7 @@ struct sllg_system {
     int64_t opt_tile_order = 1;         // plane-swept column groups when a plane stride is found
     int64_t opt_tile_group = 0;         // tile columns per group, 0 = from the L2 size
     int64_t opt_tile_sites = 0;         // sites per tile, 0 = from the system size
+    int64_t opt_lds_window = 1;         // neighbours through the LDS tile window (1) or all from HBM (0)
     bool tuned = false;
     double tuned_us = 0.0;
     int64_t opt_stencil = 1;
@@ -213,6 +216,7 @@ Engine& engine(sllg_system* s)
         s->eng->set_remap((int)s->opt_xcd_remap);
         s->eng->set_grid_scale(s->opt_grid_scale_pct / 100.0);
         s->eng->set_tile_order((int)s->opt_tile_order, (int)s->opt_tile_group);
+        s->eng->set_window(s->opt_lds_window != 0);
     }
     hip_check(hipSetDevice(s->device), "hipSetDevice");
     return *s->eng;
@@ -383,17 +387,20 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
         int64_t scale_pct;
         int64_t graph;
         int64_t order;
+        int64_t window;
     };
     std::vector<Cand> cands;
     const bool small = s->n < (int64_t(1) << 20);
-    for (int64_t order : {1, 0})
-        for (int remap : {1, 2, 0})
-            for (int64_t scale : {100, 50, 200})
-                for (int64_t g : small ? std::vector<int64_t>{64, 16, 256} : std::vector<int64_t>{0})
-                    cands.push_back({remap, scale, g, order});
+    for (int64_t window : {1, 0})
+        for (int64_t order : {1, 0})
+            for (int remap : {1, 2, 0})
+                for (int64_t scale : {100, 50, 200})
+                    for (int64_t g : small ? std::vector<int64_t>{64, 16, 256} : std::vector<int64_t>{0})
+                        cands.push_back({remap, scale, g, order, window});
     hipEvent_t a = nullptr, b = nullptr;
     double best = 1e30;
-    Cand best_c = {(int)s->opt_xcd_remap, s->opt_grid_scale_pct, graph_steps(s), s->opt_tile_order};
+    Cand best_c = {(int)s->opt_xcd_remap, s->opt_grid_scale_pct, graph_steps(s), s->opt_tile_order,
+                   s->opt_lds_window};
     const int32_t flags0 = *r.flags;
     const char* log_env = std::getenv("SLLG_AUTOTUNE_LOG");   // print every candidate's time
     const bool log = log_env && *log_env && *log_env != '0';
@@ -409,9 +416,11 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
             s->opt_grid_scale_pct = c.scale_pct;
             s->opt_graph_steps = c.graph;
             s->opt_tile_order = c.order;
+            s->opt_lds_window = c.window;
             e.set_remap(c.remap);
             e.set_grid_scale(c.scale_pct / 100.0);
             e.set_tile_order((int)c.order, (int)s->opt_tile_group);
+            e.set_window(c.window != 0);
             const int steps = c.graph > 0 ? (int)std::max<int64_t>(c.graph, trial_steps) : trial_steps;
             run_steps(s, std::max<int64_t>(c.graph, 2), nullptr, nullptr, nullptr, nullptr, st, 0);  // warm
             double us = 1e30;
@@ -425,8 +434,11 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
                 us = std::min(us, 1e3 * ms / steps);
             }
             if (log)
-                std::fprintf(stderr, "[sllg autotune] xcd_remap %d grid %lld%% graph %lld tile_order %lld: %.1f us/step\n",
-                             c.remap, (long long)c.scale_pct, (long long)c.graph, (long long)c.order, us);
+                std::fprintf(stderr,
+                             "[sllg autotune] lds_window %lld xcd_remap %d grid %lld%% graph %lld tile_order %lld: "
+                             "%.1f us/step\n",
+                             (long long)c.window, c.remap, (long long)c.scale_pct, (long long)c.graph,
+                             (long long)c.order, us);
             if (us < best) {
                 best = us;
                 best_c = c;
@@ -455,9 +467,11 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
     s->opt_grid_scale_pct = best_c.scale_pct;
     s->opt_graph_steps = best_c.graph;
     s->opt_tile_order = best_c.order;
+    s->opt_lds_window = best_c.window;
     e.set_remap(best_c.remap);
     e.set_grid_scale(best_c.scale_pct / 100.0);
     e.set_tile_order((int)best_c.order, (int)s->opt_tile_group);
+    e.set_window(best_c.window != 0);
     s->tuned = true;
     s->tuned_us = best;
     return best;
@@ -871,6 +885,12 @@ sllg_status sllg_set_option(sllg_system* sys, const char* key, int64_t value)
                 sys->opt_tile_sites = value;
                 sys->st.tile_request = (int)value;
             }
+        } else if (k == "lds_window") {
+            if (value < 0 || value > 1)
+                fail(SLLG_E_ARG, "lds_window must be 0 or 1");
+            sys->opt_lds_window = value;
+            if (sys->eng)
+                sys->eng->set_window(value != 0);
         } else if (k == "tile_order") {
             if (value < 0 || value > 1)
                 fail(SLLG_E_ARG, "tile_order must be 0 or 1");
@@ -916,6 +936,8 @@ sllg_status sllg_get_option(const sllg_system* sys, const char* key, int64_t* va
         *value = sys->opt_xcd_remap;
     else if (k == "tile_order")
         *value = sys->opt_tile_order;
+    else if (k == "lds_window")
+        *value = sys->opt_lds_window;
     else if (k == "tile_group")
         *value = sys->opt_tile_group;
     else if (k == "stencil")

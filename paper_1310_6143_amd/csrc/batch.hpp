@@ -470,6 +470,8 @@ public:
         work_.clear();
         for (size_t q = 0; q < slots_.size(); ++q) {
             host_reps_[q] = slots_[q].used ? slots_[q].rec : ReplicaDev<R>{};
+            if (slots_[q].used && !window_)
+                host_reps_[q].flags |= kDirect;
             if (!slots_[q].used)
                 host_reps_[q].nsteps = 0;
             if (slots_[q].used && slots_[q].rec.nsteps > 0)
@@ -587,6 +589,15 @@ public:
         remap_ = v;
     }
     int remap() const { return remap_; }
+    // Neighbour spins through the LDS tile window (default) or all straight
+    // from global memory; results are the same bit for bit.
+    void set_window(bool on)
+    {
+        if (on != window_) {
+            window_ = on;
+            dirty_ = true;
+        }
+    }
     // Tile listing: 0 in site order, 1 plane-swept column groups of
     // `group` tiles (lattices with a detected plane stride); group 0 sizes
     // the groups from the L2 capacity.
@@ -682,6 +693,7 @@ private:
         return (pt + groups - 1) / groups;
     }
 
+    bool window_ = true;
     int order_ = 1;
     int group_ = 0;
     int64_t group_sites_ = 1 << 14;

@@ -378,13 +378,24 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
                 fr[q] = bload3(rs, ib + fp[q].off, R(0));
         }
         overlap();
-        SLLG_UNROLL(SLLG_NEAR_UNROLL)
-        for (int k = b; k < f; ++k) {
-            const PatEntry<R> pe = sh.pat[k];
-            const V3<R> sj = wload3(tl.win, wbyte + pe.off);
-            hn.x += pe.J * sj.x;
-            hn.y += pe.J * sj.y;
-            hn.z += pe.J * sj.z;
+        if (r.flags & kDirect) {   // same terms, same order, from global memory
+            SLLG_UNROLL(SLLG_GATHER_UNROLL)
+            for (int k = b; k < f; ++k) {
+                const PatEntry<R> pe = sh.pat[k];
+                const V3<R> sj = bload3(rs, ib + pe.off, R(0));
+                hn.x += pe.J * sj.x;
+                hn.y += pe.J * sj.y;
+                hn.z += pe.J * sj.z;
+            }
+        } else {
+            SLLG_UNROLL(SLLG_NEAR_UNROLL)
+            for (int k = b; k < f; ++k) {
+                const PatEntry<R> pe = sh.pat[k];
+                const V3<R> sj = wload3(tl.win, wbyte + pe.off);
+                hn.x += pe.J * sj.x;
+                hn.y += pe.J * sj.y;
+                hn.z += pe.J * sj.z;
+            }
         }
         if (far) {
 #pragma unroll
@@ -421,7 +432,8 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
         for (int k = 0; k < nn; ++k) {
             const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
             const R J = sh.jt[e >> kColBits];
-            const V3<R> sj = wload3(tl.win, site_bytes<R>((int)(e & kColMask) - wb));
+            const V3<R> sj = (r.flags & kDirect) ? load3(S, (int64_t)(e & kColMask))
+                                                 : wload3(tl.win, site_bytes<R>((int)(e & kColMask) - wb));
             hn.x += J * sj.x;
             hn.y += J * sj.y;
             hn.z += J * sj.z;
@@ -702,7 +714,7 @@ __device__ __forceinline__ void predict_sites(const ReplicaDev<R>& r, const R* _
             break;
         const MaterialDev<R> m = PS ? site_material(r, i) : m0;   // loaded before the gathers are issued
         const int wbyte = site_bytes<R>(l + r.halo);
-        const V3<R> s = wload3(tl.win, wbyte);
+        const V3<R> s = (r.flags & kDirect) ? load3(S, i) : wload3(tl.win, wbyte);
         R g[3] = {0, 0, 0};
         const V3<R> sum = exchange_sum(r, S, sh, tl, i, l, wb, wbyte, [&] {
             if (!MEASURE && m.sigma != (R)0)
@@ -758,7 +770,8 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
             stage_tables(r, sh);
             staged = w.replica;
         }
-        stage_window(S, r.n, wb, T + 2 * r.halo, tl.win);
+        if (!(r.flags & kDirect))
+            stage_window(S, r.n, wb, T + 2 * r.halo, tl.win);
         if (r.flags & kStencil)
             stage_ids(r.pat_id, r.n, i0, T, tl.pid);
         __syncthreads();
@@ -807,7 +820,7 @@ __device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* _
             break;
         const MaterialDev<R> m = PS ? site_material(r, i) : m0;   // loaded before the gathers are issued
         const int wbyte = site_bytes<R>(l + r.halo);
-        const V3<R> sp = wload3(tl.win, wbyte);
+        const V3<R> sp = (r.flags & kDirect) ? load3(Sp, i) : wload3(tl.win, wbyte);
         const V3<R> b = load3_once((const R*)r.Bc, i);
         R g[3] = {0, 0, 0};
         const V3<R> sum = exchange_sum(r, Sp, sh, tl, i, l, wb, wbyte, [&] {
@@ -849,7 +862,8 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
             stage_tables(r, sh);
             staged = w.replica;
         }
-        stage_window(Sp, r.n, wb, T + 2 * r.halo, tl.win);
+        if (!(r.flags & kDirect))
+            stage_window(Sp, r.n, wb, T + 2 * r.halo, tl.win);
         if (r.flags & kStencil)
             stage_ids(r.pat_id, r.n, i0, T, tl.pid);
         __syncthreads();

@@ -104,6 +104,7 @@ enum ReplicaFlags : int32_t {
     kAverage = 16,          // add the records to the thermal-average block sums acc[]
     kStencil = 32,          // neighbours in stencil form (pat_id / pat_tab) instead of SELL
     kNoFar = 64,            // stencil form without far links (every neighbour in the LDS window)
+    kDirect = 128,          // no LDS window: every neighbour and the own spin read from global memory
 };
 
 template <typename R>

@@ -187,6 +187,23 @@ def test_tile_order_does_not_change_results():
             assert np.array_equal(res[0][2], other[2])
 
 
+@pytest.mark.parametrize("make", [lambda: bcc_block(cells=24, n_steps=100),
+                                  lambda: fcc_nanoparticle(radius_nm=1.6, temperature=300.0)])
+def test_lds_window_does_not_change_results(make):
+    """Near neighbours through the LDS tile window or straight from global
+    memory: the same terms in the same order, so the same bits."""
+    w = make()
+    for prec in (sl.FP32, sl.FP64):
+        res = []
+        for window in (1, 0):
+            with sl.from_workload(w, precision=prec, check_symmetry=False) as g:
+                g.set_option("lds_window", window)
+                m, E = g.integrate(80)
+                res.append((g.get_spins(), m, E))
+        assert np.array_equal(res[0][0], res[1][0])
+        assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][2], res[1][2])
+
+
 def test_tile_size_changes_only_record_rounding():
     """Spin updates never depend on the tiling; the m/E records differ only
     by the FP64 summation order of their first reduction level."""
