@@ -10,7 +10,8 @@ standard errors), written in numpy.
 
 Paper passages: the section on the classical spin Hamiltonian (energy),
 "Spin Dynamics" and "Langevin Dynamics" (LLG and thermal field), "Time
-Integration of the LLG Equation" (Heun scheme), the temperature-dependent
+Integration of the LLG Equation" (Heun scheme), "Monte Carlo Methods"
+(Metropolis acceptance with Hinzke-Nowak trial moves, ``mc.c``), the temperature-dependent
 magnetisation protocol of the "Curie temperature" test (heating with the
 previous state as the next starting point), and the Stoner-Wohlfarth test
 (relaxation until the torque falls below 1e-6 T).
@@ -25,7 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["philox.c", "llg.c"]
+_SOURCES = ["philox.c", "llg.c", "mc.c"]
 KB = 1.3807e-23  # J/K, Table 1
 
 _lib = None
@@ -88,6 +89,13 @@ def lib():
         L.orc_llg_rhs.argtypes = [ctypes.c_double, ctypes.c_double, P, P, P]
         L.orc_neighbours.argtypes = [ctypes.c_int64, P, P, ctypes.c_int, P, P, P, P, P, ctypes.c_int64]
         L.orc_neighbours.restype = ctypes.c_int64
+        L.orc_greedy_colours.argtypes = [ctypes.c_int64, P, P, P]
+        L.orc_greedy_colours.restype = ctypes.c_int
+        L.orc_mc_cone_width.argtypes = [ctypes.c_double]
+        L.orc_mc_cone_width.restype = ctypes.c_double
+        L.orc_mc_choice.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, P, P]
+        L.orc_mc_run.argtypes = [ctypes.POINTER(_System), P, ctypes.c_uint64, ctypes.c_int64, P, P, P]
+        L.orc_mc_run.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -113,6 +121,32 @@ def gaussians(seed, step, sites, purpose=0):
     out = np.empty((sites.size, 3), dtype=np.float64)
     lib().orc_gaussian3_batch(int(seed), int(step), sites.size, _ptr(sites), int(purpose), _ptr(out))
     return out
+
+
+def greedy_colours(row_ptr, col):
+    """Colour of every site: the smallest colour no neighbour with a lower
+    index has.  Returns (colours int32 [n], number of colours)."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    n = row_ptr.size - 1
+    colour = np.zeros(max(n, 1), dtype=np.int32)
+    k = lib().orc_greedy_colours(n, _ptr(row_ptr), _ptr(col), _ptr(colour))
+    if k < 0:
+        raise MemoryError("oracle colouring failed")
+    return colour[:n], int(k)
+
+
+def mc_cone_width(temperature):
+    """Width of the Gaussian trial move, (2/25)(kB T/muB)^(1/5)."""
+    return float(lib().orc_mc_cone_width(float(temperature)))
+
+
+def mc_choice(seed, step, site):
+    """Move type (0 flip, 1 Gaussian, 2 random) and acceptance uniform."""
+    move = ctypes.c_uint32()
+    u = ctypes.c_double()
+    lib().orc_mc_choice(int(seed), int(step), int(site), ctypes.byref(move), ctypes.byref(u))
+    return int(move.value), float(u.value)
 
 
 def llg_rhs(gamma, alpha, spin, h):
@@ -197,6 +231,22 @@ class System:
             raise FloatingPointError(f"oracle integrate failed ({rc})")
         return m, E
 
+    def mc(self, S, step0, n_steps, record=True):
+        """Monte Carlo steps step0 .. step0+n_steps-1 (Hinzke-Nowak moves,
+        colour-class sweeps) in place on S.  Returns (m [n_steps, 3],
+        E [n_steps], accepted trials [n_steps]); m and E are None unless
+        record."""
+        assert S.dtype == np.float64 and S.flags.c_contiguous and S.shape == (self.n, 3)
+        m = np.empty((n_steps, 3)) if record else None
+        E = np.empty(n_steps) if record else None
+        acc = np.empty(n_steps, dtype=np.int64)
+        st = self._struct()
+        rc = lib().orc_mc_run(ctypes.byref(st), _ptr(S), int(step0), int(n_steps),
+                              _ptr(m) if record else None, _ptr(E) if record else None, _ptr(acc))
+        if rc != 0:
+            raise MemoryError(f"oracle Monte Carlo failed ({rc})")
+        return m, E, acc
+
     def energy(self, S):
         st = self._struct()
         return lib().orc_energy(ctypes.byref(st), _ptr(np.ascontiguousarray(S, dtype=np.float64)))
@@ -248,6 +298,19 @@ def average(sys: System, S, step0, n_eq, n_avg, n_blocks=10):
     mean_E, se_E = block_stats(E, n_blocks)
     out = {"m_abs": mean_abs, "m_abs_se": se_abs, "m": m.mean(axis=0), "E": mean_E,
            "E_se": se_E}
+    return out, step0 + n_eq + n_avg
+
+
+def mc_average(sys: System, S, step0, n_eq, n_avg, n_blocks=10):
+    """Monte Carlo counterpart of average(): n_eq steps to equilibrate, then
+    n_avg steps sampled after every step."""
+    sys.mc(S, step0, n_eq, record=False)
+    m, E, acc = sys.mc(S, step0 + n_eq, n_avg, record=True)
+    mabs = np.sqrt((m * m).sum(axis=1))
+    mean_abs, se_abs = block_stats(mabs, n_blocks)
+    mean_E, se_E = block_stats(E, n_blocks)
+    out = {"m_abs": mean_abs, "m_abs_se": se_abs, "m": m.mean(axis=0), "E": mean_E,
+           "E_se": se_E, "acceptance": float(acc.sum()) / (sys.n * n_avg)}
     return out, step0 + n_eq + n_avg
 
 

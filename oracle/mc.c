@@ -1,0 +1,162 @@
+/*
+ * Monte Carlo Metropolis sampling of the classical spin Hamiltonian with the
+ * Hinzke-Nowak mixture of trial moves (section "Monte Carlo Methods").
+ * TEST INFRASTRUCTURE ONLY (see sllg_oracle.h).
+ *
+ * A trial on spin i draws one of three moves with equal probability:
+ * reversal S' = -S, a Gaussian move S' = |S + sigma_g Gamma| with the cone
+ * width sigma_g = (2/25)(kB T/muB)^(1/5), or a uniform point on the sphere
+ * S' = Gamma/|Gamma|.  It is accepted with probability exp(-dE/(kB T)),
+ * unconditionally when dE <= 0.
+ *
+ * The paper picks the N trial sites of one Monte Carlo step at random.
+ * Here a step visits every site once, colour class by colour class of a
+ * greedy colouring of the neighbour graph (ascending colour, ascending site
+ * within a colour).  Sites of one colour share no link, so their trials do
+ * not interact and the order within a class is immaterial; every single
+ * trial satisfies detailed balance, so the chain samples the same Boltzmann
+ * distribution.  Random numbers are counter-based like the thermal field:
+ * the Gaussian numbers of site i at Monte Carlo step k come from Philox
+ * counter (i, k lo, k hi, 2), the move choice and the acceptance uniform
+ * from counter (i, k lo, k hi, 3).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#include "sllg_oracle.h"
+
+static double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+int orc_greedy_colours(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t *colour)
+{
+    int n_colours = 0;
+    /* a site has at most (row length) coloured neighbours, so a free colour
+     * exists among the first (row length + 1) */
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t deg = row_ptr[i + 1] - row_ptr[i];
+        char *used = (char *)calloc((size_t)deg + 1, 1);
+        if (!used)
+            return -1;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const int64_t j = col[k];
+            if (j < i && colour[j] <= deg)
+                used[colour[j]] = 1;
+        }
+        int c = 0;
+        while (used[c])
+            ++c;
+        free(used);
+        colour[i] = c;
+        if (c + 1 > n_colours)
+            n_colours = c + 1;
+    }
+    return n_colours;
+}
+
+double orc_mc_cone_width(double temperature)
+{
+    return 2.0 / 25.0 * pow(ORC_KB * temperature / ORC_MUB, 0.2);
+}
+
+void orc_mc_choice(uint64_t seed, uint64_t step, uint64_t site, uint32_t *move, double *u)
+{
+    const uint32_t ctr[4] = {(uint32_t)site, (uint32_t)step, (uint32_t)(step >> 32), 3u};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    *move = (uint32_t)(((uint64_t)r[0] * 3u) >> 32);   /* 0, 1 or 2, each with probability 1/3 */
+    *u = (double)r[1] * (1.0 / 4294967296.0);          /* uniform in [0, 1) */
+}
+
+/* Energy of spin i's terms when it points along x, with the neighbours as
+ * they are: -x.(sum_j J_ij S_j) - k_u (x.e)^2 - mu_s x.H. */
+static double site_energy(const orc_system *s, const double *S, int64_t i, const double x[3])
+{
+    double sum[3] = {0.0, 0.0, 0.0};
+    for (int64_t k = s->row_ptr[i]; k < s->row_ptr[i + 1]; ++k) {
+        const double J = s->J[s->ntype ? s->ntype[k] : 0];
+        const double *sj = S + 3 * (int64_t)s->col[k];
+        sum[0] += J * sj[0];
+        sum[1] += J * sj[1];
+        sum[2] += J * sj[2];
+    }
+    const double xe = dot3(x, s->easy_axis + 3 * i);
+    return -dot3(x, sum) - s->k_u[i] * xe * xe - s->mu_s[i] * dot3(x, s->H);
+}
+
+int orc_mc_trial(const orc_system *s, double *S, int64_t i, uint64_t step)
+{
+    double *si = S + 3 * i;
+    uint32_t move;
+    double u, g[3], trial[3];
+    orc_mc_choice(s->seed, step, (uint64_t)i, &move, &u);
+    orc_gaussian3(s->seed, step, (uint64_t)i, 2u, g);
+    if (move == 0) {            /* spin flip */
+        trial[0] = -si[0];
+        trial[1] = -si[1];
+        trial[2] = -si[2];
+    } else {
+        if (move == 1) {        /* Gaussian move in a cone around S */
+            const double w = orc_mc_cone_width(s->temperature);
+            for (int c = 0; c < 3; ++c)
+                trial[c] = si[c] + w * g[c];
+        } else {                /* uniform on the sphere */
+            for (int c = 0; c < 3; ++c)
+                trial[c] = g[c];
+        }
+        const double len = sqrt(dot3(trial, trial));
+        if (!(len > 0.0))
+            return 0;
+        trial[0] /= len;
+        trial[1] /= len;
+        trial[2] /= len;
+    }
+    const double dE = site_energy(s, S, i, trial) - site_energy(s, S, i, si);
+    int accept = dE <= 0.0;
+    if (!accept && s->temperature > 0.0)
+        accept = u < exp(-dE / (ORC_KB * s->temperature));
+    if (accept) {
+        si[0] = trial[0];
+        si[1] = trial[1];
+        si[2] = trial[2];
+    }
+    return accept;
+}
+
+int64_t orc_mc_step(const orc_system *s, double *S, const int32_t *colour, int n_colours, uint64_t step)
+{
+    int64_t accepted = 0;
+    for (int c = 0; c < n_colours; ++c)
+        for (int64_t i = 0; i < s->n; ++i)
+            if (colour[i] == c)
+                accepted += orc_mc_trial(s, S, i, step);
+    return accepted;
+}
+
+int orc_mc_run(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, double *m_out,
+               double *E_out, int64_t *accepted_out)
+{
+    int32_t *colour = (int32_t *)malloc(sizeof(int32_t) * (size_t)(s->n > 0 ? s->n : 1));
+    if (!colour)
+        return -2;
+    const int n_colours = orc_greedy_colours(s->n, s->row_ptr, s->col, colour);
+    if (n_colours < 0) {
+        free(colour);
+        return -2;
+    }
+    for (int64_t t = 0; t < n_steps; ++t) {
+        const int64_t acc = orc_mc_step(s, S, colour, n_colours, step0 + (uint64_t)t);
+        if (accepted_out)
+            accepted_out[t] = acc;
+        if (m_out)
+            orc_magnetisation(s, S, m_out + 3 * t);
+        if (E_out)
+            E_out[t] = orc_energy(s, S);
+    }
+    free(colour);
+    return 0;
+}

@@ -1,7 +1,8 @@
 /*
  * sllg_oracle.h -- plain, single-threaded FP64 reference implementation of
  * the stochastic Landau-Lifshitz-Gilbert (sLLG) spin dynamics integrated
- * with the Heun predictor-corrector scheme, as described in Evans et al.,
+ * with the Heun predictor-corrector scheme, and of Metropolis Monte Carlo
+ * with Hinzke-Nowak trial moves, as described in Evans et al.,
  * "Atomistic spin model simulations of magnetic nanomaterials"
  * (J. Phys.: Condens. Matter 26, 103202 (2014); arXiv:1310.6143).
  *
@@ -24,8 +25,9 @@
 extern "C" {
 #endif
 
-/* Boltzmann constant, Table 1 of the paper (J/K). */
+/* Boltzmann constant and Bohr magneton, Table 1 of the paper. */
 #define ORC_KB 1.3807e-23
+#define ORC_MUB 9.2740e-24
 
 /* A spin system in the form the Hamiltonian section writes it.
  * Every per-site array has n entries (easy_axis has 3n).  The neighbour
@@ -90,6 +92,26 @@ int orc_integrate(const orc_system *s, double *S, uint64_t step0, int64_t n_step
 int64_t orc_relax(const orc_system *s, double *S, double torque_tol, int64_t max_steps,
                   uint64_t step0);
 double orc_max_torque(const orc_system *s, const double *S);
+
+/* Monte Carlo ("Monte Carlo Methods", Hinzke-Nowak moves; see mc.c for the
+ * colour-class sweep order and the random-number layout).
+ * orc_greedy_colours: colour[i] = the smallest colour not taken by a
+ * neighbour j < i; returns the number of colours (-1 on allocation failure).
+ * orc_mc_cone_width: sigma_g = (2/25)(kB T/muB)^(1/5).
+ * orc_mc_choice: move type (0 flip, 1 Gaussian, 2 random) and acceptance
+ * uniform of (site, step).
+ * orc_mc_trial: one trial on spin i at Monte Carlo step `step`; returns 1
+ * when accepted.  orc_mc_step: one step (every site once, colour by colour);
+ * returns the number of accepted trials.  orc_mc_run: n_steps steps
+ * numbered step0, step0+1, ...; m, E and the accepted count after each
+ * step go to the arrays that are not NULL.  Returns 0 or -2. */
+int orc_greedy_colours(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t *colour);
+double orc_mc_cone_width(double temperature);
+void orc_mc_choice(uint64_t seed, uint64_t step, uint64_t site, uint32_t *move, double *u);
+int orc_mc_trial(const orc_system *s, double *S, int64_t i, uint64_t step);
+int64_t orc_mc_step(const orc_system *s, double *S, const int32_t *colour, int n_colours, uint64_t step);
+int orc_mc_run(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, double *m_out,
+               double *E_out, int64_t *accepted_out);
 
 /* Brute-force neighbour search over all pairs (minimum image on the axes
  * with box[a] > 0).  A pair at distance r with shell_lo[t] <= r <= shell_hi[t]

@@ -1,0 +1,128 @@
+"""Pins for the oracle's Monte Carlo ("Monte Carlo Methods": Metropolis
+acceptance, Hinzke-Nowak flip / Gaussian / random trial moves), each against
+something other than the oracle's own formulas:
+
+- the colouring is proper (no link inside a colour class) and greedy, by
+  brute force over every link;
+- the move choice and the acceptance uniform have the distributions the
+  counter layout promises;
+- a single spin samples the Boltzmann distribution: with uniaxial
+  anisotropy the <cos^2 theta> integral ("Boltzmann distribution for a
+  single spin"), in an applied field the Langevin function coth x - 1/x;
+- at T = 0 no accepted trial raises the energy;
+- the paper's simple-cubic M(T) fit (Tc = 631.82 K, beta = 0.334297 for
+  J = 6.0e-21 J/link) and agreement with the stochastic LLG oracle at the
+  same temperature (the paper's Monte Carlo vs LLG comparison).
+"""
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+from spin_systems import MU_B, bcc, bcc_film, fcc_nanoparticle, sc_reference, simple_cubic, single_spin
+
+KB = 1.3807e-23
+
+
+def _check_colouring(orc, row_ptr, col):
+    colour, k = orc.greedy_colours(row_ptr, col)
+    n = row_ptr.size - 1
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    assert np.all(colour[rows] != colour[col]), "a link joins two sites of one colour"
+    assert colour.min() >= 0 and colour.max() == k - 1
+    # greedy: every smaller colour is taken by an earlier neighbour
+    for i in range(min(n, 3000)):
+        nb = col[row_ptr[i]:row_ptr[i + 1]]
+        taken = set(colour[nb[nb < i]].tolist())
+        assert all(c in taken for c in range(colour[i]))
+    return k
+
+
+def test_colouring_is_proper_and_greedy(orc):
+    sc = simple_cubic((6, 6, 6), (True, True, True))
+    assert _check_colouring(orc, sc.row_ptr, sc.col) == 2    # even periodic sc: a checkerboard
+    b = bcc((4, 4, 4), (True, True, True), second_neighbours=True)
+    k = _check_colouring(orc, b.row_ptr, b.col)
+    assert k <= 15
+    f = bcc_film(nx=6, ny=6, nz=4).lattice
+    _check_colouring(orc, f.row_ptr, f.col)
+    s = fcc_nanoparticle(radius_nm=1.2).lattice
+    _check_colouring(orc, s.row_ptr, s.col)
+
+
+def test_move_choice_and_acceptance_uniform(orc):
+    draws = [orc.mc_choice(7, 123, i) for i in range(60000)]
+    moves = np.array([d[0] for d in draws])
+    u = np.array([d[1] for d in draws])
+    counts = np.bincount(moves, minlength=3)
+    assert counts.size == 3
+    assert stats.chisquare(counts).pvalue > 1e-4
+    assert stats.kstest(u, "uniform").pvalue > 1e-4
+    assert u.min() >= 0.0 and u.max() < 1.0
+    # the move choice and the uniform are independent
+    assert abs(np.corrcoef(moves, u)[0, 1]) < 0.03
+
+
+def _single_spin_samples(orc, w, n_steps):
+    s = orc.System(w)
+    S = w.S0.copy()
+    s.mc(S, 0, 2000, record=False)
+    m, _, _ = s.mc(S, 2000, n_steps)
+    return m[:, 2]
+
+
+@pytest.mark.parametrize("xi", [1.0, 3.0, 10.0])
+def test_mc_boltzmann_uniaxial(orc, xi):
+    ku = 1e-23
+    w = single_spin(mu_s=1.5 * MU_B, k_u=ku, temperature=ku / (KB * xi), S0=(0, 0, 1), seed=21)
+    cz = _single_spin_samples(orc, w, 400_000)
+    mean, se = orc.block_stats(cz ** 2, 40)
+    num = integrate.quad(lambda t: np.cos(t) ** 2 * np.sin(t) * np.exp(xi * np.cos(t) ** 2), 0, np.pi)[0]
+    den = integrate.quad(lambda t: np.sin(t) * np.exp(xi * np.cos(t) ** 2), 0, np.pi)[0]
+    assert abs(mean - num / den) < 4 * se + 2e-3, (mean, se, num / den)
+
+
+@pytest.mark.parametrize("x", [0.5, 2.0, 5.0])
+def test_mc_langevin_function_in_a_field(orc, x):
+    """No anisotropy, field along +z: <cos theta> = coth(x) - 1/x with
+    x = mu_s H / (kB T)."""
+    mu, T = 1.5 * MU_B, 50.0
+    H = x * KB * T / mu
+    w = single_spin(mu_s=mu, k_u=0.0, H=(0.0, 0.0, H), temperature=T, S0=(1, 0, 0), seed=22)
+    cz = _single_spin_samples(orc, w, 400_000)
+    mean, se = orc.block_stats(cz, 40)
+    assert abs(mean - (1.0 / np.tanh(x) - 1.0 / x)) < 4 * se + 2e-3, (mean, se)
+
+
+def test_mc_at_zero_temperature_never_raises_the_energy(orc):
+    w = sc_reference(L=6, temperature=0.0, seed=4)
+    rng = np.random.default_rng(0)
+    S = rng.standard_normal((w.n, 3))
+    S /= np.linalg.norm(S, axis=1, keepdims=True)
+    s = orc.System(w)
+    E0 = s.energy(S)
+    _, E, acc = s.mc(S, 0, 50)
+    assert E[0] <= E0 and np.all(np.diff(E) <= 1e-30)
+    assert acc.sum() > 0 and E[-1] < E0
+
+
+@pytest.mark.parametrize("T", [300.0, 400.0])
+def test_mc_matches_paper_sc_magnetisation_fit(orc, T):
+    """The paper fits its simple-cubic M(T) (J = 6.0e-21 J/link) with
+    m = (1 - T/Tc)^beta, Tc = 631.82 K, beta = 0.334297."""
+    w = sc_reference(L=12, temperature=T, seed=3)
+    r, _ = orc.mc_average(orc.System(w), w.S0.copy(), 0, 1000, 3000, 10)
+    fit = (1.0 - T / 631.82) ** 0.334297
+    assert abs(r["m_abs"] - fit) < 0.03, (r["m_abs"], fit)
+    assert 0.1 < r["acceptance"] < 0.9
+
+
+def test_mc_agrees_with_llg_at_equilibrium(orc):
+    """Monte Carlo and Langevin dynamics sample the same equilibrium
+    (the paper's Monte Carlo vs LLG comparison)."""
+    T = 400.0
+    w = sc_reference(L=8, temperature=T, seed=6)
+    w.alpha = 1.0
+    mc, _ = orc.mc_average(orc.System(w), w.S0.copy(), 0, 2000, 20000, 20)
+    llg, _ = orc.average(orc.System(w), w.S0.copy(), 0, 20000, 200000, 20)
+    tol = 4 * np.hypot(mc["m_abs_se"], llg["m_abs_se"]) + 5e-3
+    assert abs(mc["m_abs"] - llg["m_abs"]) < tol, (mc, llg)
