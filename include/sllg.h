@@ -142,6 +142,25 @@ sllg_status sllg_integrate(sllg_system *sys, int64_t n_steps, double *m_out, dou
 sllg_status sllg_integrate_dev(sllg_system *sys, int64_t n_steps, double *m_dev, double *E_dev,
                                void *stream);
 
+/* Monte Carlo (section "Monte Carlo Methods"): n_steps >= 0 Metropolis
+ * steps at the current temperature, field and materials.  A step makes one
+ * trial on every site, colour class by colour class of a greedy colouring
+ * of the neighbour graph (site i takes the smallest colour no neighbour
+ * j < i has; sites of one class share no link, so their trials are made at
+ * once).  A trial picks, with probability 1/3 each, a spin flip S' = -S, a
+ * Gaussian move S' = |S + sigma_g Gamma| with sigma_g = (2/25)(kB T/muB)^(1/5),
+ * or a uniform point on the sphere S' = Gamma/|Gamma| (Hinzke and Nowak),
+ * and accepts it if dE <= 0, else if u < exp(-dE/(kB T)).  Random numbers
+ * of site i at step k: Gamma from Philox counter (i, k lo, k hi, 2) with
+ * Box-Muller as for the thermal field; the move (floor(3 r0 / 2^32)) and u
+ * (r1 / 2^32) from counter (i, k lo, k hi, 3).  Steps are numbered by, and
+ * advance, the same step counter as the LLG steps.  After every step m and
+ * E go to m_out / E_out and the number of accepted trials to
+ * accepted_out[t], for the pointers that are not NULL.  The FP64 path
+ * takes every decision in double precision, the FP32 path in single. */
+sllg_status sllg_mc(sllg_system *sys, int64_t n_steps, double *m_out, double *E_out,
+                    int64_t *accepted_out, void *stream);
+
 /* Observables of the current state: m[3] and E (either may be NULL). */
 sllg_status sllg_measure(sllg_system *sys, double m[3], double *E, void *stream);
 

@@ -52,6 +52,9 @@ struct Engine {
     virtual void set_grid_scale(double f) = 0;
     virtual void set_tile_order(int order, int group) = 0;
     virtual void set_window(bool on) = 0;
+    virtual void mc_sweep(uint64_t step, double cone, double inv_kT, unsigned long long* accepted,
+                          hipStream_t st) = 0;
+    virtual void record_current(int slot, hipStream_t st) = 0;
     virtual size_t spin_bytes() = 0;
     virtual void save_spins(void* dst, hipStream_t st) = 0;
     virtual void load_spins(const void* src, hipStream_t st) = 0;
@@ -108,6 +111,12 @@ struct EngineT final : Engine {
     void set_grid_scale(double f) override { batch.set_grid_scale(f); }
     void set_tile_order(int order, int group) override { batch.set_tile_order(order, group); }
     void set_window(bool on) override { batch.set_window(on); }
+    void mc_sweep(uint64_t step, double cone, double inv_kT, unsigned long long* accepted,
+                  hipStream_t st) override
+    {
+        batch.mc_sweep(q, step, cone, inv_kT, accepted, st);
+    }
+    void record_current(int slot, hipStream_t st) override { batch.record_current(slot, st); }
     size_t spin_bytes() override { return 3 * (size_t)batch.mirror(q).n * sizeof(R); }
     void save_spins(void* dst, hipStream_t st) override { batch.save_spins(q, dst, st); }
     void load_spins(const void* src, hipStream_t st) override { batch.load_spins(q, src, st); }
@@ -313,6 +322,80 @@ void run_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, do
     }
     if (bad)
         fail(SLLG_E_NUMERIC, "the energy became non-finite during integration");
+}
+
+// Monte Carlo steps ("Monte Carlo Methods"): each step sweeps every colour
+// class once; records of m and E after each step, accepted trials per step.
+void mc_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, int64_t* acc_out,
+              hipStream_t st)
+{
+    Engine& e = engine(s);
+    ReplicaDevBase& r = e.rec();
+    const bool record = m_out || E_out;
+    const double T = s->dyn.temperature;
+    const double cone = 2.0 / 25.0 * std::pow(kBoltzmann * T / kBohrMagneton, 0.2);
+    const double inv_kT = T > 0.0 ? 1.0 / (kBoltzmann * T) : 0.0;
+    const int64_t chunk = std::min<int64_t>(kHostChunk, e.rec_cap());
+    const int32_t saved_flags = *r.flags;
+    const int32_t saved_nsteps = *r.nsteps;
+    // the measuring pass sweeps the replica's tiles: it takes part with nsteps 1
+    *r.flags = (saved_flags & ~(kRecord | kRecordSeries | kAverage)) | (record ? kRecord : 0);
+    *r.nsteps = 1;
+    *r.rec_pos = 0;
+    e.mark_dirty();
+    unsigned long long* d_acc = nullptr;
+    hip_check(hipMalloc(&d_acc, sizeof(unsigned long long) * (size_t)chunk), "hipMalloc(accepted)");
+    std::vector<unsigned long long> acc((size_t)chunk);
+    const uint64_t step0 = e.step();
+    bool bad = false;
+    try {
+        for (int64_t done = 0; done < n_steps;) {
+            const int64_t ns = std::min<int64_t>(chunk, n_steps - done);
+            hip_check(hipMemsetAsync(d_acc, 0, sizeof(unsigned long long) * (size_t)ns, st), "clear counts");
+            for (int64_t t = 0; t < ns; ++t) {
+                e.mc_sweep(step0 + (uint64_t)(done + t), cone, inv_kT, d_acc + t, st);
+                if (record)
+                    e.record_current((int)t, st);
+            }
+            hip_check(hipMemcpyAsync(acc.data(), d_acc, sizeof(unsigned long long) * (size_t)ns,
+                                     hipMemcpyDeviceToHost, st),
+                      "download counts");
+            if (record) {
+                s->staging.resize(4 * (size_t)ns);
+                hip_check(hipMemcpyAsync(s->staging.data(), *r.records, 32 * (size_t)ns, hipMemcpyDeviceToHost,
+                                         st),
+                          "download records");
+            }
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            for (int64_t t = 0; t < ns; ++t) {
+                if (acc_out)
+                    acc_out[done + t] = (int64_t)acc[(size_t)t];
+                if (!record)
+                    continue;
+                const double* rec = &s->staging[4 * (size_t)t];
+                if (m_out) {
+                    m_out[3 * (done + t)] = rec[0];
+                    m_out[3 * (done + t) + 1] = rec[1];
+                    m_out[3 * (done + t) + 2] = rec[2];
+                }
+                if (E_out)
+                    E_out[done + t] = rec[3];
+                if (!std::isfinite(rec[3]))
+                    bad = true;
+            }
+            done += ns;
+        }
+    } catch (...) {
+        (void)hipFree(d_acc);
+        throw;
+    }
+    (void)hipFree(d_acc);
+    *r.flags = saved_flags;
+    *r.nsteps = saved_nsteps;
+    e.set_step(step0 + (uint64_t)n_steps);
+    e.mark_dirty();
+    if (bad)
+        fail(SLLG_E_NUMERIC, "the energy became non-finite during Monte Carlo");
 }
 
 void measure_state(sllg_system* s, double m[3], double* E, hipStream_t st)
@@ -563,6 +646,7 @@ sllg_status sllg_set_neighbours(sllg_system* sys, const int64_t* row_ptr, const 
         HostStructure st = build_structure(sys->n, row_ptr, col, ntype, J, n_types,
                                            sys->opt_check_symmetry != 0, kHaloCap, sys->opt_stencil != 0);
         st.tile_request = (int)sys->opt_tile_sites;
+        build_colours(st, row_ptr, col);
         drop_engine(sys);
         sys->st = std::move(st);
         sys->has_nb = true;
@@ -701,6 +785,17 @@ sllg_status sllg_integrate_dev(sllg_system* sys, int64_t n_steps, double* m_dev,
 sllg_status sllg_measure(sllg_system* sys, double m[3], double* E, void* stream)
 {
     return guard(sys, [&] { measure_state(sys, m, E, pick_stream(sys, stream)); });
+}
+
+sllg_status sllg_mc(sllg_system* sys, int64_t n_steps, double* m_out, double* E_out, int64_t* accepted_out,
+                    void* stream)
+{
+    return guard(sys, [&] {
+        if (n_steps < 0)
+            fail(SLLG_E_ARG, "n_steps must be >= 0");
+        if (n_steps > 0)
+            mc_steps(sys, n_steps, m_out, E_out, accepted_out, pick_stream(sys, stream));
+    });
 }
 
 sllg_status sllg_average(sllg_system* sys, int64_t n_eq, int64_t n_avg, int n_blocks, double out[8],

@@ -142,6 +142,8 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
         b += r(pad16(n)) + r(s.pat_tab.size() * 4) + r(s.pat_start.size() * 2) + r(s.pat_far.size() * 2);
     else
         b += r(s.nb.size() * 4) + r(s.slice_off.size() * 8) + r(2 * n);
+    if (!s.colour_sites.empty())
+        b += r(4 * n);
     if (m.per_site_material)
         b += r(n);
     if (m.per_site_axis)
@@ -220,6 +222,8 @@ public:
         int avg_cap = 0;
         size_t bytes = 0;
         int plane_tiles = 0;     // see plane_tiles()
+        int32_t* d_colour = nullptr;            // Monte Carlo: sites by colour class
+        std::vector<int64_t> colour_start;      // [n_colours + 1]
     };
 
     Batch(int device, Allocator* alloc, int max_replicas)
@@ -384,6 +388,12 @@ public:
             set_spins(q, S0);
             sl.bytes = replica_bytes(s, m, sizeof(R), sl.rec_cap, sl.avg_cap);
             sl.plane_tiles = plane_tiles(s, (int)tile);
+            if (!s.colour_sites.empty()) {
+                sl.d_colour = (int32_t*)get(4 * n);
+                hip_check(hipMemcpy(sl.d_colour, s.colour_sites.data(), 4 * n, hipMemcpyHostToDevice),
+                          "upload colour classes");
+                sl.colour_start = s.colour_start;
+            }
             sl.used = true;
         } catch (...) {
             for (void* p : sl.mem)
@@ -550,6 +560,35 @@ public:
         }
     }
 
+    // Monte Carlo: one sweep (every colour class in turn) over replica q's
+    // current state, numbered `step` for the random-number counters.
+    void mc_sweep(int q, uint64_t step, double cone, double inv_kT, unsigned long long* accepted, hipStream_t st)
+    {
+        sync_tables();
+        last_stream_ = st;
+        const Slot& sl = slots_[q];
+        if (!sl.d_colour)
+            fail(SLLG_E_STATE, "the replica has no colour classes");
+        for (size_t c = 0; c + 1 < sl.colour_start.size(); ++c)
+            hip_check(launch_mc<R>(d_reps_ + q, sl.d_colour + sl.colour_start[c],
+                                   (int)(sl.colour_start[c + 1] - sl.colour_start[c]), step, cone, inv_kT,
+                                   accepted, st),
+                      "Monte Carlo sweep");
+    }
+
+    // m and E of the current state of every recording replica that takes
+    // part in the work list into record slot `slot`.
+    void record_current(int slot, hipStream_t st)
+    {
+        sync_tables();
+        last_stream_ = st;
+        if (grid_ <= 0)
+            return;
+        hip_check(launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 1, remap_, true, per_site_, st),
+                  "measure");
+        hip_check(launch_finish<R>(d_reps_, (int)slots_.size(), 1, slot, st), "finish record");
+    }
+
     // m and E of every recording replica's current state into records[rec_pos].
     void measure_now(hipStream_t st)
     {
@@ -574,7 +613,7 @@ public:
         if (e == hipSuccess)
             e = launch_predict<R>(d_reps_, d_all, d_n, n, 1, 0, true, per_site_, st);
         if (e == hipSuccess)
-            e = launch_finish<R>(d_reps_, (int)slots_.size(), 1, st);
+            e = launch_finish<R>(d_reps_, (int)slots_.size(), 1, 0, st);
         if (e == hipSuccess)
             e = hipStreamSynchronize(st);
         (void)hipFree(d_all);
@@ -650,7 +689,7 @@ private:
         if (e == hipSuccess)
             e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 0, remap_, true, per_site_, st);
         if (e == hipSuccess)
-            e = launch_finish<R>(d_reps_, nrep, 0, st);
+            e = launch_finish<R>(d_reps_, nrep, 0, 0, st);
         if (e == hipSuccess)
             e = launch_accumulate<R>(d_reps_, nrep, st);
         if (e == hipSuccess)

@@ -96,13 +96,14 @@ __device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c
 }
 
 // Three standard normals for (site, step): counter (site, step lo, step hi,
-// 0), key = seed; Box-Muller on the pairs (r0, r1) and (r2, r3), the fourth
-// normal dropped.  Uniforms u = (r + 1) 2^-32 in (0, 1] for the radius,
+// purpose), key = seed (purpose 0: the thermal field, 2: Monte Carlo trial
+// moves); Box-Muller on the pairs (r0, r1) and (r2, r3), the fourth normal
+// dropped.  Uniforms u = (r + 1) 2^-32 in (0, 1] for the radius,
 // u' = r 2^-32 in [0, 1) for the angle.
 __device__ __forceinline__ void thermal_normals(uint64_t seed, uint64_t step, uint32_t site,
-                                                float g[3])
+                                                float g[3], uint32_t purpose = 0u)
 {
-    uint32_t c0 = site, c1 = (uint32_t)step, c2 = (uint32_t)(step >> 32), c3 = 0u;
+    uint32_t c0 = site, c1 = (uint32_t)step, c2 = (uint32_t)(step >> 32), c3 = purpose;
     philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
     const float two_m32 = 2.3283064365386963e-10f;   // 2^-32
     const float u1 = ((float)c0 + 1.0f) * two_m32;
@@ -118,9 +119,9 @@ __device__ __forceinline__ void thermal_normals(uint64_t seed, uint64_t step, ui
 }
 
 __device__ __forceinline__ void thermal_normals(uint64_t seed, uint64_t step, uint32_t site,
-                                                double g[3])
+                                                double g[3], uint32_t purpose = 0u)
 {
-    uint32_t c0 = site, c1 = (uint32_t)step, c2 = (uint32_t)(step >> 32), c3 = 0u;
+    uint32_t c0 = site, c1 = (uint32_t)step, c2 = (uint32_t)(step >> 32), c3 = purpose;
     philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
     const double two_m32 = 2.3283064365386963e-10;
     const double u1 = ((double)c0 + 1.0) * two_m32;
@@ -877,11 +878,12 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
     }
 }
 
-// The last record of a chunk (mode 0) or the current state's (mode 1): all
-// groups, then the total, by one workgroup per replica, in the same order
-// as the per-step path.
+// The last record of a chunk (mode 0) or the current state's (mode 1, into
+// record slot `slot`): all groups, then the total, by one workgroup per
+// replica, in the same order as the per-step path.
 template <typename R>
-__global__ __launch_bounds__(kBlockThreads) void k_finish(const ReplicaDev<R>* __restrict__ reps, int mode)
+__global__ __launch_bounds__(kBlockThreads) void k_finish(const ReplicaDev<R>* __restrict__ reps, int mode,
+                                                          int slot)
 {
     __shared__ double red[4][kWaves];
     const ReplicaDev<R>& r = reps[blockIdx.x];
@@ -892,7 +894,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_finish(const ReplicaDev<R>* _
         group_reduce(r, g, red);
     __threadfence_block();
     __syncthreads();
-    final_reduce(r, mode == 0 ? r.nsteps - 1 : 0, red);
+    final_reduce(r, mode == 0 ? r.nsteps - 1 : slot, red);
 }
 
 // End of a chunk: advance the step counter and the ping-pong parity.
@@ -922,6 +924,102 @@ __global__ void k_noise(uint64_t seed, uint64_t step, int n, double* __restrict_
         out[3 * i + 1] = (double)g[1];
         out[3 * i + 2] = (double)g[2];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Monte Carlo ("Monte Carlo Methods"): one Metropolis trial with a
+// Hinzke-Nowak move on every site of one colour class of a greedy colouring
+// of the neighbour graph.  Sites of a class share no link, so their trials
+// are independent and can run at once, in place.  Move type (flip,
+// Gaussian in a cone of width sigma_g, uniform on the sphere) and the
+// acceptance uniform come from Philox counter (site, step lo, step hi, 3),
+// the Gaussian numbers from counter (site, step lo, step hi, 2).
+// ---------------------------------------------------------------------------
+
+// sum_k J_k S[j_k] / mu_ref over the neighbours of site i, straight from
+// global memory.
+template <typename R>
+__device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, const R* __restrict__ S, int i)
+{
+    V3<R> h{0, 0, 0};
+    if (r.flags & kStencil) {
+        const int p = gload(r.pat_id, i);
+        const int b = gload(r.pat_start, p), e = gload(r.pat_start, p + 1);
+        for (int k = b; k < e; ++k) {
+            const int32_t raw = gload(r.pat_tab, k);
+            if ((raw >> 4) == 0)
+                continue;   // far-part padding
+            const R J = r.jt[raw & 15];
+            const V3<R> sj = load3(S, (int64_t)i + (raw >> 4));
+            h.x += J * sj.x;
+            h.y += J * sj.y;
+            h.z += J * sj.z;
+        }
+        return h;
+    }
+    const int64_t base = gload(r.slice_off, i >> 6) + (i & 63);
+    const int d = gload(r.deg, i) & 255;
+    for (int k = 0; k < d; ++k) {
+        const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
+        const R J = r.jt[e >> kColBits];
+        const V3<R> sj = load3(S, (int64_t)(e & kColMask));
+        h.x += J * sj.x;
+        h.y += J * sj.y;
+        h.z += J * sj.z;
+    }
+    return h;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_mc(const ReplicaDev<R>* __restrict__ rep,
+                                            const int32_t* __restrict__ sites, int count, uint64_t step,
+                                            R cone, double inv_kT, unsigned long long* __restrict__ accepted)
+{
+    __shared__ unsigned int acc_block;
+    if (threadIdx.x == 0)
+        acc_block = 0;
+    __syncthreads();
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) {
+        const ReplicaDev<R>& r = *rep;
+        const int i = gload(sites, t);
+        R* __restrict__ S = r.S[r.parity];
+        const MaterialDev<R> m = site_material(r, i);
+        const V3<R> s = load3((const R*)S, i);
+        const V3<R> sum = exchange_sum_global(r, (const R*)S, i);
+        const V3<R> h{m.mu_rel * sum.x + r.H[0], m.mu_rel * sum.y + r.H[1], m.mu_rel * sum.z + r.H[2]};
+        uint32_t c0 = (uint32_t)i, c1 = (uint32_t)step, c2 = (uint32_t)(step >> 32), c3 = 3u;
+        philox10(c0, c1, c2, c3, (uint32_t)r.seed, (uint32_t)(r.seed >> 32));
+        const uint32_t move = (uint32_t)(((uint64_t)c0 * 3u) >> 32);
+        const double u = (double)c1 * 2.3283064365386963e-10;
+        R g[3];
+        thermal_normals(r.seed, step, (uint32_t)i, g, 2u);
+        V3<R> tr;
+        if (move == 0) {
+            tr = V3<R>{-s.x, -s.y, -s.z};
+        } else {
+            tr = move == 1 ? V3<R>{s.x + cone * g[0], s.y + cone * g[1], s.z + cone * g[2]}
+                           : V3<R>{g[0], g[1], g[2]};
+            tr = normalised(tr);
+        }
+        const V3<R> e = site_axis(r, m, i);
+        const R se = dot(s, e), te = dot(tr, e);
+        // dE = -mu_s [(S' - S).(H_exc + H) + (k_u/mu_s)((S'.e)^2 - (S.e)^2)]
+        const V3<R> d{tr.x - s.x, tr.y - s.y, tr.z - s.z};
+        const R bracket = dot(d, h) + m.ku_mu * (te * te - se * se);
+        // accept when dE <= 0, else with probability exp(-dE/(kB T)); the
+        // decision is taken in the kernel's precision
+        bool accept = bracket >= (R)0;
+        if (!accept && inv_kT > 0.0)
+            accept = (R)u < exp(bracket * (R)(m.mu_s * inv_kT));
+        if (accept) {
+            store3(S, i, tr);
+            atomicAdd(&acc_block, 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && acc_block)
+        atomicAdd(accepted, (unsigned long long)acc_block);
 }
 
 // Copy per-step records (m, E) of one replica into caller arrays.
@@ -1010,11 +1108,11 @@ hipError_t launch_correct(const ReplicaDev<R>* reps, const WorkItem* work, const
 }
 
 template <typename R>
-hipError_t launch_finish(const ReplicaDev<R>* reps, int n_rep, int mode, hipStream_t st)
+hipError_t launch_finish(const ReplicaDev<R>* reps, int n_rep, int mode, int slot, hipStream_t st)
 {
     if (n_rep <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((k_finish<R>), dim3(n_rep), dim3(kBlockThreads), 0, st, reps, mode);
+    hipLaunchKernelGGL((k_finish<R>), dim3(n_rep), dim3(kBlockThreads), 0, st, reps, mode, slot);
     return hipGetLastError();
 }
 
@@ -1033,6 +1131,17 @@ hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStr
     if (n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL((k_noise<R>), dim3((n + 255) / 256), dim3(256), 0, st, seed, step, n, out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, uint64_t step, double cone,
+                     double inv_kT, unsigned long long* accepted, hipStream_t st)
+{
+    if (count <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_mc<R>), dim3((count + 255) / 256), dim3(256), 0, st, rep, sites, count, step,
+                       (R)cone, inv_kT, accepted);
     return hipGetLastError();
 }
 
@@ -1076,10 +1185,12 @@ hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t s
     template hipError_t launch_correct<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, \
                                           int, bool, hipStream_t);                                   \
     template hipError_t launch_accumulate<R>(const ReplicaDev<R>*, int, hipStream_t);                \
-    template hipError_t launch_finish<R>(const ReplicaDev<R>*, int, int, hipStream_t);              \
+    template hipError_t launch_finish<R>(const ReplicaDev<R>*, int, int, int, hipStream_t);         \
     template hipError_t launch_advance<R>(ReplicaDev<R>*, int, hipStream_t);                         \
     template hipError_t launch_noise<R>(uint64_t, uint64_t, int, double*, hipStream_t);             \
-    template int resident_blocks<R>(int, bool);
+    template int resident_blocks<R>(int, bool);                                                       \
+    template hipError_t launch_mc<R>(const ReplicaDev<R>*, const int32_t*, int, uint64_t, double, double, \
+                                     unsigned long long*, hipStream_t);
 
 SLLG_INSTANTIATE(float)
 SLLG_INSTANTIATE(double)

@@ -29,9 +29,9 @@ template <typename R>
 hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t st);
 // Completes the record of the measuring predictor's state for every
 // recording replica: mode 0 = the chunk's last step (slot nsteps - 1),
-// mode 1 = the current state (slot 0).
+// mode 1 = the current state (record slot `slot`).
 template <typename R>
-hipError_t launch_finish(const ReplicaDev<R>* reps, int n_rep, int mode, hipStream_t st);
+hipError_t launch_finish(const ReplicaDev<R>* reps, int n_rep, int mode, int slot, hipStream_t st);
 // Step counter and ping-pong parity update at the end of a chunk.
 template <typename R>
 hipError_t launch_advance(ReplicaDev<R>* reps, int n_rep, hipStream_t st);
@@ -43,6 +43,14 @@ hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStr
 // (compute units x resident blocks per unit); 0 if it cannot be queried.
 template <typename R>
 int resident_blocks(int device, bool per_site);
+
+// One Monte Carlo sweep of one colour class (count sites listed in
+// `sites`) of the replica at *rep, step number `step` for the counters;
+// cone = sigma_g, inv_kT = 1/(kB T) (0 at T = 0); accepted trials are added
+// to *accepted.
+template <typename R>
+hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, uint64_t step, double cone,
+                     double inv_kT, unsigned long long* accepted, hipStream_t st);
 
 hipError_t launch_scatter_records(const double* rec, int count, double* m_dev, double* E_dev,
                                   hipStream_t st);

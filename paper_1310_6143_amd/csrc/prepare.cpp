@@ -193,6 +193,36 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
     return s;
 }
 
+void build_colours(HostStructure& s, const int64_t* row_ptr, const int32_t* col)
+{
+    const int64_t n = s.n;
+    std::vector<int32_t> colour((size_t)n);
+    std::vector<int64_t> seen(kMaxDegree + 2, -1);   // seen[c] == i: colour c is taken around site i
+    int n_colours = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t deg = row_ptr[i + 1] - row_ptr[i];
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const int64_t j = col[k];
+            if (j < i && colour[(size_t)j] <= deg)
+                seen[(size_t)colour[(size_t)j]] = i;
+        }
+        int c = 0;
+        while (seen[(size_t)c] == i)
+            ++c;
+        colour[(size_t)i] = c;
+        n_colours = std::max(n_colours, c + 1);
+    }
+    s.colour_start.assign((size_t)n_colours + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        ++s.colour_start[(size_t)colour[(size_t)i] + 1];
+    for (int c = 0; c < n_colours; ++c)
+        s.colour_start[(size_t)c + 1] += s.colour_start[(size_t)c];
+    std::vector<int64_t> fill(s.colour_start.begin(), s.colour_start.end() - 1);
+    s.colour_sites.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        s.colour_sites[(size_t)fill[(size_t)colour[(size_t)i]]++] = (int32_t)i;
+}
+
 HostMaterials build_materials(int64_t n, const double* mu_s, const double* k_u,
                               const double* easy_axis, int per_site)
 {

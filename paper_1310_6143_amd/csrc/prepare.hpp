@@ -22,6 +22,8 @@ struct Failure {
 
 // Boltzmann constant (J/K), Table 1 of the paper.
 constexpr double kBoltzmann = 1.3807e-23;
+// Bohr magneton (J/T), Table 1 of the paper.
+constexpr double kBohrMagneton = 9.2740e-24;
 
 // Neighbour structure in stencil or SELL-64 form.  Every row lists its
 // near links (|col - row| <= halo_cap) first and the far ones after, each
@@ -45,6 +47,9 @@ struct HostStructure {
     std::vector<uint16_t> pat_start;   // [n_patterns + 1]
     std::vector<uint16_t> pat_far;     // [n_patterns] first far entry of each pattern
     bool no_far = false;               // no pattern has a far link (no padding then)
+    // Monte Carlo colour classes (build_colours): sites sorted by colour
+    std::vector<int32_t> colour_sites;
+    std::vector<int64_t> colour_start;   // [n_colours + 1]
 };
 
 // Sites per tile of this structure at a precision (see tile_request).
@@ -56,6 +61,11 @@ int tile_of(const HostStructure& s, size_t real_bytes);
 HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* col,
                               const uint8_t* ntype, const double* J, int n_types,
                               bool check_symmetry, int halo_cap, bool allow_stencil = true);
+
+// Greedy colouring of the neighbour graph for Monte Carlo: site i takes the
+// smallest colour no neighbour j < i has (so no link joins two sites of one
+// colour); fills colour_sites / colour_start.
+void build_colours(HostStructure& s, const int64_t* row_ptr, const int32_t* col);
 
 // Materials: distinct (mu_s, k_u) pairs, per-site ids when there is more
 // than one, per-site easy axes when they differ.

@@ -1,0 +1,92 @@
+"""GPU Monte Carlo (Hinzke-Nowak moves, colour-class sweeps) against the
+oracle's Monte Carlo on the same inputs and the same counter-based draws.
+
+In FP64 both sides take every acceptance decision in double precision from
+the same random numbers, so the chains coincide (a decision could only
+differ if a uniform fell within rounding of its acceptance probability):
+spins, records and accepted counts are compared directly.  In FP32 the
+decisions are the kernel's own, so the comparison is statistical.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import paper_1310_6143_amd as sl
+from spin_systems import MU_B, bcc_block, fcc_nanoparticle, sc_reference
+from spin_systems.lattice import Lattice
+from spin_systems.workloads import GAMMA, Workload
+from tests.gpu_util import max_angle
+
+pytestmark = pytest.mark.gpu
+KB = 1.3807e-23
+
+
+def _oracle_mc(w, n_steps):
+    S = np.ascontiguousarray(w.S0.copy())
+    m, E, acc = oracle.System(w).mc(S, 0, n_steps)
+    return S, m, E, acc
+
+
+@pytest.mark.parametrize("make", [lambda: sc_reference(L=12, temperature=300.0, seed=7),
+                                  lambda: bcc_block(cells=10, temperature=900.0, seed=8),
+                                  lambda: fcc_nanoparticle(radius_nm=1.6, temperature=300.0)])
+def test_mc_fp64_chain_matches_oracle(make):
+    w = make()
+    S_ref, m_ref, E_ref, acc_ref = _oracle_mc(w, 25)
+    with sl.from_workload(w, precision=sl.FP64, check_symmetry=False) as g:
+        m, E, acc = g.mc(25)
+        S = g.get_spins()
+        assert g.step == 25
+    assert np.array_equal(acc, acc_ref)
+    assert max_angle(S, S_ref) <= 1e-12
+    assert np.abs(m - m_ref).max() <= 1e-12
+    assert np.abs(E - E_ref).max() <= 1e-12 * np.abs(E_ref).max()
+
+
+def test_mc_chunked_equals_single_call_and_is_deterministic():
+    w = sc_reference(L=10, temperature=500.0, seed=3)
+    for prec in (sl.FP32, sl.FP64):
+        with sl.from_workload(w, precision=prec) as a, sl.from_workload(w, precision=prec) as b:
+            m1, E1, acc1 = a.mc(40)
+            m2a, E2a, acc2a = b.mc(15)
+            m2b, E2b, acc2b = b.mc(25)
+            assert np.array_equal(a.get_spins(), b.get_spins())
+            assert np.array_equal(m1, np.concatenate([m2a, m2b]))
+            assert np.array_equal(acc1, np.concatenate([acc2a, acc2b]))
+
+
+@pytest.mark.parametrize("T", [300.0, 400.0])
+def test_mc_fp32_thermal_average_matches_oracle(T):
+    w = sc_reference(L=12, temperature=T, seed=3)
+    with sl.from_workload(w, precision=sl.FP32) as g:
+        gpu = g.mc_average(1000, 3000, 10)
+    ref, _ = oracle.mc_average(oracle.System(w), w.S0.copy(), 0, 1000, 3000, 10)
+    tol = 4 * np.hypot(gpu["m_abs_se"], ref["m_abs_se"]) + 5e-3
+    assert abs(gpu["m_abs"] - ref["m_abs"]) < tol, (gpu, ref)
+    assert abs(gpu["acceptance"] - ref["acceptance"]) < 0.02
+
+
+@pytest.mark.parametrize("precision", [sl.FP32, sl.FP64])
+def test_mc_boltzmann_ensemble_of_free_spins(precision):
+    """4096 uncoupled anisotropic spins (k_u/kB T = 3): <cos^2 theta> over
+    the ensemble and 400 steps against the Boltzmann integral."""
+    n, ku, xi = 4096, 1e-23, 3.0
+    lat = Lattice("free spins", np.zeros((n, 3)), np.zeros(n + 1, dtype=np.int64),
+                  np.zeros(0, dtype=np.int32), np.zeros(0, dtype=np.uint8))
+    w = Workload(name="free spins", lattice=lat, J=np.array([0.0]), mu_s=np.full(n, 1.5 * MU_B),
+                 k_u=np.full(n, ku), easy_axis=np.tile([0.0, 0.0, 1.0], (n, 1)), alpha=0.1, gamma=GAMMA,
+                 dt=1e-16, temperature=ku / (KB * xi), H=np.zeros(3), seed=17, n_steps=0,
+                 S0=np.tile([0.0, 0.0, 1.0], (n, 1)))
+    with sl.from_workload(w, precision=precision) as g:
+        g.mc(200, record=False)
+        samples = []
+        for _ in range(40):
+            g.mc(10, record=False)
+            S = g.get_spins()
+            samples.append((S[:, 2] ** 2).mean())
+    samples = np.array(samples)
+    num = integrate.quad(lambda t: np.cos(t) ** 2 * np.sin(t) * np.exp(xi * np.cos(t) ** 2), 0, np.pi)[0]
+    den = integrate.quad(lambda t: np.sin(t) * np.exp(xi * np.cos(t) ** 2), 0, np.pi)[0]
+    se = samples.std(ddof=1) / np.sqrt(samples.size)
+    assert abs(samples.mean() - num / den) < 4 * se + 2e-3, (samples.mean(), se, num / den)
