@@ -186,10 +186,62 @@ def run_sweep(kind, precision, args):
                         "E": r["E"], "E_se": r["E_se"]} for r in rows]}
 
 
+def run_mc(precision, args):
+    """Monte Carlo M(T) of the paper's simple-cubic test system (21,952 spins,
+    J = 6.0e-21 J/link, periodic): heating 50..1000 K in 50 K steps with
+    continuation, 5000 equilibration + 5000 averaging steps per point
+    (the paper uses 50,000 each), records every step; then the Monte Carlo
+    step rate of the 8,192,000-spin bcc block (50 steps with records)."""
+    import paper_1310_6143_amd as sl
+    from spin_systems import bcc_block, sc_reference
+
+    w = sc_reference(L=28, temperature=50.0, seed=1)
+    temps = np.arange(50.0, 1001.0, 50.0)
+    n_eq = n_avg = args.mc_steps
+    sysm = sl.from_workload(w, precision=precision)
+    sysm.mc(10, record=False)                       # first use: upload
+    rows = []
+    t0 = time.perf_counter()
+    for T in temps:
+        sysm.set_conditions(float(T), (0.0, 0.0, 0.0))
+        r = sysm.mc_average(n_eq, n_avg, 10)
+        rows.append({"x": float(T), "m_abs": r["m_abs"], "m_abs_se": r["m_abs_se"], "E": r["E"],
+                     "E_se": r["E_se"], "acceptance": r["acceptance"]})
+    dt = time.perf_counter() - t0
+    sysm.close()
+    steps = len(temps) * (n_eq + n_avg)
+    blk = bcc_block(cells=args.cells)
+    g = sl.from_workload(blk, precision=precision, check_symmetry=False)
+    g.mc(2)
+    t1 = time.perf_counter()
+    _, _, acc = g.mc(50)
+    dt_blk = time.perf_counter() - t1
+    g.close()
+    return {"spin_steps_per_s": w.n * steps / dt, "seconds": dt, "n_spins": w.n, "steps": steps,
+            "points": rows,
+            "block": {"n_spins": blk.n, "mc_steps": 50, "trials_per_s": blk.n * 50 / dt_blk,
+                      "ms_per_mc_step": dt_blk * 1e3 / 50, "acceptance": float(acc.sum()) / (blk.n * 50)}}
+
+
 def sweep_main(args):
     import paper_1310_6143_amd as sl
 
     kind = args.workload
+    if kind == "mc":
+        r32 = run_mc(sl.FP32, args)
+        out = {
+            "metric": "spin trials/s (Monte Carlo, Hinzke-Nowak moves)", "value": r32["spin_steps_per_s"],
+            "unit": "spin-trials/s", "n_gpus": 1, "steps": r32["steps"], "warmup": 10,
+            "ms_per_step": r32["seconds"] * 1e3 / r32["steps"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"Monte Carlo M(T), sc 28^3 (21,952 spins), 50..1000 K in 50 K steps, "
+                                   f"{args.mc_steps} + {args.mc_steps} steps per point"},
+            "fp32": r32,
+        }
+        if not args.no_fp64:
+            out["fp64"] = run_mc(sl.FP64, args)
+        print(json.dumps(out))
+        return
     r32 = run_sweep(kind, sl.FP32, args)
     out = {
         "metric": METRIC, "value": r32["spin_steps_per_s"], "unit": "spin-steps/s", "n_gpus": 1,
@@ -246,9 +298,12 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-budget", type=int, default=16384, help="MiB")
     ap.add_argument("--serving-chunk", type=int, default=64)
-    ap.add_argument("--workload", default="block", choices=["block", "film", "sphere"],
+    ap.add_argument("--workload", default="block", choices=["block", "film", "sphere", "mc"],
                     help="block: 8.19M-spin bcc step throughput (default); film: full M(T) ramp; "
-                         "sphere: full hysteresis sweep")
+                         "sphere: full hysteresis sweep; mc: Monte Carlo M(T) of the sc test system "
+                         "and the Monte Carlo step rate of the block")
+    ap.add_argument("--mc-steps", type=int, default=5000, help="equilibration (= averaging) steps per "
+                    "temperature for --workload mc")
     ap.add_argument("--sweep-points", type=int, default=0, help="limit the sweep to its first points")
     ap.add_argument("--launch", default="", help="fixed launch shape 'xcd_remap,grid_scale_pct[,tile_order]' "
                     "instead of the library default")
