@@ -216,11 +216,15 @@ def run_mc(precision, args):
     t1 = time.perf_counter()
     _, _, acc = g.mc(50)
     dt_blk = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    g.mc(50, record=False)
+    dt_sweep = time.perf_counter() - t2
     g.close()
     return {"spin_steps_per_s": w.n * steps / dt, "seconds": dt, "n_spins": w.n, "steps": steps,
             "points": rows,
             "block": {"n_spins": blk.n, "mc_steps": 50, "trials_per_s": blk.n * 50 / dt_blk,
-                      "ms_per_mc_step": dt_blk * 1e3 / 50, "acceptance": float(acc.sum()) / (blk.n * 50)}}
+                      "ms_per_mc_step": dt_blk * 1e3 / 50,
+                      "ms_per_sweep_without_record": dt_sweep * 1e3 / 50, "acceptance": float(acc.sum()) / (blk.n * 50)}}
 
 
 def sweep_main(args):

@@ -936,57 +936,83 @@ __global__ void k_noise(uint64_t seed, uint64_t step, int n, double* __restrict_
 // the Gaussian numbers from counter (site, step lo, step hi, 2).
 // ---------------------------------------------------------------------------
 
-// sum_k J_k S[j_k] / mu_ref over the neighbours of site i, straight from
-// global memory.
+// sum_k J_k S[j_k] / mu_ref over the neighbours of site i, the spins
+// straight from global memory.  Pattern tables come from LDS; neighbours are
+// taken kMcBatch at a time, every load of a batch issued before the first is
+// used (entries past the end repeat the last one with J = 0), and added in
+// table order.
+constexpr int kMcBatch = 8;
+
 template <typename R>
-__device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, const R* __restrict__ S, int i)
+__device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, const Shared<R>& sh,
+                                                     const R* __restrict__ S, int i)
 {
     V3<R> h{0, 0, 0};
+    const char* sb = (const char*)S;
     if (r.flags & kStencil) {
         const int p = gload(r.pat_id, i);
-        const int b = gload(r.pat_start, p), e = gload(r.pat_start, p + 1);
-        for (int k = b; k < e; ++k) {
-            const int32_t raw = gload(r.pat_tab, k);
-            if ((raw >> 4) == 0)
-                continue;   // far-part padding
-            const R J = r.jt[raw & 15];
-            const V3<R> sj = load3(S, (int64_t)i + (raw >> 4));
-            h.x += J * sj.x;
-            h.y += J * sj.y;
-            h.z += J * sj.z;
+        const int b = sh.pat_start[p], e = sh.pat_start[p + 1];
+        const char* si = sb + (int64_t)i * (3 * sizeof(R));
+        for (int k = b; k < e; k += kMcBatch) {
+            V3<R> sj[kMcBatch];
+            R J[kMcBatch];
+#pragma unroll
+            for (int u = 0; u < kMcBatch; ++u) {
+                const int kk = k + u < e ? k + u : e - 1;
+                const PatEntry<R> pe = sh.pat[kk];
+                J[u] = k + u < e ? pe.J : (R)0;
+                sj[u] = load3((const R*)(si + pe.off), 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kMcBatch; ++u) {
+                h.x += J[u] * sj[u].x;
+                h.y += J[u] * sj[u].y;
+                h.z += J[u] * sj[u].z;
+            }
         }
         return h;
     }
     const int64_t base = gload(r.slice_off, i >> 6) + (i & 63);
     const int d = gload(r.deg, i) & 255;
-    for (int k = 0; k < d; ++k) {
-        const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
-        const R J = r.jt[e >> kColBits];
-        const V3<R> sj = load3(S, (int64_t)(e & kColMask));
-        h.x += J * sj.x;
-        h.y += J * sj.y;
-        h.z += J * sj.z;
+    for (int k = 0; k < d; k += kMcBatch) {
+        uint32_t ent[kMcBatch];
+#pragma unroll
+        for (int u = 0; u < kMcBatch; ++u)
+            ent[u] = gload(r.nb, base + (int64_t)(k + u < d ? k + u : d - 1) * kSlice);
+        V3<R> sj[kMcBatch];
+#pragma unroll
+        for (int u = 0; u < kMcBatch; ++u)
+            sj[u] = load3(S, (int64_t)(ent[u] & kColMask));
+#pragma unroll
+        for (int u = 0; u < kMcBatch; ++u) {
+            const R J = k + u < d ? sh.jt[ent[u] >> kColBits] : (R)0;
+            h.x += J * sj[u].x;
+            h.y += J * sj[u].y;
+            h.z += J * sj[u].z;
+        }
     }
     return h;
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_mc(const ReplicaDev<R>* __restrict__ rep,
-                                            const int32_t* __restrict__ sites, int count, uint64_t step,
-                                            R cone, double inv_kT, unsigned long long* __restrict__ accepted)
+__global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __restrict__ rep,
+                                                      const int32_t* __restrict__ sites, int count, uint64_t step,
+                                                      R cone, double inv_kT, unsigned long long* __restrict__ accepted)
 {
+    __shared__ Shared<R> sh;
     __shared__ unsigned int acc_block;
+    const ReplicaDev<R>& r = *rep;
     if (threadIdx.x == 0)
         acc_block = 0;
+    stage_tables(r, sh);
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) {
-        const ReplicaDev<R>& r = *rep;
         const int i = gload(sites, t);
         R* __restrict__ S = r.S[r.parity];
         const MaterialDev<R> m = site_material(r, i);
         const V3<R> s = load3((const R*)S, i);
-        const V3<R> sum = exchange_sum_global(r, (const R*)S, i);
+        const V3<R> sum = exchange_sum_global(r, sh, (const R*)S, i);
         const V3<R> h{m.mu_rel * sum.x + r.H[0], m.mu_rel * sum.y + r.H[1], m.mu_rel * sum.z + r.H[2]};
         uint32_t c0 = (uint32_t)i, c1 = (uint32_t)step, c2 = (uint32_t)(step >> 32), c3 = 3u;
         philox10(c0, c1, c2, c3, (uint32_t)r.seed, (uint32_t)(r.seed >> 32));
@@ -1140,8 +1166,8 @@ hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, 
 {
     if (count <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((k_mc<R>), dim3((count + 255) / 256), dim3(256), 0, st, rep, sites, count, step,
-                       (R)cone, inv_kT, accepted);
+    hipLaunchKernelGGL((k_mc<R>), dim3((count + kBlockThreads - 1) / kBlockThreads), dim3(kBlockThreads), 0, st,
+                       rep, sites, count, step, (R)cone, inv_kT, accepted);
     return hipGetLastError();
 }
 
