@@ -62,6 +62,8 @@ class _System(ctypes.Structure):
         ("temperature", ctypes.c_double),
         ("H", ctypes.c_double * 3),
         ("seed", ctypes.c_uint64),
+        ("J_tensor", ctypes.c_void_p),
+        ("k_c", ctypes.c_void_p),
     ]
 
 
@@ -200,6 +202,11 @@ class System:
         self.temperature = float(w.temperature)
         self.H = np.array(w.H, dtype=np.float64)
         self.seed = int(w.seed)
+        Jt = getattr(w, "J_tensor", None)
+        self.J_tensor = None if Jt is None else np.ascontiguousarray(Jt, dtype=np.float64).reshape(-1, 9)
+        kc = getattr(w, "k_c", None)
+        self.k_c = None if kc is None else np.ascontiguousarray(np.broadcast_to(kc, (self.n,)),
+                                                                dtype=np.float64)
 
     def _struct(self):
         s = _System()
@@ -216,6 +223,8 @@ class System:
         s.temperature = self.temperature
         s.H = (ctypes.c_double * 3)(*[float(v) for v in self.H])
         s.seed = self.seed
+        s.J_tensor = None if self.J_tensor is None else self.J_tensor.ctypes.data
+        s.k_c = None if self.k_c is None else self.k_c.ctypes.data
         return s
 
     def integrate(self, S, step0, n_steps, record=True):

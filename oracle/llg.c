@@ -7,7 +7,11 @@
  *    uniaxial anisotropy -k_u sum_i (S_i.e)^2, applied field
  *    -sum_i mu_s S_i.H_app.  J is given in joules per link (Table 1), so
  *    each link enters the energy once and the field on spin i from
- *    neighbour j is J_ij S_j / mu_s.
+ *    neighbour j is J_ij S_j / mu_s.  Tensorial exchange replaces the
+ *    scalar by a 3x3 matrix, energy -S_i^T J_ij S_j per link; with
+ *    J_ji = J_ij^T the field on i is again (1/mu_s) sum_j J_ij S_j (matrix
+ *    times vector).  Cubic anisotropy (k_c/2)(Sx^4 + Sy^4 + Sz^4) per site
+ *    gives the field -(2 k_c/mu_s)(Sx^3, Sy^3, Sz^3).
  *  - "Spin Dynamics": the atomistic LLG equation and the effective field
  *    H_i = -(1/mu_s) dH/dS_i.
  *  - "Langevin Dynamics": the thermal field Gamma sqrt(2 lambda kB T /
@@ -49,16 +53,25 @@ static int normalise3(double v[3])
 }
 
 /* Exchange field of spin i: (1/mu_s,i) sum over the links of row i of
- * J[type] S_j, the negative derivative of -sum_{i!=j} J_ij S_i.S_j. */
+ * J[type] S_j, the negative derivative of -sum_{i!=j} J_ij S_i.S_j; with
+ * tensors, the matrix J_tensor[type] applied to S_j. */
 void orc_exchange_field(const orc_system *s, const double *S, int64_t i, double h[3])
 {
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t k = s->row_ptr[i]; k < s->row_ptr[i + 1]; ++k) {
         int64_t j = s->col[k];
-        double Jij = s->J[s->ntype ? s->ntype[k] : 0];
-        acc[0] += Jij * S[3 * j + 0];
-        acc[1] += Jij * S[3 * j + 1];
-        acc[2] += Jij * S[3 * j + 2];
+        const int t = s->ntype ? s->ntype[k] : 0;
+        const double *sj = S + 3 * j;
+        if (s->J_tensor) {
+            const double *M = s->J_tensor + 9 * t;
+            for (int a = 0; a < 3; ++a)
+                acc[a] += M[3 * a + 0] * sj[0] + M[3 * a + 1] * sj[1] + M[3 * a + 2] * sj[2];
+        } else {
+            double Jij = s->J[t];
+            acc[0] += Jij * sj[0];
+            acc[1] += Jij * sj[1];
+            acc[2] += Jij * sj[2];
+        }
     }
     h[0] = acc[0] / s->mu_s[i];
     h[1] = acc[1] / s->mu_s[i];
@@ -66,7 +79,7 @@ void orc_exchange_field(const orc_system *s, const double *S, int64_t i, double 
 }
 
 /* Deterministic effective field: exchange + uniaxial anisotropy
- * (2 k_u / mu_s)(S.e) e + applied field. */
+ * (2 k_u / mu_s)(S.e) e + applied field (+ cubic anisotropy). */
 void orc_effective_field(const orc_system *s, const double *S, int64_t i, double h[3])
 {
     const double *e = s->easy_axis + 3 * i;
@@ -76,6 +89,12 @@ void orc_effective_field(const orc_system *s, const double *S, int64_t i, double
     h[0] += a * e[0] + s->H[0];
     h[1] += a * e[1] + s->H[1];
     h[2] += a * e[2] + s->H[2];
+    if (s->k_c) {
+        /* -(1/mu_s) d/dS of (k_c/2) sum_a S_a^4 */
+        const double c = -2.0 * s->k_c[i] / s->mu_s[i];
+        for (int q = 0; q < 3; ++q)
+            h[q] += c * si[q] * si[q] * si[q];
+    }
 }
 
 void orc_effective_fields(const orc_system *s, const double *S, double *H_out)
@@ -116,6 +135,10 @@ double orc_energy(const orc_system *s, const double *S)
         double ani = s->k_u[i] * se * se;
         double app = s->mu_s[i] * dot3(si, s->H);
         total -= exc + ani + app;
+        if (s->k_c) {
+            const double x2 = si[0] * si[0], y2 = si[1] * si[1], z2 = si[2] * si[2];
+            total += 0.5 * s->k_c[i] * (x2 * x2 + y2 * y2 + z2 * z2);
+        }
     }
     return total;
 }

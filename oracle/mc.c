@@ -73,19 +73,33 @@ void orc_mc_choice(uint64_t seed, uint64_t step, uint64_t site, uint32_t *move, 
 }
 
 /* Energy of spin i's terms when it points along x, with the neighbours as
- * they are: -x.(sum_j J_ij S_j) - k_u (x.e)^2 - mu_s x.H. */
+ * they are: -x.(sum_j J_ij S_j) - k_u (x.e)^2 - mu_s x.H, plus
+ * (k_c/2)(x_x^4 + x_y^4 + x_z^4) with cubic anisotropy; J_ij S_j is a
+ * matrix product with tensorial exchange. */
 static double site_energy(const orc_system *s, const double *S, int64_t i, const double x[3])
 {
     double sum[3] = {0.0, 0.0, 0.0};
     for (int64_t k = s->row_ptr[i]; k < s->row_ptr[i + 1]; ++k) {
-        const double J = s->J[s->ntype ? s->ntype[k] : 0];
+        const int t = s->ntype ? s->ntype[k] : 0;
         const double *sj = S + 3 * (int64_t)s->col[k];
-        sum[0] += J * sj[0];
-        sum[1] += J * sj[1];
-        sum[2] += J * sj[2];
+        if (s->J_tensor) {
+            const double *M = s->J_tensor + 9 * t;
+            for (int a = 0; a < 3; ++a)
+                sum[a] += M[3 * a + 0] * sj[0] + M[3 * a + 1] * sj[1] + M[3 * a + 2] * sj[2];
+        } else {
+            const double J = s->J[t];
+            sum[0] += J * sj[0];
+            sum[1] += J * sj[1];
+            sum[2] += J * sj[2];
+        }
     }
     const double xe = dot3(x, s->easy_axis + 3 * i);
-    return -dot3(x, sum) - s->k_u[i] * xe * xe - s->mu_s[i] * dot3(x, s->H);
+    double E = -dot3(x, sum) - s->k_u[i] * xe * xe - s->mu_s[i] * dot3(x, s->H);
+    if (s->k_c) {
+        const double x2 = x[0] * x[0], y2 = x[1] * x[1], z2 = x[2] * x[2];
+        E += 0.5 * s->k_c[i] * (x2 * x2 + y2 * y2 + z2 * z2);
+    }
+    return E;
 }
 
 int orc_mc_trial(const orc_system *s, double *S, int64_t i, uint64_t step)

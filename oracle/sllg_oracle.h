@@ -32,7 +32,11 @@ extern "C" {
 /* A spin system in the form the Hamiltonian section writes it.
  * Every per-site array has n entries (easy_axis has 3n).  The neighbour
  * list is CSR: the entries of row i are row_ptr[i] .. row_ptr[i+1]-1, with
- * neighbour col[k] coupled by J[ntype[k]] (ntype may be NULL: all type 0). */
+ * neighbour col[k] coupled by J[ntype[k]] (ntype may be NULL: all type 0).
+ * With J_tensor (n_types x 9, row-major) the coupling of a link of type t
+ * is the matrix J_tensor[t] instead of J[t] (tensorial exchange; the
+ * reverse link must carry the transposed matrix).  k_c (n entries, may be
+ * NULL) adds cubic anisotropy (k_c/2)(Sx^4 + Sy^4 + Sz^4) per site. */
 typedef struct {
     int64_t n;
     const int64_t *row_ptr;
@@ -49,6 +53,8 @@ typedef struct {
     double temperature;    /* K */
     double H[3];           /* applied field, T */
     uint64_t seed;         /* Philox key */
+    const double *J_tensor;  /* NULL: scalar exchange J[type] */
+    const double *k_c;       /* NULL: no cubic anisotropy */
 } orc_system;
 
 /* Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, "Parallel random

@@ -23,7 +23,7 @@ GAMMA = 1.76e11        # 1/(T s), Table 1
 __all__ = [
     "MU_B", "GAMMA", "Workload",
     "sc_reference", "bcc_film", "fcc_nanoparticle", "bcc_block", "serving_requests",
-    "sc_request_system", "single_spin",
+    "sc_request_system", "single_spin", "dmi_matrix", "with_tensor_exchange",
 ]
 
 
@@ -45,6 +45,8 @@ class Workload:
     n_steps: int
     S0: np.ndarray                   # [n, 3] unit vectors
     extra: dict = field(default_factory=dict)
+    J_tensor: np.ndarray | None = None   # [n_types, 3, 3] joules/link, replaces J when set
+    k_c: np.ndarray | None = None        # [n] cubic anisotropy, J/atom
 
     @property
     def n(self) -> int:
@@ -191,3 +193,53 @@ def single_spin(mu_s=1.5 * MU_B, k_u=0.0, axis=(0.0, 0.0, 1.0), H=(0.0, 0.0, 0.0
         mu_s=np.array([float(mu_s)]), k_u=np.array([float(k_u)]), easy_axis=ax[None, :],
         alpha=alpha, gamma=GAMMA, dt=dt, temperature=temperature,
         H=np.asarray(H, dtype=np.float64), seed=seed, n_steps=n_steps, S0=s0[None, :])
+
+
+def dmi_matrix(D):
+    """The matrix A with S_i^T A S_j = D . (S_i x S_j)."""
+    Dx, Dy, Dz = (float(v) for v in D)
+    return np.array([[0.0, Dz, -Dy], [-Dz, 0.0, Dx], [Dy, -Dx, 0.0]])
+
+
+def with_tensor_exchange(w, D=0.0, dmi="bulk", k_c=None) -> Workload:
+    """A copy of a periodic-lattice workload with one interaction type per
+    (shell, bond direction) and exchange tensors J_ij = J_shell I - A(D_ij):
+    the isotropic exchange of w plus a Dzyaloshinskii-Moriya energy
+    D_ij . (S_i x S_j) per link, D_ij = D r_ij ("bulk") or D (z x r_ij)
+    ("interfacial") with r_ij the unit bond vector (D in joules, one value
+    or one per shell).  The reverse link gets the transposed tensor.  k_c
+    (one value or [n], J/atom) adds cubic anisotropy."""
+    lat = w.lattice
+    n = lat.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(lat.row_ptr))
+    d = lat.pos[lat.col] - lat.pos[rows]
+    if lat.dims is not None:
+        for a in range(3):
+            if lat.periodic[a]:
+                L = float(lat.dims[a])
+                d[:, a] -= L * np.round(d[:, a] / L)
+    q = np.rint(d * 2.0).astype(np.int64)                 # bond vectors in units of a/2
+    if np.abs(q).max(initial=0) > 2 or not np.allclose(q, d * 2.0):
+        raise ValueError("bond vectors are not on the a/2 grid of the builder")
+    key = ((lat.ntype.astype(np.int64) * 5 + q[:, 0] + 2) * 5 + q[:, 1] + 2) * 5 + q[:, 2] + 2
+    uniq, new_type = np.unique(key, return_inverse=True)
+    if uniq.size > 16:
+        raise ValueError(f"{uniq.size} directed interaction types (at most 16)")
+    shells = uniq // 125
+    vec = np.stack([(uniq // 25) % 5 - 2, (uniq // 5) % 5 - 2, uniq % 5 - 2], axis=1).astype(np.float64)
+    rhat = vec / np.linalg.norm(vec, axis=1, keepdims=True)
+    Dsh = np.broadcast_to(np.asarray(D, dtype=np.float64), (int(shells.max()) + 1,))
+    J_iso = np.asarray(w.J, dtype=np.float64)[shells]
+    tens = np.empty((uniq.size, 3, 3))
+    for t in range(uniq.size):
+        Dvec = Dsh[shells[t]] * (rhat[t] if dmi == "bulk" else np.cross([0.0, 0.0, 1.0], rhat[t]))
+        tens[t] = J_iso[t] * np.eye(3) - dmi_matrix(Dvec)
+    new_lat = Lattice(lat.kind + " directed", lat.pos, lat.row_ptr, lat.col,
+                      new_type.astype(np.uint8), lat.dims, lat.periodic)
+    out = Workload(name=w.name + f" + DMI {dmi}", lattice=new_lat, J=J_iso, mu_s=w.mu_s, k_u=w.k_u,
+                   easy_axis=w.easy_axis, alpha=w.alpha, gamma=w.gamma, dt=w.dt,
+                   temperature=w.temperature, H=w.H, seed=w.seed, n_steps=w.n_steps, S0=w.S0,
+                   extra=dict(w.extra), J_tensor=tens)
+    if k_c is not None:
+        out.k_c = np.ascontiguousarray(np.broadcast_to(np.asarray(k_c, dtype=np.float64), (n,)))
+    return out
