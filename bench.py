@@ -302,8 +302,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-budget", type=int, default=16384, help="MiB")
     ap.add_argument("--serving-chunk", type=int, default=64)
-    ap.add_argument("--workload", default="block", choices=["block", "film", "sphere", "mc"],
-                    help="block: 8.19M-spin bcc step throughput (default); film: full M(T) ramp; "
+    ap.add_argument("--workload", default="block", choices=["block", "dmi", "film", "sphere", "mc"],
+                    help="block: 8.19M-spin bcc step throughput (default); dmi: the same block with "
+                         "exchange tensors and cubic anisotropy; film: full M(T) ramp; "
                          "sphere: full hysteresis sweep; mc: Monte Carlo M(T) of the sc test system "
                          "and the Monte Carlo step rate of the block")
     ap.add_argument("--mc-steps", type=int, default=5000, help="equilibration (= averaging) steps per "
@@ -342,14 +343,18 @@ def main():
                           "read_plus_write_GBs": 2 * n * 4 / (ms / 1e3) / 1e9}))
         return
 
-    if args.workload != "block":
+    if args.workload not in ("block", "dmi"):
         sweep_main(args)
         return
 
-    from spin_systems import bcc_block
+    from spin_systems import bcc_block, with_tensor_exchange
 
     t0 = time.time()
     w = bcc_block(cells=args.cells)
+    dmi = args.workload == "dmi"
+    if dmi:   # the general kernel variant: 14 directed exchange tensors and cubic anisotropy
+        w = with_tensor_exchange(w, D=(1.2e-21, 0.5e-21), dmi="bulk", k_c=4e-24)
+        args.no_serving = True
     deg = w.lattice.nnz / w.n
     log(f"workload: {w.n} spins, {w.lattice.nnz} neighbour entries, built in {time.time() - t0:.1f} s")
 
@@ -368,7 +373,7 @@ def main():
     value = n * args.steps / (r32["ms"] / 1e3)
     b_alg = algorithmic_bytes_per_spin_step(4, deg)
     achieved = b_alg * n / (ms_step / 1e3) / 1e9
-    traffic = measured_traffic("fp32")
+    traffic = None if dmi else measured_traffic("fp32")
     out = {
         "metric": METRIC,
         "value": value,
@@ -384,7 +389,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"periodic bcc {args.cells}^3 cells, J1+J2 14-entry CSR, {n} spins, T=300 K, "
-                        "alpha=0.05, dt=1e-16 s, seed 4; FP32 spins, FP64 m/E reductions every step",
+                        "alpha=0.05, dt=1e-16 s, seed 4; FP32 spins, FP64 m/E reductions every step"
+                        + ("; exchange tensors per bond direction (14 types: J plus bulk "
+                           "Dzyaloshinskii-Moriya D1 = 1.2e-21 J, D2 = 0.5e-21 J) and cubic "
+                           "anisotropy k_c = 4e-24 J" if dmi else ""),
             "n_spins": n,
             "neighbour_entries": int(w.lattice.nnz),
             "launch_shape": r32["launch"],

@@ -82,9 +82,10 @@ const char *sllg_status_string(sllg_status status);
  * links; ntype[row_ptr[n]] interaction types in [0, n_types), or NULL for
  * all type 0; J[n_types] exchange constants in joules per link, 1 <= n_types
  * <= 16.  At most 255 neighbours per site.  Each link must appear in both
- * rows with the same type (the pair sum runs over i != j with J_ij = J_ji);
+ * rows with the same J (the pair sum runs over i != j with J_ij = J_ji);
  * this is checked unless the option "check_symmetry" is 0.  The exchange
- * field on spin i is (1/mu_s,i) sum_k J[ntype[k]] S[col[k]]. */
+ * field on spin i is (1/mu_s,i) sum_k J[ntype[k]] S[col[k]].  A new
+ * neighbour list drops exchange tensors set before it. */
 sllg_status sllg_set_neighbours(sllg_system *sys, const int64_t *row_ptr, const int32_t *col,
                                 const uint8_t *ntype, const double *J, int n_types);
 
@@ -96,6 +97,32 @@ sllg_status sllg_set_neighbours(sllg_system *sys, const int64_t *row_ptr, const 
  * anisotropy; anisotropy field 2 k_u / mu_s (section "Anisotropy energy"). */
 sllg_status sllg_set_materials(sllg_system *sys, const double *mu_s, const double *k_u,
                                const double *easy_axis, int per_site);
+
+/* Tensorial exchange (section "The classical spin Hamiltonian": the exchange
+ * interaction as a 3x3 tensor; its antisymmetric off-diagonal part is the
+ * Dzyaloshinskii-Moriya interaction).  J[n_types][3][3] row-major, joules
+ * per link, for the types of the current neighbour list (n_types must
+ * match it); replaces the scalar J of those types.  A link i -> j of type t
+ * contributes -S_i^T J[t] S_j to the energy once; the field on spin i is
+ * (1/mu_s,i) sum_k J[ntype[k]] S[col[k]] (matrix times vector).  The
+ * reverse link j -> i must carry the transpose: checked against the types
+ * the symmetry check of sllg_set_neighbours found on reverse links (not
+ * checked when "check_symmetry" was 0).  The library copies J.  J = NULL
+ * returns to the scalar table.  Errors: SLLG_E_STATE before
+ * sllg_set_neighbours; SLLG_E_ARG for a count mismatch, a non-finite
+ * entry or a tensor that is not the transpose of its reverse type's.
+ * Not available to serving requests. */
+sllg_status sllg_set_exchange_tensors(sllg_system *sys, const double *J, int n_types);
+
+/* Cubic anisotropy (section "The classical spin Hamiltonian": energy
+ * (k_c/2)(Sx^4 + Sy^4 + Sz^4) per atom along the crystal axes x, y, z;
+ * field -(2 k_c/mu_s)(Sx^3, Sy^3, Sz^3)).  k_c in J/atom, any sign:
+ * per_site = 0 one value for every site, 1 one per site (k_c[n]); combined
+ * with the materials of sllg_set_materials (whichever call comes last), at
+ * most 256 distinct (mu_s, k_u, k_c).  k_c = NULL removes it.  Errors:
+ * SLLG_E_STATE before sllg_set_materials; SLLG_E_ARG for a non-finite
+ * value.  Not available to serving requests. */
+sllg_status sllg_set_cubic_anisotropy(sllg_system *sys, const double *k_c, int per_site);
 
 /* Damping lambda >= 0, gyromagnetic ratio gamma > 0 (1/(T s); Table 1 gives
  * 1.76e11) and time step dt > 0 (s).  Section "Spin Dynamics" (atomistic LLG

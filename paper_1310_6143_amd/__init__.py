@@ -23,7 +23,7 @@ STATUS = {0: "SLLG_OK", -1: "SLLG_E_ARG", -2: "SLLG_E_NOMEM", -3: "SLLG_E_DEVICE
 # every symbol include/sllg.h declares
 EXPORTS = [
     "sllg_create", "sllg_destroy", "sllg_last_error", "sllg_status_string", "sllg_set_neighbours",
-    "sllg_set_materials", "sllg_set_integrator", "sllg_set_conditions", "sllg_set_rng",
+    "sllg_set_materials", "sllg_set_exchange_tensors", "sllg_set_cubic_anisotropy", "sllg_set_integrator", "sllg_set_conditions", "sllg_set_rng",
     "sllg_get_step", "sllg_set_spins", "sllg_get_spins", "sllg_integrate", "sllg_integrate_dev",
     "sllg_measure", "sllg_average", "sllg_sweep_temperature", "sllg_sweep_field",
     "sllg_thermal_normals", "sllg_autotune", "sllg_mc", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
@@ -91,6 +91,8 @@ def lib():
         "sllg_status_string": (ctypes.c_char_p, [c]),
         "sllg_set_neighbours": (c, [P, P, P, P, P, c]),
         "sllg_set_materials": (c, [P, P, P, P, c]),
+        "sllg_set_exchange_tensors": (c, [P, P, c]),
+        "sllg_set_cubic_anisotropy": (c, [P, P, c]),
         "sllg_set_integrator": (c, [P, D, D, D]),
         "sllg_set_conditions": (c, [P, D, P]),
         "sllg_set_rng": (c, [P, U64, U64]),
@@ -217,6 +219,26 @@ class SpinSystem:
         if per_site is None:
             per_site = 1 if mu_s.size > 1 else 0
         self._check(lib().sllg_set_materials(self._h, _ptr(mu_s), _ptr(k_u), _ptr(axis), int(per_site)))
+
+    def set_exchange_tensors(self, J):
+        """Exchange tensors [n_types, 3, 3] (joules per link) for the
+        neighbour list's types; None returns to the scalar table."""
+        if J is None:
+            self._check(lib().sllg_set_exchange_tensors(self._h, None, 0))
+            return
+        J = _c64(J).reshape(-1, 9)
+        self._check(lib().sllg_set_exchange_tensors(self._h, _ptr(J), int(J.shape[0])))
+
+    def set_cubic_anisotropy(self, k_c, per_site=None):
+        """Cubic anisotropy constants k_c (J/atom): one value or one per
+        site; None removes it."""
+        if k_c is None:
+            self._check(lib().sllg_set_cubic_anisotropy(self._h, None, 0))
+            return
+        k_c = _c64(np.atleast_1d(k_c))
+        if per_site is None:
+            per_site = 1 if k_c.size > 1 else 0
+        self._check(lib().sllg_set_cubic_anisotropy(self._h, _ptr(k_c), int(per_site)))
 
     def set_integrator(self, alpha, gamma, dt):
         self._check(lib().sllg_set_integrator(self._h, float(alpha), float(gamma), float(dt)))
@@ -359,6 +381,12 @@ def from_workload(w, precision=FP32, device=0, check_symmetry=True, stencil=1):
         s.set_materials(mu[:1], ku[:1], ax[:1], per_site=0)
     else:
         s.set_materials(mu, ku, ax, per_site=1)
+    if getattr(w, "J_tensor", None) is not None:
+        s.set_exchange_tensors(w.J_tensor)
+    kc = getattr(w, "k_c", None)
+    if kc is not None:
+        kc = np.asarray(kc, dtype=np.float64)
+        s.set_cubic_anisotropy(kc[:1] if np.all(kc == kc.flat[0]) else kc)
     s.set_integrator(w.alpha, w.gamma, w.dt)
     s.set_conditions(w.temperature, w.H)
     s.set_rng(w.seed, 0)

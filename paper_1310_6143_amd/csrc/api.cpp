@@ -148,6 +148,10 @@ struct sllg_system {
     HostMaterials mat;
     Dynamics dyn;
     std::vector<double> spins;       // host state until the engine exists
+    // the caller's material arrays, kept so that the cubic anisotropy can
+    // be combined with them whichever is set last
+    std::vector<double> in_mu, in_ku, in_axis, in_kc;
+    int in_per_site = 0, in_kc_per_site = 0;
     int64_t opt_check_symmetry = 1;
     int64_t opt_graph_steps = -1;    // -1 = automatic
     int64_t opt_xcd_remap = 1;
@@ -653,21 +657,64 @@ sllg_status sllg_set_neighbours(sllg_system* sys, const int64_t* row_ptr, const 
     });
 }
 
+namespace {
+
+void install_materials(sllg_system* sys, HostMaterials m)
+{
+    if (sys->eng && m.per_site_material == sys->mat.per_site_material &&
+        m.per_site_axis == sys->mat.per_site_axis && !m.per_site_material && !m.per_site_axis &&
+        m.mat_mu.size() == sys->mat.mat_mu.size() && m.cubic == sys->mat.cubic) {
+        sys->mat = std::move(m);
+        apply_dynamics(sys);   // uniform materials: a table update suffices
+    } else {
+        drop_engine(sys);
+        sys->mat = std::move(m);
+    }
+}
+
+}  // namespace
+
 sllg_status sllg_set_materials(sllg_system* sys, const double* mu_s, const double* k_u,
                                const double* easy_axis, int per_site)
 {
     return guard(sys, [&] {
-        HostMaterials m = build_materials(sys->n, mu_s, k_u, easy_axis, per_site);
-        if (sys->eng && m.per_site_material == sys->mat.per_site_material &&
-            m.per_site_axis == sys->mat.per_site_axis && !m.per_site_material && !m.per_site_axis &&
-            m.mat_mu.size() == sys->mat.mat_mu.size()) {
-            sys->mat = std::move(m);
-            apply_dynamics(sys);   // uniform materials: a table update suffices
-        } else {
-            drop_engine(sys);
-            sys->mat = std::move(m);
-        }
+        HostMaterials m = build_materials(sys->n, mu_s, k_u, easy_axis, per_site,
+                                          sys->in_kc.empty() ? nullptr : sys->in_kc.data(), sys->in_kc_per_site);
+        const size_t cnt = per_site ? (size_t)sys->n : 1;
+        sys->in_mu.assign(mu_s, mu_s + cnt);
+        sys->in_ku.assign(k_u, k_u + cnt);
+        sys->in_axis.assign(easy_axis, easy_axis + 3 * cnt);
+        sys->in_per_site = per_site;
+        install_materials(sys, std::move(m));
         sys->has_mat = true;
+    });
+}
+
+sllg_status sllg_set_cubic_anisotropy(sllg_system* sys, const double* k_c, int per_site)
+{
+    return guard(sys, [&] {
+        if (!sys->has_mat)
+            fail(SLLG_E_STATE, "materials not set (sllg_set_materials)");
+        if (per_site != 0 && per_site != 1)
+            fail(SLLG_E_ARG, "per_site must be 0 or 1");
+        std::vector<double> kc;
+        if (k_c)
+            kc.assign(k_c, k_c + (per_site ? (size_t)sys->n : 1));
+        HostMaterials m = build_materials(sys->n, sys->in_mu.data(), sys->in_ku.data(), sys->in_axis.data(),
+                                          sys->in_per_site, kc.empty() ? nullptr : kc.data(), per_site);
+        sys->in_kc = std::move(kc);
+        sys->in_kc_per_site = per_site;
+        install_materials(sys, std::move(m));
+    });
+}
+
+sllg_status sllg_set_exchange_tensors(sllg_system* sys, const double* J, int n_types)
+{
+    return guard(sys, [&] {
+        if (!sys->has_nb)
+            fail(SLLG_E_STATE, "neighbour list not set (sllg_set_neighbours)");
+        set_exchange_tensors(sys->st, J, n_types);   // validates before it changes anything
+        drop_engine(sys);
     });
 }
 

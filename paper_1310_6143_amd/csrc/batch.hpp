@@ -234,14 +234,14 @@ public:
         hip_check(hipMalloc(&d_nwork_, sizeof(int)), "hipMalloc(nwork)");
         hip_check(hipMemset(d_nwork_, 0, sizeof(int)), "hipMemset");
         host_reps_.resize(max_replicas);
-        for (int ps = 0; ps < 2; ++ps) {
-            int& res = resident_pair_[ps];
-            res = resident_blocks<R>(device_, ps != 0);
+        for (int v = 0; v < 3; ++v) {
+            int& res = resident_v_[v];
+            res = resident_blocks<R>(device_, v);
             if (res < 8)
                 res = 8 * 256;
             res &= ~7;
         }
-        resident_ = resident_pair_[0];
+        resident_ = resident_v_[0];
         // A group's tiles stream about 9 sizeof(R) bytes per site through the
         // L2 per launch (S read, S' and Bc written, then read back); the
         // plane-to-plane reuse spans two planes of a group, kept within a
@@ -469,14 +469,21 @@ public:
                 ((r.flags & kAverage) && (!(r.flags & kRecord) || !r.acc)))
                 fail(SLLG_E_STATE, "replica flags do not match its buffers");
         }
-        // the per-site kernel variant is needed when any replica has per-site data
-        bool per_site = false;
-        for (const auto& sl : slots_)
-            per_site = per_site || (sl.used && (sl.rec.flags & (kPerSiteMaterial | kPerSiteAxis)));
-        if (per_site != per_site_)
+        // kernel variant: 1 when any replica has per-site data, 2 when any
+        // has exchange tensors or cubic anisotropy
+        int variant = 0;
+        for (const auto& sl : slots_) {
+            if (!sl.used)
+                continue;
+            if (sl.rec.flags & (kTensor | kCubic))
+                variant = 2;
+            else if ((sl.rec.flags & kGeneralFlags) && variant < 1)
+                variant = 1;
+        }
+        if (variant != variant_)
             drop_graph();
-        per_site_ = per_site;
-        resident_ = resident_pair_[per_site_ ? 1 : 0];
+        variant_ = variant;
+        resident_ = resident_v_[variant_];
         work_.clear();
         for (size_t q = 0; q < slots_.size(); ++q) {
             host_reps_[q] = slots_[q].used ? slots_[q].rec : ReplicaDev<R>{};
@@ -584,7 +591,7 @@ public:
         last_stream_ = st;
         if (grid_ <= 0)
             return;
-        hip_check(launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 1, remap_, true, per_site_, st),
+        hip_check(launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 1, remap_, true, variant_, st),
                   "measure");
         hip_check(launch_finish<R>(d_reps_, (int)slots_.size(), 1, slot, st), "finish record");
     }
@@ -611,7 +618,7 @@ public:
         if (e == hipSuccess)
             e = hipMemcpy(d_n, &n, sizeof(int), hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = launch_predict<R>(d_reps_, d_all, d_n, n, 1, 0, true, per_site_, st);
+            e = launch_predict<R>(d_reps_, d_all, d_n, n, 1, 0, true, variant_, st);
         if (e == hipSuccess)
             e = launch_finish<R>(d_reps_, (int)slots_.size(), 1, 0, st);
         if (e == hipSuccess)
@@ -682,12 +689,12 @@ private:
         const int nrep = (int)slots_.size();
         hipError_t e = hipSuccess;
         for (int k = 0; k < K && e == hipSuccess; ++k) {
-            e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, false, per_site_, st);
+            e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, false, variant_, st);
             if (e == hipSuccess)
-                e = launch_correct<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, per_site_, st);
+                e = launch_correct<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, variant_, st);
         }
         if (e == hipSuccess)
-            e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 0, remap_, true, per_site_, st);
+            e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 0, remap_, true, variant_, st);
         if (e == hipSuccess)
             e = launch_finish<R>(d_reps_, nrep, 0, 0, st);
         if (e == hipSuccess)
@@ -717,8 +724,8 @@ private:
     int64_t work_cap_ = 0;
     int grid_ = 0;
     int resident_ = 0;
-    int resident_pair_[2] = {0, 0};   // resident workgroups: uniform / per-site kernel variant
-    bool per_site_ = false;
+    int resident_v_[3] = {0, 0, 0};   // resident workgroups of each kernel variant
+    int variant_ = 0;                 // kernel variant the batch needs (launch_predict)
     double grid_scale_ = 1.0;
     int remap_ = SLLG_DEFAULT_REMAP;
     // Columns per group sized from the L2 (group_sites_ sites), the plane's

@@ -60,12 +60,20 @@
 #ifndef SLLG_WAVES_F64_PS
 #define SLLG_WAVES_F64_PS 3
 #endif
+#ifndef SLLG_WAVES_F32_GEN
+#define SLLG_WAVES_F32_GEN 4
+#endif
+#ifndef SLLG_WAVES_F64_GEN
+#define SLLG_WAVES_F64_GEN 2
+#endif
 // Waves per SIMD the step kernels are compiled for: as many as their LDS
-// allows (register use is capped to match).  PS: the variant that reads
-// per-site materials and easy axes.
+// allows (register use is capped to match).  Kernel variant V: 0 uniform
+// material, 1 per-site materials and easy axes, 2 general (also exchange
+// tensors and cubic anisotropy).
 #define SLLG_STEP_ATTRS                                                                        \
     __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(                       \
-        sizeof(R) == 4 ? (PS ? SLLG_WAVES_F32_PS : SLLG_WAVES_F32) : (PS ? SLLG_WAVES_F64_PS : SLLG_WAVES_F64))))
+        sizeof(R) == 4 ? (V == 0 ? SLLG_WAVES_F32 : V == 1 ? SLLG_WAVES_F32_PS : SLLG_WAVES_F32_GEN)   \
+                       : (V == 0 ? SLLG_WAVES_F64 : V == 1 ? SLLG_WAVES_F64_PS : SLLG_WAVES_F64_GEN))))
 #define SLLG_PRAGMA(x) _Pragma(#x)
 #define SLLG_UNROLL(n) SLLG_PRAGMA(unroll n)
 
@@ -265,6 +273,10 @@ struct Shared {
     uint16_t pat_start[kMaxPatterns + 1];
     uint16_t pat_far[kMaxPatterns];
     PatEntry<R> pat[kMaxPatternEntries];
+    // exchange tensors (kTensor): jm[type], jm[kMaxTypes] = 0 for padding
+    // entries, and the type of every pattern entry
+    R jm[kMaxTypes + 1][9];
+    uint8_t ptype[kMaxPatternEntries];
 };
 
 // The tile being integrated: spins of sites [i0 - halo, i0 + tile + halo)
@@ -277,11 +289,16 @@ struct TileLds {
 };
 
 // Caller synchronises before (tables may still be read) and after.
-template <typename R>
+template <typename R, bool TX>
 __device__ __forceinline__ void stage_tables(const ReplicaDev<R>& r, Shared<R>& sh)
 {
     if (threadIdx.x < kMaxTypes)
         sh.jt[threadIdx.x] = r.jt[threadIdx.x];
+    const bool tensor = TX && (r.flags & kTensor);
+    if (tensor && threadIdx.x < (kMaxTypes + 1) * 9) {
+        const int t = threadIdx.x / 9, q = threadIdx.x % 9;
+        sh.jm[t][q] = t < kMaxTypes ? r.jm[t][q] : (R)0;
+    }
     if (r.flags & kStencil) {
         const int np = r.n_patterns;
         for (int q = threadIdx.x; q <= np; q += kBlockThreads)
@@ -293,6 +310,8 @@ __device__ __forceinline__ void stage_tables(const ReplicaDev<R>& r, Shared<R>& 
             const int32_t raw = gload(r.pat_tab, q);
             sh.pat[q].off = (raw >> 4) * (int)(3 * sizeof(R));
             sh.pat[q].J = (raw >> 4) != 0 ? r.jt[raw & 15] : (R)0;   // offset 0: padding
+            if (tensor)
+                sh.ptype[q] = (raw >> 4) != 0 ? (uint8_t)(raw & 15) : (uint8_t)kMaxTypes;
         }
     }
 }
@@ -350,16 +369,42 @@ __device__ __forceinline__ int site_bytes(int x)
     return (int)__umul24((unsigned)x, 3u * (unsigned)sizeof(R));
 }
 
+// h += M S_j for a 3x3 row-major coupling matrix M.
+template <typename R>
+__device__ __forceinline__ void add_link(V3<R>& h, const R* M, const V3<R>& sj)
+{
+    h.x += M[0] * sj.x + M[1] * sj.y + M[2] * sj.z;
+    h.y += M[3] * sj.x + M[4] * sj.y + M[5] * sj.z;
+    h.z += M[6] * sj.x + M[7] * sj.y + M[8] * sj.z;
+}
+
+// h += (coupling of a link) S_j: the scalar J, or with exchange tensors
+// (TX and kTensor) the matrix of the link's type.
+template <typename R, bool TX>
+__device__ __forceinline__ void add_coupled(V3<R>& h, bool tensor, const Shared<R>& sh, int type, R J,
+                                            const V3<R>& sj)
+{
+    if (TX && tensor) {
+        add_link(h, sh.jm[type], sj);
+    } else {
+        h.x += J * sj.x;
+        h.y += J * sj.y;
+        h.z += J * sj.z;
+    }
+}
+
 // sum_k J_k S[j_k] over the neighbours of site i (tile position l, window
 // base site wb): the near part from the window, the far part from global
 // memory, each in the row's order, then near + far.  `overlap` runs while
-// the far gathers are in flight.
-template <typename R, typename F>
+// the far gathers are in flight.  TX: exchange tensors allowed (general
+// kernel variant).
+template <typename R, bool TX, typename F>
 __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* __restrict__ S,
                                               const Shared<R>& sh, const TileLds<R>& tl, int i, int l,
                                               int wb, int wbyte, F&& overlap)
 {
     V3<R> hn{0, 0, 0}, hf{0, 0, 0};
+    const bool tensor = TX && (r.flags & kTensor);
     if (r.flags & kStencil) {
         // byte offsets fit in 31 bits in the stencil form
         const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, r.n * (int)(3 * sizeof(R)));
@@ -384,36 +429,26 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
             for (int k = b; k < f; ++k) {
                 const PatEntry<R> pe = sh.pat[k];
                 const V3<R> sj = bload3(rs, ib + pe.off, R(0));
-                hn.x += pe.J * sj.x;
-                hn.y += pe.J * sj.y;
-                hn.z += pe.J * sj.z;
+                add_coupled<R, TX>(hn, tensor, sh, TX ? sh.ptype[k] : 0, pe.J, sj);
             }
         } else {
             SLLG_UNROLL(SLLG_NEAR_UNROLL)
             for (int k = b; k < f; ++k) {
                 const PatEntry<R> pe = sh.pat[k];
                 const V3<R> sj = wload3(tl.win, wbyte + pe.off);
-                hn.x += pe.J * sj.x;
-                hn.y += pe.J * sj.y;
-                hn.z += pe.J * sj.z;
+                add_coupled<R, TX>(hn, tensor, sh, TX ? sh.ptype[k] : 0, pe.J, sj);
             }
         }
         if (far) {
 #pragma unroll
-            for (int q = 0; q < kFarRegs; ++q) {
-                const R J = fp[q].J;
-                hf.x += J * fr[q].x;
-                hf.y += J * fr[q].y;
-                hf.z += J * fr[q].z;
-            }
+            for (int q = 0; q < kFarRegs; ++q)
+                add_coupled<R, TX>(hf, tensor, sh, TX ? sh.ptype[f + q] : 0, fp[q].J, fr[q]);
         }
         SLLG_UNROLL(SLLG_GATHER_UNROLL)
         for (int k = f + kFarRegs; k < e; ++k) {
             const PatEntry<R> pe = sh.pat[k];
             const V3<R> sj = bload3(rs, ib + pe.off, R(0));
-            hf.x += pe.J * sj.x;
-            hf.y += pe.J * sj.y;
-            hf.z += pe.J * sj.z;
+            add_coupled<R, TX>(hf, tensor, sh, TX ? sh.ptype[k] : 0, pe.J, sj);
         }
     } else {
         overlap();
@@ -423,21 +458,15 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
 #pragma unroll 2
         for (int k = nn; k < d; ++k) {
             const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
-            const R J = sh.jt[e >> kColBits];
             const V3<R> sj = load3(S, (int64_t)(e & kColMask));
-            hf.x += J * sj.x;
-            hf.y += J * sj.y;
-            hf.z += J * sj.z;
+            add_coupled<R, TX>(hf, tensor, sh, (int)(e >> kColBits), sh.jt[e >> kColBits], sj);
         }
         SLLG_UNROLL(SLLG_NEAR_UNROLL)
         for (int k = 0; k < nn; ++k) {
             const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
-            const R J = sh.jt[e >> kColBits];
             const V3<R> sj = (r.flags & kDirect) ? load3(S, (int64_t)(e & kColMask))
                                                  : wload3(tl.win, site_bytes<R>((int)(e & kColMask) - wb));
-            hn.x += J * sj.x;
-            hn.y += J * sj.y;
-            hn.z += J * sj.z;
+            add_coupled<R, TX>(hn, tensor, sh, (int)(e >> kColBits), sh.jt[e >> kColBits], sj);
         }
     }
     return V3<R>{hn.x + hf.x, hn.y + hf.y, hn.z + hf.z};
@@ -633,6 +662,8 @@ __device__ __forceinline__ MaterialDev<R> site_material(const ReplicaDev<R>& r, 
     m.axis[0] = g.axis[0];
     m.axis[1] = g.axis[1];
     m.axis[2] = g.axis[2];
+    m.cub = g.cub;
+    m.kc_mu = g.kc_mu;
     m.mu_s = g.mu_s;
     return m;
 }
@@ -664,6 +695,8 @@ __device__ __forceinline__ MaterialDev<R> uniform_material(const ReplicaDev<R>& 
     m.axis[0] = wave_uniform(g.axis[0]);
     m.axis[1] = wave_uniform(g.axis[1]);
     m.axis[2] = wave_uniform(g.axis[2]);
+    m.cub = 0;     // cubic anisotropy takes the general variant
+    m.kc_mu = 0;
     m.mu_s = wave_uniform(g.mu_s);
     return m;
 }
@@ -674,6 +707,23 @@ __device__ __forceinline__ V3<R> site_axis(const ReplicaDev<R>& r, const Materia
     if (r.flags & kPerSiteAxis)
         return load3(r.axis, i);
     return V3<R>{m.axis[0], m.axis[1], m.axis[2]};
+}
+
+// Sx^4 + Sy^4 + Sz^4.
+template <typename R>
+__device__ __forceinline__ R quartic(const V3<R>& s)
+{
+    const R x2 = s.x * s.x, y2 = s.y * s.y, z2 = s.z * s.z;
+    return x2 * x2 + y2 * y2 + z2 * z2;
+}
+
+// Adds the cubic anisotropy field -(2 k_c/mu_s)(Sx^3, Sy^3, Sz^3).
+template <typename R>
+__device__ __forceinline__ void add_cubic(const MaterialDev<R>& m, const V3<R>& s, V3<R>& h)
+{
+    h.x += m.cub * s.x * s.x * s.x;
+    h.y += m.cub * s.y * s.y * s.y;
+    h.z += m.cub * s.z * s.z * s.z;
 }
 
 // Adds the thermal field sigma * g (normals g drawn for this site and step).
@@ -702,11 +752,12 @@ __device__ __forceinline__ void add_thermal(const MaterialDev<R>& m, const R g[3
 // ---------------------------------------------------------------------------
 // The sites of one tile (PS: per-site materials or axes; otherwise the
 // material is read once into scalar registers).
-template <typename R, bool MEASURE, bool PS>
+template <typename R, bool MEASURE, int V>
 __device__ __forceinline__ void predict_sites(const ReplicaDev<R>& r, const R* __restrict__ S,
                                               const Shared<R>& sh, const TileLds<R>& tl, int i0, int wb,
                                               int k, bool partials, double v[4])
 {
+    constexpr bool PS = V != 0, TX = V == 2;
     const int T = r.tile;
     const MaterialDev<R> m0 = PS ? MaterialDev<R>{} : uniform_material(r);
     for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
@@ -717,7 +768,7 @@ __device__ __forceinline__ void predict_sites(const ReplicaDev<R>& r, const R* _
         const int wbyte = site_bytes<R>(l + r.halo);
         const V3<R> s = (r.flags & kDirect) ? load3(S, i) : wload3(tl.win, wbyte);
         R g[3] = {0, 0, 0};
-        const V3<R> sum = exchange_sum(r, S, sh, tl, i, l, wb, wbyte, [&] {
+        const V3<R> sum = exchange_sum<R, TX>(r, S, sh, tl, i, l, wb, wbyte, [&] {
             if (!MEASURE && m.sigma != (R)0)
                 thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
         });
@@ -725,16 +776,22 @@ __device__ __forceinline__ void predict_sites(const ReplicaDev<R>& r, const R* _
         const V3<R> e = PS ? site_axis(r, m, i) : V3<R>{m.axis[0], m.axis[1], m.axis[2]};
         const R se = dot(s, e);
         const V3<R> Happ{r.H[0], r.H[1], r.H[2]};
+        const bool cubic = TX && (r.flags & kCubic);
         if (partials) {
             // in units of mu_ref: mu_s/mu_ref S and mu_s/mu_ref (-E_i/mu_s)
             v[0] += (double)(m.mu_frac * s.x);
             v[1] += (double)(m.mu_frac * s.y);
             v[2] += (double)(m.mu_frac * s.z);
-            v[3] += (double)(m.mu_frac * ((R)0.5 * dot(s, hex) + m.ku_mu * se * se + dot(s, Happ)));
+            R u = (R)0.5 * dot(s, hex) + m.ku_mu * se * se + dot(s, Happ);
+            if (cubic)
+                u -= (R)0.5 * m.kc_mu * quartic(s);
+            v[3] += (double)(m.mu_frac * u);
         }
         if (!MEASURE) {
             V3<R> h{hex.x + m.ani * se * e.x + Happ.x, hex.y + m.ani * se * e.y + Happ.y,
                     hex.z + m.ani * se * e.z + Happ.z};
+            if (cubic)
+                add_cubic(m, s, h);
             add_thermal(m, g, h);
             const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
             const V3<R> sp = normalised(V3<R>{s.x + ds.x, s.y + ds.y, s.z + ds.z});
@@ -744,7 +801,7 @@ __device__ __forceinline__ void predict_sites(const ReplicaDev<R>& r, const R* _
     }
 }
 
-template <typename R, bool MEASURE, bool PS>
+template <typename R, bool MEASURE, int V>
 __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps,
                                           const WorkItem* __restrict__ work,
                                           const int* __restrict__ n_work, int k, int remap)
@@ -768,7 +825,7 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
         const int i0 = w.block * T, wb = i0 - r.halo;
         __syncthreads();   // every lane is done with the previous tile's LDS
         if (w.replica != staged) {
-            stage_tables(r, sh);
+            stage_tables<R, V == 2>(r, sh);
             staged = w.replica;
         }
         if (!(r.flags & kDirect))
@@ -777,10 +834,10 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
             stage_ids(r.pat_id, r.n, i0, T, tl.pid);
         __syncthreads();
         double v[4] = {0.0, 0.0, 0.0, 0.0};
-        if (PS && (r.flags & (kPerSiteMaterial | kPerSiteAxis)))
-            predict_sites<R, MEASURE, true>(r, S, sh, tl, i0, wb, k, partials, v);
+        if (V != 0 && (r.flags & kGeneralFlags))
+            predict_sites<R, MEASURE, V>(r, S, sh, tl, i0, wb, k, partials, v);
         else
-            predict_sites<R, MEASURE, false>(r, S, sh, tl, i0, wb, k, partials, v);
+            predict_sites<R, MEASURE, 0>(r, S, sh, tl, i0, wb, k, partials, v);
         if (partials) {
             double out[4];
             block_sum4(v, out, red);
@@ -808,11 +865,12 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
 // ping-pong buffer.  Workgroups whose tile opens a group of kGroupTiles also
 // sum that group of the predictor's partials.
 // ---------------------------------------------------------------------------
-template <typename R, bool PS>
+template <typename R, int V>
 __device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* __restrict__ Sp,
                                               R* __restrict__ Sn, const Shared<R>& sh,
                                               const TileLds<R>& tl, int i0, int wb, int k)
 {
+    constexpr bool PS = V != 0, TX = V == 2;
     const int T = r.tile;
     const MaterialDev<R> m0 = PS ? MaterialDev<R>{} : uniform_material(r);
     for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
@@ -824,7 +882,7 @@ __device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* _
         const V3<R> sp = (r.flags & kDirect) ? load3(Sp, i) : wload3(tl.win, wbyte);
         const V3<R> b = load3_once((const R*)r.Bc, i);
         R g[3] = {0, 0, 0};
-        const V3<R> sum = exchange_sum(r, Sp, sh, tl, i, l, wb, wbyte, [&] {
+        const V3<R> sum = exchange_sum<R, TX>(r, Sp, sh, tl, i, l, wb, wbyte, [&] {
             if (m.sigma != (R)0)
                 thermal_normals(r.seed, r.step + (uint64_t)k, (uint32_t)i, g);
         });
@@ -833,6 +891,8 @@ __device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* _
         V3<R> h{m.mu_rel * sum.x + m.ani * se * e.x + r.H[0],
                 m.mu_rel * sum.y + m.ani * se * e.y + r.H[1],
                 m.mu_rel * sum.z + m.ani * se * e.z + r.H[2]};
+        if (TX && (r.flags & kCubic))
+            add_cubic(m, sp, h);
         add_thermal(m, g, h);
         const V3<R> ds = llg_step(sp, h, r.gdt, r.alpha);
         const V3<R> sn = normalised(V3<R>{b.x + (R)0.5 * ds.x, b.y + (R)0.5 * ds.y, b.z + (R)0.5 * ds.z});
@@ -840,7 +900,7 @@ __device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* _
     }
 }
 
-template <typename R, bool PS>
+template <typename R, int V>
 __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps,
                                           const WorkItem* __restrict__ work,
                                           const int* __restrict__ n_work, int k, int remap)
@@ -860,7 +920,7 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
         const int i0 = w.block * T, wb = i0 - r.halo;
         __syncthreads();   // every lane is done with the previous tile's LDS
         if (w.replica != staged) {
-            stage_tables(r, sh);
+            stage_tables<R, V == 2>(r, sh);
             staged = w.replica;
         }
         if (!(r.flags & kDirect))
@@ -869,10 +929,10 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
             stage_ids(r.pat_id, r.n, i0, T, tl.pid);
         __syncthreads();
         R* __restrict__ Sn = r.S[(r.parity + k + 1) & 1];
-        if (PS && (r.flags & (kPerSiteMaterial | kPerSiteAxis)))
-            correct_sites<R, true>(r, Sp, Sn, sh, tl, i0, wb, k);
+        if (V != 0 && (r.flags & kGeneralFlags))
+            correct_sites<R, V>(r, Sp, Sn, sh, tl, i0, wb, k);
         else
-            correct_sites<R, false>(r, Sp, Sn, sh, tl, i0, wb, k);
+            correct_sites<R, 0>(r, Sp, Sn, sh, tl, i0, wb, k);
         if ((r.flags & kRecord) && k >= 1 && (w.block % kGroupTiles) == 0)
             group_reduce(r, w.block / kGroupTiles, red);
     }
@@ -949,6 +1009,7 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
 {
     V3<R> h{0, 0, 0};
     const char* sb = (const char*)S;
+    const bool tensor = (r.flags & kTensor) != 0;
     if (r.flags & kStencil) {
         const int p = gload(r.pat_id, i);
         const int b = sh.pat_start[p], e = sh.pat_start[p + 1];
@@ -956,19 +1017,18 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
         for (int k = b; k < e; k += kMcBatch) {
             V3<R> sj[kMcBatch];
             R J[kMcBatch];
+            int ty[kMcBatch];
 #pragma unroll
             for (int u = 0; u < kMcBatch; ++u) {
                 const int kk = k + u < e ? k + u : e - 1;
                 const PatEntry<R> pe = sh.pat[kk];
                 J[u] = k + u < e ? pe.J : (R)0;
+                ty[u] = tensor ? (k + u < e ? (int)sh.ptype[kk] : kMaxTypes) : 0;
                 sj[u] = load3((const R*)(si + pe.off), 0);
             }
 #pragma unroll
-            for (int u = 0; u < kMcBatch; ++u) {
-                h.x += J[u] * sj[u].x;
-                h.y += J[u] * sj[u].y;
-                h.z += J[u] * sj[u].z;
-            }
+            for (int u = 0; u < kMcBatch; ++u)
+                add_coupled<R, true>(h, tensor, sh, ty[u], J[u], sj[u]);
         }
         return h;
     }
@@ -985,10 +1045,8 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
             sj[u] = load3(S, (int64_t)(ent[u] & kColMask));
 #pragma unroll
         for (int u = 0; u < kMcBatch; ++u) {
-            const R J = k + u < d ? sh.jt[ent[u] >> kColBits] : (R)0;
-            h.x += J * sj[u].x;
-            h.y += J * sj[u].y;
-            h.z += J * sj[u].z;
+            const int t = k + u < d ? (int)(ent[u] >> kColBits) : kMaxTypes;
+            add_coupled<R, true>(h, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj[u]);
         }
     }
     return h;
@@ -1004,7 +1062,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __res
     const ReplicaDev<R>& r = *rep;
     if (threadIdx.x == 0)
         acc_block = 0;
-    stage_tables(r, sh);
+    stage_tables<R, true>(r, sh);
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) {
@@ -1030,9 +1088,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __res
         }
         const V3<R> e = site_axis(r, m, i);
         const R se = dot(s, e), te = dot(tr, e);
-        // dE = -mu_s [(S' - S).(H_exc + H) + (k_u/mu_s)((S'.e)^2 - (S.e)^2)]
+        // dE = -mu_s [(S' - S).(H_exc + H) + (k_u/mu_s)((S'.e)^2 - (S.e)^2)
+        //             - (k_c/(2 mu_s))(S'x^4 + S'y^4 + S'z^4 - Sx^4 - Sy^4 - Sz^4)]
         const V3<R> d{tr.x - s.x, tr.y - s.y, tr.z - s.z};
-        const R bracket = dot(d, h) + m.ku_mu * (te * te - se * se);
+        R bracket = dot(d, h) + m.ku_mu * (te * te - se * se);
+        if (r.flags & kCubic)
+            bracket -= (R)0.5 * m.kc_mu * (quartic(tr) - quartic(s));
         // accept when dE <= 0, else with probability exp(-dE/(kB T)); the
         // decision is taken in the kernel's precision
         bool accept = bracket >= (R)0;
@@ -1103,33 +1164,42 @@ __global__ void k_accumulate(const ReplicaDev<R>* __restrict__ reps, int n_rep)
 // ---------------------------------------------------------------------------
 template <typename R>
 hipError_t launch_predict(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work,
-                          int grid, int k, int remap, bool measure, bool per_site, hipStream_t st)
+                          int grid, int k, int remap, bool measure, int variant, hipStream_t st)
 {
     if (grid <= 0)
         return hipSuccess;
     const dim3 g(grid), b(kBlockThreads);
-    if (measure && per_site)
-        hipLaunchKernelGGL((k_predict<R, true, true>), g, b, 0, st, reps, work, n_work, k, remap);
-    else if (measure)
-        hipLaunchKernelGGL((k_predict<R, true, false>), g, b, 0, st, reps, work, n_work, k, remap);
-    else if (per_site)
-        hipLaunchKernelGGL((k_predict<R, false, true>), g, b, 0, st, reps, work, n_work, k, remap);
-    else
-        hipLaunchKernelGGL((k_predict<R, false, false>), g, b, 0, st, reps, work, n_work, k, remap);
+    if (measure) {
+        if (variant == 2)
+            hipLaunchKernelGGL((k_predict<R, true, 2>), g, b, 0, st, reps, work, n_work, k, remap);
+        else if (variant == 1)
+            hipLaunchKernelGGL((k_predict<R, true, 1>), g, b, 0, st, reps, work, n_work, k, remap);
+        else
+            hipLaunchKernelGGL((k_predict<R, true, 0>), g, b, 0, st, reps, work, n_work, k, remap);
+    } else {
+        if (variant == 2)
+            hipLaunchKernelGGL((k_predict<R, false, 2>), g, b, 0, st, reps, work, n_work, k, remap);
+        else if (variant == 1)
+            hipLaunchKernelGGL((k_predict<R, false, 1>), g, b, 0, st, reps, work, n_work, k, remap);
+        else
+            hipLaunchKernelGGL((k_predict<R, false, 0>), g, b, 0, st, reps, work, n_work, k, remap);
+    }
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_correct(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work,
-                          int grid, int k, int remap, bool per_site, hipStream_t st)
+                          int grid, int k, int remap, int variant, hipStream_t st)
 {
     if (grid <= 0)
         return hipSuccess;
     const dim3 g(grid), b(kBlockThreads);
-    if (per_site)
-        hipLaunchKernelGGL((k_correct<R, true>), g, b, 0, st, reps, work, n_work, k, remap);
+    if (variant == 2)
+        hipLaunchKernelGGL((k_correct<R, 2>), g, b, 0, st, reps, work, n_work, k, remap);
+    else if (variant == 1)
+        hipLaunchKernelGGL((k_correct<R, 1>), g, b, 0, st, reps, work, n_work, k, remap);
     else
-        hipLaunchKernelGGL((k_correct<R, false>), g, b, 0, st, reps, work, n_work, k, remap);
+        hipLaunchKernelGGL((k_correct<R, 0>), g, b, 0, st, reps, work, n_work, k, remap);
     return hipGetLastError();
 }
 
@@ -1172,13 +1242,15 @@ hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, 
 }
 
 template <typename R>
-int resident_blocks(int device, bool per_site)
+int resident_blocks(int device, int variant)
 {
     int cus = 0, a = 0, b = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
         return 0;
-    const void* kp = per_site ? (const void*)k_predict<R, false, true> : (const void*)k_predict<R, false, false>;
-    const void* kc = per_site ? (const void*)k_correct<R, true> : (const void*)k_correct<R, false>;
+    const void* kp = variant == 2 ? (const void*)k_predict<R, false, 2>
+                     : variant == 1 ? (const void*)k_predict<R, false, 1> : (const void*)k_predict<R, false, 0>;
+    const void* kc = variant == 2 ? (const void*)k_correct<R, 2>
+                     : variant == 1 ? (const void*)k_correct<R, 1> : (const void*)k_correct<R, 0>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kp, kBlockThreads, 0) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kc, kBlockThreads, 0) != hipSuccess)
         return 0;
@@ -1207,14 +1279,14 @@ hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t s
 
 #define SLLG_INSTANTIATE(R)                                                                          \
     template hipError_t launch_predict<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, \
-                                          int, bool, bool, hipStream_t);                             \
+                                          int, bool, int, hipStream_t);                              \
     template hipError_t launch_correct<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, \
-                                          int, bool, hipStream_t);                                   \
+                                          int, int, hipStream_t);                                    \
     template hipError_t launch_accumulate<R>(const ReplicaDev<R>*, int, hipStream_t);                \
     template hipError_t launch_finish<R>(const ReplicaDev<R>*, int, int, int, hipStream_t);         \
     template hipError_t launch_advance<R>(ReplicaDev<R>*, int, hipStream_t);                         \
     template hipError_t launch_noise<R>(uint64_t, uint64_t, int, double*, hipStream_t);             \
-    template int resident_blocks<R>(int, bool);                                                       \
+    template int resident_blocks<R>(int, int);                                                        \
     template hipError_t launch_mc<R>(const ReplicaDev<R>*, const int32_t*, int, uint64_t, double, double, \
                                      unsigned long long*, hipStream_t);
 

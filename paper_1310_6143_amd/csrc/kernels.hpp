@@ -15,15 +15,16 @@ namespace sllg {
 // `grid` workgroups are launched; those whose (remapped) index is at or past
 // *n_work (device memory) exit at once, so a captured graph can serve any
 // batch up to `grid` blocks.
-// per_site selects the kernels that can read per-site materials and easy
-// axes (needed when any replica of the batch has them).
+// variant selects the kernels: 0 uniform materials only, 1 also per-site
+// materials and easy axes, 2 also exchange tensors and cubic anisotropy (the
+// highest any replica of the batch needs).
 template <typename R>
 hipError_t launch_predict(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work,
-                          int grid, int k, int remap, bool measure, bool per_site, hipStream_t st);
+                          int grid, int k, int remap, bool measure, int variant, hipStream_t st);
 // Corrector of step k of the current chunk.
 template <typename R>
 hipError_t launch_correct(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work,
-                          int grid, int k, int remap, bool per_site, hipStream_t st);
+                          int grid, int k, int remap, int variant, hipStream_t st);
 // Thermal-average block sums of every replica with kAverage.
 template <typename R>
 hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t st);
@@ -42,7 +43,7 @@ hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStr
 // Workgroups of the step kernels that fit on the device at once
 // (compute units x resident blocks per unit); 0 if it cannot be queried.
 template <typename R>
-int resident_blocks(int device, bool per_site);
+int resident_blocks(int device, int variant);
 
 // One Monte Carlo sweep of one colour class (count sites listed in
 // `sites`) of the replica at *rep, step number `step` for the counters;

@@ -93,6 +93,8 @@ struct MaterialDev {
     R ku_mu;        // k_u / mu_s    (anisotropy energy per unit moment)
     R sigma;        // thermal-field width sqrt(2 lambda kB T / (gamma mu_s dt))
     R axis[3];      // easy axis when it is uniform over the material
+    R cub;          // -2 k_c / mu_s (cubic anisotropy field factor, kCubic)
+    R kc_mu;        // k_c / mu_s    (cubic anisotropy energy per unit moment)
     double mu_s;    // J/T, for the energy and magnetisation sums
 };
 
@@ -105,7 +107,12 @@ enum ReplicaFlags : int32_t {
     kStencil = 32,          // neighbours in stencil form (pat_id / pat_tab) instead of SELL
     kNoFar = 64,            // stencil form without far links (every neighbour in the LDS window)
     kDirect = 128,          // no LDS window: every neighbour and the own spin read from global memory
+    kTensor = 256,          // exchange tensors jm[type] instead of the scalars jt[type]
+    kCubic = 512,           // cubic anisotropy (material fields cub, kc_mu)
 };
+
+// Flags that need the general (per-site) kernel variant.
+constexpr int32_t kGeneralFlags = kPerSiteMaterial | kPerSiteAxis | kTensor | kCubic;
 
 template <typename R>
 struct ReplicaDev {
@@ -127,6 +134,7 @@ struct ReplicaDev {
     double* records;                // [cap][4] per-step m (3) and E
     double* acc;                    // [avg_blocks][5] sums of |m|, m (3), E per averaging block
     R jt[kMaxTypes];                // J / mu_ref per type (tesla)
+    R jm[kMaxTypes][9];             // exchange tensor / mu_ref per type, row-major (kTensor)
     R gdt;                          // gamma / (1 + lambda^2) * dt
     R alpha;                        // lambda
     R H[3];                         // applied field (T)

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <unordered_map>
+#include <tuple>
 #include <utility>
 
 namespace sllg {
@@ -59,22 +60,29 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
                 fail(SLLG_E_ARG, "interaction type out of range in row " + std::to_string(i));
         }
     }
+    HostStructure s;
     if (check_symmetry) {
+        // every link i -> j of type t needs a reverse link j -> i of a type u
+        // with the same coupling (u = t, or a type with an equal J, which
+        // exchange tensors may tell apart: the pairs (t, u) are recorded)
         for (int64_t i = 0; i < n; ++i) {
             for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
                 const int64_t j = col[k];
                 const int t = ntype ? ntype[k] : 0;
-                bool found = false;
-                for (int64_t q = row_ptr[j]; q < row_ptr[j + 1] && !found; ++q)
-                    found = (col[q] == i) && ((ntype ? ntype[q] : 0) == t);
-                if (!found)
+                int u = -1;
+                for (int64_t q = row_ptr[j]; q < row_ptr[j + 1] && u != t; ++q) {
+                    const int tq = ntype ? ntype[q] : 0;
+                    if (col[q] == i && (u < 0 || tq == t) && J[tq] == J[t])
+                        u = tq;
+                }
+                if (u < 0)
                     fail(SLLG_E_ARG, "link " + std::to_string(i) + "->" + std::to_string(j) +
-                                         " has no reverse link of the same type");
+                                         " has no reverse link with the same J");
+                s.reverse[t] |= (uint16_t)(1u << u);
             }
         }
+        s.rev_known = true;
     }
-
-    HostStructure s;
     s.n = n;
     s.nnz = nnz;
     s.n_types = n_types;
@@ -193,6 +201,33 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
     return s;
 }
 
+void set_exchange_tensors(HostStructure& s, const double* Jt, int n_types)
+{
+    if (!Jt) {
+        s.tensor = false;
+        s.Jt.clear();
+        return;
+    }
+    if (n_types != s.n_types)
+        fail(SLLG_E_ARG, "exchange tensors: n_types must match the neighbour list's (" +
+                             std::to_string(s.n_types) + ")");
+    for (int q = 0; q < 9 * n_types; ++q)
+        if (!std::isfinite(Jt[q]))
+            fail(SLLG_E_ARG, "exchange tensor holds a non-finite value");
+    if (s.rev_known)
+        for (int t = 0; t < n_types; ++t)
+            for (int u = 0; u < n_types; ++u)
+                if (s.reverse[t] & (1u << u))
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b)
+                            if (Jt[9 * u + 3 * b + a] != Jt[9 * t + 3 * a + b])
+                                fail(SLLG_E_ARG, "exchange tensor of type " + std::to_string(u) +
+                                                     " is not the transpose of type " + std::to_string(t) +
+                                                     ", which its links reverse");
+    s.Jt.assign(Jt, Jt + 9 * n_types);
+    s.tensor = true;
+}
+
 void build_colours(HostStructure& s, const int64_t* row_ptr, const int32_t* col)
 {
     const int64_t n = s.n;
@@ -224,12 +259,18 @@ void build_colours(HostStructure& s, const int64_t* row_ptr, const int32_t* col)
 }
 
 HostMaterials build_materials(int64_t n, const double* mu_s, const double* k_u,
-                              const double* easy_axis, int per_site)
+                              const double* easy_axis, int per_site, const double* k_c, int kc_per_site)
 {
     if (!mu_s || !k_u || !easy_axis)
         fail(SLLG_E_ARG, "mu_s, k_u and easy_axis must not be NULL");
     if (per_site != 0 && per_site != 1)
         fail(SLLG_E_ARG, "per_site must be 0 or 1");
+    if (kc_per_site != 0 && kc_per_site != 1)
+        fail(SLLG_E_ARG, "per_site must be 0 or 1");
+    if (k_c)
+        for (int64_t i = 0; i < (kc_per_site ? n : 1); ++i)
+            if (!std::isfinite(k_c[i]))
+                fail(SLLG_E_ARG, "k_c must be finite");
     const int64_t m = per_site ? n : 1;
     for (int64_t i = 0; i < m; ++i) {
         if (!(mu_s[i] > 0.0) || !std::isfinite(mu_s[i]))
@@ -243,23 +284,29 @@ HostMaterials build_materials(int64_t n, const double* mu_s, const double* k_u,
     }
     HostMaterials h;
     h.n = n;
-    std::map<std::pair<double, double>, int> ids;
-    std::vector<uint8_t> matid(per_site ? n : 0);
-    for (int64_t i = 0; i < m; ++i) {
-        auto key = std::make_pair(mu_s[i], k_u[i]);
+    const bool kc_sites = k_c && kc_per_site;
+    const int64_t mm = (per_site || kc_sites) ? n : 1;   // sites that may differ
+    std::map<std::tuple<double, double, double>, int> ids;
+    std::vector<uint8_t> matid(mm > 1 || per_site ? n : 0);
+    for (int64_t i = 0; i < mm; ++i) {
+        const double mu = mu_s[per_site ? i : 0], ku = k_u[per_site ? i : 0];
+        const double kc = k_c ? k_c[kc_sites ? i : 0] : 0.0;
+        auto key = std::make_tuple(mu, ku, kc);
         auto it = ids.find(key);
         int id;
         if (it == ids.end()) {
             id = (int)ids.size();
             if (id >= 256)
-                fail(SLLG_E_ARG, "more than 256 distinct (mu_s, k_u) materials");
+                fail(SLLG_E_ARG, "more than 256 distinct (mu_s, k_u, k_c) materials");
             ids.emplace(key, id);
-            h.mat_mu.push_back(mu_s[i]);
-            h.mat_ku.push_back(k_u[i]);
+            h.mat_mu.push_back(mu);
+            h.mat_ku.push_back(ku);
+            h.mat_kc.push_back(kc);
+            h.cubic = h.cubic || kc != 0.0;
         } else {
             id = it->second;
         }
-        if (per_site)
+        if (!matid.empty())
             matid[i] = (uint8_t)id;
     }
     h.per_site_material = h.mat_mu.size() > 1;
@@ -343,6 +390,9 @@ std::vector<MaterialDev<R>> material_table(const HostMaterials& m, const Dynamic
         t[q].axis[0] = (R)m.axis[0];
         t[q].axis[1] = (R)m.axis[1];
         t[q].axis[2] = (R)m.axis[2];
+        const double kc = q < m.mat_kc.size() ? m.mat_kc[q] : 0.0;
+        t[q].cub = (R)(-2.0 * kc / mu);
+        t[q].kc_mu = (R)(kc / mu);
         t[q].mu_s = mu;
     }
     return t;
@@ -352,8 +402,11 @@ template <typename R>
 void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMaterials& m,
                      const Dynamics& d)
 {
-    for (int t = 0; t < kMaxTypes; ++t)
+    for (int t = 0; t < kMaxTypes; ++t) {
         rec.jt[t] = t < s.n_types ? (R)(s.J[t] / m.mu_ref) : (R)0;
+        for (int q = 0; q < 9; ++q)
+            rec.jm[t][q] = s.tensor && t < s.n_types ? (R)(s.Jt[9 * t + q] / m.mu_ref) : (R)0;
+    }
     rec.gdt = (R)(d.gamma / (1.0 + d.alpha * d.alpha) * d.dt);
     rec.alpha = (R)d.alpha;
     rec.H[0] = (R)d.H[0];
@@ -376,6 +429,10 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
         flags |= kStencil;
     if (s.stencil && s.no_far)
         flags |= kNoFar;
+    if (s.tensor)
+        flags |= kTensor;
+    if (m.cubic)
+        flags |= kCubic;
     rec.flags = flags;
     rec.n_patterns = s.stencil ? (int32_t)s.pat_start.size() - 1 : 0;
 }

@@ -37,6 +37,13 @@ struct HostStructure {
     int halo = 0;                      // window halo: max near |col - row|, rounded up to 4
     int tile_request = 0;              // sites per tile: 0 from n (tile_for), -1 the largest, else this
     std::vector<double> J;             // joules per link, per type
+    // exchange tensors (set_exchange_tensors): 9 per type, row-major, joules
+    bool tensor = false;
+    std::vector<double> Jt;
+    // reverse[t] bit u: some link of type t has its reverse link of type u
+    // (recorded by the symmetry check; rev_known = false without it)
+    bool rev_known = false;
+    uint16_t reverse[kMaxTypes] = {};
     std::vector<uint32_t> nb;          // packed entries, 64 rows per slice, column-major
     std::vector<int64_t> slice_off;    // [n_slices + 1]
     std::vector<uint16_t> deg;         // [n] near << 8 | degree
@@ -62,17 +69,25 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
                               const uint8_t* ntype, const double* J, int n_types,
                               bool check_symmetry, int halo_cap, bool allow_stencil = true);
 
+// Exchange tensors for the types of s (n_types must match).  With the
+// symmetry check's record, every link of type t whose reverse has type u
+// needs Jt[u] = Jt[t]^T, so the energy -S_i^T J_ij S_j is the same read
+// from either end.  Jt = NULL returns to the scalar table.
+void set_exchange_tensors(HostStructure& s, const double* Jt, int n_types);
+
 // Greedy colouring of the neighbour graph for Monte Carlo: site i takes the
 // smallest colour no neighbour j < i has (so no link joins two sites of one
 // colour); fills colour_sites / colour_start.
 void build_colours(HostStructure& s, const int64_t* row_ptr, const int32_t* col);
 
-// Materials: distinct (mu_s, k_u) pairs, per-site ids when there is more
-// than one, per-site easy axes when they differ.
+// Materials: distinct (mu_s, k_u, k_c) triples, per-site ids when there is
+// more than one, per-site easy axes when they differ.
 struct HostMaterials {
     int64_t n = 0;
     std::vector<double> mat_mu;        // J/T per material
     std::vector<double> mat_ku;        // J per material
+    std::vector<double> mat_kc;        // J per material (cubic anisotropy)
+    bool cubic = false;                // some k_c != 0
     double axis[3] = {0, 0, 1};        // uniform easy axis (when !per_site_axis)
     std::vector<uint8_t> matid;        // [n] when per_site_material
     std::vector<double> axis_site;     // [3n] when per_site_axis
@@ -82,8 +97,10 @@ struct HostMaterials {
     double mu_total = 0.0;             // sum over sites of mu_s
 };
 
+// k_c: cubic anisotropy, n values when kc_per_site, else one (NULL: none).
 HostMaterials build_materials(int64_t n, const double* mu_s, const double* k_u,
-                              const double* easy_axis, int per_site);
+                              const double* easy_axis, int per_site, const double* k_c = nullptr,
+                              int kc_per_site = 0);
 
 // Validate spins (3n doubles; throws on zero or non-finite length) and
 // normalise them, or with normalise = false copy them unchanged (a restored

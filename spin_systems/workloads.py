@@ -211,20 +211,29 @@ def with_tensor_exchange(w, D=0.0, dmi="bulk", k_c=None) -> Workload:
     (one value or [n], J/atom) adds cubic anisotropy."""
     lat = w.lattice
     n = lat.n
-    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(lat.row_ptr))
-    d = lat.pos[lat.col] - lat.pos[rows]
-    if lat.dims is not None:
-        for a in range(3):
-            if lat.periodic[a]:
-                L = float(lat.dims[a])
-                d[:, a] -= L * np.round(d[:, a] / L)
-    q = np.rint(d * 2.0).astype(np.int64)                 # bond vectors in units of a/2
-    if np.abs(q).max(initial=0) > 2 or not np.allclose(q, d * 2.0):
-        raise ValueError("bond vectors are not on the a/2 grid of the builder")
-    key = ((lat.ntype.astype(np.int64) * 5 + q[:, 0] + 2) * 5 + q[:, 1] + 2) * 5 + q[:, 2] + 2
-    uniq, new_type = np.unique(key, return_inverse=True)
+    p2 = np.rint(lat.pos * 2.0).astype(np.int32)          # positions in units of a/2
+    if not np.allclose(p2, lat.pos * 2.0):
+        raise ValueError("positions are not on the a/2 grid of the builders")
+    rows = np.repeat(np.arange(n, dtype=np.intp), np.diff(lat.row_ptr))
+    cols = lat.col.astype(np.intp)
+    key = lat.ntype.astype(np.int32) * 125
+    for a, scale in enumerate((25, 5, 1)):
+        pa = np.ascontiguousarray(p2[:, a])
+        q = pa[cols]
+        q -= pa[rows]
+        if lat.dims is not None and lat.periodic[a]:
+            L2 = 2 * int(lat.dims[a])                      # minimum image
+            q[q > L2 // 2] -= L2
+            q[q < -(L2 // 2)] += L2
+        if np.abs(q).max(initial=0) > 2:
+            raise ValueError("bond vectors longer than the a/2 grid of the builders allows")
+        key += (q + 2) * scale
+    present = np.zeros(16 * 125, dtype=bool)
+    present[key] = True
+    uniq = np.nonzero(present)[0]
     if uniq.size > 16:
         raise ValueError(f"{uniq.size} directed interaction types (at most 16)")
+    new_type = (np.cumsum(present) - 1).astype(np.uint8)[key]
     shells = uniq // 125
     vec = np.stack([(uniq // 25) % 5 - 2, (uniq // 5) % 5 - 2, uniq % 5 - 2], axis=1).astype(np.float64)
     rhat = vec / np.linalg.norm(vec, axis=1, keepdims=True)
@@ -234,8 +243,8 @@ def with_tensor_exchange(w, D=0.0, dmi="bulk", k_c=None) -> Workload:
     for t in range(uniq.size):
         Dvec = Dsh[shells[t]] * (rhat[t] if dmi == "bulk" else np.cross([0.0, 0.0, 1.0], rhat[t]))
         tens[t] = J_iso[t] * np.eye(3) - dmi_matrix(Dvec)
-    new_lat = Lattice(lat.kind + " directed", lat.pos, lat.row_ptr, lat.col,
-                      new_type.astype(np.uint8), lat.dims, lat.periodic)
+    new_lat = Lattice(lat.kind + " directed", lat.pos, lat.row_ptr, lat.col, new_type, lat.dims,
+                      lat.periodic)
     out = Workload(name=w.name + f" + DMI {dmi}", lattice=new_lat, J=J_iso, mu_s=w.mu_s, k_u=w.k_u,
                    easy_axis=w.easy_axis, alpha=w.alpha, gamma=w.gamma, dt=w.dt,
                    temperature=w.temperature, H=w.H, seed=w.seed, n_steps=w.n_steps, S0=w.S0,

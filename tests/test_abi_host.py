@@ -123,3 +123,38 @@ def test_create_rejects_bad_arguments():
     assert L.sllg_create(0, 5, 10, ctypes.byref(h)) == -1
     assert L.sllg_create(0, 0, 1 << 28, ctypes.byref(h)) == -1
     assert L.sllg_status_string(-5) == b"SLLG_E_BUDGET"
+
+
+def test_exchange_tensors_and_cubic_anisotropy_validation():
+    from spin_systems import with_tensor_exchange
+    w = with_tensor_exchange(sc_reference(L=4), D=1e-21, dmi="bulk")
+    s = sl.SpinSystem(w.n, sl.FP64)
+    assert _status(lambda: s.set_exchange_tensors(w.J_tensor)) == "SLLG_E_STATE"     # no neighbours yet
+    assert _status(lambda: s.set_cubic_anisotropy([1e-24])) == "SLLG_E_STATE"       # no materials yet
+    lat = w.lattice
+    s.set_neighbours(lat.row_ptr, lat.col, lat.ntype, w.J)     # 6 directed types, equal J
+    s.set_exchange_tensors(w.J_tensor)
+    assert _status(lambda: s.set_exchange_tensors(w.J_tensor[:5])) == "SLLG_E_ARG"  # count
+    bad = w.J_tensor.copy()
+    bad[2] = bad[2].T                        # no longer the transpose of its reverse type
+    assert _status(lambda: s.set_exchange_tensors(bad)) == "SLLG_E_ARG"
+    bad = w.J_tensor.copy()
+    bad[0, 1, 2] = np.inf
+    assert _status(lambda: s.set_exchange_tensors(bad)) == "SLLG_E_ARG"
+    sym = w.J_tensor.copy()
+    sym[:] = 6e-21 * np.eye(3)               # symmetric tensors are their own transpose
+    s.set_exchange_tensors(sym)
+    s.set_exchange_tensors(None)
+    s.set_materials([1.5 * 9.274e-24], [1e-23], [0, 0, 1.0], 0)
+    assert _status(lambda: s.set_cubic_anisotropy([np.nan])) == "SLLG_E_ARG"
+    s.set_cubic_anisotropy([2e-24])
+    kc = np.linspace(-1e-24, 1e-24, w.n)
+    s.set_cubic_anisotropy(kc)
+    s.set_materials([1.5 * 9.274e-24], [1e-23], [0, 0, 1.0], 0)   # keeps the cubic constants
+    s.set_cubic_anisotropy(None)
+    # reverse links with a different type are accepted when their J agrees
+    # (scalar exchange), and rejected when it does not
+    J = np.array(w.J)
+    J[1] *= 2
+    assert _status(lambda: s.set_neighbours(lat.row_ptr, lat.col, lat.ntype, J)) == "SLLG_E_ARG"
+    s.close()

@@ -1,0 +1,149 @@
+"""GPU parity for tensorial exchange (with its Dzyaloshinskii-Moriya part) and
+cubic anisotropy: the general kernel variant against the FP64 oracle on the
+same inputs and the same noise stream, in both neighbour forms, with
+per-site materials, for Monte Carlo, and at the full 8,192,000-spin size.
+
+Tolerances as for the scalar path: FP64 max angle <= 1e-9 rad after 1000
+steps (observed differences come from FMA contraction and device
+transcendentals), FP32 max angle <= 2e-3 rad and mean <= 2e-4 rad,
+|dm| and |dE/E| <= 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1310_6143_amd as sl
+from spin_systems import bcc_block, fcc_nanoparticle, sc_reference, with_tensor_exchange
+from tests.gpu_util import max_angle, mean_angle
+from tests.test_oracle_tensor_cubic import _ring, _spiral, _turn_angles
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_run(w, n_steps):
+    S = np.ascontiguousarray(w.S0.copy())
+    m, E = oracle.System(w).integrate(S, 0, n_steps)
+    return S, m, E
+
+
+def _gpu_run(w, n_steps, precision, stencil=1, check_symmetry=True):
+    with sl.from_workload(w, precision=precision, stencil=stencil, check_symmetry=check_symmetry) as g:
+        m, E = g.integrate(n_steps)
+        return g.get_spins(), m, E
+
+
+def _tilted(w, seed, spread=0.3):
+    rng = np.random.default_rng(seed)
+    S0 = np.tile([0.0, 0.0, 1.0], (w.n, 1)) + spread * rng.standard_normal((w.n, 3))
+    w.S0 = S0 / np.linalg.norm(S0, axis=1, keepdims=True)
+    return w
+
+
+def _bcc_dmi(cells=12, T=300.0):
+    w = with_tensor_exchange(bcc_block(cells=cells, temperature=T, n_steps=1000), D=(1.2e-21, 0.5e-21),
+                             dmi="bulk", k_c=4e-24)
+    w.H = np.array([0.1, -0.2, 0.3])
+    return _tilted(w, 3)
+
+
+@pytest.mark.parametrize("stencil", [1, 0])
+def test_bcc_dmi_cubic_fp64_matches_oracle(stencil):
+    w = _bcc_dmi()
+    S_ref, m_ref, E_ref = _oracle_run(w, 1000)
+    S, m, E = _gpu_run(w, 1000, sl.FP64, stencil=stencil)
+    ang = max_angle(S, S_ref)
+    print(f"bcc DMI + cubic FP64 stencil={stencil}: max angle {ang:.3e}")
+    assert ang <= 1e-9
+    assert np.abs(m - m_ref).max() <= 1e-10
+    assert np.abs(E - E_ref).max() <= 1e-10 * np.abs(E_ref).max()
+
+
+def test_bcc_dmi_cubic_fp32_within_stated_bound():
+    w = _bcc_dmi()
+    S_ref, m_ref, E_ref = _oracle_run(w, 1000)
+    S, m, E = _gpu_run(w, 1000, sl.FP32)
+    amax, amean = max_angle(S, S_ref), mean_angle(S, S_ref)
+    dm = np.abs(m - m_ref).max()
+    dE = (np.abs(E - E_ref) / np.abs(E_ref)).max()
+    print(f"bcc DMI + cubic FP32: max angle {amax:.3e}, mean {amean:.3e}, |dm| {dm:.3e}, |dE/E| {dE:.3e}")
+    assert amax <= 2e-3 and amean <= 2e-4
+    assert dm <= 1e-4 and dE <= 1e-4
+
+
+def test_sphere_interfacial_dmi_per_site_cubic_fp64():
+    """Ragged fcc particle: 12 directed types, per-site k_u, easy axes and
+    cubic constants (several materials), SELL-form rows of 3..12."""
+    base = fcc_nanoparticle(radius_nm=1.6, temperature=300.0)
+    base.H = np.array([0.2, -0.1, 0.5])
+    kc = np.where(np.arange(base.n) % 3 == 0, 6e-24, -3e-24)
+    w = _tilted(with_tensor_exchange(base, D=0.8e-21, dmi="interfacial", k_c=kc), 5)
+    S_ref, m_ref, E_ref = _oracle_run(w, 1000)
+    for stencil in (1, 0):
+        S, m, E = _gpu_run(w, 1000, sl.FP64, stencil=stencil)
+        ang = max_angle(S, S_ref)
+        print(f"sphere DMI FP64 stencil={stencil}: max angle {ang:.3e}")
+        assert ang <= 1e-9
+        assert np.abs(m - m_ref).max() <= 1e-10
+    S32, m32, _ = _gpu_run(w, 1000, sl.FP32)
+    assert max_angle(S32, S_ref) <= 2e-3 and np.abs(m32 - m_ref).max() <= 1e-4
+
+
+def test_isotropic_tensors_match_the_scalar_path():
+    w = _tilted(sc_reference(L=16, temperature=300.0, seed=42), 7)
+    S_a, m_a, _ = _gpu_run(w, 300, sl.FP64)
+    w.J_tensor = np.array([6.0e-21 * np.eye(3)])
+    S_b, m_b, _ = _gpu_run(w, 300, sl.FP64)
+    assert max_angle(S_a, S_b) <= 1e-12
+    assert np.abs(m_a - m_b).max() <= 1e-13
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_dmi_ring_relaxes_to_the_helix(sign):
+    n, J = 16, 6.0e-21
+    theta = -sign * 2 * np.pi / n
+    D = -J * np.tan(theta)
+    w = _ring(n, J, D)
+    w.S0 = _spiral(n, theta, np.random.default_rng(1), 0.15)
+    S_ref, _, _ = _oracle_run(w, 20000)
+    for prec, tol in ((sl.FP64, 1e-10), (sl.FP32, 1e-4)):
+        with sl.from_workload(w, precision=prec) as g:
+            g.integrate(20000, record=False)
+            S = g.get_spins()
+            assert max_angle(S, S_ref) <= tol
+            g.integrate(100000, record=False)
+            S = g.get_spins()
+        ang = _turn_angles(S)
+        print(f"ring {'FP64' if prec == sl.FP64 else 'FP32'}: turn angles {ang.min():.6f}..{ang.max():.6f}, "
+              f"helix {theta:.6f}")
+        assert np.abs(ang - theta).max() < (1e-7 if prec == sl.FP64 else 1e-4)
+
+
+def test_mc_chain_with_tensors_and_cubic_matches_oracle():
+    w = _bcc_dmi(cells=8, T=600.0)
+    S_ref = np.ascontiguousarray(w.S0.copy())
+    m_ref, E_ref, acc_ref = oracle.System(w).mc(S_ref, 0, 20)
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        m, E, acc = g.mc(20)
+        S = g.get_spins()
+    assert np.array_equal(acc, acc_ref)
+    assert max_angle(S, S_ref) <= 1e-12
+    assert np.abs(m - m_ref).max() <= 1e-12
+    assert np.abs(E - E_ref).max() <= 1e-12 * np.abs(E_ref).max()
+
+
+def test_full_size_block_with_dmi_and_cubic():
+    """The 8,192,000-spin block with bulk DMI (14 directed types) and cubic
+    anisotropy in the launch configuration bench.py times: 3 steps against
+    the oracle, every site."""
+    w = with_tensor_exchange(bcc_block(cells=160, n_steps=3), D=(1.2e-21, 0.5e-21), dmi="bulk", k_c=4e-24)
+    w = _tilted(w, 11, 0.1)
+    S_ref, m_ref, E_ref = _oracle_run(w, 3)
+    for prec, ang_tol, rec_tol in ((sl.FP64, 1e-10, 1e-9), (sl.FP32, 1e-5, 1e-6)):
+        with sl.from_workload(w, precision=prec, check_symmetry=False) as g:
+            m, E = g.integrate(3)
+            S = g.get_spins()
+        ang = max_angle(S, S_ref)
+        print(f"full block DMI {'FP32' if prec == sl.FP32 else 'FP64'}: max angle {ang:.2e}")
+        assert ang <= ang_tol
+        assert np.abs(m - m_ref).max() <= rec_tol
+        assert np.abs(E - E_ref).max() <= rec_tol * np.abs(E_ref).max()
