@@ -227,10 +227,69 @@ def run_mc(precision, args):
                       "ms_per_sweep_without_record": dt_sweep * 1e3 / 50, "acceptance": float(acc.sum()) / (blk.n * 50)}}
 
 
+def run_sw(precision, args, n_angles=1024):
+    """Quasi-static Stoner-Wohlfarth loops ("Angular variation of the
+    Coercivity"): n_angles uncoupled spins (H_k = 2 k_u/mu_s = 1 T, easy axes
+    at 0.05..89.95 degrees from the field), field along z from +1.5 to -1.5
+    H_k in steps of 0.01 H_k, relaxed at each point to a torque of 1e-6 T
+    (FP64; 2e-5 T in FP32, whose Heun updates stall below that), torque
+    checked every 10 steps.  Switching fields against the astroid."""
+    import paper_1310_6143_amd as sl
+    from spin_systems import MU_B, GAMMA, Workload
+    from spin_systems.lattice import Lattice
+
+    psi = np.radians(np.linspace(0.05, 89.95, n_angles))
+    axes = np.stack([np.sin(psi), np.zeros(n_angles), np.cos(psi)], axis=1)
+    lat = Lattice("uncoupled", np.zeros((n_angles, 3)), np.zeros(n_angles + 1, dtype=np.int64),
+                  np.zeros(0, dtype=np.int32), np.zeros(0, dtype=np.uint8))
+    mu = 1.5 * MU_B
+    w = Workload(name="Stoner-Wohlfarth", lattice=lat, J=np.array([0.0]), mu_s=np.full(n_angles, mu),
+                 k_u=np.full(n_angles, mu / 2), easy_axis=axes, alpha=1.0, gamma=GAMMA, dt=2e-13,
+                 temperature=0.0, H=np.array([0.0, 0.0, 1.5]), seed=0, n_steps=0,
+                 S0=np.tile([0.0, 0.0, 1.0], (n_angles, 1)))
+    h = np.round(np.arange(150, -151, -1) * 0.01, 10)
+    tol = 1e-6 if precision == sl.FP64 else 2e-5
+    sysm = sl.from_workload(w, precision=precision)
+    sysm.relax(tol, 200_000, check_every=10)            # first use: upload
+    # per point, to read every spin's projection on its easy axis
+    t0 = time.perf_counter()
+    proj = np.empty((h.size, n_angles))
+    steps = np.empty(h.size, dtype=np.int64)
+    for k in range(h.size):
+        _, st = sysm.hysteresis(np.array([[0.0, 0.0, h[k]]]), tol, 200_000, check_every=10)
+        steps[k] = st[0]
+        proj[k] = (sysm.get_spins() * axes).sum(1)
+    dt = time.perf_counter() - t0
+    sysm.close()
+    sw = h[np.argmax(proj < 0, axis=0)]
+    h_sw = (np.cos(psi) ** (2 / 3) + np.sin(psi) ** (2 / 3)) ** -1.5
+    miss = (sw < -h_sw - 0.0101) | (sw > -h_sw + 1e-6)
+    return {"seconds": dt, "angles": n_angles, "field_points": int(h.size), "steps": int(steps.sum()),
+            "unconverged_points": int((steps < 0).sum()), "torque_tol_T": tol,
+            "angle_field_points_per_s": n_angles * h.size / dt,
+            "switching_fields_off_the_astroid": int(miss.sum())}
+
+
 def sweep_main(args):
     import paper_1310_6143_amd as sl
 
     kind = args.workload
+    if kind == "sw":
+        r32 = run_sw(sl.FP32, args)
+        out = {
+            "metric": "relaxed (angle, field) points/s (quasi-static Stoner-Wohlfarth loops)",
+            "value": r32["angle_field_points_per_s"], "unit": "points/s", "n_gpus": 1,
+            "steps": r32["steps"], "warmup": 1, "ms_per_step": r32["seconds"] * 1e3 / max(r32["steps"], 1),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "1024 uncoupled spins, easy axes 0.05..89.95 deg from the field, "
+                                   "H = +1.5..-1.5 H_k in 0.01 H_k steps, relaxed to the torque tolerance"},
+            "fp32": r32,
+        }
+        if not args.no_fp64:
+            out["fp64"] = run_sw(sl.FP64, args)
+        print(json.dumps(out))
+        return
     if kind == "mc":
         r32 = run_mc(sl.FP32, args)
         out = {
@@ -302,11 +361,12 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-budget", type=int, default=16384, help="MiB")
     ap.add_argument("--serving-chunk", type=int, default=64)
-    ap.add_argument("--workload", default="block", choices=["block", "dmi", "film", "sphere", "mc"],
+    ap.add_argument("--workload", default="block", choices=["block", "dmi", "film", "sphere", "mc", "sw"],
                     help="block: 8.19M-spin bcc step throughput (default); dmi: the same block with "
                          "exchange tensors and cubic anisotropy; film: full M(T) ramp; "
                          "sphere: full hysteresis sweep; mc: Monte Carlo M(T) of the sc test system "
-                         "and the Monte Carlo step rate of the block")
+                         "and the Monte Carlo step rate of the block; sw: quasi-static "
+                         "Stoner-Wohlfarth loops at 1024 angles")
     ap.add_argument("--mc-steps", type=int, default=5000, help="equilibration (= averaging) steps per "
                     "temperature for --workload mc")
     ap.add_argument("--sweep-points", type=int, default=0, help="limit the sweep to its first points")

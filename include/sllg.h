@@ -212,6 +212,36 @@ sllg_status sllg_sweep_temperature(sllg_system *sys, const double *T, int64_t n_
 sllg_status sllg_sweep_field(sllg_system *sys, const double *H, int64_t n_points, int64_t n_eq,
                              int64_t n_avg, int n_blocks, double *out, void *stream);
 
+/* Largest torque max_i |S_i x H_i| (tesla) of the current state, with the
+ * deterministic effective field (exchange, anisotropy, applied field; no
+ * thermal term).  Section "Angular variation of the Coercivity": the
+ * convergence measure of the quasi-static solution. */
+sllg_status sllg_max_torque(sllg_system *sys, double *torque_out, void *stream);
+
+/* Quasi-static relaxation (section "Angular variation of the Coercivity":
+ * the LLG equation is solved at zero temperature until the torque on the
+ * system is at most 1e-6 T, a local energy minimum).  Heun steps with the
+ * system's damping and dt, continuing the step counter; the largest torque
+ * is checked before the first step and then after every check_every steps
+ * (check_every = 1 stops at the first step that reaches torque_tol).
+ * steps_out: steps taken, or -1 when max_steps were taken without reaching
+ * the tolerance (status SLLG_E_NUMERIC then); torque_out: the last value
+ * checked.  Either may be NULL.  Errors: SLLG_E_STATE when the temperature
+ * is not 0; SLLG_E_ARG for tol < 0, max_steps < 0 or check_every < 1. */
+sllg_status sllg_relax(sllg_system *sys, double torque_tol, int64_t max_steps, int64_t check_every,
+                       int64_t *steps_out, double *torque_out, void *stream);
+
+/* Quasi-static hysteresis loop (the same test: the field is changed in
+ * steps and the spins relaxed again after each): for each applied field
+ * H[3*k .. 3*k+2], set it, sllg_relax, then the reduced magnetisation of the
+ * relaxed state into m_out[3*k .. 3*k+2] and the steps taken into
+ * steps_out[k] (-1 where max_steps did not suffice; may be NULL).  Several
+ * uncoupled spins with per-site easy axes give loops at several angles
+ * between field and easy axis in one run. */
+sllg_status sllg_hysteresis(sllg_system *sys, const double *H, int64_t n_points, double torque_tol,
+                            int64_t max_steps, int64_t check_every, double *m_out, int64_t *steps_out,
+                            void *stream);
+
 /* Launch-shape autotuner: times every candidate launch configuration of the
  * step kernels ("lds_window" 1 or 0; "tile_order" 1 or 0; XCD mappings 0,
  * 1, 2 of "xcd_remap";

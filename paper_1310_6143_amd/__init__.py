@@ -26,7 +26,7 @@ EXPORTS = [
     "sllg_set_materials", "sllg_set_exchange_tensors", "sllg_set_cubic_anisotropy", "sllg_set_integrator", "sllg_set_conditions", "sllg_set_rng",
     "sllg_get_step", "sllg_set_spins", "sllg_get_spins", "sllg_integrate", "sllg_integrate_dev",
     "sllg_measure", "sllg_average", "sllg_sweep_temperature", "sllg_sweep_field",
-    "sllg_thermal_normals", "sllg_autotune", "sllg_mc", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
+    "sllg_max_torque", "sllg_relax", "sllg_hysteresis", "sllg_thermal_normals", "sllg_autotune", "sllg_mc", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
     "sllg_set_option", "sllg_get_option",
     "sllg_server_create", "sllg_server_destroy", "sllg_server_last_error", "sllg_submit",
     "sllg_poll", "sllg_wait", "sllg_fetch", "sllg_cancel", "sllg_release", "sllg_server_get_stats",
@@ -92,6 +92,9 @@ def lib():
         "sllg_set_neighbours": (c, [P, P, P, P, P, c]),
         "sllg_set_materials": (c, [P, P, P, P, c]),
         "sllg_set_exchange_tensors": (c, [P, P, c]),
+        "sllg_max_torque": (c, [P, P, P]),
+        "sllg_relax": (c, [P, D, I64, I64, P, P, P]),
+        "sllg_hysteresis": (c, [P, P, I64, D, I64, I64, P, P, P]),
         "sllg_set_cubic_anisotropy": (c, [P, P, c]),
         "sllg_set_integrator": (c, [P, D, D, D]),
         "sllg_set_conditions": (c, [P, D, P]),
@@ -294,6 +297,33 @@ class SpinSystem:
         self._check(lib().sllg_autotune(self._h, int(trial_steps), ctypes.byref(us), _stream(stream)))
         return us.value, {k: self.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps",
                                                           "tile_order", "lds_window")}
+
+    def max_torque(self, stream=None):
+        """Largest |S_i x H_i| (tesla) of the current state."""
+        t = D()
+        self._check(lib().sllg_max_torque(self._h, ctypes.byref(t), _stream(stream)))
+        return t.value
+
+    def relax(self, torque_tol=1e-6, max_steps=10_000_000, check_every=1, stream=None):
+        """Heun steps at T = 0 until the largest torque is at most
+        torque_tol.  Returns (steps taken, final torque); raises SllgError
+        (SLLG_E_NUMERIC) when max_steps do not suffice."""
+        n = ctypes.c_int64()
+        t = D()
+        self._check(lib().sllg_relax(self._h, float(torque_tol), int(max_steps), int(check_every),
+                                     ctypes.byref(n), ctypes.byref(t), _stream(stream)))
+        return n.value, t.value
+
+    def hysteresis(self, H, torque_tol=1e-6, max_steps=10_000_000, check_every=1, stream=None):
+        """Quasi-static loop over the fields H [n, 3]: relax at each, record
+        the reduced magnetisation.  Returns (m [n, 3], steps [n]; -1 where
+        max_steps did not suffice)."""
+        H = _c64(H).reshape(-1, 3)
+        m = np.empty((H.shape[0], 3))
+        steps = np.empty(H.shape[0], dtype=np.int64)
+        self._check(lib().sllg_hysteresis(self._h, _ptr(H), H.shape[0], float(torque_tol), int(max_steps),
+                                          int(check_every), _ptr(m), _ptr(steps), _stream(stream)))
+        return m, steps
 
     def mc(self, n_steps, record=True, stream=None):
         """Monte Carlo steps (Hinzke-Nowak moves, colour-class sweeps).

@@ -55,6 +55,7 @@ struct Engine {
     virtual void mc_sweep(uint64_t step, double cone, double inv_kT, unsigned long long* accepted,
                           hipStream_t st) = 0;
     virtual void record_current(int slot, hipStream_t st) = 0;
+    virtual double max_torque(hipStream_t st) = 0;
     virtual size_t spin_bytes() = 0;
     virtual void save_spins(void* dst, hipStream_t st) = 0;
     virtual void load_spins(const void* src, hipStream_t st) = 0;
@@ -117,6 +118,12 @@ struct EngineT final : Engine {
         batch.mc_sweep(q, step, cone, inv_kT, accepted, st);
     }
     void record_current(int slot, hipStream_t st) override { batch.record_current(slot, st); }
+    double max_torque(hipStream_t st) override
+    {
+        std::vector<double> t;
+        batch.max_torque(t, st);
+        return t[(size_t)q];
+    }
     size_t spin_bytes() override { return 3 * (size_t)batch.mirror(q).n * sizeof(R); }
     void save_spins(void* dst, hipStream_t st) override { batch.save_spins(q, dst, st); }
     void load_spins(const void* src, hipStream_t st) override { batch.load_spins(q, src, st); }
@@ -889,6 +896,98 @@ sllg_status sllg_sweep_field(sllg_system* sys, const double* H, int64_t n_points
             sys->dyn.step = e.step();
             apply_dynamics(sys);
             average(sys, n_eq, n_avg, n_blocks, out + 8 * k, st);
+        }
+    });
+}
+
+namespace {
+
+// Heun steps at T = 0 until the largest torque is at most tol (checked
+// before the first step and after every check_every steps); returns the
+// steps taken, or -1 when max_steps were taken first.  *torque: the last
+// value checked.
+int64_t relax(sllg_system* sys, double tol, int64_t max_steps, int64_t check_every, double* torque,
+              hipStream_t st)
+{
+    if (!(tol >= 0.0) || !std::isfinite(tol))
+        fail(SLLG_E_ARG, "torque_tol must be finite and >= 0");
+    if (max_steps < 0 || check_every < 1)
+        fail(SLLG_E_ARG, "max_steps must be >= 0 and check_every >= 1");
+    if (sys->dyn.temperature != 0.0)
+        fail(SLLG_E_STATE, "relaxation needs T = 0 (the thermal field keeps the torque finite)");
+    Engine& e = engine(sys);
+    int64_t taken = 0;
+    double t = e.max_torque(st);
+    while (t > tol) {
+        if (taken >= max_steps) {
+            *torque = t;
+            return -1;
+        }
+        const int64_t ns = std::min(check_every, max_steps - taken);
+        run_steps(sys, ns, nullptr, nullptr, nullptr, nullptr, st, 0);
+        taken += ns;
+        t = e.max_torque(st);
+    }
+    *torque = t;
+    return taken;
+}
+
+}  // namespace
+
+sllg_status sllg_max_torque(sllg_system* sys, double* torque_out, void* stream)
+{
+    return guard(sys, [&] {
+        if (!torque_out)
+            fail(SLLG_E_ARG, "torque_out must not be NULL");
+        *torque_out = engine(sys).max_torque(pick_stream(sys, stream));
+    });
+}
+
+sllg_status sllg_relax(sllg_system* sys, double torque_tol, int64_t max_steps, int64_t check_every,
+                       int64_t* steps_out, double* torque_out, void* stream)
+{
+    sllg_status failed = SLLG_OK;
+    const sllg_status st = guard(sys, [&] {
+        double t = 0.0;
+        const int64_t n = relax(sys, torque_tol, max_steps, check_every, &t, pick_stream(sys, stream));
+        if (steps_out)
+            *steps_out = n;
+        if (torque_out)
+            *torque_out = t;
+        if (n < 0)
+            failed = SLLG_E_NUMERIC;
+    });
+    if (st == SLLG_OK && failed != SLLG_OK) {
+        sys->err = "relaxation did not reach the torque tolerance within max_steps";
+        return failed;
+    }
+    return st;
+}
+
+sllg_status sllg_hysteresis(sllg_system* sys, const double* H, int64_t n_points, double torque_tol,
+                            int64_t max_steps, int64_t check_every, double* m_out, int64_t* steps_out,
+                            void* stream)
+{
+    return guard(sys, [&] {
+        if (!H || !m_out || n_points < 0)
+            fail(SLLG_E_ARG, "H and m_out must not be NULL");
+        for (int64_t k = 0; k < 3 * n_points; ++k)
+            if (!std::isfinite(H[k]))
+                fail(SLLG_E_ARG, "fields must be finite");
+        hipStream_t st = pick_stream(sys, stream);
+        for (int64_t k = 0; k < n_points; ++k) {
+            Engine& e = engine(sys);
+            sys->dyn.H[0] = H[3 * k];
+            sys->dyn.H[1] = H[3 * k + 1];
+            sys->dyn.H[2] = H[3 * k + 2];
+            sys->dyn.step = e.step();
+            apply_dynamics(sys);
+            double t = 0.0;
+            const int64_t n = relax(sys, torque_tol, max_steps, check_every, &t, st);
+            if (steps_out)
+                steps_out[k] = n;
+            double E;
+            measure_state(sys, m_out + 3 * k, &E, st);
         }
     });
 }

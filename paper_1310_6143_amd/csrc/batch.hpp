@@ -263,6 +263,8 @@ public:
         (void)hipFree(d_reps_);
         (void)hipFree(d_work_);
         (void)hipFree(d_nwork_);
+        (void)hipFree(d_torque_work_);
+        (void)hipFree(d_torque_);
     }
 
     Batch(const Batch&) = delete;
@@ -596,6 +598,46 @@ public:
         hip_check(launch_finish<R>(d_reps_, (int)slots_.size(), 1, slot, st), "finish record");
     }
 
+    // Largest torque |S_i x H_i| over the sites of every used replica's
+    // current state (deterministic field, no thermal term): out[q] per slot.
+    void max_torque(std::vector<double>& out, hipStream_t st)
+    {
+        sync_tables();
+        last_stream_ = st;
+        std::vector<WorkItem> all;
+        for (size_t q = 0; q < slots_.size(); ++q)
+            if (slots_[q].used)
+                for (int b = 0; b < slots_[q].rec.blocks; ++b)
+                    all.push_back(WorkItem{(int32_t)q, b});
+        out.assign(slots_.size(), 0.0);
+        if (all.empty())
+            return;
+        if (all.size() != torque_work_.size() ||
+            std::memcmp(all.data(), torque_work_.data(), all.size() * sizeof(WorkItem)) != 0) {
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            (void)hipFree(d_torque_work_);
+            d_torque_work_ = nullptr;
+            hip_check(hipMalloc(&d_torque_work_, sizeof(WorkItem) * all.size() + sizeof(int)), "hipMalloc(torque)");
+            const int n = (int)all.size();
+            hip_check(hipMemcpy(d_torque_work_, all.data(), sizeof(WorkItem) * all.size(), hipMemcpyHostToDevice),
+                      "upload torque work");
+            hip_check(hipMemcpy((char*)d_torque_work_ + sizeof(WorkItem) * all.size(), &n, sizeof(int),
+                                hipMemcpyHostToDevice),
+                      "upload torque work");
+            torque_work_ = std::move(all);
+        }
+        if (!d_torque_)
+            hip_check(hipMalloc(&d_torque_, sizeof(double) * slots_.size()), "hipMalloc(torque)");
+        const int n = (int)torque_work_.size();
+        const int* d_n = (const int*)((const char*)d_torque_work_ + sizeof(WorkItem) * torque_work_.size());
+        hip_check(launch_torque<R>(d_reps_, d_torque_work_, d_n, std::min(n, resident_), (int)slots_.size(), variant_,
+                                   d_torque_, st),
+                  "torque");
+        hip_check(hipMemcpyAsync(out.data(), d_torque_, sizeof(double) * slots_.size(), hipMemcpyDeviceToHost, st),
+                  "download torque");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    }
+
     // m and E of every recording replica's current state into records[rec_pos].
     void measure_now(hipStream_t st)
     {
@@ -725,6 +767,9 @@ private:
     int grid_ = 0;
     int resident_ = 0;
     int resident_v_[3] = {0, 0, 0};   // resident workgroups of each kernel variant
+    std::vector<WorkItem> torque_work_;   // every tile of every used replica (max_torque)
+    WorkItem* d_torque_work_ = nullptr;   // the same list, then its length (int)
+    double* d_torque_ = nullptr;          // [slots] largest torque per replica
     int variant_ = 0;                 // kernel variant the batch needs (launch_predict)
     double grid_scale_ = 1.0;
     int remap_ = SLLG_DEFAULT_REMAP;

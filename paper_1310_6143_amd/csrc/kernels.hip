@@ -957,6 +957,107 @@ __global__ __launch_bounds__(kBlockThreads) void k_finish(const ReplicaDev<R>* _
     final_reduce(r, mode == 0 ? r.nsteps - 1 : slot, red);
 }
 
+// ---------------------------------------------------------------------------
+// Torque ("Angular variation of the coercivity": the LLG equation is solved
+// until the torque |S x H_eff| on the system is small).  k_torque: per tile,
+// the largest |S_i x H_i| of the current state with the deterministic field
+// (exchange, anisotropy, applied field; no thermal term) into
+// partials[4 * tile]; k_torque_max: the largest over each replica's tiles.
+// The maximum does not depend on the order, so the result is exact and
+// reproducible.
+// ---------------------------------------------------------------------------
+template <typename R, int V>
+__device__ __forceinline__ double torque_sites(const ReplicaDev<R>& r, const R* __restrict__ S,
+                                               const Shared<R>& sh, const TileLds<R>& tl, int i0, int wb)
+{
+    constexpr bool PS = V != 0, TX = V == 2;
+    const int T = r.tile;
+    const MaterialDev<R> m0 = PS ? MaterialDev<R>{} : uniform_material(r);
+    double worst = 0.0;
+    for (int l = (int)threadIdx.x; l < T; l += kBlockThreads) {
+        const int i = i0 + l;
+        if (i >= r.n)
+            break;
+        const MaterialDev<R> m = PS ? site_material(r, i) : m0;
+        const int wbyte = site_bytes<R>(l + r.halo);
+        const V3<R> s = (r.flags & kDirect) ? load3(S, i) : wload3(tl.win, wbyte);
+        const V3<R> sum = exchange_sum<R, TX>(r, S, sh, tl, i, l, wb, wbyte, [] {});
+        const V3<R> e = PS ? site_axis(r, m, i) : V3<R>{m.axis[0], m.axis[1], m.axis[2]};
+        const R se = dot(s, e);
+        V3<R> h{m.mu_rel * sum.x + m.ani * se * e.x + r.H[0], m.mu_rel * sum.y + m.ani * se * e.y + r.H[1],
+                m.mu_rel * sum.z + m.ani * se * e.z + r.H[2]};
+        if (TX && (r.flags & kCubic))
+            add_cubic(m, s, h);
+        const V3<R> t{s.y * h.z - s.z * h.y, s.z * h.x - s.x * h.z, s.x * h.y - s.y * h.x};
+        worst = fmax(worst, (double)sqrt(dot(t, t)));
+    }
+    return worst;
+}
+
+// Largest value over the block; result valid in thread 0.  Ends with a barrier.
+__device__ __forceinline__ double block_max(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kWaves; ++w)
+            m = fmax(m, red[w]);
+    __syncthreads();
+    return m;
+}
+
+template <typename R, int V>
+__global__ SLLG_STEP_ATTRS void k_torque(const ReplicaDev<R>* __restrict__ reps, const WorkItem* __restrict__ work,
+                                         const int* __restrict__ n_work, int remap)
+{
+    __shared__ Shared<R> sh;
+    __shared__ TileLds<R> tl;
+    __shared__ double red[kWaves];
+    const int W = *n_work;
+    int staged = -1;
+    for (TileIter it(W, remap); it.more(); it.next()) {
+        const WorkItem w = work[it.t];
+        const ReplicaDev<R>& r = reps[w.replica];
+        const R* __restrict__ S = r.S[r.parity];
+        const int T = r.tile;
+        const int i0 = w.block * T, wb = i0 - r.halo;
+        __syncthreads();   // every lane is done with the previous tile's LDS
+        if (w.replica != staged) {
+            stage_tables<R, V == 2>(r, sh);
+            staged = w.replica;
+        }
+        if (!(r.flags & kDirect))
+            stage_window(S, r.n, wb, T + 2 * r.halo, tl.win);
+        if (r.flags & kStencil)
+            stage_ids(r.pat_id, r.n, i0, T, tl.pid);
+        __syncthreads();
+        const double worst = (V != 0 && (r.flags & kGeneralFlags)) ? torque_sites<R, V>(r, S, sh, tl, i0, wb)
+                                                                   : torque_sites<R, 0>(r, S, sh, tl, i0, wb);
+        const double m = block_max(worst, red);
+        if (threadIdx.x == 0)
+            r.partials[4 * (int64_t)w.block] = m;
+    }
+}
+
+// One workgroup per replica: the largest tile value -> out[replica].
+template <typename R>
+__global__ __launch_bounds__(kBlockThreads) void k_torque_max(const ReplicaDev<R>* __restrict__ reps,
+                                                              double* __restrict__ out)
+{
+    __shared__ double red[kWaves];
+    const ReplicaDev<R>& r = reps[blockIdx.x];
+    double v = 0.0;
+    for (int b = (int)threadIdx.x; b < r.blocks; b += kBlockThreads)
+        v = fmax(v, r.partials[4 * (int64_t)b]);
+    const double m = block_max(v, red);
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = m;
+}
+
 // End of a chunk: advance the step counter and the ping-pong parity.
 template <typename R>
 __global__ void k_advance(ReplicaDev<R>* __restrict__ reps, int n_rep)
@@ -1242,6 +1343,26 @@ hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, 
 }
 
 template <typename R>
+hipError_t launch_torque(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work, int grid,
+                         int n_rep, int variant, double* out, hipStream_t st)
+{
+    if (grid <= 0 || n_rep <= 0)
+        return hipSuccess;
+    const dim3 g(grid), b(kBlockThreads);
+    if (variant == 2)
+        hipLaunchKernelGGL((k_torque<R, 2>), g, b, 0, st, reps, work, n_work, 0);
+    else if (variant == 1)
+        hipLaunchKernelGGL((k_torque<R, 1>), g, b, 0, st, reps, work, n_work, 0);
+    else
+        hipLaunchKernelGGL((k_torque<R, 0>), g, b, 0, st, reps, work, n_work, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_torque_max<R>), dim3(n_rep), b, 0, st, reps, out);
+    return hipGetLastError();
+}
+
+template <typename R>
 int resident_blocks(int device, int variant)
 {
     int cus = 0, a = 0, b = 0;
@@ -1287,6 +1408,8 @@ hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t s
     template hipError_t launch_advance<R>(ReplicaDev<R>*, int, hipStream_t);                         \
     template hipError_t launch_noise<R>(uint64_t, uint64_t, int, double*, hipStream_t);             \
     template int resident_blocks<R>(int, int);                                                        \
+    template hipError_t launch_torque<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, int, \
+                                         double*, hipStream_t);                                      \
     template hipError_t launch_mc<R>(const ReplicaDev<R>*, const int32_t*, int, uint64_t, double, double, \
                                      unsigned long long*, hipStream_t);
 

@@ -40,6 +40,13 @@ hipError_t launch_advance(ReplicaDev<R>* reps, int n_rep, hipStream_t st);
 template <typename R>
 hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStream_t st);
 
+// Largest torque |S_i x H_i| (deterministic field) of the current state of
+// each replica, over the tiles listed in `work` (grid workgroups), into
+// out[q] for q < n_rep.  Every tile of a replica with tiles must be listed.
+template <typename R>
+hipError_t launch_torque(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work, int grid,
+                         int n_rep, int variant, double* out, hipStream_t st);
+
 // Workgroups of the step kernels that fit on the device at once
 // (compute units x resident blocks per unit); 0 if it cannot be queried.
 template <typename R>
