@@ -26,7 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["philox.c", "llg.c", "mc.c"]
+_SOURCES = ["philox.c", "llg.c", "mc.c", "demag.c"]
 KB = 1.3807e-23  # J/K, Table 1
 
 _lib = None
@@ -43,6 +43,18 @@ def build(force: bool = True) -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+class _Demag(ctypes.Structure):
+    _fields_ = [
+        ("pos", ctypes.c_void_p),
+        ("cell_size", ctypes.c_double),
+        ("atom_volume", ctypes.c_double),
+        ("every", ctypes.c_int64),
+        ("field", ctypes.c_void_p),
+        ("valid", ctypes.c_int),
+        ("n_cells", ctypes.c_int64),
+    ]
 
 
 class _System(ctypes.Structure):
@@ -64,6 +76,7 @@ class _System(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("J_tensor", ctypes.c_void_p),
         ("k_c", ctypes.c_void_p),
+        ("demag", ctypes.POINTER(_Demag)),
     ]
 
 
@@ -98,6 +111,8 @@ def lib():
         L.orc_mc_choice.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, P, P]
         L.orc_mc_run.argtypes = [ctypes.POINTER(_System), P, ctypes.c_uint64, ctypes.c_int64, P, P, P]
         L.orc_mc_run.restype = ctypes.c_int
+        L.orc_demag_update.argtypes = [ctypes.POINTER(_System), P]
+        L.orc_demag_update.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -207,6 +222,15 @@ class System:
         kc = getattr(w, "k_c", None)
         self.k_c = None if kc is None else np.ascontiguousarray(np.broadcast_to(kc, (self.n,)),
                                                                 dtype=np.float64)
+        dm = getattr(w, "demag", None)
+        self._demag = None
+        if dm is not None:
+            # the field and its valid flag persist across calls, like the library's
+            self._demag_pos = np.ascontiguousarray(dm["pos"], dtype=np.float64).reshape(self.n, 3)
+            self._demag_field = np.zeros((self.n, 3))
+            self._demag = _Demag(self._demag_pos.ctypes.data, float(dm["cell_size"]),
+                                 float(dm["atom_volume"]), int(dm["every"]), self._demag_field.ctypes.data,
+                                 0, 0)
 
     def _struct(self):
         s = _System()
@@ -225,7 +249,17 @@ class System:
         s.seed = self.seed
         s.J_tensor = None if self.J_tensor is None else self.J_tensor.ctypes.data
         s.k_c = None if self.k_c is None else self.k_c.ctypes.data
+        s.demag = ctypes.pointer(self._demag) if self._demag is not None else None
         return s
+
+    def demag_field(self, S):
+        """Recompute the macrocell demagnetising field from S and return it
+        per atom ([n, 3] tesla) with the number of macrocells."""
+        st = self._struct()
+        rc = lib().orc_demag_update(ctypes.byref(st), _ptr(np.ascontiguousarray(S, dtype=np.float64)))
+        if rc != 0:
+            raise MemoryError("oracle demagnetising field failed")
+        return self._demag_field.copy(), int(self._demag.n_cells)
 
     def integrate(self, S, step0, n_steps, record=True):
         """Heun steps step0 .. step0+n_steps-1 in place on S ([n, 3] float64).

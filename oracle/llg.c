@@ -16,6 +16,8 @@
  *    H_i = -(1/mu_s) dH/dS_i.
  *  - "Langevin Dynamics": the thermal field Gamma sqrt(2 lambda kB T /
  *    (gamma mu_s dt)), added to the effective field.
+ *  - "Demagnetising fields": the macrocell field (demag.c), added to the
+ *    effective field of every atom of a cell, held fixed between updates.
  *  - "Time Integration of the LLG Equation": Heun predictor on every spin,
  *    renormalisation, field re-evaluated at the predicted spins with the
  *    same thermal field, corrector from the original spin with the mean of
@@ -95,6 +97,9 @@ void orc_effective_field(const orc_system *s, const double *S, int64_t i, double
         for (int q = 0; q < 3; ++q)
             h[q] += c * si[q] * si[q] * si[q];
     }
+    if (s->demag && s->demag->valid)
+        for (int q = 0; q < 3; ++q)
+            h[q] += s->demag->field[3 * i + q];
 }
 
 void orc_effective_fields(const orc_system *s, const double *S, double *H_out)
@@ -164,6 +169,12 @@ int orc_heun_step(const orc_system *s, double *S, uint64_t step, double *work)
     double *dS = work + 3 * n;  /* predictor slope */
     double *Hth = work + 6 * n; /* thermal field, fixed for the whole step */
 
+    /* Demagnetising field: updated from the current spins on schedule,
+     * then fixed for the whole step like the thermal field. */
+    if (s->demag && (!s->demag->valid || step % (uint64_t)s->demag->every == 0))
+        if (orc_demag_update(s, S))
+            return -2;
+
     /* Thermal field of this step, one draw per spin. */
     for (int64_t i = 0; i < n; ++i) {
         double g[3];
@@ -212,8 +223,9 @@ int orc_integrate(const orc_system *s, double *S, uint64_t step0, int64_t n_step
         return -2;
     int rc = 0;
     for (int64_t t = 0; t < n_steps; ++t) {
-        if (orc_heun_step(s, S, step0 + (uint64_t)t, work)) {
-            rc = -1;
+        const int st = orc_heun_step(s, S, step0 + (uint64_t)t, work);
+        if (st) {
+            rc = st;
             break;
         }
         if (m_out)
@@ -246,6 +258,10 @@ int64_t orc_relax(const orc_system *s, double *S, double torque_tol, int64_t max
     if (!work)
         return -2;
     int64_t taken = 0;
+    if (s->demag && !s->demag->valid && orc_demag_update(s, S)) {
+        free(work);
+        return -2;
+    }
     while (orc_max_torque(s, S) > torque_tol) {
         if (taken >= max_steps) {
             free(work);

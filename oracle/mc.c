@@ -157,6 +157,10 @@ int orc_mc_run(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, 
     int32_t *colour = (int32_t *)malloc(sizeof(int32_t) * (size_t)(s->n > 0 ? s->n : 1));
     if (!colour)
         return -2;
+    if (s->demag) {   /* not defined for Monte Carlo here */
+        free(colour);
+        return -3;
+    }
     const int n_colours = orc_greedy_colours(s->n, s->row_ptr, s->col, colour);
     if (n_colours < 0) {
         free(colour);

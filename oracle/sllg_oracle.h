@@ -29,6 +29,24 @@ extern "C" {
 #define ORC_KB 1.3807e-23
 #define ORC_MUB 9.2740e-24
 
+/* Macrocell demagnetising field ("Demagnetising fields"; see demag.c).
+ * pos: [3n] atom positions in metres; cell_size: macrocell edge (m);
+ * atom_volume: unit-cell volume / atoms per unit cell (m^3); every: steps
+ * between updates.  field ([3n], caller-owned) holds the field of the last
+ * update, per atom (tesla); valid says whether it holds one.  A Heun step
+ * numbered k first recomputes it from the current spins when k is a
+ * multiple of `every` or no field is held, then uses it, unchanged, in
+ * predictor and corrector.  The energy records leave it out. */
+typedef struct {
+    const double *pos;
+    double cell_size;
+    double atom_volume;
+    int64_t every;
+    double *field;
+    int valid;
+    int64_t n_cells;    /* set by the update */
+} orc_demag;
+
 /* A spin system in the form the Hamiltonian section writes it.
  * Every per-site array has n entries (easy_axis has 3n).  The neighbour
  * list is CSR: the entries of row i are row_ptr[i] .. row_ptr[i+1]-1, with
@@ -55,7 +73,12 @@ typedef struct {
     uint64_t seed;         /* Philox key */
     const double *J_tensor;  /* NULL: scalar exchange J[type] */
     const double *k_c;       /* NULL: no cubic anisotropy */
+    orc_demag *demag;        /* NULL: no demagnetising field */
 } orc_system;
+
+/* Recompute the demagnetising field from the spins S (0, or -2 when out of
+ * memory). */
+int orc_demag_update(const orc_system *s, const double *S);
 
 /* Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11). */

@@ -27,6 +27,7 @@ __all__ = [
     "simple_cubic",
     "bcc",
     "fcc_sphere",
+    "fcc_ellipsoid",
     "csr_from_padded",
 ]
 
@@ -177,6 +178,43 @@ def bcc(dims, periodic=(True, True, True), second_neighbours=False) -> Lattice:
     pos[0::2] = base
     pos[1::2] = base + 0.5
     return Lattice("bcc", pos, row_ptr, col, ntype, dims, tuple(periodic))
+
+
+def fcc_ellipsoid(a_nm: float, semi_axes_nm, tie: float = 1e-9) -> Lattice:
+    """Ellipsoid cut from an fcc crystal, centred on a lattice site: the sites
+    (x, y, z) * a/2 (x + y + z even) with sum_k (x_k / r_k)^2 <= 1 + tie for
+    semi-axes r = semi_axes_nm along x, y, z.  Nearest neighbours as in
+    fcc_sphere; positions in units of a."""
+    half = a_nm / 2.0
+    r = np.asarray(semi_axes_nm, dtype=np.float64)
+    m = int(np.floor(r.max() / half)) + 1
+    rng = np.arange(-m, m + 1)
+    z, y, x = np.meshgrid(rng, rng, rng, indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()
+    q = (x * half / r[0]) ** 2 + (y * half / r[1]) ** 2 + (z * half / r[2]) ** 2
+    keep = ((x + y + z) % 2 == 0) & (q <= 1.0 + tie)
+    return _fcc_from_points(x[keep], y[keep], z[keep], m, "fcc_ellipsoid")
+
+
+def _fcc_from_points(x, y, z, m, kind):
+    n = x.size
+    width = 2 * m + 1
+    grid = np.full((width, width, width), -1, dtype=np.int64)
+    grid[z + m, y + m, x + m] = np.arange(n)
+    offsets = [(sx, sy, 0) for sx in (-1, 1) for sy in (-1, 1)] + \
+              [(sx, 0, sz) for sx in (-1, 1) for sz in (-1, 1)] + \
+              [(0, sy, sz) for sy in (-1, 1) for sz in (-1, 1)]
+    nbr = np.full((n, 12), -1, dtype=np.int64)
+    for k, (dx, dy, dz) in enumerate(offsets):
+        nx, ny, nz = x + dx + m, y + dy + m, z + dz + m
+        inside = (nx >= 0) & (nx < width) & (ny >= 0) & (ny < width) & (nz >= 0) & (nz < width)
+        j = np.full(n, -1, dtype=np.int64)
+        j[inside] = grid[nz[inside], ny[inside], nx[inside]]
+        nbr[:, k] = j
+    typ = np.zeros((n, 12), dtype=np.uint8)
+    row_ptr, col, ntype = csr_from_padded(nbr, typ)
+    pos = np.stack([x, y, z], axis=1).astype(np.float64) * 0.5
+    return Lattice(kind, pos, row_ptr, col, ntype, None, None)
 
 
 def fcc_sphere(a_nm: float, radius_nm: float, tie_nm: float = 1e-9) -> Lattice:

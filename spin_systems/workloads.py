@@ -23,7 +23,7 @@ GAMMA = 1.76e11        # 1/(T s), Table 1
 __all__ = [
     "MU_B", "GAMMA", "Workload",
     "sc_reference", "bcc_film", "fcc_nanoparticle", "bcc_block", "serving_requests",
-    "sc_request_system", "single_spin", "dmi_matrix", "with_tensor_exchange",
+    "sc_request_system", "single_spin", "dmi_matrix", "with_tensor_exchange", "with_demag",
 ]
 
 
@@ -47,6 +47,7 @@ class Workload:
     extra: dict = field(default_factory=dict)
     J_tensor: np.ndarray | None = None   # [n_types, 3, 3] joules/link, replaces J when set
     k_c: np.ndarray | None = None        # [n] cubic anisotropy, J/atom
+    demag: dict | None = None            # macrocell demagnetising field (with_demag)
 
     @property
     def n(self) -> int:
@@ -252,3 +253,19 @@ def with_tensor_exchange(w, D=0.0, dmi="bulk", k_c=None) -> Workload:
     if k_c is not None:
         out.k_c = np.ascontiguousarray(np.broadcast_to(np.asarray(k_c, dtype=np.float64), (n,)))
     return out
+
+
+ATOMS_PER_CELL = {"sc": 1, "bcc": 2, "fcc_sphere": 4, "fcc_ellipsoid": 4}
+
+
+def with_demag(w, a_nm, cell_size_nm, every=100, atom_volume_nm3=None) -> Workload:
+    """w with the macrocell demagnetising field switched on: atom positions in
+    metres (lattice positions times the cubic cell edge a_nm), macrocells of
+    edge cell_size_nm, updated every `every` steps; the atomic volume
+    defaults to a^3 / (atoms per cubic cell)."""
+    if atom_volume_nm3 is None:
+        kind = w.lattice.kind.split(" ")[0]
+        atom_volume_nm3 = a_nm ** 3 / ATOMS_PER_CELL[kind]
+    w.demag = {"pos": np.ascontiguousarray(w.lattice.pos * (a_nm * 1e-9)), "cell_size": cell_size_nm * 1e-9,
+               "atom_volume": atom_volume_nm3 * 1e-27, "every": int(every)}
+    return w

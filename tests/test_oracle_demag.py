@@ -1,0 +1,113 @@
+"""Pins for the oracle's macrocell demagnetising field (section
+"Demagnetising fields"), each against magnetostatics rather than the
+oracle's own formula:
+
+- a uniformly magnetised cube of 3 x 3 x 3 macrocells: at the centre cell
+  the dipole sum of the 26 others cancels by symmetry, leaving the self field
+  -mu0 M / 3 exactly;
+- the trace identity: the demagnetising tensor has trace 1 (each pair term
+  3 r r^T - I is traceless, the self term is I/3), so the mean fields of one
+  body magnetised along x, y and z add up to -mu0 M exactly;
+- a uniformly magnetised sphere has the interior field -mu0 M / 3;
+- the field at the centre of a uniformly magnetised rectangular prism
+  (continuum: -(2/pi) arctan(A B / (C sqrt(A^2 + B^2 + C^2))) mu0 M for
+  half-sides A, B, C);
+- a prolate spheroid of aspect ratio 2 has the demagnetising factors of
+  Osborn's closed form (N_z = 0.1736, N_x = N_y = 0.4132), as in the paper's
+  ellipsoid test;
+- the update schedule: the field is computed from the spins at steps that
+  are multiples of `every` and held in between.
+"""
+import numpy as np
+
+from spin_systems import MU_B, GAMMA, Workload, fcc_ellipsoid, fcc_sphere, simple_cubic, with_demag
+
+MU0 = 4e-7 * np.pi
+
+
+def _wl(lat, mu=1.5 * MU_B, S=(0.0, 0.0, 1.0)):
+    n = lat.n
+    return Workload(name="demag", lattice=lat, J=np.array([0.0]), mu_s=np.full(n, mu), k_u=np.zeros(n),
+                    easy_axis=np.tile([0.0, 0.0, 1.0], (n, 1)), alpha=0.1, gamma=GAMMA, dt=1e-16,
+                    temperature=0.0, H=np.zeros(3), seed=1, n_steps=0, S0=np.tile(np.asarray(S, float), (n, 1)))
+
+
+def test_cube_centre_is_the_self_field(orc):
+    lat = simple_cubic((9, 9, 9), (False, False, False))
+    w = with_demag(_wl(lat), 0.3, 0.9, every=1)
+    d = np.array([0.3, -0.5, 0.8])
+    d /= np.linalg.norm(d)
+    H, n_cells = orc.System(w).demag_field(np.tile(d, (w.n, 1)))
+    assert n_cells == 27
+    M = 1.5 * MU_B / (0.3e-9) ** 3
+    centre = 4 + 9 * (4 + 9 * 4)
+    assert np.allclose(H[centre], -MU0 * M / 3 * d, rtol=1e-12, atol=1e-15)
+    # the 27 atoms of the centre cell share its field
+    cell = (lat.pos // 3 == 1).all(axis=1)
+    assert np.abs(H[cell] - H[centre]).max() == 0.0
+
+
+def test_trace_identity_and_sphere(orc):
+    lat = fcc_sphere(0.354, 3.0)
+    w = with_demag(_wl(lat), 0.354, 0.354, every=1)
+    s = orc.System(w)
+    M = 1.5 * MU_B / (0.354e-9 ** 3 / 4)
+    N = []
+    for k in range(3):
+        d = np.zeros(3)
+        d[k] = 1.0
+        H, _ = s.demag_field(np.tile(d, (w.n, 1)))
+        N.append(-H[:, k].mean() / (MU0 * M))
+        r = np.linalg.norm(lat.pos * 0.354, axis=1)
+        inner = -H[r < 1.5, k].mean() / (MU0 * M)
+        assert abs(inner - 1 / 3) < 0.01, (k, inner)
+    assert abs(sum(N) - 1.0) < 1e-12, N
+
+
+def test_prism_centre_matches_the_continuum(orc):
+    lat = simple_cubic((63, 63, 9), (False, False, False))
+    w = with_demag(_wl(lat), 0.25, 0.75, every=1)
+    H, n_cells = orc.System(w).demag_field(w.S0)
+    assert n_cells == 21 * 21 * 3
+    M = 1.5 * MU_B / (0.25e-9) ** 3
+    A = B = 63 * 0.25 / 2
+    C = 9 * 0.25 / 2
+    exact = -(2 / np.pi) * np.arctan(A * B / (C * np.sqrt(A * A + B * B + C * C)))
+    centre = 31 + 63 * (31 + 63 * 4)
+    assert abs(H[centre, 2] / (MU0 * M) - exact) < 0.01 * abs(exact), (H[centre, 2] / (MU0 * M), exact)
+
+
+def test_prolate_spheroid_matches_osborn(orc):
+    lat = fcc_ellipsoid(0.354, (2.5, 2.5, 5.0))
+    w = with_demag(_wl(lat), 0.354, 0.354, every=1)
+    s = orc.System(w)
+    M = 1.5 * MU_B / (0.354e-9 ** 3 / 4)
+    Hz, _ = s.demag_field(np.tile([0.0, 0.0, 1.0], (w.n, 1)))
+    Hx, _ = s.demag_field(np.tile([1.0, 0.0, 0.0], (w.n, 1)))
+    Nz, Nx = -Hz[:, 2].mean() / (MU0 * M), -Hx[:, 0].mean() / (MU0 * M)
+    m = 2.0
+    Nz_o = (m / np.sqrt(m * m - 1) * np.log(m + np.sqrt(m * m - 1)) - 1) / (m * m - 1)
+    Nx_o = (1 - Nz_o) / 2
+    assert abs(Nz - Nz_o) < 0.08 * Nz_o and abs(Nx - Nx_o) < 0.03 * Nx_o, (Nz, Nz_o, Nx, Nx_o)
+    assert abs((Nx - Nz) - (Nx_o - Nz_o)) < 0.1 * (Nx_o - Nz_o)
+
+
+def test_update_schedule(orc):
+    lat = simple_cubic((6, 6, 2), (False, False, False))
+    w = _wl(lat)
+    w.alpha, w.dt = 0.5, 1e-15
+    rng = np.random.default_rng(3)
+    S0 = rng.standard_normal((w.n, 3))
+    w.S0 = S0 / np.linalg.norm(S0, axis=1, keepdims=True)
+    w = with_demag(w, 0.3, 0.6, every=4)
+    s = orc.System(w)
+    S = w.S0.copy()
+    s.integrate(S, 0, 3, record=False)               # steps 0, 1, 2 use the field of S0
+    H0, _ = orc.System(w).demag_field(w.S0)
+    assert np.array_equal(s._demag_field, H0)
+    s.integrate(S, 3, 2, record=False)               # step 4 recomputes from the state before it
+    before4 = w.S0.copy()
+    orc.System(w).integrate(before4, 0, 4, record=False)
+    H4, _ = orc.System(w).demag_field(before4)
+    assert np.array_equal(s._demag_field, H4)
+    assert not np.array_equal(H4, H0)
