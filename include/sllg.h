@@ -124,6 +124,34 @@ sllg_status sllg_set_exchange_tensors(sllg_system *sys, const double *J, int n_t
  * value.  Not available to serving requests. */
 sllg_status sllg_set_cubic_anisotropy(sllg_system *sys, const double *k_c, int per_site);
 
+/* Macrocell demagnetising field (section "Demagnetising fields").  pos[3n]:
+ * atom positions in metres; the sample is cut into cubic macrocells of edge
+ * cell_size (m) on a grid that starts a thousandth of a cell below the
+ * smallest coordinate on each axis (atomic planes on a cell boundary belong
+ * to the upper cell); only cells holding atoms take part.  Cell moment
+ * m_p = sum mu_s,i S_i; cell position = magnetic centre of mass
+ * sum mu_s,i x_i / sum mu_s,i; cell volume = atoms * atom_volume (unit-cell
+ * volume / atoms per unit cell, m^3).  Field of cell p:
+ * mu0/(4 pi) sum_{q != p} [3 (m_q . r) r - m_q] / |x_q - x_p|^3
+ * - (mu0/3) m_p / V_p (r the unit vector from p to q), added to the
+ * effective field of every atom of the cell.  It is recomputed from the
+ * current spins before every step whose number is a multiple of `every`
+ * (and before the first step after it was set, after sllg_set_spins or
+ * sllg_restore, or after an option that rebuilds the device state), then
+ * held, the same in predictor and corrector.  The energy records leave it
+ * out.  Monte Carlo refuses a system with it (SLLG_E_STATE).  pos = NULL
+ * switches it off; a new neighbour list drops it.  The library copies pos.
+ * Errors: SLLG_E_STATE before sllg_set_neighbours; SLLG_E_ARG for
+ * non-finite positions, cell_size or atom_volume <= 0, every < 1.  Not
+ * available to serving requests. */
+sllg_status sllg_set_demag(sllg_system *sys, const double *pos, double cell_size, double atom_volume,
+                           int64_t every);
+
+/* Recompute the demagnetising field from the current spins now (it is then
+ * held as after a scheduled update) and write it per atom into
+ * field_out[3n] (tesla).  SLLG_E_STATE without sllg_set_demag. */
+sllg_status sllg_demag_field(sllg_system *sys, double *field_out, void *stream);
+
 /* Damping lambda >= 0, gyromagnetic ratio gamma > 0 (1/(T s); Table 1 gives
  * 1.76e11) and time step dt > 0 (s).  Section "Spin Dynamics" (atomistic LLG
  * equation) and "Time Integration of the LLG Equation". */

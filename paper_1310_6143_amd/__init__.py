@@ -23,7 +23,8 @@ STATUS = {0: "SLLG_OK", -1: "SLLG_E_ARG", -2: "SLLG_E_NOMEM", -3: "SLLG_E_DEVICE
 # every symbol include/sllg.h declares
 EXPORTS = [
     "sllg_create", "sllg_destroy", "sllg_last_error", "sllg_status_string", "sllg_set_neighbours",
-    "sllg_set_materials", "sllg_set_exchange_tensors", "sllg_set_cubic_anisotropy", "sllg_set_integrator", "sllg_set_conditions", "sllg_set_rng",
+    "sllg_set_materials", "sllg_set_exchange_tensors", "sllg_set_cubic_anisotropy", "sllg_set_demag",
+    "sllg_demag_field", "sllg_set_integrator", "sllg_set_conditions", "sllg_set_rng",
     "sllg_get_step", "sllg_set_spins", "sllg_get_spins", "sllg_integrate", "sllg_integrate_dev",
     "sllg_measure", "sllg_average", "sllg_sweep_temperature", "sllg_sweep_field",
     "sllg_max_torque", "sllg_relax", "sllg_hysteresis", "sllg_thermal_normals", "sllg_autotune", "sllg_mc", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
@@ -93,6 +94,8 @@ def lib():
         "sllg_set_materials": (c, [P, P, P, P, c]),
         "sllg_set_exchange_tensors": (c, [P, P, c]),
         "sllg_max_torque": (c, [P, P, P]),
+        "sllg_set_demag": (c, [P, P, D, D, I64]),
+        "sllg_demag_field": (c, [P, P, P]),
         "sllg_relax": (c, [P, D, I64, I64, P, P, P]),
         "sllg_hysteresis": (c, [P, P, I64, D, I64, I64, P, P, P]),
         "sllg_set_cubic_anisotropy": (c, [P, P, c]),
@@ -298,6 +301,23 @@ class SpinSystem:
         return us.value, {k: self.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps",
                                                           "tile_order", "lds_window")}
 
+    def set_demag(self, pos, cell_size, atom_volume, every):
+        """Macrocell demagnetising field: atom positions [n, 3] (m), cell
+        edge (m), atomic volume (m^3), update interval (steps); pos None
+        switches it off."""
+        if pos is None:
+            self._check(lib().sllg_set_demag(self._h, None, 0.0, 0.0, 1))
+            return
+        pos = _c64(pos).reshape(-1)
+        self._check(lib().sllg_set_demag(self._h, _ptr(pos), float(cell_size), float(atom_volume), int(every)))
+
+    def demag_field(self, stream=None):
+        """Recompute the demagnetising field from the current spins; per
+        atom [n, 3] tesla."""
+        out = np.empty((self.n, 3))
+        self._check(lib().sllg_demag_field(self._h, _ptr(out), _stream(stream)))
+        return out
+
     def max_torque(self, stream=None):
         """Largest |S_i x H_i| (tesla) of the current state."""
         t = D()
@@ -417,6 +437,9 @@ def from_workload(w, precision=FP32, device=0, check_symmetry=True, stencil=1):
     if kc is not None:
         kc = np.asarray(kc, dtype=np.float64)
         s.set_cubic_anisotropy(kc[:1] if np.all(kc == kc.flat[0]) else kc)
+    dm = getattr(w, "demag", None)
+    if dm is not None:
+        s.set_demag(dm["pos"], dm["cell_size"], dm["atom_volume"], dm["every"])
     s.set_integrator(w.alpha, w.gamma, w.dt)
     s.set_conditions(w.temperature, w.H)
     s.set_rng(w.seed, 0)

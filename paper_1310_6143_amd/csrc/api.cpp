@@ -56,6 +56,8 @@ struct Engine {
                           hipStream_t st) = 0;
     virtual void record_current(int slot, hipStream_t st) = 0;
     virtual double max_torque(hipStream_t st) = 0;
+    virtual void demag_update(hipStream_t st) = 0;
+    virtual void demag_fetch(std::vector<double>& out, hipStream_t st) = 0;
     virtual size_t spin_bytes() = 0;
     virtual void save_spins(void* dst, hipStream_t st) = 0;
     virtual void load_spins(const void* src, hipStream_t st) = 0;
@@ -118,6 +120,8 @@ struct EngineT final : Engine {
         batch.mc_sweep(q, step, cone, inv_kT, accepted, st);
     }
     void record_current(int slot, hipStream_t st) override { batch.record_current(slot, st); }
+    void demag_update(hipStream_t st) override { batch.demag_update(q, st); }
+    void demag_fetch(std::vector<double>& out, hipStream_t st) override { batch.demag_fetch(q, out, st); }
     double max_torque(hipStream_t st) override
     {
         std::vector<double> t;
@@ -159,6 +163,9 @@ struct sllg_system {
     // be combined with them whichever is set last
     std::vector<double> in_mu, in_ku, in_axis, in_kc;
     int in_per_site = 0, in_kc_per_site = 0;
+    // the demagnetising field on the device belongs to the current state
+    // and schedule; false: recompute before the next step that needs it
+    bool demag_valid = false;
     int64_t opt_check_symmetry = 1;
     int64_t opt_graph_steps = -1;    // -1 = automatic
     int64_t opt_xcd_remap = 1;
@@ -252,6 +259,25 @@ void drop_engine(sllg_system* s)
     s->eng->get_spins(s->spins.data(), s->own);
     s->dyn.step = s->eng->step();
     s->eng.reset();
+    s->demag_valid = false;
+}
+
+// The demagnetising field for the step about to run: recomputed from the
+// current state when the step number is a multiple of the update interval
+// or no field is held.  Returns the steps that may run before the next
+// update (n_steps when there is no demagnetising field).
+int64_t demag_before_steps(sllg_system* s, Engine& e, int64_t n_steps, hipStream_t st)
+{
+    const HostDemag& dm = s->st.demag;
+    if (!dm.on)
+        return n_steps;
+    const uint64_t k = e.step();
+    const int64_t into = (int64_t)(k % (uint64_t)dm.every);
+    if (!s->demag_valid || into == 0) {
+        e.demag_update(st);
+        s->demag_valid = true;
+    }
+    return std::min<int64_t>(n_steps, dm.every - into);
 }
 
 sllg_status guard(sllg_system* sys, const std::function<void()>& fn)
@@ -299,7 +325,7 @@ void run_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, do
     int64_t done = 0;
     bool bad = false;
     while (done < n_steps) {
-        const int64_t ns = std::min<int64_t>(chunk, n_steps - done);
+        const int64_t ns = demag_before_steps(s, e, std::min<int64_t>(chunk, n_steps - done), st);
         if (*r.nsteps != (int32_t)ns || *r.flags != flags) {
             *r.nsteps = (int32_t)ns;
             *r.flags = flags;
@@ -340,6 +366,8 @@ void run_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, do
 void mc_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, int64_t* acc_out,
               hipStream_t st)
 {
+    if (s->st.demag.on)
+        fail(SLLG_E_STATE, "Monte Carlo with the demagnetising field is not supported");
     Engine& e = engine(s);
     ReplicaDevBase& r = e.rec();
     const bool record = m_out || E_out;
@@ -789,6 +817,7 @@ sllg_status sllg_set_spins(sllg_system* sys, const double* S)
 {
     return guard(sys, [&] {
         std::vector<double> v = normalised_spins(sys->n, S);
+        sys->demag_valid = false;
         if (sys->eng) {
             hip_check(hipSetDevice(sys->device), "hipSetDevice");
             sys->eng->set_spins(v);
@@ -917,6 +946,10 @@ int64_t relax(sllg_system* sys, double tol, int64_t max_steps, int64_t check_eve
         fail(SLLG_E_STATE, "relaxation needs T = 0 (the thermal field keeps the torque finite)");
     Engine& e = engine(sys);
     int64_t taken = 0;
+    if (sys->st.demag.on && !sys->demag_valid) {
+        e.demag_update(st);
+        sys->demag_valid = true;
+    }
     double t = e.max_torque(st);
     while (t > tol) {
         if (taken >= max_steps) {
@@ -939,7 +972,48 @@ sllg_status sllg_max_torque(sllg_system* sys, double* torque_out, void* stream)
     return guard(sys, [&] {
         if (!torque_out)
             fail(SLLG_E_ARG, "torque_out must not be NULL");
-        *torque_out = engine(sys).max_torque(pick_stream(sys, stream));
+        hipStream_t st = pick_stream(sys, stream);
+        Engine& e = engine(sys);
+        if (sys->st.demag.on && !sys->demag_valid) {
+            e.demag_update(st);
+            sys->demag_valid = true;
+        }
+        *torque_out = e.max_torque(st);
+    });
+}
+
+sllg_status sllg_set_demag(sllg_system* sys, const double* pos, double cell_size, double atom_volume,
+                           int64_t every)
+{
+    return guard(sys, [&] {
+        if (!sys->has_nb)
+            fail(SLLG_E_STATE, "neighbour list not set (sllg_set_neighbours)");
+        HostDemag d;
+        if (pos)
+            d = build_demag(sys->n, pos, cell_size, atom_volume, every);
+        drop_engine(sys);
+        sys->st.demag = std::move(d);
+        sys->demag_valid = false;
+    });
+}
+
+sllg_status sllg_demag_field(sllg_system* sys, double* field_out, void* stream)
+{
+    return guard(sys, [&] {
+        if (!field_out)
+            fail(SLLG_E_ARG, "field_out must not be NULL");
+        if (!sys->st.demag.on)
+            fail(SLLG_E_STATE, "no demagnetising field set (sllg_set_demag)");
+        hipStream_t st = pick_stream(sys, stream);
+        Engine& e = engine(sys);
+        e.demag_update(st);
+        sys->demag_valid = true;
+        std::vector<double> cells;
+        e.demag_fetch(cells, st);
+        const HostDemag& dm = sys->st.demag;
+        for (int64_t i = 0; i < sys->n; ++i)
+            for (int a = 0; a < 3; ++a)
+                field_out[3 * i + a] = cells[3 * (size_t)dm.cell_of[(size_t)i] + a];
     });
 }
 
@@ -1049,6 +1123,7 @@ sllg_status sllg_restore(sllg_system* sys, const void* buf, size_t bytes)
             fail(SLLG_E_ARG, "checkpoint truncated");
         const double* S = reinterpret_cast<const double*>(static_cast<const char*>(buf) + sizeof(h));
         std::vector<double> v = normalised_spins(sys->n, S, false);
+        sys->demag_valid = false;
         if (sys->eng)
             sys->eng->set_spins(v);
         else

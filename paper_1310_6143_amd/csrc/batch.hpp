@@ -148,6 +148,10 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
         b += r(n);
     if (m.per_site_axis)
         b += r(3 * n * real_bytes);
+    if (s.demag.on) {
+        const size_t nc = (size_t)s.demag.cells;
+        b += 2 * r(4 * n) + r(4 * (nc + 1)) + 3 * r(3 * nc * real_bytes) + r(nc * real_bytes);
+    }
     b += r(m.mat_mu.size() * sizeof(MaterialDev<double>));
     const size_t groups = (blocks + kGroupTiles - 1) / kGroupTiles;
     b += r(groups * 32);
@@ -372,6 +376,37 @@ public:
                 hip_check(hipMemcpy(a, ax.data(), 3 * n * sizeof(R), hipMemcpyHostToDevice), "upload axes");
                 r.axis = a;
             }
+            r.dm_cell = r.dm_start = r.dm_atoms = nullptr;
+            r.dm_pos = r.dm_self = nullptr;
+            r.dm_m = r.dm_field = nullptr;
+            if (s.demag.on) {
+                const HostDemag& dm = s.demag;
+                const size_t nc = (size_t)dm.cells;
+                std::vector<double> centre, self;
+                demag_cells(dm, m, centre, self);
+                std::vector<R> cR(centre.begin(), centre.end()), sR(self.begin(), self.end());
+                int32_t* dc = (int32_t*)get(4 * n);
+                int32_t* ds = (int32_t*)get(4 * (nc + 1));
+                int32_t* da = (int32_t*)get(4 * n);
+                R* dp = (R*)get(3 * nc * sizeof(R));
+                R* dsf = (R*)get(nc * sizeof(R));
+                R* dmm = (R*)get(3 * nc * sizeof(R));
+                R* df = (R*)get(3 * nc * sizeof(R));
+                hip_check(hipMemcpy(dc, dm.cell_of.data(), 4 * n, hipMemcpyHostToDevice), "upload macrocells");
+                hip_check(hipMemcpy(ds, dm.start.data(), 4 * (nc + 1), hipMemcpyHostToDevice), "upload macrocells");
+                hip_check(hipMemcpy(da, dm.atoms.data(), 4 * n, hipMemcpyHostToDevice), "upload macrocells");
+                hip_check(hipMemcpy(dp, cR.data(), 3 * nc * sizeof(R), hipMemcpyHostToDevice), "upload macrocells");
+                hip_check(hipMemcpy(dsf, sR.data(), nc * sizeof(R), hipMemcpyHostToDevice), "upload macrocells");
+                hip_check(hipMemset(dmm, 0, 3 * nc * sizeof(R)), "clear macrocells");
+                hip_check(hipMemset(df, 0, 3 * nc * sizeof(R)), "clear macrocells");
+                r.dm_cell = dc;
+                r.dm_start = ds;
+                r.dm_atoms = da;
+                r.dm_pos = dp;
+                r.dm_self = dsf;
+                r.dm_m = dmm;
+                r.dm_field = df;
+            }
             r.mat = (MaterialDev<R>*)get(m.mat_mu.size() * sizeof(MaterialDev<R>));
             r.partials = (double*)get(blocks * 4 * sizeof(double));
             const size_t groups = (blocks + kGroupTiles - 1) / kGroupTiles;
@@ -477,7 +512,7 @@ public:
         for (const auto& sl : slots_) {
             if (!sl.used)
                 continue;
-            if (sl.rec.flags & (kTensor | kCubic))
+            if (sl.rec.flags & kVariant2Flags)
                 variant = 2;
             else if ((sl.rec.flags & kGeneralFlags) && variant < 1)
                 variant = 1;
@@ -596,6 +631,27 @@ public:
         hip_check(launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 1, remap_, true, variant_, st),
                   "measure");
         hip_check(launch_finish<R>(d_reps_, (int)slots_.size(), 1, slot, st), "finish record");
+    }
+
+    // Macrocell demagnetising field of replica q from its current state
+    // (queued on st).
+    void demag_update(int q, hipStream_t st)
+    {
+        sync_tables();
+        last_stream_ = st;
+        hip_check(launch_demag<R>(d_reps_ + q, slots_[q].rec.dm_cells, st), "demagnetising field");
+    }
+
+    // The field of the last update, per macrocell (3 per cell).
+    void demag_fetch(int q, std::vector<double>& out, hipStream_t st)
+    {
+        const ReplicaDev<R>& r = slots_[q].rec;
+        std::vector<R> tmp(3 * (size_t)r.dm_cells);
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        quiesce();
+        hip_check(hipMemcpy(tmp.data(), r.dm_field, tmp.size() * sizeof(R), hipMemcpyDeviceToHost),
+                  "download demagnetising field");
+        out.assign(tmp.begin(), tmp.end());
     }
 
     // Largest torque |S_i x H_i| over the sites of every used replica's

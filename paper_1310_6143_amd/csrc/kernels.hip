@@ -726,6 +726,16 @@ __device__ __forceinline__ void add_cubic(const MaterialDev<R>& m, const V3<R>& 
     h.z += m.cub * s.z * s.z * s.z;
 }
 
+// Adds the demagnetising field of the site's macrocell (last update).
+template <typename R>
+__device__ __forceinline__ void add_demag(const ReplicaDev<R>& r, int i, V3<R>& h)
+{
+    const V3<R> f = load3((const R*)r.dm_field, (int64_t)gload(r.dm_cell, i));
+    h.x += f.x;
+    h.y += f.y;
+    h.z += f.z;
+}
+
 // Adds the thermal field sigma * g (normals g drawn for this site and step).
 template <typename R>
 __device__ __forceinline__ void add_thermal(const MaterialDev<R>& m, const R g[3], V3<R>& h)
@@ -792,6 +802,8 @@ __device__ __forceinline__ void predict_sites(const ReplicaDev<R>& r, const R* _
                     hex.z + m.ani * se * e.z + Happ.z};
             if (cubic)
                 add_cubic(m, s, h);
+            if (TX && (r.flags & kDemag))
+                add_demag(r, i, h);
             add_thermal(m, g, h);
             const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
             const V3<R> sp = normalised(V3<R>{s.x + ds.x, s.y + ds.y, s.z + ds.z});
@@ -893,6 +905,8 @@ __device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* _
                 m.mu_rel * sum.z + m.ani * se * e.z + r.H[2]};
         if (TX && (r.flags & kCubic))
             add_cubic(m, sp, h);
+        if (TX && (r.flags & kDemag))
+            add_demag(r, i, h);
         add_thermal(m, g, h);
         const V3<R> ds = llg_step(sp, h, r.gdt, r.alpha);
         const V3<R> sn = normalised(V3<R>{b.x + (R)0.5 * ds.x, b.y + (R)0.5 * ds.y, b.z + (R)0.5 * ds.z});
@@ -988,6 +1002,8 @@ __device__ __forceinline__ double torque_sites(const ReplicaDev<R>& r, const R* 
                 m.mu_rel * sum.z + m.ani * se * e.z + r.H[2]};
         if (TX && (r.flags & kCubic))
             add_cubic(m, s, h);
+        if (TX && (r.flags & kDemag))
+            add_demag(r, i, h);
         const V3<R> t{s.y * h.z - s.z * h.y, s.z * h.x - s.x * h.z, s.x * h.y - s.y * h.x};
         worst = fmax(worst, (double)sqrt(dot(t, t)));
     }
@@ -1056,6 +1072,85 @@ __global__ __launch_bounds__(kBlockThreads) void k_torque_max(const ReplicaDev<R
     const double m = block_max(v, red);
     if (threadIdx.x == 0)
         out[blockIdx.x] = m;
+}
+
+// ---------------------------------------------------------------------------
+// Macrocell demagnetising field ("Demagnetising fields").  k_demag_moments:
+// m_p = sum over the cell's sites of mu_s,i S_i, one thread per cell, sites
+// in a fixed order.  k_demag_field: for every cell p,
+//   H_p = mu0/(4 pi) sum_{q != p} [3 (m_q . r) r - m_q] / |x_q - x_p|^3
+//         - (mu0/3) m_p / V_p,
+// one thread per cell p, the cells q staged through LDS a workgroup's width
+// at a time (all-pairs: the work is n_cells^2 pair terms, the data n_cells
+// moments and positions).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_demag_moments(const ReplicaDev<R>* __restrict__ rep)
+{
+    const ReplicaDev<R>& r = *rep;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= r.dm_cells)
+        return;
+    const R* __restrict__ S = r.S[r.parity];
+    const int b = gload(r.dm_start, p), e = gload(r.dm_start, p + 1);
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int k = b; k < e; ++k) {
+        const int i = gload(r.dm_atoms, k);
+        const double mu = site_material(r, i).mu_s;
+        const V3<R> s = load3(S, i);
+        m[0] += mu * (double)s.x;
+        m[1] += mu * (double)s.y;
+        m[2] += mu * (double)s.z;
+    }
+    store3(r.dm_m, p, V3<R>{(R)m[0], (R)m[1], (R)m[2]});
+}
+
+constexpr int kDemagBlock = 256;
+
+template <typename R>
+__global__ __launch_bounds__(kDemagBlock) void k_demag_field(const ReplicaDev<R>* __restrict__ rep)
+{
+    __shared__ R tile[6][kDemagBlock];
+    const ReplicaDev<R>& r = *rep;
+    const int nc = r.dm_cells;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = p < nc;
+    const V3<R> xp = live ? load3(r.dm_pos, p) : V3<R>{0, 0, 0};
+    R hx = 0, hy = 0, hz = 0;
+    for (int q0 = 0; q0 < nc; q0 += kDemagBlock) {
+        const int q = q0 + (int)threadIdx.x;
+        __syncthreads();
+        if (q < nc) {
+            const V3<R> x = load3(r.dm_pos, q), m = load3((const R*)r.dm_m, q);
+            tile[0][threadIdx.x] = x.x;
+            tile[1][threadIdx.x] = x.y;
+            tile[2][threadIdx.x] = x.z;
+            tile[3][threadIdx.x] = m.x;
+            tile[4][threadIdx.x] = m.y;
+            tile[5][threadIdx.x] = m.z;
+        }
+        __syncthreads();
+        const int cnt = min(kDemagBlock, nc - q0);
+        for (int k = 0; k < cnt; ++k) {
+            const R dx = tile[0][k] - xp.x, dy = tile[1][k] - xp.y, dz = tile[2][k] - xp.z;
+            const R mx = tile[3][k], my = tile[4][k], mz = tile[5][k];
+            const bool self = q0 + k == p;
+            const R r2 = self ? (R)1 : dx * dx + dy * dy + dz * dz;
+            const R inv = (R)1 / sqrt(r2);
+            const R inv2 = inv * inv;
+            const R inv3 = self ? (R)0 : inv2 * inv;
+            const R md = (R)3 * (mx * dx + my * dy + mz * dz) * inv2;   // 3 (m . r) / |d| with r = d / |d|
+            hx += (md * dx - mx) * inv3;
+            hy += (md * dy - my) * inv3;
+            hz += (md * dz - mz) * inv3;
+        }
+    }
+    if (live) {
+        const V3<R> mp = load3((const R*)r.dm_m, p);
+        const R self = gload(r.dm_self, p);
+        const R k = (R)1e-7;   // mu0 / (4 pi), T m / A
+        store3(r.dm_field, p, V3<R>{k * hx - self * mp.x, k * hy - self * mp.y, k * hz - self * mp.z});
+    }
 }
 
 // End of a chunk: advance the step counter and the ping-pong parity.
@@ -1363,6 +1458,20 @@ hipError_t launch_torque(const ReplicaDev<R>* reps, const WorkItem* work, const 
 }
 
 template <typename R>
+hipError_t launch_demag(const ReplicaDev<R>* rep, int cells, hipStream_t st)
+{
+    if (cells <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_demag_moments<R>), dim3((cells + 255) / 256), dim3(256), 0, st, rep);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_demag_field<R>), dim3((cells + kDemagBlock - 1) / kDemagBlock), dim3(kDemagBlock), 0, st,
+                       rep);
+    return hipGetLastError();
+}
+
+template <typename R>
 int resident_blocks(int device, int variant)
 {
     int cus = 0, a = 0, b = 0;
@@ -1408,6 +1517,7 @@ hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t s
     template hipError_t launch_advance<R>(ReplicaDev<R>*, int, hipStream_t);                         \
     template hipError_t launch_noise<R>(uint64_t, uint64_t, int, double*, hipStream_t);             \
     template int resident_blocks<R>(int, int);                                                        \
+    template hipError_t launch_demag<R>(const ReplicaDev<R>*, int, hipStream_t);                     \
     template hipError_t launch_torque<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, int, \
                                          double*, hipStream_t);                                      \
     template hipError_t launch_mc<R>(const ReplicaDev<R>*, const int32_t*, int, uint64_t, double, double, \

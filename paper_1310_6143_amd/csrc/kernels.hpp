@@ -47,6 +47,11 @@ template <typename R>
 hipError_t launch_torque(const ReplicaDev<R>* reps, const WorkItem* work, const int* n_work, int grid,
                          int n_rep, int variant, double* out, hipStream_t st);
 
+// Macrocell demagnetising field of the replica at *rep from its current
+// state: cell moments, then the field of every cell (dm_field).
+template <typename R>
+hipError_t launch_demag(const ReplicaDev<R>* rep, int cells, hipStream_t st);
+
 // Workgroups of the step kernels that fit on the device at once
 // (compute units x resident blocks per unit); 0 if it cannot be queried.
 template <typename R>

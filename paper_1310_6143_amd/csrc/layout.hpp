@@ -109,10 +109,13 @@ enum ReplicaFlags : int32_t {
     kDirect = 128,          // no LDS window: every neighbour and the own spin read from global memory
     kTensor = 256,          // exchange tensors jm[type] instead of the scalars jt[type]
     kCubic = 512,           // cubic anisotropy (material fields cub, kc_mu)
+    kDemag = 1024,          // macrocell demagnetising field dm_field[dm_cell[i]] added to every site
 };
 
 // Flags that need the general (per-site) kernel variant.
-constexpr int32_t kGeneralFlags = kPerSiteMaterial | kPerSiteAxis | kTensor | kCubic;
+constexpr int32_t kGeneralFlags = kPerSiteMaterial | kPerSiteAxis | kTensor | kCubic | kDemag;
+// Flags that need variant 2 (exchange tensors, cubic anisotropy, demagnetising field).
+constexpr int32_t kVariant2Flags = kTensor | kCubic | kDemag;
 
 template <typename R>
 struct ReplicaDev {
@@ -135,6 +138,16 @@ struct ReplicaDev {
     double* acc;                    // [avg_blocks][5] sums of |m|, m (3), E per averaging block
     R jt[kMaxTypes];                // J / mu_ref per type (tesla)
     R jm[kMaxTypes][9];             // exchange tensor / mu_ref per type, row-major (kTensor)
+    // macrocell demagnetising field (kDemag)
+    const int32_t* dm_cell;         // [n] macrocell of each site
+    const int32_t* dm_start;        // [cells + 1] first entry of each cell in dm_atoms
+    const int32_t* dm_atoms;        // [n] sites sorted by cell
+    const R* dm_pos;                // [3 cells] magnetic centres of mass (m, from the grid corner)
+    const R* dm_self;               // [cells] mu0 / (3 V) of each cell: self field per unit moment
+    R* dm_m;                        // [3 cells] cell moments (J/T)
+    R* dm_field;                    // [3 cells] field of the last update (T)
+    int32_t dm_cells;
+    int32_t pad2;
     R gdt;                          // gamma / (1 + lambda^2) * dt
     R alpha;                        // lambda
     R H[3];                         // applied field (T)

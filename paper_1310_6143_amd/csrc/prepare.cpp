@@ -228,6 +228,84 @@ void set_exchange_tensors(HostStructure& s, const double* Jt, int n_types)
     s.tensor = true;
 }
 
+HostDemag build_demag(int64_t n, const double* pos, double cell_size, double atom_volume, int64_t every)
+{
+    if (!pos)
+        fail(SLLG_E_ARG, "positions must not be NULL");
+    if (!(cell_size > 0.0) || !std::isfinite(cell_size) || !(atom_volume > 0.0) || !std::isfinite(atom_volume))
+        fail(SLLG_E_ARG, "cell_size and atom_volume must be finite and > 0");
+    if (every < 1)
+        fail(SLLG_E_ARG, "every must be >= 1");
+    HostDemag d;
+    d.on = true;
+    d.cell_size = cell_size;
+    d.atom_volume = atom_volume;
+    d.every = every;
+    double lo[3] = {pos[0], pos[1], pos[2]}, hi[3] = {pos[0], pos[1], pos[2]};
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            const double x = pos[3 * i + a];
+            if (!std::isfinite(x))
+                fail(SLLG_E_ARG, "positions must be finite");
+            lo[a] = std::min(lo[a], x);
+            hi[a] = std::max(hi[a], x);
+        }
+    for (int a = 0; a < 3; ++a)
+        lo[a] -= cell_size / 1000.0;
+    int64_t dims[3];
+    for (int a = 0; a < 3; ++a) {
+        const double ext = std::floor((hi[a] - lo[a]) / cell_size) + 1.0;
+        if (ext > 2.0e6)
+            fail(SLLG_E_ARG, "the sample spans too many macrocells along one axis");
+        dims[a] = (int64_t)ext;
+    }
+    std::vector<std::pair<int64_t, int32_t>> key((size_t)n);
+    d.pos.resize(3 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) {
+            c[a] = (int64_t)std::floor((pos[3 * i + a] - lo[a]) / cell_size);
+            d.pos[3 * i + a] = pos[3 * i + a] - lo[a];
+        }
+        key[(size_t)i] = {(c[0] * dims[1] + c[1]) * dims[2] + c[2], (int32_t)i};
+    }
+    std::sort(key.begin(), key.end());
+    d.cell_of.resize((size_t)n);
+    d.atoms.resize((size_t)n);
+    d.start.assign(1, 0);
+    for (int64_t k = 0; k < n; ++k) {
+        if (k > 0 && key[(size_t)k].first != key[(size_t)k - 1].first)
+            d.start.push_back((int32_t)k);
+        d.cell_of[(size_t)key[(size_t)k].second] = (int32_t)d.start.size() - 1;
+        d.atoms[(size_t)k] = key[(size_t)k].second;
+    }
+    d.start.push_back((int32_t)n);
+    d.cells = (int64_t)d.start.size() - 1;
+    return d;
+}
+
+void demag_cells(const HostDemag& dm, const HostMaterials& m, std::vector<double>& centre,
+                 std::vector<double>& self)
+{
+    constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
+    centre.assign(3 * (size_t)dm.cells, 0.0);
+    self.assign((size_t)dm.cells, 0.0);
+    for (int64_t p = 0; p < dm.cells; ++p) {
+        double mu_sum = 0.0, x[3] = {0.0, 0.0, 0.0};
+        for (int32_t k = dm.start[(size_t)p]; k < dm.start[(size_t)p + 1]; ++k) {
+            const int32_t i = dm.atoms[(size_t)k];
+            const double mu = m.mat_mu[m.per_site_material ? m.matid[(size_t)i] : 0];
+            mu_sum += mu;
+            for (int a = 0; a < 3; ++a)
+                x[a] += mu * dm.pos[3 * (size_t)i + a];
+        }
+        for (int a = 0; a < 3; ++a)
+            centre[3 * (size_t)p + a] = x[a] / mu_sum;
+        const double atoms = (double)(dm.start[(size_t)p + 1] - dm.start[(size_t)p]);
+        self[(size_t)p] = kMu0 / 3.0 / (atoms * dm.atom_volume);
+    }
+}
+
 void build_colours(HostStructure& s, const int64_t* row_ptr, const int32_t* col)
 {
     const int64_t n = s.n;
@@ -433,8 +511,11 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
         flags |= kTensor;
     if (m.cubic)
         flags |= kCubic;
+    if (s.demag.on)
+        flags |= kDemag;
     rec.flags = flags;
     rec.n_patterns = s.stencil ? (int32_t)s.pat_start.size() - 1 : 0;
+    rec.dm_cells = s.demag.on ? (int32_t)s.demag.cells : 0;
 }
 
 void averages_from_block_sums(const double* acc, int n_blocks, int64_t block_len, double out[8])

@@ -25,6 +25,24 @@ constexpr double kBoltzmann = 1.3807e-23;
 // Bohr magneton (J/T), Table 1 of the paper.
 constexpr double kBohrMagneton = 9.2740e-24;
 
+// Macrocell decomposition for the demagnetising field: cubic cells of edge
+// cell_size on a grid that starts a thousandth of a cell below the smallest
+// atom coordinate on each axis (atomic planes on a cell boundary go to the
+// upper cell); cells are numbered in the order of (x, y, z) cell index.
+struct HostDemag {
+    bool on = false;
+    double cell_size = 0.0, atom_volume = 0.0;
+    int64_t every = 1;
+    int64_t cells = 0;
+    std::vector<double> pos;           // [3n] atom positions relative to the grid corner (m)
+    std::vector<int32_t> cell_of;      // [n]
+    std::vector<int32_t> start;        // [cells + 1]
+    std::vector<int32_t> atoms;        // [n] sites sorted by cell, ascending within a cell
+};
+
+// Validates and builds the decomposition (pos: 3n metres).
+HostDemag build_demag(int64_t n, const double* pos, double cell_size, double atom_volume, int64_t every);
+
 // Neighbour structure in stencil or SELL-64 form.  Every row lists its
 // near links (|col - row| <= halo_cap) first and the far ones after, each
 // part in the caller's order; the step kernels sum the two parts separately
@@ -54,6 +72,8 @@ struct HostStructure {
     std::vector<uint16_t> pat_start;   // [n_patterns + 1]
     std::vector<uint16_t> pat_far;     // [n_patterns] first far entry of each pattern
     bool no_far = false;               // no pattern has a far link (no padding then)
+    // macrocell demagnetising field (set_demag)
+    HostDemag demag;
     // Monte Carlo colour classes (build_colours): sites sorted by colour
     std::vector<int32_t> colour_sites;
     std::vector<int64_t> colour_start;   // [n_colours + 1]
@@ -96,6 +116,12 @@ struct HostMaterials {
     double mu_ref = 0.0;               // reference moment for the field units
     double mu_total = 0.0;             // sum over sites of mu_s
 };
+
+// Per demagnetising macrocell: magnetic centre of mass sum mu x / sum mu (3
+// per cell, relative to the grid corner) and the self-field factor
+// mu0 / (3 V), V = atoms * atom_volume.
+void demag_cells(const HostDemag& dm, const HostMaterials& m, std::vector<double>& centre,
+                 std::vector<double>& self);
 
 // k_c: cubic anisotropy, n values when kc_per_site, else one (NULL: none).
 HostMaterials build_materials(int64_t n, const double* mu_s, const double* k_u,
