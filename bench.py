@@ -270,10 +270,121 @@ def run_sw(precision, args, n_angles=1024):
             "switching_fields_off_the_astroid": int(miss.sum())}
 
 
+def run_demag(precision, args):
+    """Macrocell demagnetising field.  (1) All-pairs field update throughput:
+    simple-cubic slab 128 x 128 x 32 atoms (a = 0.25 nm) in macrocells of 2
+    atoms per edge: 65,536 cells, 4.3e9 pair terms per update.  (2) The
+    paper's prolate-ellipsoid test: fcc (a = 0.354 nm), mu_s = 1.5 muB,
+    H_k = 1 T along the long axis z, diameter 10 nm, height 20 nm,
+    macrocells of 2 unit cells updated every 100 steps; LLG step rate with
+    and without the field, and the easy-axis switching field with and
+    without it (field 0.5 degree off z; each probe starts from +z, relaxes
+    to 1e-4 T at T = 0 and is read as switched when m_z < 0; bisection to
+    0.01 T)."""
+    import paper_1310_6143_amd as sl
+    from spin_systems import MU_B, GAMMA, Workload, fcc_ellipsoid, simple_cubic, with_demag
+
+    def wl(lat, J, mu, ku, dt):
+        n = lat.n
+        return Workload(name="demag", lattice=lat, J=np.array([J]), mu_s=np.full(n, mu), k_u=np.full(n, ku),
+                        easy_axis=np.tile([0.0, 0.0, 1.0], (n, 1)), alpha=1.0, gamma=GAMMA, dt=dt,
+                        temperature=0.0, H=np.zeros(3), seed=5, n_steps=0, S0=np.tile([0.0, 0.0, 1.0], (n, 1)))
+
+    out = {}
+    slab = with_demag(wl(simple_cubic((128, 128, 32), (False, False, False)), 1e-21, 1.5 * MU_B, 0.0, 1e-16),
+                      0.25, 0.5, every=1)
+    S = np.random.default_rng(1).standard_normal((slab.lattice.n, 3))
+    slab.S0 = S / np.linalg.norm(S, axis=1, keepdims=True)
+    g = sl.from_workload(slab, precision=precision)
+    g.demag_field()                                    # first use: upload
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.demag_field()
+    dt = (time.perf_counter() - t0) / reps
+    g.close()
+    cells = 64 * 64 * 16
+    pairs = cells * (cells - 1)
+    out["update"] = {"cells": cells, "pair_terms": pairs, "seconds": dt, "pair_terms_per_s": pairs / dt,
+                     "flops_per_pair": 31, "achieved_TFLOPs": 31 * pairs / dt / 1e12,
+                     "note": "wall time of sllg_demag_field (update, copy of the cell fields, per-atom expansion)"}
+
+    mu = 1.5 * MU_B
+    lat = fcc_ellipsoid(0.354, (5.0, 5.0, 10.0))
+    M = mu / (0.354e-9 ** 3 / 4)
+    MU0 = 4e-7 * np.pi
+
+    def system(demag):
+        w = wl(lat, 1e-21, mu, mu / 2, 1e-15)
+        return with_demag(w, 0.354, 0.708, every=100) if demag else w
+
+    rates = {}
+    for demag in (False, True):
+        g = sl.from_workload(system(demag), precision=precision)
+        g.integrate(200, record=False)
+        t0 = time.perf_counter()
+        g.integrate(2000, record=False)
+        rates["with" if demag else "without"] = 2000 / (time.perf_counter() - t0)
+        g.close()
+
+    psi = np.radians(0.5)
+    d = np.array([np.sin(psi), 0.0, np.cos(psi)])
+
+    def switches(g, h):
+        g.set_spins(np.tile([0.0, 0.0, 1.0], (lat.n, 1)))
+        g.set_conditions(0.0, tuple(-h * d))
+        try:
+            g.relax(1e-4, 300_000, check_every=100)
+        except sl.SllgError:
+            pass                                        # still moving: read the state reached
+        return g.get_spins()[:, 2].mean() < 0
+
+    hc = {}
+    for demag in (False, True):
+        g = sl.from_workload(system(demag), precision=precision)
+        lo, hi = 0.5, 2.5
+        while hi - lo > 0.01:
+            mid = 0.5 * (lo + hi)
+            sw = switches(g, mid)
+            log(f"  ellipsoid {'with' if demag else 'without'} demag: h = {mid:.4f} T "
+                f"{'switches' if sw else 'holds'}")
+            if sw:
+                hi = mid
+            else:
+                lo = mid
+        g.close()
+        hc["with" if demag else "without"] = 0.5 * (lo + hi)
+    Nz_o = (2 / np.sqrt(3) * np.log(2 + np.sqrt(3)) - 1) / 3
+    out["ellipsoid"] = {
+        "atoms": int(lat.n), "steps_per_s_without": rates["without"], "steps_per_s_with_demag": rates["with"],
+        "switching_field_T_without": hc["without"], "switching_field_T_with": hc["with"],
+        "rise_T": hc["with"] - hc["without"],
+        "osborn_rise_T": ((1 - Nz_o) / 2 - Nz_o) * MU0 * M, "paper_rise_T": 0.33, "paper_expected_T": 0.37,
+    }
+    return out
+
+
 def sweep_main(args):
     import paper_1310_6143_amd as sl
 
     kind = args.workload
+    if kind == "demag":
+        r32 = run_demag(sl.FP32, args)
+        out = {
+            "metric": "demagnetising-field pair terms/s (all-pairs macrocell update)",
+            "value": r32["update"]["pair_terms_per_s"], "unit": "pair-terms/s", "n_gpus": 1, "steps": 5,
+            "warmup": 1, "ms_per_step": r32["update"]["seconds"] * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "65,536 macrocells (sc slab 128x128x32 atoms, 2-atom cells); prolate "
+                                   "fcc ellipsoid 10 x 20 nm with macrocells of 2 unit cells"},
+            "roofline": {"bound": "alu", "achieved": r32["update"]["achieved_TFLOPs"], "peak": 157.3,
+                         "unit": "TFLOP/s", "frac": r32["update"]["achieved_TFLOPs"] / 157.3, "traffic": None},
+            "fp32": r32,
+        }
+        if not args.no_fp64:
+            out["fp64"] = run_demag(sl.FP64, args)
+        print(json.dumps(out))
+        return
     if kind == "sw":
         r32 = run_sw(sl.FP32, args)
         out = {
@@ -361,12 +472,12 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-budget", type=int, default=16384, help="MiB")
     ap.add_argument("--serving-chunk", type=int, default=64)
-    ap.add_argument("--workload", default="block", choices=["block", "dmi", "film", "sphere", "mc", "sw"],
+    ap.add_argument("--workload", default="block", choices=["block", "dmi", "film", "sphere", "mc", "sw", "demag"],
                     help="block: 8.19M-spin bcc step throughput (default); dmi: the same block with "
                          "exchange tensors and cubic anisotropy; film: full M(T) ramp; "
                          "sphere: full hysteresis sweep; mc: Monte Carlo M(T) of the sc test system "
                          "and the Monte Carlo step rate of the block; sw: quasi-static "
-                         "Stoner-Wohlfarth loops at 1024 angles")
+                         "Stoner-Wohlfarth loops at 1024 angles; demag: macrocell demagnetising field")
     ap.add_argument("--mc-steps", type=int, default=5000, help="equilibration (= averaging) steps per "
                     "temperature for --workload mc")
     ap.add_argument("--sweep-points", type=int, default=0, help="limit the sweep to its first points")

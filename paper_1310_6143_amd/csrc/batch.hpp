@@ -150,7 +150,8 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
         b += r(3 * n * real_bytes);
     if (s.demag.on) {
         const size_t nc = (size_t)s.demag.cells;
-        b += 2 * r(4 * n) + r(4 * (nc + 1)) + 3 * r(3 * nc * real_bytes) + r(nc * real_bytes);
+        b += 2 * r(4 * n) + r(4 * (nc + 1)) + 3 * r(3 * nc * real_bytes) + r(nc * real_bytes) +
+             r(3 * nc * (size_t)demag_chunks(s.demag.cells) * real_bytes);
     }
     b += r(m.mat_mu.size() * sizeof(MaterialDev<double>));
     const size_t groups = (blocks + kGroupTiles - 1) / kGroupTiles;
@@ -378,7 +379,7 @@ public:
             }
             r.dm_cell = r.dm_start = r.dm_atoms = nullptr;
             r.dm_pos = r.dm_self = nullptr;
-            r.dm_m = r.dm_field = nullptr;
+            r.dm_m = r.dm_field = r.dm_part = nullptr;
             if (s.demag.on) {
                 const HostDemag& dm = s.demag;
                 const size_t nc = (size_t)dm.cells;
@@ -392,6 +393,8 @@ public:
                 R* dsf = (R*)get(nc * sizeof(R));
                 R* dmm = (R*)get(3 * nc * sizeof(R));
                 R* df = (R*)get(3 * nc * sizeof(R));
+                const int chunks = demag_chunks(dm.cells);
+                R* dpart = (R*)get(3 * nc * (size_t)chunks * sizeof(R));
                 hip_check(hipMemcpy(dc, dm.cell_of.data(), 4 * n, hipMemcpyHostToDevice), "upload macrocells");
                 hip_check(hipMemcpy(ds, dm.start.data(), 4 * (nc + 1), hipMemcpyHostToDevice), "upload macrocells");
                 hip_check(hipMemcpy(da, dm.atoms.data(), 4 * n, hipMemcpyHostToDevice), "upload macrocells");
@@ -406,6 +409,7 @@ public:
                 r.dm_self = dsf;
                 r.dm_m = dmm;
                 r.dm_field = df;
+                r.dm_part = dpart;
             }
             r.mat = (MaterialDev<R>*)get(m.mat_mu.size() * sizeof(MaterialDev<R>));
             r.partials = (double*)get(blocks * 4 * sizeof(double));
@@ -639,7 +643,8 @@ public:
     {
         sync_tables();
         last_stream_ = st;
-        hip_check(launch_demag<R>(d_reps_ + q, slots_[q].rec.dm_cells, st), "demagnetising field");
+        hip_check(launch_demag<R>(d_reps_ + q, slots_[q].rec.dm_cells, slots_[q].rec.dm_chunks, st),
+                  "demagnetising field");
     }
 
     // The field of the last update, per macrocell (3 per cell).

@@ -1107,20 +1107,28 @@ __global__ __launch_bounds__(256) void k_demag_moments(const ReplicaDev<R>* __re
 
 constexpr int kDemagBlock = 256;
 
+// 1/sqrt: the hardware reciprocal square root in FP32, exact division in FP64.
+__device__ __forceinline__ float inv_sqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+
+// Partial dipole sums: block (bx, c) takes cells p of block bx and the
+// sources q of chunk c, staged through LDS; dm_part[c] receives the sums.
 template <typename R>
-__global__ __launch_bounds__(kDemagBlock) void k_demag_field(const ReplicaDev<R>* __restrict__ rep)
+__global__ __launch_bounds__(kDemagBlock) void k_demag_pairs(const ReplicaDev<R>* __restrict__ rep)
 {
     __shared__ R tile[6][kDemagBlock];
     const ReplicaDev<R>& r = *rep;
     const int nc = r.dm_cells;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = p < nc;
+    const int per = (nc + r.dm_chunks - 1) / r.dm_chunks;
+    const int qb = (int)blockIdx.y * per, qe = min(nc, qb + per);
     const V3<R> xp = live ? load3(r.dm_pos, p) : V3<R>{0, 0, 0};
     R hx = 0, hy = 0, hz = 0;
-    for (int q0 = 0; q0 < nc; q0 += kDemagBlock) {
+    for (int q0 = qb; q0 < qe; q0 += kDemagBlock) {
         const int q = q0 + (int)threadIdx.x;
         __syncthreads();
-        if (q < nc) {
+        if (q < qe) {
             const V3<R> x = load3(r.dm_pos, q), m = load3((const R*)r.dm_m, q);
             tile[0][threadIdx.x] = x.x;
             tile[1][threadIdx.x] = x.y;
@@ -1130,13 +1138,13 @@ __global__ __launch_bounds__(kDemagBlock) void k_demag_field(const ReplicaDev<R>
             tile[5][threadIdx.x] = m.z;
         }
         __syncthreads();
-        const int cnt = min(kDemagBlock, nc - q0);
+        const int cnt = min(kDemagBlock, qe - q0);
         for (int k = 0; k < cnt; ++k) {
             const R dx = tile[0][k] - xp.x, dy = tile[1][k] - xp.y, dz = tile[2][k] - xp.z;
             const R mx = tile[3][k], my = tile[4][k], mz = tile[5][k];
             const bool self = q0 + k == p;
             const R r2 = self ? (R)1 : dx * dx + dy * dy + dz * dz;
-            const R inv = (R)1 / sqrt(r2);
+            const R inv = inv_sqrt(r2);
             const R inv2 = inv * inv;
             const R inv3 = self ? (R)0 : inv2 * inv;
             const R md = (R)3 * (mx * dx + my * dy + mz * dz) * inv2;   // 3 (m . r) / |d| with r = d / |d|
@@ -1146,11 +1154,31 @@ __global__ __launch_bounds__(kDemagBlock) void k_demag_field(const ReplicaDev<R>
         }
     }
     if (live) {
-        const V3<R> mp = load3((const R*)r.dm_m, p);
-        const R self = gload(r.dm_self, p);
-        const R k = (R)1e-7;   // mu0 / (4 pi), T m / A
-        store3(r.dm_field, p, V3<R>{k * hx - self * mp.x, k * hy - self * mp.y, k * hz - self * mp.z});
+        R* part = r.dm_part + 3 * (int64_t)nc * blockIdx.y;
+        store3(part, p, V3<R>{hx, hy, hz});
     }
+}
+
+// Chunk sums in chunk order, scaled by mu0 / (4 pi), plus the self term.
+template <typename R>
+__global__ __launch_bounds__(256) void k_demag_field(const ReplicaDev<R>* __restrict__ rep)
+{
+    const ReplicaDev<R>& r = *rep;
+    const int nc = r.dm_cells;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nc)
+        return;
+    R hx = 0, hy = 0, hz = 0;
+    for (int c = 0; c < r.dm_chunks; ++c) {
+        const V3<R> h = load3((const R*)r.dm_part + 3 * (int64_t)nc * c, p);
+        hx += h.x;
+        hy += h.y;
+        hz += h.z;
+    }
+    const V3<R> mp = load3((const R*)r.dm_m, p);
+    const R self = gload(r.dm_self, p);
+    const R k = (R)1e-7;   // mu0 / (4 pi), T m / A
+    store3(r.dm_field, p, V3<R>{k * hx - self * mp.x, k * hy - self * mp.y, k * hz - self * mp.z});
 }
 
 // End of a chunk: advance the step counter and the ping-pong parity.
@@ -1458,7 +1486,7 @@ hipError_t launch_torque(const ReplicaDev<R>* reps, const WorkItem* work, const 
 }
 
 template <typename R>
-hipError_t launch_demag(const ReplicaDev<R>* rep, int cells, hipStream_t st)
+hipError_t launch_demag(const ReplicaDev<R>* rep, int cells, int chunks, hipStream_t st)
 {
     if (cells <= 0)
         return hipSuccess;
@@ -1466,8 +1494,12 @@ hipError_t launch_demag(const ReplicaDev<R>* rep, int cells, hipStream_t st)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_demag_field<R>), dim3((cells + kDemagBlock - 1) / kDemagBlock), dim3(kDemagBlock), 0, st,
-                       rep);
+    hipLaunchKernelGGL((k_demag_pairs<R>), dim3((cells + kDemagBlock - 1) / kDemagBlock, chunks), dim3(kDemagBlock), 0,
+                       st, rep);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_demag_field<R>), dim3((cells + 255) / 256), dim3(256), 0, st, rep);
     return hipGetLastError();
 }
 
@@ -1517,7 +1549,7 @@ hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t s
     template hipError_t launch_advance<R>(ReplicaDev<R>*, int, hipStream_t);                         \
     template hipError_t launch_noise<R>(uint64_t, uint64_t, int, double*, hipStream_t);             \
     template int resident_blocks<R>(int, int);                                                        \
-    template hipError_t launch_demag<R>(const ReplicaDev<R>*, int, hipStream_t);                     \
+    template hipError_t launch_demag<R>(const ReplicaDev<R>*, int, int, hipStream_t);                \
     template hipError_t launch_torque<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, int, \
                                          double*, hipStream_t);                                      \
     template hipError_t launch_mc<R>(const ReplicaDev<R>*, const int32_t*, int, uint64_t, double, double, \

@@ -48,9 +48,11 @@ hipError_t launch_torque(const ReplicaDev<R>* reps, const WorkItem* work, const 
                          int n_rep, int variant, double* out, hipStream_t st);
 
 // Macrocell demagnetising field of the replica at *rep from its current
-// state: cell moments, then the field of every cell (dm_field).
+// state: cell moments, partial dipole sums over `chunks` source ranges
+// (dm_part, chunks as allocated for the replica), then the field of every
+// cell (dm_field).
 template <typename R>
-hipError_t launch_demag(const ReplicaDev<R>* rep, int cells, hipStream_t st);
+hipError_t launch_demag(const ReplicaDev<R>* rep, int cells, int chunks, hipStream_t st);
 
 // Workgroups of the step kernels that fit on the device at once
 // (compute units x resident blocks per unit); 0 if it cannot be queried.

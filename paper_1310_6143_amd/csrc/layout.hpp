@@ -146,8 +146,9 @@ struct ReplicaDev {
     const R* dm_self;               // [cells] mu0 / (3 V) of each cell: self field per unit moment
     R* dm_m;                        // [3 cells] cell moments (J/T)
     R* dm_field;                    // [3 cells] field of the last update (T)
+    R* dm_part;                     // [chunks][3 cells] partial dipole sums over one chunk of cells q
     int32_t dm_cells;
-    int32_t pad2;
+    int32_t dm_chunks;              // chunks the sources q are split into (parallelism of the update)
     R gdt;                          // gamma / (1 + lambda^2) * dt
     R alpha;                        // lambda
     R H[3];                         // applied field (T)

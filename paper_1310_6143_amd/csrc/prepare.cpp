@@ -516,6 +516,7 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
     rec.flags = flags;
     rec.n_patterns = s.stencil ? (int32_t)s.pat_start.size() - 1 : 0;
     rec.dm_cells = s.demag.on ? (int32_t)s.demag.cells : 0;
+    rec.dm_chunks = s.demag.on ? demag_chunks(s.demag.cells) : 0;
 }
 
 void averages_from_block_sums(const double* acc, int n_blocks, int64_t block_len, double out[8])

@@ -40,6 +40,15 @@ struct HostDemag {
     std::vector<int32_t> atoms;        // [n] sites sorted by cell, ascending within a cell
 };
 
+// Source chunks of the demagnetising-field update: enough workgroups
+// (blocks of 256 cells x chunks, about 2048) to fill the chip, at most 32.
+inline int demag_chunks(int64_t cells)
+{
+    const int64_t blocks = (cells + 255) / 256;
+    const int64_t c = (2048 + blocks - 1) / (blocks > 0 ? blocks : 1);
+    return (int)(c < 1 ? 1 : (c > 32 ? 32 : c));
+}
+
 // Validates and builds the decomposition (pos: 3n metres).
 HostDemag build_demag(int64_t n, const double* pos, double cell_size, double atom_volume, int64_t every);
 
