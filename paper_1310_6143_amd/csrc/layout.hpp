@@ -40,7 +40,10 @@ constexpr int tile_sites()
 }
 // Tiles a replica should have at least, so that small systems still spread
 // over the whole chip.
-constexpr int64_t kMinTiles = 2048;
+#ifndef SLLG_MIN_TILES
+#define SLLG_MIN_TILES 2048
+#endif
+constexpr int64_t kMinTiles = SLLG_MIN_TILES;
 // Tile size of an n-site replica: the largest power-of-two fraction of the
 // largest tile (down to one site per lane) that still gives kMinTiles
 // tiles.  A function of n and the precision only, so a replica is tiled the
