@@ -233,7 +233,8 @@ def run_sw(precision, args, n_angles=1024):
     at 0.05..89.95 degrees from the field), field along z from +1.5 to -1.5
     H_k in steps of 0.01 H_k, relaxed at each point to a torque of 1e-6 T
     (FP64; 2e-5 T in FP32, whose Heun updates stall below that), torque
-    checked every 10 steps.  Switching fields against the astroid."""
+    checked every 64 steps (one captured graph of steps between checks).
+    Switching fields against the astroid."""
     import paper_1310_6143_amd as sl
     from spin_systems import MU_B, GAMMA, Workload
     from spin_systems.lattice import Lattice
@@ -250,13 +251,13 @@ def run_sw(precision, args, n_angles=1024):
     h = np.round(np.arange(150, -151, -1) * 0.01, 10)
     tol = 1e-6 if precision == sl.FP64 else 2e-5
     sysm = sl.from_workload(w, precision=precision)
-    sysm.relax(tol, 200_000, check_every=10)            # first use: upload
+    sysm.relax(tol, 200_000, check_every=64)            # first use: upload, graph capture
     # per point, to read every spin's projection on its easy axis
     t0 = time.perf_counter()
     proj = np.empty((h.size, n_angles))
     steps = np.empty(h.size, dtype=np.int64)
     for k in range(h.size):
-        _, st = sysm.hysteresis(np.array([[0.0, 0.0, h[k]]]), tol, 200_000, check_every=10)
+        _, st = sysm.hysteresis(np.array([[0.0, 0.0, h[k]]]), tol, 200_000, check_every=64)
         steps[k] = st[0]
         proj[k] = (sysm.get_spins() * axes).sum(1)
     dt = time.perf_counter() - t0
