@@ -93,8 +93,10 @@ sllg_status sllg_set_neighbours(sllg_system *sys, const int64_t *row_ptr, const 
  * (J/atom, any sign) and easy axes e (unit vectors, normalised here).
  * per_site = 0: one value each (mu_s[1], k_u[1], easy_axis[3]) for every
  * site; per_site = 1: mu_s[n], k_u[n], easy_axis[3n].  At most 256 distinct
- * (mu_s, k_u) pairs.  Section "The classical spin Hamiltonian", uniaxial
- * anisotropy; anisotropy field 2 k_u / mu_s (section "Anisotropy energy"). */
+ * (mu_s, k_u) pairs, (mu_s, k_u, k_c) triples with sllg_set_cubic_anisotropy
+ * (whose constants are kept when the materials are set again).  Section
+ * "The classical spin Hamiltonian", uniaxial anisotropy; anisotropy field
+ * 2 k_u / mu_s. */
 sllg_status sllg_set_materials(sllg_system *sys, const double *mu_s, const double *k_u,
                                const double *easy_axis, int per_site);
 
