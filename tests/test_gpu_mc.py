@@ -108,3 +108,18 @@ def test_mc_chains_agree_bitwise_across_neighbour_forms():
                 ref = (S, m, acc)
             else:
                 assert np.array_equal(S, ref[0]) and np.array_equal(acc, ref[2]), (stencil, window)
+
+
+def test_mc_longer_chain_in_two_calls_matches_oracle():
+    """200 sweeps in two calls (136 + 64; the step counter continues) give
+    the oracle's chain."""
+    w = sc_reference(L=8, temperature=450.0, seed=12)
+    S_ref, m_ref, E_ref, acc_ref = _oracle_mc(w, 200)
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        m, E, acc = g.mc(136)
+        m2, E2, acc2 = g.mc(64)
+        S = g.get_spins()
+        assert g.step == 200
+    assert np.array_equal(np.concatenate([acc, acc2]), acc_ref)
+    assert max_angle(S, S_ref) <= 1e-12
+    assert np.abs(np.concatenate([m, m2]) - m_ref).max() <= 1e-12
