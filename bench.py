@@ -309,6 +309,8 @@ def run_demag(precision, args):
     out["update"] = {"cells": cells, "pair_terms": pairs, "seconds": dt, "pair_terms_per_s": pairs / dt,
                      "flops_per_pair": 31, "achieved_TFLOPs": 31 * pairs / dt / 1e12,
                      "note": "wall time of sllg_demag_field (update, copy of the cell fields, per-atom expansion)"}
+    if args.demag_update_only:
+        return out
 
     mu = 1.5 * MU_B
     lat = fcc_ellipsoid(0.354, (5.0, 5.0, 10.0))
@@ -482,6 +484,8 @@ def main():
     ap.add_argument("--mc-steps", type=int, default=5000, help="equilibration (= averaging) steps per "
                     "temperature for --workload mc")
     ap.add_argument("--sweep-points", type=int, default=0, help="limit the sweep to its first points")
+    ap.add_argument("--demag-update-only", action="store_true",
+                    help="demag workload: time the field update only (skip the ellipsoid)")
     ap.add_argument("--launch", default="", help="fixed launch shape 'xcd_remap,grid_scale_pct[,tile_order]' "
                     "instead of the library default")
     ap.add_argument("--autotune", action="store_true", help="time the candidate launch shapes first "
