@@ -876,6 +876,8 @@ sllg_status sllg_mc(sllg_system* sys, int64_t n_steps, double* m_out, double* E_
     return guard(sys, [&] {
         if (n_steps < 0)
             fail(SLLG_E_ARG, "n_steps must be >= 0");
+        if (sys->st.demag.on)
+            fail(SLLG_E_STATE, "Monte Carlo with the demagnetising field is not supported");
         if (n_steps > 0)
             mc_steps(sys, n_steps, m_out, E_out, accepted_out, pick_stream(sys, stream));
     });
@@ -935,8 +937,7 @@ namespace {
 // before the first step and after every check_every steps); returns the
 // steps taken, or -1 when max_steps were taken first.  *torque: the last
 // value checked.
-int64_t relax(sllg_system* sys, double tol, int64_t max_steps, int64_t check_every, double* torque,
-              hipStream_t st)
+void check_relax(const sllg_system* sys, double tol, int64_t max_steps, int64_t check_every)
 {
     if (!(tol >= 0.0) || !std::isfinite(tol))
         fail(SLLG_E_ARG, "torque_tol must be finite and >= 0");
@@ -944,6 +945,12 @@ int64_t relax(sllg_system* sys, double tol, int64_t max_steps, int64_t check_eve
         fail(SLLG_E_ARG, "max_steps must be >= 0 and check_every >= 1");
     if (sys->dyn.temperature != 0.0)
         fail(SLLG_E_STATE, "relaxation needs T = 0 (the thermal field keeps the torque finite)");
+}
+
+int64_t relax(sllg_system* sys, double tol, int64_t max_steps, int64_t check_every, double* torque,
+              hipStream_t st)
+{
+    check_relax(sys, tol, max_steps, check_every);
     Engine& e = engine(sys);
     int64_t taken = 0;
     if (sys->st.demag.on && !sys->demag_valid) {
@@ -1022,6 +1029,7 @@ sllg_status sllg_relax(sllg_system* sys, double torque_tol, int64_t max_steps, i
 {
     sllg_status failed = SLLG_OK;
     const sllg_status st = guard(sys, [&] {
+        check_relax(sys, torque_tol, max_steps, check_every);   // before the device is opened
         double t = 0.0;
         const int64_t n = relax(sys, torque_tol, max_steps, check_every, &t, pick_stream(sys, stream));
         if (steps_out)
@@ -1048,6 +1056,7 @@ sllg_status sllg_hysteresis(sllg_system* sys, const double* H, int64_t n_points,
         for (int64_t k = 0; k < 3 * n_points; ++k)
             if (!std::isfinite(H[k]))
                 fail(SLLG_E_ARG, "fields must be finite");
+        check_relax(sys, torque_tol, max_steps, check_every);
         hipStream_t st = pick_stream(sys, stream);
         for (int64_t k = 0; k < n_points; ++k) {
             Engine& e = engine(sys);

@@ -158,3 +158,31 @@ def test_exchange_tensors_and_cubic_anisotropy_validation():
     J[1] *= 2
     assert _status(lambda: s.set_neighbours(lat.row_ptr, lat.col, lat.ntype, J)) == "SLLG_E_ARG"
     s.close()
+
+
+def test_demag_and_relaxation_validation():
+    w, s = _valid_system()
+    lat = w.lattice
+    pos = lat.pos * 0.3e-9
+    assert _status(lambda: s.set_demag(pos, 0.6e-9, 2.7e-29, 10)) == "SLLG_E_STATE"   # no neighbours yet
+    s.set_neighbours(lat.row_ptr, lat.col, lat.ntype, w.J)
+    s.set_materials(w.mu_s[:1], w.k_u[:1], w.easy_axis[:1], 0)
+    s.set_integrator(0.1, 1.76e11, 1e-16)
+    s.set_conditions(0.0, (0.0, 0.0, 0.0))
+    s.set_spins(w.S0)
+    assert _status(lambda: s.demag_field()) == "SLLG_E_STATE"                        # not set
+    assert _status(lambda: s.set_demag(pos, 0.0, 2.7e-29, 10)) == "SLLG_E_ARG"
+    assert _status(lambda: s.set_demag(pos, 0.6e-9, -1.0, 10)) == "SLLG_E_ARG"
+    assert _status(lambda: s.set_demag(pos, 0.6e-9, 2.7e-29, 0)) == "SLLG_E_ARG"
+    bad = pos.copy()
+    bad[3, 1] = np.nan
+    assert _status(lambda: s.set_demag(bad, 0.6e-9, 2.7e-29, 10)) == "SLLG_E_ARG"
+    s.set_demag(pos, 0.6e-9, 2.7e-29, 10)
+    assert _status(lambda: s.mc(5)) == "SLLG_E_STATE"          # Monte Carlo refuses the demagnetising field
+    s.set_demag(None, 0, 0, 1)
+    # relaxation arguments are checked before the device is touched
+    assert _status(lambda: s.relax(-1.0, 10)) == "SLLG_E_ARG"
+    assert _status(lambda: s.relax(1e-6, 10, check_every=0)) == "SLLG_E_ARG"
+    s.set_conditions(300.0, (0.0, 0.0, 0.0))
+    assert _status(lambda: s.relax(1e-6, 10)) == "SLLG_E_STATE"   # T > 0
+    s.close()
