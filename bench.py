@@ -49,17 +49,22 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(precision):
-    """HBM bytes per step from the committed rocprofv3 counter summary, or
-    None when it is missing or the kernels changed since it was taken."""
+def profile_value(key):
+    """A machine-readable value of the committed rocprofv3 counter summary,
+    or None when it is missing or the kernels changed since it was taken."""
     if not os.path.exists(COUNTER_FILE):
         return None
     text = open(COUNTER_FILE).read()
     h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
-    v = re.search(rf"{precision}_hbm_bytes_per_step:\s*([0-9.eE+]+)", text)
+    v = re.search(rf"{key}:\s*([0-9.eE+]+)", text)
     if not h or not v or h.group(1) != kernel_hash():
         return None
     return float(v.group(1))
+
+
+def measured_traffic(precision):
+    """HBM bytes per spin-step from the committed counter summary (or None)."""
+    return profile_value(f"{precision}_hbm_bytes_per_step")
 
 
 def run_gpu(w, precision, steps, warmup, torch, launch=None, autotune=False):
@@ -582,6 +587,10 @@ def main():
             "traffic": None if traffic is None else traffic * n,
             "kernel": "Heun step (predictor + corrector launches)",
             "algorithmic_bytes_per_spin_step": b_alg,
+            "traffic_GBs": None if traffic is None else traffic * n / (ms_step / 1e3) / 1e9,
+            "traffic_frac": None if traffic is None else traffic * n / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "valu_busy": None if dmi else {"predictor": profile_value("fp32_predictor_valu_busy"),
+                                           "corrector": profile_value("fp32_corrector_valu_busy")},
         },
     }
     if r64 is not None:
