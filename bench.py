@@ -480,9 +480,11 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-budget", type=int, default=16384, help="MiB")
     ap.add_argument("--serving-chunk", type=int, default=64)
-    ap.add_argument("--workload", default="block", choices=["block", "dmi", "film", "sphere", "mc", "sw", "demag"],
+    ap.add_argument("--workload", default="block",
+                    choices=["block", "dmi", "lr", "film", "sphere", "mc", "sw", "demag"],
                     help="block: 8.19M-spin bcc step throughput (default); dmi: the same block with "
-                         "exchange tensors and cubic anisotropy; film: full M(T) ramp; "
+                         "exchange tensors and cubic anisotropy; lr: long-range exchange (388 partners); "
+                         "film: full M(T) ramp; "
                          "sphere: full hysteresis sweep; mc: Monte Carlo M(T) of the sc test system "
                          "and the Monte Carlo step rate of the block; sw: quasi-static "
                          "Stoner-Wohlfarth loops at 1024 angles; demag: macrocell demagnetising field")
@@ -524,15 +526,20 @@ def main():
                           "read_plus_write_GBs": 2 * n * 4 / (ms / 1e3) / 1e9}))
         return
 
-    if args.workload not in ("block", "dmi"):
+    if args.workload not in ("block", "dmi", "lr"):
         sweep_main(args)
         return
 
-    from spin_systems import bcc_block, with_tensor_exchange
+    from spin_systems import bcc_block, long_range_sc, with_tensor_exchange
 
     t0 = time.time()
-    w = bcc_block(cells=args.cells)
     dmi = args.workload == "dmi"
+    lr = args.workload == "lr"
+    if lr:    # long-range exchange: 388 partners per site, 16 radial types
+        w = long_range_sc(L=64, r_cut=4.5)
+        args.no_serving = True
+    else:
+        w = bcc_block(cells=args.cells)
     if dmi:   # the general kernel variant: 14 directed exchange tensors and cubic anisotropy
         w = with_tensor_exchange(w, D=(1.2e-21, 0.5e-21), dmi="bulk", k_c=4e-24)
         args.no_serving = True
@@ -554,7 +561,7 @@ def main():
     value = n * args.steps / (r32["ms"] / 1e3)
     b_alg = algorithmic_bytes_per_spin_step(4, deg)
     achieved = b_alg * n / (ms_step / 1e3) / 1e9
-    traffic = None if dmi else measured_traffic("fp32")
+    traffic = None if (dmi or lr) else measured_traffic("fp32")
     out = {
         "metric": METRIC,
         "value": value,
@@ -569,11 +576,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"periodic bcc {args.cells}^3 cells, J1+J2 14-entry CSR, {n} spins, T=300 K, "
-                        "alpha=0.05, dt=1e-16 s, seed 4; FP32 spins, FP64 m/E reductions every step"
-                        + ("; exchange tensors per bond direction (14 types: J plus bulk "
-                           "Dzyaloshinskii-Moriya D1 = 1.2e-21 J, D2 = 0.5e-21 J) and cubic "
-                           "anisotropy k_c = 4e-24 J" if dmi else ""),
+            "workload": (f"periodic sc 64^3 ({n} spins), every pair within 4.5 lattice constants linked "
+                         "(388 partners, 16 radial types, J = 6e-21 J exp(-(r - 1))), T=300 K, alpha=0.1, "
+                         "dt=1e-16 s; FP32 spins, FP64 m/E reductions every step") if lr else
+                        (f"periodic bcc {args.cells}^3 cells, J1+J2 14-entry CSR, {n} spins, T=300 K, "
+                         "alpha=0.05, dt=1e-16 s, seed 4; FP32 spins, FP64 m/E reductions every step"
+                         + ("; exchange tensors per bond direction (14 types: J plus bulk "
+                            "Dzyaloshinskii-Moriya D1 = 1.2e-21 J, D2 = 0.5e-21 J) and cubic "
+                            "anisotropy k_c = 4e-24 J" if dmi else "")),
             "n_spins": n,
             "neighbour_entries": int(w.lattice.nnz),
             "launch_shape": r32["launch"],
@@ -589,10 +599,18 @@ def main():
             "algorithmic_bytes_per_spin_step": b_alg,
             "traffic_GBs": None if traffic is None else traffic * n / (ms_step / 1e3) / 1e9,
             "traffic_frac": None if traffic is None else traffic * n / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "valu_busy": None if dmi else {"predictor": profile_value("fp32_predictor_valu_busy"),
-                                           "corrector": profile_value("fp32_corrector_valu_busy")},
+            "valu_busy": None if (dmi or lr) else {"predictor": profile_value("fp32_predictor_valu_busy"),
+                                                   "corrector": profile_value("fp32_corrector_valu_busy")},
         },
     }
+    if lr:
+        # 388 links x 3 FMAs x 2 passes = 12 z flops per spin-step of exchange arithmetic alone
+        flops = 12.0 * deg * n / (ms_step / 1e3)
+        out["roofline"] = {"bound": "alu", "achieved": flops / 1e12, "peak": 157.3, "unit": "TFLOP/s",
+                           "frac": flops / 1e12 / 157.3, "traffic": None,
+                           "kernel": "Heun step (predictor + corrector launches)",
+                           "flops_per_spin_step": 12.0 * deg,
+                           "hbm_view_GBs_at_B_alg": achieved}
     if r64 is not None:
         ms64 = r64["ms"] / args.steps
         b64 = algorithmic_bytes_per_spin_step(8, deg)

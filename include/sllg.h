@@ -81,7 +81,8 @@ const char *sllg_status_string(sllg_status status);
  * non-decreasing); col[row_ptr[n]] neighbour indices in [0, n), no self
  * links; ntype[row_ptr[n]] interaction types in [0, n_types), or NULL for
  * all type 0; J[n_types] exchange constants in joules per link, 1 <= n_types
- * <= 16.  At most 255 neighbours per site.  Each link must appear in both
+ * <= 16.  At most 4095 neighbours per site (long-range exchange: the paper
+ * notes hundreds of partners per atom).  Each link must appear in both
  * rows with the same J (the pair sum runs over i != j with J_ij = J_ji);
  * this is checked unless the option "check_symmetry" is 0.  The exchange
  * field on spin i is (1/mu_s,i) sum_k J[ntype[k]] S[col[k]].  A new

@@ -174,7 +174,7 @@ def llg_rhs(gamma, alpha, spin, h):
     return out
 
 
-def neighbours(pos, box, shells):
+def neighbours(pos, box, shells, max_degree=64):
     """Brute-force neighbour list.  box: 3 lengths (0 = open axis);
     shells: list of (r_lo, r_hi), one per interaction type."""
     pos = np.ascontiguousarray(pos, dtype=np.float64)
@@ -182,7 +182,7 @@ def neighbours(pos, box, shells):
     box = np.ascontiguousarray(box, dtype=np.float64)
     lo = np.ascontiguousarray([s[0] for s in shells], dtype=np.float64)
     hi = np.ascontiguousarray([s[1] for s in shells], dtype=np.float64)
-    cap = n * 64
+    cap = n * max_degree
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     col = np.zeros(cap, dtype=np.int32)
     ntype = np.zeros(cap, dtype=np.uint8)

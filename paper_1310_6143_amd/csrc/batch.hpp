@@ -141,7 +141,7 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
     if (s.stencil)
         b += r(pad16(n)) + r(s.pat_tab.size() * 4) + r(s.pat_start.size() * 2) + r(s.pat_far.size() * 2);
     else
-        b += r(s.nb.size() * 4) + r(s.slice_off.size() * 8) + r(2 * n);
+        b += r(s.nb.size() * 4) + r(s.slice_off.size() * 8) + r(4 * n);
     if (!s.colour_sites.empty())
         b += r(4 * n);
     if (m.per_site_material)
@@ -353,11 +353,11 @@ public:
             } else {
                 uint32_t* nb = (uint32_t*)get(std::max<size_t>(s.nb.size(), 1) * 4);
                 int64_t* so = (int64_t*)get(s.slice_off.size() * 8);
-                uint16_t* dg = (uint16_t*)get(2 * n);
+                uint32_t* dg = (uint32_t*)get(4 * n);
                 hip_check(hipMemcpy(nb, s.nb.data(), s.nb.size() * 4, hipMemcpyHostToDevice), "upload nb");
                 hip_check(hipMemcpy(so, s.slice_off.data(), s.slice_off.size() * 8, hipMemcpyHostToDevice),
                           "upload slices");
-                hip_check(hipMemcpy(dg, s.deg.data(), 2 * n, hipMemcpyHostToDevice), "upload deg");
+                hip_check(hipMemcpy(dg, s.deg.data(), 4 * n, hipMemcpyHostToDevice), "upload deg");
                 r.nb = nb;
                 r.slice_off = so;
                 r.deg = dg;

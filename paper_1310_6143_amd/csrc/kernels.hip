@@ -369,6 +369,9 @@ __device__ __forceinline__ int site_bytes(int x)
     return (int)__umul24((unsigned)x, 3u * (unsigned)sizeof(R));
 }
 
+// Links per batch of the long-row SELL gathers.
+constexpr int kSellBatch = 8;
+
 // h += M S_j for a 3x3 row-major coupling matrix M.
 template <typename R>
 __device__ __forceinline__ void add_link(V3<R>& h, const R* M, const V3<R>& sj)
@@ -453,20 +456,60 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
     } else {
         overlap();
         const int64_t base = gload(r.slice_off, i >> 6) + (i & 63);
-        const int dw = gload(r.deg, i);
-        const int d = dw & 255, nn = dw >> 8;
+        const uint32_t dw = gload(r.deg, i);
+        const int d = (int)(dw & 0xFFFFu), nn = (int)(dw >> 16);
+        // Rows of a few dozen links: one link at a time.  Long rows
+        // (kLongRows, long-range exchange; general variant only):
+        // kSellBatch entries, then their spins, all in flight together,
+        // added in row order (an entry past the row's end repeats the last
+        // one with a zero coupling).
+        const bool batched = TX && (r.flags & kLongRows);
+        if (!batched) {
 #pragma unroll 2
-        for (int k = nn; k < d; ++k) {
-            const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
-            const V3<R> sj = load3(S, (int64_t)(e & kColMask));
-            add_coupled<R, TX>(hf, tensor, sh, (int)(e >> kColBits), sh.jt[e >> kColBits], sj);
+            for (int k = nn; k < d; ++k) {
+                const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
+                const V3<R> sj = load3(S, (int64_t)(e & kColMask));
+                add_coupled<R, TX>(hf, tensor, sh, (int)(e >> kColBits), sh.jt[e >> kColBits], sj);
+            }
+        } else {
+            for (int k = nn; k < d; k += kSellBatch) {
+                uint32_t ent[kSellBatch];
+#pragma unroll
+                for (int u = 0; u < kSellBatch; ++u)
+                    ent[u] = gload(r.nb, base + (int64_t)(k + u < d ? k + u : d - 1) * kSlice);
+                V3<R> sj[kSellBatch];
+#pragma unroll
+                for (int u = 0; u < kSellBatch; ++u)
+                    sj[u] = load3(S, (int64_t)(ent[u] & kColMask));
+#pragma unroll
+                for (int u = 0; u < kSellBatch; ++u) {
+                    const int t = k + u < d ? (int)(ent[u] >> kColBits) : kMaxTypes;
+                    add_coupled<R, TX>(hf, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj[u]);
+                }
+            }
         }
-        SLLG_UNROLL(SLLG_NEAR_UNROLL)
-        for (int k = 0; k < nn; ++k) {
-            const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
-            const V3<R> sj = (r.flags & kDirect) ? load3(S, (int64_t)(e & kColMask))
-                                                 : wload3(tl.win, site_bytes<R>((int)(e & kColMask) - wb));
-            add_coupled<R, TX>(hn, tensor, sh, (int)(e >> kColBits), sh.jt[e >> kColBits], sj);
+        if (!batched) {
+            SLLG_UNROLL(SLLG_NEAR_UNROLL)
+            for (int k = 0; k < nn; ++k) {
+                const uint32_t e = gload(r.nb, base + (int64_t)k * kSlice);
+                const V3<R> sj = (r.flags & kDirect) ? load3(S, (int64_t)(e & kColMask))
+                                                     : wload3(tl.win, site_bytes<R>((int)(e & kColMask) - wb));
+                add_coupled<R, TX>(hn, tensor, sh, (int)(e >> kColBits), sh.jt[e >> kColBits], sj);
+            }
+        } else {
+            for (int k = 0; k < nn; k += kSellBatch) {
+                uint32_t ent[kSellBatch];
+#pragma unroll
+                for (int u = 0; u < kSellBatch; ++u)
+                    ent[u] = gload(r.nb, base + (int64_t)(k + u < nn ? k + u : nn - 1) * kSlice);
+#pragma unroll
+                for (int u = 0; u < kSellBatch; ++u) {
+                    const int c = (int)(ent[u] & kColMask);
+                    const V3<R> sj = (r.flags & kDirect) ? load3(S, (int64_t)c) : wload3(tl.win, site_bytes<R>(c - wb));
+                    const int t = k + u < nn ? (int)(ent[u] >> kColBits) : kMaxTypes;
+                    add_coupled<R, TX>(hn, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj);
+                }
+            }
         }
     }
     return V3<R>{hn.x + hf.x, hn.y + hf.y, hn.z + hf.z};
@@ -1257,7 +1300,7 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
         return h;
     }
     const int64_t base = gload(r.slice_off, i >> 6) + (i & 63);
-    const int d = gload(r.deg, i) & 255;
+    const int d = (int)(gload(r.deg, i) & 0xFFFFu);
     for (int k = 0; k < d; k += kMcBatch) {
         uint32_t ent[kMcBatch];
 #pragma unroll

@@ -73,7 +73,7 @@ constexpr int kSlice = 64;            // rows per SELL slice = one wavefront
 constexpr int kMaxTypes = 16;         // interaction types per replica
 constexpr uint32_t kColBits = 28;     // packed neighbour: type << 28 | column
 constexpr uint32_t kColMask = (1u << kColBits) - 1u;
-constexpr int kMaxDegree = 255;
+constexpr int kMaxDegree = 4095;       // neighbours per site (long-range exchange)
 // Stencil format: rows whose (column - row, type) lists coincide share one
 // pattern; a site stores only its pattern id (uint8).  Pattern entries pack
 // (column - row) << 4 | type in an int32 (offsets within +-2^27).
@@ -113,12 +113,17 @@ enum ReplicaFlags : int32_t {
     kTensor = 256,          // exchange tensors jm[type] instead of the scalars jt[type]
     kCubic = 512,           // cubic anisotropy (material fields cub, kc_mu)
     kDemag = 1024,          // macrocell demagnetising field dm_field[dm_cell[i]] added to every site
+    kLongRows = 2048,       // SELL rows longer than kLongRow links: batched gathers (general variant)
 };
 
+// Rows longer than this take the batched gathers of the general variant.
+constexpr int kLongRow = 32;
+
 // Flags that need the general (per-site) kernel variant.
-constexpr int32_t kGeneralFlags = kPerSiteMaterial | kPerSiteAxis | kTensor | kCubic | kDemag;
-// Flags that need variant 2 (exchange tensors, cubic anisotropy, demagnetising field).
-constexpr int32_t kVariant2Flags = kTensor | kCubic | kDemag;
+constexpr int32_t kGeneralFlags = kPerSiteMaterial | kPerSiteAxis | kTensor | kCubic | kDemag | kLongRows;
+// Flags that need variant 2 (exchange tensors, cubic anisotropy,
+// demagnetising field, long rows).
+constexpr int32_t kVariant2Flags = kTensor | kCubic | kDemag | kLongRows;
 
 template <typename R>
 struct ReplicaDev {
@@ -127,7 +132,7 @@ struct ReplicaDev {
     R* Bc;                          // corrector base S + dS dt / 2 [3n]
     const uint32_t* nb;             // SELL-64 neighbour entries
     const int64_t* slice_off;       // [n_slices + 1] first entry of each slice
-    const uint16_t* deg;            // [n] near << 8 | neighbours, per site (SELL)
+    const uint32_t* deg;            // [n] near << 16 | neighbours, per site (SELL)
     const uint8_t* pat_id;          // [n padded to 16] stencil pattern of each site (kStencil)
     const int32_t* pat_tab;         // [pat_entries] packed offset << 4 | type
     const uint16_t* pat_start;      // [n_patterns + 1] first entry of each pattern

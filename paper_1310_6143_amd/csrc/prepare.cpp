@@ -44,7 +44,8 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
         if (d < 0)
             fail(SLLG_E_ARG, "row_ptr is decreasing at row " + std::to_string(i));
         if (d > kMaxDegree)
-            fail(SLLG_E_ARG, "row " + std::to_string(i) + " has more than 255 neighbours");
+            fail(SLLG_E_ARG, "row " + std::to_string(i) + " has more than " + std::to_string(kMaxDegree) +
+                                 " neighbours");
     }
     const int64_t nnz = row_ptr[n];
     if (nnz > 0 && !col)
@@ -96,7 +97,7 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
         return off >= -halo_cap && off <= halo_cap;
     };
     std::vector<int64_t> order((size_t)nnz);   // CSR positions, rows reordered
-    std::vector<uint8_t> n_near((size_t)n);
+    std::vector<uint16_t> n_near((size_t)n);
     int64_t max_near = 0;
     for (int64_t i = 0; i < n; ++i) {
         int64_t w = row_ptr[i];
@@ -105,7 +106,7 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
                 order[(size_t)w++] = q;
                 max_near = std::max<int64_t>(max_near, std::llabs((int64_t)col[q] - i));
             }
-        n_near[(size_t)i] = (uint8_t)(w - row_ptr[i]);
+        n_near[(size_t)i] = (uint16_t)(w - row_ptr[i]);
         for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q)
             if (!near(i, q))
                 order[(size_t)w++] = q;
@@ -130,7 +131,7 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
         const size_t far_min = any_far ? (size_t)kFarRegs : 0;
         for (int64_t i = 0; i < n && ok; ++i) {
             key.clear();
-            key.push_back((char)n_near[(size_t)i]);
+            key.append(reinterpret_cast<const char*>(&n_near[(size_t)i]), sizeof(uint16_t));
             for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
                 const int64_t q = order[(size_t)p];
                 const int64_t off = (int64_t)col[q] - i;
@@ -147,18 +148,20 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
             auto it = ids.find(key);
             if (it == ids.end()) {
                 const int id = (int)ids.size();
-                const size_t cnt = (key.size() - 1) / sizeof(int32_t);
-                const size_t n_far = cnt - (uint8_t)key[0];
+                uint16_t nn;
+                std::memcpy(&nn, key.data(), sizeof(nn));
+                const size_t cnt = (key.size() - sizeof(uint16_t)) / sizeof(int32_t);
+                const size_t n_far = cnt - nn;
                 const size_t pad = n_far < far_min ? far_min - n_far : 0;
                 if (id >= kMaxPatterns || tab.size() + cnt + pad > (size_t)kMaxPatternEntries) {
                     ok = false;
                     break;
                 }
                 it = ids.emplace(key, id).first;
-                far.push_back((uint16_t)(tab.size() + (uint8_t)key[0]));
+                far.push_back((uint16_t)(tab.size() + nn));
                 for (size_t c = 0; c < cnt; ++c) {
                     int32_t e;
-                    std::memcpy(&e, key.data() + 1 + c * sizeof(int32_t), sizeof(e));
+                    std::memcpy(&e, key.data() + sizeof(uint16_t) + c * sizeof(int32_t), sizeof(e));
                     tab.push_back(e);
                 }
                 tab.insert(tab.end(), pad, 0);
@@ -180,12 +183,14 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
     const int64_t n_slices = (n + kSlice - 1) / kSlice;
     s.slice_off.assign(n_slices + 1, 0);
     s.deg.resize(n);
-    for (int64_t i = 0; i < n; ++i)
-        s.deg[i] = (uint16_t)(((uint32_t)n_near[(size_t)i] << 8) | (uint32_t)(row_ptr[i + 1] - row_ptr[i]));
+    for (int64_t i = 0; i < n; ++i) {
+        s.deg[i] = ((uint32_t)n_near[(size_t)i] << 16) | (uint32_t)(row_ptr[i + 1] - row_ptr[i]);
+        s.long_rows = s.long_rows || row_ptr[i + 1] - row_ptr[i] > kLongRow;
+    }
     for (int64_t sl = 0; sl < n_slices; ++sl) {
         int width = 0;
         for (int64_t i = sl * kSlice; i < std::min<int64_t>(n, (sl + 1) * kSlice); ++i)
-            width = std::max<int>(width, s.deg[i] & 255);
+            width = std::max<int>(width, (int)(s.deg[i] & 0xFFFFu));
         s.slice_off[sl + 1] = s.slice_off[sl] + (int64_t)kSlice * width;
     }
     s.nb.assign((size_t)s.slice_off[n_slices], 0u);
@@ -513,6 +518,8 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
         flags |= kCubic;
     if (s.demag.on)
         flags |= kDemag;
+    if (!s.stencil && s.long_rows)
+        flags |= kLongRows;
     rec.flags = flags;
     rec.n_patterns = s.stencil ? (int32_t)s.pat_start.size() - 1 : 0;
     rec.dm_cells = s.demag.on ? (int32_t)s.demag.cells : 0;

@@ -73,7 +73,8 @@ struct HostStructure {
     uint16_t reverse[kMaxTypes] = {};
     std::vector<uint32_t> nb;          // packed entries, 64 rows per slice, column-major
     std::vector<int64_t> slice_off;    // [n_slices + 1]
-    std::vector<uint16_t> deg;         // [n] near << 8 | degree
+    std::vector<uint32_t> deg;         // [n] near << 16 | degree
+    bool long_rows = false;            // SELL rows longer than kLongRow links
     // stencil form, filled when every row matches one of few patterns
     bool stencil = false;
     std::vector<uint8_t> pat_id;       // [n]

@@ -25,6 +25,7 @@ import numpy as np
 __all__ = [
     "Lattice",
     "simple_cubic",
+    "sc_long_range",
     "bcc",
     "fcc_sphere",
     "fcc_ellipsoid",
@@ -122,6 +123,37 @@ def simple_cubic(dims, periodic=(True, True, True)) -> Lattice:
     row_ptr, col, ntype = csr_from_padded(nbr, typ)
     pos = np.stack([x, y, z], axis=1).astype(np.float64)
     return Lattice("sc", pos, row_ptr, col, ntype, dims, tuple(periodic))
+
+
+def sc_long_range(L, r_cut, n_types=16):
+    """Periodic simple-cubic L^3 lattice in which every site is linked to all
+    sites within r_cut lattice constants (hundreds of partners for r_cut
+    around 4).  The distances are cut into at most n_types bins of equal
+    width in r (type t covers 1 + t (r_cut - 1)/n_types .. the next bound);
+    shells() returns the (r_lo, r_hi) of every type.  L must exceed 2 r_cut
+    so that no pair is linked twice through the periodic images."""
+    if L <= 2 * r_cut:
+        raise ValueError("L must exceed 2 r_cut")
+    m = int(np.floor(r_cut))
+    rng_ = np.arange(-m, m + 1)
+    dz, dy, dx = np.meshgrid(rng_, rng_, rng_, indexing="ij")
+    off = np.stack([dx.ravel(), dy.ravel(), dz.ravel()], axis=1)
+    r = np.sqrt((off ** 2).sum(1))
+    keep = (r > 0) & (r <= r_cut + 1e-9)
+    off, r = off[keep], r[keep]
+    edges = 1.0 + (r_cut - 1.0) * np.arange(n_types + 1) / n_types
+    edges[-1] = r_cut + 1e-6
+    typ = np.clip(np.searchsorted(edges, r, side="right") - 1, 0, n_types - 1).astype(np.uint8)
+    x, y, z = _cell_grid((L, L, L))
+    n = x.size
+    nbr = np.empty((n, off.shape[0]), dtype=np.int32)
+    for k, (ox, oy, oz) in enumerate(off):
+        nbr[:, k] = ((x + ox) % L) + L * (((y + oy) % L) + L * ((z + oz) % L))
+    row_ptr, col, ntype = csr_from_padded(nbr, np.tile(typ, (n, 1)))
+    pos = np.stack([x, y, z], axis=1).astype(np.float64)
+    lat = Lattice("sc", pos, row_ptr, col, ntype, (L, L, L), (True, True, True))
+    lat.shells = [(edges[t], edges[t + 1]) for t in range(n_types)]
+    return lat
 
 
 def bcc(dims, periodic=(True, True, True), second_neighbours=False) -> Lattice:

@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .lattice import Lattice, bcc, fcc_sphere, simple_cubic
+from .lattice import Lattice, bcc, fcc_sphere, sc_long_range, simple_cubic
 
 MU_B = 9.2740e-24      # J/T, Table 1
 GAMMA = 1.76e11        # 1/(T s), Table 1
@@ -24,6 +24,7 @@ __all__ = [
     "MU_B", "GAMMA", "Workload",
     "sc_reference", "bcc_film", "fcc_nanoparticle", "bcc_block", "serving_requests",
     "sc_request_system", "single_spin", "dmi_matrix", "with_tensor_exchange", "with_demag",
+    "long_range_sc",
 ]
 
 
@@ -269,3 +270,20 @@ def with_demag(w, a_nm, cell_size_nm, every=100, atom_volume_nm3=None) -> Worklo
     w.demag = {"pos": np.ascontiguousarray(w.lattice.pos * (a_nm * 1e-9)), "cell_size": cell_size_nm * 1e-9,
                "atom_volume": atom_volume_nm3 * 1e-27, "every": int(every)}
     return w
+
+
+def long_range_sc(L=16, r_cut=4.5, J1=6.0e-21, decay=1.0, temperature=300.0, seed=5, n_steps=1000,
+                  alpha=0.1, dt=1e-16) -> Workload:
+    """Long-range exchange on a periodic simple-cubic lattice (the paper's
+    remark that exchange can reach hundreds of partners): every pair within
+    r_cut lattice constants is linked, J(r) = J1 exp(-(r - 1)/decay) taken
+    at the middle of each of 16 radial bins.  At r_cut = 4.5, 388 partners
+    per site.  Materials and start as the simple-cubic test system."""
+    lat = sc_long_range(L, r_cut)
+    mid = np.array([0.5 * (a + b) for a, b in lat.shells])
+    J = J1 * np.exp(-(mid - 1.0) / decay)
+    n = lat.n
+    return Workload(
+        name=f"sc {L}^3 long-range r<={r_cut}", lattice=lat, J=J, mu_s=_uniform(n, 1.5 * MU_B),
+        k_u=_uniform(n, 1e-23), easy_axis=_axis(n), alpha=alpha, gamma=GAMMA, dt=dt,
+        temperature=temperature, H=np.zeros(3), seed=seed, n_steps=n_steps, S0=_spins(n, (0, 0, 1)))

@@ -1,0 +1,65 @@
+"""GPU parity for long-range exchange (hundreds of partners per site, the
+paper's remark on exchange reaching several lattice spacings): rows of 388
+links in 16 radial types against the FP64 oracle; Heun steps and Monte Carlo
+chains.  The periodic images give 9 row patterns per axis (729 > 256), so
+the rows take the SELL form; links within the halo come from the LDS
+window (lds_window 1) or every link from memory (lds_window 0).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1310_6143_amd as sl
+from spin_systems import long_range_sc
+from tests.gpu_util import max_angle, mean_angle
+
+pytestmark = pytest.mark.gpu
+
+
+def _system(T=300.0, seed=5):
+    w = long_range_sc(L=12, r_cut=4.5, temperature=T, seed=seed)
+    rng = np.random.default_rng(seed)
+    S0 = np.tile([0.0, 0.0, 1.0], (w.n, 1)) + 0.3 * rng.standard_normal((w.n, 3))
+    w.S0 = S0 / np.linalg.norm(S0, axis=1, keepdims=True)
+    w.H = np.array([0.1, 0.0, 0.3])
+    return w
+
+
+def test_long_range_rows_are_388_links():
+    w = _system()
+    assert np.all(np.diff(w.lattice.row_ptr) == 388)
+    assert w.J.size == 16
+
+
+@pytest.mark.parametrize("window", [1, 0])
+def test_long_range_heun_matches_oracle(window):
+    w = _system()
+    S_ref = np.ascontiguousarray(w.S0.copy())
+    m_ref, E_ref = oracle.System(w).integrate(S_ref, 0, 300)
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        assert g.get_option("neighbour_format") == 0
+        g.set_option("lds_window", window)
+        m, E = g.integrate(300)
+        S = g.get_spins()
+    ang = max_angle(S, S_ref)
+    print(f"long range FP64 lds_window={window}: max angle {ang:.2e}")
+    assert ang <= 1e-9
+    assert np.abs(m - m_ref).max() <= 1e-10
+    assert np.abs(E - E_ref).max() <= 1e-10 * np.abs(E_ref).max()
+    with sl.from_workload(w, precision=sl.FP32) as g:
+        g.set_option("lds_window", window)
+        m32, E32 = g.integrate(300)
+        S32 = g.get_spins()
+    assert max_angle(S32, S_ref) <= 2e-3 and mean_angle(S32, S_ref) <= 2e-4
+    assert np.abs(m32 - m_ref).max() <= 1e-4
+
+
+def test_long_range_mc_chain_matches_oracle():
+    w = _system(T=900.0, seed=7)
+    S_ref = np.ascontiguousarray(w.S0.copy())
+    m_ref, E_ref, acc_ref = oracle.System(w).mc(S_ref, 0, 10)
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        m, E, acc = g.mc(10)
+        S = g.get_spins()
+    assert np.array_equal(acc, acc_ref)
+    assert max_angle(S, S_ref) <= 1e-12

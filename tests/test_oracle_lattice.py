@@ -16,7 +16,7 @@ import os
 import numpy as np
 import pytest
 
-from spin_systems import bcc, fcc_sphere, simple_cubic, MU_B
+from spin_systems import bcc, fcc_sphere, sc_long_range, simple_cubic, MU_B
 from spin_systems import sc_reference, bcc_film, fcc_nanoparticle, bcc_block
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,8 +28,8 @@ def _rows_as_sets(row_ptr, col, ntype):
             for i in range(row_ptr.size - 1)]
 
 
-def _check_against_bruteforce(orc, lat, box, shells):
-    rp, c, t = orc.neighbours(lat.pos, box, shells)
+def _check_against_bruteforce(orc, lat, box, shells, max_degree=64):
+    rp, c, t = orc.neighbours(lat.pos, box, shells, max_degree)
     ours = _rows_as_sets(lat.row_ptr, lat.col, lat.ntype)
     ref = _rows_as_sets(rp, c, t)
     assert ours == ref
@@ -43,6 +43,18 @@ def test_sc_periodic_matches_bruteforce(orc):
     lat = simple_cubic((5, 4, 3), (True, True, True))
     _check_against_bruteforce(orc, lat, [5, 4, 3], [(0.99, 1.01)])
     assert np.all(lat.degree() == 6)
+
+
+def test_long_range_sc_matches_bruteforce(orc):
+    """Every pair within r_cut, 16 radial bins of equal width as types: the
+    count of integer vectors of length <= 3.2 is 146."""
+    lat = sc_long_range(7, 3.2)
+    # the builder's bins are closed on the left; the brute force takes the
+    # first bin whose closed interval holds r: nudge the inner bounds apart
+    shells = [(lo + 1e-9 if t > 0 else lo - 1e-9, hi - 1e-9 if t < 15 else hi + 1e-9)
+              for t, (lo, hi) in enumerate(lat.shells)]
+    _check_against_bruteforce(orc, lat, [7, 7, 7], shells, max_degree=200)
+    assert np.all(lat.degree() == 146)
 
 
 def test_sc_open_matches_bruteforce(orc):
