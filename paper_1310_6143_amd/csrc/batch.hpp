@@ -620,7 +620,7 @@ public:
         for (size_t c = 0; c + 1 < sl.colour_start.size(); ++c)
             hip_check(launch_mc<R>(d_reps_ + q, sl.d_colour + sl.colour_start[c],
                                    (int)(sl.colour_start[c + 1] - sl.colour_start[c]), step, cone, inv_kT,
-                                   accepted, st),
+                                   accepted, (sl.rec.flags & kTensor) != 0, st),
                       "Monte Carlo sweep");
     }
 

@@ -1270,13 +1270,13 @@ __global__ void k_noise(uint64_t seed, uint64_t step, int n, double* __restrict_
 // table order.
 constexpr int kMcBatch = 8;
 
-template <typename R>
+template <typename R, bool TX>
 __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, const Shared<R>& sh,
                                                      const R* __restrict__ S, int i)
 {
     V3<R> h{0, 0, 0};
     const char* sb = (const char*)S;
-    const bool tensor = (r.flags & kTensor) != 0;
+    const bool tensor = TX && (r.flags & kTensor);
     if (r.flags & kStencil) {
         const int p = gload(r.pat_id, i);
         const int b = sh.pat_start[p], e = sh.pat_start[p + 1];
@@ -1295,7 +1295,7 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
             }
 #pragma unroll
             for (int u = 0; u < kMcBatch; ++u)
-                add_coupled<R, true>(h, tensor, sh, ty[u], J[u], sj[u]);
+                add_coupled<R, TX>(h, tensor, sh, ty[u], J[u], sj[u]);
         }
         return h;
     }
@@ -1313,13 +1313,13 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
 #pragma unroll
         for (int u = 0; u < kMcBatch; ++u) {
             const int t = k + u < d ? (int)(ent[u] >> kColBits) : kMaxTypes;
-            add_coupled<R, true>(h, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj[u]);
+            add_coupled<R, TX>(h, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj[u]);
         }
     }
     return h;
 }
 
-template <typename R>
+template <typename R, bool TX>
 __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __restrict__ rep,
                                                       const int32_t* __restrict__ sites, int count, uint64_t step,
                                                       R cone, double inv_kT, unsigned long long* __restrict__ accepted)
@@ -1329,7 +1329,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __res
     const ReplicaDev<R>& r = *rep;
     if (threadIdx.x == 0)
         acc_block = 0;
-    stage_tables<R, true>(r, sh);
+    stage_tables<R, TX>(r, sh);
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) {
@@ -1337,7 +1337,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __res
         R* __restrict__ S = r.S[r.parity];
         const MaterialDev<R> m = site_material(r, i);
         const V3<R> s = load3((const R*)S, i);
-        const V3<R> sum = exchange_sum_global(r, sh, (const R*)S, i);
+        const V3<R> sum = exchange_sum_global<R, TX>(r, sh, (const R*)S, i);
         const V3<R> h{m.mu_rel * sum.x + r.H[0], m.mu_rel * sum.y + r.H[1], m.mu_rel * sum.z + r.H[2]};
         uint32_t c0 = (uint32_t)i, c1 = (uint32_t)step, c2 = (uint32_t)(step >> 32), c3 = 3u;
         philox10(c0, c1, c2, c3, (uint32_t)r.seed, (uint32_t)(r.seed >> 32));
@@ -1499,12 +1499,15 @@ hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStr
 
 template <typename R>
 hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, uint64_t step, double cone,
-                     double inv_kT, unsigned long long* accepted, hipStream_t st)
+                     double inv_kT, unsigned long long* accepted, bool tensor, hipStream_t st)
 {
     if (count <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((k_mc<R>), dim3((count + kBlockThreads - 1) / kBlockThreads), dim3(kBlockThreads), 0, st,
-                       rep, sites, count, step, (R)cone, inv_kT, accepted);
+    const dim3 g((count + kBlockThreads - 1) / kBlockThreads), b(kBlockThreads);
+    if (tensor)
+        hipLaunchKernelGGL((k_mc<R, true>), g, b, 0, st, rep, sites, count, step, (R)cone, inv_kT, accepted);
+    else
+        hipLaunchKernelGGL((k_mc<R, false>), g, b, 0, st, rep, sites, count, step, (R)cone, inv_kT, accepted);
     return hipGetLastError();
 }
 
@@ -1596,7 +1599,7 @@ hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t s
     template hipError_t launch_torque<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, int, \
                                          double*, hipStream_t);                                      \
     template hipError_t launch_mc<R>(const ReplicaDev<R>*, const int32_t*, int, uint64_t, double, double, \
-                                     unsigned long long*, hipStream_t);
+                                     unsigned long long*, bool, hipStream_t);
 
 SLLG_INSTANTIATE(float)
 SLLG_INSTANTIATE(double)

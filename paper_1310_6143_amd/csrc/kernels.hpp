@@ -62,10 +62,11 @@ int resident_blocks(int device, int variant);
 // One Monte Carlo sweep of one colour class (count sites listed in
 // `sites`) of the replica at *rep, step number `step` for the counters;
 // cone = sigma_g, inv_kT = 1/(kB T) (0 at T = 0); accepted trials are added
-// to *accepted.
+// to *accepted.  tensor: the replica has exchange tensors (kernel variant
+// that applies them).
 template <typename R>
 hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, uint64_t step, double cone,
-                     double inv_kT, unsigned long long* accepted, hipStream_t st);
+                     double inv_kT, unsigned long long* accepted, bool tensor, hipStream_t st);
 
 hipError_t launch_scatter_records(const double* rec, int count, double* m_dev, double* E_dev,
                                   hipStream_t st);
