@@ -113,6 +113,8 @@ def lib():
         L.orc_mc_run.restype = ctypes.c_int
         L.orc_demag_update.argtypes = [ctypes.POINTER(_System), P]
         L.orc_demag_update.restype = ctypes.c_int
+        L.orc_demag_sample.argtypes = [ctypes.POINTER(_System), P, ctypes.c_int64, P, P]
+        L.orc_demag_sample.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -260,6 +262,18 @@ class System:
         if rc != 0:
             raise MemoryError("oracle demagnetising field failed")
         return self._demag_field.copy(), int(self._demag.n_cells)
+
+    def demag_sample(self, S, sites):
+        """The demagnetising field computed from S at the given sites only
+        ([len(sites), 3] tesla); the held field is left as it was."""
+        sites = np.ascontiguousarray(sites, dtype=np.int64)
+        out = np.empty((sites.size, 3))
+        st = self._struct()
+        rc = lib().orc_demag_sample(ctypes.byref(st), _ptr(np.ascontiguousarray(S, dtype=np.float64)),
+                                    int(sites.size), _ptr(sites), _ptr(out))
+        if rc != 0:
+            raise ValueError(f"oracle demagnetising sample failed ({rc})")
+        return out
 
     def integrate(self, S, step0, n_steps, record=True):
         """Heun steps step0 .. step0+n_steps-1 in place on S ([n, 3] float64).

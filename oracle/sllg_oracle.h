@@ -79,6 +79,10 @@ typedef struct {
 /* Recompute the demagnetising field from the spins S (0, or -2 when out of
  * memory). */
 int orc_demag_update(const orc_system *s, const double *S);
+/* The same field at the cells of the given sites only (out: 3 per site), the
+ * held field left untouched: for spot checks of large systems.  0, -1 for a
+ * site out of range or no demagnetising field, -2 when out of memory. */
+int orc_demag_sample(const orc_system *s, const double *S, int64_t n_sites, const int64_t *sites, double *out);
 
 /* Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11). */

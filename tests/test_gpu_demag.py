@@ -69,3 +69,26 @@ def test_integration_with_demag_matches_oracle():
     with sl.from_workload(w, precision=sl.FP32) as g:
         g.integrate(500)
         assert max_angle(g.get_spins(), S_ref) <= 2e-3
+
+
+def test_demag_field_at_benchmark_size_sampled():
+    """The update the benchmark times: a simple-cubic slab of 128 x 128 x 32
+    atoms (a = 0.25 nm) in macrocells of 2 atoms per edge (65,536 cells,
+    8 source chunks of 8,192 cells), random spins; 512 sampled atoms against the oracle's
+    per-cell evaluation.  FP32 bound: positions carry about 6e-8 of the
+    32 nm slab (4e-6 of the nearest cell distance, tripled by 1/r^3) and each
+    chunk sums 8,192 terms in FP32, about 2e-5 of the largest field in all;
+    the bound is five times that."""
+    lat = simple_cubic((128, 128, 32), (False, False, False))
+    w = with_demag(_wl(lat, J=1e-21, spread=0.0), 0.25, 0.5, every=1)
+    S = np.random.default_rng(1).standard_normal((w.n, 3))
+    w.S0 = S / np.linalg.norm(S, axis=1, keepdims=True)
+    sites = np.random.default_rng(2).choice(w.n, 512, replace=False)
+    H_ref = oracle.System(w).demag_sample(w.S0, sites)
+    scale = np.abs(H_ref).max()
+    for prec, tol in ((sl.FP64, 1e-12), (sl.FP32, 1e-4)):
+        with sl.from_workload(w, precision=prec) as g:
+            H = g.demag_field()[sites]
+        err = np.abs(H - H_ref).max() / scale
+        print(f"65,536-cell slab {'FP64' if prec == sl.FP64 else 'FP32'}: max rel error {err:.2e} over 512 sites")
+        assert err <= tol

@@ -16,7 +16,7 @@ import paper_1310_6143_amd as sl
 from spin_systems import MU_B, bcc_block, fcc_nanoparticle, sc_reference
 from spin_systems.lattice import Lattice
 from spin_systems.workloads import GAMMA, Workload
-from tests.gpu_util import max_angle
+from tests.gpu_util import angles, max_angle
 
 pytestmark = pytest.mark.gpu
 KB = 1.3807e-23
@@ -123,3 +123,31 @@ def test_mc_longer_chain_in_two_calls_matches_oracle():
     assert np.array_equal(np.concatenate([acc, acc2]), acc_ref)
     assert max_angle(S, S_ref) <= 1e-12
     assert np.abs(np.concatenate([m, m2]) - m_ref).max() <= 1e-12
+
+
+def test_mc_full_block_in_the_bench_launch_shape():
+    """The 8,192,000-spin bcc J1+J2 block as the benchmark runs it (default
+    launch shape, 10 colour classes): FP64 chain identical to the oracle's
+    over 2 steps at every site; FP32 after 1 step within 1e-4 rad of the
+    oracle at all but a few sites (FP32 decisions can flip where the uniform
+    falls within FP32 rounding of the acceptance probability, about one
+    trial in 10^7, and a flipped site can tip a neighbour's later decision)."""
+    w = bcc_block(cells=160)
+    S_ref = np.ascontiguousarray(w.S0.copy())
+    orc = oracle.System(w)
+    _, _, acc1 = orc.mc(S_ref, 0, 1)
+    S1 = S_ref.copy()
+    _, _, acc2 = orc.mc(S_ref, 1, 1)
+    with sl.from_workload(w, precision=sl.FP64, check_symmetry=False) as g:
+        _, _, acc = g.mc(2)
+        S = g.get_spins()
+    assert np.array_equal(acc, np.concatenate([acc1, acc2]))
+    assert max_angle(S, S_ref) <= 1e-12
+    with sl.from_workload(w, precision=sl.FP32, check_symmetry=False) as g:
+        _, _, acc = g.mc(1)
+        S = g.get_spins()
+    off = int((angles(S, S1) > 1e-4).sum())
+    print(f"full block MC: FP64 accepted {acc1[0]} + {acc2[0]} as the oracle; FP32 step 1: "
+          f"{off} of {w.n} sites off by more than 1e-4 rad, accepted {acc[0]} vs {acc1[0]}")
+    assert off <= w.n // 10000
+    assert abs(int(acc[0]) - int(acc1[0])) <= w.n // 10000

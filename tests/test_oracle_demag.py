@@ -111,3 +111,18 @@ def test_update_schedule(orc):
     H4, _ = orc.System(w).demag_field(before4)
     assert np.array_equal(s._demag_field, H4)
     assert not np.array_equal(H4, H0)
+
+
+def test_sampled_field_equals_the_full_update(orc):
+    """The spot-check entry point (used at sizes where the full all-pairs
+    update is too slow for a test) gives the full update's values."""
+    lat = fcc_sphere(0.354, 2.0)
+    w = with_demag(_wl(lat), 0.354, 0.708, every=1)
+    rng = np.random.default_rng(5)
+    S = rng.standard_normal((w.n, 3))
+    S /= np.linalg.norm(S, axis=1, keepdims=True)
+    s = orc.System(w)
+    H, _ = s.demag_field(S)
+    sites = rng.choice(w.n, 40, replace=False)
+    assert np.array_equal(s.demag_sample(S, sites), H[sites])
+    assert np.array_equal(s._demag_field, H)          # the held field is untouched
