@@ -63,3 +63,18 @@ def test_long_range_mc_chain_matches_oracle():
         S = g.get_spins()
     assert np.array_equal(acc, acc_ref)
     assert max_angle(S, S_ref) <= 1e-12
+
+
+def test_long_range_at_benchmark_size():
+    """The system the benchmark times (64^3 = 262,144 spins, 388 links per
+    row, default launch shape): every site after 3 Heun steps against the
+    oracle, as the main block is checked at full size."""
+    w = long_range_sc(L=64, r_cut=4.5)
+    S_ref = np.ascontiguousarray(w.S0.copy())
+    oracle.System(w).integrate(S_ref, 0, 3, record=False)
+    for prec, tol in ((sl.FP64, 1e-12), (sl.FP32, 1e-5)):
+        with sl.from_workload(w, precision=prec) as g:
+            g.integrate(3, record=False)
+            ang = max_angle(g.get_spins(), S_ref)
+        print(f"long range 64^3 {'FP64' if prec == sl.FP64 else 'FP32'}: max angle {ang:.2e} after 3 steps")
+        assert ang <= tol
