@@ -1,6 +1,7 @@
 """GPU parity at the edges: degenerate systems (one spin, two spins),
-ragged sizes that end mid-wavefront and mid-tile, and the full 8,192,000-spin
-bcc block in the launch configuration bench.py times.  Everything is checked
+ragged sizes that end mid-wavefront and mid-tile, the full 8,192,000-spin
+bcc block in the launch configuration bench.py times, and the largest system
+the library accepts (2^28 - 1 spins).  Everything is checked
 against the FP64 oracle on the same inputs and noise stream.
 """
 import numpy as np
@@ -93,3 +94,72 @@ def test_full_size_block_matches_oracle():
         assert ang <= ang_tol
         assert np.abs(m - m_ref).max() <= rec_tol
         assert np.abs(E - E_ref).max() <= rec_tol * np.abs(E_ref).max()
+
+
+@pytest.mark.parametrize("precision,tol", [(sl.FP32, 1e-6), (sl.FP64, 1e-12)])
+def test_maximum_size_ring(precision, tol):
+    """The largest system the C ABI accepts, 2^28 - 1 spins, as a ring: spin
+    byte offsets pass 2^31 (so the rows take the SELL form), and the last
+    tile is ragged.  One step at T = 0 from a twisted state; 1024
+    sampled sites (both ends and the middle among them) against the oracle
+    on the 5-site open chain around each: a site's Heun step reads its own
+    and its neighbours' predictors, which read one site further, so the
+    chain's middle site is exact.  The step's m record against the mean of
+    the returned spins."""
+    n = (1 << 28) - 1
+    J, mu, ku, H = 6.0e-21, 1.5 * MU_B, 1e-23, np.array([0.3, -0.2, 0.5])
+    axis = np.array([0.0, 0.6, 0.8])
+
+    def state(i):
+        i = np.asarray(i, dtype=np.float64)
+        th = 0.6 + 0.4 * np.sin(0.013 * i)
+        ph = 0.37 * i
+        return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=-1)
+
+    g = sl.SpinSystem(n, precision)
+    try:
+        g.set_option("check_symmetry", 0)
+        i = np.arange(n, dtype=np.int64)
+        col = np.empty(2 * n, dtype=np.int32)
+        col[0::2] = (i - 1) % n
+        col[1::2] = (i + 1) % n
+        del i
+        g.set_neighbours(np.arange(0, 2 * n + 1, 2, dtype=np.int64), col, None, [J])
+        del col
+        assert g.get_option("neighbour_format") == 0          # SELL: the stencil needs offsets below 2^31 bytes
+        g.set_materials([mu], [ku], axis, per_site=0)
+        g.set_integrator(0.1, GAMMA, 1e-16)
+        g.set_conditions(0.0, H)
+        g.set_rng(1, 0)
+        g.set_spins(state(np.arange(n)))
+        m, _ = g.integrate(1)
+        S = g.get_spins()
+    finally:
+        g.close()
+    rng = np.random.default_rng(11)
+    sites = np.concatenate([[0, 1, 2, n // 2, (1 << 27) + 5, n - 3, n - 2, n - 1],
+                            rng.integers(0, n, 1016)])
+    k = sites.size
+    # k disjoint open chains of 5 sites, centre at local index 2
+    loc = np.arange(5 * k).reshape(k, 5)
+    rows = [[] for _ in range(5 * k)]
+    for a, b in zip(loc[:, :-1].ravel(), loc[:, 1:].ravel()):
+        rows[a].append(b)
+        rows[b].append(a)
+    row_ptr = np.zeros(5 * k + 1, dtype=np.int64)
+    row_ptr[1:] = np.cumsum([len(r) for r in rows])
+    ccol = np.array([c for r in rows for c in sorted(r)], dtype=np.int32)
+    lat = Lattice("chains", np.zeros((5 * k, 3)), row_ptr, ccol, np.zeros(ccol.size, dtype=np.uint8))
+    S0 = state((sites[:, None] + np.arange(-2, 3)[None, :]) % n).reshape(-1, 3)
+    S0 /= np.linalg.norm(S0, axis=1, keepdims=True)
+    w = Workload(name="chains", lattice=lat, J=np.array([J]), mu_s=np.full(5 * k, mu), k_u=np.full(5 * k, ku),
+                 easy_axis=np.tile(axis, (5 * k, 1)), alpha=0.1, gamma=GAMMA, dt=1e-16, temperature=0.0, H=H,
+                 seed=1, n_steps=1, S0=S0)
+    S_ref = np.ascontiguousarray(S0.copy())
+    oracle.System(w).integrate(S_ref, 0, 1, record=False)
+    ang = max_angle(S[sites], S_ref[loc[:, 2]])
+    dm = np.abs(m[0] - S.mean(axis=0)).max()
+    name = "FP32" if precision == sl.FP32 else "FP64"
+    print(f"ring of {n} spins {name}: max angle {ang:.2e} over {k} sampled sites; |m - mean S| {dm:.1e}")
+    assert ang <= tol
+    assert dm <= 1e-9
