@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import paper_1310_6143_amd as sl
-from spin_systems import bcc_block, single_spin
+from spin_systems import bcc_block, sc_reference, single_spin
 from spin_systems.lattice import Lattice
 from spin_systems.workloads import GAMMA, MU_B, Workload
 from tests.gpu_util import max_angle
@@ -163,3 +163,28 @@ def test_maximum_size_ring(precision, tol):
     print(f"ring of {n} spins {name}: max angle {ang:.2e} over {k} sampled sites; |m - mean S| {dm:.1e}")
     assert ang <= tol
     assert dm <= 1e-9
+
+
+def test_undamped_dynamics_and_zero_steps():
+    """lambda = 0, the method's degenerate damping: the thermal width
+    vanishes with lambda, so the run is noise-free even at 300 K.  FP64 vs
+    the oracle over 1000 steps from a tilted random state with anisotropy and
+    a field along z: spins, m and E (whose drift is then the Heun scheme's
+    alone, the same on both sides).  integrate(0) changes nothing."""
+    w = sc_reference(L=8, temperature=300.0, alpha=0.0, dt=1e-16)
+    rng = np.random.default_rng(21)
+    S0 = np.tile([0.0, 0.0, 1.0], (w.n, 1)) + 0.5 * rng.standard_normal((w.n, 3))
+    w.S0 = S0 / np.linalg.norm(S0, axis=1, keepdims=True)
+    w.H = np.array([0.0, 0.0, 0.4])
+    S_ref, m_ref, E_ref = _oracle(w, 1000)
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        m0, E0 = g.integrate(0)
+        assert m0.shape == (0, 3) and E0.shape == (0,) and g.step == 0
+        assert np.abs(g.get_spins() - w.S0).max() <= 1e-15
+        m, E = g.integrate(1000)
+        S = g.get_spins()
+    ang = max_angle(S, S_ref)
+    print(f"lambda = 0 FP64: max angle {ang:.2e}, E drift {E[-1] - E[0]:.3e} J (oracle {E_ref[-1] - E_ref[0]:.3e})")
+    assert ang <= 1e-9
+    assert np.abs(m - m_ref).max() <= 1e-12
+    assert np.abs(E - E_ref).max() <= 1e-12 * np.abs(E_ref).max()
