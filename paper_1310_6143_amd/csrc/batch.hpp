@@ -137,7 +137,7 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
     const size_t n = (size_t)s.n;
     const size_t tile = (size_t)tile_of(s, real_bytes);
     const size_t blocks = (n + tile - 1) / tile;
-    size_t b = 4 * r(spin_buffer_bytes(s.n, real_bytes));       // S[2], Sp, Bc
+    size_t b = 3 * r(spin_buffer_bytes(s.n, real_bytes));       // S[2], Sp
     if (s.stencil)
         b += r(pad16(n)) + r(s.pat_tab.size() * 4) + r(s.pat_start.size() * 2) + r(s.pat_far.size() * 2);
     else
@@ -248,7 +248,7 @@ public:
         }
         resident_ = resident_v_[0];
         // A group's tiles stream about 9 sizeof(R) bytes per site through the
-        // L2 per launch (S read, S' and Bc written, then read back); the
+        // L2 per launch (the corrector reads S' and S and writes S); the
         // plane-to-plane reuse spans two planes of a group, kept within a
         // quarter of one L2 (the L2 of one XCD on MI355X): group_sites_ is
         // that budget in sites.
@@ -322,9 +322,8 @@ public:
             r.S[0] = (R*)get(sb);
             r.S[1] = (R*)get(sb);
             r.Sp = (R*)get(sb);
-            r.Bc = (R*)get(sb);
             // the padding is staged with the last tile's window: keep it finite
-            for (void* p : {(void*)r.S[0], (void*)r.S[1], (void*)r.Sp, (void*)r.Bc})
+            for (void* p : {(void*)r.S[0], (void*)r.S[1], (void*)r.Sp})
                 hip_check(hipMemset(p, 0, sb), "clear spins");
             r.nb = nullptr;
             r.slice_off = nullptr;

@@ -33,8 +33,9 @@
 #ifndef SLLG_GATHER_UNROLL
 #define SLLG_GATHER_UNROLL 4
 #endif
-// Streaming (non-temporal) stores of S', Bc and S, and loads of Bc (read
-// once): measured faster on MI355X for the loads, and for FP64 stores.
+// Streaming (non-temporal) stores of S' and S, and the corrector's loads of
+// the old S (read once): measured faster on MI355X for the loads, and for
+// FP64 stores.
 #ifndef SLLG_NT_STORES_F32
 #define SLLG_NT_STORES_F32 0
 #endif
@@ -186,7 +187,8 @@ __device__ __forceinline__ void store3(R* __restrict__ p, int64_t i, V3<R> v)
     }
 }
 
-// Corrector base: read once, so streamed past the caches when enabled.
+// The corrector's own old spin: read once, so streamed past the caches when
+// enabled.
 template <typename R>
 __device__ __forceinline__ V3<R> load3_once(const R* __restrict__ p, int64_t i)
 {
@@ -851,7 +853,6 @@ __device__ __forceinline__ void predict_sites(const ReplicaDev<R>& r, const R* _
             const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
             const V3<R> sp = normalised(V3<R>{s.x + ds.x, s.y + ds.y, s.z + ds.z});
             store3(r.Sp, i, sp);
-            store3(r.Bc, i, V3<R>{s.x + (R)0.5 * ds.x, s.y + (R)0.5 * ds.y, s.z + (R)0.5 * ds.z});
         }
     }
 }
@@ -917,13 +918,22 @@ __global__ SLLG_STEP_ATTRS void k_predict(const ReplicaDev<R>* __restrict__ reps
 // ---------------------------------------------------------------------------
 // Corrector.  Field at S' with the same thermal numbers (same counter),
 // slope dS', and S_new = |S + (dS + dS') dt / 2| written to the other
-// ping-pong buffer.  Workgroups whose tile opens a group of kGroupTiles also
-// sum that group of the predictor's partials.
+// ping-pong buffer.  The predictor's increment is not stored: dS is
+// perpendicular to S and |S| = 1, so the site's own predictor
+// S' = (S + dS dt)/|S + dS dt| has S.S' = 1/|S + dS dt|, and
+// S + dS dt / 2 = (S + S'/(S.S'))/2 comes from S and S' (whatever the
+// rounding of the predictor's normalisation, which cancels in S'/(S.S')).
+// Workgroups whose tile opens a group of kGroupTiles also sum that group of
+// the predictor's partials.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <typename R, int V>
-__device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* __restrict__ Sp,
-                                              R* __restrict__ Sn, const Shared<R>& sh,
-                                              const TileLds<R>& tl, int i0, int wb, int k)
+__device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* __restrict__ Sc,
+                                              const R* __restrict__ Sp, R* __restrict__ Sn,
+                                              const Shared<R>& sh, const TileLds<R>& tl, int i0, int wb,
+                                              int k)
 {
     constexpr bool PS = V != 0, TX = V == 2;
     const int T = r.tile;
@@ -935,7 +945,7 @@ __device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* _
         const MaterialDev<R> m = PS ? site_material(r, i) : m0;   // loaded before the gathers are issued
         const int wbyte = site_bytes<R>(l + r.halo);
         const V3<R> sp = (r.flags & kDirect) ? load3(Sp, i) : wload3(tl.win, wbyte);
-        const V3<R> b = load3_once((const R*)r.Bc, i);
+        const V3<R> s0 = load3_once(Sc, i);
         R g[3] = {0, 0, 0};
         const V3<R> sum = exchange_sum<R, TX>(r, Sp, sh, tl, i, l, wb, wbyte, [&] {
             if (m.sigma != (R)0)
@@ -952,6 +962,8 @@ __device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* _
             add_demag(r, i, h);
         add_thermal(m, g, h);
         const V3<R> ds = llg_step(sp, h, r.gdt, r.alpha);
+        const R q = (R)0.5 * recip(dot(s0, sp));
+        const V3<R> b{(R)0.5 * s0.x + q * sp.x, (R)0.5 * s0.y + q * sp.y, (R)0.5 * s0.z + q * sp.z};
         const V3<R> sn = normalised(V3<R>{b.x + (R)0.5 * ds.x, b.y + (R)0.5 * ds.y, b.z + (R)0.5 * ds.z});
         store3(Sn, i, sn);
     }
@@ -985,11 +997,12 @@ __global__ SLLG_STEP_ATTRS void k_correct(const ReplicaDev<R>* __restrict__ reps
         if (r.flags & kStencil)
             stage_ids(r.pat_id, r.n, i0, T, tl.pid);
         __syncthreads();
+        const R* __restrict__ Sc = r.S[(r.parity + k) & 1];
         R* __restrict__ Sn = r.S[(r.parity + k + 1) & 1];
         if (V != 0 && (r.flags & kGeneralFlags))
-            correct_sites<R, V>(r, Sp, Sn, sh, tl, i0, wb, k);
+            correct_sites<R, V>(r, Sc, Sp, Sn, sh, tl, i0, wb, k);
         else
-            correct_sites<R, 0>(r, Sp, Sn, sh, tl, i0, wb, k);
+            correct_sites<R, 0>(r, Sc, Sp, Sn, sh, tl, i0, wb, k);
         if ((r.flags & kRecord) && k >= 1 && (w.block % kGroupTiles) == 0)
             group_reduce(r, w.block / kGroupTiles, red);
     }

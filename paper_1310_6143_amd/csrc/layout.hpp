@@ -129,7 +129,6 @@ template <typename R>
 struct ReplicaDev {
     R* S[2];                        // ping-pong spin buffers [3n]
     R* Sp;                          // predicted spins S' [3n]
-    R* Bc;                          // corrector base S + dS dt / 2 [3n]
     const uint32_t* nb;             // SELL-64 neighbour entries
     const int64_t* slice_off;       // [n_slices + 1] first entry of each slice
     const uint32_t* deg;            // [n] near << 16 | neighbours, per site (SELL)
