@@ -67,11 +67,15 @@ def measured_traffic(precision):
     return profile_value(f"{precision}_hbm_bytes_per_step")
 
 
-def run_gpu(w, precision, steps, warmup, torch, launch=None, autotune=False):
+def run_gpu(w, precision, steps, warmup, torch, launch=None, autotune=False, fused=1, fused_shape=None):
     import paper_1310_6143_amd as sl
 
     t0 = time.time()
     sysm = sl.from_workload(w, precision=precision, check_symmetry=False)
+    sysm.set_option("fused", fused)
+    if fused_shape and sysm.get_option("lattice") == 2:
+        for key, v in zip(("fused_tile_x", "fused_tile_y", "fused_planes", "fused_threads"), fused_shape):
+            sysm.set_option(key, v)
     log(f"precision {'fp32' if precision == sl.FP32 else 'fp64'}: set-up {time.time() - t0:.1f} s")
     st = torch.cuda.Stream()
     if launch:
@@ -107,8 +111,11 @@ def run_gpu(w, precision, steps, warmup, torch, launch=None, autotune=False):
     E = E_dev.cpu().numpy()
     if not np.all(np.isfinite(E)):
         raise SystemExit("non-finite energy in the timed run")
+    fused_on = sysm.get_option("fused_active")
+    shape = [sysm.get_option(k) for k in ("fused_tile_x", "fused_tile_y", "fused_planes", "fused_threads")]
     sysm.close()
-    log(f"  {steps} steps in {ms:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
+    log(f"  {steps} steps in {ms:.2f} ms (events), {wall * 1e3:.2f} ms (wall); fused {fused_on} shape {shape}")
+    choice = dict(choice, fused=int(fused_on), fused_shape=shape if fused_on else None)
     return {"ms": ms, "wall_s": wall, "m": m, "E": E, "launch": choice}
 
 
@@ -497,6 +504,10 @@ def main():
                     "instead of the library default")
     ap.add_argument("--autotune", action="store_true", help="time the candidate launch shapes first "
                     "and run the fastest (sllg_autotune)")
+    ap.add_argument("--no-fused", action="store_true", help="run the two-launch step even where the "
+                    "lattice allows the fused one")
+    ap.add_argument("--fused-shape", default="", help="fused work-item shape 'tile_x,tile_y,planes,threads' "
+                    "instead of the library's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy of this many MiB (for counter calibration)")
     args = ap.parse_args()
@@ -549,12 +560,15 @@ def main():
     import paper_1310_6143_amd as sl
 
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    fshape = tuple(int(v) for v in args.fused_shape.split(",")) if args.fused_shape else None
+    fused = 0 if args.no_fused else 1
     if args.only_fp64:
-        r64 = run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch, args.autotune)
+        r64 = run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch, args.autotune, fused, fshape)
         print(json.dumps({"fp64_ms_per_step": r64["ms"] / args.steps}))
         return
-    r32 = run_gpu(w, sl.FP32, args.steps, args.warmup, torch, launch, args.autotune)
-    r64 = None if args.no_fp64 else run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch, args.autotune)
+    r32 = run_gpu(w, sl.FP32, args.steps, args.warmup, torch, launch, args.autotune, fused, fshape)
+    r64 = None if args.no_fp64 else run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch, args.autotune,
+                                            fused, fshape)
 
     n = w.n
     ms_step = r32["ms"] / args.steps

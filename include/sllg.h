@@ -90,6 +90,31 @@ const char *sllg_status_string(sllg_status status);
 sllg_status sllg_set_neighbours(sllg_system *sys, const int64_t *row_ptr, const int32_t *col,
                                 const uint8_t *ntype, const double *J, int n_types);
 
+/* Lattice numbering (section "Atomistic system generation": a unit cell of
+ * n_basis sites replicated on a grid of cells[0] x cells[1] x cells[2]
+ * cells).  Declares that site i of the current neighbour list is basis site
+ * b of cell (x, y, z) with i = b + n_basis (x + cells[0] (y + cells[1] z));
+ * periodic[a] != 0 marks axis a as periodic.  Every link must join cells at
+ * most one cell apart on each axis (across the boundary on a periodic
+ * axis); SLLG_E_ARG otherwise, or when n_basis x cells does not equal the
+ * number of spins.  The declaration lets the library run the fused step: a
+ * single launch per Heun step in which each workgroup recomputes the
+ * predictor on a ring of cells around its tile, so that every predictor of
+ * its sites' neighbours is ready before its correctors, the order the
+ * section "Time Integration of the LLG Equation" requires.  The fused step
+ * takes lattices periodic in x and y (z periodic or open) with at most 2
+ * sites per cell whose links depend only on the plane and the basis site,
+ * uniform materials, scalar exchange, no cubic anisotropy or demagnetising
+ * field, in FP32 (sllg_get_option "lattice" = 2 when the structure
+ * qualifies, "fused_active" = 1 when the next integration takes it); other
+ * systems run the two-launch step.  The exchange sum of a site is then
+ * added in a fixed order (links into the plane below, its own plane, the
+ * plane above), so trajectories agree with the two-launch step to FP32
+ * rounding, not bit for bit.  Call after sllg_set_neighbours; a new
+ * neighbour list drops the declaration.  SLLG_E_STATE before
+ * sllg_set_neighbours. */
+sllg_status sllg_set_lattice(sllg_system *sys, int n_basis, const int cells[3], const int periodic[3]);
+
 /* Atomic moments mu_s (J/T, > 0), uniaxial anisotropy constants k_u
  * (J/atom, any sign) and easy axes e (unit vectors, normalised here).
  * per_site = 0: one value each (mu_s[1], k_u[1], easy_axis[3]) for every
@@ -338,7 +363,23 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     the list as per-site stencil patterns when at most 256
  *                     distinct (column - row, type) rows occur (<= 1024
  *                     entries in all); 0 keeps the general SELL-64 form
+ *   "fused"           1 (default): integrate with the fused step whenever the
+ *                     system qualifies (sllg_set_lattice); 0: always the
+ *                     two-launch step
+ *   "fused_tile_x", "fused_tile_y", "fused_planes", "fused_threads"
+ *                     shape of the fused step's work items: a tile of
+ *                     tile_x x tile_y cell columns marched through `planes`
+ *                     planes by a workgroup of `threads` (256, 512 or 640)
+ *                     threads, which needs (tile_x + 2)(tile_y + 2) <=
+ *                     threads and tile_x, tile_y >= 6; takes effect once all
+ *                     four are set (0 returns to the library's choice; the
+ *                     autotuner also picks among shapes).  Results do not
+ *                     depend on the shape except the m and E records, at FP64
+ *                     rounding.
  * sllg_get_option also reads "neighbour_format": 1 stencil, 0 SELL, -1 unset;
+ * "lattice": 0 none declared, 1 declared, 2 declared and the fused step can
+ * take its structure; "fused_active": 1 when the next integration runs the
+ * fused step; the fused_* shape keys read the shape in use;
  * "halo": neighbours with |column - row| up to this many
  * sites are read from the tile's window in LDS, the rest from HBM (-1 unset).
  */

@@ -23,6 +23,7 @@ STATUS = {0: "SLLG_OK", -1: "SLLG_E_ARG", -2: "SLLG_E_NOMEM", -3: "SLLG_E_DEVICE
 # every symbol include/sllg.h declares
 EXPORTS = [
     "sllg_create", "sllg_destroy", "sllg_last_error", "sllg_status_string", "sllg_set_neighbours",
+    "sllg_set_lattice",
     "sllg_set_materials", "sllg_set_exchange_tensors", "sllg_set_cubic_anisotropy", "sllg_set_demag",
     "sllg_demag_field", "sllg_set_integrator", "sllg_set_conditions", "sllg_set_rng",
     "sllg_get_step", "sllg_set_spins", "sllg_get_spins", "sllg_integrate", "sllg_integrate_dev",
@@ -91,6 +92,7 @@ def lib():
         "sllg_last_error": (ctypes.c_char_p, [P]),
         "sllg_status_string": (ctypes.c_char_p, [c]),
         "sllg_set_neighbours": (c, [P, P, P, P, P, c]),
+        "sllg_set_lattice": (c, [P, c, P, P]),
         "sllg_set_materials": (c, [P, P, P, P, c]),
         "sllg_set_exchange_tensors": (c, [P, P, c]),
         "sllg_max_torque": (c, [P, P, P]),
@@ -217,6 +219,13 @@ class SpinSystem:
         J = _c64(np.atleast_1d(J))
         self._check(lib().sllg_set_neighbours(self._h, _ptr(row_ptr), _ptr(col), _ptr(ntype), _ptr(J),
                                               int(J.size)))
+
+    def set_lattice(self, n_basis, cells, periodic):
+        """Declare site i = b + n_basis (x + cells[0] (y + cells[1] z))
+        (sllg_set_lattice): lets the library take the fused step."""
+        cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(3)
+        per = np.ascontiguousarray([1 if p else 0 for p in periodic], dtype=np.int32).reshape(3)
+        self._check(lib().sllg_set_lattice(self._h, int(n_basis), _ptr(cells), _ptr(per)))
 
     def set_materials(self, mu_s, k_u, easy_axis, per_site=None):
         mu_s = _c64(np.atleast_1d(mu_s))
@@ -415,9 +424,10 @@ def _avg_dict(o):
             "E_se": float(o[6]), "n_blocks": int(o[7])}
 
 
-def from_workload(w, precision=FP32, device=0, check_symmetry=True, stencil=1):
+def from_workload(w, precision=FP32, device=0, check_symmetry=True, stencil=1, lattice=True):
     """Build a SpinSystem from a spin_systems.Workload-like object.
-    stencil=0 keeps the general SELL-64 neighbour layout."""
+    stencil=0 keeps the general SELL-64 neighbour layout; lattice=False
+    leaves the cell grid of a crystal lattice undeclared (no fused step)."""
     s = SpinSystem(w.lattice.n, precision, device)
     if not check_symmetry:
         s.set_option("check_symmetry", 0)
@@ -425,6 +435,16 @@ def from_workload(w, precision=FP32, device=0, check_symmetry=True, stencil=1):
         s.set_option("stencil", 0)
     lat = w.lattice
     s.set_neighbours(lat.row_ptr, lat.col, lat.ntype, w.J)
+    if lattice and lat.dims is not None:
+        cells = int(np.prod(lat.dims))
+        if cells > 0 and lat.n % cells == 0:
+            try:
+                s.set_lattice(lat.n // cells, lat.dims, lat.periodic)
+            except SllgError as err:
+                # links beyond the next cell (long-range exchange): no cell
+                # lattice in the library's sense
+                if err.status != -1:   # SLLG_E_ARG
+                    raise
     mu, ku, ax = np.asarray(w.mu_s), np.asarray(w.k_u), np.asarray(w.easy_axis)
     uniform = bool(np.all(mu == mu[0]) and np.all(ku == ku[0]) and np.all(ax == ax[0]))
     if uniform:

@@ -67,6 +67,13 @@ struct Engine {
     virtual uint64_t step() = 0;
     virtual void set_step(uint64_t step) = 0;
     virtual int64_t rec_cap() = 0;
+    // fused plane-marching step
+    virtual void set_fused(bool on) = 0;
+    virtual bool fused_capable() = 0;          // the replica can take the fused step
+    virtual FusedShape fused_shape() = 0;
+    virtual void set_fused_shape(const FusedShape& f) = 0;
+    virtual std::vector<FusedShape> fused_candidates(int max_count) = 0;
+    virtual size_t lds_limit() = 0;
 };
 
 }  // namespace
@@ -145,6 +152,20 @@ struct EngineT final : Engine {
         batch.mark_dirty();
     }
     int64_t rec_cap() override { return cap; }
+    void set_fused(bool on) override { batch.set_fused(on); }
+    bool fused_capable() override
+    {
+        return (batch.mirror(q).flags & kFused) && batch.mirror(q).f_partials;
+    }
+    FusedShape fused_shape() override { return batch.fused_shape(q); }
+    void set_fused_shape(const FusedShape& f) override { batch.set_fused_shape(q, f); }
+    size_t lds_limit() override { return batch.lds_limit(); }
+    std::vector<FusedShape> fused_candidates(int max_count) override
+    {
+        if (!batch.mirror(q).f_partials)
+            return {};
+        return batch.fused_candidate_shapes(q, max_count);
+    }
 };
 
 }  // namespace
@@ -177,6 +198,8 @@ struct sllg_system {
     bool tuned = false;
     double tuned_us = 0.0;
     int64_t opt_stencil = 1;
+    int64_t opt_fused = 1;              // the fused plane-marching step where the lattice allows it
+    FusedShape opt_fshape;              // all fields > 0: this shape instead of the model's
     hipStream_t own = nullptr;
     std::unique_ptr<Engine> eng;
     std::vector<double> staging;
@@ -244,6 +267,10 @@ Engine& engine(sllg_system* s)
         s->eng->set_grid_scale(s->opt_grid_scale_pct / 100.0);
         s->eng->set_tile_order((int)s->opt_tile_order, (int)s->opt_tile_group);
         s->eng->set_window(s->opt_lds_window != 0);
+        s->eng->set_fused(s->opt_fused != 0);
+        const FusedShape& f = s->opt_fshape;
+        if (f.px > 0 && f.py > 0 && f.planes > 0 && f.bt > 0 && s->eng->fused_capable())
+            s->eng->set_fused_shape(f);
     }
     hip_check(hipSetDevice(s->device), "hipSetDevice");
     return *s->eng;
@@ -599,6 +626,23 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
     return best;
 }
 
+// The fused shape in use (engine), requested (option), or 0 when unknown.
+FusedShape current_fused_shape(const sllg_system* s)
+{
+    if (s->eng && s->eng->fused_capable())
+        return s->eng->fused_shape();
+    return s->opt_fshape;
+}
+
+// The next integration takes the fused step: a fusable lattice, uniform
+// materials, scalar exchange, no cubic anisotropy or demagnetising field,
+// FP32, and the option on.
+bool fused_will_run(const sllg_system* s)
+{
+    return s->opt_fused && s->prec == SLLG_FP32 && s->st.lat.on && s->st.lat.fusable && s->has_mat &&
+           !s->mat.per_site_material && !s->mat.per_site_axis && !s->st.tensor && !s->mat.cubic && !s->st.demag.on;
+}
+
 void apply_dynamics(sllg_system* s)
 {
     if (s->eng)
@@ -689,6 +733,18 @@ sllg_status sllg_set_neighbours(sllg_system* sys, const int64_t* row_ptr, const 
         drop_engine(sys);
         sys->st = std::move(st);
         sys->has_nb = true;
+    });
+}
+
+sllg_status sllg_set_lattice(sllg_system* sys, int n_basis, const int cells[3], const int periodic[3])
+{
+    return guard(sys, [&] {
+        if (!sys->has_nb)
+            fail(SLLG_E_STATE, "neighbour list not set (sllg_set_neighbours)");
+        HostStructure st = sys->st;
+        set_lattice(st, n_basis, cells, periodic);
+        drop_engine(sys);   // rebuilt at the next run with the fused step's buffers, state kept
+        sys->st = std::move(st);
     });
 }
 
@@ -1234,6 +1290,44 @@ sllg_status sllg_set_option(sllg_system* sys, const char* key, int64_t value)
             sys->opt_xcd_remap = value;
             if (sys->eng)
                 sys->eng->set_remap((int)sys->opt_xcd_remap);
+        } else if (k == "fused") {
+            if (value < 0 || value > 1)
+                fail(SLLG_E_ARG, "fused must be 0 or 1");
+            sys->opt_fused = value;
+            if (sys->eng)
+                sys->eng->set_fused(value != 0);
+        } else if (k == "fused_tile_x" || k == "fused_tile_y" || k == "fused_planes" || k == "fused_threads") {
+            if (value < 0 || value > 0xFFFF)
+                fail(SLLG_E_ARG, k + " must be in 0..65535");
+            // fields not set yet start from the shape in use (once the engine exists)
+            FusedShape f = sys->opt_fshape;
+            const FusedShape cur = current_fused_shape(sys);
+            if (f.px <= 0 && f.py <= 0 && f.planes <= 0 && f.bt <= 0)
+                f = cur;
+            if (k == "fused_tile_x")
+                f.px = value > 0 ? (int)value + 2 : 0;
+            else if (k == "fused_tile_y")
+                f.py = value > 0 ? (int)value + 2 : 0;
+            else if (k == "fused_planes")
+                f.planes = (int)value;
+            else
+                f.bt = (int)value;
+            if (value == 0) {
+                sys->opt_fshape = FusedShape{};   // the model's shape at the next rebuild
+            } else if (f.px > 0 && f.py > 0 && f.planes > 0 && f.bt > 0) {
+                if (!sys->st.lat.on || !sys->st.lat.fusable)
+                    fail(SLLG_E_STATE, "no fused step: declare a lattice the fused step takes (sllg_set_lattice)");
+                // the device's LDS limit once it is open (MI355X: 160 KB per workgroup)
+                if (!fused_shape_ok(f, sys->st.lat, sys->eng ? sys->eng->lds_limit() : (size_t)160 * 1024))
+                    fail(SLLG_E_ARG, "fused shape out of range (tile " + std::to_string(f.px - 2) + " x " +
+                                         std::to_string(f.py - 2) + ", " + std::to_string(f.planes) +
+                                         " planes, " + std::to_string(f.bt) + " threads)");
+                sys->opt_fshape = f;
+                if (sys->eng && sys->eng->fused_capable())
+                    sys->eng->set_fused_shape(f);
+            } else {
+                sys->opt_fshape = f;   // applied once every field is set
+            }
         } else {
             fail(SLLG_E_ARG, "unknown option '" + k + "'");
         }
@@ -1273,7 +1367,18 @@ sllg_status sllg_get_option(const sllg_system* sys, const char* key, int64_t* va
         *value = sys->tuned ? (int64_t)(sys->tuned_us * 1e3) : -1;
     else if (k == "neighbour_format")
         *value = sys->has_nb ? (sys->st.stencil ? 1 : 0) : -1;
-    else
+    else if (k == "fused")
+        *value = sys->opt_fused;
+    else if (k == "lattice")
+        *value = sys->st.lat.on ? (sys->st.lat.fusable ? 2 : 1) : 0;
+    else if (k == "fused_active")
+        *value = fused_will_run(sys) ? 1 : 0;
+    else if (k == "fused_tile_x" || k == "fused_tile_y" || k == "fused_planes" || k == "fused_threads") {
+        const FusedShape f = current_fused_shape(sys);
+        *value = k == "fused_tile_x" ? f.px - 2 : k == "fused_tile_y" ? f.py - 2 : k == "fused_planes" ? f.planes : f.bt;
+        if (f.px <= 0)
+            *value = 0;
+    } else
         return SLLG_E_ARG;
     return SLLG_OK;
 }

@@ -129,6 +129,109 @@ private:
 
 inline size_t pad16(size_t b) { return (b + 15) & ~size_t(15); }
 
+// Shape of the fused step's work items: thread region px x py (tile + 2 cells
+// per axis), `planes` planes per item, bt threads per workgroup.
+struct FusedShape {
+    int px = 0, py = 0, planes = 0, bt = 0;
+    bool operator==(const FusedShape& o) const
+    {
+        return px == o.px && py == o.py && planes == o.planes && bt == o.bt;
+    }
+};
+
+constexpr int kFusedMinPlanes = 4;
+
+// Most work items any allowed shape gives (smallest tiles, fewest planes).
+inline int64_t fused_item_cap(const HostLattice& L)
+{
+    const int64_t t = kFusedMinEdge - 2, p = std::max(std::min(kFusedMinPlanes, L.nz), 1);
+    return ((L.nx + t - 1) / t) * ((L.ny + t - 1) / t) * ((L.nz + p - 1) / p);
+}
+
+// LDS bytes of one plane of the fused kernel (a slot of 16 bytes per site
+// of the tile, the ring and one more ring).
+inline int fused_plane_bytes(const FusedShape& f, int nb)
+{
+    return (f.px + 2) * (f.py + 2) * nb * 16;
+}
+
+// A shape the kernels take for lattice L: the region fits the block, the
+// LDS planes fit the device (lds_limit bytes per workgroup) and each wave
+// copies at most three chunks of 64 sites per plane; items have at least
+// kFusedMinPlanes planes (all of them on thinner lattices).
+inline bool fused_shape_ok(const FusedShape& f, const HostLattice& L, size_t lds_limit)
+{
+    if (!fused_block_ok(f.bt) || f.px < kFusedMinEdge || f.py < kFusedMinEdge || f.px > 0x7FFF || f.py > 0x7FFF ||
+        (int64_t)f.px * f.py > f.bt || f.planes < std::min(kFusedMinPlanes, L.nz))
+        return false;
+    const int64_t slots = (int64_t)(f.px + 2) * (f.py + 2) * L.nb;
+    if ((slots + 63) / 64 > 3 * (f.bt / 64))
+        return false;
+    return fused_lds_bytes(L.kind, fused_plane_bytes(f, L.nb), f.bt) <= lds_limit;
+}
+
+// Work items of a lattice for a shape.
+inline int64_t fused_items(const HostLattice& L, const FusedShape& f)
+{
+    const int64_t tx = f.px - 2, ty = f.py - 2;
+    return ((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty) * ((L.nz + f.planes - 1) / f.planes);
+}
+
+// Candidate shapes for a lattice (the autotuner times them; the first is
+// the model's choice).  resident(f) gives the workgroups the device holds
+// at once for shape f.  The planes per item are chosen so that the items
+// fill whole rounds of the resident workgroups; the model counts
+// wave-instructions of one item (predictor on planes + 2, corrector on
+// planes, plane copies on planes + 4) times rounds.
+template <typename Resident>
+inline std::vector<FusedShape> fused_candidates(const HostLattice& L, size_t lds_limit, Resident&& resident,
+                                                int max_count)
+{
+    struct Scored {
+        double cost;
+        FusedShape f;
+    };
+    std::vector<Scored> all;
+    for (int bt : {256, 512}) {
+        for (int px = kFusedMinEdge; px <= 64; ++px)
+            for (int py = kFusedMinEdge; py <= bt / kFusedMinEdge; ++py) {
+                FusedShape f{px, py, std::min(kFusedMinPlanes, L.nz), bt};
+                if (!fused_shape_ok(f, L, lds_limit))
+                    continue;
+                const int tx = px - 2, ty = py - 2;
+                if (tx > L.nx + 6 || ty > L.ny + 6)   // far wider than the lattice
+                    continue;
+                const int R = std::max(resident(f), 1);
+                const int64_t cols = (int64_t)((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty);
+                const int waves = (px * py + 63) / 64;
+                for (int segs = 1; segs <= L.nz; ++segs) {
+                    const int planes = (L.nz + segs - 1) / segs;
+                    if (planes < std::min(kFusedMinPlanes, L.nz))
+                        break;
+                    if (segs > 1 && (L.nz + segs - 2) / (segs - 1) == planes)
+                        continue;   // the same planes as fewer segments
+                    const int64_t items = cols * ((L.nz + planes - 1) / planes);
+                    const double item = waves * ((planes + 2) * 1.0 + planes * 0.6 + (planes + 4) * 0.25);
+                    const double rounds = std::ceil((double)items / R);
+                    f.planes = planes;
+                    all.push_back({rounds * item * R, f});
+                }
+            }
+    }
+    std::sort(all.begin(), all.end(), [](const Scored& a, const Scored& b) { return a.cost < b.cost; });
+    std::vector<FusedShape> out;
+    for (const auto& a : all) {
+        if ((int)out.size() >= max_count)
+            break;
+        bool dup = false;
+        for (const auto& o : out)
+            dup = dup || o == a.f;
+        if (!dup)
+            out.push_back(a.f);
+    }
+    return out;
+}
+
 // Bytes of device memory one replica needs (used for admission).
 inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size_t real_bytes,
                             int64_t rec_cap, int avg_cap)
@@ -137,7 +240,7 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
     const size_t n = (size_t)s.n;
     const size_t tile = (size_t)tile_of(s, real_bytes);
     const size_t blocks = (n + tile - 1) / tile;
-    size_t b = 3 * r(spin_buffer_bytes(s.n, real_bytes));       // S[2], Sp
+    size_t b = 3 * r(spin_buffer_bytes(s.n, real_bytes) + 16);  // S[2], Sp
     if (s.stencil)
         b += r(pad16(n)) + r(s.pat_tab.size() * 4) + r(s.pat_start.size() * 2) + r(s.pat_far.size() * 2);
     else
@@ -152,6 +255,13 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
         const size_t nc = (size_t)s.demag.cells;
         b += 2 * r(4 * n) + r(4 * (nc + 1)) + 3 * r(3 * nc * real_bytes) + r(nc * real_bytes) +
              r(3 * nc * (size_t)demag_chunks(s.demag.cells) * real_bytes);
+    }
+    if (s.lat.on && s.lat.fusable && real_bytes == 4) {
+        size_t ent = 0;
+        for (const auto& p : s.lat.pats)
+            ent += p.size();
+        b += r(ent * sizeof(FusedEntry)) + r(s.lat.pats.size() * 16) + r(s.lat.plane_pat.size()) +
+             r((size_t)fused_item_cap(s.lat) * 64);
     }
     b += r(m.mat_mu.size() * sizeof(MaterialDev<double>));
     const size_t groups = (blocks + kGroupTiles - 1) / kGroupTiles;
@@ -229,6 +339,11 @@ public:
         int plane_tiles = 0;     // see plane_tiles()
         int32_t* d_colour = nullptr;            // Monte Carlo: sites by colour class
         std::vector<int64_t> colour_start;      // [n_colours + 1]
+        // fused step (kFused): patterns, shape and work items
+        HostLattice lat;
+        FusedShape fshape;
+        int64_t f_cap_items = 0;                // items the partials buffer holds
+        std::vector<FusedItem> f_items;
     };
 
     Batch(int device, Allocator* alloc, int max_replicas)
@@ -267,6 +382,7 @@ public:
                 remove(q);
         (void)hipFree(d_reps_);
         (void)hipFree(d_work_);
+        (void)hipFree(d_fwork_);
         (void)hipFree(d_nwork_);
         (void)hipFree(d_torque_work_);
         (void)hipFree(d_torque_);
@@ -319,12 +435,14 @@ public:
             };
             ReplicaDev<R>& r = sl.rec;
             const size_t sb = spin_buffer_bytes(s.n, sizeof(R));
-            r.S[0] = (R*)get(sb);
-            r.S[1] = (R*)get(sb);
+            // 16 bytes past the last site: the fused step copies 16 bytes per site
+            r.S[0] = (R*)get(sb + 16);
+            r.S[1] = (R*)get(sb + 16);
             r.Sp = (R*)get(sb);
             // the padding is staged with the last tile's window: keep it finite
-            for (void* p : {(void*)r.S[0], (void*)r.S[1], (void*)r.Sp})
-                hip_check(hipMemset(p, 0, sb), "clear spins");
+            for (void* p : {(void*)r.S[0], (void*)r.S[1]})
+                hip_check(hipMemset(p, 0, sb + 16), "clear spins");
+            hip_check(hipMemset(r.Sp, 0, sb), "clear spins");
             r.nb = nullptr;
             r.slice_off = nullptr;
             r.deg = nullptr;
@@ -410,6 +528,27 @@ public:
                 r.dm_field = df;
                 r.dm_part = dpart;
             }
+            r.f_ent = nullptr;
+            r.f_pat = nullptr;
+            r.f_plane = nullptr;
+            r.f_partials = nullptr;
+            r.f_px = r.f_py = r.f_items = 0;
+            if (sizeof(R) == 4 && s.lat.on && s.lat.fusable) {
+                size_t ent = 0;
+                for (const auto& p : s.lat.pats)
+                    ent += p.size();
+                sl.lat = s.lat;
+                sl.f_cap_items = fused_item_cap(s.lat);
+                r.f_ent = get(std::max<size_t>(ent, 1) * sizeof(FusedEntry));
+                r.f_pat = (const int32_t*)get(s.lat.pats.size() * 16);
+                if (!s.lat.plane_pat.empty()) {
+                    uint8_t* pp = (uint8_t*)get(s.lat.plane_pat.size());
+                    hip_check(hipMemcpy(pp, s.lat.plane_pat.data(), s.lat.plane_pat.size(), hipMemcpyHostToDevice),
+                              "upload plane patterns");
+                    r.f_plane = pp;
+                }
+                r.f_partials = (double*)get((size_t)sl.f_cap_items * 2 * 4 * sizeof(double));
+            }
             r.mat = (MaterialDev<R>*)get(m.mat_mu.size() * sizeof(MaterialDev<R>));
             r.partials = (double*)get(blocks * 4 * sizeof(double));
             const size_t groups = (blocks + kGroupTiles - 1) / kGroupTiles;
@@ -418,6 +557,10 @@ public:
             r.acc = (double*)get((size_t)sl.avg_cap * 5 * sizeof(double));
             r.flags = 0;
             fill_parameters(r, s, m, d);
+            if (r.f_partials)
+                sl.fshape = fused_candidates(sl.lat, lds_limit(), [&](const FusedShape& f) { return fused_resident(sl.lat, f); },
+                                             1)
+                                .at(0);
             upload_materials(q, m, d);
             r.parity = 0;
             r.nsteps = 0;
@@ -464,6 +607,112 @@ public:
         hip_check(hipMemcpy((void*)slots_[q].rec.mat, table.data(), table.size() * sizeof(MaterialDev<R>),
                             hipMemcpyHostToDevice),
                   "upload materials");
+        upload_fused(q);
+    }
+
+    // Fused step: pattern entries for the slot's shape (LDS offsets depend
+    // on the region width; J / mu_ref from the replica's table) and its work
+    // items.
+    void upload_fused(int q)
+    {
+        Slot& sl = slots_[q];
+        ReplicaDev<R>& r = sl.rec;
+        if (!r.f_partials)
+            return;
+        const FusedShape f = sl.fshape;
+        const HostLattice& L = sl.lat;
+        // LDS planes hold slots basis-major: (b, row, column) -> b * area + row * SW + column
+        const int SW = f.px + 2, area = (f.px + 2) * (f.py + 2);
+        std::vector<int32_t> hdr;
+        std::vector<FusedEntry> ent;
+        for (size_t p = 0; p < L.pats.size(); ++p) {
+            const int b = L.pat_b[p];
+            int cnt[3] = {0, 0, 0};
+            hdr.push_back((int32_t)ent.size());
+            for (const FusedLink& l : L.pats[p]) {
+                ++cnt[l.dz + 1];
+                const int slot_off = ((int)l.bp - b) * area + l.dy * SW + l.dx;
+                ent.push_back(FusedEntry{slot_off * 16, (float)r.jt[l.type]});
+            }
+            hdr.push_back(cnt[0]);
+            hdr.push_back(cnt[1]);
+            hdr.push_back(cnt[2]);
+        }
+        quiesce();
+        if (!ent.empty())
+            hip_check(hipMemcpy((void*)r.f_ent, ent.data(), ent.size() * sizeof(FusedEntry), hipMemcpyHostToDevice),
+                      "upload fused entries");
+        hip_check(hipMemcpy((void*)r.f_pat, hdr.data(), hdr.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                  "upload fused patterns");
+        r.f_px = f.px;
+        r.f_py = f.py;
+        sl.f_items.clear();
+        const int tx = f.px - 2, ty = f.py - 2;
+        int32_t idx = 0;
+        for (int z0 = 0; z0 < L.nz; z0 += f.planes)
+            for (int y0 = 0; y0 < L.ny; y0 += ty)
+                for (int x0 = 0; x0 < L.nx; x0 += tx)
+                    sl.f_items.push_back(FusedItem{q, x0, y0, z0, std::min(z0 + f.planes, L.nz), idx++});
+        if ((int64_t)sl.f_items.size() > sl.f_cap_items)
+            fail(SLLG_E_STATE, "fused work items exceed their buffer");
+        r.f_items = idx;
+        dirty_ = true;
+    }
+
+    // Shape of replica q's fused step (fused_shape_ok).
+    void set_fused_shape(int q, const FusedShape& f)
+    {
+        Slot& sl = slots_[q];
+        if (!sl.rec.f_partials)
+            fail(SLLG_E_STATE, "the replica has no fused step");
+        if (!fused_shape_ok(f, sl.lat, lds_limit()))
+            fail(SLLG_E_ARG, "fused shape out of range");
+        if (sl.fshape == f)
+            return;
+        sl.fshape = f;
+        upload_fused(q);
+        drop_graph();
+    }
+    FusedShape fused_shape(int q) const { return slots_[q].fshape; }
+    const HostLattice& lattice(int q) const { return slots_[q].lat; }
+    bool fused_active() const { return fused_mode_; }
+    void set_fused(bool on)
+    {
+        if (on != fused_on_) {
+            fused_on_ = on;
+            dirty_ = true;
+        }
+    }
+    // Workgroups of the fused kernel the device holds at once for lattice L
+    // in shape f: the register limit (queried once per kernel) and the LDS
+    // of the compute units.
+    int fused_resident(const HostLattice& L, const FusedShape& f)
+    {
+        const int key = (L.kind * 4 + L.nb) * 2 + (f.bt == 512 ? 1 : 0);
+        auto it = fused_occ_.find(key);
+        if (it == fused_occ_.end())
+            it = fused_occ_.emplace(key, fused_resident_blocks<float>(device_, L.kind, L.nb, f.bt, 16)).first;
+        int cus = 0, lds_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device_) != hipSuccess || cus <= 0)
+            cus = 256;
+        if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device_) != hipSuccess ||
+            lds_cu <= 0)
+            lds_cu = 160 * 1024;
+        const size_t per_wg = fused_lds_bytes(L.kind, fused_plane_bytes(f, L.nb), f.bt) + 1024;
+        const int by_lds = (int)std::max<size_t>(1, (size_t)lds_cu / per_wg);
+        const int by_regs = std::max(1, it->second / cus);
+        return cus * std::min(by_lds, by_regs);
+    }
+    size_t lds_limit()
+    {
+        if (lds_limit_ == 0)
+            lds_limit_ = fused_lds_limit(device_);
+        return lds_limit_;
+    }
+    std::vector<FusedShape> fused_candidate_shapes(int q, int max_count)
+    {
+        const HostLattice& L = slots_[q].lat;
+        return fused_candidates(L, lds_limit(), [&](const FusedShape& f) { return fused_resident(L, f); }, max_count);
     }
 
     // Write the current state (spins are normalised doubles, 3n).
@@ -536,6 +785,62 @@ public:
                                             group_ > 0 ? group_
                                                        : balanced_group(slots_[q].plane_tiles, slots_[q].rec.tile)))
                     work_.push_back(WorkItem{(int32_t)q, b});
+        }
+        // fused step: every replica of the batch can take it, with one block
+        // size and one number of sites per cell
+        bool fused = fused_on_ && sizeof(R) == 4;
+        int f_nb = -1, f_bt = -1, f_kind = -1, f_plane = 0;
+        for (const auto& sl : slots_) {
+            if (!sl.used || !fused)
+                continue;
+            if (!(sl.rec.flags & kFused) || !sl.rec.f_partials)
+                fused = false;
+            else if ((f_nb >= 0 && f_nb != sl.lat.nb) || (f_bt >= 0 && f_bt != sl.fshape.bt) ||
+                     (f_kind >= 0 && f_kind != sl.lat.kind))
+                fused = false;
+            f_nb = sl.lat.nb;
+            f_bt = sl.fshape.bt;
+            f_kind = sl.lat.kind;
+            f_plane = std::max(f_plane, fused_plane_bytes(sl.fshape, sl.lat.nb));
+        }
+        fwork_.clear();
+        if (fused)
+            for (size_t q = 0; q < slots_.size(); ++q)
+                if (slots_[q].used && slots_[q].rec.nsteps > 0)
+                    fwork_.insert(fwork_.end(), slots_[q].f_items.begin(), slots_[q].f_items.end());
+        if (fused != fused_mode_ || f_nb != fused_nb_ || f_bt != fused_bt_ || f_kind != fused_kind_ ||
+            f_plane != fused_plane_)
+            drop_graph();
+        fused_mode_ = fused;
+        fused_nb_ = f_nb;
+        fused_bt_ = f_bt;
+        fused_kind_ = f_kind;
+        fused_plane_ = f_plane;
+        if (fused) {
+            const int nf = (int)fwork_.size();
+            if (nf > fwork_cap_ || !d_fwork_) {
+                drop_graph();
+                (void)hipFree(d_fwork_);
+                d_fwork_ = nullptr;
+                fwork_cap_ = std::max<int64_t>(std::max(nf, 1), 2 * fwork_cap_);
+                hip_check(hipMalloc(&d_fwork_, sizeof(FusedItem) * (size_t)fwork_cap_ + sizeof(int)),
+                          "hipMalloc(fused work)");
+            }
+            int res = 1 << 30;
+            for (const auto& sl : slots_)
+                if (sl.used)
+                    res = std::min(res, fused_resident(sl.lat, sl.fshape));
+            const int64_t cap = std::max<int64_t>(8, ((int64_t)(res * grid_scale_) + 7) & ~int64_t(7));
+            const int fgrid = nf == 0 ? 0 : (int)std::min<int64_t>(((int64_t)nf + 7) & ~int64_t(7), cap);
+            if (fgrid != fgrid_)
+                drop_graph();
+            fgrid_ = fgrid;
+            if (nf > 0)
+                hip_check(hipMemcpy(d_fwork_, fwork_.data(), sizeof(FusedItem) * (size_t)nf, hipMemcpyHostToDevice),
+                          "upload fused work");
+            hip_check(hipMemcpy(reinterpret_cast<char*>(d_fwork_) + sizeof(FusedItem) * (size_t)fwork_cap_, &nf,
+                                sizeof(int), hipMemcpyHostToDevice),
+                      "upload fused work");
         }
         const int nwork = (int)work_.size();
         if (nwork > work_cap_) {
@@ -790,6 +1095,24 @@ private:
     {
         const int nrep = (int)slots_.size();
         hipError_t e = hipSuccess;
+        if (fused_mode_) {
+            // one launch per step, a measuring launch for the chunk's last
+            // record, then the records and the advance
+            const int* nf = (const int*)(reinterpret_cast<const char*>(d_fwork_) + sizeof(FusedItem) * (size_t)fwork_cap_);
+            for (int k = 0; k < K && e == hipSuccess; ++k)
+                e = launch_fused<float>((const ReplicaDev<float>*)d_reps_, d_fwork_, nf, fgrid_, k, remap_, false,
+                                        fused_kind_, fused_nb_, fused_bt_, fused_plane_, st);
+            if (e == hipSuccess)
+                e = launch_fused<float>((const ReplicaDev<float>*)d_reps_, d_fwork_, nf, fgrid_, 0, remap_, true,
+                                        fused_kind_, fused_nb_, fused_bt_, fused_plane_, st);
+            if (e == hipSuccess)
+                e = launch_fused_finish<float>((const ReplicaDev<float>*)d_reps_, nrep, st);
+            if (e == hipSuccess)
+                e = launch_accumulate<R>(d_reps_, nrep, st);
+            if (e == hipSuccess)
+                e = launch_advance<R>(d_reps_, nrep, st);
+            return e;
+        }
         for (int k = 0; k < K && e == hipSuccess; ++k) {
             e = launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, k, remap_, false, variant_, st);
             if (e == hipSuccess)
@@ -843,6 +1166,17 @@ private:
         const int groups = (pt + cap - 1) / cap;
         return (pt + groups - 1) / groups;
     }
+
+    // fused step
+    bool fused_on_ = true;            // option: use it when the whole batch can
+    bool fused_mode_ = false;         // the current work list runs it
+    int fused_nb_ = -1, fused_bt_ = -1, fused_kind_ = -1, fused_plane_ = 0;
+    int fgrid_ = 0;
+    std::map<int, int> fused_occ_;    // register-limited resident workgroups per (kind, nb, bt)
+    size_t lds_limit_ = 0;
+    std::vector<FusedItem> fwork_;
+    FusedItem* d_fwork_ = nullptr;    // items, then their count (int) at fwork_cap_
+    int64_t fwork_cap_ = 0;
 
     bool window_ = true;
     int order_ = 1;

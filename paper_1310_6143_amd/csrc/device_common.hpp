@@ -1,0 +1,310 @@
+// Device helpers shared by the step kernels (kernels.hip) and the fused
+// plane-marching step (fused.hip): the counter-based noise, the LLG
+// right-hand side, vector helpers, work distribution over workgroups and
+// the fixed-order wavefront sums of the FP64 reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "layout.hpp"
+
+// Streaming (non-temporal) stores of S' and S, and the corrector's loads of
+// the old S (read once): measured faster on MI355X for the loads, and for
+// FP64 stores.
+#ifndef SLLG_NT_STORES_F32
+#define SLLG_NT_STORES_F32 0
+#endif
+#ifndef SLLG_NT_STORES_F64
+#define SLLG_NT_STORES_F64 1
+#endif
+#ifndef SLLG_NT_LOADS
+#define SLLG_NT_LOADS 1
+#endif
+
+namespace sllg {
+namespace dev {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64-bit products; the key is bumped by the Weyl constants between
+// rounds.
+// ---------------------------------------------------------------------------
+// a ^ b ^ c in one instruction: the three-input bitwise operation of gfx950
+// with truth table 0x96 (set where an odd number of inputs is set).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                         uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        // the first two rounds still mix counter words that are the same
+        // across the wavefront (step and purpose), which stay on the scalar
+        // unit with plain xors
+        const uint32_t n0 = r < 2 ? (uint32_t)(p1 >> 32) ^ c1 ^ k0 : xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = r < 2 ? (uint32_t)(p0 >> 32) ^ c3 ^ k1 : xor3((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Three standard normals for (site, step): counter (site, step lo, step hi,
+// purpose), key = seed (purpose 0: the thermal field, 2: Monte Carlo trial
+// moves); Box-Muller on the pairs (r0, r1) and (r2, r3), the fourth normal
+// dropped.  Uniforms u = (r + 1) 2^-32 in (0, 1] for the radius,
+// u' = r 2^-32 in [0, 1) for the angle.
+__device__ __forceinline__ void thermal_normals(uint64_t seed, uint64_t step, uint32_t site,
+                                                float g[3], uint32_t purpose = 0u)
+{
+    uint32_t c0 = site, c1 = (uint32_t)step, c2 = (uint32_t)(step >> 32), c3 = purpose;
+    philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float two_m32 = 2.3283064365386963e-10f;   // 2^-32
+    const float u1 = ((float)c0 + 1.0f) * two_m32;
+    const float u3 = ((float)c2 + 1.0f) * two_m32;
+    const float a2 = (float)c1 * two_m32;             // angle in revolutions
+    const float a4 = (float)c3 * two_m32;
+    // -2 ln u = -2 ln(2) log2(u); v_log_f32 is log2, v_sin/v_cos take revolutions
+    const float rho1 = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+    const float rho2 = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u3));
+    g[0] = rho1 * __builtin_amdgcn_cosf(a2);
+    g[1] = rho1 * __builtin_amdgcn_sinf(a2);
+    g[2] = rho2 * __builtin_amdgcn_cosf(a4);
+}
+
+__device__ __forceinline__ void thermal_normals(uint64_t seed, uint64_t step, uint32_t site,
+                                                double g[3], uint32_t purpose = 0u)
+{
+    uint32_t c0 = site, c1 = (uint32_t)step, c2 = (uint32_t)(step >> 32), c3 = purpose;
+    philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double two_m32 = 2.3283064365386963e-10;
+    const double u1 = ((double)c0 + 1.0) * two_m32;
+    const double u3 = ((double)c2 + 1.0) * two_m32;
+    const double rho1 = sqrt(-2.0 * log(u1));
+    const double rho2 = sqrt(-2.0 * log(u3));
+    double s2, c2d, s4, c4d;
+    sincospi(2.0 * ((double)c1 * two_m32), &s2, &c2d);
+    sincospi(2.0 * ((double)c3 * two_m32), &s4, &c4d);
+    (void)s4;
+    g[0] = rho1 * c2d;
+    g[1] = rho1 * s2;
+    g[2] = rho2 * c4d;
+}
+
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+
+template <typename R>
+struct V3 {
+    R x, y, z;
+};
+
+// Every buffer the kernels touch lives in global memory; saying so lets the
+// compiler emit global_load/global_store instead of generic flat accesses
+// for pointers it reads out of the replica table.
+#define SLLG_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ T gload(const T* p, int64_t i)
+{
+    return ((const SLLG_GLOBAL T*)p)[i];
+}
+
+template <typename R>
+__device__ __forceinline__ V3<R> load3(const R* __restrict__ p, int64_t i)
+{
+    const SLLG_GLOBAL R* g = (const SLLG_GLOBAL R*)p + 3 * i;
+    return V3<R>{g[0], g[1], g[2]};
+}
+
+template <typename R>
+__device__ __forceinline__ void store3(R* __restrict__ p, int64_t i, V3<R> v)
+{
+    SLLG_GLOBAL R* g = (SLLG_GLOBAL R*)p + 3 * i;
+    if constexpr (sizeof(R) == 4 ? SLLG_NT_STORES_F32 : SLLG_NT_STORES_F64) {
+        __builtin_nontemporal_store(v.x, &g[0]);
+        __builtin_nontemporal_store(v.y, &g[1]);
+        __builtin_nontemporal_store(v.z, &g[2]);
+    } else {
+        g[0] = v.x;
+        g[1] = v.y;
+        g[2] = v.z;
+    }
+}
+
+// The corrector's own old spin: read once, so streamed past the caches when
+// enabled.
+template <typename R>
+__device__ __forceinline__ V3<R> load3_once(const R* __restrict__ p, int64_t i)
+{
+    const SLLG_GLOBAL R* g = (const SLLG_GLOBAL R*)p + 3 * i;
+#if SLLG_NT_LOADS
+    return V3<R>{__builtin_nontemporal_load(&g[0]), __builtin_nontemporal_load(&g[1]),
+                 __builtin_nontemporal_load(&g[2])};
+#else
+    return V3<R>{g[0], g[1], g[2]};
+#endif
+}
+
+template <typename R>
+__device__ __forceinline__ R dot(V3<R> a, V3<R> b)
+{
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+
+// dS dt = -gamma dt/(1+lambda^2) [S x H + lambda S x (S x H)]
+template <typename R>
+__device__ __forceinline__ V3<R> llg_step(V3<R> s, V3<R> h, R gdt, R alpha)
+{
+    const V3<R> a{s.y * h.z - s.z * h.y, s.z * h.x - s.x * h.z, s.x * h.y - s.y * h.x};
+    const V3<R> b{s.y * a.z - s.z * a.y, s.z * a.x - s.x * a.z, s.x * a.y - s.y * a.x};
+    return V3<R>{-gdt * (a.x + alpha * b.x), -gdt * (a.y + alpha * b.y), -gdt * (a.z + alpha * b.z)};
+}
+
+template <typename R>
+__device__ __forceinline__ V3<R> normalised(V3<R> v)
+{
+    const R inv = rsqrt_r(dot(v, v));
+    return V3<R>{v.x * inv, v.y * inv, v.z * inv};
+}
+
+
+// Work distribution.  A launch has a fixed number of workgroups (about the
+// number that fit on the chip at once), each sweeping many tiles.
+// Workgroups are handed to the 8 XCDs round-robin.  Mode 0: plain
+// grid-stride.  Mode 1: the workgroups of XCD x share one contiguous range
+// of tiles (neighbouring sites meet in that XCD's L2), interleaved tile by
+// tile.  Mode 2: the same XCD ranges, each split into one contiguous run of
+// tiles per workgroup (the previous tiles of a run are still in the
+// workgroup's L1 when the next one needs them).
+struct TileIter {
+    int64_t t, end, stride;
+    __device__ TileIter(int W, int mode)
+    {
+        const int G = (int)gridDim.x, b = (int)blockIdx.x;
+        if (mode != 0 && (G & 7) == 0) {
+            const int x = b & 7, u = b >> 3, Gx = G >> 3;
+            const int64_t lo = (int64_t)W * x / 8, hi = (int64_t)W * (x + 1) / 8;
+            if (mode == 2) {
+                const int64_t run = (hi - lo + Gx - 1) / Gx;
+                t = lo + (int64_t)u * run;
+                end = t + run < hi ? t + run : hi;
+                stride = 1;
+            } else {
+                t = lo + u;
+                end = hi;
+                stride = Gx;
+            }
+        } else {
+            t = b;
+            end = W;
+            stride = G;
+        }
+    }
+    __device__ bool more() const { return t < end; }
+    __device__ void next() { t += stride; }
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const uint64_t u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Sum within each row of 16 lanes (quad swaps, then rotations by 4 and 8).
+template <typename T>
+__device__ __forceinline__ T row_sum(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        v += dpp_f<0xB1>(v);    // quad_perm [1,0,3,2]
+        v += dpp_f<0x4E>(v);    // quad_perm [2,3,0,1]
+        v += dpp_f<0x124>(v);   // row_ror:4
+        v += dpp_f<0x128>(v);   // row_ror:8
+    } else {
+        v += dpp_d<0xB1>(v);
+        v += dpp_d<0x4E>(v);
+        v += dpp_d<0x124>(v);
+        v += dpp_d<0x128>(v);
+    }
+    return v;
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t l = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)h << 32) | l));
+}
+
+__device__ __forceinline__ double lane_value(float v, int lane)
+{
+    return (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Wavefront total: rows of 16 lanes, then the four rows.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v = row_sum(v);
+    return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+}
+
+
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+
+// The replica's only material (no per-site materials), in scalar registers.
+template <typename R>
+__device__ __forceinline__ MaterialDev<R> uniform_material(const ReplicaDev<R>& r)
+{
+    const SLLG_GLOBAL MaterialDev<R>& g = *(const SLLG_GLOBAL MaterialDev<R>*)r.mat;
+    MaterialDev<R> m;
+    m.mu_rel = wave_uniform(g.mu_rel);
+    m.mu_frac = wave_uniform(g.mu_frac);
+    m.ani = wave_uniform(g.ani);
+    m.ku_mu = wave_uniform(g.ku_mu);
+    m.sigma = wave_uniform(g.sigma);
+    m.axis[0] = wave_uniform(g.axis[0]);
+    m.axis[1] = wave_uniform(g.axis[1]);
+    m.axis[2] = wave_uniform(g.axis[2]);
+    m.cub = 0;     // cubic anisotropy takes the general variant
+    m.kc_mu = 0;
+    m.mu_s = wave_uniform(g.mu_s);
+    return m;
+}
+
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+}  // namespace dev
+}  // namespace sllg

@@ -1,0 +1,716 @@
+// Fused Heun step of libsllg for gfx950: one launch per step of the
+// stochastic LLG equation on lattices declared cell by cell (sites
+// i = b + nb (x + nx (y + ny z)), links between cells at most one cell
+// apart on every axis).
+//
+// Paper (Evans et al., arXiv:1310.6143), "Time Integration of the LLG
+// Equation": every spin takes the predictor S' = |S + dS dt| before any
+// corrector S <- |S + (dS + dS') dt / 2| uses it, the field re-evaluated
+// at S' with the same thermal field ("Langevin Dynamics").  The two-launch
+// kernels (kernels.hip) keep that order with a launch boundary.  Here a
+// workgroup instead owns a tile of TX x TY cell columns and recomputes the
+// predictor on the ring of cells around it, so its corrector needs no other
+// workgroup's results, and the step reads S once and writes it once.
+//
+// Plane marching.  The workgroup walks its columns up through a range of
+// planes.  At plane q the spins S(q) of the tile, the ring and one more
+// ring sit in LDS; thread (px, py) owns one column of the tile-plus-ring
+// region and keeps, in registers, running exchange sums of its sites in the
+// planes q - 1, q, q + 1: the links of a site in plane q - 1 that reach
+// plane q complete its field, so the predictor of plane q - 1 runs, writes
+// S'(q - 1) to another LDS plane, and the same running sums over S' give the
+// corrector of plane q - 2.  A site's exchange sum is therefore added in a
+// fixed order, links into the plane below, then its own plane, then the
+// plane above, each in the canonical link order, whatever the tiling.
+// Thermal field, S' and S + dS dt / 2 of a site stay in the registers of
+// the thread that owns its column from the predictor to the corrector.
+//
+// Memory.  S(q + 1) streams into a second LDS plane by direct global-to-LDS
+// loads while plane q is worked on (no registers held for it).  For the
+// lattice kinds compiled in (simple cubic, bcc, bcc with second
+// neighbours) a link's LDS offset is a constant: one LDS read and three
+// FMAs per link.  Planes beyond an open z surface are zero, so surface
+// sites use the bulk link list (the missing links add J * 0).
+//
+// Records.  The predictor of step k sees the state after step k - 1 with
+// its exchange field, so each item leaves FP64 sums of m and E of that
+// state for its own sites; the first item of a replica in the launch of
+// step k + 1 adds the items' sums (a fixed order) into record k - 1; a
+// measuring launch and k_fused_finish complete the last two of a chunk.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace sllg {
+namespace {
+
+using namespace dev;
+
+// LDS slot of one site: x, y, z and a fourth word (the next site's x as it
+// arrives from memory; never used).
+template <typename R>
+struct alignas(4 * sizeof(R)) Slot4 {
+    R x, y, z, w;
+};
+
+template <typename R>
+using FEnt = std::conditional_t<sizeof(R) == 4, FusedEntry, FusedEntryD>;
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// Sum of four values over the first 256 threads (fixed order: per wave, then
+// the four waves in turn); result valid in thread 0.  Every thread of the
+// block calls it.
+template <int BT>
+__device__ __forceinline__ void sum4_256(const double v[4], double out[4], double (*red)[BT / 64])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double s = wave_sum(threadIdx.x < 256 ? v[c] : 0.0);
+        if (lane == 0 && wave < 4)
+            red[c][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            out[c] = ((red[c][0] + red[c][1]) + red[c][2]) + red[c][3];
+    __syncthreads();
+}
+
+// Record `slot` of replica r from its items' sums of parity `par`: thread t
+// < 256 adds items t, t + 256, ... in order, then the fixed 256-lane sum.
+// The same order whichever kernel runs it.
+template <typename R, int BT>
+__device__ void fused_record(const ReplicaDev<R>& r, int par, int64_t slot, double (*red)[BT / 64])
+{
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* p = r.f_partials + 4 * (int64_t)par * r.f_items;
+    if (threadIdx.x < 256)
+        for (int q = (int)threadIdx.x; q < r.f_items; q += 256) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                v[c] += p[4 * (int64_t)q + c];
+        }
+    double tot[4];
+    sum4_256<BT>(v, tot, red);
+    if (threadIdx.x == 0) {
+        double* out = r.records + 4 * (r.rec_pos + slot);
+        const double f = r.mu_ref * r.inv_mu_total;
+        out[0] = tot[0] * f;
+        out[1] = tot[1] * f;
+        out[2] = tot[2] * f;
+        out[3] = -r.mu_ref * tot[3];
+    }
+}
+
+__device__ __forceinline__ int wrap_cell(int u, int n)
+{
+    const int m = u % n;
+    return m < 0 ? m + n : m;
+}
+
+// m and E terms of one site (in units of mu_ref) added to v: mu_s/mu_ref S
+// and mu_s/mu_ref (-E_i/mu_s) with -E_i/mu_s = S.H_ex/2 + (k_u/mu_s)(S.e)^2
+// + S.H_app.  Written out operation by operation so that the step and the
+// measuring launch round alike.
+template <typename R>
+__device__ __forceinline__ void record_terms(const MaterialDev<R>& m, const V3<R>& s, const V3<R>& hex,
+                                             const V3<R>& e, const V3<R>& Happ, double* acc)
+{
+#pragma clang fp contract(off)
+    const R se = s.x * e.x + s.y * e.y + s.z * e.z;
+    const R sh = s.x * hex.x + s.y * hex.y + s.z * hex.z;
+    const R sa = s.x * Happ.x + s.y * Happ.y + s.z * Happ.z;
+    const R u = (R)0.5 * sh + m.ku_mu * se * se + sa;
+    const double t[4] = {(double)(m.mu_frac * s.x), (double)(m.mu_frac * s.y), (double)(m.mu_frac * s.z),
+                         (double)(m.mu_frac * u)};
+    // the thread's own FP64 sums in LDS (acc[c * BT]), added in plane order
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        acc[c * blockDim.x] += t[c];
+}
+
+// x, y, z of the LDS slot at p (the fourth word is never read): a 12-byte
+// read, so a value held for later takes three registers, not four.
+template <typename R>
+struct __attribute__((packed, aligned(sizeof(R)))) Xyz {
+    R x, y, z;
+};
+
+template <typename R>
+__device__ __forceinline__ V3<R> slot_xyz(const char* p)
+{
+    const Xyz<R> v = *reinterpret_cast<const Xyz<R>*>(p);
+    return V3<R>{v.x, v.y, v.z};
+}
+
+// Per-thread geometry of an item.  An LDS plane holds the region's sites
+// basis-major: slot (b, ry, rx) = b * area + ry * sw + rx, 16 bytes each,
+// so the lanes of a wave read consecutive slots.
+template <int NB>
+struct ItemGeo {
+    int rb[NB][3];      // byte offset of slot (bp, row py + 1 + dy, column px) for dy = -1, 0, 1
+    uint32_t col;       // site index of the thread's cell, plane 0, site 0
+    uint32_t plane_sites;
+    bool live, interior;
+    __device__ int own(int b) const { return rb[b][1] + 16; }   // the thread's site b
+};
+
+// h += links of basis site b whose dz is DZ, read from the plane at `base`
+// (the slots of this thread's cell: rb).  Compiled kinds: constant offsets
+// and the two slot couplings kj; generic: pattern p's entries from LDS.
+template <typename R, int KIND, int NB, int DZ>
+__device__ __forceinline__ void add_dz(V3<R>& h, const char* __restrict__ base, const ItemGeo<NB>& g, int b,
+                                       const R kj[2], const int4* pat, const FEnt<R>* ent, int p)
+{
+    if constexpr (KIND != kKindGeneric) {
+        (void)pat;
+        (void)ent;
+        (void)p;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx)
+#pragma unroll
+                for (int bp = 0; bp < NB; ++bp) {
+                    int slot = 0;
+                    if (!kind_link(KIND, b, DZ, dy, dx, bp, &slot))
+                        continue;
+                    const V3<R> v = slot_xyz<R>(base + g.rb[bp][dy + 1] + (dx + 1) * 16);
+                    h.x = fma(kj[slot], v.x, h.x);
+                    h.y = fma(kj[slot], v.y, h.y);
+                    h.z = fma(kj[slot], v.z, h.z);
+                }
+    } else {
+        (void)kj;
+        if (p < 0)
+            return;
+        const int4 hd = pat[p];
+        const int first = hd.x + (DZ >= 0 ? hd.y : 0) + (DZ > 0 ? hd.z : 0);
+        const int cnt = DZ < 0 ? hd.y : DZ == 0 ? hd.z : hd.w;
+        // entry offsets are from the site's own slot
+        const char* own = base + g.own(b);
+#pragma unroll 4
+        for (int q = 0; q < cnt; ++q) {
+            const FEnt<R> en = ent[first + q];
+            const V3<R> v = slot_xyz<R>(own + en.off);
+            h.x = fma((R)en.J, v.x, h.x);
+            h.y = fma((R)en.J, v.y, h.y);
+            h.z = fma((R)en.J, v.z, h.z);
+        }
+    }
+}
+
+// Whether any link of `kind` (any basis site, any dz) reads slot (dy, dx, bp)
+// of a plane.
+__host__ __device__ constexpr bool kind_reads(int kind, int dy, int dx, int bp)
+{
+    for (int b = 0; b < 2; ++b)
+        for (int dz = -1; dz <= 1; ++dz) {
+            int slot = 0;
+            if (b < kind_basis(kind) && kind_link(kind, b, dz, dy, dx, bp, &slot))
+                return true;
+        }
+    return false;
+}
+
+// Compiled kinds: every link the thread's sites take from one plane at
+// `base`, each distinct slot read once.  hu (sites one plane below, their
+// dz = +1 links), h0 (sites of this plane, dz = 0) and hd (sites one plane
+// above, dz = -1) receive the sums, each link in the canonical order.
+template <typename R, int KIND, int NB>
+__device__ __forceinline__ void plane_links(const char* __restrict__ base, const ItemGeo<NB>& g, const R kj[2],
+                                            V3<R> hu[NB], V3<R> h0[NB], V3<R> hd[NB])
+{
+    V3<R> v[3][3][NB];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx)
+#pragma unroll
+            for (int bp = 0; bp < NB; ++bp)
+                if (kind_reads(KIND, dy, dx, bp))
+                    v[dy + 1][dx + 1][bp] = slot_xyz<R>(base + g.rb[bp][dy + 1] + (dx + 1) * 16);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int dz = 1; dz >= -1; --dz) {
+            V3<R>& h = dz > 0 ? hu[b] : dz == 0 ? h0[b] : hd[b];
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx)
+#pragma unroll
+                    for (int bp = 0; bp < NB; ++bp) {
+                        int slot = 0;
+                        if (!kind_link(KIND, b, dz, dy, dx, bp, &slot))
+                            continue;
+                        const V3<R>& u = v[dy + 1][dx + 1][bp];
+                        h.x = fma(kj[slot], u.x, h.x);
+                        h.y = fma(kj[slot], u.y, h.y);
+                        h.z = fma(kj[slot], u.z, h.z);
+                    }
+        }
+}
+
+// Pattern of basis site b in plane z for the generic kind, -1 where the
+// plane does not exist.
+template <typename R>
+__device__ __forceinline__ int plane_pattern(const ReplicaDev<R>& r, int z, int b)
+{
+    if (r.f_zper)
+        z = wrap_cell(z, r.f_nz);
+    else if (z < 0 || z >= r.f_nz)
+        return -1;
+    return r.f_plane ? (int)r.f_plane[z * r.f_nb + b] : b;
+}
+
+// Chunks of 64 LDS slots a wave copies per plane (the region of the largest
+// allowed shape fits in three per wave).
+constexpr int kChunksPerWave = 3;
+
+// Running state of the thread's sites between planes, in two slots chosen
+// by the parity of the plane (relative to the item's first), so that a
+// value stays in the same registers from the plane step that creates it
+// to the one that uses it.
+template <typename R, int NB>
+struct ColumnState {
+    V3<R> hp[2][NB];              // predictor sums of plane p in slot p & 1
+    V3<R> hc[2][NB];              // corrector sums of plane p in slot p & 1
+    V3<R> c_sp[2][NB], c_base[2][NB], c_th[2][NB];   // S', S + dS dt / 2, thermal field of plane p
+};
+
+// Fixed facts of an item for its plane iterations.
+template <typename R>
+struct ItemRun {
+    const R* S;                   // state the step starts from
+    R* Sn;                        // state it writes
+    const uint32_t* dcol;         // [kChunksPerWave][BT] byte offset (plane 0) of the sites each lane copies, or ~0
+    __amdgpu_buffer_rsrc_t rsrc;  // the spins S as a buffer (reads past its end return 0)
+    int n_chunks;
+    int z0, z1;
+    bool partials;
+    uint64_t step;
+};
+
+// One plane step q of an item (P: parity of q relative to the item's
+// first plane step): A links from S(q) in `cur` into planes q - 1
+// (completing it), q and q + 1; B predictor of plane q - 1 (its spins still
+// in `nxt`) into `sp`; barrier; the copy of S(q + 1) into `nxt` is issued
+// (direct global-to-LDS loads of 16 bytes per site, or zeros beyond an open
+// surface); D links from S'(q - 1) into planes q - 2 (completing it), q - 1
+// and q; E corrector of plane q - 2; barrier.  The LDS pointers are distinct planes (restrict), so the
+// reads of `cur` and `sp` need not wait for the copy into `nxt`; the
+// closing barrier does.
+template <typename R, int KIND, int NB, int BT, bool MEASURE, int P>
+__device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo<NB>& g, const ItemRun<R>& run,
+                                           ColumnState<R, NB>& cs, const char* __restrict__ cur,
+                                           char* __restrict__ nxt, char* __restrict__ sp, double* __restrict__ acc,
+                                           const int4* pat, const FEnt<R>* ent, int q, int zw_m2, int zw_m1,
+                                           int zw_p1, const MaterialDev<R>& m)
+{
+    constexpr int S0 = P, S1 = P ^ 1;   // slots of planes q (and q - 2, q + 2) and q - 1 (and q + 1)
+    const int nz = r.f_nz;
+    const bool zper = r.f_zper != 0;
+    const int z0 = run.z0, z1 = run.z1;
+    const R kj[2] = {r.f_kj[0], r.f_kj[1]};
+    const V3<R> e{m.axis[0], m.axis[1], m.axis[2]};
+    const V3<R> Happ{r.H[0], r.H[1], r.H[2]};
+    const int zp = q - 1;
+    const bool zp_exists = zper || (zp >= 0 && zp < nz);
+    const bool zp_need = zp >= z0 - 1 && zp <= z1 && zp_exists;
+    const bool zp_own = zp >= z0 && zp < z1;
+    // A: links from S(q) into planes q - 1 (completing it), q and q + 1
+    V3<R> up[NB];   // plane q + 1's first sums, moved into the slot of q - 1 after B
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        up[b] = V3<R>{0, 0, 0};
+    if (g.live) {
+        if constexpr (KIND != kKindGeneric) {
+            plane_links<R, KIND, NB>(cur, g, kj, cs.hp[S1], cs.hp[S0], up);
+        } else {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                add_dz<R, KIND, NB, 1>(cs.hp[S1][b], cur, g, b, kj, pat, ent, plane_pattern(r, q - 1, b));
+                add_dz<R, KIND, NB, 0>(cs.hp[S0][b], cur, g, b, kj, pat, ent, plane_pattern(r, q, b));
+                add_dz<R, KIND, NB, -1>(up[b], cur, g, b, kj, pat, ent, plane_pattern(r, q + 1, b));
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        // B: predictor of plane q - 1
+        if (g.live && zp_need) {
+            const V3<R> s = slot_xyz<R>(nxt + g.own(b));
+            const V3<R> hex{m.mu_rel * cs.hp[S1][b].x, m.mu_rel * cs.hp[S1][b].y, m.mu_rel * cs.hp[S1][b].z};
+            if (run.partials && g.interior && zp_own)
+                record_terms(m, s, hex, e, Happ, acc);
+            if (!MEASURE) {
+                const R se = dot(s, e);
+                R gn[3] = {0, 0, 0};
+                if (m.sigma != (R)0)
+                    thermal_normals(r.seed, run.step, g.col + (uint32_t)b + g.plane_sites * (uint32_t)zw_m1, gn);
+                const V3<R> th{m.sigma * gn[0], m.sigma * gn[1], m.sigma * gn[2]};
+                const V3<R> h{hex.x + m.ani * se * e.x + Happ.x + th.x, hex.y + m.ani * se * e.y + Happ.y + th.y,
+                              hex.z + m.ani * se * e.z + Happ.z + th.z};
+                const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
+                const V3<R> spn = normalised(V3<R>{s.x + ds.x, s.y + ds.y, s.z + ds.z});
+                cs.c_th[S1][b] = th;
+                cs.c_sp[S1][b] = spn;
+                cs.c_base[S1][b] = V3<R>{s.x + (R)0.5 * ds.x, s.y + (R)0.5 * ds.y, s.z + (R)0.5 * ds.z};
+                *reinterpret_cast<Slot4<R>*>(sp + g.own(b)) = Slot4<R>{spn.x, spn.y, spn.z, (R)0};
+            }
+        }
+        cs.hp[S1][b] = up[b];
+    }
+    __syncthreads();   // S'(q - 1) complete; every thread is done with S(q) and S(q - 1)
+    // S(q + 1) into the other S plane
+    if (q + 1 <= z1 + 1) {
+        const bool exists = zper || (q + 1 >= 0 && q + 1 < nz);
+        const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+#pragma unroll
+        for (int j = 0; j < kChunksPerWave; ++j) {
+            const int c = wave + j * (BT / 64);
+            if (c >= run.n_chunks)
+                break;   // uniform over the wave
+            char* d = nxt + c * 64 * 16;
+            const uint32_t dc = run.dcol[j * BT + (int)threadIdx.x];
+            if (dc != 0xFFFFFFFFu) {
+                if (exists) {
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(run.rsrc, (lds_ptr)d, 16, (int)dc,
+                                                             (int)(g.plane_sites * 3u * (uint32_t)sizeof(R) * (uint32_t)zw_p1),
+                                                             0, 0);
+                } else {
+                    reinterpret_cast<Slot4<R>*>(d)[lane] = Slot4<R>{0, 0, 0, 0};
+                }
+            }
+        }
+    }
+    if (!MEASURE && g.interior) {
+        const int zc = q - 2;
+        const bool zc_own = zc >= z0 && zc < z1 && (zper || (zc >= 0 && zc < nz));
+        // D: links from S'(q - 1) into planes q - 2 (completing it), q - 1 and
+        // q (when S'(q - 1) does not exist, no site has links to it)
+        V3<R> down[NB];   // plane q's first sums, moved into the slot of q - 2 after E
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            down[b] = V3<R>{0, 0, 0};
+        if (zp_need) {
+            if constexpr (KIND != kKindGeneric) {
+                plane_links<R, KIND, NB>(sp, g, kj, cs.hc[S0], cs.hc[S1], down);
+            } else {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    add_dz<R, KIND, NB, 1>(cs.hc[S0][b], sp, g, b, kj, pat, ent, plane_pattern(r, zc, b));
+                    add_dz<R, KIND, NB, 0>(cs.hc[S1][b], sp, g, b, kj, pat, ent, plane_pattern(r, zp, b));
+                    add_dz<R, KIND, NB, -1>(down[b], sp, g, b, kj, pat, ent, plane_pattern(r, q, b));
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            // E: corrector of plane q - 2
+            if (zc_own) {
+                const V3<R> s = cs.c_sp[S0][b];
+                const R se = dot(s, e);
+                const V3<R> h{m.mu_rel * cs.hc[S0][b].x + m.ani * se * e.x + Happ.x + cs.c_th[S0][b].x,
+                              m.mu_rel * cs.hc[S0][b].y + m.ani * se * e.y + Happ.y + cs.c_th[S0][b].y,
+                              m.mu_rel * cs.hc[S0][b].z + m.ani * se * e.z + Happ.z + cs.c_th[S0][b].z};
+                const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
+                const V3<R> sn = normalised(V3<R>{cs.c_base[S0][b].x + (R)0.5 * ds.x,
+                                                  cs.c_base[S0][b].y + (R)0.5 * ds.y,
+                                                  cs.c_base[S0][b].z + (R)0.5 * ds.z});
+                store3(run.Sn, (int64_t)(g.col + (uint32_t)b + g.plane_sites * (uint32_t)zw_m2), sn);
+            }
+            cs.hc[S0][b] = down[b];
+        }
+    }
+    __syncthreads();   // S(q + 1) complete; every thread is done with S'(q - 1)
+}
+
+template <typename R, int KIND, int NB, int BT, bool MEASURE>
+__device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedItem& w, int k, char* lds,
+                                           int plane_bytes, const int4* pat, const FEnt<R>* ent,
+                                           double (*red)[BT / 64], double* acc_base, uint32_t* dcol)
+{
+    const int PX = r.f_px, PY = r.f_py, SW = PX + 2, SH = PY + 2, area = SW * SH;
+    const int nx = r.f_nx, ny = r.f_ny, nz = r.f_nz;
+    const bool zper = r.f_zper != 0;
+    const int t = (int)threadIdx.x;
+    ItemGeo<NB> g;
+    g.live = t < PX * PY;
+    const int py = t / PX, px = t - py * PX;
+    const int ux = w.x0 - 1 + px, uy = w.y0 - 1 + py;   // cell, before wrapping
+    g.interior = g.live && px >= 1 && px <= PX - 2 && py >= 1 && py <= PY - 2 && ux < nx && uy < ny;
+    g.col = (uint32_t)NB * (uint32_t)(wrap_cell(ux, nx) + nx * wrap_cell(uy, ny));
+    g.plane_sites = (uint32_t)NB * (uint32_t)nx * (uint32_t)ny;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+            g.rb[b][dy + 1] = (b * area + (py + 1 + dy) * SW + px) * 16;
+
+    ItemRun<R> run;
+    // the LDS slots (64 per chunk) each lane copies, kept in LDS
+    const int slots = area * NB;
+    run.n_chunks = (slots + 63) / 64;
+#pragma unroll
+    for (int j = 0; j < kChunksPerWave; ++j) {
+        const int s = ((t >> 6) + j * (BT / 64)) * 64 + (t & 63);
+        const int b = s / area, cell = s - b * area;
+        const int ry = cell / SW, rx = cell - ry * SW;
+        const uint32_t site = (uint32_t)NB * (uint32_t)(wrap_cell(w.x0 - 2 + rx, nx) + nx * wrap_cell(w.y0 - 2 + ry, ny)) +
+                              (uint32_t)b;
+        dcol[j * BT + t] = s < slots ? site * 3u * (uint32_t)sizeof(R) : 0xFFFFFFFFu;
+    }
+    run.dcol = dcol;
+    const int par = (r.parity + (MEASURE ? r.nsteps : k)) & 1;
+    run.S = r.S[par];
+    run.Sn = r.S[par ^ 1];
+    // the spin buffer holds 16 bytes past its last site (the copies read 16 bytes per site)
+    run.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(run.S), 0,
+                                                 (int)(3u * (uint32_t)sizeof(R) * (uint32_t)r.n + 16u), 0x00020000);
+    run.z0 = w.z0;
+    run.z1 = w.z1;
+    run.partials = (r.flags & kRecord) && (MEASURE || k >= 1);
+    run.step = r.step + (uint64_t)k;
+    char* planes[2] = {lds, lds + plane_bytes};
+    char* sp = lds + 2 * plane_bytes;
+    double* acc = acc_base + t;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        acc[c * BT] = 0.0;
+
+    const MaterialDev<R> m = uniform_material(r);
+    ColumnState<R, NB> cs;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            cs.hp[i][b] = cs.hc[i][b] = cs.c_sp[i][b] = cs.c_base[i][b] = cs.c_th[i][b] = V3<R>{0, 0, 0};
+
+    const int z0 = w.z0, z1 = w.z1;
+    // wrapped plane numbers of q - 2, q - 1, q and q + 1, advanced by one per plane
+    auto wrapz = [&](int z) { return zper ? wrap_cell(z, nz) : z; };
+    int zw_m2 = wrapz(z0 - 4), zw_m1 = wrapz(z0 - 3), zw_0 = wrapz(z0 - 2), zw_p1 = wrapz(z0 - 1);
+    {
+        // S(z0 - 2) into plane 0
+        const bool exists = zper || (z0 - 2 >= 0 && z0 - 2 < nz);
+        const int wave = t >> 6, lane = t & 63;
+#pragma unroll
+        for (int j = 0; j < kChunksPerWave; ++j) {
+            const int c = wave + j * (BT / 64);
+            if (c >= run.n_chunks)
+                break;
+            Slot4<R>* d = reinterpret_cast<Slot4<R>*>(planes[0] + c * 64 * 16);
+            const uint32_t dc = dcol[j * BT + t];
+            if (dc != 0xFFFFFFFFu) {
+                if (exists) {
+                    const R* src = reinterpret_cast<const R*>(reinterpret_cast<const char*>(run.S) + dc) +
+                                   3 * (size_t)g.plane_sites * (uint32_t)zw_0;
+                    d[lane] = Slot4<R>{src[0], src[1], src[2], (R)0};
+                } else {
+                    d[lane] = Slot4<R>{0, 0, 0, 0};
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = z0 - 2; q <= z1 + 1; q += 2) {
+        plane_step<R, KIND, NB, BT, MEASURE, 0>(r, g, run, cs, planes[0], planes[1], sp, acc, pat, ent, q, zw_m2,
+                                                zw_m1, zw_p1, m);
+        zw_m2 = zw_m1;
+        zw_m1 = zw_0;
+        zw_0 = zw_p1;
+        zw_p1 = zper ? (zw_p1 + 1 == nz ? 0 : zw_p1 + 1) : zw_p1 + 1;
+        if (q + 1 > z1 + 1)
+            break;
+        plane_step<R, KIND, NB, BT, MEASURE, 1>(r, g, run, cs, planes[1], planes[0], sp, acc, pat, ent, q + 1, zw_m2,
+                                                zw_m1, zw_p1, m);
+        zw_m2 = zw_m1;
+        zw_m1 = zw_0;
+        zw_0 = zw_p1;
+        zw_p1 = zper ? (zw_p1 + 1 == nz ? 0 : zw_p1 + 1) : zw_p1 + 1;
+    }
+    if (run.partials) {
+        const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double s = wave_sum(acc[c * BT]);
+            if (lane == 0)
+                red[c][wave] = s;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double* out = r.f_partials + 4 * ((int64_t)((MEASURE ? r.nsteps : k) & 1) * r.f_items + w.idx);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double s = 0.0;
+                for (int q = 0; q < BT / 64; ++q)
+                    s += red[c][q];
+                out[c] = s;
+            }
+        }
+    }
+}
+
+// One Heun step (k of the chunk) of every item, or with MEASURE the m and E
+// sums of the current state of every recording replica.  Dynamic LDS: two
+// S planes and one S' plane of plane_bytes each, then (generic kind) the
+// pattern tables.
+// Registers capped for four waves per SIMD (two 512-lane or four 256-lane
+// workgroups per compute unit).
+#ifndef SLLG_FUSED_WAVES
+#define SLLG_FUSED_WAVES 4
+#endif
+
+template <typename R, int KIND, int NB, int BT, bool MEASURE>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(SLLG_FUSED_WAVES))) void k_fused(const ReplicaDev<R>* __restrict__ reps,
+                                              const FusedItem* __restrict__ items,
+                                              const int* __restrict__ n_items, int k, int remap, int plane_bytes)
+{
+    // dynamic: two S planes, one S' plane, then (generic kind) the pattern
+    // tables; static: the threads' FP64 m and E sums and the copy table,
+    // separate objects so that their accesses need not wait for the plane
+    // copies in flight
+    extern __shared__ __attribute__((aligned(16))) char fused_lds[];
+    __shared__ double red[4][BT / 64];
+    __shared__ double acc[4 * BT];
+    __shared__ uint32_t dcol[kChunksPerWave * BT];
+    int4* pat = reinterpret_cast<int4*>(fused_lds + 3 * plane_bytes);
+    FEnt<R>* ent = reinterpret_cast<FEnt<R>*>(pat + kFusedMaxPatterns);
+    const int W = *n_items;
+    int staged = -1;
+    for (TileIter it(W, remap); it.more(); it.next()) {
+        const FusedItem w = items[it.t];
+        const ReplicaDev<R>& r = reps[w.replica];
+        if (MEASURE ? (!(r.flags & kRecord) || r.nsteps <= 0) : k >= r.nsteps)
+            continue;   // uniform over the block
+        __syncthreads();   // every thread is done with the previous item's LDS
+        if (KIND == kKindGeneric && w.replica != staged) {
+            for (int q = (int)threadIdx.x; q < r.f_npat; q += BT)
+                pat[q] = reinterpret_cast<const int4*>(r.f_pat)[q];
+            for (int q = (int)threadIdx.x; q < r.f_nent; q += BT)
+                ent[q] = reinterpret_cast<const FEnt<R>*>(r.f_ent)[q];
+            staged = w.replica;
+            __syncthreads();
+        }
+        // items' sums of the previous launch -> the record two steps back
+        if (!MEASURE && w.idx == 0 && (r.flags & kRecord) && k >= 2)
+            fused_record<R, BT>(r, (k - 1) & 1, k - 2, red);
+        fused_item<R, KIND, NB, BT, MEASURE>(r, w, k, fused_lds, plane_bytes, pat, ent, red, acc, dcol);
+    }
+}
+
+// After the measuring launch: the last two records of the chunk, one
+// workgroup per replica.
+template <typename R>
+__global__ __launch_bounds__(256) void k_fused_finish(const ReplicaDev<R>* __restrict__ reps)
+{
+    __shared__ double red[4][4];
+    const ReplicaDev<R>& r = reps[blockIdx.x];
+    if (!(r.flags & kFused) || !(r.flags & kRecord) || r.nsteps <= 0)
+        return;
+    if (r.nsteps >= 2)
+        fused_record<R, 256>(r, (r.nsteps - 1) & 1, r.nsteps - 2, red);
+    fused_record<R, 256>(r, r.nsteps & 1, r.nsteps - 1, red);
+}
+
+template <typename R, int KIND, int NB, int BT>
+const void* fused_ptr(bool measure)
+{
+    return measure ? (const void*)k_fused<R, KIND, NB, BT, true> : (const void*)k_fused<R, KIND, NB, BT, false>;
+}
+
+// The kernel of (kind, nb, bt, measure), or null if it is not built.
+template <typename R>
+const void* fused_kernel(int kind, int nb, int bt, bool measure)
+{
+#define SLLG_FUSED_CASE(K_, NB_, BT_)           \
+    if (kind == K_ && nb == NB_ && bt == BT_)   \
+        return fused_ptr<R, K_, NB_, BT_>(measure);
+    SLLG_FUSED_CASE(kKindSc6, 1, 256)
+    SLLG_FUSED_CASE(kKindSc6, 1, 512)
+    SLLG_FUSED_CASE(kKindBcc8, 2, 256)
+    SLLG_FUSED_CASE(kKindBcc8, 2, 512)
+    SLLG_FUSED_CASE(kKindBcc14, 2, 256)
+    SLLG_FUSED_CASE(kKindBcc14, 2, 512)
+    SLLG_FUSED_CASE(kKindGeneric, 1, 256)
+    SLLG_FUSED_CASE(kKindGeneric, 1, 512)
+    SLLG_FUSED_CASE(kKindGeneric, 2, 256)
+    SLLG_FUSED_CASE(kKindGeneric, 2, 512)
+#undef SLLG_FUSED_CASE
+    return nullptr;
+}
+
+}  // namespace
+
+bool fused_block_ok(int bt) { return bt == 256 || bt == 512; }
+
+size_t fused_lds_bytes(int kind, int plane_bytes, int bt)
+{
+    // dynamic part only; the static arrays come on top (fused_static_lds)
+    (void)bt;
+    size_t b = 3 * (size_t)plane_bytes;
+    if (kind == kKindGeneric)
+        b += kFusedMaxPatterns * sizeof(int4) + kFusedMaxEntries * sizeof(FusedEntryD);
+    return b;
+}
+
+template <typename R>
+hipError_t launch_fused(const ReplicaDev<R>* reps, const FusedItem* items, const int* n_items, int grid, int k,
+                        int remap, bool measure, int kind, int nb, int bt, int plane_bytes, hipStream_t st)
+{
+    if (grid <= 0)
+        return hipSuccess;
+    const void* f = fused_kernel<R>(kind, nb, bt, measure);
+    if (!f)
+        return hipErrorInvalidValue;
+    void* args[] = {(void*)&reps, (void*)&items, (void*)&n_items, (void*)&k, (void*)&remap, (void*)&plane_bytes};
+    return hipLaunchKernel(f, dim3(grid), dim3(bt), args, fused_lds_bytes(kind, plane_bytes, bt), st);
+}
+
+template <typename R>
+hipError_t launch_fused_finish(const ReplicaDev<R>* reps, int n_rep, hipStream_t st)
+{
+    if (n_rep <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_fused_finish<R>), dim3(n_rep), dim3(256), 0, st, reps);
+    return hipGetLastError();
+}
+
+template <typename R>
+int fused_resident_blocks(int device, int kind, int nb, int bt, int plane_bytes)
+{
+    int cus = 0, a = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        return 0;
+    const void* f = fused_kernel<R>(kind, nb, bt, false);
+    if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, f, bt, fused_lds_bytes(kind, plane_bytes, bt)) !=
+                  hipSuccess)
+        return 0;
+    return cus * a;
+}
+
+// LDS one workgroup may take (the device limit).
+size_t fused_lds_limit(int device)
+{
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v <= 0)
+        return 64 * 1024;
+    return (size_t)v;
+}
+
+template hipError_t launch_fused<float>(const ReplicaDev<float>*, const FusedItem*, const int*, int, int, int, bool,
+                                        int, int, int, int, hipStream_t);
+template hipError_t launch_fused_finish<float>(const ReplicaDev<float>*, int, hipStream_t);
+template int fused_resident_blocks<float>(int, int, int, int, int);
+
+}  // namespace sllg

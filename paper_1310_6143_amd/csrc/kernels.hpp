@@ -68,6 +68,27 @@ template <typename R>
 hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, uint64_t step, double cone,
                      double inv_kT, unsigned long long* accepted, bool tensor, hipStream_t st);
 
+// Fused plane-marching Heun step (fused.hip) of step k over the work items
+// (one launch per step; measure: m and E sums of the state after the chunk
+// instead, for k_fused_finish).  kind: FusedKind of every replica of the
+// launch, nb its sites per cell, bt threads per workgroup (fused_block_ok);
+// plane_bytes: LDS bytes of one plane, the largest over the replicas.
+template <typename R>
+hipError_t launch_fused(const ReplicaDev<R>* reps, const FusedItem* items, const int* n_items, int grid, int k,
+                        int remap, bool measure, int kind, int nb, int bt, int plane_bytes, hipStream_t st);
+// The chunk's last two records of every fused recording replica.
+template <typename R>
+hipError_t launch_fused_finish(const ReplicaDev<R>* reps, int n_rep, hipStream_t st);
+// Resident workgroups of the fused kernel (kind, nb, bt) per device with
+// plane_bytes LDS planes; 0 if unknown.
+template <typename R>
+int fused_resident_blocks(int device, int kind, int nb, int bt, int plane_bytes);
+bool fused_block_ok(int bt);
+// Dynamic LDS of a fused workgroup with planes of plane_bytes.
+size_t fused_lds_bytes(int kind, int plane_bytes, int bt);
+// LDS one workgroup may take on the device.
+size_t fused_lds_limit(int device);
+
 hipError_t launch_scatter_records(const double* rec, int count, double* m_dev, double* E_dev,
                                   hipStream_t st);
 

@@ -114,6 +114,7 @@ enum ReplicaFlags : int32_t {
     kCubic = 512,           // cubic anisotropy (material fields cub, kc_mu)
     kDemag = 1024,          // macrocell demagnetising field dm_field[dm_cell[i]] added to every site
     kLongRows = 2048,       // SELL rows longer than kLongRow links: batched gathers (general variant)
+    kFused = 4096,          // the lattice runs the fused plane-marching step (f_* fields)
 };
 
 // Rows longer than this take the batched gathers of the general variant.
@@ -124,6 +125,78 @@ constexpr int32_t kGeneralFlags = kPerSiteMaterial | kPerSiteAxis | kTensor | kC
 // Flags that need variant 2 (exchange tensors, cubic anisotropy,
 // demagnetising field, long rows).
 constexpr int32_t kVariant2Flags = kTensor | kCubic | kDemag | kLongRows;
+
+// Fused plane-marching step (one launch per Heun step).  A lattice of nb
+// sites per cell on an nx x ny x nz grid of cells, site i = b + nb (x + nx
+// (y + ny z)), periodic in x and y, periodic or open in z, whose links join
+// cells at most one cell apart on every axis.  A work item is a tile of
+// columns marched through a range of planes; its workgroup holds one plane
+// of S and one of S' in LDS, one thread per column of the tile and a ring
+// of one cell around it (the predictor is recomputed on the ring so that
+// the corrector of the tile needs no other workgroup).
+constexpr int kFusedMaxPatterns = 64;     // distinct (plane class, basis site) link patterns
+constexpr int kFusedMaxEntries = 1024;    // entries of all patterns together
+constexpr int kFusedMaxBasis = 2;         // sites per cell the fused kernels are built for
+constexpr int kFusedMinEdge = 8;          // smallest thread region per axis (cells)
+
+// Lattice kinds the fused kernel is compiled for, so that a site's links
+// are compile-time constants (LDS offsets become instruction immediates):
+// simple cubic with 6 nearest neighbours; bcc with its 8 nearest neighbours
+// (type slot 0); bcc with the 6 second neighbours as well (slot 1).  A link
+// is (dz, dy, dx, bp): the neighbour is basis site bp of the cell offset by
+// (dx, dy, dz).  Kind 0 is any other lattice the fused step takes, its
+// links read from a table at run time.
+enum FusedKind : int32_t { kKindGeneric = 0, kKindSc6 = 1, kKindBcc8 = 2, kKindBcc14 = 3 };
+
+__host__ __device__ constexpr int kind_basis(int kind)
+{
+    return kind == kKindSc6 ? 1 : (kind == kKindBcc8 || kind == kKindBcc14) ? 2 : 0;
+}
+
+// Whether basis site b of `kind` has the link (dz, dy, dx, bp); its type
+// slot goes to *slot.  Enumerating dz, dy, dx, bp in increasing order
+// lists the links in the canonical order the fused step sums them in.
+__host__ __device__ constexpr bool kind_link(int kind, int b, int dz, int dy, int dx, int bp, int* slot)
+{
+    const int manhattan = (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy) + (dz < 0 ? -dz : dz);
+    if (kind == kKindSc6) {
+        *slot = 0;
+        return bp == 0 && manhattan == 1;
+    }
+    if (kind == kKindBcc8 || kind == kKindBcc14) {
+        // site 0 at cell c touches the body centres (site 1) of cells
+        // c + {-1, 0}^3; site 1 touches the corners (site 0) of c + {0, 1}^3
+        const int lo = b == 0 ? -1 : 0;
+        if (bp != b && dx >= lo && dx <= lo + 1 && dy >= lo && dy <= lo + 1 && dz >= lo && dz <= lo + 1) {
+            *slot = 0;
+            return true;
+        }
+        if (kind == kKindBcc14 && bp == b && manhattan == 1) {
+            *slot = 1;
+            return true;
+        }
+    }
+    return false;
+}
+
+// A pattern entry: byte offset of the neighbour's LDS slot from the site's
+// own (for the replica's region width) and J / mu_ref.
+struct FusedEntry {
+    int32_t off;
+    float J;
+};
+struct FusedEntryD {
+    int32_t off;
+    int32_t pad;
+    double J;
+};
+
+struct FusedItem {
+    int32_t replica;
+    int32_t x0, y0;      // first cell of the tile (interior) on x and y
+    int32_t z0, z1;      // planes the item integrates: [z0, z1)
+    int32_t idx;         // item number within its replica (slot of its partials)
+};
 
 template <typename R>
 struct ReplicaDev {
@@ -176,6 +249,21 @@ struct ReplicaDev {
     int32_t n_patterns;             // stencil patterns (kStencil)
     int32_t tile;                   // sites per tile: tile_for(n, sizeof(R))
     int32_t pad1;
+    // fused plane-marching step (kFused)
+    const void* f_ent;              // FusedEntry (FP32) / FusedEntryD (FP64) of every pattern
+    const int32_t* f_pat;           // [patterns][4]: first entry, entries with dz = -1, 0, +1
+    const uint8_t* f_plane;         // [nz][nb] pattern of each (plane, basis site); null: pattern = basis site
+    double* f_partials;             // [2][f_items][4] m and E sums per item, by step parity
+    int32_t f_nb;                   // sites per cell
+    int32_t f_nx, f_ny, f_nz;       // cells per axis
+    int32_t f_zper;                 // 1: periodic in z
+    int32_t f_px, f_py;             // thread region per axis: tile + 2 cells
+    int32_t f_items;                // work items of the replica
+    int32_t f_npat;                 // patterns
+    int32_t f_nent;                 // pattern entries
+    int32_t f_kind;                 // FusedKind of the lattice
+    int32_t f_pad;
+    R f_kj[2];                      // J / mu_ref of the kind's type slots
 };
 
 struct WorkItem {

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <unordered_map>
 #include <tuple>
 #include <utility>
@@ -204,6 +205,194 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
         }
     }
     return s;
+}
+
+// The links of row i from the stored device form: (column, type) pairs.
+template <typename F>
+static void for_each_link(const HostStructure& s, int64_t i, F&& fn)
+{
+    if (s.stencil) {
+        const int p = s.pat_id[(size_t)i];
+        for (int e = s.pat_start[p]; e < s.pat_start[p + 1]; ++e) {
+            const int32_t raw = s.pat_tab[(size_t)e];
+            const int32_t off = raw >> 4;
+            if (off != 0)   // offset 0: padding of the far part, never a link
+                fn(i + off, raw & 15);
+        }
+        return;
+    }
+    const int64_t base = s.slice_off[(size_t)(i / kSlice)] + (i % kSlice);
+    const int d = (int)(s.deg[(size_t)i] & 0xFFFFu);
+    for (int k = 0; k < d; ++k) {
+        const uint32_t e = s.nb[(size_t)(base + (int64_t)k * kSlice)];
+        fn((int64_t)(e & kColMask), (int)(e >> kColBits));
+    }
+}
+
+void set_lattice(HostStructure& s, int nb, const int cells[3], const int periodic[3])
+{
+    if (!cells || !periodic)
+        fail(SLLG_E_ARG, "cells and periodic must not be NULL");
+    if (nb < 1 || nb > 255 || cells[0] < 1 || cells[1] < 1 || cells[2] < 1)
+        fail(SLLG_E_ARG, "need 1 <= n_basis <= 255 and at least one cell per axis");
+    const int64_t n_cells = (int64_t)cells[0] * cells[1] * cells[2];
+    if (n_cells * nb != s.n)
+        fail(SLLG_E_ARG, "n_basis x cells = " + std::to_string(n_cells * nb) + " sites, the system has " +
+                             std::to_string(s.n));
+    HostLattice L;
+    L.on = true;
+    L.nb = nb;
+    L.nx = cells[0];
+    L.ny = cells[1];
+    L.nz = cells[2];
+    for (int a = 0; a < 3; ++a)
+        L.per[a] = periodic[a] != 0;
+    const int dim[3] = {L.nx, L.ny, L.nz};
+    // offset of coordinate v from u on axis a: -1, 0 or +1, else 2
+    auto delta = [&](int a, int64_t u, int64_t v) -> int {
+        int64_t d = v - u;
+        if (L.per[a]) {
+            d = ((d % dim[a]) + dim[a]) % dim[a];
+            if (d == 0) return 0;
+            if (d == 1) return 1;
+            if (d == dim[a] - 1) return -1;
+            return 2;
+        }
+        return d >= -1 && d <= 1 ? (int)d : 2;
+    };
+    // one (plane, basis site) pattern from the plane's first site of that
+    // basis; every other site of the plane must match it.  Planes are
+    // split over host threads.
+    std::vector<std::vector<FusedLink>> ref((size_t)L.nz * nb);
+    const uint32_t unb = (uint32_t)nb, unx = (uint32_t)L.nx, uny = (uint32_t)L.ny;
+    const int64_t plane_sites = (int64_t)nb * L.nx * L.ny;
+    int n_threads = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
+    n_threads = (int)std::min<int64_t>(n_threads, L.nz);
+    std::vector<int64_t> bad_site((size_t)n_threads, -1);
+    std::vector<char> uniform((size_t)n_threads, 1);
+    auto work = [&](int w) {
+        std::vector<FusedLink> row;
+        for (int64_t z = (int64_t)L.nz * w / n_threads; z < (int64_t)L.nz * (w + 1) / n_threads; ++z) {
+            for (int64_t i = z * plane_sites; i < (z + 1) * plane_sites; ++i) {
+                const uint32_t c = (uint32_t)i / unb, b = (uint32_t)i % unb;
+                const uint32_t x = c % unx, y = (c / unx) % uny;
+                row.clear();
+                bool bad = false;
+                for_each_link(s, i, [&](int64_t j, int type) {
+                    const uint32_t cj = (uint32_t)j / unb, t = cj / unx;
+                    const int dx = delta(0, x, cj % unx), dy = delta(1, y, t % uny), dz = delta(2, z, t / uny);
+                    bad = bad || dx == 2 || dy == 2 || dz == 2;
+                    row.push_back(FusedLink{(int8_t)dz, (int8_t)dy, (int8_t)dx, (uint8_t)((uint32_t)j % unb),
+                                            (uint8_t)type});
+                });
+                if (bad) {
+                    bad_site[(size_t)w] = i;
+                    return;
+                }
+                std::sort(row.begin(), row.end());
+                std::vector<FusedLink>& r = ref[(size_t)z * nb + b];
+                if (i - z * plane_sites < nb)
+                    r = row;
+                else if (uniform[(size_t)w] && row != r)
+                    uniform[(size_t)w] = 0;
+            }
+        }
+    };
+    {
+        std::vector<std::thread> pool;
+        for (int w = 1; w < n_threads; ++w)
+            pool.emplace_back(work, w);
+        work(0);
+        for (auto& th : pool)
+            th.join();
+    }
+    for (int64_t i : bad_site)
+        if (i >= 0)
+            fail(SLLG_E_ARG, "site " + std::to_string(i) + " has a link to a cell more than one cell away "
+                             "in the declared lattice");
+    bool uniform_in_plane = true;
+    for (char u : uniform)
+        uniform_in_plane = uniform_in_plane && u;
+    // patterns: distinct (basis site, link list)
+    std::vector<uint8_t> plane(ref.size());
+    bool by_basis = true;
+    for (size_t key = 0; key < ref.size(); ++key) {
+        const int b = (int)(key % nb);
+        int id = -1;
+        for (size_t p = 0; p < L.pats.size(); ++p)
+            if (L.pat_b[p] == b && L.pats[p] == ref[key]) {
+                id = (int)p;
+                break;
+            }
+        if (id < 0) {
+            if ((int)L.pats.size() >= kFusedMaxPatterns) {
+                id = kFusedMaxPatterns;   // too many: not fusable (below)
+            } else {
+                id = (int)L.pats.size();
+                L.pats.push_back(ref[key]);
+                L.pat_b.push_back((uint8_t)b);
+            }
+        }
+        plane[key] = (uint8_t)std::min(id, 255);
+        by_basis = by_basis && id == b;
+    }
+    size_t entries = 0;
+    for (const auto& p : L.pats)
+        entries += p.size();
+    if (!L.per[0] || !L.per[1])
+        L.why = "the fused step needs periodic x and y";
+    else if (nb > kFusedMaxBasis)
+        L.why = "the fused step is built for at most " + std::to_string(kFusedMaxBasis) + " sites per cell";
+    else if (!uniform_in_plane)
+        L.why = "the links of a basis site change within a plane";
+    else if ((int)L.pats.size() >= kFusedMaxPatterns || entries > (size_t)kFusedMaxEntries)
+        L.why = "too many link patterns for the fused step";
+    else if (L.nx > 0xFFFF || L.ny > 0xFFFF)
+        L.why = "too many cells per axis for the fused step";
+    L.fusable = L.why.empty();
+    // a compiled kind: every (plane, basis site) has the kind's links, less
+    // those into planes beyond an open z surface, with one type per slot
+    for (int kind : {(int)kKindSc6, (int)kKindBcc8, (int)kKindBcc14}) {
+        if (!L.fusable || kind_basis(kind) != nb)
+            continue;
+        int slot_type[2] = {-1, -1};
+        bool match = true;
+        for (int z = 0; z < L.nz && match; ++z)
+            for (int b = 0; b < nb && match; ++b) {
+                const std::vector<FusedLink>& have = ref[(size_t)z * nb + b];
+                size_t k = 0;
+                for (int dz = -1; dz <= 1 && match; ++dz) {
+                    if (!L.per[2] && ((dz < 0 && z == 0) || (dz > 0 && z == L.nz - 1)))
+                        continue;
+                    for (int dy = -1; dy <= 1 && match; ++dy)
+                        for (int dx = -1; dx <= 1 && match; ++dx)
+                            for (int bp = 0; bp < nb && match; ++bp) {
+                                int slot = 0;
+                                if (!kind_link(kind, b, dz, dy, dx, bp, &slot))
+                                    continue;
+                                if (k >= have.size() || have[k].dz != dz || have[k].dy != dy || have[k].dx != dx ||
+                                    have[k].bp != bp) {
+                                    match = false;
+                                    break;
+                                }
+                                if (slot_type[slot] < 0)
+                                    slot_type[slot] = have[k].type;
+                                match = slot_type[slot] == have[k].type;
+                                ++k;
+                            }
+                }
+                match = match && k == have.size();
+            }
+        if (match) {
+            L.kind = kind;
+            L.slot_type[0] = std::max(slot_type[0], 0);
+            L.slot_type[1] = std::max(slot_type[1], 0);
+            break;
+        }
+    }
+    if (!by_basis)
+        L.plane_pat = std::move(plane);
+    s.lat = std::move(L);
 }
 
 void set_exchange_tensors(HostStructure& s, const double* Jt, int n_types)
@@ -520,7 +709,26 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
         flags |= kDemag;
     if (!s.stencil && s.long_rows)
         flags |= kLongRows;
+    // the fused step: a fusable lattice with uniform materials, scalar
+    // exchange and no cubic anisotropy or demagnetising field (FP32)
+    if (sizeof(R) == 4 && s.lat.on && s.lat.fusable && !m.per_site_material && !m.per_site_axis && !s.tensor &&
+        !m.cubic && !s.demag.on)
+        flags |= kFused;
     rec.flags = flags;
+    rec.f_nb = s.lat.nb;
+    rec.f_nx = s.lat.nx;
+    rec.f_ny = s.lat.ny;
+    rec.f_nz = s.lat.nz;
+    rec.f_zper = s.lat.per[2] ? 1 : 0;
+    rec.f_npat = (int32_t)s.lat.pats.size();
+    rec.f_kind = s.lat.kind;
+    rec.f_pad = 0;
+    for (int q = 0; q < 2; ++q)
+        rec.f_kj[q] = s.lat.on ? rec.jt[s.lat.slot_type[q]] : (R)0;
+    int32_t nent = 0;
+    for (const auto& p : s.lat.pats)
+        nent += (int32_t)p.size();
+    rec.f_nent = nent;
     rec.n_patterns = s.stencil ? (int32_t)s.pat_start.size() - 1 : 0;
     rec.dm_cells = s.demag.on ? (int32_t)s.demag.cells : 0;
     rec.dm_chunks = s.demag.on ? demag_chunks(s.demag.cells) : 0;

@@ -52,6 +52,42 @@ inline int demag_chunks(int64_t cells)
 // Validates and builds the decomposition (pos: 3n metres).
 HostDemag build_demag(int64_t n, const double* pos, double cell_size, double atom_volume, int64_t every);
 
+// A lattice declared cell by cell (sllg_set_lattice): site
+// i = b + nb (x + nx (y + ny z)); every link joins cells at most one cell
+// apart on each axis (across the boundary of a periodic axis).  The fused
+// step keeps one link pattern per (plane, basis site).
+struct FusedLink {
+    int8_t dz, dy, dx;      // cell offset of the neighbour
+    uint8_t bp;             // its basis site
+    uint8_t type;           // interaction type
+    bool operator<(const FusedLink& o) const
+    {
+        if (dz != o.dz) return dz < o.dz;
+        if (dy != o.dy) return dy < o.dy;
+        if (dx != o.dx) return dx < o.dx;
+        if (bp != o.bp) return bp < o.bp;
+        return type < o.type;
+    }
+    bool operator==(const FusedLink& o) const
+    {
+        return dz == o.dz && dy == o.dy && dx == o.dx && bp == o.bp && type == o.type;
+    }
+};
+
+struct HostLattice {
+    bool on = false;
+    int nb = 0, nx = 0, ny = 0, nz = 0;
+    bool per[3] = {false, false, false};
+    bool fusable = false;                       // the fused step can run on this structure
+    std::string why;                            // why not, when it cannot
+    std::vector<std::vector<FusedLink>> pats;   // link patterns, each sorted (dz first)
+    std::vector<uint8_t> pat_b;                 // basis site of each pattern
+    std::vector<uint8_t> plane_pat;             // [nz * nb] pattern of each (plane, basis site);
+                                                // empty when the pattern is the basis site itself
+    int kind = 0;                               // FusedKind whose links every site has (kKindGeneric: none)
+    int slot_type[2] = {0, 0};                  // interaction type of each of the kind's slots
+};
+
 // Neighbour structure in stencil or SELL-64 form.  Every row lists its
 // near links (|col - row| <= halo_cap) first and the far ones after, each
 // part in the caller's order; the step kernels sum the two parts separately
@@ -87,7 +123,18 @@ struct HostStructure {
     // Monte Carlo colour classes (build_colours): sites sorted by colour
     std::vector<int32_t> colour_sites;
     std::vector<int64_t> colour_start;   // [n_colours + 1]
+    // lattice declaration and fused-step patterns (set_lattice)
+    HostLattice lat;
 };
+
+// Declares the structure's sites as a lattice of nb sites per cell on
+// cells[0] x cells[1] x cells[2] cells (periodic[a] != 0: periodic axis) and
+// derives the fused step's link patterns.  Throws Failure(SLLG_E_ARG) when
+// the counts do not match or a link joins cells more than one cell apart;
+// otherwise sets s.lat (fusable false, with the reason, when the fused step
+// cannot take the structure: open x or y, patterns that change within a
+// plane, more than 2 sites per cell, too many patterns).
+void set_lattice(HostStructure& s, int nb, const int cells[3], const int periodic[3]);
 
 // Sites per tile of this structure at a precision (see tile_request).
 int tile_of(const HostStructure& s, size_t real_bytes);

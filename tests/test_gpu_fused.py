@@ -1,0 +1,144 @@
+"""GPU parity of the fused plane-marching Heun step (one launch per step,
+the predictor recomputed on a ring of cells around each workgroup's tile)
+against the FP64 oracle, through the C ABI.
+
+The fused step adds a site's exchange links in its own fixed order (links
+into the plane below, its own plane, the plane above), so it agrees with
+the oracle and with the two-launch step to FP32 rounding; the tolerances
+are those of the FP32 two-launch path.  Spins do not depend on the tile
+shape (each site's arithmetic is the same whichever workgroup computes it),
+so different shapes must give bit-identical spins; the m and E records are
+sums over items and may differ at FP64 rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1310_6143_amd as sl
+from spin_systems import bcc_block, bcc_film, sc_reference
+from tests.gpu_util import max_angle, mean_angle
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_run(w, n_steps, step0=0):
+    ref = oracle.System(w)
+    S = np.ascontiguousarray(w.S0.copy())
+    m, E = ref.integrate(S, step0, n_steps)
+    return S, m, E
+
+
+def _fused_system(w, shape=None, fused=1):
+    g = sl.from_workload(w, precision=sl.FP32)
+    g.set_option("fused", fused)
+    if shape is not None:
+        tx, ty, planes, threads = shape
+        g.set_option("fused_tile_x", tx)
+        g.set_option("fused_tile_y", ty)
+        g.set_option("fused_planes", planes)
+        g.set_option("fused_threads", threads)
+    return g
+
+
+def _run(w, n_steps, shape=None, fused=1, chunks=None):
+    with _fused_system(w, shape, fused) as g:
+        assert g.get_option("fused_active") == fused
+        if chunks is None:
+            m, E = g.integrate(n_steps)
+        else:
+            parts = [g.integrate(c) for c in chunks]
+            m = np.concatenate([p[0] for p in parts])
+            E = np.concatenate([p[1] for p in parts])
+        return g.get_spins(), m, E
+
+
+def test_lattice_declared_for_crystals():
+    for w in (sc_reference(L=8), bcc_block(cells=6, n_steps=10), bcc_film(nx=8, ny=8, nz=4)):
+        with sl.from_workload(w, precision=sl.FP32) as g:
+            assert g.get_option("lattice") == 2
+            assert g.get_option("fused_active") == 1
+        with sl.from_workload(w, precision=sl.FP64) as g:
+            assert g.get_option("fused_active") == 0
+
+
+def test_sc4096_fused_fp32_matches_oracle():
+    w = sc_reference(L=16, temperature=300.0, n_steps=1000, seed=42)
+    S_ref, m_ref, E_ref = _oracle_run(w, 1000)
+    S, m, E = _run(w, 1000)
+    amax, amean = max_angle(S, S_ref), mean_angle(S, S_ref)
+    dm = np.abs(m - m_ref).max()
+    dE = (np.abs(E - E_ref) / np.abs(E_ref)).max()
+    print(f"fused FP32 sc 16^3 T=300 K, 1000 steps: max angle {amax:.3e}, mean {amean:.3e}, "
+          f"|dm| {dm:.3e}, |dE/E| {dE:.3e}")
+    assert amax <= 2e-3 and amean <= 2e-4
+    assert dm <= 1e-4 and dE <= 1e-4
+    assert np.abs(np.linalg.norm(S, axis=1) - 1).max() <= 1e-6
+
+
+def test_bcc_j1j2_fused_fp32_matches_oracle():
+    w = bcc_block(cells=24, n_steps=300)
+    w.H = np.array([0.3, -0.2, 0.5])
+    S_ref, m_ref, E_ref = _oracle_run(w, 300)
+    S, m, E = _run(w, 300)
+    amax, amean = max_angle(S, S_ref), mean_angle(S, S_ref)
+    dm = np.abs(m - m_ref).max()
+    dE = (np.abs(E - E_ref) / np.abs(E_ref)).max()
+    print(f"fused FP32 bcc 24^3 J1+J2, 300 steps: max angle {amax:.3e}, mean {amean:.3e}, "
+          f"|dm| {dm:.3e}, |dE/E| {dE:.3e}")
+    assert amax <= 2e-3 and amean <= 2e-4
+    assert dm <= 1e-4 and dE <= 1e-4
+
+
+def test_film_open_z_fused_fp32_matches_oracle():
+    # open z: the surface planes have their own link patterns
+    w = bcc_film(nx=20, ny=12, nz=7, seed=5)
+    w.temperature = 500.0
+    w.H = np.array([0.0, 0.4, -0.3])
+    S_ref, m_ref, E_ref = _oracle_run(w, 300)
+    S, m, E = _run(w, 300)
+    amax, amean = max_angle(S, S_ref), mean_angle(S, S_ref)
+    dm = np.abs(m - m_ref).max()
+    print(f"fused FP32 film 20x12x7 open z, 300 steps: max angle {amax:.3e}, mean {amean:.3e}, |dm| {dm:.3e}")
+    assert amax <= 2e-3 and amean <= 2e-4
+    assert dm <= 1e-4
+
+
+@pytest.mark.parametrize("make", [lambda: bcc_block(cells=20, n_steps=50),
+                                  lambda: bcc_film(nx=26, ny=14, nz=9, seed=7),
+                                  lambda: sc_reference(L=30, temperature=300.0, seed=9)])
+def test_spins_independent_of_shape(make):
+    """Tiles that divide the lattice or not, planes per item that divide
+    the thickness or not, tiles wider than the lattice (the region wraps
+    more than once), every block size: spins bit for bit the same."""
+    w = make()
+    w.temperature = 400.0
+    shapes = [(6, 6, 4, 256), (14, 14, 10, 256), (30, 14, 7, 512), (20, 20, 16, 512), (62, 6, 5, 512),
+              (40, 10, 64, 512)]
+    ref = None
+    for shp in shapes:
+        S, m, E = _run(w, 20, shape=shp)
+        if ref is None:
+            ref = (S, m, E)
+            continue
+        assert np.array_equal(S, ref[0]), shp
+        assert np.allclose(m, ref[1], rtol=0, atol=1e-12), shp
+        assert np.allclose(E, ref[2], rtol=1e-12, atol=0), shp
+
+
+def test_chunked_equals_one_call_bitwise():
+    w = bcc_block(cells=12, n_steps=50)
+    S1, m1, E1 = _run(w, 37)
+    S2, m2, E2 = _run(w, 37, chunks=[1, 2, 11, 23])
+    assert np.array_equal(S1, S2)
+    assert np.array_equal(m1, m2) and np.array_equal(E1, E2)
+
+
+def test_fused_agrees_with_two_launch_step():
+    w = bcc_block(cells=16, n_steps=30)
+    Sf, mf, Ef = _run(w, 30, fused=1)
+    St, mt, Et = _run(w, 30, fused=0)
+    ang = max_angle(Sf, St)
+    print(f"fused vs two-launch FP32, 30 steps: max angle {ang:.3e}")
+    assert ang <= 1e-4
+    assert np.abs(mf - mt).max() <= 1e-6
+    assert (np.abs(Ef - Et) / np.abs(Et)).max() <= 1e-6

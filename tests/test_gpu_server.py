@@ -45,13 +45,14 @@ def test_result_alone_equals_result_in_mix_bitwise():
 
 def test_server_matches_single_system_path_bitwise():
     """With the same tiling (the server always uses the largest tile) the
-    server and the single-system path give the same result bit for bit."""
+    server and the single-system path give the same result bit for bit.
+    Requests carry no lattice declaration, so both take the two-launch step."""
     w = sc_request_system(10, 400.0, [0.1, 0.2, 0.3], 200, 77)
     with sl.Server(hbm_budget=1 << 30, chunk_steps=64) as srv:
         t = srv.submit(w, record=True)
         srv.wait(t, 120)
         S, m, E = srv.fetch(t)
-    with sl.from_workload(w, precision=sl.FP32) as g:
+    with sl.from_workload(w, precision=sl.FP32, lattice=False) as g:
         g.set_option("tile_sites", 2048)
         m2, E2 = g.integrate(200)
         S2 = g.get_spins()
