@@ -84,7 +84,8 @@ def run_gpu(w, precision, steps, warmup, torch, launch=None, autotune=False, fus
         if len(launch) > 2:
             sysm.set_option("tile_order", launch[2])
         choice = {k: sysm.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps", "tile_order")}
-    elif autotune:
+    elif autotune and not fused_shape:
+        # also brings the GPU out of its idle clocks before the timed steps
         tuned_us, choice = sysm.autotune(25, stream=st)
         log(f"  autotune: {tuned_us:.1f} us/step with {choice}")
     else:   # the library's default launch shape (the one the counter summary was taken at)
@@ -502,8 +503,8 @@ def main():
                     help="demag workload: time the field update only (skip the ellipsoid)")
     ap.add_argument("--launch", default="", help="fixed launch shape 'xcd_remap,grid_scale_pct[,tile_order]' "
                     "instead of the library default")
-    ap.add_argument("--autotune", action="store_true", help="time the candidate launch shapes first "
-                    "and run the fastest (sllg_autotune)")
+    ap.add_argument("--no-autotune", action="store_true", help="run the library's default launch shape "
+                    "instead of timing the candidate shapes first (sllg_autotune) and running the fastest")
     ap.add_argument("--no-fused", action="store_true", help="run the two-launch step even where the "
                     "lattice allows the fused one")
     ap.add_argument("--fused-shape", default="", help="fused work-item shape 'tile_x,tile_y,planes,threads' "
@@ -563,11 +564,11 @@ def main():
     fshape = tuple(int(v) for v in args.fused_shape.split(",")) if args.fused_shape else None
     fused = 0 if args.no_fused else 1
     if args.only_fp64:
-        r64 = run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch, args.autotune, fused, fshape)
+        r64 = run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch, not args.no_autotune, fused, fshape)
         print(json.dumps({"fp64_ms_per_step": r64["ms"] / args.steps}))
         return
-    r32 = run_gpu(w, sl.FP32, args.steps, args.warmup, torch, launch, args.autotune, fused, fshape)
-    r64 = None if args.no_fp64 else run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch, args.autotune,
+    r32 = run_gpu(w, sl.FP32, args.steps, args.warmup, torch, launch, not args.no_autotune, fused, fshape)
+    r64 = None if args.no_fp64 else run_gpu(w, sl.FP64, args.steps, args.warmup, torch, launch, not args.no_autotune,
                                             fused, fshape)
 
     n = w.n

@@ -175,9 +175,12 @@ sllg_status sllg_set_cubic_anisotropy(sllg_system *sys, const double *k_c, int p
 sllg_status sllg_set_demag(sllg_system *sys, const double *pos, double cell_size, double atom_volume,
                            int64_t every);
 
-/* Recompute the demagnetising field from the current spins now (it is then
- * held as after a scheduled update) and write it per atom into
- * field_out[3n] (tesla).  SLLG_E_STATE without sllg_set_demag. */
+/* Write the demagnetising field in effect per atom into field_out[3n]
+ * (tesla): the field held since the last scheduled update (every `every`
+ * steps, Section "Demagnetising field"), so that reading it never changes
+ * the trajectory; when no field is held yet (after sllg_set_demag or
+ * sllg_set_spins) the field of the current spins, computed now and held as
+ * a scheduled update would hold it.  SLLG_E_STATE without sllg_set_demag. */
 sllg_status sllg_demag_field(sllg_system *sys, double *field_out, void *stream);
 
 /* Damping lambda >= 0, gyromagnetic ratio gamma > 0 (1/(T s); Table 1 gives
@@ -298,18 +301,25 @@ sllg_status sllg_hysteresis(sllg_system *sys, const double *H, int64_t n_points,
                             int64_t max_steps, int64_t check_every, double *m_out, int64_t *steps_out,
                             void *stream);
 
-/* Launch-shape autotuner: times every candidate launch configuration of the
- * step kernels ("lds_window" 1 or 0; "tile_order" 1 or 0; XCD mappings 0,
- * 1, 2 of "xcd_remap";
- * 1/2, 1 or 2 resident grids of workgroups per launch; for systems under
- * 2^20 spins, 16, 64 or 256 steps per captured HIP graph), the best of two
- * runs of trial_steps (2..100000) steps of this system each, keeps the
- * fastest and writes its time per step (us) to *us_per_step (may be NULL).
- * The spins, the step counter and every result stay exactly as they were:
- * launch shapes do not change the arithmetic.  The choice can be read back
- * with sllg_get_option ("lds_window", "tile_order", "xcd_remap", "grid_scale_pct",
- * "graph_steps", "tuned_ns_per_step").  Setting SLLG_AUTOTUNE_LOG=1 in the
- * environment prints every candidate's time to stderr. */
+/* Launch-shape autotuner: times every candidate launch configuration, the
+ * best of two runs of trial_steps (2..100000) steps of this system each,
+ * keeps the fastest and writes its time per step (us) to *us_per_step (may
+ * be NULL).  With the fused step active ("fused_active" 1) the candidates
+ * are the eight fused shapes (tile, planes per item, threads per
+ * workgroup) the occupancy and traffic model ranks best; otherwise the
+ * two-launch step's shapes ("lds_window" 1 or 0; "tile_order" 1 or 0; XCD
+ * mappings 0, 1, 2 of "xcd_remap"; 1/2, 1 or 2 resident grids of
+ * workgroups per launch).  Systems under 2^20 spins also try 16, 64 or 256
+ * steps per captured HIP graph.  The spins, the step counter, the held
+ * demagnetising field and every result stay exactly as they were.  Launch
+ * shapes do not change the arithmetic of a spin; with the fused step the
+ * m and E records (FP64 sums of per-workgroup partial sums) may change at
+ * FP64 rounding when the tile shape changes.  The choice can be read back
+ * with sllg_get_option ("fused_tile_x", "fused_tile_y", "fused_planes",
+ * "fused_threads"; "lds_window", "tile_order", "xcd_remap",
+ * "grid_scale_pct"; "graph_steps", "tuned_ns_per_step").  Setting
+ * SLLG_AUTOTUNE_LOG=1 in the environment prints every candidate's time to
+ * stderr. */
 sllg_status sllg_autotune(sllg_system *sys, int trial_steps, double *us_per_step, void *stream);
 
 /* Thermal normals Gamma[3n] of sites 0..n-1 at step `step`, drawn exactly as
@@ -320,9 +330,13 @@ sllg_status sllg_thermal_normals(int device, sllg_precision precision, uint64_t 
                                  int64_t n, double *out);
 
 /* ---------------------------------------------------------------------------
- * Checkpoint / resume.  The state is the spins, the noise seed and the step
- * counter; because the noise is counter-based, a restored run continues
- * exactly as the uninterrupted one would.
+ * Checkpoint / resume.  The state is the spins, the noise seed, the step
+ * counter and, with a demagnetising field on, the field held since its last
+ * scheduled update; because the noise is counter-based, a restored run
+ * continues exactly as the uninterrupted one would.  Restoring needs a
+ * system set up the same way (sites, precision, demagnetising field on or
+ * off); a blob written without a held field leaves the field to be
+ * computed at the next step.
  * ------------------------------------------------------------------------- */
 sllg_status sllg_checkpoint_size(const sllg_system *sys, size_t *bytes);
 sllg_status sllg_checkpoint(sllg_system *sys, void *buf, size_t bytes);

@@ -307,8 +307,12 @@ class SpinSystem:
         returns (us per step, chosen options)."""
         us = D()
         self._check(lib().sllg_autotune(self._h, int(trial_steps), ctypes.byref(us), _stream(stream)))
-        return us.value, {k: self.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps",
-                                                          "tile_order", "lds_window")}
+        keys = ["graph_steps"]
+        if self.get_option("fused_active"):
+            keys += ["fused_tile_x", "fused_tile_y", "fused_planes", "fused_threads"]
+        else:
+            keys += ["xcd_remap", "grid_scale_pct", "tile_order", "lds_window"]
+        return us.value, {k: self.get_option(k) for k in keys}
 
     def set_demag(self, pos, cell_size, atom_volume, every):
         """Macrocell demagnetising field: atom positions [n, 3] (m), cell
@@ -321,8 +325,9 @@ class SpinSystem:
         self._check(lib().sllg_set_demag(self._h, _ptr(pos), float(cell_size), float(atom_volume), int(every)))
 
     def demag_field(self, stream=None):
-        """Recompute the demagnetising field from the current spins; per
-        atom [n, 3] tesla."""
+        """The demagnetising field in effect, per atom [n, 3] tesla: the
+        field held since the last scheduled update, or, when none is held
+        yet, the field of the current spins (computed now and held)."""
         out = np.empty((self.n, 3))
         self._check(lib().sllg_demag_field(self._h, _ptr(out), _stream(stream)))
         return out

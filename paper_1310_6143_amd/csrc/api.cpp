@@ -58,6 +58,7 @@ struct Engine {
     virtual double max_torque(hipStream_t st) = 0;
     virtual void demag_update(hipStream_t st) = 0;
     virtual void demag_fetch(std::vector<double>& out, hipStream_t st) = 0;
+    virtual void demag_set(const std::vector<double>& in) = 0;
     virtual size_t spin_bytes() = 0;
     virtual void save_spins(void* dst, hipStream_t st) = 0;
     virtual void load_spins(const void* src, hipStream_t st) = 0;
@@ -129,6 +130,7 @@ struct EngineT final : Engine {
     void record_current(int slot, hipStream_t st) override { batch.record_current(slot, st); }
     void demag_update(hipStream_t st) override { batch.demag_update(q, st); }
     void demag_fetch(std::vector<double>& out, hipStream_t st) override { batch.demag_fetch(q, out, st); }
+    void demag_set(const std::vector<double>& in) override { batch.demag_set(q, in); }
     double max_torque(hipStream_t st) override
     {
         std::vector<double> t;
@@ -187,6 +189,8 @@ struct sllg_system {
     // the demagnetising field on the device belongs to the current state
     // and schedule; false: recompute before the next step that needs it
     bool demag_valid = false;
+    // a held field restored from a checkpoint before the engine exists
+    std::vector<double> demag_pending;
     int64_t opt_check_symmetry = 1;
     int64_t opt_graph_steps = -1;    // -1 = automatic
     int64_t opt_xcd_remap = 1;
@@ -271,6 +275,9 @@ Engine& engine(sllg_system* s)
         const FusedShape& f = s->opt_fshape;
         if (f.px > 0 && f.py > 0 && f.planes > 0 && f.bt > 0 && s->eng->fused_capable())
             s->eng->set_fused_shape(f);
+        if (s->st.demag.on && s->demag_valid && !s->demag_pending.empty())
+            s->eng->demag_set(s->demag_pending);
+        s->demag_pending.clear();
     }
     hip_check(hipSetDevice(s->device), "hipSetDevice");
     return *s->eng;
@@ -285,8 +292,11 @@ void drop_engine(sllg_system* s)
     s->spins.assign(3 * (size_t)s->n, 0.0);
     s->eng->get_spins(s->spins.data(), s->own);
     s->dyn.step = s->eng->step();
+    // a held demagnetising field stays in effect across the rebuild
+    s->demag_pending.clear();
+    if (s->st.demag.on && s->demag_valid)
+        s->eng->demag_fetch(s->demag_pending, s->own);
     s->eng.reset();
-    s->demag_valid = false;
 }
 
 // The demagnetising field for the step about to run: recomputed from the
@@ -517,10 +527,13 @@ void average(sllg_system* s, int64_t n_eq, int64_t n_avg, int n_blocks, double o
         fail(SLLG_E_NUMERIC, "the energy became non-finite during averaging");
 }
 
-// Launch-shape autotuner: time each candidate (XCD-contiguous tile ranges or
-// not; workgroups per launch as 1/2, 1 or 2 resident grids; for small
-// systems the steps per captured graph) over a few steps of the real system
-// and keep the fastest.  Results do not depend on these choices, and the
+// Launch-shape autotuner: time each candidate over a few steps of the real
+// system and keep the fastest.  With the fused step active: the model's
+// eight best fused shapes (tile, planes per item, block size); else the
+// two-launch step's launch shapes
+// (XCD-contiguous tile ranges or not; workgroups per launch as 1/2, 1 or 2
+// resident grids; tile order; LDS window).  Small systems also try the
+// steps per captured graph.  Results do not depend on these choices, and the
 // spins, step counter and buffer parity are restored afterwards, so tuning
 // leaves the trajectory untouched.
 double autotune(sllg_system* s, int trial_steps, hipStream_t st)
@@ -537,20 +550,52 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
         int64_t graph;
         int64_t order;
         int64_t window;
+        int64_t fused;       // 1: the fused step in shape fs
+        FusedShape fs;
     };
     std::vector<Cand> cands;
     const bool small = s->n < (int64_t(1) << 20);
-    for (int64_t window : {1, 0})
-        for (int64_t order : {1, 0})
-            for (int remap : {1, 2, 0})
-                for (int64_t scale : {100, 50, 200})
-                    for (int64_t g : small ? std::vector<int64_t>{64, 16, 256} : std::vector<int64_t>{0})
-                        cands.push_back({remap, scale, g, order, window});
+    const std::vector<int64_t> graphs = small ? std::vector<int64_t>{64, 16, 256} : std::vector<int64_t>{0};
+    const bool fusable = s->opt_fused && e.fused_capable();
+    if (fusable) {
+        // the model's best fused shapes (the spins do not depend on the shape)
+        for (const FusedShape& f : e.fused_candidates(8))
+            for (int64_t g : graphs)
+                cands.push_back({1, 100, g, 1, 1, 1, f});
+    } else {
+        for (int64_t window : {1, 0})
+            for (int64_t order : {1, 0})
+                for (int remap : {1, 2, 0})
+                    for (int64_t scale : {100, 50, 200})
+                        for (int64_t g : graphs)
+                            cands.push_back({remap, scale, g, order, window, 0, FusedShape{}});
+    }
     hipEvent_t a = nullptr, b = nullptr;
     double best = 1e30;
     Cand best_c = {(int)s->opt_xcd_remap, s->opt_grid_scale_pct, graph_steps(s), s->opt_tile_order,
-                   s->opt_lds_window};
+                   s->opt_lds_window, fusable ? 1 : 0, fusable ? e.fused_shape() : FusedShape{}};
+    auto apply = [&](const Cand& c) {
+        s->opt_xcd_remap = c.remap;
+        s->opt_grid_scale_pct = c.scale_pct;
+        s->opt_graph_steps = c.graph;
+        s->opt_tile_order = c.order;
+        s->opt_lds_window = c.window;
+        e.set_remap(c.remap);
+        e.set_grid_scale(c.scale_pct / 100.0);
+        e.set_tile_order((int)c.order, (int)s->opt_tile_group);
+        e.set_window(c.window != 0);
+        if (c.fused) {
+            s->opt_fshape = c.fs;
+            e.set_fused_shape(c.fs);
+        }
+    };
     const int32_t flags0 = *r.flags;
+    // the held demagnetising field belongs to the trajectory: kept aside and
+    // put back, so the schedule continues as if no trial had run
+    const bool demag_valid0 = s->demag_valid;
+    std::vector<double> demag0;
+    if (s->st.demag.on && demag_valid0)
+        e.demag_fetch(demag0, st);
     const char* log_env = std::getenv("SLLG_AUTOTUNE_LOG");   // print every candidate's time
     const bool log = log_env && *log_env && *log_env != '0';
     try {
@@ -561,15 +606,7 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
         for (const Cand& c : cands) {
             if (c.graph > e.rec_cap())
                 continue;
-            s->opt_xcd_remap = c.remap;
-            s->opt_grid_scale_pct = c.scale_pct;
-            s->opt_graph_steps = c.graph;
-            s->opt_tile_order = c.order;
-            s->opt_lds_window = c.window;
-            e.set_remap(c.remap);
-            e.set_grid_scale(c.scale_pct / 100.0);
-            e.set_tile_order((int)c.order, (int)s->opt_tile_group);
-            e.set_window(c.window != 0);
+            apply(c);
             const int steps = c.graph > 0 ? (int)std::max<int64_t>(c.graph, trial_steps) : trial_steps;
             run_steps(s, std::max<int64_t>(c.graph, 2), nullptr, nullptr, nullptr, nullptr, st, 0);  // warm
             double us = 1e30;
@@ -582,7 +619,10 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
                 hip_check(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
                 us = std::min(us, 1e3 * ms / steps);
             }
-            if (log)
+            if (log && c.fused)
+                std::fprintf(stderr, "[sllg autotune] fused tile %d x %d, %d planes, %d threads, graph %lld: %.1f us/step\n",
+                             c.fs.px - 2, c.fs.py - 2, c.fs.planes, c.fs.bt, (long long)c.graph, us);
+            else if (log)
                 std::fprintf(stderr,
                              "[sllg autotune] lds_window %lld xcd_remap %d grid %lld%% graph %lld tile_order %lld: "
                              "%.1f us/step\n",
@@ -609,18 +649,15 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
     e.set_step(step0);
     *r.flags = flags0;
     e.mark_dirty();
+    if (s->st.demag.on) {
+        if (demag_valid0)
+            e.demag_set(demag0);
+        s->demag_valid = demag_valid0;
+    }
     (void)hipFree(saved);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    s->opt_xcd_remap = best_c.remap;
-    s->opt_grid_scale_pct = best_c.scale_pct;
-    s->opt_graph_steps = best_c.graph;
-    s->opt_tile_order = best_c.order;
-    s->opt_lds_window = best_c.window;
-    e.set_remap(best_c.remap);
-    e.set_grid_scale(best_c.scale_pct / 100.0);
-    e.set_tile_order((int)best_c.order, (int)s->opt_tile_group);
-    e.set_window(best_c.window != 0);
+    apply(best_c);
     s->tuned = true;
     s->tuned_us = best;
     return best;
@@ -1069,8 +1106,12 @@ sllg_status sllg_demag_field(sllg_system* sys, double* field_out, void* stream)
             fail(SLLG_E_STATE, "no demagnetising field set (sllg_set_demag)");
         hipStream_t st = pick_stream(sys, stream);
         Engine& e = engine(sys);
-        e.demag_update(st);
-        sys->demag_valid = true;
+        // the field in effect: computed now only when none is held (the next
+        // step would compute the same from the current state)
+        if (!sys->demag_valid) {
+            e.demag_update(st);
+            sys->demag_valid = true;
+        }
         std::vector<double> cells;
         e.demag_fetch(cells, st);
         const HostDemag& dm = sys->st.demag;
@@ -1140,13 +1181,27 @@ struct CheckpointHeader {
     uint64_t seed;
     uint64_t step;
 };
+
+// Version 2 adds the held demagnetising field: it belongs to the state
+// (it was computed at the last update step and is held until the next), so
+// a restored run continues exactly as the uninterrupted one.
+struct CheckpointDemag {
+    int64_t cells;       // cells of the field that follows (0: none held)
+    int64_t reserved;
+};
+
+size_t demag_checkpoint_cells(const sllg_system* sys)
+{
+    return sys->st.demag.on && sys->demag_valid ? (size_t)sys->st.demag.cells : 0;
+}
 }  // namespace
 
 sllg_status sllg_checkpoint_size(const sllg_system* sys, size_t* bytes)
 {
     if (!sys || !bytes)
         return SLLG_E_ARG;
-    *bytes = sizeof(CheckpointHeader) + 3 * (size_t)sys->n * sizeof(double);
+    *bytes = sizeof(CheckpointHeader) + sizeof(CheckpointDemag) + 3 * (size_t)sys->n * sizeof(double) +
+             3 * demag_checkpoint_cells(sys) * sizeof(double);
     return SLLG_OK;
 }
 
@@ -1158,18 +1213,32 @@ sllg_status sllg_checkpoint(sllg_system* sys, void* buf, size_t bytes)
         if (!buf || bytes < need)
             fail(SLLG_E_ARG, "checkpoint buffer too small");
         CheckpointHeader h{};
-        std::memcpy(h.magic, "SLLGCKP1", 8);
-        h.version = 1;
+        std::memcpy(h.magic, "SLLGCKP2", 8);
+        h.version = 2;
         h.precision = (uint32_t)sys->prec;
         h.n = sys->n;
         h.seed = sys->dyn.seed;
         h.step = sys->eng ? sys->eng->step() : sys->dyn.step;
-        std::memcpy(buf, &h, sizeof(h));
-        double* S = reinterpret_cast<double*>(static_cast<char*>(buf) + sizeof(h));
+        CheckpointDemag d{};
+        d.cells = (int64_t)demag_checkpoint_cells(sys);
+        char* p = static_cast<char*>(buf);
+        std::memcpy(p, &h, sizeof(h));
+        std::memcpy(p + sizeof(h), &d, sizeof(d));
+        double* S = reinterpret_cast<double*>(p + sizeof(h) + sizeof(d));
         if (sys->eng)
             sys->eng->get_spins(S, sys->own);
         else
             std::memcpy(S, sys->spins.data(), sys->spins.size() * sizeof(double));
+        if (d.cells > 0) {
+            std::vector<double> field;
+            if (sys->eng)
+                sys->eng->demag_fetch(field, sys->own);
+            else
+                field = sys->demag_pending;
+            if (field.size() != 3 * (size_t)d.cells)
+                fail(SLLG_E_STATE, "held demagnetising field missing");
+            std::memcpy(S + 3 * (size_t)sys->n, field.data(), 3 * (size_t)d.cells * sizeof(double));
+        }
     });
 }
 
@@ -1180,21 +1249,41 @@ sllg_status sllg_restore(sllg_system* sys, const void* buf, size_t bytes)
         if (!buf || bytes < sizeof(h))
             fail(SLLG_E_ARG, "checkpoint buffer too small");
         std::memcpy(&h, buf, sizeof(h));
-        if (std::memcmp(h.magic, "SLLGCKP1", 8) != 0 || h.version != 1)
+        const bool v1 = std::memcmp(h.magic, "SLLGCKP1", 8) == 0 && h.version == 1;
+        const bool v2 = std::memcmp(h.magic, "SLLGCKP2", 8) == 0 && h.version == 2;
+        if (!v1 && !v2)
             fail(SLLG_E_ARG, "not a checkpoint of this library");
         if (h.n != sys->n || h.precision != (uint32_t)sys->prec)
             fail(SLLG_E_ARG, "checkpoint is of a different system size or precision");
-        if (bytes < sizeof(h) + 3 * (size_t)h.n * sizeof(double))
+        CheckpointDemag d{};
+        size_t off = sizeof(h);
+        if (v2) {
+            if (bytes < off + sizeof(d))
+                fail(SLLG_E_ARG, "checkpoint truncated");
+            std::memcpy(&d, static_cast<const char*>(buf) + off, sizeof(d));
+            off += sizeof(d);
+            if (d.cells < 0 || (d.cells > 0 && (!sys->st.demag.on || d.cells != sys->st.demag.cells)))
+                fail(SLLG_E_ARG, "checkpoint holds a demagnetising field of another macrocell set");
+        }
+        if (bytes < off + 3 * ((size_t)h.n + (size_t)d.cells) * sizeof(double))
             fail(SLLG_E_ARG, "checkpoint truncated");
-        const double* S = reinterpret_cast<const double*>(static_cast<const char*>(buf) + sizeof(h));
+        const double* S = reinterpret_cast<const double*>(static_cast<const char*>(buf) + off);
         std::vector<double> v = normalised_spins(sys->n, S, false);
-        sys->demag_valid = false;
+        std::vector<double> field(S + 3 * (size_t)h.n, S + 3 * ((size_t)h.n + (size_t)d.cells));
         if (sys->eng)
             sys->eng->set_spins(v);
         else
             sys->spins = v;
         if (sllg_set_rng(sys, h.seed, h.step) != SLLG_OK)
             fail(SLLG_E_DEVICE, sys->err);
+        // the held field of the checkpoint (none: recomputed before the next step)
+        sys->demag_valid = d.cells > 0;
+        if (d.cells > 0) {
+            if (sys->eng)
+                sys->eng->demag_set(field);
+            else
+                sys->demag_pending = field;
+        }
     });
 }
 

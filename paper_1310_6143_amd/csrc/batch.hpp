@@ -963,6 +963,18 @@ public:
         out.assign(tmp.begin(), tmp.end());
     }
 
+    // Replace the held field of replica q (3 per cell, tesla).
+    void demag_set(int q, const std::vector<double>& in)
+    {
+        const ReplicaDev<R>& r = slots_[q].rec;
+        if (in.size() != 3 * (size_t)r.dm_cells)
+            fail(SLLG_E_ARG, "demagnetising field of the wrong size");
+        std::vector<R> tmp(in.begin(), in.end());
+        quiesce();
+        hip_check(hipMemcpy(r.dm_field, tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice),
+                  "upload demagnetising field");
+    }
+
     // Largest torque |S_i x H_i| over the sites of every used replica's
     // current state (deterministic field, no thermal term): out[q] per slot.
     void max_torque(std::vector<double>& out, hipStream_t st)
