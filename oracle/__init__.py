@@ -111,6 +111,8 @@ def lib():
         L.orc_mc_choice.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, P, P]
         L.orc_mc_run.argtypes = [ctypes.POINTER(_System), P, ctypes.c_uint64, ctypes.c_int64, P, P, P]
         L.orc_mc_run.restype = ctypes.c_int
+        L.orc_mc_run_random.argtypes = [ctypes.POINTER(_System), P, ctypes.c_uint64, ctypes.c_int64, P, P, P]
+        L.orc_mc_run_random.restype = ctypes.c_int
         L.orc_demag_update.argtypes = [ctypes.POINTER(_System), P]
         L.orc_demag_update.restype = ctypes.c_int
         L.orc_demag_sample.argtypes = [ctypes.POINTER(_System), P, ctypes.c_int64, P, P]
@@ -288,18 +290,21 @@ class System:
             raise FloatingPointError(f"oracle integrate failed ({rc})")
         return m, E
 
-    def mc(self, S, step0, n_steps, record=True):
-        """Monte Carlo steps step0 .. step0+n_steps-1 (Hinzke-Nowak moves,
-        colour-class sweeps) in place on S.  Returns (m [n_steps, 3],
-        E [n_steps], accepted trials [n_steps]); m and E are None unless
-        record."""
+    def mc(self, S, step0, n_steps, record=True, order="colour"):
+        """Monte Carlo steps step0 .. step0+n_steps-1 (Hinzke-Nowak moves)
+        in place on S; order "colour" (colour-class sweeps, every site once)
+        or "random" (the paper's: N trials on random sites).  Returns
+        (m [n_steps, 3], E [n_steps], accepted trials [n_steps]); m and E
+        are None unless record."""
         assert S.dtype == np.float64 and S.flags.c_contiguous and S.shape == (self.n, 3)
+        assert order in ("colour", "random")
         m = np.empty((n_steps, 3)) if record else None
         E = np.empty(n_steps) if record else None
         acc = np.empty(n_steps, dtype=np.int64)
         st = self._struct()
-        rc = lib().orc_mc_run(ctypes.byref(st), _ptr(S), int(step0), int(n_steps),
-                              _ptr(m) if record else None, _ptr(E) if record else None, _ptr(acc))
+        run = lib().orc_mc_run if order == "colour" else lib().orc_mc_run_random
+        rc = run(ctypes.byref(st), _ptr(S), int(step0), int(n_steps),
+                 _ptr(m) if record else None, _ptr(E) if record else None, _ptr(acc))
         if rc != 0:
             raise MemoryError(f"oracle Monte Carlo failed ({rc})")
         return m, E, acc
@@ -358,11 +363,11 @@ def average(sys: System, S, step0, n_eq, n_avg, n_blocks=10):
     return out, step0 + n_eq + n_avg
 
 
-def mc_average(sys: System, S, step0, n_eq, n_avg, n_blocks=10):
+def mc_average(sys: System, S, step0, n_eq, n_avg, n_blocks=10, order="colour"):
     """Monte Carlo counterpart of average(): n_eq steps to equilibrate, then
-    n_avg steps sampled after every step."""
-    sys.mc(S, step0, n_eq, record=False)
-    m, E, acc = sys.mc(S, step0 + n_eq, n_avg, record=True)
+    n_avg steps sampled after every step (trial order as in System.mc)."""
+    sys.mc(S, step0, n_eq, record=False, order=order)
+    m, E, acc = sys.mc(S, step0 + n_eq, n_avg, record=True, order=order)
     mabs = np.sqrt((m * m).sum(axis=1))
     mean_abs, se_abs = block_stats(mabs, n_blocks)
     mean_E, se_E = block_stats(E, n_blocks)

@@ -9,16 +9,23 @@
  * S' = Gamma/|Gamma|.  It is accepted with probability exp(-dE/(kB T)),
  * unconditionally when dE <= 0.
  *
- * The paper picks the N trial sites of one Monte Carlo step at random.
- * Here a step visits every site once, colour class by colour class of a
- * greedy colouring of the neighbour graph (ascending colour, ascending site
- * within a colour).  Sites of one colour share no link, so their trials do
- * not interact and the order within a class is immaterial; every single
- * trial satisfies detailed balance, so the chain samples the same Boltzmann
- * distribution.  Random numbers are counter-based like the thermal field:
- * the Gaussian numbers of site i at Monte Carlo step k come from Philox
- * counter (i, k lo, k hi, 2), the move choice and the acceptance uniform
- * from counter (i, k lo, k hi, 3).
+ * Two orders of the N trials of one Monte Carlo step:
+ *
+ * - the paper's (orc_mc_step_random): N trials, each on a site drawn
+ *   uniformly at random with replacement.  Trial t of step k takes its
+ *   site, move and acceptance uniform from Philox counter (t, k lo, k hi, 4)
+ *   and its Gaussian numbers from counter (t, k lo, k hi, 5);
+ * - colour classes (orc_mc_step): every site once, colour class by colour
+ *   class of a greedy colouring of the neighbour graph (ascending colour,
+ *   ascending site within a colour).  Sites of one colour share no link, so
+ *   their trials do not interact and the order within a class is
+ *   immaterial.  The Gaussian numbers of site i at step k come from counter
+ *   (i, k lo, k hi, 2), the move choice and the acceptance uniform from
+ *   counter (i, k lo, k hi, 3).
+ *
+ * Every single trial satisfies detailed balance, so both chains sample the
+ * same Boltzmann distribution; the test suite checks that their averages
+ * agree within their statistical errors.
  */
 #include <math.h>
 #include <stdint.h>
@@ -102,13 +109,13 @@ static double site_energy(const orc_system *s, const double *S, int64_t i, const
     return E;
 }
 
-int orc_mc_trial(const orc_system *s, double *S, int64_t i, uint64_t step)
+/* One Metropolis trial on spin i with its random numbers given: move type,
+ * acceptance uniform u and three Gaussian numbers g.  Returns 1 when
+ * accepted. */
+static int mc_trial_with(const orc_system *s, double *S, int64_t i, uint32_t move, double u, const double g[3])
 {
     double *si = S + 3 * i;
-    uint32_t move;
-    double u, g[3], trial[3];
-    orc_mc_choice(s->seed, step, (uint64_t)i, &move, &u);
-    orc_gaussian3(s->seed, step, (uint64_t)i, 2u, g);
+    double trial[3];
     if (move == 0) {            /* spin flip */
         trial[0] = -si[0];
         trial[1] = -si[1];
@@ -139,6 +146,35 @@ int orc_mc_trial(const orc_system *s, double *S, int64_t i, uint64_t step)
         si[2] = trial[2];
     }
     return accept;
+}
+
+int orc_mc_trial(const orc_system *s, double *S, int64_t i, uint64_t step)
+{
+    uint32_t move;
+    double u, g[3];
+    orc_mc_choice(s->seed, step, (uint64_t)i, &move, &u);
+    orc_gaussian3(s->seed, step, (uint64_t)i, 2u, g);
+    return mc_trial_with(s, S, i, move, u, g);
+}
+
+int64_t orc_mc_step_random(const orc_system *s, double *S, uint64_t step)
+{
+    const uint32_t key[2] = {(uint32_t)s->seed, (uint32_t)(s->seed >> 32)};
+    int64_t accepted = 0;
+    for (int64_t t = 0; t < s->n; ++t) {
+        const uint32_t ctr[4] = {(uint32_t)t, (uint32_t)step, (uint32_t)(step >> 32), 4u};
+        uint32_t r[4];
+        orc_philox4x32_10(ctr, key, r);
+        /* site: a 64-bit uniform scaled to [0, n) */
+        const uint64_t x = (uint64_t)r[0] | ((uint64_t)r[1] << 32);
+        const int64_t i = (int64_t)(((unsigned __int128)x * (uint64_t)s->n) >> 64);
+        const uint32_t move = (uint32_t)(((uint64_t)r[2] * 3u) >> 32);
+        const double u = (double)r[3] * (1.0 / 4294967296.0);
+        double g[3];
+        orc_gaussian3(s->seed, step, (uint64_t)t, 5u, g);
+        accepted += mc_trial_with(s, S, i, move, u, g);
+    }
+    return accepted;
 }
 
 int64_t orc_mc_step(const orc_system *s, double *S, const int32_t *colour, int n_colours, uint64_t step)
@@ -176,5 +212,22 @@ int orc_mc_run(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, 
             E_out[t] = orc_energy(s, S);
     }
     free(colour);
+    return 0;
+}
+
+int orc_mc_run_random(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, double *m_out,
+                      double *E_out, int64_t *accepted_out)
+{
+    if (s->demag)
+        return -3;
+    for (int64_t t = 0; t < n_steps; ++t) {
+        const int64_t acc = orc_mc_step_random(s, S, step0 + (uint64_t)t);
+        if (accepted_out)
+            accepted_out[t] = acc;
+        if (m_out)
+            orc_magnetisation(s, S, m_out + 3 * t);
+        if (E_out)
+            E_out[t] = orc_energy(s, S);
+    }
     return 0;
 }

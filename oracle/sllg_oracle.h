@@ -137,7 +137,9 @@ double orc_max_torque(const orc_system *s, const double *S);
  * when accepted.  orc_mc_step: one step (every site once, colour by colour);
  * returns the number of accepted trials.  orc_mc_run: n_steps steps
  * numbered step0, step0+1, ...; m, E and the accepted count after each
- * step go to the arrays that are not NULL.  Returns 0 or -2. */
+ * step go to the arrays that are not NULL.  Returns 0 or -2.
+ * orc_mc_step_random / orc_mc_run_random: the same in the paper's order, N
+ * trials on sites drawn at random with replacement. */
 int orc_greedy_colours(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t *colour);
 double orc_mc_cone_width(double temperature);
 void orc_mc_choice(uint64_t seed, uint64_t step, uint64_t site, uint32_t *move, double *u);
@@ -145,6 +147,9 @@ int orc_mc_trial(const orc_system *s, double *S, int64_t i, uint64_t step);
 int64_t orc_mc_step(const orc_system *s, double *S, const int32_t *colour, int n_colours, uint64_t step);
 int orc_mc_run(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, double *m_out,
                double *E_out, int64_t *accepted_out);
+int64_t orc_mc_step_random(const orc_system *s, double *S, uint64_t step);
+int orc_mc_run_random(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, double *m_out,
+                      double *E_out, int64_t *accepted_out);
 
 /* Brute-force neighbour search over all pairs (minimum image on the axes
  * with box[a] > 0).  A pair at distance r with shell_lo[t] <= r <= shell_hi[t]
