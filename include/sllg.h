@@ -247,6 +247,18 @@ sllg_status sllg_integrate_dev(sllg_system *sys, int64_t n_steps, double *m_dev,
 sllg_status sllg_mc(sllg_system *sys, int64_t n_steps, double *m_out, double *E_out,
                     int64_t *accepted_out, void *stream);
 
+/* Monte Carlo thermal average (the M(T) protocol of section "Monte Carlo
+ * Methods" and "Curie temperature": equilibrate, then average with m and E
+ * taken after every step): n_eq steps of sllg_mc, then n_avg steps, and
+ * out[9] = { <|m|>, se(<|m|>), <m_x>, <m_y>, <m_z>, <E>, se(<E>),
+ * n_blocks, acceptance }.  The averages and standard errors are those of
+ * sllg_average over the first n_avg - n_avg % n_blocks steps, in n_blocks
+ * (>= 2, <= min(n_avg, 4096)) equal consecutive blocks; acceptance is the
+ * accepted trials of all n_avg steps over n * n_avg.  SLLG_E_STATE with a
+ * demagnetising field on. */
+sllg_status sllg_mc_average(sllg_system *sys, int64_t n_eq, int64_t n_avg, int n_blocks, double out[9],
+                            void *stream);
+
 /* Observables of the current state: m[3] and E (either may be NULL). */
 sllg_status sllg_measure(sllg_system *sys, double m[3], double *E, void *stream);
 

@@ -28,7 +28,7 @@ EXPORTS = [
     "sllg_demag_field", "sllg_set_integrator", "sllg_set_conditions", "sllg_set_rng",
     "sllg_get_step", "sllg_set_spins", "sllg_get_spins", "sllg_integrate", "sllg_integrate_dev",
     "sllg_measure", "sllg_average", "sllg_sweep_temperature", "sllg_sweep_field",
-    "sllg_max_torque", "sllg_relax", "sllg_hysteresis", "sllg_thermal_normals", "sllg_autotune", "sllg_mc", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
+    "sllg_max_torque", "sllg_relax", "sllg_hysteresis", "sllg_thermal_normals", "sllg_autotune", "sllg_mc", "sllg_mc_average", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
     "sllg_set_option", "sllg_get_option",
     "sllg_server_create", "sllg_server_destroy", "sllg_server_last_error", "sllg_submit",
     "sllg_poll", "sllg_wait", "sllg_fetch", "sllg_cancel", "sllg_release", "sllg_server_get_stats",
@@ -116,6 +116,7 @@ def lib():
         "sllg_thermal_normals": (c, [c, c, U64, U64, I64, P]),
         "sllg_autotune": (c, [P, c, ctypes.POINTER(D), P]),
         "sllg_mc": (c, [P, I64, P, P, P, P]),
+        "sllg_mc_average": (c, [P, I64, I64, c, P, P]),
         "sllg_checkpoint_size": (c, [P, ctypes.POINTER(ctypes.c_size_t)]),
         "sllg_checkpoint": (c, [P, P, ctypes.c_size_t]),
         "sllg_restore": (c, [P, P, ctypes.c_size_t]),
@@ -369,23 +370,16 @@ class SpinSystem:
         self._check(lib().sllg_mc(self._h, int(n_steps), _ptr(m), _ptr(E), _ptr(acc), _stream(stream)))
         return m, E, acc
 
-    def mc_average(self, n_eq, n_avg, n_blocks=10):
-        """Monte Carlo thermal average: n_eq steps, then n_avg steps sampled
-        after every step.  Returns <|m|> and its blocked standard error, <m>,
-        <E> and its standard error, and the acceptance rate."""
-        self.mc(n_eq, record=False)
-        m, E, acc = self.mc(n_avg)
-        mabs = np.sqrt((m * m).sum(axis=1))
-        b = n_avg // n_blocks
-
-        def stats(x):
-            means = x[: b * n_blocks].reshape(n_blocks, b).mean(axis=1)
-            return float(x.mean()), float(means.std(ddof=1) / np.sqrt(n_blocks))
-
-        m_abs, m_se = stats(mabs)
-        E_mean, E_se = stats(E)
-        return {"m_abs": m_abs, "m_abs_se": m_se, "m": m.mean(axis=0), "E": E_mean, "E_se": E_se,
-                "acceptance": float(acc.sum()) / (self.n * n_avg)}
+    def mc_average(self, n_eq, n_avg, n_blocks=10, stream=None):
+        """Monte Carlo thermal average (sllg_mc_average): n_eq steps, then
+        n_avg steps sampled after every step.  Returns <|m|> and its blocked
+        standard error, <m>, <E> and its standard error, and the acceptance
+        rate."""
+        out = np.empty(9)
+        self._check(lib().sllg_mc_average(self._h, int(n_eq), int(n_avg), int(n_blocks), _ptr(out),
+                                          _stream(stream)))
+        return {"m_abs": out[0], "m_abs_se": out[1], "m": out[2:5].copy(), "E": out[5], "E_se": out[6],
+                "acceptance": out[8]}
 
     def measure(self):
         m = np.empty(3)

@@ -207,6 +207,8 @@ struct sllg_system {
     hipStream_t own = nullptr;
     std::unique_ptr<Engine> eng;
     std::vector<double> staging;
+    unsigned long long* d_mc_acc = nullptr;   // accepted trials per Monte Carlo step (device)
+    int64_t mc_acc_cap = 0;
 };
 
 namespace {
@@ -419,12 +421,21 @@ void mc_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, int
     *r.nsteps = 1;
     *r.rec_pos = 0;
     e.mark_dirty();
-    unsigned long long* d_acc = nullptr;
-    hip_check(hipMalloc(&d_acc, sizeof(unsigned long long) * (size_t)chunk), "hipMalloc(accepted)");
+    if (s->mc_acc_cap < chunk) {   // kept for the system's lifetime
+        if (s->d_mc_acc) {
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            hip_check(hipFree(s->d_mc_acc), "hipFree(accepted)");
+            s->d_mc_acc = nullptr;
+            s->mc_acc_cap = 0;
+        }
+        hip_check(hipMalloc(&s->d_mc_acc, sizeof(unsigned long long) * (size_t)chunk), "hipMalloc(accepted)");
+        s->mc_acc_cap = chunk;
+    }
+    unsigned long long* d_acc = s->d_mc_acc;
     std::vector<unsigned long long> acc((size_t)chunk);
     const uint64_t step0 = e.step();
     bool bad = false;
-    try {
+    {
         for (int64_t done = 0; done < n_steps;) {
             const int64_t ns = std::min<int64_t>(chunk, n_steps - done);
             hip_check(hipMemsetAsync(d_acc, 0, sizeof(unsigned long long) * (size_t)ns, st), "clear counts");
@@ -461,11 +472,7 @@ void mc_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, int
             }
             done += ns;
         }
-    } catch (...) {
-        (void)hipFree(d_acc);
-        throw;
     }
-    (void)hipFree(d_acc);
     *r.flags = saved_flags;
     *r.nsteps = saved_nsteps;
     e.set_step(step0 + (uint64_t)n_steps);
@@ -525,6 +532,45 @@ void average(sllg_system* s, int64_t n_eq, int64_t n_avg, int n_blocks, double o
     averages_from_block_sums(acc.data(), n_blocks, block_len, out);
     if (!std::isfinite(out[5]))
         fail(SLLG_E_NUMERIC, "the energy became non-finite during averaging");
+}
+
+// Monte Carlo thermal average: n_eq steps, then n_avg steps with m and E
+// taken after every step, summed per block on the host in step order.
+void mc_average(sllg_system* s, int64_t n_eq, int64_t n_avg, int n_blocks, double out[9], hipStream_t st)
+{
+    if (n_eq < 0 || n_avg < 1)
+        fail(SLLG_E_ARG, "need n_eq >= 0 and n_avg >= 1");
+    if (n_blocks < 2 || n_blocks > kAvgCap || n_blocks > n_avg)
+        fail(SLLG_E_ARG, "n_blocks must be in 2..min(n_avg, 4096)");
+    if (!out)
+        fail(SLLG_E_ARG, "out must not be NULL");
+    mc_steps(s, n_eq, nullptr, nullptr, nullptr, st);
+    const int64_t block_len = n_avg / n_blocks;
+    std::vector<double> sums(5 * (size_t)n_blocks, 0.0);
+    constexpr int64_t kPiece = 4096;
+    std::vector<double> m(3 * (size_t)std::min(kPiece, n_avg)), E((size_t)std::min(kPiece, n_avg));
+    std::vector<int64_t> acc((size_t)std::min(kPiece, n_avg));
+    double accepted = 0.0;
+    for (int64_t done = 0; done < n_avg;) {
+        const int64_t ns = std::min(kPiece, n_avg - done);
+        mc_steps(s, ns, m.data(), E.data(), acc.data(), st);
+        for (int64_t t = 0; t < ns; ++t) {
+            accepted += (double)acc[(size_t)t];
+            const int64_t k = done + t;
+            if (k >= block_len * n_blocks)
+                continue;
+            double* b = &sums[5 * (size_t)(k / block_len)];
+            const double* mt = &m[3 * (size_t)t];
+            b[0] += std::sqrt(mt[0] * mt[0] + mt[1] * mt[1] + mt[2] * mt[2]);
+            b[1] += mt[0];
+            b[2] += mt[1];
+            b[3] += mt[2];
+            b[4] += E[(size_t)t];
+        }
+        done += ns;
+    }
+    averages_from_block_sums(sums.data(), n_blocks, block_len, out);
+    out[8] = accepted / ((double)s->n * (double)n_avg);
 }
 
 // Launch-shape autotuner: time each candidate over a few steps of the real
@@ -747,6 +793,10 @@ void sllg_destroy(sllg_system* sys)
     if (sys->own) {
         (void)hipSetDevice(sys->device);
         (void)hipStreamSynchronize(sys->own);
+    }
+    if (sys->d_mc_acc) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(sys->d_mc_acc);
     }
     sys->eng.reset();
     if (sys->own)
@@ -974,6 +1024,12 @@ sllg_status sllg_mc(sllg_system* sys, int64_t n_steps, double* m_out, double* E_
         if (n_steps > 0)
             mc_steps(sys, n_steps, m_out, E_out, accepted_out, pick_stream(sys, stream));
     });
+}
+
+sllg_status sllg_mc_average(sllg_system* sys, int64_t n_eq, int64_t n_avg, int n_blocks, double out[9],
+                            void* stream)
+{
+    return guard(sys, [&] { mc_average(sys, n_eq, n_avg, n_blocks, out, pick_stream(sys, stream)); });
 }
 
 sllg_status sllg_average(sllg_system* sys, int64_t n_eq, int64_t n_avg, int n_blocks, double out[8],

@@ -5,7 +5,8 @@ against the FP64 oracle, through the C ABI.
 The fused step adds a site's exchange links in its own fixed order (links
 into the plane below, its own plane, the plane above), so it agrees with
 the oracle and with the two-launch step to FP32 rounding; the tolerances
-are those of the FP32 two-launch path.  Spins do not depend on the tile
+are about ten times the differences measured on MI355X (printed on the
+lines starting "PARITY").  Spins do not depend on the tile
 shape (each site's arithmetic is the same whichever workgroup computes it),
 so different shapes must give bit-identical spins; the m and E records are
 sums over items and may differ at FP64 rounding.
@@ -16,7 +17,7 @@ import pytest
 import oracle
 import paper_1310_6143_amd as sl
 from spin_systems import bcc_block, bcc_film, sc_reference
-from tests.gpu_util import max_angle, mean_angle
+from tests.gpu_util import max_angle, mean_angle, parity_report
 
 pytestmark = pytest.mark.gpu
 
@@ -65,13 +66,13 @@ def test_sc4096_fused_fp32_matches_oracle():
     w = sc_reference(L=16, temperature=300.0, n_steps=1000, seed=42)
     S_ref, m_ref, E_ref = _oracle_run(w, 1000)
     S, m, E = _run(w, 1000)
+    parity_report("fused sc 16^3 T=300 K FP32 1000 steps", S, S_ref, m, m_ref, E, E_ref)
     amax, amean = max_angle(S, S_ref), mean_angle(S, S_ref)
     dm = np.abs(m - m_ref).max()
     dE = (np.abs(E - E_ref) / np.abs(E_ref)).max()
-    print(f"fused FP32 sc 16^3 T=300 K, 1000 steps: max angle {amax:.3e}, mean {amean:.3e}, "
-          f"|dm| {dm:.3e}, |dE/E| {dE:.3e}")
-    assert amax <= 2e-3 and amean <= 2e-4
-    assert dm <= 1e-4 and dE <= 1e-4
+    # measured 1.5e-6, 3.4e-7, 3.6e-8, 6.1e-8
+    assert amax <= 2e-5 and amean <= 5e-6
+    assert dm <= 5e-7 and dE <= 1e-6
     assert np.abs(np.linalg.norm(S, axis=1) - 1).max() <= 1e-6
 
 
@@ -80,13 +81,13 @@ def test_bcc_j1j2_fused_fp32_matches_oracle():
     w.H = np.array([0.3, -0.2, 0.5])
     S_ref, m_ref, E_ref = _oracle_run(w, 300)
     S, m, E = _run(w, 300)
+    parity_report("fused bcc 24^3 J1+J2 FP32 300 steps", S, S_ref, m, m_ref, E, E_ref)
     amax, amean = max_angle(S, S_ref), mean_angle(S, S_ref)
     dm = np.abs(m - m_ref).max()
     dE = (np.abs(E - E_ref) / np.abs(E_ref)).max()
-    print(f"fused FP32 bcc 24^3 J1+J2, 300 steps: max angle {amax:.3e}, mean {amean:.3e}, "
-          f"|dm| {dm:.3e}, |dE/E| {dE:.3e}")
-    assert amax <= 2e-3 and amean <= 2e-4
-    assert dm <= 1e-4 and dE <= 1e-4
+    # measured 7.8e-7, 1.7e-7, 3.4e-9, 1.7e-8
+    assert amax <= 1e-5 and amean <= 2e-6
+    assert dm <= 5e-8 and dE <= 2e-7
 
 
 def test_film_open_z_fused_fp32_matches_oracle():
@@ -96,11 +97,12 @@ def test_film_open_z_fused_fp32_matches_oracle():
     w.H = np.array([0.0, 0.4, -0.3])
     S_ref, m_ref, E_ref = _oracle_run(w, 300)
     S, m, E = _run(w, 300)
+    parity_report("fused film 20x12x7 open z FP32 300 steps", S, S_ref, m, m_ref, E, E_ref)
     amax, amean = max_angle(S, S_ref), mean_angle(S, S_ref)
     dm = np.abs(m - m_ref).max()
-    print(f"fused FP32 film 20x12x7 open z, 300 steps: max angle {amax:.3e}, mean {amean:.3e}, |dm| {dm:.3e}")
-    assert amax <= 2e-3 and amean <= 2e-4
-    assert dm <= 1e-4
+    # measured 1.1e-6, 1.7e-7, 2.9e-8
+    assert amax <= 2e-5 and amean <= 2e-6
+    assert dm <= 5e-7
 
 
 @pytest.mark.parametrize("make", [lambda: bcc_block(cells=20, n_steps=50),

@@ -62,9 +62,46 @@ def test_mc_fp32_thermal_average_matches_oracle(T):
     with sl.from_workload(w, precision=sl.FP32) as g:
         gpu = g.mc_average(1000, 3000, 10)
     ref, _ = oracle.mc_average(oracle.System(w), w.S0.copy(), 0, 1000, 3000, 10)
-    tol = 4 * np.hypot(gpu["m_abs_se"], ref["m_abs_se"]) + 5e-3
+    # FP32 acceptance decisions differ from the oracle's where a uniform
+    # falls within FP32 rounding of its probability, so the chains part and
+    # agree in distribution: 3 combined blocked standard errors
+    tol = 3 * np.hypot(gpu["m_abs_se"], ref["m_abs_se"])
+    print(f"MC T={T}: gpu {gpu['m_abs']:.4f}+-{gpu['m_abs_se']:.4f} oracle {ref['m_abs']:.4f}+-{ref['m_abs_se']:.4f}")
     assert abs(gpu["m_abs"] - ref["m_abs"]) < tol, (gpu, ref)
     assert abs(gpu["acceptance"] - ref["acceptance"]) < 0.02
+
+
+def test_mc_average_fp64_equals_oracle():
+    """sllg_mc_average in FP64 runs the oracle's chain, so its averages are
+    the oracle's up to the order of the FP64 sums; the accepted counts are
+    the same integers."""
+    w = sc_reference(L=8, temperature=500.0, seed=5)
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        r = g.mc_average(200, 600, 6)
+        assert g.step == 800
+        # a second call continues the chain (step counter 800 onwards)
+        r2 = g.mc_average(0, 300, 3)
+    ref = oracle.System(w)
+    S = w.S0.copy()
+    o, step = oracle.mc_average(ref, S, 0, 200, 600, 6)
+    o2, _ = oracle.mc_average(ref, S, step, 0, 300, 3)
+    for a, b in ((r, o), (r2, o2)):
+        assert abs(a["m_abs"] - b["m_abs"]) <= 1e-12
+        assert abs(a["m_abs_se"] - b["m_abs_se"]) <= 1e-12
+        assert np.abs(a["m"] - b["m"]).max() <= 1e-12
+        assert abs(a["E"] - b["E"]) <= 1e-12 * abs(b["E"])
+        assert abs(a["E_se"] - b["E_se"]) <= 1e-9 * abs(b["E"])
+        assert a["acceptance"] == b["acceptance"]
+
+
+def test_mc_average_rejects_bad_arguments():
+    w = sc_reference(L=6, temperature=300.0, seed=5)
+    with sl.from_workload(w, precision=sl.FP32) as g:
+        for args in ((10, 0, 2), (-1, 10, 2), (10, 10, 1), (10, 10, 11)):
+            with pytest.raises(sl.SllgError) as e:
+                g.mc_average(*args)
+            assert e.value.name == "SLLG_E_ARG"
+        assert g.step == 0
 
 
 @pytest.mark.parametrize("precision", [sl.FP32, sl.FP64])
@@ -89,7 +126,8 @@ def test_mc_boltzmann_ensemble_of_free_spins(precision):
     num = integrate.quad(lambda t: np.cos(t) ** 2 * np.sin(t) * np.exp(xi * np.cos(t) ** 2), 0, np.pi)[0]
     den = integrate.quad(lambda t: np.sin(t) * np.exp(xi * np.cos(t) ** 2), 0, np.pi)[0]
     se = samples.std(ddof=1) / np.sqrt(samples.size)
-    assert abs(samples.mean() - num / den) < 4 * se + 2e-3, (samples.mean(), se, num / den)
+    print(f"free spins: <cos^2> {samples.mean():.5f} +- {se:.5f}, Boltzmann {num / den:.5f}")
+    assert abs(samples.mean() - num / den) < 3 * se, (samples.mean(), se, num / den)
 
 
 def test_mc_chains_agree_bitwise_across_neighbour_forms():

@@ -3,10 +3,12 @@
 The heating ramp (the M(T) protocol of the "Curie temperature" test: each
 temperature starts from the previous final state) and the field sweep are
 run on small versions of the film and particle workloads, on the GPU in FP32
-and FP64 and in the oracle, with the same noise streams.  Thermal averages
-must agree within 4 combined blocked standard errors (plus 2e-3 for the
-finite number of blocks); FP64 trajectories stay close to the oracle's, FP32
-ones decorrelate and agree only in distribution.
+and FP64 and in the oracle, with the same noise streams.  FP64 trajectories
+follow the oracle's (the same steps and the same noise to rounding); at
+1300 K the dynamics amplify the rounding differences to 2e-10 in <|m|> and
+6e-10 |E| in <E> by the end of the 20,000-step ramp, so the bound is 1e-8.  FP32 trajectories start on the oracle's and
+decorrelate through rounding; they agree in distribution, so their averages
+must agree within 3 combined blocked standard errors.
 """
 import numpy as np
 import pytest
@@ -18,8 +20,11 @@ from spin_systems import bcc_film, fcc_nanoparticle
 pytestmark = pytest.mark.gpu
 
 
-def _agree(a, b, key="m_abs", se_key="m_abs_se"):
-    tol = 4 * np.hypot(a[se_key], b[se_key]) + 2e-3
+def _agree(a, b, precision, key="m_abs", se_key="m_abs_se"):
+    if precision == sl.FP64:
+        tol = 1e-8 * (abs(b[key]) if key == "E" else 1.0)
+    else:
+        tol = 3 * np.hypot(a[se_key], b[se_key])
     return abs(a[key] - b[key]) <= tol, abs(a[key] - b[key]), tol
 
 
@@ -33,11 +38,12 @@ def test_film_temperature_ramp_matches_oracle(precision):
     S = w.S0.copy()
     orows, _ = oracle.sweep_temperature(ref, S, temps, 1000, 4000, 0, 10)
     for a, b in zip(rows, orows):
-        ok, d, tol = _agree(a, b)
-        print(f"T={a['T']}: gpu {a['m_abs']:.4f}+-{a['m_abs_se']:.4f} oracle {b['m_abs']:.4f}+-{b['m_abs_se']:.4f}")
+        ok, d, tol = _agree(a, b, precision)
+        print(f"T={a['T']}: gpu {a['m_abs']:.4f}+-{a['m_abs_se']:.4f} oracle {b['m_abs']:.4f}+-{b['m_abs_se']:.4f} "
+              f"|d m_abs| {d:.2e} |d E|/|E| {abs(a['E'] - b['E']) / abs(b['E']):.2e}")
         assert ok, (a["T"], d, tol)
-        ok, d, tol = _agree(a, b, "E", "E_se")
-        assert abs(a["E"] - b["E"]) <= 4 * np.hypot(a["E_se"], b["E_se"]) + 2e-3 * abs(b["E"])
+        ok, d, tol = _agree(a, b, precision, "E", "E_se")
+        assert ok, (a["T"], d, tol)
     m = [r["m_abs"] for r in rows]
     assert all(x > y for x, y in zip(m, m[1:]))   # magnetisation falls with temperature
     assert m[0] > 0.9 and m[-1] < 0.3             # ordered at 100 K, disordered at 1300 K
@@ -53,7 +59,9 @@ def test_particle_field_sweep_matches_oracle(precision):
     S = w.S0.copy()
     orows, _ = oracle.sweep_field(ref, S, fields, 500, 1000, 0, 10)
     for a, b in zip(rows, orows):
-        assert abs(a["m"][2] - b["m"][2]) <= 4 * np.hypot(a["m_abs_se"], b["m_abs_se"]) + 2e-3
+        d = abs(a["m"][2] - b["m"][2])
+        print(f"H={a['H'][2]}: gpu m_z {a['m'][2]:.5f} oracle {b['m'][2]:.5f} (se {a['m_abs_se']:.1e})")
+        assert d <= (1e-8 if precision == sl.FP64 else 3 * np.hypot(a["m_abs_se"], b["m_abs_se"]))
     # saturated along the first field; at 10 K the particle stays nearly
     # collinear.  (A point is 0.15 ps here, far shorter than one precession
     # period at 5 T, so no switching is expected.)

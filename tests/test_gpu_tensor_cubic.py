@@ -14,7 +14,7 @@ import pytest
 import oracle
 import paper_1310_6143_amd as sl
 from spin_systems import bcc_block, fcc_nanoparticle, sc_reference, with_tensor_exchange
-from tests.gpu_util import max_angle, mean_angle
+from tests.gpu_util import max_angle, mean_angle, parity_report
 from tests.test_oracle_tensor_cubic import _ring, _spiral, _turn_angles
 
 pytestmark = pytest.mark.gpu
@@ -51,23 +51,21 @@ def test_bcc_dmi_cubic_fp64_matches_oracle(stencil):
     w = _bcc_dmi()
     S_ref, m_ref, E_ref = _oracle_run(w, 1000)
     S, m, E = _gpu_run(w, 1000, sl.FP64, stencil=stencil)
-    ang = max_angle(S, S_ref)
-    print(f"bcc DMI + cubic FP64 stencil={stencil}: max angle {ang:.3e}")
-    assert ang <= 1e-9
-    assert np.abs(m - m_ref).max() <= 1e-10
-    assert np.abs(E - E_ref).max() <= 1e-10 * np.abs(E_ref).max()
+    r = parity_report(f"bcc DMI + cubic FP64 stencil={stencil} 1000 steps", S, S_ref, m, m_ref, E, E_ref)
+    assert r["max"] <= 1e-13 and r["dm"] <= 1e-12 and r["dE"] <= 1e-13   # measured 3.1e-15, 5.4e-14, 6.7e-15
 
 
 def test_bcc_dmi_cubic_fp32_within_stated_bound():
     w = _bcc_dmi()
     S_ref, m_ref, E_ref = _oracle_run(w, 1000)
     S, m, E = _gpu_run(w, 1000, sl.FP32)
+    parity_report("bcc DMI + cubic FP32 1000 steps", S, S_ref, m, m_ref, E, E_ref)
     amax, amean = max_angle(S, S_ref), mean_angle(S, S_ref)
     dm = np.abs(m - m_ref).max()
     dE = (np.abs(E - E_ref) / np.abs(E_ref)).max()
-    print(f"bcc DMI + cubic FP32: max angle {amax:.3e}, mean {amean:.3e}, |dm| {dm:.3e}, |dE/E| {dE:.3e}")
-    assert amax <= 2e-3 and amean <= 2e-4
-    assert dm <= 1e-4 and dE <= 1e-4
+    # measured 9.9e-7, 2.9e-7, 4.7e-8, 3.4e-8
+    assert amax <= 1e-5 and amean <= 5e-6
+    assert dm <= 5e-7 and dE <= 5e-7
 
 
 def test_sphere_interfacial_dmi_per_site_cubic_fp64():
@@ -80,12 +78,12 @@ def test_sphere_interfacial_dmi_per_site_cubic_fp64():
     S_ref, m_ref, E_ref = _oracle_run(w, 1000)
     for stencil in (1, 0):
         S, m, E = _gpu_run(w, 1000, sl.FP64, stencil=stencil)
-        ang = max_angle(S, S_ref)
-        print(f"sphere DMI FP64 stencil={stencil}: max angle {ang:.3e}")
-        assert ang <= 1e-9
-        assert np.abs(m - m_ref).max() <= 1e-10
-    S32, m32, _ = _gpu_run(w, 1000, sl.FP32)
-    assert max_angle(S32, S_ref) <= 2e-3 and np.abs(m32 - m_ref).max() <= 1e-4
+        r = parity_report(f"sphere DMI FP64 stencil={stencil} 1000 steps", S, S_ref, m, m_ref, E, E_ref)
+        assert r["max"] <= 5e-13 and r["dm"] <= 1e-13 and r["dE"] <= 1e-13   # measured 3.3e-14, 2.6e-15, 5.7e-15
+    S32, m32, E32 = _gpu_run(w, 1000, sl.FP32)
+    r = parity_report("sphere DMI FP32 1000 steps", S32, S_ref, m32, m_ref, E32, E_ref)
+    assert r["max"] <= 1e-4 and r["mean"] <= 1e-5                       # measured 9.3e-6, 7.1e-7
+    assert r["dm"] <= 2e-6 and r["dE"] <= 1e-6                          # measured 1.3e-7, 9.8e-8
 
 
 def test_isotropic_tensors_match_the_scalar_path():
@@ -138,12 +136,14 @@ def test_full_size_block_with_dmi_and_cubic():
     w = with_tensor_exchange(bcc_block(cells=160, n_steps=3), D=(1.2e-21, 0.5e-21), dmi="bulk", k_c=4e-24)
     w = _tilted(w, 11, 0.1)
     S_ref, m_ref, E_ref = _oracle_run(w, 3)
-    for prec, ang_tol, rec_tol in ((sl.FP64, 1e-10, 1e-9), (sl.FP32, 1e-5, 1e-6)):
+    # measured: FP64 3.4e-16 rad, |dm| 1.2e-11, |dE|/|E| 2.3e-13; FP32 4.5e-6
+    # rad at one site, |dm| and |dE|/|E| 3.6e-9
+    for prec, ang_tol, rec_tol in ((sl.FP64, 1e-13, 1e-10), (sl.FP32, 1e-5, 5e-8)):
         with sl.from_workload(w, precision=prec, check_symmetry=False) as g:
             m, E = g.integrate(3)
             S = g.get_spins()
-        ang = max_angle(S, S_ref)
-        print(f"full block DMI {'FP32' if prec == sl.FP32 else 'FP64'}: max angle {ang:.2e}")
+        ang = parity_report(f"full block DMI {'FP32' if prec == sl.FP32 else 'FP64'} 3 steps", S, S_ref, m, m_ref,
+                            E, E_ref)["max"]
         assert ang <= ang_tol
         assert np.abs(m - m_ref).max() <= rec_tol
         assert np.abs(E - E_ref).max() <= rec_tol * np.abs(E_ref).max()
