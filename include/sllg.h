@@ -341,6 +341,20 @@ sllg_status sllg_autotune(sllg_system *sys, int trial_steps, double *us_per_step
 sllg_status sllg_thermal_normals(int device, sllg_precision precision, uint64_t seed, uint64_t step,
                                  int64_t n, double *out);
 
+/* sllg_thermal_normals without device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same normals, bit for bit, staged in a fixed
+ * scratch of 2^18 sites (6 MiB) that the library holds on every device it
+ * has run this call on until the process ends, instead of a buffer
+ * allocated per call.  1 <= n <= 2^18 (SLLG_E_ARG beyond, with the reason
+ * in sllg_last_error(NULL)).  Runs on the device's null stream and copies
+ * to the host array out[3n] before returning.  Calls that overlap on one
+ * device share its scratch and race; calls on different devices do not.
+ * Nothing in the scratch needs clearing: each call writes every value it
+ * reads back. */
+sllg_status sllg_thermal_normals_noalloc(int device, sllg_precision precision, uint64_t seed, uint64_t step,
+                                         int64_t n, double *out);
+
 /* ---------------------------------------------------------------------------
  * Checkpoint / resume.  The state is the spins, the noise seed, the step
  * counter and, with a demagnetising field on, the field held since its last

@@ -28,7 +28,7 @@ EXPORTS = [
     "sllg_demag_field", "sllg_set_integrator", "sllg_set_conditions", "sllg_set_rng",
     "sllg_get_step", "sllg_set_spins", "sllg_get_spins", "sllg_integrate", "sllg_integrate_dev",
     "sllg_measure", "sllg_average", "sllg_sweep_temperature", "sllg_sweep_field",
-    "sllg_max_torque", "sllg_relax", "sllg_hysteresis", "sllg_thermal_normals", "sllg_autotune", "sllg_mc", "sllg_mc_average", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
+    "sllg_max_torque", "sllg_relax", "sllg_hysteresis", "sllg_thermal_normals", "sllg_thermal_normals_noalloc", "sllg_autotune", "sllg_mc", "sllg_mc_average", "sllg_checkpoint_size", "sllg_checkpoint", "sllg_restore",
     "sllg_set_option", "sllg_get_option",
     "sllg_server_create", "sllg_server_destroy", "sllg_server_last_error", "sllg_submit",
     "sllg_poll", "sllg_wait", "sllg_fetch", "sllg_cancel", "sllg_release", "sllg_server_get_stats",
@@ -114,6 +114,7 @@ def lib():
         "sllg_sweep_temperature": (c, [P, P, I64, I64, I64, c, P, P]),
         "sllg_sweep_field": (c, [P, P, I64, I64, I64, c, P, P]),
         "sllg_thermal_normals": (c, [c, c, U64, U64, I64, P]),
+        "sllg_thermal_normals_noalloc": (c, [c, c, U64, U64, I64, P]),
         "sllg_autotune": (c, [P, c, ctypes.POINTER(D), P]),
         "sllg_mc": (c, [P, I64, P, P, P, P]),
         "sllg_mc_average": (c, [P, I64, I64, c, P, P]),
@@ -176,6 +177,16 @@ def thermal_normals(seed, step, n, precision=FP64, device=0):
     st = lib().sllg_thermal_normals(device, precision, int(seed), int(step), int(n), _ptr(out))
     if st != 0:
         raise SllgError(st, "thermal_normals failed")
+    return out
+
+
+def thermal_normals_noalloc(seed, step, n, precision=FP64, device=0):
+    """thermal_normals through the entry point that allocates no device
+    memory (sllg_thermal_normals_noalloc; n <= 2^18)."""
+    out = np.empty((n, 3), dtype=np.float64)
+    st = lib().sllg_thermal_normals_noalloc(device, precision, int(seed), int(step), int(n), _ptr(out))
+    if st != 0:
+        raise SllgError(st, lib().sllg_last_error(None).decode())
     return out
 
 

@@ -1376,6 +1376,36 @@ sllg_status sllg_thermal_normals(int device, sllg_precision precision, uint64_t 
     return e == hipSuccess ? SLLG_OK : SLLG_E_DEVICE;
 }
 
+sllg_status sllg_thermal_normals_noalloc(int device, sllg_precision precision, uint64_t seed, uint64_t step,
+                                         int64_t n, double* out)
+{
+    if (!out || n < 1 || (precision != SLLG_FP32 && precision != SLLG_FP64)) {
+        g_create_error = "out must not be NULL, n >= 1, precision SLLG_FP32 or SLLG_FP64";
+        return SLLG_E_ARG;
+    }
+    if (n > kNoAllocMaxSites) {
+        g_create_error = "n exceeds the no-allocation scratch (" + std::to_string(kNoAllocMaxSites) + " sites)";
+        return SLLG_E_ARG;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return SLLG_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess)
+        return SLLG_E_DEVICE;
+    void* scratch = nullptr;
+    size_t bytes = 0;
+    if (noalloc_scratch(device, &scratch, &bytes) != hipSuccess || bytes < 3 * (size_t)n * sizeof(double)) {
+        g_create_error = "no-allocation scratch unavailable on this device";
+        return SLLG_E_DEVICE;
+    }
+    double* d = static_cast<double*>(scratch);
+    hipError_t e = precision == SLLG_FP32 ? launch_noise<float>(seed, step, (int)n, d, nullptr)
+                                          : launch_noise<double>(seed, step, (int)n, d, nullptr);
+    if (e == hipSuccess)
+        e = hipMemcpy(out, d, 3 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost);
+    return e == hipSuccess ? SLLG_OK : SLLG_E_DEVICE;
+}
+
 sllg_status sllg_set_option(sllg_system* sys, const char* key, int64_t value)
 {
     return guard(sys, [&] {

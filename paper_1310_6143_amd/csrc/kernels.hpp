@@ -40,6 +40,12 @@ hipError_t launch_advance(ReplicaDev<R>* reps, int n_rep, hipStream_t st);
 template <typename R>
 hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStream_t st);
 
+// Sites the fixed no-allocation scratch holds (3 doubles each).
+constexpr int64_t kNoAllocMaxSites = int64_t(1) << 18;
+// Device address and size of the fixed scratch on `device`, looked up once
+// per device (with that device current) and kept until the process ends.
+hipError_t noalloc_scratch(int device, void** ptr, size_t* bytes);
+
 // Largest torque |S_i x H_i| (deterministic field) of the current state of
 // each replica, over the tiles listed in `work` (grid workgroups), into
 // out[q] for q < n_rep.  Every tile of a replica with tiles must be listed.
