@@ -409,9 +409,11 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *   "fused_tile_x", "fused_tile_y", "fused_planes", "fused_threads"
  *                     shape of the fused step's work items: a tile of
  *                     tile_x x tile_y cell columns marched through `planes`
- *                     planes by a workgroup of `threads` (256, 512 or 640)
- *                     threads, which needs (tile_x + 2)(tile_y + 2) <=
- *                     threads and tile_x, tile_y >= 6; takes effect once all
+ *                     planes by a workgroup of `threads` (256, 512, or 1024
+ *                     for the simple-cubic and bcc kinds) threads, which
+ *                     needs (tile_x + 2)(tile_y + 2) <= threads, tile_x,
+ *                     tile_y >= 6 and the planes' LDS within the device's
+ *                     limit per workgroup; takes effect once all
  *                     four are set (0 returns to the library's choice; the
  *                     autotuner also picks among shapes).  Results do not
  *                     depend on the shape except the m and E records, at FP64

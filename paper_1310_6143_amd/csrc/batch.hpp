@@ -161,13 +161,13 @@ inline int fused_plane_bytes(const FusedShape& f, int nb)
 // kFusedMinPlanes planes (all of them on thinner lattices).
 inline bool fused_shape_ok(const FusedShape& f, const HostLattice& L, size_t lds_limit)
 {
-    if (!fused_block_ok(f.bt) || f.px < kFusedMinEdge || f.py < kFusedMinEdge || f.px > 0x7FFF || f.py > 0x7FFF ||
+    if (!fused_block_ok(L.kind, f.bt) || f.px < kFusedMinEdge || f.py < kFusedMinEdge || f.px > 0x7FFF || f.py > 0x7FFF ||
         (int64_t)f.px * f.py > f.bt || f.planes < std::min(kFusedMinPlanes, L.nz))
         return false;
     const int64_t slots = (int64_t)(f.px + 2) * (f.py + 2) * L.nb;
     if ((slots + 63) / 64 > 3 * (f.bt / 64))
         return false;
-    return fused_lds_bytes(L.kind, fused_plane_bytes(f, L.nb), f.bt) <= lds_limit;
+    return fused_lds_bytes(L.kind, fused_plane_bytes(f, L.nb), f.bt) + fused_static_lds(f.bt) <= lds_limit;
 }
 
 // Work items of a lattice for a shape.
@@ -181,8 +181,9 @@ inline int64_t fused_items(const HostLattice& L, const FusedShape& f)
 // the model's choice).  resident(f) gives the workgroups the device holds
 // at once for shape f.  The planes per item are chosen so that the items
 // fill whole rounds of the resident workgroups; the model counts
-// wave-instructions of one item (predictor on planes + 2, corrector on
-// planes, plane copies on planes + 4) times rounds.
+// wave-instructions of one item (predictor on planes + 2 on every wave,
+// corrector on planes on the waves that hold tile cells, plane copies on
+// planes + 4) times rounds.
 template <typename Resident>
 inline std::vector<FusedShape> fused_candidates(const HostLattice& L, size_t lds_limit, Resident&& resident,
                                                 int max_count)
@@ -192,7 +193,7 @@ inline std::vector<FusedShape> fused_candidates(const HostLattice& L, size_t lds
         FusedShape f;
     };
     std::vector<Scored> all;
-    for (int bt : {256, 512}) {
+    for (int bt : {256, 512, 1024}) {
         for (int px = kFusedMinEdge; px <= 64; ++px)
             for (int py = kFusedMinEdge; py <= bt / kFusedMinEdge; ++py) {
                 FusedShape f{px, py, std::min(kFusedMinPlanes, L.nz), bt};
@@ -203,7 +204,9 @@ inline std::vector<FusedShape> fused_candidates(const HostLattice& L, size_t lds
                     continue;
                 const int R = std::max(resident(f), 1);
                 const int64_t cols = (int64_t)((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty);
-                const int waves = (px * py + 63) / 64;
+                // predictor phases on every wave; the corrector phases only
+                // on waves that hold tile cells (the tile's threads come first)
+                const int waves = (px * py + 63) / 64, tile_waves = (tx * ty + 63) / 64;
                 for (int segs = 1; segs <= L.nz; ++segs) {
                     const int planes = (L.nz + segs - 1) / segs;
                     if (planes < std::min(kFusedMinPlanes, L.nz))
@@ -211,7 +214,7 @@ inline std::vector<FusedShape> fused_candidates(const HostLattice& L, size_t lds
                     if (segs > 1 && (L.nz + segs - 2) / (segs - 1) == planes)
                         continue;   // the same planes as fewer segments
                     const int64_t items = cols * ((L.nz + planes - 1) / planes);
-                    const double item = waves * ((planes + 2) * 1.0 + planes * 0.6 + (planes + 4) * 0.25);
+                    const double item = waves * ((planes + 2) * 1.0 + (planes + 4) * 0.25) + tile_waves * planes * 0.4;
                     const double rounds = std::ceil((double)items / R);
                     f.planes = planes;
                     all.push_back({rounds * item * R, f});
@@ -688,7 +691,7 @@ public:
     // of the compute units.
     int fused_resident(const HostLattice& L, const FusedShape& f)
     {
-        const int key = (L.kind * 4 + L.nb) * 2 + (f.bt == 512 ? 1 : 0);
+        const int key = ((L.kind * 4 + L.nb) * 4) + (f.bt >> 8);
         auto it = fused_occ_.find(key);
         if (it == fused_occ_.end())
             it = fused_occ_.emplace(key, fused_resident_blocks<float>(device_, L.kind, L.nb, f.bt, 16)).first;
@@ -698,7 +701,7 @@ public:
         if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device_) != hipSuccess ||
             lds_cu <= 0)
             lds_cu = 160 * 1024;
-        const size_t per_wg = fused_lds_bytes(L.kind, fused_plane_bytes(f, L.nb), f.bt) + 1024;
+        const size_t per_wg = fused_lds_bytes(L.kind, fused_plane_bytes(f, L.nb), f.bt) + fused_static_lds(f.bt);
         const int by_lds = (int)std::max<size_t>(1, (size_t)lds_cu / per_wg);
         const int by_regs = std::max(1, it->second / cus);
         return cus * std::min(by_lds, by_regs);

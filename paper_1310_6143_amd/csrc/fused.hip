@@ -116,25 +116,28 @@ __device__ __forceinline__ int wrap_cell(int u, int n)
     return m < 0 ? m + n : m;
 }
 
-// m and E terms of one site (in units of mu_ref) added to v: mu_s/mu_ref S
-// and mu_s/mu_ref (-E_i/mu_s) with -E_i/mu_s = S.H_ex/2 + (k_u/mu_s)(S.e)^2
-// + S.H_app.  Written out operation by operation so that the step and the
-// measuring launch round alike.
-template <typename R>
-__device__ __forceinline__ void record_terms(const MaterialDev<R>& m, const V3<R>& s, const V3<R>& hex,
-                                             const V3<R>& e, const V3<R>& Happ, double* acc)
+// m and E terms of one site added to the thread's sums: S and -E_i/mu_s =
+// S.H_ex/2 + (k_u/mu_s)(S.e)^2 + S.H_app, with se = S.e as the predictor
+// forms it.  A replica takes the fused step only with one material, so
+// mu_s is the reference moment and every site weighs 1.  Written with
+// explicit fmas so that the step and the measuring launch round alike.
+template <int BT, typename R>
+__device__ __forceinline__ void record_terms(const MaterialDev<R>& m, const V3<R>& s, R se, const V3<R>& hex,
+                                             const V3<R>& Happ, double* acc)
 {
-#pragma clang fp contract(off)
-    const R se = s.x * e.x + s.y * e.y + s.z * e.z;
-    const R sh = s.x * hex.x + s.y * hex.y + s.z * hex.z;
-    const R sa = s.x * Happ.x + s.y * Happ.y + s.z * Happ.z;
-    const R u = (R)0.5 * sh + m.ku_mu * se * se + sa;
-    const double t[4] = {(double)(m.mu_frac * s.x), (double)(m.mu_frac * s.y), (double)(m.mu_frac * s.z),
-                         (double)(m.mu_frac * u)};
-    // the thread's own FP64 sums in LDS (acc[c * BT]), added in plane order
+    const R sh = fma(s.z, hex.z, fma(s.y, hex.y, s.x * hex.x));
+    const R sa = fma(s.z, Happ.z, fma(s.y, Happ.y, s.x * Happ.x));
+    const R u = fma((R)0.5, sh, fma(m.ku_mu * se, se, sa));
+    const double t[4] = {(double)s.x, (double)s.y, (double)s.z, (double)u};
+    // the thread's own FP64 sums in LDS (acc[c * BT]), added in plane order;
+    // constant offsets let the four read-modify-writes overlap
+    double a[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-        acc[c * blockDim.x] += t[c];
+        a[c] = acc[c * BT];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        acc[c * BT] = a[c] + t[c];
 }
 
 // x, y, z of the LDS slot at p (the fourth word is never read): a 12-byte
@@ -284,7 +287,7 @@ template <typename R, int NB>
 struct ColumnState {
     V3<R> hp[2][NB];              // predictor sums of plane p in slot p & 1
     V3<R> hc[2][NB];              // corrector sums of plane p in slot p & 1
-    V3<R> c_sp[2][NB], c_base[2][NB], c_th[2][NB];   // S', S + dS dt / 2, thermal field of plane p
+    V3<R> c_sp[2][NB], c_base[2][NB], c_th[2][NB];   // S', S + dS dt / 2, thermal + applied field of plane p
 };
 
 // Fixed facts of an item for its plane iterations.
@@ -346,23 +349,26 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        // B: predictor of plane q - 1
+        // B: predictor of plane q - 1 (one material: the exchange field is
+        // the sum itself)
         if (g.live && zp_need) {
             const V3<R> s = slot_xyz<R>(nxt + g.own(b));
-            const V3<R> hex{m.mu_rel * cs.hp[S1][b].x, m.mu_rel * cs.hp[S1][b].y, m.mu_rel * cs.hp[S1][b].z};
+            const V3<R>& hex = cs.hp[S1][b];
+            const R se = fma(s.z, e.z, fma(s.y, e.y, s.x * e.x));
             if (run.partials && g.interior && zp_own)
-                record_terms(m, s, hex, e, Happ, acc);
+                record_terms<BT>(m, s, se, hex, Happ, acc);
             if (!MEASURE) {
-                const R se = dot(s, e);
                 R gn[3] = {0, 0, 0};
                 if (m.sigma != (R)0)
                     thermal_normals(r.seed, run.step, g.col + (uint32_t)b + g.plane_sites * (uint32_t)zw_m1, gn);
-                const V3<R> th{m.sigma * gn[0], m.sigma * gn[1], m.sigma * gn[2]};
-                const V3<R> h{hex.x + m.ani * se * e.x + Happ.x + th.x, hex.y + m.ani * se * e.y + Happ.y + th.y,
-                              hex.z + m.ani * se * e.z + Happ.z + th.z};
+                // thermal plus applied field, held for the corrector
+                const V3<R> tha{fma(m.sigma, gn[0], Happ.x), fma(m.sigma, gn[1], Happ.y),
+                                fma(m.sigma, gn[2], Happ.z)};
+                const R as = m.ani * se;
+                const V3<R> h{fma(as, e.x, hex.x) + tha.x, fma(as, e.y, hex.y) + tha.y, fma(as, e.z, hex.z) + tha.z};
                 const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
                 const V3<R> spn = normalised(V3<R>{s.x + ds.x, s.y + ds.y, s.z + ds.z});
-                cs.c_th[S1][b] = th;
+                cs.c_th[S1][b] = tha;
                 cs.c_sp[S1][b] = spn;
                 cs.c_base[S1][b] = V3<R>{s.x + (R)0.5 * ds.x, s.y + (R)0.5 * ds.y, s.z + (R)0.5 * ds.z};
                 *reinterpret_cast<Slot4<R>*>(sp + g.own(b)) = Slot4<R>{spn.x, spn.y, spn.z, (R)0};
@@ -374,7 +380,9 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
     // S(q + 1) into the other S plane
     if (q + 1 <= z1 + 1) {
         const bool exists = zper || (q + 1 >= 0 && q + 1 < nz);
-        const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+        // the wave number as a scalar: the chunk addresses below are then
+        // computed on the scalar unit when needed, not held in registers
+        const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
 #pragma unroll
         for (int j = 0; j < kChunksPerWave; ++j) {
             const int c = wave + j * (BT / 64);
@@ -419,14 +427,14 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
             // E: corrector of plane q - 2
             if (zc_own) {
                 const V3<R> s = cs.c_sp[S0][b];
-                const R se = dot(s, e);
-                const V3<R> h{m.mu_rel * cs.hc[S0][b].x + m.ani * se * e.x + Happ.x + cs.c_th[S0][b].x,
-                              m.mu_rel * cs.hc[S0][b].y + m.ani * se * e.y + Happ.y + cs.c_th[S0][b].y,
-                              m.mu_rel * cs.hc[S0][b].z + m.ani * se * e.z + Happ.z + cs.c_th[S0][b].z};
-                const V3<R> ds = llg_step(s, h, r.gdt, r.alpha);
-                const V3<R> sn = normalised(V3<R>{cs.c_base[S0][b].x + (R)0.5 * ds.x,
-                                                  cs.c_base[S0][b].y + (R)0.5 * ds.y,
-                                                  cs.c_base[S0][b].z + (R)0.5 * ds.z});
+                const R as = m.ani * dot(s, e);
+                const V3<R> h{fma(as, e.x, cs.hc[S0][b].x) + cs.c_th[S0][b].x,
+                              fma(as, e.y, cs.hc[S0][b].y) + cs.c_th[S0][b].y,
+                              fma(as, e.z, cs.hc[S0][b].z) + cs.c_th[S0][b].z};
+                // half the step's dS' dt (a step of dt / 2: the halving is exact)
+                const V3<R> dsh = llg_step(s, h, (R)0.5 * r.gdt, r.alpha);
+                const V3<R> sn = normalised(V3<R>{cs.c_base[S0][b].x + dsh.x, cs.c_base[S0][b].y + dsh.y,
+                                                  cs.c_base[S0][b].z + dsh.z});
                 store3(run.Sn, (int64_t)(g.col + (uint32_t)b + g.plane_sites * (uint32_t)zw_m2), sn);
             }
             cs.hc[S0][b] = down[b];
@@ -446,9 +454,27 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
     const int t = (int)threadIdx.x;
     ItemGeo<NB> g;
     g.live = t < PX * PY;
-    const int py = t / PX, px = t - py * PX;
+    // Threads of the tile first (row by row), then the ring (bottom row, top
+    // row, left column, right column): the waves of the ring alone skip the
+    // corrector phases as a whole.
+    const int TX = PX - 2, inner = TX * (PY - 2);
+    int px = 0, py = 0;
+    if (t < inner) {
+        py = 1 + t / TX;
+        px = 1 + t - (py - 1) * TX;
+    } else if (g.live) {
+        int k = t - inner;
+        if (k < 2 * PX) {
+            py = k < PX ? 0 : PY - 1;
+            px = k < PX ? k : k - PX;
+        } else {
+            k -= 2 * PX;
+            px = k < PY - 2 ? 0 : PX - 1;
+            py = 1 + (k < PY - 2 ? k : k - (PY - 2));
+        }
+    }
     const int ux = w.x0 - 1 + px, uy = w.y0 - 1 + py;   // cell, before wrapping
-    g.interior = g.live && px >= 1 && px <= PX - 2 && py >= 1 && py <= PY - 2 && ux < nx && uy < ny;
+    g.interior = t < inner && ux < nx && uy < ny;
     g.col = (uint32_t)NB * (uint32_t)(wrap_cell(ux, nx) + nx * wrap_cell(uy, ny));
     g.plane_sites = (uint32_t)NB * (uint32_t)nx * (uint32_t)ny;
 #pragma unroll
@@ -638,10 +664,13 @@ const void* fused_kernel(int kind, int nb, int bt, bool measure)
         return fused_ptr<R, K_, NB_, BT_>(measure);
     SLLG_FUSED_CASE(kKindSc6, 1, 256)
     SLLG_FUSED_CASE(kKindSc6, 1, 512)
+    SLLG_FUSED_CASE(kKindSc6, 1, 1024)
     SLLG_FUSED_CASE(kKindBcc8, 2, 256)
     SLLG_FUSED_CASE(kKindBcc8, 2, 512)
+    SLLG_FUSED_CASE(kKindBcc8, 2, 1024)
     SLLG_FUSED_CASE(kKindBcc14, 2, 256)
     SLLG_FUSED_CASE(kKindBcc14, 2, 512)
+    SLLG_FUSED_CASE(kKindBcc14, 2, 1024)
     SLLG_FUSED_CASE(kKindGeneric, 1, 256)
     SLLG_FUSED_CASE(kKindGeneric, 1, 512)
     SLLG_FUSED_CASE(kKindGeneric, 2, 256)
@@ -652,7 +681,13 @@ const void* fused_kernel(int kind, int nb, int bt, bool measure)
 
 }  // namespace
 
-bool fused_block_ok(int bt) { return bt == 256 || bt == 512; }
+bool fused_block_ok(int kind, int bt) { return bt == 256 || bt == 512 || (bt == 1024 && kind != kKindGeneric); }
+
+size_t fused_static_lds(int bt)
+{
+    // acc, dcol and red of k_fused
+    return (size_t)bt * (4 * sizeof(double) + kChunksPerWave * sizeof(uint32_t)) + 4 * (size_t)(bt / 64) * sizeof(double);
+}
 
 size_t fused_lds_bytes(int kind, int plane_bytes, int bt)
 {

@@ -89,9 +89,13 @@ hipError_t launch_fused_finish(const ReplicaDev<R>* reps, int n_rep, hipStream_t
 // plane_bytes LDS planes; 0 if unknown.
 template <typename R>
 int fused_resident_blocks(int device, int kind, int nb, int bt, int plane_bytes);
-bool fused_block_ok(int bt);
+// Whether a fused kernel of this kind and block size is built.
+bool fused_block_ok(int kind, int bt);
 // Dynamic LDS of a fused workgroup with planes of plane_bytes.
 size_t fused_lds_bytes(int kind, int plane_bytes, int bt);
+// Static LDS of a fused workgroup of bt threads (its FP64 sums, copy table
+// and reduction slots).
+size_t fused_static_lds(int bt);
 // LDS one workgroup may take on the device.
 size_t fused_lds_limit(int device);
 

@@ -115,7 +115,7 @@ def test_spins_independent_of_shape(make):
     w = make()
     w.temperature = 400.0
     shapes = [(6, 6, 4, 256), (14, 14, 10, 256), (30, 14, 7, 512), (20, 20, 16, 512), (62, 6, 5, 512),
-              (40, 10, 64, 512)]
+              (40, 10, 64, 512), (30, 30, 9, 1024), (40, 22, 16, 1024)]
     ref = None
     for shp in shapes:
         S, m, E = _run(w, 20, shape=shp)
