@@ -29,8 +29,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "spin-steps/s (Heun sLLG) FP32 vs FP64 at 1 GPU; p50/p99 latency of batched sweeps"
 HBM_PEAK_GBS = 8000.0
-COUNTER_FILE = os.path.join(ROOT, "profiles", "bcc160_step_hbm_counters.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_1310_6143_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1310_6143_amd", "csrc")
+# committed rocprofv3 counter summaries, each tied to the sources of the
+# kernels it measured (and, for the fused step, to the work-item shape)
+COUNTER_FILES = {
+    "two_launch": (os.path.join(ROOT, "profiles", "bcc160_step_hbm_counters.md"),
+                   ["kernels.hip", "device_common.hpp"]),
+    "fused": (os.path.join(ROOT, "profiles", "bcc160_fused_step_counters.md"),
+              ["fused.hip", "device_common.hpp"]),
+}
 
 
 def log(msg):
@@ -44,27 +51,29 @@ def algorithmic_bytes_per_spin_step(w_bytes, mean_degree):
     return 6 * w_bytes + 4 + 4 * mean_degree
 
 
-def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_hash(kind):
+    h = hashlib.sha256()
+    for name in COUNTER_FILES[kind][1]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def profile_value(key):
-    """A machine-readable value of the committed rocprofv3 counter summary,
-    or None when it is missing or the kernels changed since it was taken."""
-    if not os.path.exists(COUNTER_FILE):
+def profile_value(kind, key, shape=None):
+    """A machine-readable value of the committed rocprofv3 counter summary
+    of `kind`, or None when it is missing, the kernels changed since it was
+    taken, or (fused step) it was taken at another work-item shape."""
+    path = COUNTER_FILES[kind][0]
+    if not os.path.exists(path):
         return None
-    text = open(COUNTER_FILE).read()
+    text = open(path).read()
     h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
-    v = re.search(rf"{key}:\s*([0-9.eE+]+)", text)
-    if not h or not v or h.group(1) != kernel_hash():
+    if shape is not None:    # values per work-item shape: key[tx,ty,planes,threads]
+        key = re.escape(f"{key}[{','.join(str(x) for x in shape)}]")
+    v = re.search(rf"^{key}:\s*([0-9.eE+]+)", text, re.M)
+    if not h or not v or h.group(1) != kernel_hash(kind):
         return None
     return float(v.group(1))
-
-
-def measured_traffic(precision):
-    """HBM bytes per spin-step from the committed counter summary (or None)."""
-    return profile_value(f"{precision}_hbm_bytes_per_step")
 
 
 def run_gpu(w, precision, steps, warmup, torch, launch=None, autotune=False, fused=1, fused_shape=None):
@@ -576,7 +585,10 @@ def main():
     value = n * args.steps / (r32["ms"] / 1e3)
     b_alg = algorithmic_bytes_per_spin_step(4, deg)
     achieved = b_alg * n / (ms_step / 1e3) / 1e9
-    traffic = None if (dmi or lr) else measured_traffic("fp32")
+    fused_on = bool(r32["launch"].get("fused"))
+    kind = "fused" if fused_on else "two_launch"
+    shape = r32["launch"].get("fused_shape") if fused_on else None
+    traffic = None if (dmi or lr) else profile_value(kind, "fp32_hbm_bytes_per_step", shape)
     out = {
         "metric": METRIC,
         "value": value,
@@ -610,12 +622,15 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None if traffic is None else traffic * n,
-            "kernel": "Heun step (predictor + corrector launches)",
+            "kernel": ("fused Heun step k_fused (one launch per step)" if fused_on else
+                       "Heun step (predictor + corrector launches)"),
             "algorithmic_bytes_per_spin_step": b_alg,
             "traffic_GBs": None if traffic is None else traffic * n / (ms_step / 1e3) / 1e9,
             "traffic_frac": None if traffic is None else traffic * n / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "valu_busy": None if (dmi or lr) else {"predictor": profile_value("fp32_predictor_valu_busy"),
-                                                   "corrector": profile_value("fp32_corrector_valu_busy")},
+            "valu_busy": None if (dmi or lr) else (
+                {"k_fused": profile_value("fused", "fp32_fused_valu_busy", shape)} if fused_on else
+                {"predictor": profile_value("two_launch", "fp32_predictor_valu_busy"),
+                 "corrector": profile_value("two_launch", "fp32_corrector_valu_busy")}),
         },
     }
     if lr:

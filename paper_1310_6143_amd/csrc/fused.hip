@@ -116,28 +116,36 @@ __device__ __forceinline__ int wrap_cell(int u, int n)
     return m < 0 ? m + n : m;
 }
 
-// m and E terms of one site added to the thread's sums: S and -E_i/mu_s =
-// S.H_ex/2 + (k_u/mu_s)(S.e)^2 + S.H_app, with se = S.e as the predictor
-// forms it.  A replica takes the fused step only with one material, so
-// mu_s is the reference moment and every site weighs 1.  Written with
-// explicit fmas so that the step and the measuring launch round alike.
-template <int BT, typename R>
+// m and E terms of one site: S and -E_i/mu_s = S.H_ex/2 + (k_u/mu_s)(S.e)^2
+// + S.H_app, with se = S.e as the predictor forms it.  A replica takes the
+// fused step only with one material, so mu_s is the reference moment and
+// every site weighs 1.  Written with explicit fmas so that the step and the
+// measuring launch round alike.
+template <typename R>
 __device__ __forceinline__ void record_terms(const MaterialDev<R>& m, const V3<R>& s, R se, const V3<R>& hex,
-                                             const V3<R>& Happ, double* acc)
+                                             const V3<R>& Happ, R t[4])
 {
     const R sh = fma(s.z, hex.z, fma(s.y, hex.y, s.x * hex.x));
     const R sa = fma(s.z, Happ.z, fma(s.y, Happ.y, s.x * Happ.x));
-    const R u = fma((R)0.5, sh, fma(m.ku_mu * se, se, sa));
-    const double t[4] = {(double)s.x, (double)s.y, (double)s.z, (double)u};
-    // the thread's own FP64 sums in LDS (acc[c * BT]), added in plane order;
-    // constant offsets let the four read-modify-writes overlap
+    t[0] = s.x;
+    t[1] = s.y;
+    t[2] = s.z;
+    t[3] = fma((R)0.5, sh, fma(m.ku_mu * se, se, sa));
+}
+
+// The terms of one cell (its basis sites added in FP32, in basis order)
+// into the thread's own FP64 sums in LDS (acc[c * BT]), added in plane
+// order; constant offsets let the four read-modify-writes overlap.
+template <int BT, typename R>
+__device__ __forceinline__ void record_add(const R t[4], double* acc)
+{
     double a[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
         a[c] = acc[c * BT];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-        acc[c * BT] = a[c] + t[c];
+        acc[c * BT] = a[c] + (double)t[c];
 }
 
 // x, y, z of the LDS slot at p (the fourth word is never read): a 12-byte
@@ -347,16 +355,28 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
             }
         }
     }
+    // B: m and E terms of plane q - 1 (its exchange sums are complete; one
+    // material: the exchange field is the sum itself), then its predictor
+    if (run.partials && g.interior && zp_need && zp_own) {
+        R tc[4];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const V3<R> s = slot_xyz<R>(nxt + g.own(b));
+            const R se = fma(s.z, e.z, fma(s.y, e.y, s.x * e.x));
+            R t[4];
+            record_terms(m, s, se, cs.hp[S1][b], Happ, t);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                tc[c] = b == 0 ? t[c] : tc[c] + t[c];
+        }
+        record_add<BT>(tc, acc);
+    }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        // B: predictor of plane q - 1 (one material: the exchange field is
-        // the sum itself)
         if (g.live && zp_need) {
             const V3<R> s = slot_xyz<R>(nxt + g.own(b));
             const V3<R>& hex = cs.hp[S1][b];
             const R se = fma(s.z, e.z, fma(s.y, e.y, s.x * e.x));
-            if (run.partials && g.interior && zp_own)
-                record_terms<BT>(m, s, se, hex, Happ, acc);
             if (!MEASURE) {
                 R gn[3] = {0, 0, 0};
                 if (m.sigma != (R)0)
