@@ -87,6 +87,13 @@ def run_gpu(w, precision, steps, warmup, torch, launch=None, autotune=False, fus
             sysm.set_option(key, v)
     log(f"precision {'fp32' if precision == sl.FP32 else 'fp64'}: set-up {time.time() - t0:.1f} s")
     st = torch.cuda.Stream()
+    # device buffers first, so that nothing allocates (and leaves the GPU
+    # idle) between the autotuner's trial steps, the warmup and the timing
+    m_w = torch.empty((max(warmup, 1), 3), dtype=torch.float64, device="cuda")
+    E_w = torch.empty(max(warmup, 1), dtype=torch.float64, device="cuda")
+    m_dev = torch.empty((steps, 3), dtype=torch.float64, device="cuda")
+    E_dev = torch.empty(steps, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
     if launch:
         sysm.set_option("xcd_remap", launch[0])
         sysm.set_option("grid_scale_pct", launch[1])
@@ -99,10 +106,6 @@ def run_gpu(w, precision, steps, warmup, torch, launch=None, autotune=False, fus
         log(f"  autotune: {tuned_us:.1f} us/step with {choice}")
     else:   # the library's default launch shape (the one the counter summary was taken at)
         choice = {k: sysm.get_option(k) for k in ("xcd_remap", "grid_scale_pct", "graph_steps", "tile_order")}
-    m_w = torch.empty((max(warmup, 1), 3), dtype=torch.float64, device="cuda")
-    E_w = torch.empty(max(warmup, 1), dtype=torch.float64, device="cuda")
-    m_dev = torch.empty((steps, 3), dtype=torch.float64, device="cuda")
-    E_dev = torch.empty(steps, dtype=torch.float64, device="cuda")
     if warmup:
         sysm.integrate_dev(warmup, m_w, E_w, stream=st)
     st.synchronize()
@@ -463,23 +466,48 @@ def sweep_main(args):
     print(json.dumps(out))
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo where there is one)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(w, n_steps):
+    """The FP64 oracle on one host thread: a bounded sample of the benchmark
+    block (n_steps steps of every spin, records every step), and the whole
+    4096-spin simple-cubic reference run (1000 steps at 300 K)."""
     import oracle
+    from spin_systems import sc_reference
 
     sysm = oracle.System(w)
     S = np.ascontiguousarray(w.S0.copy())
     t0 = time.perf_counter()
     sysm.integrate(S, 0, n_steps, record=True)
     dt = time.perf_counter() - t0
+    ref = sc_reference(L=16, temperature=300.0, n_steps=1000, seed=42)
+    S_ref = np.ascontiguousarray(ref.S0.copy())
+    t1 = time.perf_counter()
+    oracle.System(ref).integrate(S_ref, 0, 1000, record=True)
+    dt_ref = time.perf_counter() - t1
+    model = cpu_model()
     return {
         "value": w.n * n_steps / dt,
         "unit": "spin-steps/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"{n_steps} Heun steps (with per-step m and E) of the full {w.n}-spin block, "
-                  f"FP64 oracle on one thread of {platform.processor() or platform.machine()} "
-                  f"({os.cpu_count()} host threads)",
+                  f"FP64 oracle on one thread of {model} ({os.cpu_count()} host threads)",
         "seconds": dt,
+        "cpu_model": model,
+        "sc4096_1000_steps": {"seconds": dt_ref, "spin_steps_per_s": ref.n * 1000 / dt_ref,
+                              "run": "simple-cubic 16^3 = 4096 spins, T = 300 K, seed 42, 1000 Heun steps "
+                                     "with per-step m and E, the whole run"},
     }
 
 
@@ -493,7 +521,7 @@ def main():
     ap.add_argument("--only-fp64", action="store_true", help="time only the FP64 run (profiling)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-budget", type=int, default=16384, help="MiB")
     ap.add_argument("--serving-chunk", type=int, default=64)

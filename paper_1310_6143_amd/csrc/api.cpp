@@ -65,6 +65,7 @@ struct Engine {
     virtual int parity() = 0;
     virtual void set_parity(int p) = 0;
     virtual void mark_dirty() = 0;           // the record mirror changed
+    virtual void mark_scalars_dirty() = 0;   // only its step count or record flags changed
     virtual uint64_t step() = 0;
     virtual void set_step(uint64_t step) = 0;
     virtual int64_t rec_cap() = 0;
@@ -147,6 +148,7 @@ struct EngineT final : Engine {
         batch.mark_dirty();
     }
     void mark_dirty() override { batch.mark_dirty(); }
+    void mark_scalars_dirty() override { batch.mark_scalars_dirty(); }
     uint64_t step() override { return batch.mirror(q).step; }
     void set_step(uint64_t step) override
     {
@@ -359,7 +361,7 @@ void run_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, do
     if (flags != *r.flags || *r.rec_pos != 0) {
         *r.flags = flags;
         *r.rec_pos = 0;
-        e.mark_dirty();
+        e.mark_scalars_dirty();
     }
     int64_t done = 0;
     bool bad = false;
@@ -368,7 +370,7 @@ void run_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, do
         if (*r.nsteps != (int32_t)ns || *r.flags != flags) {
             *r.nsteps = (int32_t)ns;
             *r.flags = flags;
-            e.mark_dirty();
+            e.mark_scalars_dirty();
         }
         const bool use_graph = G > 0 && ns == G;
         e.run_chunk((int)(use_graph ? G : ns), st, use_graph);

@@ -357,6 +357,10 @@ public:
         hip_check(hipMalloc(&d_nwork_, sizeof(int)), "hipMalloc(nwork)");
         hip_check(hipMemset(d_nwork_, 0, sizeof(int)), "hipMemset");
         host_reps_.resize(max_replicas);
+        // pinned staging of the replica table: its per-chunk upload is then a
+        // plain DMA on the work stream
+        hip_check(hipHostMalloc((void**)&pinned_reps_, sizeof(ReplicaDev<R>) * (size_t)max_replicas),
+                  "hipHostMalloc(reps)");
         for (int v = 0; v < 3; ++v) {
             int& res = resident_v_[v];
             res = resident_blocks<R>(device_, v);
@@ -389,6 +393,7 @@ public:
         (void)hipFree(d_nwork_);
         (void)hipFree(d_torque_work_);
         (void)hipFree(d_torque_);
+        (void)hipHostFree(pinned_reps_);
     }
 
     Batch(const Batch&) = delete;
@@ -408,7 +413,17 @@ public:
     int capacity() const { return (int)slots_.size(); }
     Slot& slot(int q) { return slots_[q]; }
     ReplicaDev<R>& mirror(int q) { return slots_[q].rec; }
-    void mark_dirty() { dirty_ = true; }
+    // The replica set, shapes or launch options changed: the work lists are
+    // rebuilt at the next launch, and the replica table uploaded.
+    void mark_dirty()
+    {
+        dirty_ = true;
+        lists_dirty_ = true;
+    }
+    // Only scalar fields of the replica table changed (step counts, record
+    // flags): the next launch uploads the table and keeps the lists, unless
+    // the set of replicas that run changed.
+    void mark_scalars_dirty() { dirty_ = true; }
 
     // Allocate and fill the buffers of a new replica; returns its slot.
     int add(const HostStructure& s, const HostMaterials& m, const Dynamics& d,
@@ -587,7 +602,7 @@ public:
             sl = Slot{};
             throw;
         }
-        dirty_ = true;
+        mark_dirty();
         return q;
     }
 
@@ -600,7 +615,7 @@ public:
         for (void* p : sl.mem)
             alloc_->release(p);
         sl = Slot{};
-        dirty_ = true;
+        mark_dirty();
     }
 
     void upload_materials(int q, const HostMaterials& m, const Dynamics& d)
@@ -659,7 +674,7 @@ public:
         if ((int64_t)sl.f_items.size() > sl.f_cap_items)
             fail(SLLG_E_STATE, "fused work items exceed their buffer");
         r.f_items = idx;
-        dirty_ = true;
+        mark_dirty();
     }
 
     // Shape of replica q's fused step (fused_shape_ok).
@@ -683,7 +698,7 @@ public:
     {
         if (on != fused_on_) {
             fused_on_ = on;
-            dirty_ = true;
+            mark_dirty();
         }
     }
     // Workgroups of the fused kernel the device holds at once for lattice L
@@ -743,7 +758,10 @@ public:
     }
 
     // Upload the replica records and the work list when something changed.
-    void sync_tables()
+    // Bring the device tables up to date before a launch.  With a stream,
+    // the replica table goes up as an asynchronous copy on it (from pinned
+    // memory, which the next call reuses only after quiesce()).
+    void sync_tables(hipStream_t st = nullptr)
     {
         if (!dirty_)
             return;
@@ -761,6 +779,38 @@ public:
                 ((r.flags & kAverage) && (!(r.flags & kRecord) || !r.acc)))
                 fail(SLLG_E_STATE, "replica flags do not match its buffers");
         }
+        for (size_t q = 0; q < slots_.size(); ++q) {
+            host_reps_[q] = slots_[q].used ? slots_[q].rec : ReplicaDev<R>{};
+            if (slots_[q].used && !window_)
+                host_reps_[q].flags |= kDirect;
+            if (!slots_[q].used)
+                host_reps_[q].nsteps = 0;
+        }
+        // the work lists hold the replicas that run: rebuilt when that set changed
+        std::vector<char> active(slots_.size());
+        for (size_t q = 0; q < slots_.size(); ++q)
+            active[q] = slots_[q].used && slots_[q].rec.nsteps > 0;
+        if (active != active_)
+            lists_dirty_ = true;
+        if (lists_dirty_)
+            build_lists();
+        active_ = active;
+        lists_dirty_ = false;
+        const size_t bytes = sizeof(ReplicaDev<R>) * host_reps_.size();
+        if (st) {
+            std::memcpy(pinned_reps_, host_reps_.data(), bytes);
+            hip_check(hipMemcpyAsync(d_reps_, pinned_reps_, bytes, hipMemcpyHostToDevice, st), "upload replicas");
+            last_stream_ = st;
+        } else {
+            hip_check(hipMemcpy(d_reps_, host_reps_.data(), bytes, hipMemcpyHostToDevice), "upload replicas");
+        }
+        dirty_ = false;
+    }
+
+    // The launch variant, the two-launch work list and the fused item list of
+    // the replicas that run, uploaded.
+    void build_lists()
+    {
         // kernel variant: 1 when any replica has per-site data, 2 when any
         // has exchange tensors or cubic anisotropy
         int variant = 0;
@@ -776,19 +826,6 @@ public:
             drop_graph();
         variant_ = variant;
         resident_ = resident_v_[variant_];
-        work_.clear();
-        for (size_t q = 0; q < slots_.size(); ++q) {
-            host_reps_[q] = slots_[q].used ? slots_[q].rec : ReplicaDev<R>{};
-            if (slots_[q].used && !window_)
-                host_reps_[q].flags |= kDirect;
-            if (!slots_[q].used)
-                host_reps_[q].nsteps = 0;
-            if (slots_[q].used && slots_[q].rec.nsteps > 0)
-                for (int32_t b : tile_order(slots_[q].rec.blocks, order_ ? slots_[q].plane_tiles : 0,
-                                            group_ > 0 ? group_
-                                                       : balanced_group(slots_[q].plane_tiles, slots_[q].rec.tile)))
-                    work_.push_back(WorkItem{(int32_t)q, b});
-        }
         // fused step: every replica of the batch can take it, with one block
         // size and one number of sites per cell
         bool fused = fused_on_ && sizeof(R) == 4;
@@ -806,6 +843,14 @@ public:
             f_kind = sl.lat.kind;
             f_plane = std::max(f_plane, fused_plane_bytes(sl.fshape, sl.lat.nb));
         }
+        // two-launch tiles (the Monte Carlo records take them in fused mode too)
+        work_.clear();
+        for (size_t q = 0; q < slots_.size(); ++q)
+                if (slots_[q].used && slots_[q].rec.nsteps > 0)
+                    for (int32_t b : tile_order(slots_[q].rec.blocks, order_ ? slots_[q].plane_tiles : 0,
+                                                group_ > 0 ? group_
+                                                           : balanced_group(slots_[q].plane_tiles, slots_[q].rec.tile)))
+                        work_.push_back(WorkItem{(int32_t)q, b});
         fwork_.clear();
         if (fused)
             for (size_t q = 0; q < slots_.size(); ++q)
@@ -870,10 +915,6 @@ public:
             hip_check(hipMemcpy(d_work_, work_.data(), sizeof(WorkItem) * work_.size(), hipMemcpyHostToDevice),
                       "upload work");
         hip_check(hipMemcpy(d_nwork_, &nwork, sizeof(int), hipMemcpyHostToDevice), "upload nwork");
-        hip_check(hipMemcpy(d_reps_, host_reps_.data(), sizeof(ReplicaDev<R>) * host_reps_.size(),
-                            hipMemcpyHostToDevice),
-                  "upload replicas");
-        dirty_ = false;
     }
 
     // Run one chunk of K launch steps; replica q advances mirror(q).nsteps
@@ -881,7 +922,7 @@ public:
     // (K, grid) and replayed.
     void run_chunk(int K, hipStream_t st, bool use_graph)
     {
-        sync_tables();
+        sync_tables(st);
         last_stream_ = st;
         if (grid_ > 0) {
             if (use_graph) {
@@ -1063,7 +1104,7 @@ public:
     {
         if (on != window_) {
             window_ = on;
-            dirty_ = true;
+            mark_dirty();
         }
     }
     // Tile listing: 0 in site order, 1 plane-swept column groups of
@@ -1074,7 +1115,7 @@ public:
         if (order != order_ || group != group_) {
             order_ = order;
             group_ = group;
-            dirty_ = true;
+            mark_dirty();
         }
     }
     void set_round_grid(bool v) { round_grid_ = v; }
@@ -1085,7 +1126,7 @@ public:
     {
         if (f != grid_scale_) {
             grid_scale_ = f;
-            dirty_ = true;
+            mark_dirty();
         }
     }
     double grid_scale() const { return grid_scale_; }
@@ -1120,12 +1161,8 @@ private:
             if (e == hipSuccess)
                 e = launch_fused<float>((const ReplicaDev<float>*)d_reps_, d_fwork_, nf, fgrid_, 0, remap_, true,
                                         fused_kind_, fused_nb_, fused_bt_, fused_plane_, st);
-            if (e == hipSuccess)
-                e = launch_fused_finish<float>((const ReplicaDev<float>*)d_reps_, nrep, st);
-            if (e == hipSuccess)
-                e = launch_accumulate<R>(d_reps_, nrep, st);
-            if (e == hipSuccess)
-                e = launch_advance<R>(d_reps_, nrep, st);
+            if (e == hipSuccess)   // records, averaging sums and the advance
+                e = launch_fused_finish<float>((ReplicaDev<float>*)d_reps_, nrep, st);
             return e;
         }
         for (int k = 0; k < K && e == hipSuccess; ++k) {
@@ -1157,6 +1194,9 @@ private:
     Allocator* alloc_;
     std::vector<Slot> slots_;
     std::vector<ReplicaDev<R>> host_reps_;
+    ReplicaDev<R>* pinned_reps_ = nullptr;   // pinned staging of host_reps_
+    std::vector<char> active_;               // replicas in the current work lists (used, nsteps > 0)
+    bool lists_dirty_ = true;
     std::vector<WorkItem> work_;
     ReplicaDev<R>* d_reps_ = nullptr;
     WorkItem* d_work_ = nullptr;

@@ -303,6 +303,44 @@ __device__ __forceinline__ MaterialDev<R> uniform_material(const ReplicaDev<R>& 
     return m;
 }
 
+// End of a chunk for one replica (one thread): the averaging block sums of
+// the chunk's records (kAverage), then the step counter, buffer parity and
+// record position advance by the chunk's steps.
+template <typename R>
+__device__ inline void accumulate_records(const ReplicaDev<R>& r)
+{
+    if (r.nsteps <= 0 || !(r.flags & kAverage))
+        return;
+    for (int t = 0; t < r.nsteps; ++t) {
+        const int64_t sample = (int64_t)(r.step + (uint64_t)t) - r.avg_first;
+        if (sample < 0)
+            continue;
+        const int64_t b = sample / r.avg_block_len;
+        if (b >= r.avg_blocks)
+            break;
+        const double* rec = r.records + 4 * (r.rec_pos + t);
+        const double mx = rec[0], my = rec[1], mz = rec[2];
+        double* a = r.acc + 5 * b;
+        a[0] += sqrt(mx * mx + my * my + mz * mz);
+        a[1] += mx;
+        a[2] += my;
+        a[3] += mz;
+        a[4] += rec[3];
+    }
+}
+
+template <typename R>
+__device__ inline void advance_replica(ReplicaDev<R>& r)
+{
+    const int ns = r.nsteps;
+    if (ns > 0) {
+        r.step += (uint64_t)ns;
+        r.parity = (r.parity + ns) & 1;
+        if (r.flags & kRecordSeries)
+            r.rec_pos += ns;
+    }
+}
+
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 

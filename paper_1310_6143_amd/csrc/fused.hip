@@ -36,7 +36,10 @@
 // its exchange field, so each item leaves FP64 sums of m and E of that
 // state for its own sites; the first item of a replica in the launch of
 // step k + 1 adds the items' sums (a fixed order) into record k - 1; a
-// measuring launch and k_fused_finish complete the last two of a chunk.
+// measuring launch (the same plane walk without predictor and corrector,
+// its third LDS plane holding a third S plane so that each plane's copy
+// overlaps the work on the previous ones) and k_fused_finish complete the
+// last two of a chunk.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -148,17 +151,15 @@ __device__ __forceinline__ void record_add(const R t[4], double* acc)
         acc[c * BT] = a[c] + (double)t[c];
 }
 
-// x, y, z of the LDS slot at p (the fourth word is never read): a 12-byte
-// read, so a value held for later takes three registers, not four.
-template <typename R>
-struct __attribute__((packed, aligned(sizeof(R)))) Xyz {
-    R x, y, z;
-};
-
+// x, y, z of the LDS slot at p (the fourth word is never read).  The slot
+// is read through its 16-byte-aligned type, so the compiler emits one
+// 12-byte LDS read (ds_read_b96) for the three words it uses; through a
+// 4-byte-aligned 12-byte type it splits the read into two or three
+// instructions, which cost the step a fifth of its time.
 template <typename R>
 __device__ __forceinline__ V3<R> slot_xyz(const char* p)
 {
-    const Xyz<R> v = *reinterpret_cast<const Xyz<R>*>(p);
+    const Slot4<R> v = *reinterpret_cast<const Slot4<R>*>(p);
     return V3<R>{v.x, v.y, v.z};
 }
 
@@ -338,6 +339,39 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
     const bool zp_exists = zper || (zp >= 0 && zp < nz);
     const bool zp_need = zp >= z0 - 1 && zp <= z1 && zp_exists;
     const bool zp_own = zp >= z0 && zp < z1;
+    // Issue the copy of S(q + 1) into the LDS plane dst: direct
+    // global-to-LDS loads of 16 bytes per site, or zeros beyond an open
+    // surface; nothing past the item's last needed plane.  The next barrier
+    // completes it.
+    auto copy_next = [&](char* __restrict__ dst) {
+        if (q + 1 > z1 + 1)
+            return;
+        const bool exists = zper || (q + 1 >= 0 && q + 1 < nz);
+        // the wave number as a scalar: the chunk addresses below are then
+        // computed on the scalar unit when needed, not held in registers
+        const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
+#pragma unroll
+        for (int j = 0; j < kChunksPerWave; ++j) {
+            const int c = wave + j * (BT / 64);
+            if (c >= run.n_chunks)
+                break;   // uniform over the wave
+            char* d = dst + c * 64 * 16;
+            const uint32_t dc = run.dcol[j * BT + (int)threadIdx.x];
+            if (dc != 0xFFFFFFFFu) {
+                if (exists) {
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        run.rsrc, (lds_ptr)d, 16, (int)dc,
+                        (int)(g.plane_sites * 3u * (uint32_t)sizeof(R) * (uint32_t)zw_p1), 0, 0);
+                } else {
+                    reinterpret_cast<Slot4<R>*>(d)[lane] = Slot4<R>{0, 0, 0, 0};
+                }
+            }
+        }
+    };
+    // The measuring launch holds three S planes (it has no S'): S(q + 1)
+    // streams into the free one while S(q) and S(q - 1) are worked on.
+    if constexpr (MEASURE)
+        copy_next(sp);
     // A: links from S(q) into planes q - 1 (completing it), q and q + 1
     V3<R> up[NB];   // plane q + 1's first sums, moved into the slot of q - 1 after B
 #pragma unroll
@@ -396,32 +430,15 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
         }
         cs.hp[S1][b] = up[b];
     }
+    if constexpr (MEASURE) {
+        // S(q + 1) went into the third plane at the start of the step
+        __syncthreads();   // S(q + 1) complete; every thread is done with S(q - 1)
+        return;
+    }
     __syncthreads();   // S'(q - 1) complete; every thread is done with S(q) and S(q - 1)
     // S(q + 1) into the other S plane
-    if (q + 1 <= z1 + 1) {
-        const bool exists = zper || (q + 1 >= 0 && q + 1 < nz);
-        // the wave number as a scalar: the chunk addresses below are then
-        // computed on the scalar unit when needed, not held in registers
-        const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
-#pragma unroll
-        for (int j = 0; j < kChunksPerWave; ++j) {
-            const int c = wave + j * (BT / 64);
-            if (c >= run.n_chunks)
-                break;   // uniform over the wave
-            char* d = nxt + c * 64 * 16;
-            const uint32_t dc = run.dcol[j * BT + (int)threadIdx.x];
-            if (dc != 0xFFFFFFFFu) {
-                if (exists) {
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(run.rsrc, (lds_ptr)d, 16, (int)dc,
-                                                             (int)(g.plane_sites * 3u * (uint32_t)sizeof(R) * (uint32_t)zw_p1),
-                                                             0, 0);
-                } else {
-                    reinterpret_cast<Slot4<R>*>(d)[lane] = Slot4<R>{0, 0, 0, 0};
-                }
-            }
-        }
-    }
-    if (!MEASURE && g.interior) {
+    copy_next(nxt);
+    if (g.interior) {
         const int zc = q - 2;
         const bool zc_own = zc >= z0 && zc < z1 && (zper || (zc >= 0 && zc < nz));
         // D: links from S'(q - 1) into planes q - 2 (completing it), q - 1 and
@@ -569,21 +586,46 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
         }
     }
     __syncthreads();
-    for (int q = z0 - 2; q <= z1 + 1; q += 2) {
-        plane_step<R, KIND, NB, BT, MEASURE, 0>(r, g, run, cs, planes[0], planes[1], sp, acc, pat, ent, q, zw_m2,
-                                                zw_m1, zw_p1, m);
+    auto next_plane = [&] {
         zw_m2 = zw_m1;
         zw_m1 = zw_0;
         zw_0 = zw_p1;
         zw_p1 = zper ? (zw_p1 + 1 == nz ? 0 : zw_p1 + 1) : zw_p1 + 1;
-        if (q + 1 > z1 + 1)
-            break;
-        plane_step<R, KIND, NB, BT, MEASURE, 1>(r, g, run, cs, planes[1], planes[0], sp, acc, pat, ent, q + 1, zw_m2,
-                                                zw_m1, zw_p1, m);
-        zw_m2 = zw_m1;
-        zw_m1 = zw_0;
-        zw_0 = zw_p1;
-        zw_p1 = zper ? (zw_p1 + 1 == nz ? 0 : zw_p1 + 1) : zw_p1 + 1;
+    };
+    if constexpr (MEASURE) {
+        // three S planes in turn: S(q), S(q - 1), and the one S(q + 1) goes to
+        char* cur = planes[0];
+        char* prev = sp;   // S(z0 - 3): never read
+        char* free_plane = planes[1];
+        auto rotate = [&] {
+            char* t = prev;
+            prev = cur;
+            cur = free_plane;
+            free_plane = t;
+        };
+        for (int q = z0 - 2; q <= z1 + 1; q += 2) {
+            plane_step<R, KIND, NB, BT, MEASURE, 0>(r, g, run, cs, cur, prev, free_plane, acc, pat, ent, q, zw_m2,
+                                                    zw_m1, zw_p1, m);
+            rotate();
+            next_plane();
+            if (q + 1 > z1 + 1)
+                break;
+            plane_step<R, KIND, NB, BT, MEASURE, 1>(r, g, run, cs, cur, prev, free_plane, acc, pat, ent, q + 1,
+                                                    zw_m2, zw_m1, zw_p1, m);
+            rotate();
+            next_plane();
+        }
+    } else {
+        for (int q = z0 - 2; q <= z1 + 1; q += 2) {
+            plane_step<R, KIND, NB, BT, MEASURE, 0>(r, g, run, cs, planes[0], planes[1], sp, acc, pat, ent, q, zw_m2,
+                                                    zw_m1, zw_p1, m);
+            next_plane();
+            if (q + 1 > z1 + 1)
+                break;
+            plane_step<R, KIND, NB, BT, MEASURE, 1>(r, g, run, cs, planes[1], planes[0], sp, acc, pat, ent, q + 1,
+                                                    zw_m2, zw_m1, zw_p1, m);
+            next_plane();
+        }
     }
     if (run.partials) {
         const int lane = t & 63, wave = t >> 6;
@@ -655,18 +697,27 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(SLLG_FUSED_W
     }
 }
 
-// After the measuring launch: the last two records of the chunk, one
-// workgroup per replica.
+// After the measuring launch, one workgroup per replica: the last two
+// records of the chunk, the averaging sums of its records, then the step
+// counter, parity and record position advance (one launch for the chunk's
+// end instead of three).
 template <typename R>
-__global__ __launch_bounds__(256) void k_fused_finish(const ReplicaDev<R>* __restrict__ reps)
+__global__ __launch_bounds__(256) void k_fused_finish(ReplicaDev<R>* __restrict__ reps)
 {
     __shared__ double red[4][4];
-    const ReplicaDev<R>& r = reps[blockIdx.x];
-    if (!(r.flags & kFused) || !(r.flags & kRecord) || r.nsteps <= 0)
-        return;
-    if (r.nsteps >= 2)
-        fused_record<R, 256>(r, (r.nsteps - 1) & 1, r.nsteps - 2, red);
-    fused_record<R, 256>(r, r.nsteps & 1, r.nsteps - 1, red);
+    ReplicaDev<R>& r = reps[blockIdx.x];
+    if (r.nsteps <= 0)
+        return;   // uniform over the block
+    if ((r.flags & kFused) && (r.flags & kRecord)) {
+        if (r.nsteps >= 2)
+            fused_record<R, 256>(r, (r.nsteps - 1) & 1, r.nsteps - 2, red);
+        fused_record<R, 256>(r, r.nsteps & 1, r.nsteps - 1, red);
+    }
+    // thread 0 wrote the records (fused_record) and reads them back here
+    if (threadIdx.x == 0) {
+        accumulate_records(r);
+        advance_replica(r);
+    }
 }
 
 template <typename R, int KIND, int NB, int BT>
@@ -733,7 +784,7 @@ hipError_t launch_fused(const ReplicaDev<R>* reps, const FusedItem* items, const
 }
 
 template <typename R>
-hipError_t launch_fused_finish(const ReplicaDev<R>* reps, int n_rep, hipStream_t st)
+hipError_t launch_fused_finish(ReplicaDev<R>* reps, int n_rep, hipStream_t st)
 {
     if (n_rep <= 0)
         return hipSuccess;
@@ -765,7 +816,7 @@ size_t fused_lds_limit(int device)
 
 template hipError_t launch_fused<float>(const ReplicaDev<float>*, const FusedItem*, const int*, int, int, int, bool,
                                         int, int, int, int, hipStream_t);
-template hipError_t launch_fused_finish<float>(const ReplicaDev<float>*, int, hipStream_t);
+template hipError_t launch_fused_finish<float>(ReplicaDev<float>*, int, hipStream_t);
 template int fused_resident_blocks<float>(int, int, int, int, int);
 
 }  // namespace sllg

@@ -968,15 +968,8 @@ template <typename R>
 __global__ void k_advance(ReplicaDev<R>* __restrict__ reps, int n_rep)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n_rep) {
-        const int ns = reps[j].nsteps;
-        if (ns > 0) {
-            reps[j].step += (uint64_t)ns;
-            reps[j].parity = (reps[j].parity + ns) & 1;
-            if (reps[j].flags & kRecordSeries)
-                reps[j].rec_pos += ns;
-        }
-    }
+    if (j < n_rep)
+        advance_replica(reps[j]);
 }
 
 template <typename R>
@@ -1140,27 +1133,8 @@ template <typename R>
 __global__ void k_accumulate(const ReplicaDev<R>* __restrict__ reps, int n_rep)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_rep)
-        return;
-    const ReplicaDev<R>& r = reps[j];
-    if (r.nsteps <= 0 || !(r.flags & kAverage))
-        return;
-    for (int t = 0; t < r.nsteps; ++t) {
-        const int64_t sample = (int64_t)(r.step + (uint64_t)t) - r.avg_first;
-        if (sample < 0)
-            continue;
-        const int64_t b = sample / r.avg_block_len;
-        if (b >= r.avg_blocks)
-            break;
-        const double* rec = r.records + 4 * (r.rec_pos + t);
-        const double mx = rec[0], my = rec[1], mz = rec[2];
-        double* a = r.acc + 5 * b;
-        a[0] += sqrt(mx * mx + my * my + mz * mz);
-        a[1] += mx;
-        a[2] += my;
-        a[3] += mz;
-        a[4] += rec[3];
-    }
+    if (j < n_rep)
+        accumulate_records(reps[j]);
 }
 
 }  // namespace

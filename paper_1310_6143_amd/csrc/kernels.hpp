@@ -82,9 +82,11 @@ hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, 
 template <typename R>
 hipError_t launch_fused(const ReplicaDev<R>* reps, const FusedItem* items, const int* n_items, int grid, int k,
                         int remap, bool measure, int kind, int nb, int bt, int plane_bytes, hipStream_t st);
-// The chunk's last two records of every fused recording replica.
+// The end of a fused chunk for every replica: its last two records (when
+// recording), the averaging sums of its records, and the advance of the
+// step counter, parity and record position.
 template <typename R>
-hipError_t launch_fused_finish(const ReplicaDev<R>* reps, int n_rep, hipStream_t st);
+hipError_t launch_fused_finish(ReplicaDev<R>* reps, int n_rep, hipStream_t st);
 // Resident workgroups of the fused kernel (kind, nb, bt) per device with
 // plane_bytes LDS planes; 0 if unknown.
 template <typename R>

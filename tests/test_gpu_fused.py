@@ -144,3 +144,25 @@ def test_fused_agrees_with_two_launch_step():
     assert ang <= 1e-4
     assert np.abs(mf - mt).max() <= 1e-6
     assert (np.abs(Ef - Et) / np.abs(Et)).max() <= 1e-6
+
+
+@pytest.mark.parametrize("lattice_cells", [16, 40])
+def test_shape_change_between_calls(lattice_cells):
+    """Changing the work-item shape between two calls (as the autotuner
+    does) must re-list the items: the spins then follow the same trajectory
+    as an untouched run, bit for bit."""
+    w = bcc_block(cells=lattice_cells, n_steps=30)
+    with _fused_system(w) as a, _fused_system(w) as b:
+        a.integrate(10, record=False)
+        for key, v in zip(("fused_tile_x", "fused_tile_y", "fused_planes", "fused_threads"), (14, 6, 5, 256)):
+            a.set_option(key, v)
+        assert a.get_option("fused_tile_x") == 14 and a.get_option("fused_threads") == 256
+        a.integrate(10, record=False)
+        # one field at a time, each intermediate shape valid
+        for key, v in (("fused_threads", 1024), ("fused_planes", 9), ("fused_tile_y", 30), ("fused_tile_x", 30)):
+            a.set_option(key, v)
+        ma, Ea = a.integrate(10)
+        b.integrate(20, record=False)
+        mb, Eb = b.integrate(10)
+        assert np.array_equal(a.get_spins(), b.get_spins())
+        assert np.allclose(ma, mb, rtol=0, atol=1e-12) and np.allclose(Ea, Eb, rtol=1e-12, atol=0)
