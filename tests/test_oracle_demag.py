@@ -126,3 +126,38 @@ def test_sampled_field_equals_the_full_update(orc):
     sites = rng.choice(w.n, 40, replace=False)
     assert np.array_equal(s.demag_sample(S, sites), H[sites])
     assert np.array_equal(s._demag_field, H)          # the held field is untouched
+
+
+def _platelet_centre_field(orc, cells_per_macrocell):
+    """Centre field (z component, tesla) of the bcc Fe platelet magnetised
+    along z: 70 x 70 x 4 unit cells (20.1 x 20.1 x 1.15 nm), a = 0.287 nm,
+    mu_s = 2.22 muB, macrocells of the given edge in unit cells; mean over
+    the 8 atoms nearest the platelet's centre."""
+    from spin_systems.lattice import bcc
+    a, mu = 0.287, 2.22 * MU_B
+    lat = bcc((70, 70, 4), (False, False, False))
+    w = with_demag(_wl(lat, mu=mu), a, cells_per_macrocell * a, every=1)
+    d = np.linalg.norm(lat.pos - np.array([34.75, 34.75, 1.75]), axis=1)   # the body's centre
+    sites = np.argsort(d, kind="stable")[:8]
+    H = orc.System(w).demag_sample(w.S0, sites)
+    return H[:, 2].mean(), 2 * mu / (a * 1e-9) ** 3
+
+
+def test_platelet_approaches_minus_mu0_M(orc):
+    """"Demagnetising field of a platelet": a thin perpendicularly magnetised
+    film has a centre field near -mu0 M (the paper: -2.236 T on a 20 x 20 x
+    1 nm platelet with macrocells of 2 unit cells, against -mu0 M = -2.18 T).
+    With macrocells of one unit cell the centre field is the continuum
+    prism's, -(2/pi) arctan(AB / (C sqrt(A^2 + B^2 + C^2))) mu0 M, within
+    0.1% (measured 0.005%); macrocells of two unit cells give a larger
+    magnitude (the coarse grid overestimates, as the paper notes: measured
+    -2.134 T, 2.8% above the continuum) within 5% of the paper's -2.236 T."""
+    H1, M = _platelet_centre_field(orc, 1)
+    A = B = 70 * 0.287 / 2
+    C = 4 * 0.287 / 2
+    exact = -(2 / np.pi) * np.arctan(A * B / (C * np.sqrt(A * A + B * B + C * C))) * MU0 * M
+    assert abs(H1 - exact) < 1e-3 * abs(exact), (H1, exact)
+    H2, _ = _platelet_centre_field(orc, 2)
+    assert H2 < H1 < 0
+    assert abs(H2 - (-2.236)) < 0.05 * 2.236, H2
+    assert abs(MU0 * M - 2.18) < 0.01 * 2.18    # the paper's -mu0 M for bcc Fe
