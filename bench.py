@@ -173,6 +173,9 @@ def run_serving(args):
         "total_spin_steps": total,
         "makespan_s": span,
         "chunks": int(stats["chunks"]),
+        "launch_tuning": {"compositions_tuned": int(stats["tuned_compositions"]),
+                          "last_shape": {"xcd_remap": int(stats["last_xcd_remap"]),
+                                         "tile_order": int(stats["last_tile_order"])}},
     }
 
 

@@ -318,18 +318,20 @@ sllg_status sllg_hysteresis(sllg_system *sys, const double *H, int64_t n_points,
  * keeps the fastest and writes its time per step (us) to *us_per_step (may
  * be NULL).  With the fused step active ("fused_active" 1) the candidates
  * are the eight fused shapes (tile, planes per item, threads per
- * workgroup) the occupancy and traffic model ranks best; otherwise the
- * two-launch step's shapes ("lds_window" 1 or 0; "tile_order" 1 or 0; XCD
- * mappings 0, 1, 2 of "xcd_remap"; 1/2, 1 or 2 resident grids of
- * workgroups per launch).  Systems under 2^20 spins also try 16, 64 or 256
- * steps per captured HIP graph.  The spins, the step counter, the held
- * demagnetising field and every result stay exactly as they were.  Launch
- * shapes do not change the arithmetic of a spin; with the fused step the
- * m and E records (FP64 sums of per-workgroup partial sums) may change at
- * FP64 rounding when the tile shape changes.  The choice can be read back
- * with sllg_get_option ("fused_tile_x", "fused_tile_y", "fused_planes",
- * "fused_threads"; "lds_window", "tile_order", "xcd_remap",
- * "grid_scale_pct"; "graph_steps", "tuned_ns_per_step").  Setting
+ * workgroup) the occupancy and traffic model ranks best; otherwise every
+ * tile size of the two-launch step ("tile_sites": 512, 1024, 2048 in FP32;
+ * 512, 1024 in FP64), each with its launch shapes ("lds_window" 1 or 0;
+ * "tile_order" 1 or 0; XCD mappings 0, 1, 2 of "xcd_remap"; 1/2, 1 or 2
+ * resident grids of workgroups per launch).  Systems under 2^20 spins also
+ * try 16, 64 or 256 steps per captured HIP graph.  The spins, the step
+ * counter, the held demagnetising field and every result stay exactly as
+ * they were.  Launch shapes do not change the arithmetic of a spin; the m
+ * and E records (FP64 sums of per-tile or per-workgroup partial sums) may
+ * change at FP64 rounding when the tile size or shape changes.  The choice
+ * can be read back with sllg_get_option ("fused_tile_x", "fused_tile_y",
+ * "fused_planes", "fused_threads"; "tile_sites", "lds_window",
+ * "tile_order", "xcd_remap", "grid_scale_pct"; "graph_steps",
+ * "tuned_ns_per_step").  Setting
  * SLLG_AUTOTUNE_LOG=1 in the environment prints every candidate's time to
  * stderr. */
 sllg_status sllg_autotune(sllg_system *sys, int trial_steps, double *us_per_step, void *stream);
@@ -403,9 +405,11 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     the list as per-site stencil patterns when at most 256
  *                     distinct (column - row, type) rows occur (<= 1024
  *                     entries in all); 0 keeps the general SELL-64 form
- *   "fused"           1 (default): integrate with the fused step whenever the
- *                     system qualifies (sllg_set_lattice); 0: always the
- *                     two-launch step
+ *   "fused"           1 (default): integrate with the fused step when the
+ *                     system qualifies (sllg_set_lattice) and has at least
+ *                     2^20 spins (smaller systems run faster with the
+ *                     two-launch step's shallow launches); 2: whenever it
+ *                     qualifies; 0: always the two-launch step
  *   "fused_tile_x", "fused_tile_y", "fused_planes", "fused_threads"
  *                     shape of the fused step's work items: a tile of
  *                     tile_x x tile_y cell columns marched through `planes`
@@ -486,6 +490,13 @@ typedef struct {
     double spin_steps;        /* total spin-steps integrated so far */
     double busy_seconds;      /* time with at least one active request */
     int64_t chunks;           /* batched chunk launches so far */
+    /* Launch-shape tuning: each new batch composition (requests that run and
+     * their total spins, each bucketed to the next power of two) times the
+     * XCD mappings 1, 0, 2 x tile orders 1, 0 on its chunks (results do not
+     * depend on them) and keeps the fastest. */
+    int64_t tuned_compositions;   /* compositions tuned so far */
+    int64_t last_xcd_remap;       /* launch shape of the last chunk */
+    int64_t last_tile_order;
 } sllg_server_stats;
 
 /* Start a server on `device`.  The server thread owns its own stream. */

@@ -73,7 +73,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", I64), ("completed", I64), ("failed", I64), ("cancelled", I64),
                 ("active", I64), ("queued", I64), ("hbm_in_use", ctypes.c_size_t),
                 ("hbm_budget", ctypes.c_size_t), ("spin_steps", D), ("busy_seconds", D),
-                ("chunks", I64)]
+                ("chunks", I64), ("tuned_compositions", I64), ("last_xcd_remap", I64),
+                ("last_tile_order", I64)]
 
 
 def lib():
@@ -323,7 +324,7 @@ class SpinSystem:
         if self.get_option("fused_active"):
             keys += ["fused_tile_x", "fused_tile_y", "fused_planes", "fused_threads"]
         else:
-            keys += ["xcd_remap", "grid_scale_pct", "tile_order", "lds_window"]
+            keys += ["tile_sites", "xcd_remap", "grid_scale_pct", "tile_order", "lds_window"]
         return us.value, {k: self.get_option(k) for k in keys}
 
     def set_demag(self, pos, cell_size, atom_volume, every):

@@ -938,6 +938,7 @@ public:
                     (void)hipGraphDestroy(g);
                     hip_check(e3, "graph instantiate");
                     graph_K_ = K;
+                    ++graph_captures_;
                 }
                 hip_check(hipGraphLaunch(graph_exec_, st), "graph launch");
             } else {
@@ -1098,6 +1099,8 @@ public:
         remap_ = v;
     }
     int remap() const { return remap_; }
+    // HIP graphs captured so far (a chunk that captured one also timed the capture)
+    int64_t graph_captures() const { return graph_captures_; }
     // Neighbour spins through the LDS tile window (default) or all straight
     // from global memory; results are the same bit for bit.
     void set_window(bool on)
@@ -1197,6 +1200,7 @@ private:
     ReplicaDev<R>* pinned_reps_ = nullptr;   // pinned staging of host_reps_
     std::vector<char> active_;               // replicas in the current work lists (used, nsteps > 0)
     bool lists_dirty_ = true;
+    int64_t graph_captures_ = 0;
     std::vector<WorkItem> work_;
     ReplicaDev<R>* d_reps_ = nullptr;
     WorkItem* d_work_ = nullptr;

@@ -61,6 +61,8 @@ struct ServerBase {
     virtual void harvest(Job& j, hipStream_t st, bool finished) = 0;
     virtual void retire(Job& j) = 0;
     virtual size_t in_use() = 0;
+    virtual void set_launch(int remap, int order) = 0;   // launch shape of the next chunks
+    virtual int64_t graph_captures() = 0;
 };
 
 template <typename R>
@@ -106,6 +108,12 @@ struct ServerT final : ServerBase {
         }
     }
     void run_chunk(int K, hipStream_t st) override { batch.run_chunk(K, st, true); }
+    void set_launch(int remap, int order) override
+    {
+        batch.set_remap(remap);
+        batch.set_tile_order(order, 0);
+    }
+    int64_t graph_captures() override { return batch.graph_captures(); }
     void harvest(Job& j, hipStream_t st, bool finished) override
     {
         (void)st;
@@ -172,6 +180,14 @@ struct sllg_server {
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
     sllg_server_stats stats{};
     std::string fatal;
+    // Launch-shape tuning per batch composition (kept for the server's life).
+    struct Tuning {
+        int next = 0;          // candidate timed next
+        int best = 0;
+        double best_time = 1e300;   // seconds per spin-step
+        bool done = false;
+    };
+    std::map<uint64_t, Tuning> tuning;
 
     double now() const
     {
@@ -180,6 +196,33 @@ struct sllg_server {
 };
 
 namespace {
+
+// Launch shapes the server tries for each batch composition: XCD mapping
+// of the tile ranges and tile order (the grid is always the resident one,
+// the tile the largest).  Results do not depend on them.
+struct LaunchShape {
+    int remap, order;
+};
+constexpr LaunchShape kServerShapes[] = {{1, 1}, {1, 0}, {0, 1}, {0, 0}, {2, 1}, {2, 0}};
+constexpr int kNumServerShapes = (int)(sizeof(kServerShapes) / sizeof(kServerShapes[0]));
+
+int ceil_log2(double x)
+{
+    int k = 0;
+    while (k < 62 && (double)(int64_t(1) << k) < x)
+        ++k;
+    return k;
+}
+
+// A batch composition, bucketed: the number of requests that run and their
+// total spins, each to the next power of two.
+uint64_t composition_key(const std::vector<Job*>& run)
+{
+    double sites = 0.0;
+    for (const Job* j : run)
+        sites += (double)j->n;
+    return ((uint64_t)ceil_log2((double)run.size()) << 8) | (uint64_t)ceil_log2(sites);
+}
 
 void finish(sllg_server* s, Job& j, int state, int status)
 {
@@ -255,16 +298,24 @@ void scheduler(sllg_server* s)
         if (run.empty())
             continue;
         // one chunk for every active replica; the lock is not held while the
-        // GPU works, so clients can submit, poll and cancel meanwhile
+        // GPU works, so clients can submit, poll and cancel meanwhile.  A new
+        // batch composition times each launch shape on its chunks (a chunk
+        // that captured a graph does not count) and then keeps the fastest.
+        sllg_server::Tuning& tune = s->tuning[composition_key(run)];
+        const int shape = tune.done ? tune.best : tune.next;
         const double t_begin = s->now();
         double spin_steps = 0.0;
+        bool captured = false;
         try {
+            s->impl->set_launch(kServerShapes[shape].remap, kServerShapes[shape].order);
             for (Job* j : run) {
                 s->impl->prepare_chunk(*j, K);
                 spin_steps += (double)j->n * (double)std::min<int64_t>(K, j->n_steps - j->steps_done);
             }
+            const int64_t captures = s->impl->graph_captures();
             s->impl->run_chunk(K, s->stream);
             hip_check(hipStreamSynchronize(s->stream), "chunk");
+            captured = s->impl->graph_captures() != captures;
         } catch (const Failure& f) {
             std::lock_guard<std::mutex> lk(s->mu);
             s->fatal = f.msg;
@@ -279,10 +330,25 @@ void scheduler(sllg_server* s)
             s->done_cv.notify_all();
             continue;
         }
+        const double t_chunk = s->now() - t_begin;
+        bool newly_tuned = false;
+        if (!tune.done && !captured && spin_steps > 0.0) {
+            const double per = t_chunk / spin_steps;
+            if (per < tune.best_time) {
+                tune.best_time = per;
+                tune.best = shape;
+            }
+            if (++tune.next == kNumServerShapes)
+                tune.done = newly_tuned = true;
+        }
         std::lock_guard<std::mutex> lk(s->mu);
         s->stats.chunks++;
         s->stats.spin_steps += spin_steps;
-        s->stats.busy_seconds += s->now() - t_begin;
+        s->stats.busy_seconds += t_chunk;
+        if (newly_tuned)
+            s->stats.tuned_compositions++;
+        s->stats.last_xcd_remap = kServerShapes[shape].remap;
+        s->stats.last_tile_order = kServerShapes[shape].order;
         for (auto it = s->active.begin(); it != s->active.end();) {
             Job& j = *s->jobs[*it];
             j.steps_done += std::min<int64_t>(K, j.n_steps - j.steps_done);

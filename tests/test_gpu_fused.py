@@ -29,7 +29,7 @@ def _oracle_run(w, n_steps, step0=0):
     return S, m, E
 
 
-def _fused_system(w, shape=None, fused=1):
+def _fused_system(w, shape=None, fused=2):
     g = sl.from_workload(w, precision=sl.FP32)
     g.set_option("fused", fused)
     if shape is not None:
@@ -41,9 +41,9 @@ def _fused_system(w, shape=None, fused=1):
     return g
 
 
-def _run(w, n_steps, shape=None, fused=1, chunks=None):
+def _run(w, n_steps, shape=None, fused=2, chunks=None):
     with _fused_system(w, shape, fused) as g:
-        assert g.get_option("fused_active") == fused
+        assert g.get_option("fused_active") == (1 if fused else 0)
         if chunks is None:
             m, E = g.integrate(n_steps)
         else:
@@ -54,11 +54,16 @@ def _run(w, n_steps, shape=None, fused=1, chunks=None):
 
 
 def test_lattice_declared_for_crystals():
+    """Crystals are declared cell by cell; below 2^20 spins the default runs
+    the two-launch step, "fused" = 2 takes the fused step at any size."""
     for w in (sc_reference(L=8), bcc_block(cells=6, n_steps=10), bcc_film(nx=8, ny=8, nz=4)):
         with sl.from_workload(w, precision=sl.FP32) as g:
             assert g.get_option("lattice") == 2
+            assert g.get_option("fused_active") == 0
+            g.set_option("fused", 2)
             assert g.get_option("fused_active") == 1
         with sl.from_workload(w, precision=sl.FP64) as g:
+            g.set_option("fused", 2)
             assert g.get_option("fused_active") == 0
 
 
@@ -137,7 +142,7 @@ def test_chunked_equals_one_call_bitwise():
 
 def test_fused_agrees_with_two_launch_step():
     w = bcc_block(cells=16, n_steps=30)
-    Sf, mf, Ef = _run(w, 30, fused=1)
+    Sf, mf, Ef = _run(w, 30, fused=2)
     St, mt, Et = _run(w, 30, fused=0)
     ang = max_angle(Sf, St)
     print(f"fused vs two-launch FP32, 30 steps: max angle {ang:.3e}")

@@ -148,3 +148,23 @@ def test_ragged_per_site_request():
     with sl.from_workload(w, precision=sl.FP32) as g:
         m2, E2 = g.integrate(120)
         assert np.array_equal(S, g.get_spins()) and np.array_equal(E, E2)
+
+
+def test_server_tunes_launch_shapes_per_composition():
+    """Every new batch composition times the launch shapes on its own chunks
+    and keeps the fastest; results stay those of the single-system path."""
+    reqs = [sc_request_system(14, 300.0, [0.0, 0.0, 0.5], 2000, 3000 + k) for k in range(3)]
+    with sl.Server(hbm_budget=1 << 30, chunk_steps=32) as srv:
+        tickets = [srv.submit(w, record=True) for w in reqs]
+        results = [srv.wait(t, 300) for t in tickets]
+        st = srv.stats()
+        got = [srv.fetch(t) for t in tickets]
+    assert all(r["state"] == "done" for r in results)
+    assert st["tuned_compositions"] >= 1
+    assert st["last_xcd_remap"] in (0, 1, 2) and st["last_tile_order"] in (0, 1)
+    for w, (S, m, E) in zip(reqs, got):
+        with sl.from_workload(w, precision=sl.FP32, lattice=False) as g:
+            g.set_option("tile_sites", 2048)
+            m2, E2 = g.integrate(2000)
+            assert np.array_equal(S, g.get_spins())
+            assert np.array_equal(m, m2) and np.array_equal(E, E2)
