@@ -82,6 +82,96 @@ __device__ __forceinline__ void thermal_normals(uint64_t seed, uint64_t step, ui
     g[2] = rho2 * __builtin_amdgcn_cosf(a4);
 }
 
+// FP64 natural logarithm of u in (0, 1] (no zero, infinity or NaN
+// arrives).  u = m 2^e with m in [sqrt(1/2), sqrt(2)); f = m - 1 is exact;
+// with s = f / (2 + f), log m = 2 atanh(s) = f - s (f - R), R = sum over
+// k >= 1 of 2 s^(2k) / (2k + 1): |s| <= 0.1716, so ten terms leave a
+// truncation error below 2^-60 of the result.  s comes from a hardware
+// reciprocal refined by two Newton steps and one residual correction; e ln 2
+// is added with ln 2 as a double plus its rounding error.
+__device__ __forceinline__ double log_unit(double u)
+{
+    double m = __builtin_amdgcn_frexp_mant(u);   // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(u);
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double f = m - 1.0;
+    const double d = 2.0 + f;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    double s = f * r;
+    s = fma(fma(-s, d, f), r, s);
+    const double z = s * s;
+    double p = 2.0 / 21.0;
+    p = fma(p, z, 2.0 / 19.0);
+    p = fma(p, z, 2.0 / 17.0);
+    p = fma(p, z, 2.0 / 15.0);
+    p = fma(p, z, 2.0 / 13.0);
+    p = fma(p, z, 2.0 / 11.0);
+    p = fma(p, z, 2.0 / 9.0);
+    p = fma(p, z, 2.0 / 7.0);
+    p = fma(p, z, 2.0 / 5.0);
+    p = fma(p, z, 2.0 / 3.0);
+    const double logm = fma(-s, fma(-z, p, f), f);
+    const double ln2 = 0.6931471805599453;        // ln 2 rounded to double
+    const double ln2_err = 2.3190468138462996e-17;   // ln 2 minus that double
+    const double ed = (double)e;
+    return fma(ed, ln2, fma(ed, ln2_err, logm));
+}
+
+// cos and sin of 2 pi a for the angle a = c 2^-32 revolutions.  The nearest
+// quarter turn j = round(4 a) (mod 4) and the rest r = a - j/4 in [-1/8, 1/8)
+// come exactly from the integer; x = 2 pi r, |x| <= pi/4, and the Taylor
+// series of sin x to x^17 and of cos x to x^18 (later terms below 2^-56
+// relative); then the quarter turn swaps and negates them.
+__device__ __forceinline__ void cossin_turns(uint32_t c, double& cs, double& sn)
+{
+    const uint32_t j = (c + 0x20000000u) >> 30;
+    const int32_t ri = (int32_t)(c - (j << 30));
+    const double x = (double)ri * (6.283185307179586 * 2.3283064365386963e-10);
+    const double z = x * x;
+    double ps = -1.0 / 355687428096000.0;          // -1/17!
+    ps = fma(ps, z, 1.0 / 1307674368000.0);        //  1/15!
+    ps = fma(ps, z, -1.0 / 6227020800.0);          // -1/13!
+    ps = fma(ps, z, 1.0 / 39916800.0);             //  1/11!
+    ps = fma(ps, z, -1.0 / 362880.0);              // -1/9!
+    ps = fma(ps, z, 1.0 / 5040.0);                 //  1/7!
+    ps = fma(ps, z, -1.0 / 120.0);                 // -1/5!
+    ps = fma(ps, z, 1.0 / 6.0);
+    const double sx = fma(-x * z, ps, x);          // x - x^3 (1/3! - ...)
+    double pc = 1.0 / 6402373705728000.0;          //  1/18!
+    pc = fma(pc, z, -1.0 / 20922789888000.0);      // -1/16!
+    pc = fma(pc, z, 1.0 / 87178291200.0);          //  1/14!
+    pc = fma(pc, z, -1.0 / 479001600.0);           // -1/12!
+    pc = fma(pc, z, 1.0 / 3628800.0);              //  1/10!
+    pc = fma(pc, z, -1.0 / 40320.0);               // -1/8!
+    pc = fma(pc, z, 1.0 / 720.0);                  //  1/6!
+    pc = fma(pc, z, -1.0 / 24.0);                  // -1/4!
+    const double cx = fma(z * z, -pc, fma(-0.5, z, 1.0));   // 1 - x^2/2 + x^4 (1/4! - ...)
+    const bool swap = j & 1u;
+    const double c0 = swap ? sx : cx, s0 = swap ? cx : sx;
+    cs = ((j + 1u) & 2u) ? -c0 : c0;
+    sn = (j & 2u) ? -s0 : s0;
+}
+
+// sqrt(v) for v >= 0 (a zero gives zero): the hardware reciprocal square
+// root estimate y, one Goldschmidt step for g ~ sqrt(v) and h ~ 1/(2 sqrt v)
+// from g = v y, h = y/2, then two residual corrections g += (v - g^2) h.
+__device__ __forceinline__ double sqrt_nonneg(double v)
+{
+    const double y = __builtin_amdgcn_rsq(v);
+    double g = v * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    g = fma(fma(-g, g, v), h, g);
+    g = fma(fma(-g, g, v), h, g);
+    return v > 0.0 ? g : 0.0;
+}
+
 __device__ __forceinline__ void thermal_normals(uint64_t seed, uint64_t step, uint32_t site,
                                                 double g[3], uint32_t purpose = 0u)
 {
@@ -90,19 +180,27 @@ __device__ __forceinline__ void thermal_normals(uint64_t seed, uint64_t step, ui
     const double two_m32 = 2.3283064365386963e-10;
     const double u1 = ((double)c0 + 1.0) * two_m32;
     const double u3 = ((double)c2 + 1.0) * two_m32;
-    const double rho1 = sqrt(-2.0 * log(u1));
-    const double rho2 = sqrt(-2.0 * log(u3));
-    double s2, c2d, s4, c4d;
-    sincospi(2.0 * ((double)c1 * two_m32), &s2, &c2d);
-    sincospi(2.0 * ((double)c3 * two_m32), &s4, &c4d);
-    (void)s4;
-    g[0] = rho1 * c2d;
-    g[1] = rho1 * s2;
-    g[2] = rho2 * c4d;
+    const double rho1 = sqrt_nonneg(-2.0 * log_unit(u1));
+    const double rho2 = sqrt_nonneg(-2.0 * log_unit(u3));
+    double cs2, sn2, cs4, sn4;
+    cossin_turns(c1, cs2, sn2);
+    cossin_turns(c3, cs4, sn4);
+    (void)sn4;
+    g[0] = rho1 * cs2;
+    g[1] = rho1 * sn2;
+    g[2] = rho2 * cs4;
 }
 
 __device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+// 1/sqrt(x) for x > 0 (a spin's squared norm after a step, close to 1): the
+// hardware estimate refined by two Newton steps y <- y + (y/2)(1 - x y^2).
+__device__ __forceinline__ double rsqrt_r(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return y;
+}
 
 template <typename R>
 struct V3 {
