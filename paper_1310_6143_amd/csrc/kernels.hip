@@ -522,7 +522,8 @@ __device__ __forceinline__ void add_thermal(const MaterialDev<R>& m, const R g[3
 
 // ---------------------------------------------------------------------------
 // Predictor.  For step k of the chunk: reads S (current state), writes the
-// predicted spin S' = |S + dS dt| and the corrector base S + dS dt / 2.
+// predicted spin S' = |S + dS dt| (the corrector rebuilds S + dS dt / 2 from
+// S and S', and draws the step's thermal normals again from their counter).
 // With MEASURE it only evaluates m and E: of the state after the chunk's
 // steps (k == 0) or of the current state (k == 1).
 //
