@@ -105,12 +105,13 @@ sllg_status sllg_set_neighbours(sllg_system *sys, const int64_t *row_ptr, const 
  * takes lattices periodic in x and y (z periodic or open) with at most 2
  * sites per cell whose links depend only on the plane and the basis site,
  * uniform materials, scalar exchange, no cubic anisotropy or demagnetising
- * field, in FP32 (sllg_get_option "lattice" = 2 when the structure
- * qualifies, "fused_active" = 1 when the next integration takes it); other
- * systems run the two-launch step.  The exchange sum of a site is then
- * added in a fixed order (links into the plane below, its own plane, the
- * plane above), so trajectories agree with the two-launch step to FP32
- * rounding, not bit for bit.  Call after sllg_set_neighbours; a new
+ * field; in FP64 only lattices whose sites all have the simple-cubic or bcc
+ * links (sllg_get_option "lattice" = 2 when the structure qualifies,
+ * "fused_active" = 1 when the next integration takes it); other systems run
+ * the two-launch step.  The exchange sum of a site is then added in a fixed
+ * order (links into the plane below, its own plane, the plane above), so
+ * trajectories agree with the two-launch step to rounding, not bit for
+ * bit.  Call after sllg_set_neighbours; a new
  * neighbour list drops the declaration.  SLLG_E_STATE before
  * sllg_set_neighbours. */
 sllg_status sllg_set_lattice(sllg_system *sys, int n_basis, const int cells[3], const int periodic[3]);
@@ -414,10 +415,11 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     shape of the fused step's work items: a tile of
  *                     tile_x x tile_y cell columns marched through `planes`
  *                     planes by a workgroup of `threads` (256, 512, or 1024
- *                     for the simple-cubic and bcc kinds) threads, which
- *                     needs (tile_x + 2)(tile_y + 2) <= threads, tile_x,
- *                     tile_y >= 6 and the planes' LDS within the device's
- *                     limit per workgroup; takes effect once all
+ *                     for the simple-cubic and bcc kinds in FP32) threads,
+ *                     which needs (tile_x + 2)(tile_y + 2) <= threads,
+ *                     tile_x, tile_y >= 6, in FP64 tile_x + 4 <= 16 (256
+ *                     threads) or 32 (512), and the planes' LDS within the
+ *                     device's limit per workgroup; takes effect once all
  *                     four are set (0 returns to the library's choice; the
  *                     autotuner also picks among shapes).  Results do not
  *                     depend on the shape except the m and E records, at FP64

@@ -617,7 +617,8 @@ double autotune(sllg_system* s, int trial_steps, hipStream_t st)
     const bool fusable = fused_wanted(s) && e.fused_capable();
     if (fusable) {
         // the model's best fused shapes (the spins do not depend on the shape)
-        for (const FusedShape& f : e.fused_candidates(8))
+        // FP64: more of them (the model ranks FP64 shapes less sharply)
+        for (const FusedShape& f : e.fused_candidates(s->prec == SLLG_FP64 ? 12 : 8))
             for (int64_t g : graphs)
                 cands.push_back({1, 100, g, 1, 1, 1, f});
     } else {
@@ -729,12 +730,12 @@ FusedShape current_fused_shape(const sllg_system* s)
     return s->opt_fshape;
 }
 
-// The next integration takes the fused step: a fusable lattice, uniform
-// materials, scalar exchange, no cubic anisotropy or demagnetising field,
-// FP32, and the option on.
+// The next integration takes the fused step: a lattice it takes in the
+// system's precision (FP64: the compiled kinds), uniform materials, scalar
+// exchange, no cubic anisotropy or demagnetising field, and the option on.
 bool fused_will_run(const sllg_system* s)
 {
-    return fused_wanted(s) && s->prec == SLLG_FP32 && s->st.lat.on && s->st.lat.fusable && s->has_mat &&
+    return fused_wanted(s) && fused_precision_ok(s->st.lat, s->n, s->prec == SLLG_FP32 ? 4 : 8) && s->has_mat &&
            !s->mat.per_site_material && !s->mat.per_site_axis && !s->st.tensor && !s->mat.cubic && !s->st.demag.on;
 }
 
@@ -1552,10 +1553,12 @@ sllg_status sllg_set_option(sllg_system* sys, const char* key, int64_t value)
             if (value == 0) {
                 sys->opt_fshape = FusedShape{};   // the model's shape at the next rebuild
             } else if (f.px > 0 && f.py > 0 && f.planes > 0 && f.bt > 0) {
-                if (!sys->st.lat.on || !sys->st.lat.fusable)
-                    fail(SLLG_E_STATE, "no fused step: declare a lattice the fused step takes (sllg_set_lattice)");
+                if (!fused_precision_ok(sys->st.lat, sys->n, sys->prec == SLLG_FP32 ? 4 : 8))
+                    fail(SLLG_E_STATE, "no fused step: declare a lattice the fused step takes in this precision "
+                                       "(sllg_set_lattice; FP64: simple cubic or bcc links)");
                 // the device's LDS limit once it is open (MI355X: 160 KB per workgroup)
-                if (!fused_shape_ok(f, sys->st.lat, sys->eng ? sys->eng->lds_limit() : (size_t)160 * 1024))
+                if (!fused_shape_ok(f, sys->st.lat, sys->eng ? sys->eng->lds_limit() : (size_t)160 * 1024,
+                                    sys->prec == SLLG_FP32 ? 4 : 8))
                     fail(SLLG_E_ARG, "fused shape out of range (tile " + std::to_string(f.px - 2) + " x " +
                                          std::to_string(f.py - 2) + ", " + std::to_string(f.planes) +
                                          " planes, " + std::to_string(f.bt) + " threads)");

@@ -148,26 +148,30 @@ inline int64_t fused_item_cap(const HostLattice& L)
     return ((L.nx + t - 1) / t) * ((L.ny + t - 1) / t) * ((L.nz + p - 1) / p);
 }
 
-// LDS bytes of one plane of the fused kernel (a slot of 16 bytes per site
-// of the tile, the ring and one more ring).
-inline int fused_plane_bytes(const FusedShape& f, int nb)
+// LDS bytes of one plane of the fused kernel (the tile, the ring and one
+// more ring; fused_plane_bytes of kernels.hpp).
+inline int fused_plane_bytes(const FusedShape& f, int nb, size_t real_bytes)
 {
-    return (f.px + 2) * (f.py + 2) * nb * 16;
+    return fused_plane_bytes(f.px, f.py, nb, real_bytes, f.bt);
 }
 
-// A shape the kernels take for lattice L: the region fits the block, the
-// LDS planes fit the device (lds_limit bytes per workgroup) and each wave
-// copies at most three chunks of 64 sites per plane; items have at least
+// A shape the kernels take for lattice L in a precision (bytes per real):
+// the region fits the block (and, in FP64, the LDS row), the LDS planes fit
+// the device (lds_limit bytes per workgroup) and each wave copies at most
+// fused_chunks_per_wave chunks per plane; items have at least
 // kFusedMinPlanes planes (all of them on thinner lattices).
-inline bool fused_shape_ok(const FusedShape& f, const HostLattice& L, size_t lds_limit)
+inline bool fused_shape_ok(const FusedShape& f, const HostLattice& L, size_t lds_limit, size_t real_bytes)
 {
-    if (!fused_block_ok(L.kind, f.bt) || f.px < kFusedMinEdge || f.py < kFusedMinEdge || f.px > 0x7FFF || f.py > 0x7FFF ||
-        (int64_t)f.px * f.py > f.bt || f.planes < std::min(kFusedMinPlanes, L.nz))
+    if (!fused_block_ok(L.kind, f.bt, real_bytes) || f.px < kFusedMinEdge || f.py < kFusedMinEdge ||
+        f.px > 0x7FFF || f.py > 0x7FFF || (int64_t)f.px * f.py > f.bt || f.planes < std::min(kFusedMinPlanes, L.nz))
         return false;
-    const int64_t slots = (int64_t)(f.px + 2) * (f.py + 2) * L.nb;
-    if ((slots + 63) / 64 > 3 * (f.bt / 64))
+    if (real_bytes == 8 && f.px + 2 > fused_row_slots(real_bytes, f.bt))
         return false;
-    return fused_lds_bytes(L.kind, fused_plane_bytes(f, L.nb), f.bt) + fused_static_lds(f.bt) <= lds_limit;
+    if ((int64_t)f.py > 0x7FFF / (L.nb * 64) ||
+        fused_plane_chunks(f.px, f.py, L.nb, real_bytes, f.bt) > fused_chunks_per_wave(real_bytes) * (f.bt / 64))
+        return false;
+    return fused_lds_bytes(L.kind, fused_plane_bytes(f, L.nb, real_bytes), f.bt) + fused_static_lds(f.bt, real_bytes) <=
+           lds_limit;
 }
 
 // Work items of a lattice for a shape.
@@ -179,14 +183,17 @@ inline int64_t fused_items(const HostLattice& L, const FusedShape& f)
 
 // Candidate shapes for a lattice (the autotuner times them; the first is
 // the model's choice).  resident(f) gives the workgroups the device holds
-// at once for shape f.  The planes per item are chosen so that the items
-// fill whole rounds of the resident workgroups; the model counts
+// at once for shape f.  FP32: the planes per item are chosen so that the
+// items fill whole rounds of the resident workgroups; the model counts
 // wave-instructions of one item (predictor on planes + 2 on every wave,
 // corrector on planes on the waves that hold tile cells, plane copies on
-// planes + 4) times rounds.
+// planes + 4) times rounds.  FP64 (the predictor's FP64 noise dominates,
+// and a partly idle last round costs little): an item's predictor planes
+// plus a fifth of its corrector planes (per wave) times the items per
+// resident workgroup, at least one.
 template <typename Resident>
-inline std::vector<FusedShape> fused_candidates(const HostLattice& L, size_t lds_limit, Resident&& resident,
-                                                int max_count)
+inline std::vector<FusedShape> fused_candidates(const HostLattice& L, size_t lds_limit, size_t real_bytes,
+                                                Resident&& resident, int max_count)
 {
     struct Scored {
         double cost;
@@ -197,10 +204,15 @@ inline std::vector<FusedShape> fused_candidates(const HostLattice& L, size_t lds
         for (int px = kFusedMinEdge; px <= 64; ++px)
             for (int py = kFusedMinEdge; py <= bt / kFusedMinEdge; ++py) {
                 FusedShape f{px, py, std::min(kFusedMinPlanes, L.nz), bt};
-                if (!fused_shape_ok(f, L, lds_limit))
+                if (!fused_shape_ok(f, L, lds_limit, real_bytes))
                     continue;
                 const int tx = px - 2, ty = py - 2;
                 if (tx > L.nx + 6 || ty > L.ny + 6)   // far wider than the lattice
+                    continue;
+                // FP64: of the tiles that give the same number of columns,
+                // only the smallest (the least ring work)
+                if (real_bytes == 8 && ((tx > kFusedMinEdge - 2 && (L.nx + tx - 2) / (tx - 1) == (L.nx + tx - 1) / tx) ||
+                                        (ty > kFusedMinEdge - 2 && (L.ny + ty - 2) / (ty - 1) == (L.ny + ty - 1) / ty)))
                     continue;
                 const int R = std::max(resident(f), 1);
                 const int64_t cols = (int64_t)((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty);
@@ -214,9 +226,14 @@ inline std::vector<FusedShape> fused_candidates(const HostLattice& L, size_t lds
                     if (segs > 1 && (L.nz + segs - 2) / (segs - 1) == planes)
                         continue;   // the same planes as fewer segments
                     const int64_t items = cols * ((L.nz + planes - 1) / planes);
+                    f.planes = planes;
+                    if (real_bytes == 8) {
+                        const double item = (planes + 2) + (double)tile_waves / waves * planes * 0.2;
+                        all.push_back({std::max((double)items / R, 1.0) * item, f});
+                        continue;
+                    }
                     const double item = waves * ((planes + 2) * 1.0 + (planes + 4) * 0.25) + tile_waves * planes * 0.4;
                     const double rounds = std::ceil((double)items / R);
-                    f.planes = planes;
                     all.push_back({rounds * item * R, f});
                 }
             }
@@ -551,7 +568,7 @@ public:
             r.f_plane = nullptr;
             r.f_partials = nullptr;
             r.f_px = r.f_py = r.f_items = 0;
-            if (sizeof(R) == 4 && s.lat.on && s.lat.fusable) {
+            if (fused_precision_ok(s.lat, s.n, sizeof(R))) {
                 size_t ent = 0;
                 for (const auto& p : s.lat.pats)
                     ent += p.size();
@@ -576,8 +593,8 @@ public:
             r.flags = 0;
             fill_parameters(r, s, m, d);
             if (r.f_partials)
-                sl.fshape = fused_candidates(sl.lat, lds_limit(), [&](const FusedShape& f) { return fused_resident(sl.lat, f); },
-                                             1)
+                sl.fshape = fused_candidates(sl.lat, lds_limit(), sizeof(R),
+                                             [&](const FusedShape& f) { return fused_resident(sl.lat, f); }, 1)
                                 .at(0);
             upload_materials(q, m, d);
             r.parity = 0;
@@ -683,7 +700,7 @@ public:
         Slot& sl = slots_[q];
         if (!sl.rec.f_partials)
             fail(SLLG_E_STATE, "the replica has no fused step");
-        if (!fused_shape_ok(f, sl.lat, lds_limit()))
+        if (!fused_shape_ok(f, sl.lat, lds_limit(), sizeof(R)))
             fail(SLLG_E_ARG, "fused shape out of range");
         if (sl.fshape == f)
             return;
@@ -709,14 +726,15 @@ public:
         const int key = ((L.kind * 4 + L.nb) * 4) + (f.bt >> 8);
         auto it = fused_occ_.find(key);
         if (it == fused_occ_.end())
-            it = fused_occ_.emplace(key, fused_resident_blocks<float>(device_, L.kind, L.nb, f.bt, 16)).first;
+            it = fused_occ_.emplace(key, fused_resident_blocks<R>(device_, L.kind, L.nb, f.bt, 16)).first;
         int cus = 0, lds_cu = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device_) != hipSuccess || cus <= 0)
             cus = 256;
         if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device_) != hipSuccess ||
             lds_cu <= 0)
             lds_cu = 160 * 1024;
-        const size_t per_wg = fused_lds_bytes(L.kind, fused_plane_bytes(f, L.nb), f.bt) + fused_static_lds(f.bt);
+        const size_t per_wg =
+            fused_lds_bytes(L.kind, fused_plane_bytes(f, L.nb, sizeof(R)), f.bt) + fused_static_lds(f.bt, sizeof(R));
         const int by_lds = (int)std::max<size_t>(1, (size_t)lds_cu / per_wg);
         const int by_regs = std::max(1, it->second / cus);
         return cus * std::min(by_lds, by_regs);
@@ -730,7 +748,8 @@ public:
     std::vector<FusedShape> fused_candidate_shapes(int q, int max_count)
     {
         const HostLattice& L = slots_[q].lat;
-        return fused_candidates(L, lds_limit(), [&](const FusedShape& f) { return fused_resident(L, f); }, max_count);
+        return fused_candidates(L, lds_limit(), sizeof(R), [&](const FusedShape& f) { return fused_resident(L, f); },
+                                max_count);
     }
 
     // Write the current state (spins are normalised doubles, 3n).
@@ -828,7 +847,7 @@ public:
         resident_ = resident_v_[variant_];
         // fused step: every replica of the batch can take it, with one block
         // size and one number of sites per cell
-        bool fused = fused_on_ && sizeof(R) == 4;
+        bool fused = fused_on_;
         int f_nb = -1, f_bt = -1, f_kind = -1, f_plane = 0;
         for (const auto& sl : slots_) {
             if (!sl.used || !fused)
@@ -841,7 +860,7 @@ public:
             f_nb = sl.lat.nb;
             f_bt = sl.fshape.bt;
             f_kind = sl.lat.kind;
-            f_plane = std::max(f_plane, fused_plane_bytes(sl.fshape, sl.lat.nb));
+            f_plane = std::max(f_plane, fused_plane_bytes(sl.fshape, sl.lat.nb, sizeof(R)));
         }
         // two-launch tiles (the Monte Carlo records take them in fused mode too)
         work_.clear();
@@ -1159,13 +1178,13 @@ private:
             // record, then the records and the advance
             const int* nf = (const int*)(reinterpret_cast<const char*>(d_fwork_) + sizeof(FusedItem) * (size_t)fwork_cap_);
             for (int k = 0; k < K && e == hipSuccess; ++k)
-                e = launch_fused<float>((const ReplicaDev<float>*)d_reps_, d_fwork_, nf, fgrid_, k, remap_, false,
-                                        fused_kind_, fused_nb_, fused_bt_, fused_plane_, st);
+                e = launch_fused<R>(d_reps_, d_fwork_, nf, fgrid_, k, remap_, false, fused_kind_, fused_nb_, fused_bt_,
+                                    fused_plane_, st);
             if (e == hipSuccess)
-                e = launch_fused<float>((const ReplicaDev<float>*)d_reps_, d_fwork_, nf, fgrid_, 0, remap_, true,
-                                        fused_kind_, fused_nb_, fused_bt_, fused_plane_, st);
+                e = launch_fused<R>(d_reps_, d_fwork_, nf, fgrid_, 0, remap_, true, fused_kind_, fused_nb_, fused_bt_,
+                                    fused_plane_, st);
             if (e == hipSuccess)   // records, averaging sums and the advance
-                e = launch_fused_finish<float>((ReplicaDev<float>*)d_reps_, nrep, st);
+                e = launch_fused_finish<R>(d_reps_, nrep, st);
             return e;
         }
         for (int k = 0; k < K && e == hipSuccess; ++k) {

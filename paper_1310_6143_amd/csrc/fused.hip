@@ -54,11 +54,28 @@ namespace {
 
 using namespace dev;
 
-// LDS slot of one site: x, y, z and a fourth word (the next site's x as it
-// arrives from memory; never used).
-template <typename R>
-struct alignas(4 * sizeof(R)) Slot4 {
-    R x, y, z, w;
+// FP32 LDS slot of one site: x, y, z and a fourth word (the next site's x
+// as it arrives from memory; never used).
+struct alignas(16) Slot4 {
+    float x, y, z, w;
+};
+// FP64: x and y of a site (its z sits in the second half of the row).
+struct alignas(16) XY64 {
+    double x, y;
+};
+// 16 bytes of zeros: a lane's share of a plane beyond an open surface.
+struct alignas(16) Zero16 {
+    uint32_t w[4];
+};
+
+// Plane layout constants of a precision and block size: the FP64 row width
+// in slots (RW) and the distance of a site's z from its x, y (ZOFF); the
+// chunks a wave copies per plane (CPW).
+template <typename R, int BT>
+struct PlaneLayout {
+    static constexpr int RW = fused_row_slots(sizeof(R), BT);
+    static constexpr int ZOFF = RW * 16;
+    static constexpr int CPW = fused_chunks_per_wave(sizeof(R));
 };
 
 template <typename R>
@@ -151,21 +168,40 @@ __device__ __forceinline__ void record_add(const R t[4], double* acc)
         acc[c * BT] = a[c] + (double)t[c];
 }
 
-// x, y, z of the LDS slot at p (the fourth word is never read).  The slot
-// is read through its 16-byte-aligned type, so the compiler emits one
-// 12-byte LDS read (ds_read_b96) for the three words it uses; through a
+// x, y, z of the LDS slot at p.  FP32: the fourth word is never read; the
+// slot is read through its 16-byte-aligned type, so the compiler emits one
+// 12-byte LDS read (ds_read_b96) for the three words it uses (through a
 // 4-byte-aligned 12-byte type it splits the read into two or three
-// instructions, which cost the step a fifth of its time.
-template <typename R>
+// instructions, which cost the step a fifth of its time).  FP64: a 16-byte
+// read of x, y and an 8-byte read of z, ZOFF bytes further (one address,
+// two immediate offsets).
+template <typename R, int ZOFF>
 __device__ __forceinline__ V3<R> slot_xyz(const char* p)
 {
-    const Slot4<R> v = *reinterpret_cast<const Slot4<R>*>(p);
-    return V3<R>{v.x, v.y, v.z};
+    if constexpr (sizeof(R) == 4) {
+        const Slot4 v = *reinterpret_cast<const Slot4*>(p);
+        return V3<R>{v.x, v.y, v.z};
+    } else {
+        const XY64 v = *reinterpret_cast<const XY64*>(p);
+        return V3<R>{v.x, v.y, *reinterpret_cast<const double*>(p + ZOFF)};
+    }
+}
+
+template <typename R, int ZOFF>
+__device__ __forceinline__ void slot_store(char* p, const V3<R>& v)
+{
+    if constexpr (sizeof(R) == 4) {
+        *reinterpret_cast<Slot4*>(p) = Slot4{v.x, v.y, v.z, 0.0f};
+    } else {
+        *reinterpret_cast<XY64*>(p) = XY64{v.x, v.y};
+        *reinterpret_cast<double*>(p + ZOFF) = v.z;
+    }
 }
 
 // Per-thread geometry of an item.  An LDS plane holds the region's sites
-// basis-major: slot (b, ry, rx) = b * area + ry * sw + rx, 16 bytes each,
-// so the lanes of a wave read consecutive slots.
+// basis-major, row after row (FP32: 16 bytes per site, rows of the region's
+// width; FP64: rows of RW sites, x, y then z), so the lanes of a wave read
+// consecutive slots and a link's slot is a constant distance away.
 template <int NB>
 struct ItemGeo {
     int rb[NB][3];      // byte offset of slot (bp, row py + 1 + dy, column px) for dy = -1, 0, 1
@@ -178,7 +214,7 @@ struct ItemGeo {
 // h += links of basis site b whose dz is DZ, read from the plane at `base`
 // (the slots of this thread's cell: rb).  Compiled kinds: constant offsets
 // and the two slot couplings kj; generic: pattern p's entries from LDS.
-template <typename R, int KIND, int NB, int DZ>
+template <typename R, int KIND, int NB, int DZ, int ZOFF>
 __device__ __forceinline__ void add_dz(V3<R>& h, const char* __restrict__ base, const ItemGeo<NB>& g, int b,
                                        const R kj[2], const int4* pat, const FEnt<R>* ent, int p)
 {
@@ -195,7 +231,7 @@ __device__ __forceinline__ void add_dz(V3<R>& h, const char* __restrict__ base, 
                     int slot = 0;
                     if (!kind_link(KIND, b, DZ, dy, dx, bp, &slot))
                         continue;
-                    const V3<R> v = slot_xyz<R>(base + g.rb[bp][dy + 1] + (dx + 1) * 16);
+                    const V3<R> v = slot_xyz<R, ZOFF>(base + g.rb[bp][dy + 1] + (dx + 1) * 16);
                     h.x = fma(kj[slot], v.x, h.x);
                     h.y = fma(kj[slot], v.y, h.y);
                     h.z = fma(kj[slot], v.z, h.z);
@@ -212,7 +248,7 @@ __device__ __forceinline__ void add_dz(V3<R>& h, const char* __restrict__ base, 
 #pragma unroll 4
         for (int q = 0; q < cnt; ++q) {
             const FEnt<R> en = ent[first + q];
-            const V3<R> v = slot_xyz<R>(own + en.off);
+            const V3<R> v = slot_xyz<R, ZOFF>(own + en.off);
             h.x = fma((R)en.J, v.x, h.x);
             h.y = fma((R)en.J, v.y, h.y);
             h.z = fma((R)en.J, v.z, h.z);
@@ -237,7 +273,7 @@ __host__ __device__ constexpr bool kind_reads(int kind, int dy, int dx, int bp)
 // `base`, each distinct slot read once.  hu (sites one plane below, their
 // dz = +1 links), h0 (sites of this plane, dz = 0) and hd (sites one plane
 // above, dz = -1) receive the sums, each link in the canonical order.
-template <typename R, int KIND, int NB>
+template <typename R, int KIND, int NB, int ZOFF>
 __device__ __forceinline__ void plane_links(const char* __restrict__ base, const ItemGeo<NB>& g, const R kj[2],
                                             V3<R> hu[NB], V3<R> h0[NB], V3<R> hd[NB])
 {
@@ -249,7 +285,7 @@ __device__ __forceinline__ void plane_links(const char* __restrict__ base, const
 #pragma unroll
             for (int bp = 0; bp < NB; ++bp)
                 if (kind_reads(KIND, dy, dx, bp))
-                    v[dy + 1][dx + 1][bp] = slot_xyz<R>(base + g.rb[bp][dy + 1] + (dx + 1) * 16);
+                    v[dy + 1][dx + 1][bp] = slot_xyz<R, ZOFF>(base + g.rb[bp][dy + 1] + (dx + 1) * 16);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -284,10 +320,6 @@ __device__ __forceinline__ int plane_pattern(const ReplicaDev<R>& r, int z, int 
     return r.f_plane ? (int)r.f_plane[z * r.f_nb + b] : b;
 }
 
-// Chunks of 64 LDS slots a wave copies per plane (the region of the largest
-// allowed shape fits in three per wave).
-constexpr int kChunksPerWave = 3;
-
 // Running state of the thread's sites between planes, in two slots chosen
 // by the parity of the plane (relative to the item's first), so that a
 // value stays in the same registers from the plane step that creates it
@@ -304,7 +336,7 @@ template <typename R>
 struct ItemRun {
     const R* S;                   // state the step starts from
     R* Sn;                        // state it writes
-    const uint32_t* dcol;         // [kChunksPerWave][BT] byte offset (plane 0) of the sites each lane copies, or ~0
+    const uint32_t* dcol;         // [CPW][BT] byte offset (plane 0) of the 16 bytes each lane copies, or ~0
     __amdgpu_buffer_rsrc_t rsrc;  // the spins S as a buffer (reads past its end return 0)
     int n_chunks;
     int z0, z1;
@@ -329,6 +361,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
                                            int zw_p1, const MaterialDev<R>& m)
 {
     constexpr int S0 = P, S1 = P ^ 1;   // slots of planes q (and q - 2, q + 2) and q - 1 (and q + 1)
+    constexpr int ZOFF = PlaneLayout<R, BT>::ZOFF, CPW = PlaneLayout<R, BT>::CPW;
     const int nz = r.f_nz;
     const bool zper = r.f_zper != 0;
     const int z0 = run.z0, z1 = run.z1;
@@ -340,7 +373,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
     const bool zp_need = zp >= z0 - 1 && zp <= z1 && zp_exists;
     const bool zp_own = zp >= z0 && zp < z1;
     // Issue the copy of S(q + 1) into the LDS plane dst: direct
-    // global-to-LDS loads of 16 bytes per site, or zeros beyond an open
+    // global-to-LDS loads of 16 bytes per lane, or zeros beyond an open
     // surface; nothing past the item's last needed plane.  The next barrier
     // completes it.
     auto copy_next = [&](char* __restrict__ dst) {
@@ -351,7 +384,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
         // computed on the scalar unit when needed, not held in registers
         const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
 #pragma unroll
-        for (int j = 0; j < kChunksPerWave; ++j) {
+        for (int j = 0; j < CPW; ++j) {
             const int c = wave + j * (BT / 64);
             if (c >= run.n_chunks)
                 break;   // uniform over the wave
@@ -363,7 +396,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
                         run.rsrc, (lds_ptr)d, 16, (int)dc,
                         (int)(g.plane_sites * 3u * (uint32_t)sizeof(R) * (uint32_t)zw_p1), 0, 0);
                 } else {
-                    reinterpret_cast<Slot4<R>*>(d)[lane] = Slot4<R>{0, 0, 0, 0};
+                    reinterpret_cast<Zero16*>(d)[lane] = Zero16{{0u, 0u, 0u, 0u}};
                 }
             }
         }
@@ -379,13 +412,13 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
         up[b] = V3<R>{0, 0, 0};
     if (g.live) {
         if constexpr (KIND != kKindGeneric) {
-            plane_links<R, KIND, NB>(cur, g, kj, cs.hp[S1], cs.hp[S0], up);
+            plane_links<R, KIND, NB, ZOFF>(cur, g, kj, cs.hp[S1], cs.hp[S0], up);
         } else {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                add_dz<R, KIND, NB, 1>(cs.hp[S1][b], cur, g, b, kj, pat, ent, plane_pattern(r, q - 1, b));
-                add_dz<R, KIND, NB, 0>(cs.hp[S0][b], cur, g, b, kj, pat, ent, plane_pattern(r, q, b));
-                add_dz<R, KIND, NB, -1>(up[b], cur, g, b, kj, pat, ent, plane_pattern(r, q + 1, b));
+                add_dz<R, KIND, NB, 1, ZOFF>(cs.hp[S1][b], cur, g, b, kj, pat, ent, plane_pattern(r, q - 1, b));
+                add_dz<R, KIND, NB, 0, ZOFF>(cs.hp[S0][b], cur, g, b, kj, pat, ent, plane_pattern(r, q, b));
+                add_dz<R, KIND, NB, -1, ZOFF>(up[b], cur, g, b, kj, pat, ent, plane_pattern(r, q + 1, b));
             }
         }
     }
@@ -395,7 +428,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
         R tc[4];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const V3<R> s = slot_xyz<R>(nxt + g.own(b));
+            const V3<R> s = slot_xyz<R, ZOFF>(nxt + g.own(b));
             const R se = fma(s.z, e.z, fma(s.y, e.y, s.x * e.x));
             R t[4];
             record_terms(m, s, se, cs.hp[S1][b], Happ, t);
@@ -408,7 +441,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (g.live && zp_need) {
-            const V3<R> s = slot_xyz<R>(nxt + g.own(b));
+            const V3<R> s = slot_xyz<R, ZOFF>(nxt + g.own(b));
             const V3<R>& hex = cs.hp[S1][b];
             const R se = fma(s.z, e.z, fma(s.y, e.y, s.x * e.x));
             if (!MEASURE) {
@@ -425,7 +458,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
                 cs.c_th[S1][b] = tha;
                 cs.c_sp[S1][b] = spn;
                 cs.c_base[S1][b] = V3<R>{s.x + (R)0.5 * ds.x, s.y + (R)0.5 * ds.y, s.z + (R)0.5 * ds.z};
-                *reinterpret_cast<Slot4<R>*>(sp + g.own(b)) = Slot4<R>{spn.x, spn.y, spn.z, (R)0};
+                slot_store<R, ZOFF>(sp + g.own(b), spn);
             }
         }
         cs.hp[S1][b] = up[b];
@@ -449,13 +482,13 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
             down[b] = V3<R>{0, 0, 0};
         if (zp_need) {
             if constexpr (KIND != kKindGeneric) {
-                plane_links<R, KIND, NB>(sp, g, kj, cs.hc[S0], cs.hc[S1], down);
+                plane_links<R, KIND, NB, ZOFF>(sp, g, kj, cs.hc[S0], cs.hc[S1], down);
             } else {
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    add_dz<R, KIND, NB, 1>(cs.hc[S0][b], sp, g, b, kj, pat, ent, plane_pattern(r, zc, b));
-                    add_dz<R, KIND, NB, 0>(cs.hc[S1][b], sp, g, b, kj, pat, ent, plane_pattern(r, zp, b));
-                    add_dz<R, KIND, NB, -1>(down[b], sp, g, b, kj, pat, ent, plane_pattern(r, q, b));
+                    add_dz<R, KIND, NB, 1, ZOFF>(cs.hc[S0][b], sp, g, b, kj, pat, ent, plane_pattern(r, zc, b));
+                    add_dz<R, KIND, NB, 0, ZOFF>(cs.hc[S1][b], sp, g, b, kj, pat, ent, plane_pattern(r, zp, b));
+                    add_dz<R, KIND, NB, -1, ZOFF>(down[b], sp, g, b, kj, pat, ent, plane_pattern(r, q, b));
                 }
             }
         }
@@ -514,30 +547,50 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
     g.interior = t < inner && ux < nx && uy < ny;
     g.col = (uint32_t)NB * (uint32_t)(wrap_cell(ux, nx) + nx * wrap_cell(uy, ny));
     g.plane_sites = (uint32_t)NB * (uint32_t)nx * (uint32_t)ny;
+    constexpr int RW = PlaneLayout<R, BT>::RW, CPW = PlaneLayout<R, BT>::CPW;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy)
-            g.rb[b][dy + 1] = (b * area + (py + 1 + dy) * SW + px) * 16;
+            g.rb[b][dy + 1] = (sizeof(R) == 4 ? b * area + (py + 1 + dy) * SW + px
+                                              : (b * SH + py + 1 + dy) * 2 * RW + px) * 16;
 
     ItemRun<R> run;
-    // the LDS slots (64 per chunk) each lane copies, kept in LDS
-    const int slots = area * NB;
-    run.n_chunks = (slots + 63) / 64;
+    // the 16 bytes of S each lane copies per chunk of a plane (64 lanes, 1
+    // KiB of LDS), kept in LDS.  FP32: LDS slot s = site (b, ry, rx) of the
+    // region.  FP64: lane l of a chunk fills row c * 64 / (2 RW) + l / (2 RW)
+    // (basis-major), site rx = l mod RW, x and y (first half of the row) or
+    // z (second half, from 16 bytes into the site).
+    run.n_chunks = fused_plane_chunks(PX, PY, NB, sizeof(R), BT);
 #pragma unroll
-    for (int j = 0; j < kChunksPerWave; ++j) {
-        const int s = ((t >> 6) + j * (BT / 64)) * 64 + (t & 63);
-        const int b = s / area, cell = s - b * area;
-        const int ry = cell / SW, rx = cell - ry * SW;
+    for (int j = 0; j < CPW; ++j) {
+        const int c = (t >> 6) + j * (BT / 64), l = t & 63;
+        int b, ry, rx, part = 0;
+        bool valid;
+        if constexpr (sizeof(R) == 4) {
+            const int s = c * 64 + l;
+            b = s / area;
+            const int cell = s - b * area;
+            ry = cell / SW;
+            rx = cell - ry * SW;
+            valid = s < area * NB;
+        } else {
+            const int row = c * (32 / RW) + l / (2 * RW);
+            part = (l / RW) & 1;
+            rx = l % RW;
+            b = row / SH;
+            ry = row - b * SH;
+            valid = row < NB * SH && rx < SW;
+        }
         const uint32_t site = (uint32_t)NB * (uint32_t)(wrap_cell(w.x0 - 2 + rx, nx) + nx * wrap_cell(w.y0 - 2 + ry, ny)) +
                               (uint32_t)b;
-        dcol[j * BT + t] = s < slots ? site * 3u * (uint32_t)sizeof(R) : 0xFFFFFFFFu;
+        dcol[j * BT + t] = valid ? site * 3u * (uint32_t)sizeof(R) + 16u * (uint32_t)part : 0xFFFFFFFFu;
     }
     run.dcol = dcol;
     const int par = (r.parity + (MEASURE ? r.nsteps : k)) & 1;
     run.S = r.S[par];
     run.Sn = r.S[par ^ 1];
-    // the spin buffer holds 16 bytes past its last site (the copies read 16 bytes per site)
+    // the spin buffer holds 16 bytes past its last site (the copies read 16 bytes per lane)
     run.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(run.S), 0,
                                                  (int)(3u * (uint32_t)sizeof(R) * (uint32_t)r.n + 16u), 0x00020000);
     run.z0 = w.z0;
@@ -568,19 +621,22 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
         const bool exists = zper || (z0 - 2 >= 0 && z0 - 2 < nz);
         const int wave = t >> 6, lane = t & 63;
 #pragma unroll
-        for (int j = 0; j < kChunksPerWave; ++j) {
+        for (int j = 0; j < CPW; ++j) {
             const int c = wave + j * (BT / 64);
             if (c >= run.n_chunks)
                 break;
-            Slot4<R>* d = reinterpret_cast<Slot4<R>*>(planes[0] + c * 64 * 16);
+            char* d = planes[0] + c * 64 * 16 + lane * 16;
             const uint32_t dc = dcol[j * BT + t];
             if (dc != 0xFFFFFFFFu) {
                 if (exists) {
                     const R* src = reinterpret_cast<const R*>(reinterpret_cast<const char*>(run.S) + dc) +
                                    3 * (size_t)g.plane_sites * (uint32_t)zw_0;
-                    d[lane] = Slot4<R>{src[0], src[1], src[2], (R)0};
+                    if constexpr (sizeof(R) == 4)
+                        *reinterpret_cast<Slot4*>(d) = Slot4{src[0], src[1], src[2], 0.0f};
+                    else
+                        *reinterpret_cast<XY64*>(d) = XY64{src[0], src[1]};
                 } else {
-                    d[lane] = Slot4<R>{0, 0, 0, 0};
+                    *reinterpret_cast<Zero16*>(d) = Zero16{{0u, 0u, 0u, 0u}};
                 }
             }
         }
@@ -653,14 +709,19 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
 // sums of the current state of every recording replica.  Dynamic LDS: two
 // S planes and one S' plane of plane_bytes each, then (generic kind) the
 // pattern tables.
-// Registers capped for four waves per SIMD (two 512-lane or four 256-lane
-// workgroups per compute unit).
+// Registers capped for four waves per SIMD in FP32 (two 512-lane or four
+// 256-lane workgroups per compute unit), two in FP64 (twice the registers
+// per column).
 #ifndef SLLG_FUSED_WAVES
 #define SLLG_FUSED_WAVES 4
 #endif
+#ifndef SLLG_FUSED_WAVES_F64
+#define SLLG_FUSED_WAVES_F64 2
+#endif
 
 template <typename R, int KIND, int NB, int BT, bool MEASURE>
-__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(SLLG_FUSED_WAVES))) void k_fused(const ReplicaDev<R>* __restrict__ reps,
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? SLLG_FUSED_WAVES
+                                                                                   : SLLG_FUSED_WAVES_F64))) void k_fused(const ReplicaDev<R>* __restrict__ reps,
                                               const FusedItem* __restrict__ items,
                                               const int* __restrict__ n_items, int k, int remap, int plane_bytes)
 {
@@ -671,7 +732,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(SLLG_FUSED_W
     extern __shared__ __attribute__((aligned(16))) char fused_lds[];
     __shared__ double red[4][BT / 64];
     __shared__ double acc[4 * BT];
-    __shared__ uint32_t dcol[kChunksPerWave * BT];
+    __shared__ uint32_t dcol[PlaneLayout<R, BT>::CPW * BT];
     int4* pat = reinterpret_cast<int4*>(fused_lds + 3 * plane_bytes);
     FEnt<R>* ent = reinterpret_cast<FEnt<R>*>(pat + kFusedMaxPatterns);
     const int W = *n_items;
@@ -726,7 +787,8 @@ const void* fused_ptr(bool measure)
     return measure ? (const void*)k_fused<R, KIND, NB, BT, true> : (const void*)k_fused<R, KIND, NB, BT, false>;
 }
 
-// The kernel of (kind, nb, bt, measure), or null if it is not built.
+// The kernel of (kind, nb, bt, measure), or null if it is not built
+// (FP64: the compiled kinds, 256 and 512 threads).
 template <typename R>
 const void* fused_kernel(int kind, int nb, int bt, bool measure)
 {
@@ -735,29 +797,37 @@ const void* fused_kernel(int kind, int nb, int bt, bool measure)
         return fused_ptr<R, K_, NB_, BT_>(measure);
     SLLG_FUSED_CASE(kKindSc6, 1, 256)
     SLLG_FUSED_CASE(kKindSc6, 1, 512)
-    SLLG_FUSED_CASE(kKindSc6, 1, 1024)
     SLLG_FUSED_CASE(kKindBcc8, 2, 256)
     SLLG_FUSED_CASE(kKindBcc8, 2, 512)
-    SLLG_FUSED_CASE(kKindBcc8, 2, 1024)
     SLLG_FUSED_CASE(kKindBcc14, 2, 256)
     SLLG_FUSED_CASE(kKindBcc14, 2, 512)
-    SLLG_FUSED_CASE(kKindBcc14, 2, 1024)
-    SLLG_FUSED_CASE(kKindGeneric, 1, 256)
-    SLLG_FUSED_CASE(kKindGeneric, 1, 512)
-    SLLG_FUSED_CASE(kKindGeneric, 2, 256)
-    SLLG_FUSED_CASE(kKindGeneric, 2, 512)
+    if constexpr (sizeof(R) == 4) {
+        SLLG_FUSED_CASE(kKindSc6, 1, 1024)
+        SLLG_FUSED_CASE(kKindBcc8, 2, 1024)
+        SLLG_FUSED_CASE(kKindBcc14, 2, 1024)
+        SLLG_FUSED_CASE(kKindGeneric, 1, 256)
+        SLLG_FUSED_CASE(kKindGeneric, 1, 512)
+        SLLG_FUSED_CASE(kKindGeneric, 2, 256)
+        SLLG_FUSED_CASE(kKindGeneric, 2, 512)
+    }
 #undef SLLG_FUSED_CASE
     return nullptr;
 }
 
 }  // namespace
 
-bool fused_block_ok(int kind, int bt) { return bt == 256 || bt == 512 || (bt == 1024 && kind != kKindGeneric); }
+bool fused_block_ok(int kind, int bt, size_t real_bytes)
+{
+    if (real_bytes == 4)
+        return bt == 256 || bt == 512 || (bt == 1024 && kind != kKindGeneric);
+    return (bt == 256 || bt == 512) && kind != kKindGeneric;
+}
 
-size_t fused_static_lds(int bt)
+size_t fused_static_lds(int bt, size_t real_bytes)
 {
     // acc, dcol and red of k_fused
-    return (size_t)bt * (4 * sizeof(double) + kChunksPerWave * sizeof(uint32_t)) + 4 * (size_t)(bt / 64) * sizeof(double);
+    return (size_t)bt * (4 * sizeof(double) + (size_t)fused_chunks_per_wave(real_bytes) * sizeof(uint32_t)) +
+           4 * (size_t)(bt / 64) * sizeof(double);
 }
 
 size_t fused_lds_bytes(int kind, int plane_bytes, int bt)
@@ -816,7 +886,11 @@ size_t fused_lds_limit(int device)
 
 template hipError_t launch_fused<float>(const ReplicaDev<float>*, const FusedItem*, const int*, int, int, int, bool,
                                         int, int, int, int, hipStream_t);
+template hipError_t launch_fused<double>(const ReplicaDev<double>*, const FusedItem*, const int*, int, int, int, bool,
+                                         int, int, int, int, hipStream_t);
 template hipError_t launch_fused_finish<float>(ReplicaDev<float>*, int, hipStream_t);
+template hipError_t launch_fused_finish<double>(ReplicaDev<double>*, int, hipStream_t);
 template int fused_resident_blocks<float>(int, int, int, int, int);
+template int fused_resident_blocks<double>(int, int, int, int, int);
 
 }  // namespace sllg

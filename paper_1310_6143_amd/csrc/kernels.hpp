@@ -91,13 +91,33 @@ hipError_t launch_fused_finish(ReplicaDev<R>* reps, int n_rep, hipStream_t st);
 // plane_bytes LDS planes; 0 if unknown.
 template <typename R>
 int fused_resident_blocks(int device, int kind, int nb, int bt, int plane_bytes);
-// Whether a fused kernel of this kind and block size is built.
-bool fused_block_ok(int kind, int bt);
+// Whether a fused kernel of this kind, block size and precision (bytes per
+// real) is built.
+bool fused_block_ok(int kind, int bt, size_t real_bytes);
 // Dynamic LDS of a fused workgroup with planes of plane_bytes.
 size_t fused_lds_bytes(int kind, int plane_bytes, int bt);
 // Static LDS of a fused workgroup of bt threads (its FP64 sums, copy table
 // and reduction slots).
-size_t fused_static_lds(int bt);
+size_t fused_static_lds(int bt, size_t real_bytes);
+
+// LDS planes of the fused step for a thread region of px x py cells (tile
+// plus ring) with nb sites per cell: the region and one more ring.  FP32:
+// 16 bytes per site (x, y, z, an unused word), sites basis-major, row after
+// row.  FP64: rows of fused_row_slots sites (at least the region's width),
+// 32 bytes per site: a row's x, y (16 bytes per site) and then its z (16
+// bytes per site, the second word unused).  Planes are filled by
+// direct-to-LDS loads of 16 bytes per lane, 64 lanes (1 KiB) per chunk.
+constexpr int fused_row_slots(size_t real_bytes, int bt) { return real_bytes == 4 ? 0 : (bt == 256 ? 16 : 32); }
+// Chunks of a plane one wave copies at most.
+constexpr int fused_chunks_per_wave(size_t real_bytes) { return real_bytes == 4 ? 3 : 6; }
+constexpr int fused_plane_bytes(int px, int py, int nb, size_t real_bytes, int bt)
+{
+    return real_bytes == 4 ? (px + 2) * (py + 2) * nb * 16 : nb * (py + 2) * fused_row_slots(real_bytes, bt) * 32;
+}
+constexpr int fused_plane_chunks(int px, int py, int nb, size_t real_bytes, int bt)
+{
+    return (fused_plane_bytes(px, py, nb, real_bytes, bt) + 1023) / 1024;
+}
 // LDS one workgroup may take on the device.
 size_t fused_lds_limit(int device);
 

@@ -709,9 +709,10 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
         flags |= kDemag;
     if (!s.stencil && s.long_rows)
         flags |= kLongRows;
-    // the fused step: a fusable lattice with uniform materials, scalar
-    // exchange and no cubic anisotropy or demagnetising field (FP32)
-    if (sizeof(R) == 4 && s.lat.on && s.lat.fusable && !m.per_site_material && !m.per_site_axis && !s.tensor &&
+    // the fused step: a lattice it takes in this precision, uniform
+    // materials, scalar exchange and no cubic anisotropy or demagnetising
+    // field
+    if (fused_precision_ok(s.lat, s.n, sizeof(R)) && !m.per_site_material && !m.per_site_axis && !s.tensor &&
         !m.cubic && !s.demag.on)
         flags |= kFused;
     rec.flags = flags;

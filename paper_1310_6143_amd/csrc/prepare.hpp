@@ -88,6 +88,14 @@ struct HostLattice {
     int slot_type[2] = {0, 0};                  // interaction type of each of the kind's slots
 };
 
+// Whether the fused step is built for lattice L of n sites in a precision
+// (bytes per real): FP32 any fusable lattice, FP64 the compiled kinds; the
+// spins must be addressable with 31-bit byte offsets.
+inline bool fused_precision_ok(const HostLattice& L, int64_t n, size_t real_bytes)
+{
+    return L.on && L.fusable && (real_bytes == 4 || L.kind != kKindGeneric) && n * 3 * (int64_t)real_bytes + 16 <= 0x7FFFFFFF;
+}
+
 // Neighbour structure in stencil or SELL-64 form.  Every row lists its
 // near links (|col - row| <= halo_cap) first and the far ones after, each
 // part in the caller's order; the step kernels sum the two parts separately

@@ -4,9 +4,10 @@ against the FP64 oracle, through the C ABI.
 
 The fused step adds a site's exchange links in its own fixed order (links
 into the plane below, its own plane, the plane above), so it agrees with
-the oracle and with the two-launch step to FP32 rounding; the tolerances
-are about ten times the differences measured on MI355X (printed on the
-lines starting "PARITY").  Spins do not depend on the tile
+the oracle and with the two-launch step to rounding (FP32, or FP64 for the
+simple-cubic and bcc kinds); the FP32 tolerances are about ten times the
+differences measured on MI355X (printed on the lines starting "PARITY"),
+the FP64 ones those of the two-launch FP64 step.  Spins do not depend on the tile
 shape (each site's arithmetic is the same whichever workgroup computes it),
 so different shapes must give bit-identical spins; the m and E records are
 sums over items and may differ at FP64 rounding.
@@ -29,8 +30,8 @@ def _oracle_run(w, n_steps, step0=0):
     return S, m, E
 
 
-def _fused_system(w, shape=None, fused=2):
-    g = sl.from_workload(w, precision=sl.FP32)
+def _fused_system(w, shape=None, fused=2, precision=sl.FP32):
+    g = sl.from_workload(w, precision=precision)
     g.set_option("fused", fused)
     if shape is not None:
         tx, ty, planes, threads = shape
@@ -41,8 +42,8 @@ def _fused_system(w, shape=None, fused=2):
     return g
 
 
-def _run(w, n_steps, shape=None, fused=2, chunks=None):
-    with _fused_system(w, shape, fused) as g:
+def _run(w, n_steps, shape=None, fused=2, chunks=None, precision=sl.FP32):
+    with _fused_system(w, shape, fused, precision) as g:
         assert g.get_option("fused_active") == (1 if fused else 0)
         if chunks is None:
             m, E = g.integrate(n_steps)
@@ -53,18 +54,51 @@ def _run(w, n_steps, shape=None, fused=2, chunks=None):
         return g.get_spins(), m, E
 
 
+def _sc_two_couplings(L=8):
+    """sc L^3 whose z links have their own J: every site has the six
+    simple-cubic links, but not one coupling per link slot, so the fused
+    step reads the links from its generic pattern tables."""
+    w = sc_reference(L=L)
+    lat = w.lattice
+    rows = np.repeat(np.arange(lat.n), np.diff(lat.row_ptr))
+    lat.ntype = (lat.pos[rows, 2] != lat.pos[lat.col, 2]).astype(np.uint8)
+    w.J = np.array([6.0e-21, 3.0e-21])
+    return w
+
+
 def test_lattice_declared_for_crystals():
     """Crystals are declared cell by cell; below 2^20 spins the default runs
-    the two-launch step, "fused" = 2 takes the fused step at any size."""
+    the two-launch step, "fused" = 2 takes the fused step at any size (FP64:
+    the compiled simple-cubic and bcc kinds only)."""
     for w in (sc_reference(L=8), bcc_block(cells=6, n_steps=10), bcc_film(nx=8, ny=8, nz=4)):
-        with sl.from_workload(w, precision=sl.FP32) as g:
-            assert g.get_option("lattice") == 2
-            assert g.get_option("fused_active") == 0
-            g.set_option("fused", 2)
-            assert g.get_option("fused_active") == 1
-        with sl.from_workload(w, precision=sl.FP64) as g:
-            g.set_option("fused", 2)
-            assert g.get_option("fused_active") == 0
+        for prec in (sl.FP32, sl.FP64):
+            with sl.from_workload(w, precision=prec) as g:
+                assert g.get_option("lattice") == 2
+                assert g.get_option("fused_active") == 0
+                g.set_option("fused", 2)
+                assert g.get_option("fused_active") == 1
+    w = _sc_two_couplings()
+    with sl.from_workload(w, precision=sl.FP32) as g:
+        g.set_option("fused", 2)
+        assert g.get_option("fused_active") == 1
+    with sl.from_workload(w, precision=sl.FP64) as g:
+        g.set_option("fused", 2)
+        assert g.get_option("fused_active") == 0
+        with pytest.raises(sl.SllgError):
+            g.set_option("fused_tile_x", 6)
+            g.set_option("fused_tile_y", 6)
+            g.set_option("fused_planes", 4)
+            g.set_option("fused_threads", 256)
+
+
+def test_generic_kind_fused_fp32_matches_oracle():
+    w = _sc_two_couplings(L=12)
+    w.temperature = 300.0
+    S_ref, m_ref, E_ref = _oracle_run(w, 200)
+    S, m, E = _run(w, 200)
+    r = parity_report("fused sc 12^3 two couplings (generic kind) FP32 200 steps", S, S_ref, m, m_ref, E, E_ref)
+    assert r["max"] <= 2e-5 and r["mean"] <= 5e-6
+    assert r["dm"] <= 5e-7 and r["dE"] <= 1e-6
 
 
 def test_sc4096_fused_fp32_matches_oracle():
@@ -110,6 +144,37 @@ def test_film_open_z_fused_fp32_matches_oracle():
     assert dm <= 5e-7
 
 
+def test_sc4096_fused_fp64_matches_oracle():
+    w = sc_reference(L=16, temperature=300.0, n_steps=1000, seed=42)
+    S_ref, m_ref, E_ref = _oracle_run(w, 1000)
+    S, m, E = _run(w, 1000, precision=sl.FP64)
+    r = parity_report("fused sc 16^3 T=300 K FP64 1000 steps", S, S_ref, m, m_ref, E, E_ref)
+    assert r["max"] <= 1e-12 and r["mean"] <= 1e-13
+    assert r["dm"] <= 1e-12 and r["dE"] <= 1e-12
+    assert np.abs(np.linalg.norm(S, axis=1) - 1).max() <= 1e-15
+
+
+def test_bcc_j1j2_fused_fp64_matches_oracle():
+    w = bcc_block(cells=24, n_steps=300)
+    w.H = np.array([0.3, -0.2, 0.5])
+    S_ref, m_ref, E_ref = _oracle_run(w, 300)
+    S, m, E = _run(w, 300, precision=sl.FP64)
+    r = parity_report("fused bcc 24^3 J1+J2 FP64 300 steps", S, S_ref, m, m_ref, E, E_ref)
+    assert r["max"] <= 1e-12 and r["mean"] <= 1e-13
+    assert r["dm"] <= 1e-12 and r["dE"] <= 1e-12
+
+
+def test_film_open_z_fused_fp64_matches_oracle():
+    w = bcc_film(nx=20, ny=12, nz=7, seed=5)
+    w.temperature = 500.0
+    w.H = np.array([0.0, 0.4, -0.3])
+    S_ref, m_ref, E_ref = _oracle_run(w, 300)
+    S, m, E = _run(w, 300, precision=sl.FP64)
+    r = parity_report("fused film 20x12x7 open z FP64 300 steps", S, S_ref, m, m_ref, E, E_ref)
+    assert r["max"] <= 1e-12 and r["mean"] <= 1e-13
+    assert r["dm"] <= 1e-12 and r["dE"] <= 1e-12
+
+
 @pytest.mark.parametrize("make", [lambda: bcc_block(cells=20, n_steps=50),
                                   lambda: bcc_film(nx=26, ny=14, nz=9, seed=7),
                                   lambda: sc_reference(L=30, temperature=300.0, seed=9)])
@@ -132,12 +197,63 @@ def test_spins_independent_of_shape(make):
         assert np.allclose(E, ref[2], rtol=1e-12, atol=0), shp
 
 
+@pytest.mark.parametrize("make", [lambda: bcc_block(cells=20, n_steps=50),
+                                  lambda: bcc_film(nx=26, ny=14, nz=9, seed=7),
+                                  lambda: sc_reference(L=30, temperature=300.0, seed=9)])
+def test_spins_independent_of_shape_fp64(make):
+    """FP64 shapes (rows of 16 sites for 256 threads, 32 for 512): spins bit
+    for bit the same whatever the tile, planes per item and block size."""
+    w = make()
+    w.temperature = 400.0
+    shapes = [(6, 6, 4, 256), (12, 16, 10, 256), (6, 20, 7, 256), (28, 14, 9, 512), (20, 17, 16, 512),
+              (10, 17, 64, 512)]
+    ref = None
+    for shp in shapes:
+        S, m, E = _run(w, 20, shape=shp, precision=sl.FP64)
+        if ref is None:
+            ref = (S, m, E)
+            continue
+        assert np.array_equal(S, ref[0]), shp
+        assert np.allclose(m, ref[1], rtol=0, atol=1e-14), shp
+        assert np.allclose(E, ref[2], rtol=1e-14, atol=0), shp
+
+
+def test_fp64_shapes_out_of_range_rejected():
+    """FP64: the region must fit a row of 16 (256 threads) or 32 (512)
+    sites, and 1024 threads are not built."""
+    w = bcc_block(cells=20, n_steps=10)
+    for shp in ((14, 8, 4, 256), (30, 8, 4, 512), (20, 20, 4, 1024)):
+        with _fused_system(w, precision=sl.FP64) as g:
+            with pytest.raises(sl.SllgError):
+                for key, v in zip(("fused_tile_x", "fused_tile_y", "fused_planes", "fused_threads"), shp):
+                    g.set_option(key, v)
+
+
 def test_chunked_equals_one_call_bitwise():
     w = bcc_block(cells=12, n_steps=50)
     S1, m1, E1 = _run(w, 37)
     S2, m2, E2 = _run(w, 37, chunks=[1, 2, 11, 23])
     assert np.array_equal(S1, S2)
     assert np.array_equal(m1, m2) and np.array_equal(E1, E2)
+
+
+def test_fp64_chunked_equals_one_call_bitwise():
+    w = bcc_block(cells=12, n_steps=50)
+    S1, m1, E1 = _run(w, 37, precision=sl.FP64)
+    S2, m2, E2 = _run(w, 37, chunks=[1, 2, 11, 23], precision=sl.FP64)
+    assert np.array_equal(S1, S2)
+    assert np.array_equal(m1, m2) and np.array_equal(E1, E2)
+
+
+def test_fp64_fused_agrees_with_two_launch_step():
+    w = bcc_block(cells=16, n_steps=30)
+    Sf, mf, Ef = _run(w, 30, fused=2, precision=sl.FP64)
+    St, mt, Et = _run(w, 30, fused=0, precision=sl.FP64)
+    ang = max_angle(Sf, St)
+    print(f"fused vs two-launch FP64, 30 steps: max angle {ang:.3e}")
+    assert ang <= 1e-13
+    assert np.abs(mf - mt).max() <= 1e-13
+    assert (np.abs(Ef - Et) / np.abs(Et)).max() <= 1e-13
 
 
 def test_fused_agrees_with_two_launch_step():
