@@ -675,11 +675,19 @@ def main():
     if r64 is not None:
         ms64 = r64["ms"] / args.steps
         b64 = algorithmic_bytes_per_spin_step(8, deg)
+        fused64 = bool(r64["launch"].get("fused"))
+        shape64 = r64["launch"].get("fused_shape") if fused64 else None
+        traffic64 = None if (dmi or lr or not fused64) else profile_value("fused", "fp64_hbm_bytes_per_step", shape64)
         out["fp64"] = {
             "value": n * args.steps / (r64["ms"] / 1e3),
             "ms_per_step": ms64,
             "roofline_achieved_GBs": b64 * n / (ms64 / 1e3) / 1e9,
+            "roofline_frac": b64 * n / (ms64 / 1e3) / 1e9 / HBM_PEAK_GBS,
             "algorithmic_bytes_per_spin_step": b64,
+            "kernel": ("fused Heun step k_fused<double> (one launch per step)" if fused64 else
+                       "Heun step (predictor + corrector launches)"),
+            "launch_shape": r64["launch"],
+            "traffic": None if traffic64 is None else traffic64 * n,
         }
         dm = np.abs(r32["m"] - r64["m"]).max()
         dE = (np.abs(r32["E"] - r64["E"]) / np.abs(r64["E"])).max()
