@@ -405,7 +405,13 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *   "stencil"         1 (default) / 0: let the next sllg_set_neighbours store
  *                     the list as per-site stencil patterns when at most 256
  *                     distinct (column - row, type) rows occur (<= 1024
- *                     entries in all); 0 keeps the general SELL-64 form
+ *                     entries in all, tables in LDS), else as wide stencil
+ *                     patterns when at most 65535 occur (<= 2^22 entries
+ *                     with every pattern padded to the longest; tables in
+ *                     global memory: periodic long-range lattices); 0 keeps
+ *                     the general SELL-64 form.  The sums are the same in
+ *                     every form (near links, then far ones, each in row
+ *                     order)
  *   "fused"           1 (default): integrate with the fused step when the
  *                     system qualifies (sllg_set_lattice) and has at least
  *                     2^20 spins (smaller systems run faster with the
@@ -424,7 +430,8 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     autotuner also picks among shapes).  Results do not
  *                     depend on the shape except the m and E records, at FP64
  *                     rounding.
- * sllg_get_option also reads "neighbour_format": 1 stencil, 0 SELL, -1 unset;
+ * sllg_get_option also reads "neighbour_format": 1 stencil, 2 wide stencil,
+ * 0 SELL, -1 unset;
  * "lattice": 0 none declared, 1 declared, 2 declared and the fused step can
  * take its structure; "fused_active": 1 when the next integration runs the
  * fused step; the fused_* shape keys read the shape in use;

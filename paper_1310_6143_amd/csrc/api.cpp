@@ -1606,7 +1606,7 @@ sllg_status sllg_get_option(const sllg_system* sys, const char* key, int64_t* va
     else if (k == "tuned_ns_per_step")
         *value = sys->tuned ? (int64_t)(sys->tuned_us * 1e3) : -1;
     else if (k == "neighbour_format")
-        *value = sys->has_nb ? (sys->st.stencil ? 1 : 0) : -1;
+        *value = sys->has_nb ? (sys->st.stencil ? 1 : sys->st.wide ? 2 : 0) : -1;
     else if (k == "fused")
         *value = sys->opt_fused;
     else if (k == "lattice")

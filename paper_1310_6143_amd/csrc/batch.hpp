@@ -263,6 +263,8 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
     size_t b = 3 * r(spin_buffer_bytes(s.n, real_bytes) + 16);  // S[2], Sp
     if (s.stencil)
         b += r(pad16(n)) + r(s.pat_tab.size() * 4) + r(s.pat_start.size() * 2) + r(s.pat_far.size() * 2);
+    else if (s.wide)
+        b += r(2 * n) + r(s.w_tab.size() * 4) + r(s.w_near.size() * 2);
     else
         b += r(s.nb.size() * 4) + r(s.slice_off.size() * 8) + r(4 * n);
     if (!s.colour_sites.empty())
@@ -485,7 +487,21 @@ public:
             r.pat_tab = nullptr;
             r.pat_start = nullptr;
             r.pat_far = nullptr;
-            if (s.stencil) {
+            r.w_pid = nullptr;
+            r.w_tab = nullptr;
+            r.w_near = nullptr;
+            if (s.wide) {
+                uint16_t* pid = (uint16_t*)get(2 * n);
+                int32_t* tab = (int32_t*)get(s.w_tab.size() * 4);
+                uint16_t* nn = (uint16_t*)get(s.w_near.size() * 2);
+                hip_check(hipMemcpy(pid, s.w_pid.data(), 2 * n, hipMemcpyHostToDevice), "upload pattern ids");
+                hip_check(hipMemcpy(tab, s.w_tab.data(), s.w_tab.size() * 4, hipMemcpyHostToDevice), "upload patterns");
+                hip_check(hipMemcpy(nn, s.w_near.data(), s.w_near.size() * 2, hipMemcpyHostToDevice),
+                          "upload pattern splits");
+                r.w_pid = pid;
+                r.w_tab = tab;
+                r.w_near = nn;
+            } else if (s.stencil) {
                 uint8_t* pid = (uint8_t*)get(pad16(n));
                 int32_t* tab = (int32_t*)get(std::max<size_t>(s.pat_tab.size(), 1) * 4);
                 uint16_t* ps = (uint16_t*)get(s.pat_start.size() * 2);
@@ -791,9 +807,10 @@ public:
             if (!sl.used)
                 continue;
             const ReplicaDev<R>& r = sl.rec;
-            const bool stencil = (r.flags & kStencil) != 0;
-            if ((stencil && (!r.pat_id || !r.pat_tab || !r.pat_start || !r.pat_far)) ||
-                (!stencil && (!r.nb || !r.slice_off || !r.deg)) ||
+            const bool stencil = (r.flags & kStencil) != 0, wide = (r.flags & kWide) != 0;
+            if ((stencil && wide) || (stencil && (!r.pat_id || !r.pat_tab || !r.pat_start || !r.pat_far)) ||
+                (wide && (!r.w_pid || !r.w_tab || !r.w_near || r.w_len <= 0 || r.n_patterns <= 0)) ||
+                (!stencil && !wide && (!r.nb || !r.slice_off || !r.deg)) ||
                 ((r.flags & kPerSiteMaterial) && !r.matid) || ((r.flags & kPerSiteAxis) && !r.axis) ||
                 ((r.flags & kAverage) && (!(r.flags & kRecord) || !r.acc)))
                 fail(SLLG_E_STATE, "replica flags do not match its buffers");

@@ -259,7 +259,50 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
 {
     V3<R> hn{0, 0, 0}, hf{0, 0, 0};
     const bool tensor = TX && (r.flags & kTensor);
-    if (r.flags & kStencil) {
+    if (r.flags & kWide) {
+        // Wide stencil: entry k of the site's pattern p at w_tab[k * patterns
+        // + p], read through the L2 (the lanes of a wavefront, neighbouring
+        // sites, mostly share a few patterns with adjacent numbers); near
+        // links from the window, far ones from global memory, each part in
+        // the row's order, kSellBatch entries and then their spins in
+        // flight together.  Byte offsets fit in 31 bits in this form.
+        const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, r.n * (int)(3 * sizeof(R)));
+        const int ib = (i - l) * (int)(3 * sizeof(R)) + site_bytes<R>(l);
+        const int p = (int)gload(r.w_pid, i);
+        const int nn = (int)gload(r.w_near, p), len = r.w_len;
+        const int32_t* __restrict__ tab = r.w_tab + p;
+        const int64_t np = r.n_patterns;
+        overlap();
+        for (int k = 0; k < nn; k += kSellBatch) {
+            int32_t raw[kSellBatch];
+#pragma unroll
+            for (int u = 0; u < kSellBatch; ++u)
+                raw[u] = gload(tab, (int64_t)(k + u < nn ? k + u : nn - 1) * np);
+#pragma unroll
+            for (int u = 0; u < kSellBatch; ++u) {
+                const int off = (raw[u] >> 4) * (int)(3 * sizeof(R));
+                const V3<R> sj = (r.flags & kDirect) ? bload3(rs, ib + off, R(0)) : wload3(tl.win, wbyte + off);
+                const int t = k + u < nn ? (raw[u] & 15) : kMaxTypes;
+                add_coupled<R, TX>(hn, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj);
+            }
+        }
+        for (int k = nn; k < len; k += kSellBatch) {
+            int32_t raw[kSellBatch];
+#pragma unroll
+            for (int u = 0; u < kSellBatch; ++u)
+                raw[u] = gload(tab, (int64_t)(k + u < len ? k + u : len - 1) * np);
+            V3<R> sj[kSellBatch];
+#pragma unroll
+            for (int u = 0; u < kSellBatch; ++u)
+                sj[u] = bload3(rs, ib + (raw[u] >> 4) * (int)(3 * sizeof(R)), R(0));
+#pragma unroll
+            for (int u = 0; u < kSellBatch; ++u) {
+                // past the row's end, or offset 0 (past the pattern's end): no link
+                const int t = k + u < len && (raw[u] >> 4) != 0 ? (raw[u] & 15) : kMaxTypes;
+                add_coupled<R, TX>(hf, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj[u]);
+            }
+        }
+    } else if (r.flags & kStencil) {
         // byte offsets fit in 31 bits in the stencil form
         const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, r.n * (int)(3 * sizeof(R)));
         const int ib = (i - l) * (int)(3 * sizeof(R)) + site_bytes<R>(l);
@@ -997,8 +1040,8 @@ __global__ void k_noise(uint64_t seed, uint64_t step, int n, double* __restrict_
 // ---------------------------------------------------------------------------
 
 // sum_k J_k S[j_k] / mu_ref over the neighbours of site i, the spins
-// straight from global memory.  Pattern tables come from LDS; neighbours are
-// taken kMcBatch at a time, every load of a batch issued before the first is
+// straight from global memory.  Pattern tables come from LDS (the wide
+// form's from global memory); neighbours are taken kMcBatch at a time, every load of a batch issued before the first is
 // used (entries past the end repeat the last one with J = 0), and added in
 // table order.
 constexpr int kMcBatch = 8;
@@ -1010,6 +1053,31 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
     V3<R> h{0, 0, 0};
     const char* sb = (const char*)S;
     const bool tensor = TX && (r.flags & kTensor);
+    if (r.flags & kWide) {
+        // the pattern's entries in table order (near links, then far ones)
+        const int p = (int)gload(r.w_pid, i);
+        const int len = r.w_len;
+        const int32_t* __restrict__ tab = r.w_tab + p;
+        const int64_t np = r.n_patterns;
+        const char* si = sb + (int64_t)i * (3 * sizeof(R));
+        for (int k = 0; k < len; k += kMcBatch) {
+            int32_t raw[kMcBatch];
+#pragma unroll
+            for (int u = 0; u < kMcBatch; ++u)
+                raw[u] = gload(tab, (int64_t)(k + u < len ? k + u : len - 1) * np);
+            V3<R> sj[kMcBatch];
+#pragma unroll
+            for (int u = 0; u < kMcBatch; ++u)
+                sj[u] = load3((const R*)(si + (int64_t)(raw[u] >> 4) * (int64_t)(3 * sizeof(R))), 0);
+#pragma unroll
+            for (int u = 0; u < kMcBatch; ++u) {
+                // past the row's end, or offset 0 (past the pattern's end): no link
+                const int t = k + u < len && (raw[u] >> 4) != 0 ? (raw[u] & 15) : kMaxTypes;
+                add_coupled<R, TX>(h, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj[u]);
+            }
+        }
+        return h;
+    }
     if (r.flags & kStencil) {
         const int p = gload(r.pat_id, i);
         const int b = sh.pat_start[p], e = sh.pat_start[p + 1];

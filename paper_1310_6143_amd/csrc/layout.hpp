@@ -82,6 +82,10 @@ constexpr int kMaxPatterns = 256;
 // the host pads every pattern's far part to at least this many entries
 // (offset 0, J = 0) unless no pattern has any far link.
 constexpr int kFarRegs = 6;
+// Wide stencil form (kWide): patterns and entries (all patterns padded to
+// the longest) it takes at most.
+constexpr int kWideMaxPatterns = 65535;
+constexpr int kWideMaxEntries = 1 << 22;
 #ifndef SLLG_MAX_PATTERN_ENTRIES
 #define SLLG_MAX_PATTERN_ENTRIES 1024
 #endif
@@ -115,6 +119,7 @@ enum ReplicaFlags : int32_t {
     kDemag = 1024,          // macrocell demagnetising field dm_field[dm_cell[i]] added to every site
     kLongRows = 2048,       // SELL rows longer than kLongRow links: batched gathers (general variant)
     kFused = 4096,          // the lattice runs the fused plane-marching step (f_* fields)
+    kWide = 8192,           // neighbours in the wide stencil form (w_pid / w_tab in global memory)
 };
 
 // Rows longer than this take the batched gathers of the general variant.
@@ -248,7 +253,10 @@ struct ReplicaDev {
     int32_t flags;                  // ReplicaFlags
     int32_t n_patterns;             // stencil patterns (kStencil)
     int32_t tile;                   // sites per tile: tile_for(n, sizeof(R))
-    int32_t pad1;
+    int32_t w_len;                  // entries per pattern in the wide form (kWide)
+    const uint16_t* w_pid;          // [n] pattern of each site (kWide)
+    const int32_t* w_tab;           // [w_len][n_patterns] packed offset << 4 | type, transposed (kWide)
+    const uint16_t* w_near;         // [n_patterns] near entries of each pattern (kWide)
     // fused plane-marching step (kFused)
     const void* f_ent;              // FusedEntry (FP32) / FusedEntryD (FP64) of every pattern
     const int32_t* f_pat;           // [patterns][4]: first entry, entries with dz = -1, 0, +1

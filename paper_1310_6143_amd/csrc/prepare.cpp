@@ -116,20 +116,26 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
 
     // Stencil form: the interaction list of a row, written relative to the
     // row, repeats across a crystal (the paper builds it from the unit
-    // cell's neighbour template), so few patterns cover every row.
+    // cell's neighbour template), so few patterns cover every row.  Up to
+    // kMaxPatterns patterns of kMaxPatternEntries entries in all are staged
+    // in LDS; more (periodic images of long-range rows: one pattern per
+    // combination of boundary distances) take the wide form, whose table
+    // stays in global memory (read through the L2), transposed so that the
+    // lanes of a wavefront read entry k of their patterns side by side.
     {
         std::unordered_map<std::string, int> ids;
-        std::vector<uint8_t> pid((size_t)n);
-        std::vector<int32_t> tab;
-        std::vector<uint16_t> start{0}, far;
+        std::vector<uint16_t> pid((size_t)n);
+        std::vector<std::string> keys;   // per pattern: near count, then the packed entries
         std::string key;
-        bool ok = allow_stencil;
-        // Far parts are padded to kFarRegs entries (offset 0: never a real
-        // link, self links are rejected above) unless no row has far links.
+        bool ok = allow_stencil && n * 24 <= 0x7FFFF000;
+        // Far parts of the LDS form are padded to kFarRegs entries (offset
+        // 0: never a real link, self links are rejected above) unless no
+        // row has far links.
         bool any_far = false;
         for (int64_t i = 0; i < n && !any_far; ++i)
             any_far = n_near[(size_t)i] < row_ptr[i + 1] - row_ptr[i];
         const size_t far_min = any_far ? (size_t)kFarRegs : 0;
+        size_t lds_entries = 0, longest = 0;
         for (int64_t i = 0; i < n && ok; ++i) {
             key.clear();
             key.append(reinterpret_cast<const char*>(&n_near[(size_t)i]), sizeof(uint16_t));
@@ -137,7 +143,7 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
                 const int64_t q = order[(size_t)p];
                 const int64_t off = (int64_t)col[q] - i;
                 const int32_t t = ntype ? ntype[q] : 0;
-                if (off < -(int64_t(1) << 27) || off >= (int64_t(1) << 27) || n * 24 > 0x7FFFF000) {
+                if (off < -(int64_t(1) << 27) || off >= (int64_t(1) << 27)) {
                     ok = false;
                     break;
                 }
@@ -149,34 +155,65 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
             auto it = ids.find(key);
             if (it == ids.end()) {
                 const int id = (int)ids.size();
+                const size_t cnt = (key.size() - sizeof(uint16_t)) / sizeof(int32_t);
                 uint16_t nn;
                 std::memcpy(&nn, key.data(), sizeof(nn));
-                const size_t cnt = (key.size() - sizeof(uint16_t)) / sizeof(int32_t);
                 const size_t n_far = cnt - nn;
-                const size_t pad = n_far < far_min ? far_min - n_far : 0;
-                if (id >= kMaxPatterns || tab.size() + cnt + pad > (size_t)kMaxPatternEntries) {
+                lds_entries += cnt + (n_far < far_min ? far_min - n_far : 0);
+                longest = std::max(longest, cnt);
+                if (id >= kWideMaxPatterns || (size_t)(id + 1) * longest > (size_t)kWideMaxEntries) {
                     ok = false;
                     break;
                 }
                 it = ids.emplace(key, id).first;
-                far.push_back((uint16_t)(tab.size() + nn));
-                for (size_t c = 0; c < cnt; ++c) {
-                    int32_t e;
-                    std::memcpy(&e, key.data() + sizeof(uint16_t) + c * sizeof(int32_t), sizeof(e));
-                    tab.push_back(e);
-                }
-                tab.insert(tab.end(), pad, 0);
-                start.push_back((uint16_t)tab.size());
+                keys.push_back(key);
             }
-            pid[(size_t)i] = (uint8_t)it->second;
+            pid[(size_t)i] = (uint16_t)it->second;
         }
-        if (ok) {
+        auto entry = [&](const std::string& k, size_t c) {
+            int32_t e;
+            std::memcpy(&e, k.data() + sizeof(uint16_t) + c * sizeof(int32_t), sizeof(e));
+            return e;
+        };
+        auto near_count = [&](const std::string& k) {
+            uint16_t nn;
+            std::memcpy(&nn, k.data(), sizeof(nn));
+            return nn;
+        };
+        if (ok && keys.size() <= (size_t)kMaxPatterns && lds_entries <= (size_t)kMaxPatternEntries) {
             s.stencil = true;
-            s.pat_id = std::move(pid);
-            s.pat_tab = std::move(tab);
-            s.pat_start = std::move(start);
-            s.pat_far = std::move(far);
+            s.pat_id.resize((size_t)n);
+            for (int64_t i = 0; i < n; ++i)
+                s.pat_id[(size_t)i] = (uint8_t)pid[(size_t)i];
+            s.pat_start.assign(1, 0);
+            for (const std::string& k : keys) {
+                const size_t cnt = (k.size() - sizeof(uint16_t)) / sizeof(int32_t);
+                const uint16_t nn = near_count(k);
+                s.pat_far.push_back((uint16_t)(s.pat_tab.size() + nn));
+                for (size_t c = 0; c < cnt; ++c)
+                    s.pat_tab.push_back(entry(k, c));
+                const size_t n_far = cnt - nn;
+                s.pat_tab.insert(s.pat_tab.end(), n_far < far_min ? far_min - n_far : 0, 0);
+                s.pat_start.push_back((uint16_t)s.pat_tab.size());
+            }
             s.no_far = !any_far;
+            return s;
+        }
+        if (ok && !keys.empty()) {
+            // entry c of pattern p at w_tab[c * patterns + p]; patterns
+            // shorter than the longest end in entries of offset 0 (J = 0)
+            const size_t np = keys.size();
+            s.wide = true;
+            s.w_len = (int)longest;
+            s.w_pid = std::move(pid);
+            s.w_tab.assign(longest * np, 0);
+            s.w_near.resize(np);
+            for (size_t p = 0; p < np; ++p) {
+                const size_t cnt = (keys[p].size() - sizeof(uint16_t)) / sizeof(int32_t);
+                s.w_near[p] = near_count(keys[p]);
+                for (size_t c = 0; c < cnt; ++c)
+                    s.w_tab[c * np + p] = entry(keys[p], c);
+            }
             return s;
         }
     }
@@ -217,6 +254,16 @@ static void for_each_link(const HostStructure& s, int64_t i, F&& fn)
             const int32_t raw = s.pat_tab[(size_t)e];
             const int32_t off = raw >> 4;
             if (off != 0)   // offset 0: padding of the far part, never a link
+                fn(i + off, raw & 15);
+        }
+        return;
+    }
+    if (s.wide) {
+        const size_t np = s.w_near.size(), p = s.w_pid[(size_t)i];
+        for (int e = 0; e < s.w_len; ++e) {
+            const int32_t raw = s.w_tab[(size_t)e * np + p];
+            const int32_t off = raw >> 4;
+            if (off != 0)   // offset 0: past the pattern's end, never a link
                 fn(i + off, raw & 15);
         }
         return;
@@ -701,13 +748,15 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
         flags |= kStencil;
     if (s.stencil && s.no_far)
         flags |= kNoFar;
+    if (s.wide)
+        flags |= kWide;
     if (s.tensor)
         flags |= kTensor;
     if (m.cubic)
         flags |= kCubic;
     if (s.demag.on)
         flags |= kDemag;
-    if (!s.stencil && s.long_rows)
+    if (!s.stencil && !s.wide && s.long_rows)
         flags |= kLongRows;
     // the fused step: a lattice it takes in this precision, uniform
     // materials, scalar exchange and no cubic anisotropy or demagnetising
@@ -730,7 +779,8 @@ void fill_parameters(ReplicaDev<R>& rec, const HostStructure& s, const HostMater
     for (const auto& p : s.lat.pats)
         nent += (int32_t)p.size();
     rec.f_nent = nent;
-    rec.n_patterns = s.stencil ? (int32_t)s.pat_start.size() - 1 : 0;
+    rec.n_patterns = s.stencil ? (int32_t)s.pat_start.size() - 1 : s.wide ? (int32_t)s.w_near.size() : 0;
+    rec.w_len = s.wide ? s.w_len : 0;
     rec.dm_cells = s.demag.on ? (int32_t)s.demag.cells : 0;
     rec.dm_chunks = s.demag.on ? demag_chunks(s.demag.cells) : 0;
 }

@@ -126,6 +126,14 @@ struct HostStructure {
     std::vector<uint16_t> pat_start;   // [n_patterns + 1]
     std::vector<uint16_t> pat_far;     // [n_patterns] first far entry of each pattern
     bool no_far = false;               // no pattern has a far link (no padding then)
+    // wide stencil form, filled when the patterns exceed the LDS tables
+    // (kMaxPatterns, kMaxPatternEntries) but not kWideMaxPatterns /
+    // kWideMaxEntries: the table stays in global memory
+    bool wide = false;
+    int w_len = 0;                     // entries of the longest pattern
+    std::vector<uint16_t> w_pid;       // [n] pattern of each site
+    std::vector<int32_t> w_tab;        // [w_len][patterns] packed (col - row) << 4 | type; 0 past a pattern's end
+    std::vector<uint16_t> w_near;      // [patterns] near entries (the first ones) of each pattern
     // macrocell demagnetising field (set_demag)
     HostDemag demag;
     // Monte Carlo colour classes (build_colours): sites sorted by colour
@@ -148,7 +156,8 @@ void set_lattice(HostStructure& s, int nb, const int cells[3], const int periodi
 int tile_of(const HostStructure& s, size_t real_bytes);
 
 // Validates and converts.  Throws Failure(SLLG_E_ARG) on malformed input.
-// allow_stencil = false keeps the SELL form even when patterns would fit.
+// allow_stencil = false keeps the SELL form even when patterns would fit
+// (LDS stencil or wide stencil).
 // halo_cap (a multiple of 4) bounds the offsets read from the LDS window.
 HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* col,
                               const uint8_t* ntype, const double* J, int n_types,

@@ -86,31 +86,32 @@ def test_full_size_block_matches_oracle():
     S_ref, m_ref, E_ref = _oracle(w, 3)
     # m and E are sums over 8.2M sites: the oracle adds them one by one, the
     # GPU as a tree, so FP64 records agree to about N * eps = 2e-9 at worst
-    # FP32: the fused step in the library's default shape and in the shape
-    # the autotuner picks on the benchmark box, and the two-launch step
-    # (measured: FP64 3.4e-16 rad, |dm| 1.2e-11; FP32 4.5e-6 rad at one site,
-    # mean 1.2e-8, |dm| and |dE|/|E| 3.7e-9)
-    runs = ((sl.FP64, 1, None, 1e-13, 1e-10, 1e-12), (sl.FP32, 1, None, 1e-5, 5e-8, 5e-8),
+    # The fused step in the library's default shape and in the shape the
+    # autotuner picks on the benchmark box, and the two-launch step, in both
+    # precisions (measured: FP64 3.4e-16 rad, |dm| 1.2e-11; FP32 4.5e-6 rad
+    # at one site, mean 1.2e-8, |dm| and |dE|/|E| 3.7e-9)
+    runs = ((sl.FP64, 1, None, 1e-13, 1e-10, 1e-12), (sl.FP64, 1, (27, 15, 23, 512), 1e-13, 1e-10, 1e-12),
+            (sl.FP64, 0, None, 1e-13, 1e-10, 1e-12), (sl.FP32, 1, None, 1e-5, 5e-8, 5e-8),
             (sl.FP32, 1, (40, 10, 20, 512), 1e-5, 5e-8, 5e-8), (sl.FP32, 0, None, 1e-5, 5e-8, 5e-8))
-    fused_spins = None
+    fused_spins = {}
     for prec, fused, shape, ang_tol, m_tol, e_tol in runs:
         with sl.from_workload(w, precision=prec, check_symmetry=False) as g:
             g.set_option("fused", fused)
             if shape:
                 for key, v in zip(("fused_tile_x", "fused_tile_y", "fused_planes", "fused_threads"), shape):
                     g.set_option(key, v)
-            assert g.get_option("fused_active") == (fused if prec == sl.FP32 else 0)
-            if not g.get_option("fused_active"):
+            assert g.get_option("fused_active") == fused
+            if not fused:
                 assert g.get_option("tile_sites") == (2048 if prec == sl.FP32 else 1024)
             m, E = g.integrate(3)
             S = g.get_spins()
         label = f"full bcc block {'FP32' if prec == sl.FP32 else 'FP64'} fused={fused} shape={shape} 3 steps"
         ang = parity_report(label, S, S_ref, m, m_ref, E, E_ref)["max"]
-        if prec == sl.FP32 and fused:
-            if fused_spins is None:
-                fused_spins = S
+        if fused:
+            if prec not in fused_spins:
+                fused_spins[prec] = S
             else:
-                assert np.array_equal(S, fused_spins)     # spins do not depend on the fused shape
+                assert np.array_equal(S, fused_spins[prec])     # spins do not depend on the fused shape
         assert ang <= ang_tol
         assert np.abs(m - m_ref).max() <= m_tol
         assert np.abs(E - E_ref).max() <= e_tol * np.abs(E_ref).max()

@@ -1,9 +1,11 @@
 """GPU parity for long-range exchange (hundreds of partners per site, the
 paper's remark on exchange reaching several lattice spacings): rows of 388
 links in 16 radial types against the FP64 oracle; Heun steps and Monte Carlo
-chains.  The periodic images give 9 row patterns per axis (729 > 256), so
-the rows take the SELL form; links within the halo come from the LDS
-window (lds_window 1) or every link from memory (lds_window 0).
+chains.  The periodic images give 9 row patterns per axis (729 > 256), too
+many for the LDS stencil tables, so the rows take the wide stencil form
+(pattern tables in global memory) by default and the SELL form with the
+stencil option off; links within the halo come from the LDS window
+(lds_window 1) or every link from memory (lds_window 0).
 """
 import numpy as np
 import pytest
@@ -31,32 +33,68 @@ def test_long_range_rows_are_388_links():
     assert w.J.size == 16
 
 
+FORMS = [(1, 2), (0, 0)]   # (stencil option, neighbour_format): wide stencil, SELL
+
+
+@pytest.mark.parametrize("stencil,fmt", FORMS)
 @pytest.mark.parametrize("window", [1, 0])
-def test_long_range_heun_matches_oracle(window):
+def test_long_range_heun_matches_oracle(window, stencil, fmt):
     w = _system()
     S_ref = np.ascontiguousarray(w.S0.copy())
     m_ref, E_ref = oracle.System(w).integrate(S_ref, 0, 300)
-    with sl.from_workload(w, precision=sl.FP64) as g:
-        assert g.get_option("neighbour_format") == 0
+    with sl.from_workload(w, precision=sl.FP64, stencil=stencil) as g:
+        assert g.get_option("neighbour_format") == fmt
         g.set_option("lds_window", window)
         m, E = g.integrate(300)
         S = g.get_spins()
-    r = parity_report(f"long range FP64 lds_window={window} 300 steps", S, S_ref, m, m_ref, E, E_ref)
+    r = parity_report(f"long range FP64 format={fmt} lds_window={window} 300 steps", S, S_ref, m, m_ref, E, E_ref)
     assert r["max"] <= 1e-13 and r["dm"] <= 1e-13 and r["dE"] <= 1e-13   # measured 1e-15, 4.7e-15, 3.5e-15
-    with sl.from_workload(w, precision=sl.FP32) as g:
+    with sl.from_workload(w, precision=sl.FP32, stencil=stencil) as g:
+        assert g.get_option("neighbour_format") == fmt
         g.set_option("lds_window", window)
         m32, E32 = g.integrate(300)
         S32 = g.get_spins()
-    r = parity_report(f"long range FP32 lds_window={window} 300 steps", S32, S_ref, m32, m_ref, E32, E_ref)
+    r = parity_report(f"long range FP32 format={fmt} lds_window={window} 300 steps", S32, S_ref, m32, m_ref, E32,
+                      E_ref)
     assert r["max"] <= 5e-6 and r["mean"] <= 1e-6                       # measured 2.5e-7, 9e-8
     assert r["dm"] <= 1e-6 and r["dE"] <= 1e-6                          # measured 7.5e-8, 5.2e-8
 
 
-def test_long_range_mc_chain_matches_oracle():
+def test_wide_stencil_equals_sell():
+    """The two forms add the same links in the same order: the same
+    trajectory (FP64 and FP32), the same Monte Carlo chain."""
+    w = _system()
+    out = {}
+    for stencil, fmt in FORMS:
+        for prec in (sl.FP64, sl.FP32):
+            with sl.from_workload(w, precision=prec, stencil=stencil) as g:
+                assert g.get_option("neighbour_format") == fmt
+                m, E = g.integrate(50)
+                out[(fmt, prec)] = (g.get_spins(), m, E)
+    for prec, tol in ((sl.FP64, 1e-14), (sl.FP32, 1e-6)):
+        a, b = out[(2, prec)], out[(0, prec)]
+        ang = max_angle(a[0], b[0])
+        print(f"wide vs SELL {'FP64' if prec == sl.FP64 else 'FP32'}, 50 steps: max angle {ang:.2e}, "
+              f"bitwise {np.array_equal(a[0], b[0])}")
+        assert ang <= tol
+        assert np.abs(a[1] - b[1]).max() <= tol
+    w = _system(T=900.0, seed=7)
+    chains = []
+    for stencil, fmt in FORMS:
+        with sl.from_workload(w, precision=sl.FP64, stencil=stencil) as g:
+            assert g.get_option("neighbour_format") == fmt
+            _, _, acc = g.mc(5)
+            chains.append((acc, g.get_spins()))
+    assert np.array_equal(chains[0][0], chains[1][0])
+    assert max_angle(chains[0][1], chains[1][1]) <= 1e-14
+
+
+@pytest.mark.parametrize("stencil", [1, 0])
+def test_long_range_mc_chain_matches_oracle(stencil):
     w = _system(T=900.0, seed=7)
     S_ref = np.ascontiguousarray(w.S0.copy())
     m_ref, E_ref, acc_ref = oracle.System(w).mc(S_ref, 0, 10)
-    with sl.from_workload(w, precision=sl.FP64) as g:
+    with sl.from_workload(w, precision=sl.FP64, stencil=stencil) as g:
         m, E, acc = g.mc(10)
         S = g.get_spins()
     assert np.array_equal(acc, acc_ref)
@@ -70,9 +108,12 @@ def test_long_range_at_benchmark_size():
     w = long_range_sc(L=64, r_cut=4.5)
     S_ref = np.ascontiguousarray(w.S0.copy())
     oracle.System(w).integrate(S_ref, 0, 3, record=False)
-    for prec, tol in ((sl.FP64, 1e-14), (sl.FP32, 5e-6)):     # measured 2.2e-16, 2.3e-7
-        with sl.from_workload(w, precision=prec) as g:
-            g.integrate(3, record=False)
-            ang = max_angle(g.get_spins(), S_ref)
-        print(f"long range 64^3 {'FP64' if prec == sl.FP64 else 'FP32'}: max angle {ang:.2e} after 3 steps")
-        assert ang <= tol
+    for stencil, fmt in FORMS:
+        for prec, tol in ((sl.FP64, 1e-14), (sl.FP32, 5e-6)):     # measured 2.2e-16, 2.3e-7
+            with sl.from_workload(w, precision=prec, stencil=stencil) as g:
+                assert g.get_option("neighbour_format") == fmt
+                g.integrate(3, record=False)
+                ang = max_angle(g.get_spins(), S_ref)
+            print(f"long range 64^3 format={fmt} {'FP64' if prec == sl.FP64 else 'FP32'}: max angle {ang:.2e} "
+                  "after 3 steps")
+            assert ang <= tol
