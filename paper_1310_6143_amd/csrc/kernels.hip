@@ -1132,7 +1132,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __res
         acc_block = 0;
     stage_tables<R, TX>(r, sh);
     __syncthreads();
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    // Workgroups are handed to the 8 XCDs round-robin, and each XCD has its
+    // own L2.  Sites of neighbouring chunks of the class list share
+    // neighbours (cells one row or plane apart), so XCD x takes a
+    // contiguous range of chunks: workgroup b takes chunk
+    // start(b mod 8) + b / 8, a one-to-one map of 0..G-1.
+    const int G = (int)gridDim.x, q = G >> 3, rem = G & 7, x = (int)blockIdx.x & 7;
+    const int chunk = x * q + (x < rem ? x : rem) + ((int)blockIdx.x >> 3);
+    const int t = chunk * (int)blockDim.x + (int)threadIdx.x;
     if (t < count) {
         const int i = gload(sites, t);
         R* __restrict__ S = r.S[r.parity];
