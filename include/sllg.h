@@ -90,6 +90,40 @@ const char *sllg_status_string(sllg_status status);
 sllg_status sllg_set_neighbours(sllg_system *sys, const int64_t *row_ptr, const int32_t *col,
                                 const uint8_t *ntype, const double *J, int n_types);
 
+/* Convenience builders of the paper's test structures (appendix
+ * "Atomistic system generation": a unit cell replicated on a grid of cells,
+ * optionally cut to a shape, every site's exchange partners from the cell's
+ * neighbour template) as CSR lists for sllg_set_neighbours.  Host only, no
+ * device and no handle; errors go to sllg_last_error(NULL).  Rows are
+ * sorted by column, then type.  Two calls: with row_ptr, col, type and pos
+ * all NULL they store the number of sites in *n and of links in *nnz; then,
+ * with *n and *nnz unchanged, they fill the caller's row_ptr[n + 1],
+ * col[nnz] and, when not NULL, type[nnz] and pos[3n] (site positions in
+ * units of the cubic cell edge a).  SLLG_E_ARG for NULL n or nnz, bad
+ * sizes, counts that differ from the first call's, or more than 2^28 - 1
+ * sites; SLLG_E_NOMEM when host memory runs out.
+ *
+ * sllg_build_sc: simple cubic, cells[0] x cells[1] x cells[2] sites, site
+ * i = x + cells[0] (y + cells[1] z), the 6 nearest neighbours (type 0);
+ * periodic[a] != 0 wraps axis a (which then needs at least 3 cells).
+ * sllg_build_bcc: body-centred cubic, 2 sites per cell, i = b + 2 (x +
+ * cells[0] (y + cells[1] z)) with b = 0 at the cell corner and b = 1 at its
+ * centre: the 8 first neighbours at a sqrt(3)/2 (type 0) and, with
+ * second_neighbours != 0, the 6 second neighbours at a (type 1).  Both
+ * number their sites as sllg_set_lattice declares them (n_basis 1 or 2), so
+ * the block can take the fused step.
+ * sllg_build_fcc_sphere: a sphere cut from an fcc crystal of lattice
+ * constant a_nm, centred on a site: the sites (x, y, z) a/2 with x + y + z
+ * even at most radius_nm + 1e-9 nm from the centre, numbered by z, then y,
+ * then x; the 12 nearest neighbours at a / sqrt(2) inside the sphere
+ * (type 0), fewer at the surface. */
+sllg_status sllg_build_sc(const int cells[3], const int periodic[3], int64_t *n, int64_t *nnz, int64_t *row_ptr,
+                          int32_t *col, uint8_t *type, double *pos);
+sllg_status sllg_build_bcc(const int cells[3], const int periodic[3], int second_neighbours, int64_t *n,
+                           int64_t *nnz, int64_t *row_ptr, int32_t *col, uint8_t *type, double *pos);
+sllg_status sllg_build_fcc_sphere(double a_nm, double radius_nm, int64_t *n, int64_t *nnz, int64_t *row_ptr,
+                                  int32_t *col, uint8_t *type, double *pos);
+
 /* Lattice numbering (section "Atomistic system generation": a unit cell of
  * n_basis sites replicated on a grid of cells[0] x cells[1] x cells[2]
  * cells).  Declares that site i of the current neighbour list is basis site

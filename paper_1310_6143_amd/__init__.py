@@ -32,7 +32,7 @@ EXPORTS = [
     "sllg_set_option", "sllg_get_option",
     "sllg_server_create", "sllg_server_destroy", "sllg_server_last_error", "sllg_submit",
     "sllg_poll", "sllg_wait", "sllg_fetch", "sllg_cancel", "sllg_release", "sllg_server_get_stats",
-    "sllg_server_clock",
+    "sllg_server_clock", "sllg_build_sc", "sllg_build_bcc", "sllg_build_fcc_sphere",
 ]
 
 
@@ -135,6 +135,9 @@ def lib():
         "sllg_release": (c, [P, U64]),
         "sllg_server_get_stats": (c, [P, ctypes.POINTER(ServerStats)]),
         "sllg_server_clock": (D, [P]),
+        "sllg_build_sc": (c, [P, P, ctypes.POINTER(I64), ctypes.POINTER(I64), P, P, P, P]),
+        "sllg_build_bcc": (c, [P, P, c, ctypes.POINTER(I64), ctypes.POINTER(I64), P, P, P, P]),
+        "sllg_build_fcc_sphere": (c, [D, D, ctypes.POINTER(I64), ctypes.POINTER(I64), P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -189,6 +192,44 @@ def thermal_normals_noalloc(seed, step, n, precision=FP64, device=0):
     if st != 0:
         raise SllgError(st, lib().sllg_last_error(None).decode())
     return out
+
+
+def _built(call):
+    """Run a structure builder of the C ABI twice (counts, then the arrays):
+    (row_ptr int64 [n + 1], col int32 [nnz], type uint8 [nnz], pos [n, 3])."""
+    n, nnz = I64(0), I64(0)
+    st = call(ctypes.byref(n), ctypes.byref(nnz), None, None, None, None)
+    if st != 0:
+        raise SllgError(st, lib().sllg_last_error(None).decode())
+    row_ptr = np.empty(n.value + 1, dtype=np.int64)
+    col = np.empty(max(nnz.value, 1), dtype=np.int32)
+    typ = np.empty(max(nnz.value, 1), dtype=np.uint8)
+    pos = np.empty((n.value, 3), dtype=np.float64)
+    st = call(ctypes.byref(n), ctypes.byref(nnz), _ptr(row_ptr), _ptr(col), _ptr(typ), _ptr(pos))
+    if st != 0:
+        raise SllgError(st, lib().sllg_last_error(None).decode())
+    return row_ptr, col[:nnz.value], typ[:nnz.value], pos
+
+
+def build_sc(cells, periodic=(1, 1, 1)):
+    """Simple-cubic CSR neighbour list from the C ABI (sllg_build_sc)."""
+    c = np.ascontiguousarray(cells, dtype=np.int32).reshape(3)
+    p = np.ascontiguousarray(periodic, dtype=np.int32).reshape(3)
+    return _built(lambda n, nnz, rp, col, ty, pos: lib().sllg_build_sc(_ptr(c), _ptr(p), n, nnz, rp, col, ty, pos))
+
+
+def build_bcc(cells, periodic=(1, 1, 1), second_neighbours=False):
+    """bcc CSR neighbour list from the C ABI (sllg_build_bcc)."""
+    c = np.ascontiguousarray(cells, dtype=np.int32).reshape(3)
+    p = np.ascontiguousarray(periodic, dtype=np.int32).reshape(3)
+    return _built(lambda n, nnz, rp, col, ty, pos: lib().sllg_build_bcc(_ptr(c), _ptr(p), int(bool(second_neighbours)),
+                                                                        n, nnz, rp, col, ty, pos))
+
+
+def build_fcc_sphere(a_nm, radius_nm):
+    """fcc sphere CSR neighbour list from the C ABI (sllg_build_fcc_sphere)."""
+    return _built(lambda n, nnz, rp, col, ty, pos: lib().sllg_build_fcc_sphere(float(a_nm), float(radius_nm), n, nnz,
+                                                                               rp, col, ty, pos))
 
 
 class SpinSystem:

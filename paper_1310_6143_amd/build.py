@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libsllg.so")
-SOURCES = ["kernels.hip", "fused.hip", "noalloc.hip", "prepare.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "fused.hip", "noalloc.hip", "prepare.cpp", "api.cpp", "server.cpp", "builders.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -80,6 +80,10 @@ struct Engine {
 
 }  // namespace
 
+// Error text of the calls without a handle (sllg_last_error(NULL)); used by
+// the host-side structure builders.
+void sllg::set_create_error(const std::string& msg) { g_create_error = msg; }
+
 namespace {
 
 template <typename R>

@@ -88,6 +88,9 @@ struct HostLattice {
     int slot_type[2] = {0, 0};                  // interaction type of each of the kind's slots
 };
 
+// Sets the error text of the calls without a handle (sllg_last_error(NULL)).
+void set_create_error(const std::string& msg);
+
 // Whether the fused step is built for lattice L of n sites in a precision
 // (bytes per real): FP32 any fusable lattice, FP64 the compiled kinds; the
 // spins must be addressable with 31-bit byte offsets.
