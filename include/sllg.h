@@ -252,14 +252,21 @@ sllg_status sllg_get_spins(sllg_system *sys, double *S_out);
  * m = sum mu_s S / sum mu_s is written to m_out[3*t..3*t+2] and the energy
  * of the Hamiltonian above (thermal field excluded, each link once) to
  * E_out[t], if those pointers are not NULL.  Returns SLLG_E_NUMERIC if an
- * energy came out non-finite (the state is then kept as it is). */
+ * energy came out non-finite or a step produced a non-finite spin (every
+ * new spin is checked by the kernel that writes it, records or not; the
+ * state is then kept as it is). */
 sllg_status sllg_integrate(sllg_system *sys, int64_t n_steps, double *m_out, double *E_out,
                            void *stream);
 
 /* Same, with device output arrays m_dev[3*n_steps] and E_dev[n_steps] (either
  * may be NULL); nothing is copied to the host.  Returns when the work has
  * been queued on `stream`; the outputs are valid once the stream reaches
- * that point. */
+ * that point.  A non-finite spin (checked on every new spin) sets a flag of
+ * the system that is not waited for here: the next sllg_integrate_dev call
+ * returns SLLG_E_NUMERIC once the earlier call's work has finished,
+ * sllg_integrate and sllg_mc report it at their end, and sllg_get_option
+ * "numeric_fault" reads it (waiting for the queued work).  sllg_set_spins
+ * and sllg_restore clear it. */
 sllg_status sllg_integrate_dev(sllg_system *sys, int64_t n_steps, double *m_dev, double *E_dev,
                                void *stream);
 
@@ -465,7 +472,9 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     depend on the shape except the m and E records, at FP64
  *                     rounding.
  * sllg_get_option also reads "neighbour_format": 1 stencil, 2 wide stencil,
- * 0 SELL, -1 unset;
+ * 0 SELL, -1 unset; "numeric_fault": 1 once a step or Monte Carlo trial
+ * produced a non-finite spin since the spins were last set (waits for the
+ * queued work);
  * "lattice": 0 none declared, 1 declared, 2 declared and the fused step can
  * take its structure; "fused_active": 1 when the next integration runs the
  * fused step; the fused_* shape keys read the shape in use;

@@ -62,6 +62,10 @@ struct Engine {
     virtual size_t spin_bytes() = 0;
     virtual void save_spins(void* dst, hipStream_t st) = 0;
     virtual void load_spins(const void* src, hipStream_t st) = 0;
+    // non-finite-spin flag: read (waits for st), or copied into pinned host
+    // memory on st
+    virtual bool fault(hipStream_t st) = 0;
+    virtual void fault_async(int32_t* host, hipStream_t st) = 0;
     virtual int parity() = 0;
     virtual void set_parity(int p) = 0;
     virtual void mark_dirty() = 0;           // the record mirror changed
@@ -145,6 +149,8 @@ struct EngineT final : Engine {
     size_t spin_bytes() override { return 3 * (size_t)batch.mirror(q).n * sizeof(R); }
     void save_spins(void* dst, hipStream_t st) override { batch.save_spins(q, dst, st); }
     void load_spins(const void* src, hipStream_t st) override { batch.load_spins(q, src, st); }
+    bool fault(hipStream_t st) override { return batch.fault(q, st); }
+    void fault_async(int32_t* host, hipStream_t st) override { batch.fault_async(q, host, st); }
     int parity() override { return batch.mirror(q).parity; }
     void set_parity(int p) override
     {
@@ -215,6 +221,10 @@ struct sllg_system {
     std::vector<double> staging;
     unsigned long long* d_mc_acc = nullptr;   // accepted trials per Monte Carlo step (device)
     int64_t mc_acc_cap = 0;
+    // the non-finite-spin flag as the last sllg_integrate_dev left it:
+    // copied into pinned memory on its stream, valid once fault_ev completes
+    int32_t* fault_host = nullptr;
+    hipEvent_t fault_ev = nullptr;
 };
 
 namespace {
@@ -495,6 +505,8 @@ void mc_steps(sllg_system* s, int64_t n_steps, double* m_out, double* E_out, int
     e.mark_dirty();
     if (bad)
         fail(SLLG_E_NUMERIC, "the energy became non-finite during Monte Carlo");
+    if (n_steps > 0 && e.fault(st))
+        fail(SLLG_E_NUMERIC, "a trial spin became non-finite during Monte Carlo (the state is kept)");
 }
 
 void measure_state(sllg_system* s, double m[3], double* E, hipStream_t st)
@@ -815,6 +827,12 @@ void sllg_destroy(sllg_system* sys)
         (void)hipDeviceSynchronize();
         (void)hipFree(sys->d_mc_acc);
     }
+    if (sys->fault_ev) {
+        (void)hipEventSynchronize(sys->fault_ev);
+        (void)hipEventDestroy(sys->fault_ev);
+    }
+    if (sys->fault_host)
+        (void)hipHostFree(sys->fault_host);
     sys->eng.reset();
     if (sys->own)
         (void)hipStreamDestroy(sys->own);
@@ -973,11 +991,24 @@ sllg_status sllg_get_step(const sllg_system* sys, uint64_t* step)
     return SLLG_OK;
 }
 
+namespace {
+// A new state has no fault: forget the copy the last sllg_integrate_dev
+// queued (after it has landed) as well as the device flag (set_spins).
+void clear_fault_copy(sllg_system* s)
+{
+    if (s->fault_ev) {
+        hip_check(hipEventSynchronize(s->fault_ev), "hipEventSynchronize");
+        *s->fault_host = 0;
+    }
+}
+}  // namespace
+
 sllg_status sllg_set_spins(sllg_system* sys, const double* S)
 {
     return guard(sys, [&] {
         std::vector<double> v = normalised_spins(sys->n, S);
         sys->demag_valid = false;
+        clear_fault_copy(sys);
         if (sys->eng) {
             hip_check(hipSetDevice(sys->device), "hipSetDevice");
             sys->eng->set_spins(v);
@@ -1009,6 +1040,8 @@ sllg_status sllg_integrate(sllg_system* sys, int64_t n_steps, double* m_out, dou
         hipStream_t st = pick_stream(sys, stream);
         run_steps(sys, n_steps, m_out, E_out, nullptr, nullptr, st, 0);
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (n_steps > 0 && engine(sys).fault(st))
+            fail(SLLG_E_NUMERIC, "a spin became non-finite during integration (the state is kept)");
         if (!m_out && !E_out && n_steps > 0) {
             double E;
             measure_state(sys, nullptr, &E, st);
@@ -1021,7 +1054,23 @@ sllg_status sllg_integrate_dev(sllg_system* sys, int64_t n_steps, double* m_dev,
     return guard(sys, [&] {
         if (n_steps < 0)
             fail(SLLG_E_ARG, "n_steps must be >= 0");
-        run_steps(sys, n_steps, nullptr, nullptr, m_dev, E_dev, pick_stream(sys, stream), 0);
+        // a non-finite spin left by an earlier call whose work has finished
+        // (not waited for: the call stays asynchronous)
+        if (sys->fault_ev && hipEventQuery(sys->fault_ev) == hipSuccess && *sys->fault_host)
+            fail(SLLG_E_NUMERIC, "a spin became non-finite during an earlier sllg_integrate_dev call (the state is "
+                                 "kept)");
+        hipStream_t st = pick_stream(sys, stream);
+        run_steps(sys, n_steps, nullptr, nullptr, m_dev, E_dev, st, 0);
+        if (n_steps > 0) {
+            if (!sys->fault_host) {
+                hip_check(hipHostMalloc((void**)&sys->fault_host, sizeof(int32_t), hipHostMallocDefault),
+                          "hipHostMalloc(fault flag)");
+                *sys->fault_host = 0;
+                hip_check(hipEventCreateWithFlags(&sys->fault_ev, hipEventDisableTiming), "hipEventCreate");
+            }
+            engine(sys).fault_async(sys->fault_host, st);
+            hip_check(hipEventRecord(sys->fault_ev, st), "hipEventRecord");
+        }
     });
 }
 
@@ -1342,6 +1391,7 @@ sllg_status sllg_restore(sllg_system* sys, const void* buf, size_t bytes)
             fail(SLLG_E_ARG, "checkpoint truncated");
         const double* S = reinterpret_cast<const double*>(static_cast<const char*>(buf) + off);
         std::vector<double> v = normalised_spins(sys->n, S, false);
+        clear_fault_copy(sys);
         std::vector<double> field(S + 3 * (size_t)h.n, S + 3 * ((size_t)h.n + (size_t)d.cells));
         if (sys->eng)
             sys->eng->set_spins(v);
@@ -1609,6 +1659,8 @@ sllg_status sllg_get_option(const sllg_system* sys, const char* key, int64_t* va
         *value = sys->opt_grid_scale_pct;
     else if (k == "tuned_ns_per_step")
         *value = sys->tuned ? (int64_t)(sys->tuned_us * 1e3) : -1;
+    else if (k == "numeric_fault")
+        *value = sys->eng ? (sys->eng->fault(nullptr) ? 1 : 0) : 0;   // waits for the queued work
     else if (k == "neighbour_format")
         *value = sys->has_nb ? (sys->st.stencil ? 1 : sys->st.wide ? 2 : 0) : -1;
     else if (k == "fused")

@@ -260,7 +260,7 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
     const size_t n = (size_t)s.n;
     const size_t tile = (size_t)tile_of(s, real_bytes);
     const size_t blocks = (n + tile - 1) / tile;
-    size_t b = 3 * r(spin_buffer_bytes(s.n, real_bytes) + 16);  // S[2], Sp
+    size_t b = 3 * r(spin_buffer_bytes(s.n, real_bytes) + 16) + r(4);  // S[2], Sp, the fault flag
     if (s.stencil)
         b += r(pad16(n)) + r(s.pat_tab.size() * 4) + r(s.pat_start.size() * 2) + r(s.pat_far.size() * 2);
     else if (s.wide)
@@ -476,6 +476,8 @@ public:
             r.S[0] = (R*)get(sb + 16);
             r.S[1] = (R*)get(sb + 16);
             r.Sp = (R*)get(sb);
+            r.fault = (int32_t*)get(4);
+            hip_check(hipMemset(r.fault, 0, 4), "clear fault flag");
             // the padding is staged with the last tile's window: keep it finite
             for (void* p : {(void*)r.S[0], (void*)r.S[1]})
                 hip_check(hipMemset(p, 0, sb + 16), "clear spins");
@@ -778,6 +780,24 @@ public:
             tmp[i] = (R)S[i];
         hip_check(hipMemcpy(r.S[r.parity], tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice),
                   "upload spins");
+        hip_check(hipMemset(r.fault, 0, 4), "clear fault flag");   // new state, no fault
+    }
+
+    // Non-finite-spin flag of replica q (set by the step and Monte Carlo
+    // kernels).  fault(): waits for stream st and reads it; fault_async():
+    // queues a copy of it into host (pinned memory) on st.
+    bool fault(int q, hipStream_t st)
+    {
+        int32_t v = 0;
+        quiesce();   // the last stream the batch ran on
+        if (st)
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        hip_check(hipMemcpy(&v, slots_[q].rec.fault, 4, hipMemcpyDeviceToHost), "read fault flag");
+        return v != 0;
+    }
+    void fault_async(int q, int32_t* host, hipStream_t st)
+    {
+        hip_check(hipMemcpyAsync(host, slots_[q].rec.fault, 4, hipMemcpyDeviceToHost, st), "queue fault flag copy");
     }
 
     void get_spins(int q, double* out, hipStream_t st)

@@ -269,6 +269,20 @@ __device__ __forceinline__ V3<R> llg_step(V3<R> s, V3<R> h, R gdt, R alpha)
     return V3<R>{-gdt * (a.x + alpha * b.x), -gdt * (a.y + alpha * b.y), -gdt * (a.z + alpha * b.z)};
 }
 
+// Whether a new spin is usable: a unit vector has |x| + |y| + |z| <= sqrt 3,
+// a NaN or infinite component fails the comparison.
+template <typename R>
+__device__ __forceinline__ bool spin_ok(const V3<R>& s)
+{
+    return fabs(s.x) + fabs(s.y) + fabs(s.z) <= (R)2;
+}
+
+// Flags a non-finite spin for the host (a plain store: every writer stores 1).
+__device__ __forceinline__ void flag_fault(int32_t* fault)
+{
+    *(volatile int32_t*)fault = 1;
+}
+
 template <typename R>
 __device__ __forceinline__ V3<R> normalised(V3<R> v)
 {

@@ -506,6 +506,8 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
                 const V3<R> sn = normalised(V3<R>{cs.c_base[S0][b].x + dsh.x, cs.c_base[S0][b].y + dsh.y,
                                                   cs.c_base[S0][b].z + dsh.z});
                 store3(run.Sn, (int64_t)(g.col + (uint32_t)b + g.plane_sites * (uint32_t)zw_m2), sn);
+                if (!spin_ok(sn))
+                    flag_fault(r.fault);
             }
             cs.hc[S0][b] = down[b];
         }

@@ -736,6 +736,8 @@ __device__ __forceinline__ void correct_sites(const ReplicaDev<R>& r, const R* _
         const V3<R> b{(R)0.5 * s0.x + q * sp.x, (R)0.5 * s0.y + q * sp.y, (R)0.5 * s0.z + q * sp.z};
         const V3<R> sn = normalised(V3<R>{b.x + (R)0.5 * ds.x, b.y + (R)0.5 * ds.y, b.z + (R)0.5 * ds.z});
         store3(Sn, i, sn);
+        if (!spin_ok(sn))
+            flag_fault(r.fault);
     }
 }
 
@@ -1176,6 +1178,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __res
             accept = (R)u < exp(bracket * (R)(m.mu_s * inv_kT));
         if (accept) {
             store3(S, i, tr);
+            if (!spin_ok(tr))
+                flag_fault(r.fault);
             atomicAdd(&acc_block, 1u);
         }
     }

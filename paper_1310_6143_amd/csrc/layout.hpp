@@ -207,6 +207,7 @@ template <typename R>
 struct ReplicaDev {
     R* S[2];                        // ping-pong spin buffers [3n]
     R* Sp;                          // predicted spins S' [3n]
+    int32_t* fault;                 // set to 1 by a kernel that produced a non-finite spin (cleared with new spins)
     const uint32_t* nb;             // SELL-64 neighbour entries
     const int64_t* slice_off;       // [n_slices + 1] first entry of each slice
     const uint32_t* deg;            // [n] near << 16 | neighbours, per site (SELL)

@@ -229,3 +229,31 @@ def test_large_steps_keep_parity():
                           E, E_ref)
         assert r["max"] <= tol
         assert r["dm"] <= (1e-13 if prec == sl.FP64 else 1e-6)
+
+
+def test_non_finite_spins_are_reported():
+    """A field too large for the arithmetic (finite, 1e300 T) drives the
+    spins to NaN: every new spin is checked by the kernel that writes it, so
+    the asynchronous device-record path reports it too (at the next call,
+    once the earlier work is done), sllg_integrate at its end; new spins
+    clear the flag."""
+    for prec in (sl.FP32, sl.FP64):
+        w = sc_reference(L=8, temperature=0.0, n_steps=5)
+        w.H = np.array([1e300, 0.0, 0.0])
+        with sl.from_workload(w, precision=prec) as g:
+            assert g.get_option("numeric_fault") == 0
+            g.integrate_dev(3)
+            assert g.get_option("numeric_fault") == 1      # waits for the queued steps
+            with pytest.raises(sl.SllgError) as e:
+                g.integrate_dev(1)
+            assert e.value.name == "SLLG_E_NUMERIC"
+            g.set_spins(w.S0)
+            assert g.get_option("numeric_fault") == 0
+            with pytest.raises(sl.SllgError) as e:
+                g.integrate(2, record=False)
+            assert e.value.name == "SLLG_E_NUMERIC"
+            g.set_spins(w.S0)
+            g.set_conditions(0.0, (0.0, 0.0, 1.0))
+            g.integrate_dev(3)
+            g.integrate_dev(3)                             # no fault: the call goes through
+            assert g.get_option("numeric_fault") == 0
