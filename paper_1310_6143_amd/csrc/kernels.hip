@@ -120,7 +120,7 @@ struct PatEntry<double> {
 
 template <typename R>
 struct Shared {
-    R jt[kMaxTypes];
+    R jt[kMaxTypes + 1];   // jt[kMaxTypes] = 0: the wide form's padding entries
     uint16_t pat_start[kMaxPatterns + 1];
     uint16_t pat_far[kMaxPatterns];
     PatEntry<R> pat[kMaxPatternEntries];
@@ -143,8 +143,8 @@ struct TileLds {
 template <typename R, bool TX>
 __device__ __forceinline__ void stage_tables(const ReplicaDev<R>& r, Shared<R>& sh)
 {
-    if (threadIdx.x < kMaxTypes)
-        sh.jt[threadIdx.x] = r.jt[threadIdx.x];
+    if (threadIdx.x <= kMaxTypes)
+        sh.jt[threadIdx.x] = threadIdx.x < kMaxTypes ? r.jt[threadIdx.x] : (R)0;
     const bool tensor = TX && (r.flags & kTensor);
     if (tensor && threadIdx.x < (kMaxTypes + 1) * 9) {
         const int t = threadIdx.x / 9, q = threadIdx.x % 9;
@@ -264,8 +264,10 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
         // + p], read through the L2 (the lanes of a wavefront, neighbouring
         // sites, mostly share a few patterns with adjacent numbers); near
         // links from the window, far ones from global memory, each part in
-        // the row's order, kSellBatch entries and then their spins in
-        // flight together.  Byte offsets fit in 31 bits in this form.
+        // the row's order, a batch of kWideBatch entries and then their
+        // spins in flight together.  Both parts are padded to whole batches
+        // (type kMaxTypes, J = 0), so no batch is cut short.  Byte offsets
+        // fit in 31 bits in this form.
         const __amdgpu_buffer_rsrc_t rs = spin_rsrc(S, r.n * (int)(3 * sizeof(R)));
         const int ib = (i - l) * (int)(3 * sizeof(R)) + site_bytes<R>(l);
         const int p = (int)gload(r.w_pid, i);
@@ -273,34 +275,30 @@ __device__ __forceinline__ V3<R> exchange_sum(const ReplicaDev<R>& r, const R* _
         const int32_t* __restrict__ tab = r.w_tab + p;
         const int64_t np = r.n_patterns;
         overlap();
-        for (int k = 0; k < nn; k += kSellBatch) {
-            int32_t raw[kSellBatch];
+        for (int k = 0; k < nn; k += kWideBatch) {
+            int32_t raw[kWideBatch];
 #pragma unroll
-            for (int u = 0; u < kSellBatch; ++u)
-                raw[u] = gload(tab, (int64_t)(k + u < nn ? k + u : nn - 1) * np);
+            for (int u = 0; u < kWideBatch; ++u)
+                raw[u] = gload(tab, (int64_t)(k + u) * np);
 #pragma unroll
-            for (int u = 0; u < kSellBatch; ++u) {
-                const int off = (raw[u] >> 4) * (int)(3 * sizeof(R));
+            for (int u = 0; u < kWideBatch; ++u) {
+                const int off = (raw[u] >> 5) * (int)(3 * sizeof(R)), t = raw[u] & 31;
                 const V3<R> sj = (r.flags & kDirect) ? bload3(rs, ib + off, R(0)) : wload3(tl.win, wbyte + off);
-                const int t = k + u < nn ? (raw[u] & 15) : kMaxTypes;
-                add_coupled<R, TX>(hn, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj);
+                add_coupled<R, TX>(hn, tensor, sh, t, sh.jt[t], sj);
             }
         }
-        for (int k = nn; k < len; k += kSellBatch) {
-            int32_t raw[kSellBatch];
+        for (int k = nn; k < len; k += kWideBatch) {
+            int32_t raw[kWideBatch];
 #pragma unroll
-            for (int u = 0; u < kSellBatch; ++u)
-                raw[u] = gload(tab, (int64_t)(k + u < len ? k + u : len - 1) * np);
-            V3<R> sj[kSellBatch];
+            for (int u = 0; u < kWideBatch; ++u)
+                raw[u] = gload(tab, (int64_t)(k + u) * np);
+            V3<R> sj[kWideBatch];
 #pragma unroll
-            for (int u = 0; u < kSellBatch; ++u)
-                sj[u] = bload3(rs, ib + (raw[u] >> 4) * (int)(3 * sizeof(R)), R(0));
+            for (int u = 0; u < kWideBatch; ++u)
+                sj[u] = bload3(rs, ib + (raw[u] >> 5) * (int)(3 * sizeof(R)), R(0));
 #pragma unroll
-            for (int u = 0; u < kSellBatch; ++u) {
-                // past the row's end, or offset 0 (past the pattern's end): no link
-                const int t = k + u < len && (raw[u] >> 4) != 0 ? (raw[u] & 15) : kMaxTypes;
-                add_coupled<R, TX>(hf, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj[u]);
-            }
+            for (int u = 0; u < kWideBatch; ++u)
+                add_coupled<R, TX>(hf, tensor, sh, raw[u] & 31, sh.jt[raw[u] & 31], sj[u]);
         }
     } else if (r.flags & kStencil) {
         // byte offsets fit in 31 bits in the stencil form
@@ -1056,27 +1054,25 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
     const char* sb = (const char*)S;
     const bool tensor = TX && (r.flags & kTensor);
     if (r.flags & kWide) {
-        // the pattern's entries in table order (near links, then far ones)
+        // the pattern's entries in table order (near links, then far ones;
+        // padding entries have J = 0)
         const int p = (int)gload(r.w_pid, i);
         const int len = r.w_len;
         const int32_t* __restrict__ tab = r.w_tab + p;
         const int64_t np = r.n_patterns;
         const char* si = sb + (int64_t)i * (3 * sizeof(R));
-        for (int k = 0; k < len; k += kMcBatch) {
-            int32_t raw[kMcBatch];
+        for (int k = 0; k < len; k += kWideBatch) {
+            int32_t raw[kWideBatch];
 #pragma unroll
-            for (int u = 0; u < kMcBatch; ++u)
-                raw[u] = gload(tab, (int64_t)(k + u < len ? k + u : len - 1) * np);
-            V3<R> sj[kMcBatch];
+            for (int u = 0; u < kWideBatch; ++u)
+                raw[u] = gload(tab, (int64_t)(k + u) * np);
+            V3<R> sj[kWideBatch];
 #pragma unroll
-            for (int u = 0; u < kMcBatch; ++u)
-                sj[u] = load3((const R*)(si + (int64_t)(raw[u] >> 4) * (int64_t)(3 * sizeof(R))), 0);
+            for (int u = 0; u < kWideBatch; ++u)
+                sj[u] = load3((const R*)(si + (int64_t)(raw[u] >> 5) * (int64_t)(3 * sizeof(R))), 0);
 #pragma unroll
-            for (int u = 0; u < kMcBatch; ++u) {
-                // past the row's end, or offset 0 (past the pattern's end): no link
-                const int t = k + u < len && (raw[u] >> 4) != 0 ? (raw[u] & 15) : kMaxTypes;
-                add_coupled<R, TX>(h, tensor, sh, t, t < kMaxTypes ? sh.jt[t] : (R)0, sj[u]);
-            }
+            for (int u = 0; u < kWideBatch; ++u)
+                add_coupled<R, TX>(h, tensor, sh, raw[u] & 31, sh.jt[raw[u] & 31], sj[u]);
         }
         return h;
     }

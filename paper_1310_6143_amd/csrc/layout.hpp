@@ -86,6 +86,9 @@ constexpr int kFarRegs = 6;
 // the longest) it takes at most.
 constexpr int kWideMaxPatterns = 65535;
 constexpr int kWideMaxEntries = 1 << 22;
+// A wide-form entry packs (column - row) << 5 | type; type kMaxTypes (J = 0)
+// pads each pattern's near and far parts to whole batches of kWideBatch.
+constexpr int kWideBatch = 8;
 #ifndef SLLG_MAX_PATTERN_ENTRIES
 #define SLLG_MAX_PATTERN_ENTRIES 1024
 #endif
@@ -256,8 +259,8 @@ struct ReplicaDev {
     int32_t tile;                   // sites per tile: tile_for(n, sizeof(R))
     int32_t w_len;                  // entries per pattern in the wide form (kWide)
     const uint16_t* w_pid;          // [n] pattern of each site (kWide)
-    const int32_t* w_tab;           // [w_len][n_patterns] packed offset << 4 | type, transposed (kWide)
-    const uint16_t* w_near;         // [n_patterns] near entries of each pattern (kWide)
+    const int32_t* w_tab;           // [w_len][n_patterns] packed offset << 5 | type, transposed (kWide)
+    const uint16_t* w_near;         // [n_patterns] near entries of each pattern, padded to kWideBatch (kWide)
     // fused plane-marching step (kFused)
     const void* f_ent;              // FusedEntry (FP32) / FusedEntryD (FP64) of every pattern
     const int32_t* f_pat;           // [patterns][4]: first entry, entries with dz = -1, 0, +1

@@ -200,21 +200,39 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
             return s;
         }
         if (ok && !keys.empty()) {
-            // entry c of pattern p at w_tab[c * patterns + p]; patterns
-            // shorter than the longest end in entries of offset 0 (J = 0)
+            // entry c of pattern p at w_tab[c * patterns + p]; the near and
+            // the far part of a pattern are each padded to whole batches,
+            // and shorter patterns end in padding (type kMaxTypes, J = 0)
             const size_t np = keys.size();
-            s.wide = true;
-            s.w_len = (int)longest;
-            s.w_pid = std::move(pid);
-            s.w_tab.assign(longest * np, 0);
-            s.w_near.resize(np);
-            for (size_t p = 0; p < np; ++p) {
-                const size_t cnt = (keys[p].size() - sizeof(uint16_t)) / sizeof(int32_t);
-                s.w_near[p] = near_count(keys[p]);
-                for (size_t c = 0; c < cnt; ++c)
-                    s.w_tab[c * np + p] = entry(keys[p], c);
+            const int32_t pad = kMaxTypes;
+            auto up = [](size_t c) { return (c + kWideBatch - 1) / kWideBatch * kWideBatch; };
+            size_t len = 0;
+            bool fits = true;
+            for (const std::string& k : keys) {
+                const size_t cnt = (k.size() - sizeof(uint16_t)) / sizeof(int32_t), nn = near_count(k);
+                len = std::max(len, up(nn) + up(cnt - nn));
+                for (size_t c = 0; c < cnt; ++c) {
+                    const int32_t off = entry(k, c) >> 4;
+                    fits = fits && off >= -(1 << 26) && off < (1 << 26);
+                }
             }
-            return s;
+            if (fits && len * np <= (size_t)kWideMaxEntries && len <= 0xFFFF) {
+                s.wide = true;
+                s.w_len = (int)len;
+                s.w_pid = std::move(pid);
+                s.w_tab.assign(len * np, pad);
+                s.w_near.resize(np);
+                for (size_t p = 0; p < np; ++p) {
+                    const size_t cnt = (keys[p].size() - sizeof(uint16_t)) / sizeof(int32_t), nn = near_count(keys[p]);
+                    s.w_near[p] = (uint16_t)up(nn);
+                    for (size_t c = 0; c < cnt; ++c) {
+                        const int32_t e = entry(keys[p], c);
+                        const size_t slot = c < nn ? c : up(nn) + (c - nn);
+                        s.w_tab[slot * np + p] = (int32_t)((uint32_t)(e >> 4) << 5) | (e & 15);
+                    }
+                }
+                return s;
+            }
         }
     }
 
@@ -262,9 +280,8 @@ static void for_each_link(const HostStructure& s, int64_t i, F&& fn)
         const size_t np = s.w_near.size(), p = s.w_pid[(size_t)i];
         for (int e = 0; e < s.w_len; ++e) {
             const int32_t raw = s.w_tab[(size_t)e * np + p];
-            const int32_t off = raw >> 4;
-            if (off != 0)   // offset 0: past the pattern's end, never a link
-                fn(i + off, raw & 15);
+            if ((raw & 31) != kMaxTypes)   // type kMaxTypes: padding, never a link
+                fn(i + (raw >> 5), raw & 31);
         }
         return;
     }

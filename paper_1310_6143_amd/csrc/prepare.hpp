@@ -133,10 +133,11 @@ struct HostStructure {
     // (kMaxPatterns, kMaxPatternEntries) but not kWideMaxPatterns /
     // kWideMaxEntries: the table stays in global memory
     bool wide = false;
-    int w_len = 0;                     // entries of the longest pattern
+    int w_len = 0;                     // entries of the longest pattern (a multiple of kWideBatch)
     std::vector<uint16_t> w_pid;       // [n] pattern of each site
-    std::vector<int32_t> w_tab;        // [w_len][patterns] packed (col - row) << 4 | type; 0 past a pattern's end
-    std::vector<uint16_t> w_near;      // [patterns] near entries (the first ones) of each pattern
+    std::vector<int32_t> w_tab;        // [w_len][patterns] packed (col - row) << 5 | type: the near links,
+                                       // padded to kWideBatch, then the far ones, padded (type kMaxTypes)
+    std::vector<uint16_t> w_near;      // [patterns] near entries of each pattern with their padding
     // macrocell demagnetising field (set_demag)
     HostDemag demag;
     // Monte Carlo colour classes (build_colours): sites sorted by colour
