@@ -505,7 +505,14 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
                 const V3<R> dsh = llg_step(s, h, (R)0.5 * r.gdt, r.alpha);
                 const V3<R> sn = normalised(V3<R>{cs.c_base[S0][b].x + dsh.x, cs.c_base[S0][b].y + dsh.y,
                                                   cs.c_base[S0][b].z + dsh.z});
-                store3(run.Sn, (int64_t)(g.col + (uint32_t)b + g.plane_sites * (uint32_t)zw_m2), sn);
+                // ordinary stores: the L2 merges the lanes' 12- or 24-byte
+                // spins into whole lines (streaming stores of FP64 spins
+                // reached memory as 1.4 times their bytes, for no gain in time)
+                SLLG_GLOBAL R* dst =
+                    (SLLG_GLOBAL R*)run.Sn + 3 * (int64_t)(g.col + (uint32_t)b + g.plane_sites * (uint32_t)zw_m2);
+                dst[0] = sn.x;
+                dst[1] = sn.y;
+                dst[2] = sn.z;
                 if (!spin_ok(sn))
                     flag_fault(r.fault);
             }
