@@ -268,7 +268,7 @@ inline size_t replica_bytes(const HostStructure& s, const HostMaterials& m, size
     else
         b += r(s.nb.size() * 4) + r(s.slice_off.size() * 8) + r(4 * n);
     if (!s.colour_sites.empty())
-        b += r(4 * n);
+        b += r(4 * n) + ((s.stencil || s.wide) ? r(2 * n) : 0);
     if (m.per_site_material)
         b += r(n);
     if (m.per_site_axis)
@@ -360,6 +360,7 @@ public:
         size_t bytes = 0;
         int plane_tiles = 0;     // see plane_tiles()
         int32_t* d_colour = nullptr;            // Monte Carlo: sites by colour class
+        uint16_t* d_colour_pid = nullptr;       // their stencil patterns, in the same order (stencil forms)
         std::vector<int64_t> colour_start;      // [n_colours + 1]
         // fused step (kFused): patterns, shape and work items
         HostLattice lat;
@@ -626,6 +627,17 @@ public:
             sl.plane_tiles = plane_tiles(s, (int)tile);
             if (!s.colour_sites.empty()) {
                 sl.d_colour = (int32_t*)get(4 * n);
+                if (s.stencil || s.wide) {
+                    // each trial's pattern, read beside its site instead of after it
+                    std::vector<uint16_t> pid(n);
+                    for (size_t k = 0; k < n; ++k) {
+                        const size_t i = (size_t)s.colour_sites[k];
+                        pid[k] = s.stencil ? (uint16_t)s.pat_id[i] : s.w_pid[i];
+                    }
+                    sl.d_colour_pid = (uint16_t*)get(2 * n);
+                    hip_check(hipMemcpy(sl.d_colour_pid, pid.data(), 2 * n, hipMemcpyHostToDevice),
+                              "upload colour-class patterns");
+                }
                 hip_check(hipMemcpy(sl.d_colour, s.colour_sites.data(), 4 * n, hipMemcpyHostToDevice),
                           "upload colour classes");
                 sl.colour_start = s.colour_start;
@@ -1024,6 +1036,7 @@ public:
             fail(SLLG_E_STATE, "the replica has no colour classes");
         for (size_t c = 0; c + 1 < sl.colour_start.size(); ++c)
             hip_check(launch_mc<R>(d_reps_ + q, sl.d_colour + sl.colour_start[c],
+                                   sl.d_colour_pid ? sl.d_colour_pid + sl.colour_start[c] : nullptr,
                                    (int)(sl.colour_start[c + 1] - sl.colour_start[c]), step, cone, inv_kT,
                                    accepted, (sl.rec.flags & kTensor) != 0, st),
                       "Monte Carlo sweep");

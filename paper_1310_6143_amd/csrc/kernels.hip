@@ -1048,7 +1048,7 @@ constexpr int kMcBatch = 8;
 
 template <typename R, bool TX>
 __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, const Shared<R>& sh,
-                                                     const R* __restrict__ S, int i)
+                                                     const R* __restrict__ S, int i, int p)
 {
     V3<R> h{0, 0, 0};
     const char* sb = (const char*)S;
@@ -1056,7 +1056,6 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
     if (r.flags & kWide) {
         // the pattern's entries in table order (near links, then far ones;
         // padding entries have J = 0)
-        const int p = (int)gload(r.w_pid, i);
         const int len = r.w_len;
         const int32_t* __restrict__ tab = r.w_tab + p;
         const int64_t np = r.n_patterns;
@@ -1077,7 +1076,6 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
         return h;
     }
     if (r.flags & kStencil) {
-        const int p = gload(r.pat_id, i);
         const int b = sh.pat_start[p], e = sh.pat_start[p + 1];
         const char* si = sb + (int64_t)i * (3 * sizeof(R));
         for (int k = b; k < e; k += kMcBatch) {
@@ -1120,7 +1118,8 @@ __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, con
 
 template <typename R, bool TX>
 __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __restrict__ rep,
-                                                      const int32_t* __restrict__ sites, int count, uint64_t step,
+                                                      const int32_t* __restrict__ sites,
+                                                      const uint16_t* __restrict__ pids, int count, uint64_t step,
                                                       R cone, double inv_kT, unsigned long long* __restrict__ accepted)
 {
     __shared__ Shared<R> sh;
@@ -1139,11 +1138,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __res
     const int chunk = x * q + (x < rem ? x : rem) + ((int)blockIdx.x >> 3);
     const int t = chunk * (int)blockDim.x + (int)threadIdx.x;
     if (t < count) {
+        // the site and, for the stencil forms, its pattern: two independent
+        // loads from lists in the class's order
         const int i = gload(sites, t);
+        const int p = pids ? (int)gload(pids, t) : 0;
         R* __restrict__ S = r.S[r.parity];
         const MaterialDev<R> m = site_material(r, i);
         const V3<R> s = load3((const R*)S, i);
-        const V3<R> sum = exchange_sum_global<R, TX>(r, sh, (const R*)S, i);
+        const V3<R> sum = exchange_sum_global<R, TX>(r, sh, (const R*)S, i, p);
         const V3<R> h{m.mu_rel * sum.x + r.H[0], m.mu_rel * sum.y + r.H[1], m.mu_rel * sum.z + r.H[2]};
         uint32_t c0 = (uint32_t)i, c1 = (uint32_t)step, c2 = (uint32_t)(step >> 32), c3 = 3u;
         philox10(c0, c1, c2, c3, (uint32_t)r.seed, (uint32_t)(r.seed >> 32));
@@ -1287,16 +1289,16 @@ hipError_t launch_noise(uint64_t seed, uint64_t step, int n, double* out, hipStr
 }
 
 template <typename R>
-hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, uint64_t step, double cone,
-                     double inv_kT, unsigned long long* accepted, bool tensor, hipStream_t st)
+hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, const uint16_t* pids, int count, uint64_t step,
+                     double cone, double inv_kT, unsigned long long* accepted, bool tensor, hipStream_t st)
 {
     if (count <= 0)
         return hipSuccess;
     const dim3 g((count + kBlockThreads - 1) / kBlockThreads), b(kBlockThreads);
     if (tensor)
-        hipLaunchKernelGGL((k_mc<R, true>), g, b, 0, st, rep, sites, count, step, (R)cone, inv_kT, accepted);
+        hipLaunchKernelGGL((k_mc<R, true>), g, b, 0, st, rep, sites, pids, count, step, (R)cone, inv_kT, accepted);
     else
-        hipLaunchKernelGGL((k_mc<R, false>), g, b, 0, st, rep, sites, count, step, (R)cone, inv_kT, accepted);
+        hipLaunchKernelGGL((k_mc<R, false>), g, b, 0, st, rep, sites, pids, count, step, (R)cone, inv_kT, accepted);
     return hipGetLastError();
 }
 
@@ -1387,7 +1389,7 @@ hipError_t launch_accumulate(const ReplicaDev<R>* reps, int n_rep, hipStream_t s
     template hipError_t launch_demag<R>(const ReplicaDev<R>*, int, int, hipStream_t);                \
     template hipError_t launch_torque<R>(const ReplicaDev<R>*, const WorkItem*, const int*, int, int, int, \
                                          double*, hipStream_t);                                      \
-    template hipError_t launch_mc<R>(const ReplicaDev<R>*, const int32_t*, int, uint64_t, double, double, \
+    template hipError_t launch_mc<R>(const ReplicaDev<R>*, const int32_t*, const uint16_t*, int, uint64_t, double, double, \
                                      unsigned long long*, bool, hipStream_t);
 
 SLLG_INSTANTIATE(float)

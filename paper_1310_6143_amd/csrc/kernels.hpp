@@ -69,10 +69,11 @@ int resident_blocks(int device, int variant);
 // `sites`) of the replica at *rep, step number `step` for the counters;
 // cone = sigma_g, inv_kT = 1/(kB T) (0 at T = 0); accepted trials are added
 // to *accepted.  tensor: the replica has exchange tensors (kernel variant
-// that applies them).
+// that applies them).  pids: the stencil pattern of each of the count
+// sites, in the same order (required for the stencil forms, else null).
 template <typename R>
-hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, int count, uint64_t step, double cone,
-                     double inv_kT, unsigned long long* accepted, bool tensor, hipStream_t st);
+hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, const uint16_t* pids, int count, uint64_t step,
+                     double cone, double inv_kT, unsigned long long* accepted, bool tensor, hipStream_t st);
 
 // Fused plane-marching Heun step (fused.hip) of step k over the work items
 // (one launch per step; measure: m and E sums of the state after the chunk
