@@ -126,7 +126,10 @@ __device__ void fused_record(const ReplicaDev<R>& r, int par, int64_t slot, doub
         out[0] = tot[0] * f;
         out[1] = tot[1] * f;
         out[2] = tot[2] * f;
-        out[3] = -r.mu_ref * tot[3];
+        // the Zeeman part from the summed spins: S.H_app summed over the
+        // sites is H_app.(sum of S)
+        const double zee = (double)r.H[0] * tot[0] + (double)r.H[1] * tot[1] + (double)r.H[2] * tot[2];
+        out[3] = -r.mu_ref * (tot[3] + zee);
     }
 }
 
@@ -136,21 +139,20 @@ __device__ __forceinline__ int wrap_cell(int u, int n)
     return m < 0 ? m + n : m;
 }
 
-// m and E terms of one site: S and -E_i/mu_s = S.H_ex/2 + (k_u/mu_s)(S.e)^2
-// + S.H_app, with se = S.e as the predictor forms it.  A replica takes the
-// fused step only with one material, so mu_s is the reference moment and
-// every site weighs 1.  Written with explicit fmas so that the step and the
-// measuring launch round alike.
+// m and E terms of one site: S and S.H_ex/2 + (k_u/mu_s)(S.e)^2, with se =
+// S.e as the predictor forms it (-E_i/mu_s is that plus S.H_app, which the
+// record adds from the summed spins).  A replica takes the fused step only
+// with one material, so mu_s is the reference moment and every site weighs
+// 1.  Written with explicit fmas so that the step and the measuring launch
+// round alike.
 template <typename R>
-__device__ __forceinline__ void record_terms(const MaterialDev<R>& m, const V3<R>& s, R se, const V3<R>& hex,
-                                             const V3<R>& Happ, R t[4])
+__device__ __forceinline__ void record_terms(const MaterialDev<R>& m, const V3<R>& s, R se, const V3<R>& hex, R t[4])
 {
     const R sh = fma(s.z, hex.z, fma(s.y, hex.y, s.x * hex.x));
-    const R sa = fma(s.z, Happ.z, fma(s.y, Happ.y, s.x * Happ.x));
     t[0] = s.x;
     t[1] = s.y;
     t[2] = s.z;
-    t[3] = fma((R)0.5, sh, fma(m.ku_mu * se, se, sa));
+    t[3] = fma((R)0.5, sh, m.ku_mu * se * se);
 }
 
 // The terms of one cell (its basis sites added in FP32, in basis order)
@@ -423,27 +425,23 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
         }
     }
     // B: m and E terms of plane q - 1 (its exchange sums are complete; one
-    // material: the exchange field is the sum itself), then its predictor
-    if (run.partials && g.interior && zp_need && zp_own) {
-        R tc[4];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const V3<R> s = slot_xyz<R, ZOFF>(nxt + g.own(b));
-            const R se = fma(s.z, e.z, fma(s.y, e.y, s.x * e.x));
-            R t[4];
-            record_terms(m, s, se, cs.hp[S1][b], Happ, t);
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                tc[c] = b == 0 ? t[c] : tc[c] + t[c];
-        }
-        record_add<BT>(tc, acc);
-    }
+    // material: the exchange field is the sum itself) from the spins its
+    // predictor reads, then the predictor
+    const bool rec = run.partials && g.interior && zp_need && zp_own;
+    R tc[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (g.live && zp_need) {
             const V3<R> s = slot_xyz<R, ZOFF>(nxt + g.own(b));
             const V3<R>& hex = cs.hp[S1][b];
             const R se = fma(s.z, e.z, fma(s.y, e.y, s.x * e.x));
+            if (rec) {
+                R t[4];
+                record_terms(m, s, se, hex, t);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    tc[c] = b == 0 ? t[c] : tc[c] + t[c];
+            }
             if (!MEASURE) {
                 R gn[3] = {0, 0, 0};
                 if (m.sigma != (R)0)
@@ -463,6 +461,8 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
         }
         cs.hp[S1][b] = up[b];
     }
+    if (rec)
+        record_add<BT>(tc, acc);
     if constexpr (MEASURE) {
         // S(q + 1) went into the third plane at the start of the step
         __syncthreads();   // S(q + 1) complete; every thread is done with S(q - 1)
