@@ -273,9 +273,12 @@ sllg_status sllg_integrate_dev(sllg_system *sys, int64_t n_steps, double *m_dev,
 /* Monte Carlo (section "Monte Carlo Methods"): n_steps >= 0 Metropolis
  * steps at the current temperature, field and materials.  A step makes one
  * trial on every site, colour class by colour class of a greedy colouring
- * of the neighbour graph (site i takes the smallest colour no neighbour
- * j < i has; sites of one class share no link, so their trials are made at
- * once).  A trial picks, with probability 1/3 each, a spin flip S' = -S, a
+ * of the neighbour graph (the sites are visited in ascending order, each
+ * taking the smallest colour no earlier-visited neighbour has; with the
+ * option "mc_colouring" = 1 on a declared lattice they are visited grouped
+ * by basis site and by the parity of the cell's x + y + z, which gives the
+ * bcc lattice with first and second neighbours four equal classes; sites
+ * of one class share no link, so their trials are made at once).  A trial picks, with probability 1/3 each, a spin flip S' = -S, a
  * Gaussian move S' = |S + sigma_g Gamma| with sigma_g = (2/25)(kB T/muB)^(1/5),
  * or a uniform point on the sphere S' = Gamma/|Gamma| (Hinzke and Nowak),
  * and accepts it if dE <= 0, else if u < exp(-dE/(kB T)).  Random numbers
@@ -453,6 +456,13 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     the general SELL-64 form.  The sums are the same in
  *                     every form (near links, then far ones, each in row
  *                     order)
+ *   "mc_colouring"    0 (default): the Monte Carlo colouring visits the
+ *                     sites in ascending order; 1: on a declared lattice
+ *                     (sllg_set_lattice) grouped by basis site b, then by
+ *                     the parity of x + y + z of its cell, ascending within
+ *                     a group (without a declaration, ascending).  Sets the
+ *                     colour classes at once (the chain of sllg_mc depends
+ *                     on them; the spins are kept)
  *   "fused"           1 (default): integrate with the fused step when the
  *                     system qualifies (sllg_set_lattice) and has at least
  *                     2^20 spins (smaller systems run faster with the
@@ -472,7 +482,8 @@ sllg_status sllg_restore(sllg_system *sys, const void *buf, size_t bytes);
  *                     depend on the shape except the m and E records, at FP64
  *                     rounding.
  * sllg_get_option also reads "neighbour_format": 1 stencil, 2 wide stencil,
- * 0 SELL, -1 unset; "numeric_fault": 1 once a step or Monte Carlo trial
+ * 0 SELL, -1 unset; "mc_colours": the number of Monte Carlo colour classes
+ * (-1 unset); "numeric_fault": 1 once a step or Monte Carlo trial
  * produced a non-finite spin since the spins were last set (waits for the
  * queued work);
  * "lattice": 0 none declared, 1 declared, 2 declared and the fused step can

@@ -106,11 +106,17 @@ def lib():
         L.orc_neighbours.restype = ctypes.c_int64
         L.orc_greedy_colours.argtypes = [ctypes.c_int64, P, P, P]
         L.orc_greedy_colours.restype = ctypes.c_int
+        L.orc_greedy_colours_in.argtypes = [ctypes.c_int64, P, P, P, P]
+        L.orc_greedy_colours_in.restype = ctypes.c_int
+        L.orc_lattice_visit.argtypes = [ctypes.c_int64, ctypes.c_int, P, P]
+        L.orc_lattice_visit.restype = ctypes.c_int
         L.orc_mc_cone_width.argtypes = [ctypes.c_double]
         L.orc_mc_cone_width.restype = ctypes.c_double
         L.orc_mc_choice.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, P, P]
         L.orc_mc_run.argtypes = [ctypes.POINTER(_System), P, ctypes.c_uint64, ctypes.c_int64, P, P, P]
         L.orc_mc_run.restype = ctypes.c_int
+        L.orc_mc_run_visit.argtypes = [ctypes.POINTER(_System), P, P, ctypes.c_uint64, ctypes.c_int64, P, P, P]
+        L.orc_mc_run_visit.restype = ctypes.c_int
         L.orc_mc_run_random.argtypes = [ctypes.POINTER(_System), P, ctypes.c_uint64, ctypes.c_int64, P, P, P]
         L.orc_mc_run_random.restype = ctypes.c_int
         L.orc_demag_update.argtypes = [ctypes.POINTER(_System), P]
@@ -209,6 +215,7 @@ class System:
     def __init__(self, w):
         lat = w.lattice
         self.n = lat.n
+        self.dims = None if getattr(lat, "dims", None) is None else tuple(int(d) for d in lat.dims)
         self.row_ptr = np.ascontiguousarray(lat.row_ptr, dtype=np.int64)
         self.col = np.ascontiguousarray(lat.col, dtype=np.int32)
         self.ntype = np.ascontiguousarray(lat.ntype, dtype=np.uint8)
@@ -290,21 +297,54 @@ class System:
             raise FloatingPointError(f"oracle integrate failed ({rc})")
         return m, E
 
-    def mc(self, S, step0, n_steps, record=True, order="colour"):
+    def lattice_visit(self):
+        """The colouring's visiting order grouped by basis site and cell
+        parity (orc_lattice_visit) of the workload's cell grid."""
+        if self.dims is None:
+            raise ValueError("the workload has no cell grid")
+        cells = np.asarray(self.dims, dtype=np.int32)
+        nb = self.n // int(np.prod(cells))
+        visit = np.empty(self.n, dtype=np.int64)
+        if lib().orc_lattice_visit(self.n, nb, _ptr(cells), _ptr(visit)) != 0:
+            raise ValueError("cell grid does not match the number of sites")
+        return visit
+
+    def colours(self, visit=None):
+        """Greedy colour of every site (visit: the visiting order, None for
+        ascending sites, "lattice" for lattice_visit())."""
+        if isinstance(visit, str):
+            visit = self.lattice_visit()
+        colour = np.empty(self.n, dtype=np.int32)
+        v = None if visit is None else np.ascontiguousarray(visit, dtype=np.int64)
+        nc = lib().orc_greedy_colours_in(self.n, _ptr(self.row_ptr), _ptr(self.col), None if v is None else _ptr(v),
+                                         _ptr(colour))
+        if nc < 0:
+            raise MemoryError("oracle colouring failed")
+        return colour
+
+    def mc(self, S, step0, n_steps, record=True, order="colour", visit=None):
         """Monte Carlo steps step0 .. step0+n_steps-1 (Hinzke-Nowak moves)
         in place on S; order "colour" (colour-class sweeps, every site once)
-        or "random" (the paper's: N trials on random sites).  Returns
-        (m [n_steps, 3], E [n_steps], accepted trials [n_steps]); m and E
-        are None unless record."""
+        or "random" (the paper's: N trials on random sites).  visit: the
+        colouring's visiting order (None: ascending sites; "lattice":
+        grouped by basis site and cell parity).  Returns (m [n_steps, 3],
+        E [n_steps], accepted trials [n_steps]); m and E are None unless
+        record."""
         assert S.dtype == np.float64 and S.flags.c_contiguous and S.shape == (self.n, 3)
         assert order in ("colour", "random")
         m = np.empty((n_steps, 3)) if record else None
         E = np.empty(n_steps) if record else None
         acc = np.empty(n_steps, dtype=np.int64)
         st = self._struct()
-        run = lib().orc_mc_run if order == "colour" else lib().orc_mc_run_random
-        rc = run(ctypes.byref(st), _ptr(S), int(step0), int(n_steps),
-                 _ptr(m) if record else None, _ptr(E) if record else None, _ptr(acc))
+        outs = (_ptr(m) if record else None, _ptr(E) if record else None, _ptr(acc))
+        if order == "random":
+            rc = lib().orc_mc_run_random(ctypes.byref(st), _ptr(S), int(step0), int(n_steps), *outs)
+        else:
+            if isinstance(visit, str):
+                visit = self.lattice_visit()
+            v = None if visit is None else np.ascontiguousarray(visit, dtype=np.int64)
+            rc = lib().orc_mc_run_visit(ctypes.byref(st), None if v is None else _ptr(v), _ptr(S), int(step0),
+                                        int(n_steps), *outs)
         if rc != 0:
             raise MemoryError(f"oracle Monte Carlo failed ({rc})")
         return m, E, acc
@@ -363,11 +403,11 @@ def average(sys: System, S, step0, n_eq, n_avg, n_blocks=10):
     return out, step0 + n_eq + n_avg
 
 
-def mc_average(sys: System, S, step0, n_eq, n_avg, n_blocks=10, order="colour"):
+def mc_average(sys: System, S, step0, n_eq, n_avg, n_blocks=10, order="colour", visit=None):
     """Monte Carlo counterpart of average(): n_eq steps to equilibrate, then
     n_avg steps sampled after every step (trial order as in System.mc)."""
-    sys.mc(S, step0, n_eq, record=False, order=order)
-    m, E, acc = sys.mc(S, step0 + n_eq, n_avg, record=True, order=order)
+    sys.mc(S, step0, n_eq, record=False, order=order, visit=visit)
+    m, E, acc = sys.mc(S, step0 + n_eq, n_avg, record=True, order=order, visit=visit)
     mabs = np.sqrt((m * m).sum(axis=1))
     mean_abs, se_abs = block_stats(mabs, n_blocks)
     mean_E, se_E = block_stats(E, n_blocks)

@@ -19,7 +19,12 @@
  *   class of a greedy colouring of the neighbour graph (ascending colour,
  *   ascending site within a colour).  Sites of one colour share no link, so
  *   their trials do not interact and the order within a class is
- *   immaterial.  The Gaussian numbers of site i at step k come from counter
+ *   immaterial.  The greedy colouring visits the sites in ascending order,
+ *   or (orc_mc_run_visit) in a given order: on a lattice, grouped by basis
+ *   site and by the parity of the cell's x + y + z (orc_lattice_visit),
+ *   which gives the bcc lattice with first and second neighbours four
+ *   classes of N/4 sites where ascending order gives ten of very unequal
+ *   size.  The Gaussian numbers of site i at step k come from counter
  *   (i, k lo, k hi, 2), the move choice and the acceptance uniform from
  *   counter (i, k lo, k hi, 3).
  *
@@ -38,19 +43,23 @@ static double dot3(const double a[3], const double b[3])
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-int orc_greedy_colours(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t *colour)
+int orc_greedy_colours_in(int64_t n, const int64_t *row_ptr, const int32_t *col, const int64_t *visit,
+                          int32_t *colour)
 {
     int n_colours = 0;
+    for (int64_t i = 0; i < n; ++i)
+        colour[i] = -1;   /* not coloured yet */
     /* a site has at most (row length) coloured neighbours, so a free colour
      * exists among the first (row length + 1) */
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t i = visit ? visit[v] : v;
         const int64_t deg = row_ptr[i + 1] - row_ptr[i];
         char *used = (char *)calloc((size_t)deg + 1, 1);
         if (!used)
             return -1;
         for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
             const int64_t j = col[k];
-            if (j < i && colour[j] <= deg)
+            if (colour[j] >= 0 && colour[j] <= deg)
                 used[colour[j]] = 1;
         }
         int c = 0;
@@ -62,6 +71,31 @@ int orc_greedy_colours(int64_t n, const int64_t *row_ptr, const int32_t *col, in
             n_colours = c + 1;
     }
     return n_colours;
+}
+
+int orc_greedy_colours(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t *colour)
+{
+    return orc_greedy_colours_in(n, row_ptr, col, NULL, colour);
+}
+
+int orc_lattice_visit(int64_t n, int nb, const int cells[3], int64_t *visit)
+{
+    if (nb < 1 || (int64_t)nb * cells[0] * cells[1] * cells[2] != n)
+        return -1;
+    /* site i = b + nb (x + cells[0] (y + cells[1] z)): the sites of basis
+     * site 0 with x + y + z even, then odd, then basis site 1, ...; each
+     * group in ascending site order */
+    int64_t v = 0;
+    for (int b = 0; b < nb; ++b)
+        for (int parity = 0; parity < 2; ++parity)
+            for (int64_t i = 0; i < n; ++i) {
+                const int64_t cell = i / nb;
+                const int64_t x = cell % cells[0], y = (cell / cells[0]) % cells[1],
+                              z = cell / ((int64_t)cells[0] * cells[1]);
+                if (i % nb == b && (x + y + z) % 2 == parity)
+                    visit[v++] = i;
+            }
+    return 0;
 }
 
 double orc_mc_cone_width(double temperature)
@@ -190,6 +224,12 @@ int64_t orc_mc_step(const orc_system *s, double *S, const int32_t *colour, int n
 int orc_mc_run(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, double *m_out,
                double *E_out, int64_t *accepted_out)
 {
+    return orc_mc_run_visit(s, NULL, S, step0, n_steps, m_out, E_out, accepted_out);
+}
+
+int orc_mc_run_visit(const orc_system *s, const int64_t *visit, double *S, uint64_t step0, int64_t n_steps,
+                     double *m_out, double *E_out, int64_t *accepted_out)
+{
     int32_t *colour = (int32_t *)malloc(sizeof(int32_t) * (size_t)(s->n > 0 ? s->n : 1));
     if (!colour)
         return -2;
@@ -197,7 +237,7 @@ int orc_mc_run(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, 
         free(colour);
         return -3;
     }
-    const int n_colours = orc_greedy_colours(s->n, s->row_ptr, s->col, colour);
+    const int n_colours = orc_greedy_colours_in(s->n, s->row_ptr, s->col, visit, colour);
     if (n_colours < 0) {
         free(colour);
         return -2;

@@ -130,6 +130,13 @@ double orc_max_torque(const orc_system *s, const double *S);
  * colour-class sweep order and the random-number layout).
  * orc_greedy_colours: colour[i] = the smallest colour not taken by a
  * neighbour j < i; returns the number of colours (-1 on allocation failure).
+ * orc_greedy_colours_in: the same with the sites visited in the order
+ * visit[0..n-1] (a permutation; NULL: ascending), each taking the smallest
+ * colour no neighbour visited before it has.
+ * orc_lattice_visit: the visiting order of a lattice of nb sites per cell,
+ * site i = b + nb (x + cells[0] (y + cells[1] z)): sites grouped by basis
+ * site b, then by the parity of x + y + z, ascending within a group (0, or
+ * -1 when nb x cells != n).
  * orc_mc_cone_width: sigma_g = (2/25)(kB T/muB)^(1/5).
  * orc_mc_choice: move type (0 flip, 1 Gaussian, 2 random) and acceptance
  * uniform of (site, step).
@@ -138,15 +145,22 @@ double orc_max_torque(const orc_system *s, const double *S);
  * returns the number of accepted trials.  orc_mc_run: n_steps steps
  * numbered step0, step0+1, ...; m, E and the accepted count after each
  * step go to the arrays that are not NULL.  Returns 0 or -2.
+ * orc_mc_run_visit: orc_mc_run with the colour classes of
+ * orc_greedy_colours_in(visit).
  * orc_mc_step_random / orc_mc_run_random: the same in the paper's order, N
  * trials on sites drawn at random with replacement. */
 int orc_greedy_colours(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t *colour);
+int orc_greedy_colours_in(int64_t n, const int64_t *row_ptr, const int32_t *col, const int64_t *visit,
+                          int32_t *colour);
+int orc_lattice_visit(int64_t n, int nb, const int cells[3], int64_t *visit);
 double orc_mc_cone_width(double temperature);
 void orc_mc_choice(uint64_t seed, uint64_t step, uint64_t site, uint32_t *move, double *u);
 int orc_mc_trial(const orc_system *s, double *S, int64_t i, uint64_t step);
 int64_t orc_mc_step(const orc_system *s, double *S, const int32_t *colour, int n_colours, uint64_t step);
 int orc_mc_run(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, double *m_out,
                double *E_out, int64_t *accepted_out);
+int orc_mc_run_visit(const orc_system *s, const int64_t *visit, double *S, uint64_t step0, int64_t n_steps,
+                     double *m_out, double *E_out, int64_t *accepted_out);
 int64_t orc_mc_step_random(const orc_system *s, double *S, uint64_t step);
 int orc_mc_run_random(const orc_system *s, double *S, uint64_t step0, int64_t n_steps, double *m_out,
                       double *E_out, int64_t *accepted_out);

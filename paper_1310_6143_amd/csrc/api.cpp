@@ -214,6 +214,7 @@ struct sllg_system {
     bool tuned = false;
     double tuned_us = 0.0;
     int64_t opt_stencil = 1;
+    int64_t opt_mc_colouring = 0;       // Monte Carlo colouring visits: 0 ascending sites, 1 basis site and cell parity
     int64_t opt_fused = 1;              // fused step: 0 never, 1 large systems, 2 whenever the lattice allows it
     FusedShape opt_fshape;              // all fields > 0: this shape instead of the model's
     hipStream_t own = nullptr;
@@ -851,7 +852,7 @@ sllg_status sllg_set_neighbours(sllg_system* sys, const int64_t* row_ptr, const 
         HostStructure st = build_structure(sys->n, row_ptr, col, ntype, J, n_types,
                                            sys->opt_check_symmetry != 0, kHaloCap, sys->opt_stencil != 0);
         st.tile_request = (int)sys->opt_tile_sites;
-        build_colours(st, row_ptr, col);
+        build_colours(st, false);   // no lattice declared yet
         drop_engine(sys);
         sys->st = std::move(st);
         sys->has_nb = true;
@@ -865,6 +866,8 @@ sllg_status sllg_set_lattice(sllg_system* sys, int n_basis, const int cells[3], 
             fail(SLLG_E_STATE, "neighbour list not set (sllg_set_neighbours)");
         HostStructure st = sys->st;
         set_lattice(st, n_basis, cells, periodic);
+        if (sys->opt_mc_colouring)
+            build_colours(st, true);
         drop_engine(sys);   // rebuilt at the next run with the fused step's buffers, state kept
         sys->st = std::move(st);
     });
@@ -1549,6 +1552,18 @@ sllg_status sllg_set_option(sllg_system* sys, const char* key, int64_t value)
                 sys->eng->set_grid_scale(value / 100.0);
         } else if (k == "stencil") {
             sys->opt_stencil = value ? 1 : 0;   // applies to the next sllg_set_neighbours
+        } else if (k == "mc_colouring") {
+            if (value != 0 && value != 1)
+                fail(SLLG_E_ARG, "mc_colouring must be 0 or 1");
+            if (value != sys->opt_mc_colouring) {
+                sys->opt_mc_colouring = value;
+                if (sys->has_nb) {
+                    HostStructure st = sys->st;
+                    build_colours(st, value != 0);
+                    drop_engine(sys);   // the colour lists are uploaded with the replica, state kept
+                    sys->st = std::move(st);
+                }
+            }
         } else if (k == "tile_sites") {
             const int64_t largest = sys->prec == SLLG_FP64 ? tile_sites<double>() : tile_sites<float>();
             bool ok = value == 0;
@@ -1655,6 +1670,10 @@ sllg_status sllg_get_option(const sllg_system* sys, const char* key, int64_t* va
         *value = sys->opt_tile_group;
     else if (k == "stencil")
         *value = sys->opt_stencil;
+    else if (k == "mc_colouring")
+        *value = sys->opt_mc_colouring;
+    else if (k == "mc_colours")
+        *value = sys->has_nb ? (int64_t)sys->st.colour_start.size() - 1 : -1;
     else if (k == "grid_scale_pct")
         *value = sys->opt_grid_scale_pct;
     else if (k == "tuned_ns_per_step")

@@ -564,19 +564,38 @@ void demag_cells(const HostDemag& dm, const HostMaterials& m, std::vector<double
     }
 }
 
-void build_colours(HostStructure& s, const int64_t* row_ptr, const int32_t* col)
+void build_colours(HostStructure& s, bool lattice_order)
 {
     const int64_t n = s.n;
-    std::vector<int32_t> colour((size_t)n);
+    // visiting order: ascending sites, or on a declared lattice the sites
+    // of each basis site and cell parity (x + y + z even, then odd) in turn
+    std::vector<int64_t> visit((size_t)n);
+    const HostLattice& L = s.lat;
+    if (lattice_order && L.on) {
+        size_t v = 0;
+        for (int b = 0; b < L.nb; ++b)
+            for (int parity = 0; parity < 2; ++parity)
+                for (int64_t i = b; i < n; i += L.nb) {
+                    const int64_t cell = i / L.nb;
+                    const int64_t x = cell % L.nx, y = (cell / L.nx) % L.ny, z = cell / ((int64_t)L.nx * L.ny);
+                    if (((x + y + z) & 1) == parity)
+                        visit[v++] = i;
+                }
+    } else {
+        for (int64_t i = 0; i < n; ++i)
+            visit[(size_t)i] = i;
+    }
+    // greedy: each site takes the smallest colour no earlier-visited
+    // neighbour has (a site has at most kMaxDegree neighbours)
+    std::vector<int32_t> colour((size_t)n, -1);
     std::vector<int64_t> seen(kMaxDegree + 2, -1);   // seen[c] == i: colour c is taken around site i
     int n_colours = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t deg = row_ptr[i + 1] - row_ptr[i];
-        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-            const int64_t j = col[k];
-            if (j < i && colour[(size_t)j] <= deg)
-                seen[(size_t)colour[(size_t)j]] = i;
-        }
+    for (int64_t i : visit) {
+        for_each_link(s, i, [&](int64_t j, int) {
+            const int32_t cj = colour[(size_t)j];
+            if (cj >= 0 && cj <= kMaxDegree)
+                seen[(size_t)cj] = i;
+        });
         int c = 0;
         while (seen[(size_t)c] == i)
             ++c;

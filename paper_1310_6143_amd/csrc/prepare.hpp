@@ -173,10 +173,12 @@ HostStructure build_structure(int64_t n, const int64_t* row_ptr, const int32_t* 
 // from either end.  Jt = NULL returns to the scalar table.
 void set_exchange_tensors(HostStructure& s, const double* Jt, int n_types);
 
-// Greedy colouring of the neighbour graph for Monte Carlo: site i takes the
-// smallest colour no neighbour j < i has (so no link joins two sites of one
-// colour); fills colour_sites / colour_start.
-void build_colours(HostStructure& s, const int64_t* row_ptr, const int32_t* col);
+// Greedy colouring of the neighbour graph for Monte Carlo: the sites are
+// visited in ascending order, or (lattice_order, on a declared lattice)
+// grouped by basis site and by the parity of the cell's x + y + z, each
+// taking the smallest colour no earlier-visited neighbour has (so no link
+// joins two sites of one colour); fills colour_sites / colour_start.
+void build_colours(HostStructure& s, bool lattice_order);
 
 // Materials: distinct (mu_s, k_u, k_c) triples, per-site ids when there is
 // more than one, per-site easy axes when they differ.

@@ -189,3 +189,67 @@ def test_mc_full_block_in_the_bench_launch_shape():
           f"{off} of {w.n} sites off by more than 1e-4 rad, accepted {acc[0]} vs {acc1[0]}")
     assert off <= w.n // 10000
     assert abs(int(acc[0]) - int(acc1[0])) <= w.n // 10000
+
+
+@pytest.mark.parametrize("stencil", [1, 0])
+def test_mc_lattice_colouring_chain_matches_oracle(stencil):
+    """Option "mc_colouring" = 1: the library colours the declared lattice in
+    the visiting order grouped by basis site and cell parity, as the
+    oracle's orc_lattice_visit does; the bcc J1+J2 block then has four
+    colour classes (ten in ascending order) and the FP64 chain is the
+    oracle's in that order, in both neighbour forms.  Back to 0, the chain
+    is the ascending-order one again."""
+    w = bcc_block(cells=10, temperature=900.0, seed=8)
+    orc = oracle.System(w)
+    S_ref = np.ascontiguousarray(w.S0.copy())
+    m_ref, E_ref, acc_ref = orc.mc(S_ref, 0, 25, visit="lattice")
+    S_asc = S_ref.copy()
+    _, _, acc_asc = orc.mc(S_asc, 25, 10)
+    with sl.from_workload(w, precision=sl.FP64, check_symmetry=False, stencil=stencil) as g:
+        assert g.get_option("mc_colours") == int(orc.colours().max()) + 1
+        g.set_option("mc_colouring", 1)
+        assert g.get_option("mc_colouring") == 1
+        assert g.get_option("mc_colours") == 4
+        m, E, acc = g.mc(25)
+        S = g.get_spins()
+        g.set_option("mc_colouring", 0)
+        _, _, acc2 = g.mc(10)
+        S2 = g.get_spins()
+    print(f"lattice-ordered colouring: 4 classes, accepted {acc.sum()} as the oracle")
+    assert np.array_equal(acc, acc_ref)
+    assert max_angle(S, S_ref) <= 1e-12
+    assert np.abs(m - m_ref).max() <= 1e-12
+    assert np.abs(E - E_ref).max() <= 1e-12 * np.abs(E_ref).max()
+    assert np.array_equal(acc2, acc_asc)
+    assert max_angle(S2, S_asc) <= 1e-12
+
+
+def test_mc_lattice_colouring_without_a_lattice_is_ascending():
+    """Without a lattice declaration the option leaves the ascending order."""
+    w = bcc_block(cells=6, temperature=900.0, seed=9)
+    S_ref = np.ascontiguousarray(w.S0.copy())
+    _, _, acc_ref = oracle.System(w).mc(S_ref, 0, 10)
+    with sl.from_workload(w, precision=sl.FP64, check_symmetry=False, lattice=False) as g:
+        g.set_option("mc_colouring", 1)
+        assert g.get_option("mc_colours") == int(oracle.System(w).colours().max()) + 1
+        _, _, acc = g.mc(10)
+        S = g.get_spins()
+    assert np.array_equal(acc, acc_ref)
+    assert max_angle(S, S_ref) <= 1e-12
+
+
+def test_mc_full_block_lattice_colouring():
+    """The 8,192,000-spin block with the four lattice-ordered classes, as the
+    benchmark's Monte Carlo line runs it: one FP64 step identical to the
+    oracle's at every site."""
+    w = bcc_block(cells=160)
+    S_ref = np.ascontiguousarray(w.S0.copy())
+    _, _, acc_ref = oracle.System(w).mc(S_ref, 0, 1, visit="lattice")
+    with sl.from_workload(w, precision=sl.FP64, check_symmetry=False) as g:
+        g.set_option("mc_colouring", 1)
+        assert g.get_option("mc_colours") == 4
+        _, _, acc = g.mc(1)
+        S = g.get_spins()
+    print(f"full block, lattice-ordered classes: accepted {acc[0]} as the oracle")
+    assert np.array_equal(acc, acc_ref)
+    assert max_angle(S, S_ref) <= 1e-12

@@ -15,7 +15,11 @@ something other than the oracle's own formulas:
   same temperature (the paper's Monte Carlo vs LLG comparison);
 - the colour-class sweep order (the one the GPU kernel takes) samples the
   same equilibrium as the paper's order (N trials on random sites), below,
-  near and above Tc.
+  near and above Tc;
+- the lattice visiting order of the colouring (basis site, cell parity)
+  groups the sites as the builder placed them, gives the bcc J1+J2 lattice
+  four equal proper classes, and its chain samples the same equilibrium as
+  the random-site chain.
 """
 import os
 from multiprocessing import get_context
@@ -24,7 +28,7 @@ import numpy as np
 import pytest
 from scipy import integrate, stats
 
-from spin_systems import MU_B, bcc, bcc_film, fcc_nanoparticle, sc_reference, simple_cubic, single_spin
+from spin_systems import MU_B, bcc, bcc_block, bcc_film, fcc_nanoparticle, sc_reference, simple_cubic, single_spin
 
 KB = 1.3807e-23
 
@@ -165,6 +169,86 @@ def test_random_site_order_matches_colour_sweeps():
             diff = abs(mean[0] - mean[1])
             print(f"T = {T:.0f} K {name}: random {mean[0]:.5g} +- {se[0]:.2g}, colour {mean[1]:.5g} +- "
                   f"{se[1]:.2g}, |diff| / se {diff / np.hypot(*se):.2f}")
+            assert diff <= 3 * np.hypot(*se), (T, name, mean, se)
+        acc = out[t, :, :, 2].mean(axis=1)
+        assert abs(acc[0] - acc[1]) < 0.01
+
+
+def test_lattice_visit_order_and_its_colouring(orc):
+    """The colouring's lattice visiting order groups the sites by basis site
+    and by the parity of the cell's x + y + z (checked here from the site
+    positions the lattice builder placed, not from the index arithmetic),
+    and its greedy colouring is proper.  On the periodic bcc lattice with
+    first and second neighbours it gives four classes of N/4 (the two
+    sublattices, each split by parity: second neighbours join cells of
+    opposite parity on one sublattice), where ascending order gives nine or
+    ten unequal ones; on simple cubic it gives the two parity classes,
+    the same as ascending order.  On an odd periodic edge the parity split
+    is no colouring, and greedy still gives a proper one."""
+    w = bcc((8, 8, 8), (True, True, True), second_neighbours=True)
+    wb = bcc_block(cells=8)
+    sysb = orc.System(wb)
+    visit = sysb.lattice_visit()
+    assert np.array_equal(np.sort(visit), np.arange(wb.n))
+    pos = np.asarray(w.pos)
+    b = (np.abs(pos[:, 0] - np.round(pos[:, 0])) > 0.25).astype(int)
+    parity = np.floor(pos + 1e-9).astype(int).sum(axis=1) & 1
+    key = 2 * b + parity
+    assert np.all(np.diff(key[visit]) >= 0), "visit not grouped by (basis site, parity)"
+    for g in range(4):   # ascending within a group
+        grp = visit[key[visit] == g]
+        assert np.all(np.diff(grp) > 0)
+    rows = np.repeat(np.arange(wb.n), np.diff(sysb.row_ptr))
+    c_lat = sysb.colours("lattice")
+    c_asc = sysb.colours()
+    for c in (c_lat, c_asc):
+        assert np.all(c[rows] != c[sysb.col]), "a link joins two sites of one colour"
+    assert np.array_equal(np.bincount(c_lat), [wb.n // 4] * 4)
+    assert np.array_equal(c_lat, 2 * b + parity)
+    assert c_asc.max() + 1 >= 9
+    assert np.array_equal(c_asc, orc.greedy_colours(sysb.row_ptr, sysb.col)[0])
+    ws = sc_reference(L=12)
+    syss = orc.System(ws)
+    assert np.array_equal(syss.colours("lattice"), syss.colours())
+    assert syss.colours().max() == 1
+    wo = bcc_block(cells=5)
+    syso = orc.System(wo)
+    c = syso.colours("lattice")
+    rows = np.repeat(np.arange(wo.n), np.diff(syso.row_ptr))
+    assert np.all(c[rows] != c[syso.col])
+    assert c.max() + 1 > 4
+
+
+def _bcc_chain_average(args):
+    import oracle
+    T, order, seed = args
+    w = bcc_block(cells=6, temperature=T, seed=seed)
+    r, _ = oracle.mc_average(oracle.System(w), w.S0.copy(), 0, 4000, 8000, 10, order=order,
+                             visit="lattice" if order == "colour" else None)
+    return r["m_abs"], r["E"], r["acceptance"]
+
+
+def test_random_site_order_matches_lattice_ordered_colour_sweeps():
+    """The four balanced colour classes of the lattice visiting order sample
+    the paper's equilibrium too: on the bcc J1+J2 test block (6^3 cells, 432
+    spins) <|m|> and <E> of the colour-class chain agree with the random-site
+    chain at 800 K and near the block's ordering temperature (1300 K; mean
+    field puts Tc near 1400 K).  Sixteen independent chains per order,
+    4000 + 8000 steps each; bound 3 standard errors of the difference."""
+    temps = (800.0, 1300.0)
+    K = 16
+    jobs = [(T, order, 11 + 100 * k + (0 if order == "random" else 50))
+            for T in temps for order in ("random", "colour") for k in range(K)]
+    with get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
+        out = np.array(pool.map(_bcc_chain_average, jobs)).reshape(len(temps), 2, K, 3)
+    for t, T in enumerate(temps):
+        for col, name in ((0, "<|m|>"), (1, "<E>")):
+            x = out[t, :, :, col]
+            mean = x.mean(axis=1)
+            se = x.std(axis=1, ddof=1) / np.sqrt(K)
+            diff = abs(mean[0] - mean[1])
+            print(f"bcc T = {T:.0f} K {name}: random {mean[0]:.5g} +- {se[0]:.2g}, lattice-ordered colour "
+                  f"{mean[1]:.5g} +- {se[1]:.2g}, |diff| / se {diff / np.hypot(*se):.2f}")
             assert diff <= 3 * np.hypot(*se), (T, name, mean, se)
         acc = out[t, :, :, 2].mean(axis=1)
         assert abs(acc[0] - acc[1]) < 0.01
