@@ -569,7 +569,7 @@ void build_colours(HostStructure& s, bool lattice_order)
     const int64_t n = s.n;
     // visiting order: ascending sites, or on a declared lattice the sites
     // of each basis site and cell parity (x + y + z even, then odd) in turn
-    std::vector<int64_t> visit((size_t)n);
+    std::vector<int32_t> visit((size_t)n);   // site numbers fit 31 bits (colour_sites holds them as int32)
     const HostLattice& L = s.lat;
     if (lattice_order && L.on) {
         size_t v = 0;
@@ -579,18 +579,19 @@ void build_colours(HostStructure& s, bool lattice_order)
                     const int64_t cell = i / L.nb;
                     const int64_t x = cell % L.nx, y = (cell / L.nx) % L.ny, z = cell / ((int64_t)L.nx * L.ny);
                     if (((x + y + z) & 1) == parity)
-                        visit[v++] = i;
+                        visit[v++] = (int32_t)i;
                 }
     } else {
         for (int64_t i = 0; i < n; ++i)
-            visit[(size_t)i] = i;
+            visit[(size_t)i] = (int32_t)i;
     }
     // greedy: each site takes the smallest colour no earlier-visited
     // neighbour has (a site has at most kMaxDegree neighbours)
     std::vector<int32_t> colour((size_t)n, -1);
     std::vector<int64_t> seen(kMaxDegree + 2, -1);   // seen[c] == i: colour c is taken around site i
     int n_colours = 0;
-    for (int64_t i : visit) {
+    for (const int32_t vi : visit) {
+        const int64_t i = vi;
         for_each_link(s, i, [&](int64_t j, int) {
             const int32_t cj = colour[(size_t)j];
             if (cj >= 0 && cj <= kMaxDegree)
