@@ -864,6 +864,16 @@ public:
             build_lists();
         active_ = active;
         lists_dirty_ = false;
+        // whether the fused step launches need the record code (the record
+        // flags change without the lists); a captured chunk holds the
+        // kernel variant chosen here
+        bool any_rec = false;
+        for (const auto& sl : slots_)
+            if (sl.used && sl.rec.nsteps > 0 && (sl.rec.flags & kRecord))
+                any_rec = true;
+        if (any_rec != fused_rec_)
+            drop_graph();
+        fused_rec_ = any_rec;
         const size_t bytes = sizeof(ReplicaDev<R>) * host_reps_.size();
         if (st) {
             std::memcpy(pinned_reps_, host_reps_.data(), bytes);
@@ -1227,12 +1237,14 @@ private:
             // one launch per step, a measuring launch for the chunk's last
             // record, then the records and the advance
             const int* nf = (const int*)(reinterpret_cast<const char*>(d_fwork_) + sizeof(FusedItem) * (size_t)fwork_cap_);
+            // the first step of a chunk leaves no record sums, so it never
+            // needs the record code
             for (int k = 0; k < K && e == hipSuccess; ++k)
-                e = launch_fused<R>(d_reps_, d_fwork_, nf, fgrid_, k, remap_, false, fused_kind_, fused_nb_, fused_bt_,
-                                    fused_plane_, st);
+                e = launch_fused<R>(d_reps_, d_fwork_, nf, fgrid_, k, remap_, false, fused_rec_ && k >= 1, fused_kind_,
+                                    fused_nb_, fused_bt_, fused_plane_, st);
             if (e == hipSuccess)
-                e = launch_fused<R>(d_reps_, d_fwork_, nf, fgrid_, 0, remap_, true, fused_kind_, fused_nb_, fused_bt_,
-                                    fused_plane_, st);
+                e = launch_fused<R>(d_reps_, d_fwork_, nf, fgrid_, 0, remap_, true, true, fused_kind_, fused_nb_,
+                                    fused_bt_, fused_plane_, st);
             if (e == hipSuccess)   // records, averaging sums and the advance
                 e = launch_fused_finish<R>(d_reps_, nrep, st);
             return e;
@@ -1299,6 +1311,7 @@ private:
     bool fused_on_ = true;            // option: use it when the whole batch can
     bool fused_mode_ = false;         // the current work list runs it
     int fused_nb_ = -1, fused_bt_ = -1, fused_kind_ = -1, fused_plane_ = 0;
+    bool fused_rec_ = true;   // some replica takes records: step launches run the kernel with the record code
     int fgrid_ = 0;
     std::map<int, int> fused_occ_;    // register-limited resident workgroups per (kind, nb, bt)
     size_t lds_limit_ = 0;

@@ -355,7 +355,7 @@ struct ItemRun {
 // and q; E corrector of plane q - 2; barrier.  The LDS pointers are distinct planes (restrict), so the
 // reads of `cur` and `sp` need not wait for the copy into `nxt`; the
 // closing barrier does.
-template <typename R, int KIND, int NB, int BT, bool MEASURE, int P>
+template <typename R, int KIND, int NB, int BT, bool MEASURE, int P, bool REC>
 __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo<NB>& g, const ItemRun<R>& run,
                                            ColumnState<R, NB>& cs, const char* __restrict__ cur,
                                            char* __restrict__ nxt, char* __restrict__ sp, double* __restrict__ acc,
@@ -427,7 +427,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
     // B: m and E terms of plane q - 1 (its exchange sums are complete; one
     // material: the exchange field is the sum itself) from the spins its
     // predictor reads, then the predictor
-    const bool rec = run.partials && g.interior && zp_need && zp_own;
+    const bool rec = REC && run.partials && g.interior && zp_need && zp_own;
     R tc[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -461,7 +461,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
         }
         cs.hp[S1][b] = up[b];
     }
-    if (rec)
+    if (REC && rec)
         record_add<BT>(tc, acc);
     if constexpr (MEASURE) {
         // S(q + 1) went into the third plane at the start of the step
@@ -522,7 +522,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
     __syncthreads();   // S(q + 1) complete; every thread is done with S'(q - 1)
 }
 
-template <typename R, int KIND, int NB, int BT, bool MEASURE>
+template <typename R, int KIND, int NB, int BT, bool MEASURE, bool REC>
 __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedItem& w, int k, char* lds,
                                            int plane_bytes, const int4* pat, const FEnt<R>* ent,
                                            double (*red)[BT / 64], double* acc_base, uint32_t* dcol)
@@ -604,7 +604,7 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
                                                  (int)(3u * (uint32_t)sizeof(R) * (uint32_t)r.n + 16u), 0x00020000);
     run.z0 = w.z0;
     run.z1 = w.z1;
-    run.partials = (r.flags & kRecord) && (MEASURE || k >= 1);
+    run.partials = REC && (r.flags & kRecord) && (MEASURE || k >= 1);
     run.step = r.step + (uint64_t)k;
     char* planes[2] = {lds, lds + plane_bytes};
     char* sp = lds + 2 * plane_bytes;
@@ -669,25 +669,25 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
             free_plane = t;
         };
         for (int q = z0 - 2; q <= z1 + 1; q += 2) {
-            plane_step<R, KIND, NB, BT, MEASURE, 0>(r, g, run, cs, cur, prev, free_plane, acc, pat, ent, q, zw_m2,
+            plane_step<R, KIND, NB, BT, MEASURE, 0, REC>(r, g, run, cs, cur, prev, free_plane, acc, pat, ent, q, zw_m2,
                                                     zw_m1, zw_p1, m);
             rotate();
             next_plane();
             if (q + 1 > z1 + 1)
                 break;
-            plane_step<R, KIND, NB, BT, MEASURE, 1>(r, g, run, cs, cur, prev, free_plane, acc, pat, ent, q + 1,
+            plane_step<R, KIND, NB, BT, MEASURE, 1, REC>(r, g, run, cs, cur, prev, free_plane, acc, pat, ent, q + 1,
                                                     zw_m2, zw_m1, zw_p1, m);
             rotate();
             next_plane();
         }
     } else {
         for (int q = z0 - 2; q <= z1 + 1; q += 2) {
-            plane_step<R, KIND, NB, BT, MEASURE, 0>(r, g, run, cs, planes[0], planes[1], sp, acc, pat, ent, q, zw_m2,
+            plane_step<R, KIND, NB, BT, MEASURE, 0, REC>(r, g, run, cs, planes[0], planes[1], sp, acc, pat, ent, q, zw_m2,
                                                     zw_m1, zw_p1, m);
             next_plane();
             if (q + 1 > z1 + 1)
                 break;
-            plane_step<R, KIND, NB, BT, MEASURE, 1>(r, g, run, cs, planes[1], planes[0], sp, acc, pat, ent, q + 1,
+            plane_step<R, KIND, NB, BT, MEASURE, 1, REC>(r, g, run, cs, planes[1], planes[0], sp, acc, pat, ent, q + 1,
                                                     zw_m2, zw_m1, zw_p1, m);
             next_plane();
         }
@@ -728,7 +728,7 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
 #define SLLG_FUSED_WAVES_F64 2
 #endif
 
-template <typename R, int KIND, int NB, int BT, bool MEASURE>
+template <typename R, int KIND, int NB, int BT, bool MEASURE, bool REC>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? SLLG_FUSED_WAVES
                                                                                    : SLLG_FUSED_WAVES_F64))) void k_fused(const ReplicaDev<R>* __restrict__ reps,
                                               const FusedItem* __restrict__ items,
@@ -761,9 +761,9 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
             __syncthreads();
         }
         // items' sums of the previous launch -> the record two steps back
-        if (!MEASURE && w.idx == 0 && (r.flags & kRecord) && k >= 2)
+        if (REC && !MEASURE && w.idx == 0 && (r.flags & kRecord) && k >= 2)
             fused_record<R, BT>(r, (k - 1) & 1, k - 2, red);
-        fused_item<R, KIND, NB, BT, MEASURE>(r, w, k, fused_lds, plane_bytes, pat, ent, red, acc, dcol);
+        fused_item<R, KIND, NB, BT, MEASURE, REC>(r, w, k, fused_lds, plane_bytes, pat, ent, red, acc, dcol);
     }
 }
 
@@ -790,20 +790,25 @@ __global__ __launch_bounds__(256) void k_fused_finish(ReplicaDev<R>* __restrict_
     }
 }
 
+// The measuring launch always records; a step launch records unless no
+// replica of the batch takes records (rec false: the variant without the
+// record code).
 template <typename R, int KIND, int NB, int BT>
-const void* fused_ptr(bool measure)
+const void* fused_ptr(bool measure, bool rec)
 {
-    return measure ? (const void*)k_fused<R, KIND, NB, BT, true> : (const void*)k_fused<R, KIND, NB, BT, false>;
+    if (measure)
+        return (const void*)k_fused<R, KIND, NB, BT, true, true>;
+    return rec ? (const void*)k_fused<R, KIND, NB, BT, false, true> : (const void*)k_fused<R, KIND, NB, BT, false, false>;
 }
 
 // The kernel of (kind, nb, bt, measure), or null if it is not built
 // (FP64: the compiled kinds, 256 and 512 threads).
 template <typename R>
-const void* fused_kernel(int kind, int nb, int bt, bool measure)
+const void* fused_kernel(int kind, int nb, int bt, bool measure, bool rec = true)
 {
 #define SLLG_FUSED_CASE(K_, NB_, BT_)           \
     if (kind == K_ && nb == NB_ && bt == BT_)   \
-        return fused_ptr<R, K_, NB_, BT_>(measure);
+        return fused_ptr<R, K_, NB_, BT_>(measure, rec);
     SLLG_FUSED_CASE(kKindSc6, 1, 256)
     SLLG_FUSED_CASE(kKindSc6, 1, 512)
     SLLG_FUSED_CASE(kKindBcc8, 2, 256)
@@ -851,11 +856,11 @@ size_t fused_lds_bytes(int kind, int plane_bytes, int bt)
 
 template <typename R>
 hipError_t launch_fused(const ReplicaDev<R>* reps, const FusedItem* items, const int* n_items, int grid, int k,
-                        int remap, bool measure, int kind, int nb, int bt, int plane_bytes, hipStream_t st)
+                        int remap, bool measure, bool rec, int kind, int nb, int bt, int plane_bytes, hipStream_t st)
 {
     if (grid <= 0)
         return hipSuccess;
-    const void* f = fused_kernel<R>(kind, nb, bt, measure);
+    const void* f = fused_kernel<R>(kind, nb, bt, measure, rec);
     if (!f)
         return hipErrorInvalidValue;
     void* args[] = {(void*)&reps, (void*)&items, (void*)&n_items, (void*)&k, (void*)&remap, (void*)&plane_bytes};
@@ -894,9 +899,9 @@ size_t fused_lds_limit(int device)
 }
 
 template hipError_t launch_fused<float>(const ReplicaDev<float>*, const FusedItem*, const int*, int, int, int, bool,
-                                        int, int, int, int, hipStream_t);
+                                        bool, int, int, int, int, hipStream_t);
 template hipError_t launch_fused<double>(const ReplicaDev<double>*, const FusedItem*, const int*, int, int, int, bool,
-                                         int, int, int, int, hipStream_t);
+                                         bool, int, int, int, int, hipStream_t);
 template hipError_t launch_fused_finish<float>(ReplicaDev<float>*, int, hipStream_t);
 template hipError_t launch_fused_finish<double>(ReplicaDev<double>*, int, hipStream_t);
 template int fused_resident_blocks<float>(int, int, int, int, int);

@@ -77,12 +77,15 @@ hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, const uint1
 
 // Fused plane-marching Heun step (fused.hip) of step k over the work items
 // (one launch per step; measure: m and E sums of the state after the chunk
-// instead, for k_fused_finish).  kind: FusedKind of every replica of the
-// launch, nb its sites per cell, bt threads per workgroup (fused_block_ok);
-// plane_bytes: LDS bytes of one plane, the largest over the replicas.
+// instead, for k_fused_finish).  rec: some replica of the launch takes
+// records (false runs the kernel built without the record code; only valid
+// when none does, or at k = 0, where no step leaves record sums).  kind:
+// FusedKind of every replica of the launch, nb its sites per cell, bt
+// threads per workgroup (fused_block_ok); plane_bytes: LDS bytes of one
+// plane, the largest over the replicas.
 template <typename R>
 hipError_t launch_fused(const ReplicaDev<R>* reps, const FusedItem* items, const int* n_items, int grid, int k,
-                        int remap, bool measure, int kind, int nb, int bt, int plane_bytes, hipStream_t st);
+                        int remap, bool measure, bool rec, int kind, int nb, int bt, int plane_bytes, hipStream_t st);
 // The end of a fused chunk for every replica: its last two records (when
 // recording), the averaging sums of its records, and the advance of the
 // step counter, parity and record position.
