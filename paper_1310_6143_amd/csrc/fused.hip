@@ -155,19 +155,21 @@ __device__ __forceinline__ void record_terms(const MaterialDev<R>& m, const V3<R
     t[3] = fma((R)0.5, sh, m.ku_mu * se * se);
 }
 
-// The terms of one cell (its basis sites added in FP32, in basis order)
-// into the thread's own FP64 sums in LDS (acc[c * BT]), added in plane
-// order; constant offsets let the four read-modify-writes overlap.
-template <int BT, typename R>
+// The terms of one cell (its basis sites added in R, in basis order) into
+// the thread's own FP64 sums, added in plane order: acc[c * AS].  FP32 keeps
+// the sums in LDS (AS = the block size; constant offsets let the four
+// read-modify-writes overlap), FP64 in registers (AS = 1: its kernel has
+// room below the 256 registers of two waves per SIMD).
+template <int AS, typename R>
 __device__ __forceinline__ void record_add(const R t[4], double* acc)
 {
     double a[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-        a[c] = acc[c * BT];
+        a[c] = acc[c * AS];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-        acc[c * BT] = a[c] + (double)t[c];
+        acc[c * AS] = a[c] + (double)t[c];
 }
 
 // x, y, z of the LDS slot at p.  FP32: the fourth word is never read; the
@@ -462,7 +464,7 @@ __device__ __forceinline__ void plane_step(const ReplicaDev<R>& r, const ItemGeo
         cs.hp[S1][b] = up[b];
     }
     if (REC && rec)
-        record_add<BT>(tc, acc);
+        record_add<(sizeof(R) == 8 ? 1 : BT)>(tc, acc);
     if constexpr (MEASURE) {
         // S(q + 1) went into the third plane at the start of the step
         __syncthreads();   // S(q + 1) complete; every thread is done with S(q - 1)
@@ -608,10 +610,17 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
     run.step = r.step + (uint64_t)k;
     char* planes[2] = {lds, lds + plane_bytes};
     char* sp = lds + 2 * plane_bytes;
-    double* acc = acc_base + t;
+    // the thread's FP64 m and E sums: FP32 in LDS, FP64 in registers
+    constexpr int AS = sizeof(R) == 8 ? 1 : BT;
+    double acc_reg[4];
+    double* acc;
+    if constexpr (sizeof(R) == 8)
+        acc = acc_reg;
+    else
+        acc = acc_base + t;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-        acc[c * BT] = 0.0;
+        acc[c * AS] = 0.0;
 
     const MaterialDev<R> m = uniform_material(r);
     ColumnState<R, NB> cs;
@@ -696,7 +705,7 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
         const int lane = t & 63, wave = t >> 6;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const double s = wave_sum(acc[c * BT]);
+            const double s = wave_sum(acc[c * AS]);
             if (lane == 0)
                 red[c][wave] = s;
         }
@@ -740,7 +749,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(sizeof(R) ==
     // copies in flight
     extern __shared__ __attribute__((aligned(16))) char fused_lds[];
     __shared__ double red[4][BT / 64];
-    __shared__ double acc[4 * BT];
+    __shared__ double acc[sizeof(R) == 8 ? 1 : 4 * BT];   // FP64 keeps these sums in registers
     __shared__ uint32_t dcol[PlaneLayout<R, BT>::CPW * BT];
     int4* pat = reinterpret_cast<int4*>(fused_lds + 3 * plane_bytes);
     FEnt<R>* ent = reinterpret_cast<FEnt<R>*>(pat + kFusedMaxPatterns);
@@ -839,8 +848,9 @@ bool fused_block_ok(int kind, int bt, size_t real_bytes)
 
 size_t fused_static_lds(int bt, size_t real_bytes)
 {
-    // acc, dcol and red of k_fused
-    return (size_t)bt * (4 * sizeof(double) + (size_t)fused_chunks_per_wave(real_bytes) * sizeof(uint32_t)) +
+    // acc (FP32 only), dcol and red of k_fused
+    const size_t acc = real_bytes == 8 ? sizeof(double) : (size_t)bt * 4 * sizeof(double);
+    return acc + (size_t)bt * (size_t)fused_chunks_per_wave(real_bytes) * sizeof(uint32_t) +
            4 * (size_t)(bt / 64) * sizeof(double);
 }
 
