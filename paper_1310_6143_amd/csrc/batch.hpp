@@ -1058,6 +1058,17 @@ public:
     {
         sync_tables();
         last_stream_ = st;
+        if (fused_mode_ && fgrid_ > 0) {
+            // the fused step's measuring plane walk over the state in place
+            // (k = -1), then the items' sums into the slot
+            const int* nf =
+                (const int*)(reinterpret_cast<const char*>(d_fwork_) + sizeof(FusedItem) * (size_t)fwork_cap_);
+            hip_check(launch_fused<R>(d_reps_, d_fwork_, nf, fgrid_, -1, remap_, true, true, fused_kind_, fused_nb_,
+                                      fused_bt_, fused_plane_, st),
+                      "measure");
+            hip_check(launch_fused_record<R>(d_reps_, (int)slots_.size(), slot, st), "record");
+            return;
+        }
         if (grid_ <= 0)
             return;
         hip_check(launch_predict<R>(d_reps_, d_work_, d_nwork_, grid_, 1, remap_, true, variant_, st),

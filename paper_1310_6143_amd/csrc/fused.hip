@@ -598,7 +598,10 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
         dcol[j * BT + t] = valid ? site * 3u * (uint32_t)sizeof(R) + 16u * (uint32_t)part : 0xFFFFFFFFu;
     }
     run.dcol = dcol;
-    const int par = (r.parity + (MEASURE ? r.nsteps : k)) & 1;
+    // the measuring launch reads the state after the chunk's nsteps steps,
+    // or with k < 0 the current state in place (Monte Carlo records)
+    const int mslot = MEASURE ? (k < 0 ? 0 : r.nsteps) : k;
+    const int par = (r.parity + mslot) & 1;
     run.S = r.S[par];
     run.Sn = r.S[par ^ 1];
     // the spin buffer holds 16 bytes past its last site (the copies read 16 bytes per lane)
@@ -711,7 +714,7 @@ __device__ __forceinline__ void fused_item(const ReplicaDev<R>& r, const FusedIt
         }
         __syncthreads();
         if (t == 0) {
-            double* out = r.f_partials + 4 * ((int64_t)((MEASURE ? r.nsteps : k) & 1) * r.f_items + w.idx);
+            double* out = r.f_partials + 4 * ((int64_t)(mslot & 1) * r.f_items + w.idx);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 double s = 0.0;
@@ -797,6 +800,19 @@ __global__ __launch_bounds__(256) void k_fused_finish(ReplicaDev<R>* __restrict_
         accumulate_records(r);
         advance_replica(r);
     }
+}
+
+// After a measuring launch of the current state (k < 0), one workgroup per
+// replica: the items' sums into record `slot` (Monte Carlo records; no
+// advance of the step counter or parity).
+template <typename R>
+__global__ __launch_bounds__(256) void k_fused_record(ReplicaDev<R>* __restrict__ reps, int slot)
+{
+    __shared__ double red[4][4];
+    const ReplicaDev<R>& r = reps[blockIdx.x];
+    if (r.nsteps <= 0 || !(r.flags & kFused) || !(r.flags & kRecord))
+        return;   // uniform over the block
+    fused_record<R, 256>(r, 0, slot, red);
 }
 
 // The measuring launch always records; a step launch records unless no
@@ -887,6 +903,15 @@ hipError_t launch_fused_finish(ReplicaDev<R>* reps, int n_rep, hipStream_t st)
 }
 
 template <typename R>
+hipError_t launch_fused_record(ReplicaDev<R>* reps, int n_rep, int slot, hipStream_t st)
+{
+    if (n_rep <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_fused_record<R>), dim3(n_rep), dim3(256), 0, st, reps, slot);
+    return hipGetLastError();
+}
+
+template <typename R>
 int fused_resident_blocks(int device, int kind, int nb, int bt, int plane_bytes)
 {
     int cus = 0, a = 0;
@@ -914,6 +939,8 @@ template hipError_t launch_fused<double>(const ReplicaDev<double>*, const FusedI
                                          bool, int, int, int, int, hipStream_t);
 template hipError_t launch_fused_finish<float>(ReplicaDev<float>*, int, hipStream_t);
 template hipError_t launch_fused_finish<double>(ReplicaDev<double>*, int, hipStream_t);
+template hipError_t launch_fused_record<float>(ReplicaDev<float>*, int, int, hipStream_t);
+template hipError_t launch_fused_record<double>(ReplicaDev<double>*, int, int, hipStream_t);
 template int fused_resident_blocks<float>(int, int, int, int, int);
 template int fused_resident_blocks<double>(int, int, int, int, int);
 

@@ -91,6 +91,11 @@ hipError_t launch_fused(const ReplicaDev<R>* reps, const FusedItem* items, const
 // step counter, parity and record position.
 template <typename R>
 hipError_t launch_fused_finish(ReplicaDev<R>* reps, int n_rep, hipStream_t st);
+// Monte Carlo records on the fused step's items: after launch_fused with
+// measure and k = -1 (the current state, in place), the items' sums of
+// every recording replica into record `slot`.
+template <typename R>
+hipError_t launch_fused_record(ReplicaDev<R>* reps, int n_rep, int slot, hipStream_t st);
 // Resident workgroups of the fused kernel (kind, nb, bt) per device with
 // plane_bytes LDS planes; 0 if unknown.
 template <typename R>

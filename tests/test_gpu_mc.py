@@ -173,17 +173,28 @@ def test_mc_full_block_in_the_bench_launch_shape():
     w = bcc_block(cells=160)
     S_ref = np.ascontiguousarray(w.S0.copy())
     orc = oracle.System(w)
-    _, _, acc1 = orc.mc(S_ref, 0, 1)
+    m1, E1, acc1 = orc.mc(S_ref, 0, 1)
     S1 = S_ref.copy()
-    _, _, acc2 = orc.mc(S_ref, 1, 1)
+    m2, E2, acc2 = orc.mc(S_ref, 1, 1)
+    m_ref, E_ref = np.concatenate([m1, m2]), np.concatenate([E1, E2])
     with sl.from_workload(w, precision=sl.FP64, check_symmetry=False) as g:
-        _, _, acc = g.mc(2)
+        assert g.get_option("fused_active") == 1   # records from the fused step's measuring walk
+        m, E, acc = g.mc(2)
         S = g.get_spins()
     assert np.array_equal(acc, np.concatenate([acc1, acc2]))
     assert max_angle(S, S_ref) <= 1e-12
+    # same spins; the records differ only by the order of their FP64 sums
+    # over 8,192,000 sites, which the worst-case bound of a summation of N
+    # terms, N 2^-53 = 9.1e-10 (relative), covers
+    print(f"full block MC records: max |dm| {np.abs(m - m_ref).max():.2e}, "
+          f"max |dE|/|E| {np.abs(E - E_ref).max() / np.abs(E_ref).max():.2e}")
+    assert np.abs(m - m_ref).max() <= 1e-9
+    assert np.abs(E - E_ref).max() <= 1e-9 * np.abs(E_ref).max()
     with sl.from_workload(w, precision=sl.FP32, check_symmetry=False) as g:
-        _, _, acc = g.mc(1)
+        m, E, acc = g.mc(1)
         S = g.get_spins()
+    assert np.abs(m - m1).max() <= 1e-5
+    assert np.abs(E - E1).max() <= 1e-5 * np.abs(E1).max()
     off = int((angles(S, S1) > 1e-4).sum())
     print(f"full block MC: FP64 accepted {acc1[0]} + {acc2[0]} as the oracle; FP32 step 1: "
           f"{off} of {w.n} sites off by more than 1e-4 rad, accepted {acc[0]} vs {acc1[0]}")
@@ -244,12 +255,16 @@ def test_mc_full_block_lattice_colouring():
     oracle's at every site."""
     w = bcc_block(cells=160)
     S_ref = np.ascontiguousarray(w.S0.copy())
-    _, _, acc_ref = oracle.System(w).mc(S_ref, 0, 1, visit="lattice")
+    m_ref, E_ref, acc_ref = oracle.System(w).mc(S_ref, 0, 1, visit="lattice")
     with sl.from_workload(w, precision=sl.FP64, check_symmetry=False) as g:
         g.set_option("mc_colouring", 1)
         assert g.get_option("mc_colours") == 4
-        _, _, acc = g.mc(1)
+        m, E, acc = g.mc(1)
         S = g.get_spins()
-    print(f"full block, lattice-ordered classes: accepted {acc[0]} as the oracle")
+    print(f"full block, lattice-ordered classes: accepted {acc[0]} as the oracle; max |dm| "
+          f"{np.abs(m - m_ref).max():.2e}, max |dE|/|E| {np.abs(E - E_ref).max() / np.abs(E_ref).max():.2e}")
     assert np.array_equal(acc, acc_ref)
     assert max_angle(S, S_ref) <= 1e-12
+    # records: FP64 sums over 8,192,000 sites in another order (N 2^-53 = 9.1e-10)
+    assert np.abs(m - m_ref).max() <= 1e-9
+    assert np.abs(E - E_ref).max() <= 1e-9 * np.abs(E_ref).max()
