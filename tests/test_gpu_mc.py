@@ -268,3 +268,17 @@ def test_mc_full_block_lattice_colouring():
     # records: FP64 sums over 8,192,000 sites in another order (N 2^-53 = 9.1e-10)
     assert np.abs(m - m_ref).max() <= 1e-9
     assert np.abs(E - E_ref).max() <= 1e-9 * np.abs(E_ref).max()
+
+
+def test_mc_colouring_option_is_validated():
+    """"mc_colouring" takes 0 or 1 (anything else is SLLG_E_ARG and changes
+    nothing); "mc_colours" reads the number of classes."""
+    w = bcc_block(cells=4, temperature=300.0, seed=2)
+    with sl.from_workload(w, precision=sl.FP32, check_symmetry=False) as g:
+        before = g.get_option("mc_colours")
+        with pytest.raises(sl.SllgError):
+            g.set_option("mc_colouring", 2)
+        assert g.get_option("mc_colouring") == 0
+        assert g.get_option("mc_colours") == before
+        g.set_option("mc_colouring", 1)
+        assert g.get_option("mc_colours") == 4
