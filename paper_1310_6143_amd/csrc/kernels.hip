@@ -1045,6 +1045,10 @@ __global__ void k_noise(uint64_t seed, uint64_t step, int n, double* __restrict_
 // used (entries past the end repeat the last one with J = 0), and added in
 // table order.
 constexpr int kMcBatch = 8;
+// FP32 Monte Carlo grid: at most this many times the resident workgroups
+// (measured on the bcc block: 1, 2 and 4 give 0.21, 0.194 and 0.22 ms per
+// four-class sweep; one workgroup per chunk 0.242 ms)
+constexpr int kMcResidentFactor = 2;
 
 template <typename R, bool TX>
 __device__ __forceinline__ V3<R> exchange_sum_global(const ReplicaDev<R>& r, const Shared<R>& sh,
@@ -1132,12 +1136,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __res
     // Workgroups are handed to the 8 XCDs round-robin, and each XCD has its
     // own L2.  Sites of neighbouring chunks of the class list share
     // neighbours (cells one row or plane apart), so XCD x takes a
-    // contiguous range of chunks: workgroup b takes chunk
-    // start(b mod 8) + b / 8, a one-to-one map of 0..G-1.
-    const int G = (int)gridDim.x, q = G >> 3, rem = G & 7, x = (int)blockIdx.x & 7;
-    const int chunk = x * q + (x < rem ? x : rem) + ((int)blockIdx.x >> 3);
-    const int t = chunk * (int)blockDim.x + (int)threadIdx.x;
-    if (t < count) {
+    // contiguous range of the class's chunks, shared out among its
+    // workgroups (those with b mod 8 = x; the grid is a multiple of 8).  In
+    // FP32 the grid is capped near the resident workgroups, so a workgroup
+    // takes several chunks and stages the tables above once for them.
+    const int NC = (count + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int q = NC >> 3, rem = NC & 7, x = (int)blockIdx.x & 7;
+    const int start = x * q + (x < rem ? x : rem), len = q + (x < rem ? 1 : 0);
+    const int per_xcd = (int)gridDim.x >> 3;
+    auto trial = [&](int t) {
         // the site and, for the stencil forms, its pattern: two independent
         // loads from lists in the class's order
         const int i = gload(sites, t);
@@ -1180,6 +1187,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_mc(const ReplicaDev<R>* __res
                 flag_fault(r.fault);
             atomicAdd(&acc_block, 1u);
         }
+    };
+    if constexpr (sizeof(R) == 4) {
+        for (int j = (int)blockIdx.x >> 3; j < len; j += per_xcd) {
+            const int t = (start + j) * (int)blockDim.x + (int)threadIdx.x;
+            if (t < count)
+                trial(t);
+        }
+    } else {
+        // one chunk per workgroup (the grid covers every chunk): the loop
+        // would cost the FP64 kernel registers and a wave per SIMD
+        const int t = (start + ((int)blockIdx.x >> 3)) * (int)blockDim.x + (int)threadIdx.x;
+        if (((int)blockIdx.x >> 3) < len && t < count)
+            trial(t);
     }
     __syncthreads();
     if (threadIdx.x == 0 && acc_block)
@@ -1294,7 +1314,30 @@ hipError_t launch_mc(const ReplicaDev<R>* rep, const int32_t* sites, const uint1
 {
     if (count <= 0)
         return hipSuccess;
-    const dim3 g((count + kBlockThreads - 1) / kBlockThreads), b(kBlockThreads);
+    // one workgroup per chunk of kBlockThreads sites, rounded to a multiple
+    // of 8 (the XCD share-out in k_mc); FP32: at most kMcResidentFactor
+    // times the resident workgroups of the kernel, each then taking several
+    // chunks and staging its tables once (FP64 keeps one chunk per
+    // workgroup: the chunk loop costs its kernel a wave per SIMD)
+    static int resident[2][16];   // per kernel variant and device, 0 = not yet queried
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16)
+        return hipErrorInvalidDevice;
+    int& res = resident[tensor ? 1 : 0][dev];
+    if (res == 0) {
+        int cus = 0, per_cu = 0;
+        const void* f = tensor ? (const void*)k_mc<R, true> : (const void*)k_mc<R, false>;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlockThreads, 0) != hipSuccess)
+            return hipErrorInvalidValue;
+        res = (cus * (per_cu > 0 ? per_cu : 1)) & ~7;
+        if (res < 8)
+            res = 8;
+    }
+    const int chunks = (count + kBlockThreads - 1) / kBlockThreads;
+    const int cap = sizeof(R) == 4 ? res * kMcResidentFactor : 0x7FFFFFF8;
+    const int grid = ((chunks + 7) & ~7) < cap ? ((chunks + 7) & ~7) : cap;
+    const dim3 g(grid), b(kBlockThreads);
     if (tensor)
         hipLaunchKernelGGL((k_mc<R, true>), g, b, 0, st, rep, sites, pids, count, step, (R)cone, inv_kT, accepted);
     else
