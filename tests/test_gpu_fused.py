@@ -287,3 +287,25 @@ def test_shape_change_between_calls(lattice_cells):
         mb, Eb = b.integrate(10)
         assert np.array_equal(a.get_spins(), b.get_spins())
         assert np.allclose(ma, mb, rtol=0, atol=1e-12) and np.allclose(Ea, Eb, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("precision", [sl.FP32, sl.FP64])
+def test_records_do_not_change_the_spins(precision):
+    """The step kernel built without the record code (launches where no
+    replica records, and the first step of every call) computes the same
+    spins bit for bit as the build with it: a run with records, one
+    without, and one that switches between the two every call agree."""
+    w = bcc_block(cells=12, n_steps=60)
+    with _fused_system(w, precision=precision) as a, _fused_system(w, precision=precision) as b, \
+            _fused_system(w, precision=precision) as c:
+        assert a.get_option("fused_active") == 1
+        a.integrate(30)
+        b.integrate(30, record=False)
+        for k in range(6):
+            if k % 2:
+                c.integrate(5)
+            else:
+                c.integrate(5, record=False)
+        Sa, Sb, Sc = a.get_spins(), b.get_spins(), c.get_spins()
+    assert np.array_equal(Sa, Sb)
+    assert np.array_equal(Sa, Sc)
